@@ -1,0 +1,170 @@
+/*
+ * c3pt.h -- C ABI of the spin-open three-point contraction library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the hot path of the factorized stochastic three-point
+ * function of Bali et al., "Baryonic and mesonic 3-point functions with open
+ * spin indices" (Lattice 2017):
+ *
+ *   spectator part, Eq. (9)      c3pt_spectator_meson / c3pt_spectator_baryon
+ *   insertion part, Eq. (10)     c3pt_insertion
+ *   noise-averaged product of the two parts (Eq. (5) in Eq. (8))   c3pt_combine
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex numbers are interleaved (re, im) pairs.  Inputs are complex64
+ *    (float2) or complex128 (double2) as selected by c3pt_geom.dtype; every
+ *    output is complex128.
+ *  - Spin-colour index A = 3*spin + colour (spin 0..3, colour 0..2).  Gamma
+ *    matrices are in the DeGrand-Rossi basis, so gamma5 = diag(1, 1, -1, -1).
+ *  - Spatial site n = x1 + L1*(x2 + L2*x3).  Every field is given per timeslice,
+ *    structure-of-arrays with the site index fastest:
+ *        propagator slice   G[A_row][A_col][site]   (12*12*V3 complex),
+ *                            row = field point, column = source point;
+ *        noise eta / stochastic solution s   v[noise][A][site]  (N*12*V3),
+ *        gauge links        U[mu][c][d][site]  (4*3*3*V3), mu = x, y, z, t,
+ *                            U_mu(x) on the link x -> x + mu.
+ *  - Momenta: host array k[n_mom][3] of integers; the phase of site x is
+ *        exp(sigma * 2 pi i * sum_j k_j (x_j - r_j) / L_j)
+ *    with sigma = -1 for spectators (Eq. (9)) and +1 for insertions (Eq. (10)),
+ *    and r the spatial source position (Sec. 2.1).  Components may be any
+ *    integers; they are reduced modulo L_j.
+ *
+ * Memory and execution
+ * --------------------
+ *  - All field and output pointers are DEVICE pointers owned by the caller.
+ *    Pointer tables (G_t, s_t, U_t), k, taus, w and pairs are HOST arrays read
+ *    during the call only.
+ *  - Calls are asynchronous on the given HIP stream (NULL = the null stream):
+ *    results are valid once the stream has been synchronized.  Scratch space
+ *    (split-site partial sums) is owned by the library, one buffer per stream,
+ *    grown on demand; growing synchronizes that stream.  Calls on one stream
+ *    are ordered; calls on different streams do not share scratch space.
+ *  - Results are deterministic: no floating-point atomics; split-site partial
+ *    sums are reduced in a fixed order in FP64.
+ *
+ * Errors
+ * ------
+ *  Every entry point returns C3PT_OK (0) or a negative status.  Arguments are
+ *  validated before anything is enqueued: on error nothing is launched and the
+ *  output buffer is untouched.  c3pt_last_error() gives a message for the last
+ *  failing call on the calling thread.  No C++ exception crosses this ABI.
+ */
+#ifndef C3PT_H
+#define C3PT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define C3PT_OK            0
+#define C3PT_EINVAL       (-1)   /* bad extents, NULL pointer, index out of range  */
+#define C3PT_ENOMEM       (-2)   /* scratch allocation failed                      */
+#define C3PT_EDEVICE      (-3)   /* a HIP call failed                              */
+#define C3PT_EUNSUPPORTED (-4)   /* valid request this build cannot execute        */
+
+#define C3PT_C64   0              /* complex64 inputs (FP32 contractions)  */
+#define C3PT_C128  1              /* complex128 inputs (FP64 throughout)   */
+
+#define C3PT_PROJ_NATIVE      0   /* projection in the input precision (FP32 or FP64 MFMA)     */
+#define C3PT_PROJ_SPLIT_F16   1   /* complex64 only: hi+lo FP16 operands, FP32 MFMA accumulate */
+#define C3PT_PROJ_SPLIT_BF16  2   /* complex64 only: hi+lo BF16 operands, FP32 MFMA accumulate */
+
+#define C3PT_MAX_MOM   256        /* largest momentum list per call        */
+#define C3PT_MAX_L     256        /* largest spatial extent per direction  */
+
+typedef struct c3pt_geom {
+    int   L[3];     /* spatial extents L1, L2, L3 (each 1..C3PT_MAX_L)           */
+    int   T;        /* temporal extent (>= 1); time neighbours wrap modulo T     */
+    int   r[3];     /* spatial source position, the origin of the phases         */
+    int   dtype;    /* C3PT_C64 or C3PT_C128                                     */
+    int   proj;     /* C3PT_PROJ_*                                               */
+    void* stream;   /* hipStream_t the work is enqueued on; NULL = null stream   */
+} c3pt_geom;
+
+/*
+ * Meson spectator part, Eq. (9):
+ *   S_i(p')[b'][a'][a][c] = sum_x' exp(-i p'.(x'-r)) sum_c' [gamma5 eta_i(x')]^{b'}_{c'}
+ *                           [gamma5 G(x',r)^dag gamma5]^{a' a}_{c' c}
+ * i.e. g[b'] g[a'] g[a] sum_c' eta_i[(b',c')] conj(G[(a',c')][(a,c)]) per site.
+ *   G_tf : device, propagator slice at the sink timeslice, 144*V3 complex.
+ *   eta  : device, n_noise noise vectors on the sink timeslice, n_noise*12*V3.
+ *   out  : device, complex128 [n_noise][n_mom][192], spin order (b', a', a, c).
+ */
+int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* eta, int n_noise,
+                         const int* k, int n_mom, void* out);
+
+/*
+ * Nucleon-type spectator with epsilon-tensor colour contraction.  The paper
+ * times a baryon measurement without printing its formula; this is the
+ * reading in which the two spectator quarks run forward from the source
+ * (G1, G2) and the active quark leaves the sink on the stochastic line exactly
+ * as in Eq. (8):
+ *   S_i(p')[a1'][a1][a2'][a2][b'][c'] = sum_x' exp(-i p'.(x'-r)) g[b'] sum_c eta_i[(b',c)]
+ *        sum eps_{abc} eps_{a'b'c'} G1[(a1',a)][(a1,a')] G2[(a2',b)][(a2,b')]
+ *   G1_tf, G2_tf : device propagator slices at the sink timeslice.
+ *   out          : device complex128 [n_noise][n_mom][3072],
+ *                  order (a1', a1, a2', a2, b', c').
+ */
+int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* G2_tf,
+                          const void* eta, int n_noise, const int* k, int n_mom, void* out);
+
+/*
+ * Insertion part, Eq. (10), at every timeslice tau in taus[0..n_tau):
+ *   I_i(q,tau)[op][at][bt][b][c] = sum_y exp(+i q.(y-r)) g[at]
+ *        sum_c' conj(s_i(y)[(at,c')]) (O_op G)(y)[(bt,c')][(b,c)]
+ * with O_0 = 1 (all 16 Gamma stay open in (at, bt)) and, when n_ops == 5,
+ * O_{1+nu} = D_nu, nu = x, y, z, t:
+ *   (D_nu G)(y) = 1/2 [U_nu(y) G(y+nu) - U_nu(y-nu)^dag G(y-nu)],
+ * spatial neighbours periodic in L_j, time neighbours taken modulo T.
+ *   G_t : host array of T device pointers (slice t of the propagator, or NULL
+ *         where not needed).  Needed: every tau; with n_ops == 5 also tau+-1.
+ *   s_t : host array of T device pointers to [n_noise][12][V3]; needed at every tau.
+ *   U_t : host array of T device pointers to [4][3][3][V3], or NULL when
+ *         n_ops == 1.  With n_ops == 5 needed at every tau and tau-1.
+ *   out : device complex128 [n_noise][n_tau][n_ops][n_mom][192],
+ *         order (at, bt, b, c).
+ */
+int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* const* s_t,
+                   int n_noise, const int* taus, int n_tau, const void* const* U_t, int n_ops,
+                   const int* k, int n_mom, void* out);
+
+/*
+ * Noise-weighted product of spectator and insertion (Eq. (5) inserted into
+ * Eq. (8)), summing the source colour shared by the two parts (the delta of
+ * Eq. (1)):
+ *   C[pair][tau][op - op_begin][s][t] = sum_i w_i sum_c S_i(p'_pair)[s][c] I_i(q_pair, tau)[op][t][c]
+ *   spec      : device complex128 [n_noise][n_p][spec_spin*3] (spec_spin 64 or 1024),
+ *               the output of a spectator call.
+ *   ins       : device complex128 [n_noise][n_tau][n_ops][n_q][192], an insertion output.
+ *   w         : host [n_noise] weights, or NULL for 1/n_noise.
+ *   pairs     : host [n_pairs][2] (p' index, q index), or NULL for all n_p*n_q pairs
+ *               in the order p'*n_q + q (then n_pairs must be n_p*n_q).
+ *   op_begin, op_end : the half-open range of insertion operators combined.
+ *   out       : device complex128 [n_pairs][n_tau][op_end-op_begin][spec_spin][64].
+ * Computed entirely in FP64.
+ */
+int c3pt_combine(const void* spec, int spec_spin, const void* ins, int n_noise, int n_p, int n_q,
+                 int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
+                 int n_pairs, void* out, void* stream);
+
+/* Static description of a status code. */
+const char* c3pt_strerror(int status);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* c3pt_last_error(void);
+
+/* Library ABI version (major*100 + minor). */
+int c3pt_version(void);
+
+/* Bytes of scratch currently held for `stream` (0 if none). */
+unsigned long long c3pt_scratch_bytes(void* stream);
+
+/* Release the scratch buffers of every stream (synchronizes those streams). */
+int c3pt_release_scratch(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* C3PT_H */

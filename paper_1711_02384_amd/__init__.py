@@ -1,0 +1,241 @@
+"""Python binding of libc3pt: spin-open three-point contractions on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libc3pt.so``.  PyTorch supplies device memory and the current
+stream.  If the library is missing the import fails: there is no fallback.
+
+Entry points (same names as the C ABI in include/c3pt.h, without the prefix
+they are also exported as ``spectator_meson`` etc.):
+
+* ``c3pt_spectator_meson(G_tf, eta, k, geom)``      Eq. (9) spectator part
+* ``c3pt_spectator_baryon(G1_tf, G2_tf, eta, k, geom)``  epsilon-tensor spectator
+* ``c3pt_insertion(G_t, s_t, taus, k, geom, U_t=None, n_ops=1)``  Eq. (10)
+* ``c3pt_combine(spec, ins, ...)``                 noise-weighted product
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libc3pt.so")
+
+C3PT_OK = 0
+C3PT_EINVAL = -1
+C3PT_ENOMEM = -2
+C3PT_EDEVICE = -3
+C3PT_EUNSUPPORTED = -4
+C3PT_C64 = 0
+C3PT_C128 = 1
+PROJ_NATIVE = 0
+PROJ_SPLIT_F16 = 1
+PROJ_SPLIT_BF16 = 2
+
+EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
+            "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
+            "c3pt_release_scratch")
+
+
+class C3ptError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"c3pt status {status}: {msg}")
+        self.status = status
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 3), ("T", ctypes.c_int), ("r", ctypes.c_int * 3),
+                ("dtype", ctypes.c_int), ("proj", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1711_02384_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, i = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int
+    gp = ctypes.POINTER(_Geom)
+    lib.c3pt_spectator_meson.argtypes = [gp, vp, vp, i, ip, i, vp]
+    lib.c3pt_spectator_baryon.argtypes = [gp, vp, vp, vp, i, ip, i, vp]
+    lib.c3pt_insertion.argtypes = [gp, ctypes.POINTER(vp), ctypes.POINTER(vp), i, ip, i,
+                                   ctypes.POINTER(vp), i, ip, i, vp]
+    lib.c3pt_combine.argtypes = [vp, i, vp, i, i, i, i, i, i, i, ctypes.POINTER(ctypes.c_double), ip, i,
+                                 vp, vp]
+    for name in ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.c3pt_strerror.argtypes = [i]
+    lib.c3pt_strerror.restype = ctypes.c_char_p
+    lib.c3pt_last_error.argtypes = []
+    lib.c3pt_last_error.restype = ctypes.c_char_p
+    lib.c3pt_version.restype = ctypes.c_int
+    lib.c3pt_scratch_bytes.argtypes = [vp]
+    lib.c3pt_scratch_bytes.restype = ctypes.c_ulonglong
+    lib.c3pt_release_scratch.restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != C3PT_OK:
+        raise C3ptError(rc, lib.c3pt_last_error().decode() or lib.c3pt_strerror(rc).decode())
+
+
+@dataclass
+class Geom:
+    """Lattice geometry and execution options of one call (c3pt_geom)."""
+    L: Sequence[int]
+    T: int
+    r: Sequence[int] = (0, 0, 0)
+    proj: int = PROJ_NATIVE
+    stream: Optional[int] = None      # raw hipStream_t; None = torch's current stream
+
+    def c(self, dtype: torch.dtype) -> _Geom:
+        g = _Geom()
+        for j in range(3):
+            g.L[j] = int(self.L[j])
+            g.r[j] = int(self.r[j])
+        g.T = int(self.T)
+        g.dtype = C3PT_C128 if dtype == torch.complex128 else C3PT_C64
+        g.proj = int(self.proj)
+        st = self.stream if self.stream is not None else torch.cuda.current_stream().cuda_stream
+        g.stream = ctypes.c_void_p(st)
+        return g
+
+    @property
+    def V3(self) -> int:
+        return int(self.L[0]) * int(self.L[1]) * int(self.L[2])
+
+
+def _field(t: torch.Tensor, name: str, shape, dtype) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _momenta(k):
+    import numpy as np
+    ka = np.ascontiguousarray(np.asarray(k, dtype=np.int32).reshape(-1, 3))
+    return ka, ka.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ka.shape[0]
+
+
+def _out(out, shape, like: torch.Tensor):
+    if out is None:
+        return torch.empty(shape, dtype=torch.complex128, device=like.device)
+    _field(out, "out", shape, torch.complex128)
+    return out
+
+
+def c3pt_spectator_meson(G_tf: torch.Tensor, eta: torch.Tensor, k, geom: Geom, out=None) -> torch.Tensor:
+    """Meson spectator, Eq. (9).  G_tf [12,12,V3], eta [N,12,V3] -> [N, n_mom, 192] complex128."""
+    V3 = geom.V3
+    N = eta.shape[0]
+    _field(G_tf, "G_tf", (12, 12, V3), G_tf.dtype)
+    _field(eta, "eta", (N, 12, V3), G_tf.dtype)
+    ka, kp, n_mom = _momenta(k)
+    out = _out(out, (N, n_mom, 192), G_tf)
+    g = geom.c(G_tf.dtype)
+    _check(lib.c3pt_spectator_meson(ctypes.byref(g), G_tf.data_ptr(), eta.data_ptr(), N, kp, n_mom,
+                                    out.data_ptr()))
+    return out
+
+
+def c3pt_spectator_baryon(G1_tf: torch.Tensor, G2_tf: torch.Tensor, eta: torch.Tensor, k, geom: Geom,
+                          out=None) -> torch.Tensor:
+    """Epsilon-tensor (nucleon-type) spectator -> [N, n_mom, 3072] complex128."""
+    V3 = geom.V3
+    N = eta.shape[0]
+    _field(G1_tf, "G1_tf", (12, 12, V3), G1_tf.dtype)
+    _field(G2_tf, "G2_tf", (12, 12, V3), G1_tf.dtype)
+    _field(eta, "eta", (N, 12, V3), G1_tf.dtype)
+    ka, kp, n_mom = _momenta(k)
+    out = _out(out, (N, n_mom, 3072), G1_tf)
+    g = geom.c(G1_tf.dtype)
+    _check(lib.c3pt_spectator_baryon(ctypes.byref(g), G1_tf.data_ptr(), G2_tf.data_ptr(), eta.data_ptr(),
+                                     N, kp, n_mom, out.data_ptr()))
+    return out
+
+
+def _slice_table(slices, T: int, name: str, shape, dtype):
+    arr = (ctypes.c_void_p * T)()
+    if slices is None:
+        return arr
+    items = slices.items() if isinstance(slices, dict) else enumerate(slices)
+    for t, x in items:
+        if x is None:
+            continue
+        if not 0 <= int(t) < T:
+            raise ValueError(f"{name}: timeslice {t} outside [0, {T})")
+        arr[int(t)] = _field(x, f"{name}[{t}]", shape, dtype)
+    return arr
+
+
+def c3pt_insertion(G_t, s_t, taus, k, geom: Geom, U_t=None, n_ops: int = 1, out=None) -> torch.Tensor:
+    """Insertion, Eq. (10), for every tau in taus.
+
+    G_t, s_t, U_t: dict or list indexed by timeslice t (missing / None allowed
+    where not needed); G_t[t] [12,12,V3], s_t[t] [N,12,V3], U_t[t] [4,3,3,V3].
+    Returns [N, n_tau, n_ops, n_mom, 192] complex128."""
+    V3, T = geom.V3, int(geom.T)
+    taus = [int(t) for t in taus]
+    first = (s_t[taus[0]])
+    N = first.shape[0]
+    dtype = first.dtype
+    Gtab = _slice_table(G_t, T, "G_t", (12, 12, V3), dtype)
+    stab = _slice_table(s_t, T, "s_t", (N, 12, V3), dtype)
+    Utab = _slice_table(U_t, T, "U_t", (4, 3, 3, V3), dtype) if U_t is not None else None
+    ka, kp, n_mom = _momenta(k)
+    out = _out(out, (N, len(taus), n_ops, n_mom, 192), first)
+    tau_arr = (ctypes.c_int * len(taus))(*taus)
+    g = geom.c(dtype)
+    _check(lib.c3pt_insertion(ctypes.byref(g), Gtab, stab, N, tau_arr, len(taus),
+                              Utab if Utab is not None else None, n_ops, kp, n_mom, out.data_ptr()))
+    return out
+
+
+def c3pt_combine(spec: torch.Tensor, ins: torch.Tensor, w=None, pairs=None, op_begin: int = 0,
+                 op_end: Optional[int] = None, out=None, stream: Optional[int] = None) -> torch.Tensor:
+    """Noise-weighted product of spectator [N, n_p, spin*3] and insertion
+    [N, n_tau, n_ops, n_q, 192] -> [n_pairs, n_tau, n_sel, spin, 64] complex128."""
+    import numpy as np
+    N, n_p, sc = spec.shape
+    spin = sc // 3
+    _, n_tau, n_ops, n_q, _ = ins.shape
+    _field(spec, "spec", (N, n_p, sc), torch.complex128)
+    _field(ins, "ins", (N, n_tau, n_ops, n_q, 192), torch.complex128)
+    op_end = n_ops if op_end is None else int(op_end)
+    wp = None
+    if w is not None:
+        wa = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(N))
+        wp = wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if pairs is None:
+        n_pairs, pp = n_p * n_q, None
+    else:
+        pa = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        n_pairs, pp = pa.shape[0], pa.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    out = _out(out, (n_pairs, n_tau, op_end - op_begin, spin, 64), spec)
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(lib.c3pt_combine(spec.data_ptr(), spin, ins.data_ptr(), N, n_p, n_q, n_tau, n_ops, op_begin,
+                            op_end, wp, pp, n_pairs, out.data_ptr(), ctypes.c_void_p(st)))
+    return out
+
+
+spectator_meson = c3pt_spectator_meson
+spectator_baryon = c3pt_spectator_baryon
+insertion = c3pt_insertion
+combine = c3pt_combine
+
+
+def version() -> int:
+    return int(lib.c3pt_version())

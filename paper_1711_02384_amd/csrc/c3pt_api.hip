@@ -1,0 +1,411 @@
+// Host side of libc3pt: argument validation, per-stream scratch, launch
+// planning.  Every entry point validates all arguments before it touches the
+// device, so a failing call enqueues nothing and leaves the output untouched.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/c3pt.h"
+#include "c3pt_internal.h"
+
+using namespace c3pt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int ok() {
+    g_last_error.clear();
+    return C3PT_OK;
+}
+
+// Per-(device, stream) scratch: device memory for split-site partial sums and
+// small parameter tables, plus a pinned staging buffer for host->device
+// parameter uploads guarded by an event.
+struct Scratch {
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t ev = nullptr;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Scratch> g_scratch;
+
+int current_device(int* dev) {
+    if (hipGetDevice(dev) != hipSuccess) return fail(C3PT_EDEVICE, "hipGetDevice failed");
+    return C3PT_OK;
+}
+
+// Ensure at least `bytes` of device scratch for (device, stream). Growing
+// synchronizes the stream so that no enqueued kernel still reads the old buffer.
+int scratch_dev(hipStream_t st, size_t bytes, void** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch& s = g_scratch[{dev, st}];
+    if (s.dev_bytes < bytes) {
+        if (s.dev) {
+            if (hipStreamSynchronize(st) != hipSuccess) return fail(C3PT_EDEVICE, "stream sync failed");
+            hipFree(s.dev);
+            s.dev = nullptr;
+            s.dev_bytes = 0;
+        }
+        size_t want = std::max(bytes, (size_t)1 << 20);
+        want = (want + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+        if (hipMalloc(&s.dev, want) != hipSuccess) {
+            (void)hipGetLastError();
+            s.dev = nullptr;
+            return fail(C3PT_ENOMEM, "scratch allocation of %zu bytes failed", want);
+        }
+        s.dev_bytes = want;
+    }
+    *out = s.dev;
+    return C3PT_OK;
+}
+
+// Copy `bytes` of host data into device scratch at byte offset `off` through the
+// pinned staging buffer; the event orders reuse of the staging buffer.
+int upload(hipStream_t st, void* dev_base, size_t off, const void* host, size_t bytes) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch& s = g_scratch[{dev, st}];
+    if (!s.ev) {
+        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess)
+            return fail(C3PT_EDEVICE, "event creation failed");
+    } else if (hipEventSynchronize(s.ev) != hipSuccess) {
+        return fail(C3PT_EDEVICE, "event sync failed");
+    }
+    if (s.pinned_bytes < bytes) {
+        if (s.pinned) hipHostFree(s.pinned);
+        s.pinned = nullptr;
+        s.pinned_bytes = 0;
+        size_t want = std::max(bytes, (size_t)65536);
+        if (hipHostMalloc(&s.pinned, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s.pinned = nullptr;
+            return fail(C3PT_ENOMEM, "pinned staging allocation failed");
+        }
+        s.pinned_bytes = want;
+    }
+    memcpy(s.pinned, host, bytes);
+    if (hipMemcpyAsync((char*)dev_base + off, s.pinned, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return fail(C3PT_EDEVICE, "parameter upload failed");
+    if (hipEventRecord(s.ev, st) != hipSuccess) return fail(C3PT_EDEVICE, "event record failed");
+    return C3PT_OK;
+}
+
+int check_geom(const c3pt_geom* g) {
+    if (!g) return fail(C3PT_EINVAL, "geom is NULL");
+    for (int j = 0; j < 3; ++j)
+        if (g->L[j] < 1 || g->L[j] > C3PT_MAX_L)
+            return fail(C3PT_EINVAL, "L[%d] = %d outside [1, %d]", j, g->L[j], C3PT_MAX_L);
+    if (g->T < 1) return fail(C3PT_EINVAL, "T = %d < 1", g->T);
+    if (g->dtype != C3PT_C64 && g->dtype != C3PT_C128) return fail(C3PT_EINVAL, "unknown dtype %d", g->dtype);
+    if (g->proj != C3PT_PROJ_NATIVE && g->proj != C3PT_PROJ_SPLIT_F16 && g->proj != C3PT_PROJ_SPLIT_BF16)
+        return fail(C3PT_EINVAL, "unknown projection mode %d", g->proj);
+    if (g->proj != C3PT_PROJ_NATIVE && g->dtype != C3PT_C64)
+        return fail(C3PT_EINVAL, "split-precision projection needs complex64 inputs");
+    if (g->proj != C3PT_PROJ_NATIVE)
+        return fail(C3PT_EUNSUPPORTED, "split-precision projection is not available in this build");
+    return C3PT_OK;
+}
+
+int check_momenta(const int* k, int n_mom) {
+    if (n_mom < 1 || n_mom > C3PT_MAX_MOM)
+        return fail(C3PT_EINVAL, "n_mom = %d outside [1, %d]", n_mom, C3PT_MAX_MOM);
+    if (!k) return fail(C3PT_EINVAL, "momentum list is NULL");
+    return C3PT_OK;
+}
+
+int posmod(long long v, int L) {
+    long long r = v % L;
+    return (int)(r < 0 ? r + L : r);
+}
+
+// Momentum groups: FP32 launches take up to 96 momenta, FP64 up to 32.
+struct MomGroup {
+    int off, n;
+};
+
+std::vector<MomGroup> momentum_groups(int n_mom, bool f64) {
+    const int gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
+    std::vector<MomGroup> g;
+    for (int off = 0; off < n_mom; off += gmax) g.push_back({off, std::min(gmax, n_mom - off)});
+    return g;
+}
+
+void fill_phase(PhaseSpec& ph, const c3pt_geom* g, int sigma, const int* k, const MomGroup& mg) {
+    memset(&ph, 0, sizeof(ph));
+    for (int j = 0; j < 3; ++j) {
+        ph.L[j] = g->L[j];
+        ph.r[j] = posmod(g->r[j], g->L[j]);
+    }
+    ph.sigma = sigma;
+    ph.cubic = (g->L[0] == g->L[1] && g->L[1] == g->L[2]) ? 1 : 0;
+    ph.n_mom = mg.n;
+    for (int m = 0; m < mg.n; ++m)
+        for (int j = 0; j < 3; ++j) ph.k[j][m] = (uint8_t)posmod(k[3 * (mg.off + m) + j], g->L[j]);
+}
+
+// Sites per split-site chunk: enough chunks to fill the chip, never more than
+// kMaxSitesPerChunkF32 sites in one FP32 partial sum.
+void plan_chunks(int V3, int n_colblocks, bool f64, int* chunk_sites, int* n_chunks) {
+    const int kt = f64 ? 16 : 32;
+    const int tiles = (V3 + kt - 1) / kt;
+    const int target_wg = 2048;
+    int chunks = std::max(1, (target_wg + n_colblocks - 1) / n_colblocks);
+    chunks = std::min(chunks, tiles);
+    const int max_sites = f64 ? (1 << 30) : kMaxSitesPerChunkF32;
+    chunks = std::max(chunks, (V3 + max_sites - 1) / max_sites);
+    int tiles_per_chunk = (tiles + chunks - 1) / chunks;
+    *chunk_sites = tiles_per_chunk * kt;
+    *n_chunks = (V3 + *chunk_sites - 1) / *chunk_sites;
+}
+
+int to_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return C3PT_OK;
+    return fail(C3PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Runs projection launches over momentum groups and reduces each into `out`.
+// `launch(pg, mt)` enqueues one fused kernel for the grid pg.
+template <class Launch>
+int run_projection(const c3pt_geom* g, int sigma, const int* k, int n_mom, int n_colblocks,
+                   int group_cols, int n_groups, int inner, int outer_stride, int off,
+                   void* out, Launch launch) {
+    hipStream_t st = (hipStream_t)g->stream;
+    const bool f64 = g->dtype == C3PT_C128;
+    const int V3 = g->L[0] * g->L[1] * g->L[2];
+    auto groups = momentum_groups(n_mom, f64);
+    int chunk_sites, n_chunks;
+    plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks);
+    const size_t gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
+    const size_t bytes = (size_t)n_chunks * n_colblocks * gmax * kBlockCols * sizeof(double2);
+    void* part;
+    if (int rc = scratch_dev(st, bytes, &part)) return rc;
+    for (const MomGroup& mg : groups) {
+        ProjGrid pg;
+        fill_phase(pg.ph, g, sigma, k, mg);
+        pg.V3 = V3;
+        pg.chunk_sites = chunk_sites;
+        pg.n_chunks = n_chunks;
+        pg.n_colblocks = n_colblocks;
+        pg.partial = (double2*)part;
+        const int mt = (mg.n + 7) / 8;
+        if (int rc = to_status(launch(pg, mt), "projection launch")) return rc;
+        ReduceArgs ra;
+        ra.partial = (const double2*)part;
+        ra.out = (double2*)out;
+        ra.n_chunks = n_chunks;
+        ra.n_colblocks = n_colblocks;
+        ra.n_groups = n_groups;
+        ra.group_cols = group_cols;
+        ra.n_mom_grp = mg.n;
+        ra.n_mom_total = n_mom;
+        ra.m_off = mg.off;
+        ra.inner = inner;
+        ra.outer_stride = outer_stride;
+        ra.off = off;
+        if (int rc = to_status(launch_reduce(ra, st), "reduction launch")) return rc;
+    }
+    return C3PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int c3pt_version(void) { return 100; }
+
+const char* c3pt_strerror(int status) {
+    switch (status) {
+        case C3PT_OK: return "success";
+        case C3PT_EINVAL: return "invalid argument";
+        case C3PT_ENOMEM: return "out of device memory";
+        case C3PT_EDEVICE: return "device error";
+        case C3PT_EUNSUPPORTED: return "unsupported request";
+        default: return "unknown status";
+    }
+}
+
+const char* c3pt_last_error(void) { return g_last_error.c_str(); }
+
+unsigned long long c3pt_scratch_bytes(void* stream) {
+    int dev;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_scratch.find({dev, (hipStream_t)stream});
+    return it == g_scratch.end() ? 0ull : (unsigned long long)it->second.dev_bytes;
+}
+
+int c3pt_release_scratch(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return fail(C3PT_EDEVICE, "hipGetDevice failed");
+    for (auto& kv : g_scratch) {
+        hipSetDevice(kv.first.first);
+        hipStreamSynchronize(kv.first.second);
+        if (kv.second.dev) hipFree(kv.second.dev);
+        if (kv.second.pinned) hipHostFree(kv.second.pinned);
+        if (kv.second.ev) hipEventDestroy(kv.second.ev);
+    }
+    g_scratch.clear();
+    hipSetDevice(cur);
+    return ok();
+}
+
+int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* eta, int n_noise,
+                         const int* k, int n_mom, void* out) {
+    if (int rc = check_geom(geom)) return rc;
+    if (int rc = check_momenta(k, n_mom)) return rc;
+    if (!G_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
+    if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    MesonSpecArgs a{G_tf, eta};
+    const bool f64 = geom->dtype == C3PT_C128;
+    int rc = run_projection(geom, -1, k, n_mom, n_noise, kBlockCols, n_noise, n_noise, 0, 0, out,
+                            [&](const ProjGrid& pg, int mt) {
+                                return launch_spectator_meson(f64, mt, pg, a, (hipStream_t)geom->stream);
+                            });
+    return rc ? rc : ok();
+}
+
+int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* G2_tf,
+                          const void* eta, int n_noise, const int* k, int n_mom, void* out) {
+    if (int rc = check_geom(geom)) return rc;
+    if (int rc = check_momenta(k, n_mom)) return rc;
+    if (!G1_tf || !G2_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
+    if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    BaryonSpecArgs a{G1_tf, G2_tf, eta};
+    const bool f64 = geom->dtype == C3PT_C128;
+    int rc = run_projection(geom, -1, k, n_mom, n_noise * 16, 3072, n_noise, n_noise, 0, 0, out,
+                            [&](const ProjGrid& pg, int mt) {
+                                return launch_spectator_baryon(f64, mt, pg, a, (hipStream_t)geom->stream);
+                            });
+    return rc ? rc : ok();
+}
+
+int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* const* s_t,
+                   int n_noise, const int* taus, int n_tau, const void* const* U_t, int n_ops,
+                   const int* k, int n_mom, void* out) {
+    if (int rc = check_geom(geom)) return rc;
+    if (int rc = check_momenta(k, n_mom)) return rc;
+    if (!G_t || !s_t || !out) return fail(C3PT_EINVAL, "NULL pointer table or output");
+    if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    if (n_tau < 1 || !taus) return fail(C3PT_EINVAL, "empty timeslice list");
+    if (n_ops != 1 && n_ops != 5) return fail(C3PT_EINVAL, "n_ops = %d (must be 1 or 5)", n_ops);
+    if (n_ops == 5 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
+    const int T = geom->T;
+    for (int j = 0; j < n_tau; ++j) {
+        const int t = taus[j];
+        if (t < 0 || t >= T) return fail(C3PT_EINVAL, "taus[%d] = %d outside [0, %d)", j, t, T);
+        if (!G_t[t]) return fail(C3PT_EINVAL, "propagator slice %d missing", t);
+        if (!s_t[t]) return fail(C3PT_EINVAL, "stochastic solution slice %d missing", t);
+        if (n_ops == 5) {
+            const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
+            if (!G_t[tn] || !G_t[tp])
+                return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp, tn, t);
+            if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
+        }
+    }
+    const bool f64 = geom->dtype == C3PT_C128;
+    for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
+        const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
+        InsertionArgs a;
+        memset(&a, 0, sizeof(a));
+        a.n_tau = nt;
+        a.n_ops = n_ops;
+        a.n_noise = n_noise;
+        for (int j = 0; j < nt; ++j) {
+            const int t = taus[j0 + j];
+            const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
+            a.G[j] = G_t[t];
+            a.s[j] = s_t[t];
+            if (n_ops == 5) {
+                a.Gn[j] = G_t[tn];
+                a.Gp[j] = G_t[tp];
+                a.U[j] = U_t[t];
+                a.Up[j] = U_t[tp];
+            }
+        }
+        const int ncb = n_noise * nt * n_ops;
+        int rc = run_projection(geom, +1, k, n_mom, ncb, kBlockCols, ncb, nt * n_ops, n_tau * n_ops,
+                                j0 * n_ops, out, [&](const ProjGrid& pg, int mt) {
+                                    return launch_insertion(f64, mt, pg, a, (hipStream_t)geom->stream);
+                                });
+        if (rc) return rc;
+    }
+    return ok();
+}
+
+int c3pt_combine(const void* spec, int spec_spin, const void* ins, int n_noise, int n_p, int n_q,
+                 int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
+                 int n_pairs, void* out, void* stream) {
+    if (!spec || !ins || !out) return fail(C3PT_EINVAL, "NULL input or output pointer");
+    if (spec_spin != 64 && spec_spin != 1024) return fail(C3PT_EINVAL, "spec_spin = %d (64 or 1024)", spec_spin);
+    if (n_noise < 1 || n_p < 1 || n_q < 1 || n_tau < 1 || n_ops < 1)
+        return fail(C3PT_EINVAL, "extents must be >= 1");
+    if (op_begin < 0 || op_end > n_ops || op_begin >= op_end)
+        return fail(C3PT_EINVAL, "operator range [%d, %d) invalid for n_ops = %d", op_begin, op_end, n_ops);
+    if (!pairs) {
+        if (n_pairs != n_p * n_q) return fail(C3PT_EINVAL, "n_pairs must be n_p*n_q when pairs is NULL");
+    } else {
+        if (n_pairs < 1) return fail(C3PT_EINVAL, "n_pairs = %d < 1", n_pairs);
+        for (int j = 0; j < n_pairs; ++j)
+            if (pairs[2 * j] < 0 || pairs[2 * j] >= n_p || pairs[2 * j + 1] < 0 || pairs[2 * j + 1] >= n_q)
+                return fail(C3PT_EINVAL, "pair %d = (%d, %d) out of range", j, pairs[2 * j], pairs[2 * j + 1]);
+    }
+    if ((long long)n_pairs * n_tau * (op_end - op_begin) > 0x7fffffffLL)
+        return fail(C3PT_EINVAL, "too many (pair, tau, op) tiles");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> wv(n_noise);
+    for (int i = 0; i < n_noise; ++i) wv[i] = w ? w[i] : 1.0 / n_noise;
+    const size_t wbytes = (size_t)n_noise * sizeof(double);
+    const size_t pbytes = pairs ? (size_t)n_pairs * 2 * sizeof(int) : 0;
+    const size_t woff = 0, poff = (wbytes + 255) & ~(size_t)255;
+    // Weights and pairs go to the start of this stream's scratch; kernels of
+    // earlier calls on the same stream that use it are ordered before the upload.
+    void* base;
+    if (int rc = scratch_dev(st, poff + pbytes + 256, &base)) return rc;
+    std::vector<char> host(poff + pbytes);
+    memcpy(host.data() + woff, wv.data(), wbytes);
+    if (pairs) memcpy(host.data() + poff, pairs, pbytes);
+    if (int rc = upload(st, base, 0, host.data(), host.size())) return rc;
+    CombineArgs a;
+    a.S = (const double2*)spec;
+    a.I = (const double2*)ins;
+    a.w = (const double*)base;
+    a.pairs = pairs ? (const int*)((char*)base + poff) : nullptr;
+    a.out = (double2*)out;
+    a.n_noise = n_noise;
+    a.n_p = n_p;
+    a.n_q = n_q;
+    a.n_tau = n_tau;
+    a.n_ops = n_ops;
+    a.op_begin = op_begin;
+    a.n_sel = op_end - op_begin;
+    a.spin = spec_spin;
+    a.n_pairs = n_pairs;
+    if (int rc = to_status(launch_combine(a, st), "combine launch")) return rc;
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "c3pt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(c3pt_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1711_02384_amd as c
+    names = _declared()
+    assert "c3pt_spectator_meson" in names and "c3pt_combine" in names
+    for n in names:
+        assert hasattr(c.lib, n), n
+    assert set(names) == set(c.EXPORTED)
+
+
+def _geom(c, **kw):
+    g = c._Geom()
+    L = kw.get("L", (4, 4, 4))
+    for j in range(3):
+        g.L[j] = L[j]
+        g.r[j] = 0
+    g.T = kw.get("T", 8)
+    g.dtype = kw.get("dtype", 0)
+    g.proj = kw.get("proj", 0)
+    g.stream = None
+    return g
+
+
+def _k(n=1):
+    a = np.zeros((n, 3), dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+DUMMY = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("bad", ["L0", "Lbig", "T0", "dtype", "proj", "split_c128", "nmom0", "nmombig",
+                                 "noise0", "nullG"])
+def test_spectator_rejects_bad_arguments(bad):
+    import paper_1711_02384_amd as c
+    kw = {}
+    n_mom, n_noise, G = 1, 1, DUMMY
+    if bad == "L0":
+        kw["L"] = (0, 4, 4)
+    elif bad == "Lbig":
+        kw["L"] = (4, 257, 4)
+    elif bad == "T0":
+        kw["T"] = 0
+    elif bad == "dtype":
+        kw["dtype"] = 7
+    elif bad == "proj":
+        kw["proj"] = 9
+    elif bad == "split_c128":
+        kw["dtype"], kw["proj"] = 1, 1
+    elif bad == "nmom0":
+        n_mom = 0
+    elif bad == "nmombig":
+        n_mom = 257
+    elif bad == "noise0":
+        n_noise = 0
+    elif bad == "nullG":
+        G = None
+    g = _geom(c, **kw)
+    ka, kp = _k(max(n_mom, 1))
+    rc = c.lib.c3pt_spectator_meson(ctypes.byref(g), G, DUMMY, n_noise, kp, n_mom, DUMMY)
+    assert rc == c.C3PT_EINVAL, (bad, rc)
+    assert c.lib.c3pt_last_error().decode()
+    rc = c.lib.c3pt_spectator_baryon(ctypes.byref(g), G, DUMMY, DUMMY, n_noise, kp, n_mom, DUMMY)
+    assert rc == c.C3PT_EINVAL
+
+
+def test_insertion_rejects_missing_slices():
+    import paper_1711_02384_amd as c
+    g = _geom(c, T=4)
+    ka, kp = _k(2)
+    Gt = (ctypes.c_void_p * 4)(0x1000, 0x1000, None, 0x1000)
+    st = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    Ut = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    taus = (ctypes.c_int * 2)(0, 1)
+    # local op: slices 0, 1 present -> only a later device error could occur, so
+    # test the derivative op, which needs G at tau+1 = 2 (missing)
+    rc = c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus, 2, Ut, 5, kp, 2, DUMMY)
+    assert rc == c.C3PT_EINVAL
+    assert "needed" in c.lib.c3pt_last_error().decode()
+    taus_bad = (ctypes.c_int * 1)(4)
+    assert c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus_bad, 1, None, 1, kp, 2, DUMMY) == c.C3PT_EINVAL
+    assert c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus, 2, None, 5, kp, 2, DUMMY) == c.C3PT_EINVAL
+    assert c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus, 2, None, 3, kp, 2, DUMMY) == c.C3PT_EINVAL
+    assert c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus, 0, None, 1, kp, 2, DUMMY) == c.C3PT_EINVAL
+
+
+def test_combine_rejects_bad_arguments():
+    import paper_1711_02384_amd as c
+    L = c.lib
+    pairs = (ctypes.c_int * 4)(0, 0, 3, 0)     # p' = 3 out of range for n_p = 2
+    assert L.c3pt_combine(DUMMY, 64, DUMMY, 1, 2, 2, 1, 1, 0, 1, None, pairs, 2, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_combine(DUMMY, 65, DUMMY, 1, 2, 2, 1, 1, 0, 1, None, None, 4, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_combine(DUMMY, 64, DUMMY, 1, 2, 2, 1, 1, 0, 1, None, None, 3, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_combine(DUMMY, 64, DUMMY, 1, 2, 2, 1, 5, 2, 2, None, None, 4, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_combine(DUMMY, 64, DUMMY, 1, 2, 2, 1, 5, 0, 6, None, None, 4, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_combine(None, 64, DUMMY, 1, 2, 2, 1, 1, 0, 1, None, None, 4, DUMMY, None) == c.C3PT_EINVAL
+
+
+def test_status_strings():
+    import paper_1711_02384_amd as c
+    for s in (0, -1, -2, -3, -4):
+        assert c.lib.c3pt_strerror(s)
+    assert c.version() >= 100
