@@ -163,6 +163,26 @@ unsigned long long c3pt_scratch_bytes(void* stream);
 /* Release the scratch buffers of every stream (synchronizes those streams). */
 int c3pt_release_scratch(void);
 
+/*
+ * Kernel timing.  While enabled, every kernel the library launches is
+ * bracketed by a pair of HIP events on its stream.  c3pt_profile_read()
+ * synchronizes those events, folds them into per-kernel statistics and copies
+ * up to `max` entries into `stats` (returns the number of kernels seen, or a
+ * negative status).  `reset` != 0 clears the statistics after copying.
+ * Names: "proj_spectator_meson", "proj_spectator_baryon", "proj_insertion",
+ * "reduce", "combine".
+ */
+typedef struct c3pt_kernel_stat {
+    char      name[48];
+    long long count;
+    double    total_ms;
+    double    min_ms;
+    double    max_ms;
+} c3pt_kernel_stat;
+
+int c3pt_profile_enable(int on);
+int c3pt_profile_read(c3pt_kernel_stat* stats, int max, int reset);
+
 #ifdef __cplusplus
 }
 #endif

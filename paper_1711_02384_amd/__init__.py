@@ -37,13 +37,18 @@ PROJ_SPLIT_BF16 = 2
 
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
             "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
-            "c3pt_release_scratch")
+            "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read")
 
 
 class C3ptError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"c3pt status {status}: {msg}")
         self.status = status
+
+
+class _KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("count", ctypes.c_longlong), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
 class _Geom(ctypes.Structure):
@@ -53,7 +58,7 @@ class _Geom(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1711_02384_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1711_02384_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     vp, ip, i = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int
     gp = ctypes.POINTER(_Geom)
@@ -73,6 +78,10 @@ def _load():
     lib.c3pt_scratch_bytes.argtypes = [vp]
     lib.c3pt_scratch_bytes.restype = ctypes.c_ulonglong
     lib.c3pt_release_scratch.restype = ctypes.c_int
+    lib.c3pt_profile_enable.argtypes = [i]
+    lib.c3pt_profile_enable.restype = ctypes.c_int
+    lib.c3pt_profile_read.argtypes = [ctypes.POINTER(_KernelStat), i, i]
+    lib.c3pt_profile_read.restype = ctypes.c_int
     return lib
 
 
@@ -237,5 +246,40 @@ insertion = c3pt_insertion
 combine = c3pt_combine
 
 
+def momentum_list(n2max: int):
+    """Integer momenta k with |k|^2 <= n2max as an int32 array [n][3], ordered by
+    |k|^2, then k1, k2, k3 (p = 2 pi k / L)."""
+    import numpy as np
+    kmax = 0
+    while (kmax + 1) * (kmax + 1) <= n2max:
+        kmax += 1
+    rng = np.arange(-kmax, kmax + 1)
+    k1, k2, k3 = np.meshgrid(rng, rng, rng, indexing="ij")
+    ks = np.stack([k1.ravel(), k2.ravel(), k3.ravel()], axis=1)
+    n2 = (ks * ks).sum(axis=1)
+    ks, n2 = ks[n2 <= n2max], n2[n2 <= n2max]
+    order = np.lexsort((ks[:, 2], ks[:, 1], ks[:, 0], n2))
+    return np.ascontiguousarray(ks[order].astype(np.int32))
+
+
 def version() -> int:
     return int(lib.c3pt_version())
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every library kernel with HIP events on its stream (c3pt_profile_enable)."""
+    _check(lib.c3pt_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = False) -> dict:
+    """Per-kernel {name: {count, total_ms, min_ms, max_ms, avg_ms}} (c3pt_profile_read)."""
+    arr = (_KernelStat * 64)()
+    n = lib.c3pt_profile_read(arr, 64, 1 if reset else 0)
+    if n < 0:
+        _check(n)
+    out = {}
+    for j in range(min(n, 64)):
+        s = arr[j]
+        out[s.name.decode()] = {"count": int(s.count), "total_ms": s.total_ms, "min_ms": s.min_ms,
+                                "max_ms": s.max_ms, "avg_ms": s.total_ms / max(1, s.count)}
+    return out

@@ -1,6 +1,7 @@
 """Build libc3pt.so (HIP, gfx950) in-tree.
 
-Usage: python -m paper_1711_02384_amd.build  [--debug]
+Usage: python paper_1711_02384_amd/build.py  [--debug]
+(run as a file: importing the package itself loads the library this builds)
 """
 from __future__ import annotations
 

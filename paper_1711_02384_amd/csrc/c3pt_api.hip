@@ -113,6 +113,39 @@ int upload(hipStream_t st, void* dev_base, size_t off, const void* host, size_t 
     return C3PT_OK;
 }
 
+// ---- kernel timing -------------------------------------------------------
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+struct ProfStat {
+    long long count = 0;
+    double total = 0, mn = 1e300, mx = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::map<std::string, ProfStat> g_prof_stats;
+
+// Launch `fn` on `st`, bracketed by timing events when profiling is enabled.
+template <class F>
+hipError_t timed(const char* name, hipStream_t st, F fn) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    if (!on) return fn();
+    ProfRec r{name, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return hipErrorOutOfMemory;
+    hipEventRecord(r.a, st);
+    hipError_t e = fn();
+    hipEventRecord(r.b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(r);
+    return e;
+}
+
 int check_geom(const c3pt_geom* g) {
     if (!g) return fail(C3PT_EINVAL, "geom is NULL");
     for (int j = 0; j < 3; ++j)
@@ -189,7 +222,7 @@ int to_status(hipError_t e, const char* what) {
 // Runs projection launches over momentum groups and reduces each into `out`.
 // `launch(pg, mt)` enqueues one fused kernel for the grid pg.
 template <class Launch>
-int run_projection(const c3pt_geom* g, int sigma, const int* k, int n_mom, int n_colblocks,
+int run_projection(const char* kname, const c3pt_geom* g, int sigma, const int* k, int n_mom, int n_colblocks,
                    int group_cols, int n_groups, int inner, int outer_stride, int off,
                    void* out, Launch launch) {
     hipStream_t st = (hipStream_t)g->stream;
@@ -211,7 +244,8 @@ int run_projection(const c3pt_geom* g, int sigma, const int* k, int n_mom, int n
         pg.n_colblocks = n_colblocks;
         pg.partial = (double2*)part;
         const int mt = (mg.n + 7) / 8;
-        if (int rc = to_status(launch(pg, mt), "projection launch")) return rc;
+        if (int rc = to_status(timed(kname, st, [&] { return launch(pg, mt); }), "projection launch"))
+            return rc;
         ReduceArgs ra;
         ra.partial = (const double2*)part;
         ra.out = (double2*)out;
@@ -225,7 +259,8 @@ int run_projection(const c3pt_geom* g, int sigma, const int* k, int n_mom, int n
         ra.inner = inner;
         ra.outer_stride = outer_stride;
         ra.off = off;
-        if (int rc = to_status(launch_reduce(ra, st), "reduction launch")) return rc;
+        if (int rc = to_status(timed("reduce", st, [&] { return launch_reduce(ra, st); }), "reduction launch"))
+            return rc;
     }
     return C3PT_OK;
 }
@@ -273,6 +308,45 @@ int c3pt_release_scratch(void) {
     return ok();
 }
 
+int c3pt_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return ok();
+}
+
+int c3pt_profile_read(c3pt_kernel_stat* stats, int max, int reset) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (ProfRec& r : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            return fail(C3PT_EDEVICE, "timing event failed");
+        ProfStat& st = g_prof_stats[r.name];
+        st.count++;
+        st.total += ms;
+        st.mn = std::min(st.mn, (double)ms);
+        st.mx = std::max(st.mx, (double)ms);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    int n = 0;
+    for (auto& kv : g_prof_stats) {
+        if (stats && n < max) {
+            c3pt_kernel_stat& o = stats[n];
+            memset(&o, 0, sizeof(o));
+            strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+            o.count = kv.second.count;
+            o.total_ms = kv.second.total;
+            o.min_ms = kv.second.mn;
+            o.max_ms = kv.second.mx;
+        }
+        ++n;
+    }
+    if (reset) g_prof_stats.clear();
+    g_last_error.clear();
+    return n;
+}
+
 int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* eta, int n_noise,
                          const int* k, int n_mom, void* out) {
     if (int rc = check_geom(geom)) return rc;
@@ -281,7 +355,7 @@ int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* et
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     MesonSpecArgs a{G_tf, eta};
     const bool f64 = geom->dtype == C3PT_C128;
-    int rc = run_projection(geom, -1, k, n_mom, n_noise, kBlockCols, n_noise, n_noise, 0, 0, out,
+    int rc = run_projection("proj_spectator_meson", geom, -1, k, n_mom, n_noise, kBlockCols, n_noise, n_noise, 0, 0, out,
                             [&](const ProjGrid& pg, int mt) {
                                 return launch_spectator_meson(f64, mt, pg, a, (hipStream_t)geom->stream);
                             });
@@ -296,7 +370,7 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     BaryonSpecArgs a{G1_tf, G2_tf, eta};
     const bool f64 = geom->dtype == C3PT_C128;
-    int rc = run_projection(geom, -1, k, n_mom, n_noise * 16, 3072, n_noise, n_noise, 0, 0, out,
+    int rc = run_projection("proj_spectator_baryon", geom, -1, k, n_mom, n_noise * 16, 3072, n_noise, n_noise, 0, 0, out,
                             [&](const ProjGrid& pg, int mt) {
                                 return launch_spectator_baryon(f64, mt, pg, a, (hipStream_t)geom->stream);
                             });
@@ -347,7 +421,7 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             }
         }
         const int ncb = n_noise * nt * n_ops;
-        int rc = run_projection(geom, +1, k, n_mom, ncb, kBlockCols, ncb, nt * n_ops, n_tau * n_ops,
+        int rc = run_projection("proj_insertion", geom, +1, k, n_mom, ncb, kBlockCols, ncb, nt * n_ops, n_tau * n_ops,
                                 j0 * n_ops, out, [&](const ProjGrid& pg, int mt) {
                                     return launch_insertion(f64, mt, pg, a, (hipStream_t)geom->stream);
                                 });
@@ -404,7 +478,8 @@ int c3pt_combine(const void* spec, int spec_spin, const void* ins, int n_noise, 
     a.n_sel = op_end - op_begin;
     a.spin = spec_spin;
     a.n_pairs = n_pairs;
-    if (int rc = to_status(launch_combine(a, st), "combine launch")) return rc;
+    if (int rc = to_status(timed("combine", st, [&] { return launch_combine(a, st); }), "combine launch"))
+        return rc;
     return ok();
 }
 

@@ -42,14 +42,19 @@ __device__ __forceinline__ C2<R> cconj(C2<R> a) { return {a.x, -a.y}; }
 template <typename R>
 __device__ __forceinline__ C2<R> cscale(C2<R> a, R s) { return {a.x * s, a.y * s}; }
 
+// Accumulator layout of the 16x16x4 MFMAs on gfx950 (lane l, register j):
+//   FP32: D[4*(l/16) + j][l%16]        FP64: D[4*j + l/16][l%16]
+// kRowsByRegister selects the FP64 form.
 template <typename R> struct Mfma;
 template <> struct Mfma<float> {
+    static constexpr bool kRowsByRegister = false;
     typedef float acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
 template <> struct Mfma<double> {
+    static constexpr bool kRowsByRegister = true;
     typedef double acc_t __attribute__((ext_vector_type(4)));
     static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -396,15 +401,19 @@ proj_kernel(ProjGrid pg, typename ProdT<R, KT, 64 * WM * WN>::Args pa) {
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-    // A-operand selection: row r = lane & 15 -> momentum 8*rt + r/2, part r&1
-    // (0 = real row, 1 = imaginary row); K index lane>>4 -> site (lane>>5),
-    // component (lane>>4)&1 of P.  Real row: (phi_re, -phi_im); imaginary row:
-    // (phi_im, phi_re).
-    const int part = lane & 1, comp = (lane >> 4) & 1;
+    // A-operand rows: row r = lane & 15 of a 16-row tile holds (momentum
+    // 8*rt + m_off, part), part 0 = real row, 1 = imaginary row, arranged so that
+    // accumulator registers (0,1) / (2,3) of lane l are (re, im) of momenta
+    // 8*rt + 2*(l/16) and 8*rt + 2*(l/16) + 1 for both accumulator layouts.
+    // K index lane>>4 -> site (lane>>5), component (lane>>4)&1 of P.
+    // Real row: (phi_re, -phi_im); imaginary row: (phi_im, phi_re).
+    const int arow = lane & 15;
+    const int part = MF::kRowsByRegister ? ((arow >> 2) & 1) : (arow & 1);
+    const int a_moff = MF::kRowsByRegister ? (2 * (arow & 3) + (arow >> 3)) : (arow >> 1);
+    const int comp = (lane >> 4) & 1;
     const bool take_re = (part == comp);
     const bool negate = (part == 0) && (comp == 1);
     const int a_site = lane >> 5;
-    const int a_moff = (lane & 15) >> 1;
 
     const int s_lo = chunk * pg.chunk_sites;
     const int s_hi = min(pg.V3, s_lo + pg.chunk_sites);
