@@ -172,6 +172,20 @@ int c3pt_release_scratch(void);
  * Names: "proj_spectator_meson", "proj_spectator_baryon", "proj_insertion",
  * "reduce", "combine".
  */
+/*
+ * Kernel variants (tile shapes) of the fused contraction + projection, for
+ * the autotuner.  kind: 0 meson spectator, 1 baryon spectator, 2 insertion.
+ * mode: 0 FP64 (complex128 inputs), 1 FP32, 2 split BF16, 3 split FP16.
+ * mt_class: momentum groups of up to 32, 64, 96, 128 momenta (0..3).
+ * c3pt_variant_count returns the number of compiled variants (0 if none);
+ * c3pt_set_variant selects one for later calls (process-wide);
+ * c3pt_get_variant returns the current choice or a negative status.
+ * Every variant computes the same result up to FP32 rounding order.
+ */
+int c3pt_variant_count(int kind, int mode, int mt_class);
+int c3pt_set_variant(int kind, int mode, int mt_class, int variant);
+int c3pt_get_variant(int kind, int mode, int mt_class);
+
 typedef struct c3pt_kernel_stat {
     char      name[48];
     long long count;

@@ -37,7 +37,11 @@ PROJ_SPLIT_BF16 = 2
 
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
             "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
-            "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read")
+            "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read", "c3pt_variant_count",
+            "c3pt_set_variant", "c3pt_get_variant")
+
+KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
+MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3}
 
 
 class C3ptError(RuntimeError):
@@ -82,6 +86,11 @@ def _load():
     lib.c3pt_profile_enable.restype = ctypes.c_int
     lib.c3pt_profile_read.argtypes = [ctypes.POINTER(_KernelStat), i, i]
     lib.c3pt_profile_read.restype = ctypes.c_int
+    for name in ("c3pt_variant_count", "c3pt_set_variant", "c3pt_get_variant"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.c3pt_variant_count.argtypes = [i, i, i]
+    lib.c3pt_set_variant.argtypes = [i, i, i, i]
+    lib.c3pt_get_variant.argtypes = [i, i, i]
     return lib
 
 
@@ -264,6 +273,49 @@ def momentum_list(n2max: int):
 
 def version() -> int:
     return int(lib.c3pt_version())
+
+
+def mt_class(n_mom: int, f64: bool = False) -> int:
+    """Momentum-tile class of a call with n_mom momenta (FP64 groups of 32 use class 0)."""
+    if f64:
+        return 0
+    mt = (min(n_mom, 128) + 7) // 8
+    return 0 if mt <= 4 else 1 if mt <= 8 else 2 if mt <= 12 else 3
+
+
+def variant_count(kind: int, mode: int, cls: int) -> int:
+    return int(lib.c3pt_variant_count(kind, mode, cls))
+
+
+def set_variant(kind: int, mode: int, cls: int, variant: int) -> None:
+    _check(lib.c3pt_set_variant(kind, mode, cls, variant))
+
+
+def get_variant(kind: int, mode: int, cls: int) -> int:
+    v = int(lib.c3pt_get_variant(kind, mode, cls))
+    if v < 0:
+        _check(v)
+    return v
+
+
+def apply_tuning(table) -> int:
+    """Select kernel variants from a tuning table (dict or JSON path); returns entries applied."""
+    import json
+    if isinstance(table, str):
+        if not os.path.exists(table):
+            return 0
+        with open(table) as f:
+            table = json.load(f)
+    n = 0
+    for e in table.get("entries", []):
+        if variant_count(e["kind"], e["mode"], e["mt_class"]) > e["variant"]:
+            set_variant(e["kind"], e["mode"], e["mt_class"], e["variant"])
+            n += 1
+    return n
+
+
+DEFAULT_TUNING = os.path.join(_HERE, "tuning_mi355x.json")
+apply_tuning(os.environ.get("C3PT_TUNING", DEFAULT_TUNING))
 
 
 def profile_enable(on: bool = True) -> None:

@@ -2,6 +2,9 @@
 
 Usage: python paper_1711_02384_amd/build.py  [--debug]
 (run as a file: importing the package itself loads the library this builds)
+
+Each translation unit is compiled in its own hipcc process (in parallel), then
+linked into one shared library next to this file.
 """
 from __future__ import annotations
 
@@ -13,8 +16,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libc3pt.so")
-SOURCES = ["c3pt_api.hip", "c3pt_kernels.hip"]
+SOURCES = ["c3pt_api.hip", "c3pt_proj_meson.hip", "c3pt_proj_baryon.hip", "c3pt_proj_insertion.hip",
+           "c3pt_combine.hip"]
 
 
 def hipcc() -> str:
@@ -25,22 +30,39 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, debug: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
     flags = [
-        "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+        "--offload-arch=gfx950", "-std=c++17", "-fPIC",
         "-O1" if debug else "-O3",
         # packed FP32 instructions are kept out of every kernel of this library
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"),
         "-Wno-unused-command-line-argument",
     ]
+    procs = []
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    failed = []
+    for src, p in procs:
+        out, _ = p.communicate()
+        errs = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
+        if p.returncode != 0:
+            failed.append(src)
+            sys.stderr.write("\n".join(errs) + "\n")
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libc3pt.so")
+        raise RuntimeError("linking libc3pt.so failed")
     os.replace(tmp, LIB)
     return LIB
 

@@ -157,8 +157,6 @@ int check_geom(const c3pt_geom* g) {
         return fail(C3PT_EINVAL, "unknown projection mode %d", g->proj);
     if (g->proj != C3PT_PROJ_NATIVE && g->dtype != C3PT_C64)
         return fail(C3PT_EINVAL, "split-precision projection needs complex64 inputs");
-    if (g->proj != C3PT_PROJ_NATIVE)
-        return fail(C3PT_EUNSUPPORTED, "split-precision projection is not available in this build");
     return C3PT_OK;
 }
 
@@ -174,7 +172,25 @@ int posmod(long long v, int L) {
     return (int)(r < 0 ? r + L : r);
 }
 
-// Momentum groups: FP32 launches take up to 96 momenta, FP64 up to 32.
+int proj_mode(const c3pt_geom* g) {
+    if (g->dtype == C3PT_C128) return kModeF64;
+    if (g->proj == C3PT_PROJ_SPLIT_BF16) return kModeSplitBF16;
+    if (g->proj == C3PT_PROJ_SPLIT_F16) return kModeSplitF16;
+    return kModeF32;
+}
+
+// Kernel variant per (kind, mode, momentum-tile class); 0 = default.
+constexpr int kKinds = 3;   // 0 meson spectator, 1 baryon spectator, 2 insertion
+constexpr int kModes = 4;
+int g_variant[kKinds][kModes][kMtClasses] = {};
+
+int variant_count(int kind, int mode, int cls) {
+    if (kind < 0 || kind >= kKinds || mode < 0 || mode >= kModes || cls < 0 || cls >= kMtClasses) return 0;
+    if (mode == kModeF64) return cls == 0 ? 1 : 0;
+    return kVariantsPerClass[cls];
+}
+
+// Momentum groups: FP32 / split launches take up to 128 momenta, FP64 up to 32.
 struct MomGroup {
     int off, n;
 };
@@ -202,7 +218,7 @@ void fill_phase(PhaseSpec& ph, const c3pt_geom* g, int sigma, const int* k, cons
 // Sites per split-site chunk: enough chunks to fill the chip, never more than
 // kMaxSitesPerChunkF32 sites in one FP32 partial sum.
 void plan_chunks(int V3, int n_colblocks, bool f64, int* chunk_sites, int* n_chunks) {
-    const int kt = f64 ? 16 : 32;
+    const int kt = kSiteTile;
     const int tiles = (V3 + kt - 1) / kt;
     const int target_wg = 2048;
     int chunks = std::max(1, (target_wg + n_colblocks - 1) / n_colblocks);
@@ -222,11 +238,12 @@ int to_status(hipError_t e, const char* what) {
 // Runs projection launches over momentum groups and reduces each into `out`.
 // `launch(pg, mt)` enqueues one fused kernel for the grid pg.
 template <class Launch>
-int run_projection(const char* kname, const c3pt_geom* g, int sigma, const int* k, int n_mom, int n_colblocks,
+int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, const int* k, int n_mom, int n_colblocks,
                    int group_cols, int n_groups, int inner, int outer_stride, int off,
                    void* out, Launch launch) {
     hipStream_t st = (hipStream_t)g->stream;
     const bool f64 = g->dtype == C3PT_C128;
+    const int mode = proj_mode(g);
     const int V3 = g->L[0] * g->L[1] * g->L[2];
     auto groups = momentum_groups(n_mom, f64);
     int chunk_sites, n_chunks;
@@ -244,7 +261,12 @@ int run_projection(const char* kname, const c3pt_geom* g, int sigma, const int* 
         pg.n_colblocks = n_colblocks;
         pg.partial = (double2*)part;
         const int mt = (mg.n + 7) / 8;
-        if (int rc = to_status(timed(kname, st, [&] { return launch(pg, mt); }), "projection launch"))
+        int variant;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            variant = g_variant[kind][mode][mt_class(mt)];
+        }
+        if (int rc = to_status(timed(kname, st, [&] { return launch(mode, pg, mt, variant); }), "projection launch"))
             return rc;
         ReduceArgs ra;
         ra.partial = (const double2*)part;
@@ -308,6 +330,23 @@ int c3pt_release_scratch(void) {
     return ok();
 }
 
+int c3pt_variant_count(int kind, int mode, int mt_cls) { return variant_count(kind, mode, mt_cls); }
+
+int c3pt_set_variant(int kind, int mode, int mt_cls, int variant) {
+    const int n = variant_count(kind, mode, mt_cls);
+    if (n == 0) return fail(C3PT_EINVAL, "no kernel for kind %d, mode %d, class %d", kind, mode, mt_cls);
+    if (variant < 0 || variant >= n) return fail(C3PT_EINVAL, "variant %d outside [0, %d)", variant, n);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_variant[kind][mode][mt_cls] = variant;
+    return ok();
+}
+
+int c3pt_get_variant(int kind, int mode, int mt_cls) {
+    if (variant_count(kind, mode, mt_cls) == 0) return fail(C3PT_EINVAL, "no kernel for this key");
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_variant[kind][mode][mt_cls];
+}
+
 int c3pt_profile_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
@@ -354,10 +393,9 @@ int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* et
     if (!G_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     MesonSpecArgs a{G_tf, eta};
-    const bool f64 = geom->dtype == C3PT_C128;
-    int rc = run_projection("proj_spectator_meson", geom, -1, k, n_mom, n_noise, kBlockCols, n_noise, n_noise, 0, 0, out,
-                            [&](const ProjGrid& pg, int mt) {
-                                return launch_spectator_meson(f64, mt, pg, a, (hipStream_t)geom->stream);
+    int rc = run_projection("proj_spectator_meson", 0, geom, -1, k, n_mom, n_noise, kBlockCols, n_noise, n_noise, 0,
+                            0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
+                                return launch_spectator_meson(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
                             });
     return rc ? rc : ok();
 }
@@ -369,10 +407,9 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
     if (!G1_tf || !G2_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     BaryonSpecArgs a{G1_tf, G2_tf, eta};
-    const bool f64 = geom->dtype == C3PT_C128;
-    int rc = run_projection("proj_spectator_baryon", geom, -1, k, n_mom, n_noise * 16, 3072, n_noise, n_noise, 0, 0, out,
-                            [&](const ProjGrid& pg, int mt) {
-                                return launch_spectator_baryon(f64, mt, pg, a, (hipStream_t)geom->stream);
+    int rc = run_projection("proj_spectator_baryon", 1, geom, -1, k, n_mom, n_noise * 16, 3072, n_noise, n_noise,
+                            0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
+                                return launch_spectator_baryon(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
                             });
     return rc ? rc : ok();
 }
@@ -400,7 +437,6 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
         }
     }
-    const bool f64 = geom->dtype == C3PT_C128;
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
         InsertionArgs a;
@@ -421,9 +457,9 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             }
         }
         const int ncb = n_noise * nt * n_ops;
-        int rc = run_projection("proj_insertion", geom, +1, k, n_mom, ncb, kBlockCols, ncb, nt * n_ops, n_tau * n_ops,
-                                j0 * n_ops, out, [&](const ProjGrid& pg, int mt) {
-                                    return launch_insertion(f64, mt, pg, a, (hipStream_t)geom->stream);
+        int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, kBlockCols, ncb, nt * n_ops,
+                                n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
+                                    return launch_insertion(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
                                 });
         if (rc) return rc;
     }

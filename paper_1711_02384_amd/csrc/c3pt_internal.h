@@ -10,7 +10,7 @@ namespace c3pt {
 // One column block of the projection GEMM = one 192-component spin-colour group.
 constexpr int kBlockCols = 192;
 // Largest momentum group handled by one projection launch (FP32 / FP64).
-constexpr int kMaxMomGroupF32 = 96;
+constexpr int kMaxMomGroupF32 = 128;
 constexpr int kMaxMomGroupF64 = 32;
 constexpr int kMaxMomGroup = 128;
 // Largest number of insertion timeslices per launch (pointer tables travel as
@@ -89,12 +89,25 @@ struct CombineArgs {
     int n_noise, n_p, n_q, n_tau, n_ops, op_begin, n_sel, spin, n_pairs;
 };
 
-// Launchers (defined in c3pt_kernels.hip). They return hipError_t of the launch.
-hipError_t launch_spectator_meson(bool f64, int mt, const ProjGrid& pg, const MesonSpecArgs& a,
+// Arithmetic of a projection launch.
+constexpr int kModeF64 = 0;         // complex128 inputs, FP64 MFMA
+constexpr int kModeF32 = 1;         // complex64 inputs, FP32 MFMA
+constexpr int kModeSplitBF16 = 2;   // complex64 inputs, hi+lo BF16 MFMA, FP32 accumulation
+constexpr int kModeSplitF16 = 3;    // complex64 inputs, hi+lo FP16 MFMA, FP32 accumulation
+// Chunk sizes are multiples of the largest site tile of any variant.
+constexpr int kSiteTile = 32;
+// Momentum-tile classes (8 momenta per 16-row MFMA tile): mt <= 4, 8, 12, 16.
+constexpr int kMtClasses = 4;
+__host__ __device__ inline int mt_class(int mt) { return mt <= 4 ? 0 : mt <= 8 ? 1 : mt <= 12 ? 2 : 3; }
+// Compiled (site tile, row split) variants per class; FP64 has one (class 0).
+constexpr int kVariantsPerClass[kMtClasses] = {2, 3, 3, 2};
+
+// Launchers (c3pt_proj_*.hip, c3pt_combine.hip). They return the launch status.
+hipError_t launch_spectator_meson(int mode, int mt, int variant, const ProjGrid& pg, const MesonSpecArgs& a,
                                   hipStream_t st);
-hipError_t launch_spectator_baryon(bool f64, int mt, const ProjGrid& pg, const BaryonSpecArgs& a,
+hipError_t launch_spectator_baryon(int mode, int mt, int variant, const ProjGrid& pg, const BaryonSpecArgs& a,
                                    hipStream_t st);
-hipError_t launch_insertion(bool f64, int mt, const ProjGrid& pg, const InsertionArgs& a,
+hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, const InsertionArgs& a,
                             hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);

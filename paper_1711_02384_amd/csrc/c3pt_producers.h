@@ -1,0 +1,336 @@
+// Producers of libc3pt: contract one tile of KT sites into P[col][site] for
+// one 192-column block.  Each producer works in two phases so that the global
+// loads of the next tile are in flight while the current tile is projected:
+//   load(...)  -> registers (Regs), issued before the MFMA loop of the previous tile
+//   store(...) -> contraction from registers (+ LDS staging) into the sink
+// Sites j >= nsite contribute zeros.
+#pragma once
+
+#include "c3pt_device.h"
+
+namespace c3pt {
+
+template <int N, int NT>
+struct PerThread {
+    static constexpr int value = (N + NT - 1) / NT;
+};
+
+// ---------------------------------------------------------------------------
+// Meson spectator, Eq. (9):
+//   P[(b',a',a,c)] = g[b'] g[a'] g[a] sum_c' eta[(b',c')] conj(G[(a',c')][(a,c)])
+// Column block cb = noise.  Task (site j, q = a'*12 + a*3 + c) computes the
+// four b' columns from three propagator entries.
+// ---------------------------------------------------------------------------
+template <typename R, int KT, int NT>
+struct MesonSpecProducer {
+    using Args = MesonSpecArgs;
+    static constexpr int kV = PerThread<12 * KT, NT>::value;
+    static constexpr int kT = PerThread<48 * KT, NT>::value;
+    struct Regs {
+        C2<R> v[kV];
+        C2<R> g[kT][3];
+    };
+    struct Smem {
+        C2<R> v[12][KT];
+    };
+    static __device__ __forceinline__ void load(const Args& a, const TileGeom& tg, int cb, int t0, int nsite,
+                                                Regs& rg, int tid) {
+        const size_t V3 = (size_t)tg.V3;
+        const C2<R>* G = (const C2<R>*)a.G;
+        const C2<R>* eta = (const C2<R>*)a.eta + (size_t)cb * 12 * V3;
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            rg.v[i] = (e < 12 * KT && j < nsite) ? eta[(size_t)A * V3 + t0 + j] : C2<R>{0, 0};
+        }
+#pragma unroll
+        for (int i = 0; i < kT; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int ap = q / 12, rem = q % 12;
+            const bool ok = e < 48 * KT && j < nsite;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                rg.g[i][c] = ok ? G[(size_t)((3 * ap + c) * 12 + rem) * V3 + t0 + j] : C2<R>{0, 0};
+        }
+    }
+    template <class Sink>
+    static __device__ __forceinline__ void store(const Args&, const TileGeom&, int, int, int, const Regs& rg,
+                                                 Smem& sm, Sink& sink, int tid) {
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            if (e < 12 * KT) sm.v[A][j] = (A >= 6) ? C2<R>{-rg.v[i].x, -rg.v[i].y} : rg.v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kT; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            if (e >= 48 * KT) continue;
+            const int ap = q / 12, al = (q % 12) / 3;
+            const R sg = g5<R>(ap) * g5<R>(al);
+#pragma unroll
+            for (int bp = 0; bp < 4; ++bp) {
+                C2<R> p = cmulc(sm.v[3 * bp][j], rg.g[i][0]);
+                p = cadd(p, cmulc(sm.v[3 * bp + 1][j], rg.g[i][1]));
+                p = cadd(p, cmulc(sm.v[3 * bp + 2][j], rg.g[i][2]));
+                sink.put(bp * 48 + q, j, cscale(p, sg));
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Nucleon-type spectator with epsilon tensors at sink and source.  Column
+// block cb = noise * 16 + (a1' * 4 + a1); columns (a2', a2, b', c').
+//   P = g[b'] sum_c eta[(b',c)] Q[c][c'],
+//   Q[c][c'] = sum eps_{abc} eps_{a'b'c'} G1[(a1',a)][(a1,a')] G2[(a2',b)][(a2,b')]
+// Task (site j, q = a2'*4 + a2) forms Q from nine G2 entries and the G1 block.
+// ---------------------------------------------------------------------------
+template <typename R, int KT, int NT>
+struct BaryonSpecProducer {
+    using Args = BaryonSpecArgs;
+    static constexpr int kV = PerThread<21 * KT, NT>::value;
+    static constexpr int kT = PerThread<16 * KT, NT>::value;
+    struct Regs {
+        C2<R> v[kV];
+        C2<R> g2[kT][9];
+    };
+    struct Smem {
+        C2<R> v[12][KT];
+        C2<R> g1[9][KT];
+    };
+    static __device__ __forceinline__ void load(const Args& a, const TileGeom& tg, int cb, int t0, int nsite,
+                                                Regs& rg, int tid) {
+        const size_t V3 = (size_t)tg.V3;
+        const int noise = cb >> 4, blk = cb & 15;
+        const int a1p = blk >> 2, a1 = blk & 3;
+        const C2<R>* G1 = (const C2<R>*)a.G1;
+        const C2<R>* G2 = (const C2<R>*)a.G2;
+        const C2<R>* eta = (const C2<R>*)a.eta + (size_t)noise * 12 * V3;
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            C2<R> v = {0, 0};
+            if (e < 21 * KT && j < nsite) {
+                if (A < 12) {
+                    v = eta[(size_t)A * V3 + t0 + j];
+                } else {
+                    const int cc = A - 12;
+                    v = G1[(size_t)((3 * a1p + cc / 3) * 12 + 3 * a1 + cc % 3) * V3 + t0 + j];
+                }
+            }
+            rg.v[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < kT; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int a2p = q >> 2, a2 = q & 3;
+            const bool ok = e < 16 * KT && j < nsite;
+#pragma unroll
+            for (int cc = 0; cc < 9; ++cc)
+                rg.g2[i][cc] = ok ? G2[(size_t)((3 * a2p + cc / 3) * 12 + 3 * a2 + cc % 3) * V3 + t0 + j]
+                                  : C2<R>{0, 0};
+        }
+    }
+    template <class Sink>
+    static __device__ __forceinline__ void store(const Args&, const TileGeom&, int, int, int, const Regs& rg,
+                                                 Smem& sm, Sink& sink, int tid) {
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            if (e >= 21 * KT) continue;
+            if (A < 12) sm.v[A][j] = (A >= 6) ? C2<R>{-rg.v[i].x, -rg.v[i].y} : rg.v[i];
+            else sm.g1[A - 12][j] = rg.v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kT; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            if (e >= 16 * KT) continue;
+            C2<R> g1[9];
+#pragma unroll
+            for (int cc = 0; cc < 9; ++cc) g1[cc] = sm.g1[cc][j];
+            const C2<R>* g2 = rg.g2[i];
+            // Q[c][c'] with (a, b) = (c+1, c+2) (+) and (c+2, c+1) (-), same for primes.
+            C2<R> Q[9];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int ca = (c + 1) % 3, cb2 = (c + 2) % 3;
+#pragma unroll
+                for (int cp = 0; cp < 3; ++cp) {
+                    const int pa = (cp + 1) % 3, pb = (cp + 2) % 3;
+                    C2<R> t = cmul(g1[ca * 3 + pa], g2[cb2 * 3 + pb]);
+                    t = csub(t, cmul(g1[ca * 3 + pb], g2[cb2 * 3 + pa]));
+                    t = csub(t, cmul(g1[cb2 * 3 + pa], g2[ca * 3 + pb]));
+                    t = cfma(t, g1[cb2 * 3 + pb], g2[ca * 3 + pa]);
+                    Q[c * 3 + cp] = t;
+                }
+            }
+#pragma unroll
+            for (int bp = 0; bp < 4; ++bp) {
+                const C2<R> v0 = sm.v[3 * bp][j], v1 = sm.v[3 * bp + 1][j], v2 = sm.v[3 * bp + 2][j];
+#pragma unroll
+                for (int cp = 0; cp < 3; ++cp) {
+                    C2<R> p = cmul(v0, Q[cp]);
+                    p = cfma(p, v1, Q[3 + cp]);
+                    p = cfma(p, v2, Q[6 + cp]);
+                    sink.put((q * 4 + bp) * 3 + cp, j, p);
+                }
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Insertion, Eq. (10).  Column block cb = ((noise * n_tau) + tau) * n_ops + op;
+// columns (at, bt, b, c).  op 0: P = sum_c' v[at][c'] G[(bt,c')][(b,c)] with
+// v = g[at] conj(s[(at,c')]).  op 1+nu: the covariant derivative is moved onto
+// the stochastic vector, t+ = 1/2 v U_nu(y), t- = 1/2 v U_nu(y-nu)^dag, and
+// P = sum_d t+[at][d] G(y+nu)[(bt,d)][(b,c)] - t-[at][d] G(y-nu)[(bt,d)][(b,c)].
+// Task (site j, q = bt*12 + b*3 + c) computes the four at columns.
+// ---------------------------------------------------------------------------
+template <typename R, int KT, int NT>
+struct InsertionProducer {
+    using Args = InsertionArgs;
+    static constexpr int kV = PerThread<12 * KT, NT>::value;
+    static constexpr int kT = PerThread<48 * KT, NT>::value;
+    struct Regs {
+        C2<R> v[kV];        // s entries
+        C2<R> u[kV][6];     // transport task: U(y)[c][d], U(y-nu)[d][c] for c = 0..2
+        C2<R> g[kT][6];     // G entries: local uses [0..2]; derivative (y+nu)[0..2], (y-nu)[3..5]
+    };
+    struct Smem {
+        C2<R> v[12][KT];
+        C2<R> tp[12][KT];
+        C2<R> tm[12][KT];
+    };
+    static __device__ __forceinline__ void decode(const Args& a, int cb, int& op, int& tl, int& noise) {
+        op = cb % a.n_ops;
+        const int rest = cb / a.n_ops;
+        tl = rest % a.n_tau;
+        noise = rest / a.n_tau;
+    }
+    static __device__ __forceinline__ void load(const Args& a, const TileGeom& tg, int cb, int t0, int nsite,
+                                                Regs& rg, int tid) {
+        const size_t V3 = (size_t)tg.V3;
+        int op, tl, noise;
+        decode(a, cb, op, tl, noise);
+        const C2<R>* s = (const C2<R>*)a.s[tl] + (size_t)noise * 12 * V3;
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            rg.v[i] = (e < 12 * KT && j < nsite) ? s[(size_t)A * V3 + t0 + j] : C2<R>{0, 0};
+        }
+        if (op == 0) {
+            const C2<R>* G = (const C2<R>*)a.G[tl];
+#pragma unroll
+            for (int i = 0; i < kT; ++i) {
+                const int e = tid + i * NT, j = e % KT, q = e / KT;
+                const int bt = q / 12, rem = q % 12;
+                const bool ok = e < 48 * KT && j < nsite;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    rg.g[i][c] = ok ? G[(size_t)((3 * bt + c) * 12 + rem) * V3 + t0 + j] : C2<R>{0, 0};
+            }
+            return;
+        }
+        const int nu = op - 1;
+        // transport tasks (q = at*3 + d, site j): links at y and y - nu
+        {
+            const C2<R>* U = (const C2<R>*)a.U[tl] + (size_t)nu * 9 * V3;
+            const C2<R>* Um = (nu < 3) ? U : (const C2<R>*)a.Up[tl] + (size_t)3 * 9 * V3;
+#pragma unroll
+            for (int i = 0; i < kV; ++i) {
+                const int e = tid + i * NT, j = e % KT, q = e / KT, d = q % 3;
+                const bool ok = e < 12 * KT && j < nsite;
+                const int n = t0 + j;
+                const int nm = (ok && nu < 3) ? site_shift(tg, n, nu, -1) : n;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    rg.u[i][c] = ok ? U[(size_t)(c * 3 + d) * V3 + n] : C2<R>{0, 0};
+                    rg.u[i][3 + c] = ok ? Um[(size_t)(d * 3 + c) * V3 + nm] : C2<R>{0, 0};
+                }
+            }
+        }
+        const C2<R>* Gf = (const C2<R>*)((nu < 3) ? a.G[tl] : a.Gn[tl]);
+        const C2<R>* Gb = (const C2<R>*)((nu < 3) ? a.G[tl] : a.Gp[tl]);
+#pragma unroll
+        for (int i = 0; i < kT; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int bt = q / 12, rem = q % 12;
+            const bool ok = e < 48 * KT && j < nsite;
+            const int n = t0 + j;
+            const int np = (ok && nu < 3) ? site_shift(tg, n, nu, +1) : n;
+            const int nm = (ok && nu < 3) ? site_shift(tg, n, nu, -1) : n;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                rg.g[i][d] = ok ? Gf[(size_t)((3 * bt + d) * 12 + rem) * V3 + np] : C2<R>{0, 0};
+                rg.g[i][3 + d] = ok ? Gb[(size_t)((3 * bt + d) * 12 + rem) * V3 + nm] : C2<R>{0, 0};
+            }
+        }
+    }
+    template <class Sink>
+    static __device__ __forceinline__ void store(const Args& a, const TileGeom&, int cb, int, int,
+                                                 const Regs& rg, Smem& sm, Sink& sink, int tid) {
+        int op, tl, noise;
+        decode(a, cb, op, tl, noise);
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            if (e < 12 * KT) {
+                const C2<R> s = rg.v[i];
+                sm.v[A][j] = (A >= 6) ? C2<R>{-s.x, s.y} : C2<R>{s.x, -s.y};   // g[at] conj(s)
+            }
+        }
+        __syncthreads();
+        if (op == 0) {
+#pragma unroll
+            for (int i = 0; i < kT; ++i) {
+                const int e = tid + i * NT, j = e % KT, q = e / KT;
+                if (e >= 48 * KT) continue;
+#pragma unroll
+                for (int at = 0; at < 4; ++at) {
+                    C2<R> p = cmul(sm.v[3 * at][j], rg.g[i][0]);
+                    p = cfma(p, sm.v[3 * at + 1][j], rg.g[i][1]);
+                    p = cfma(p, sm.v[3 * at + 2][j], rg.g[i][2]);
+                    sink.put(at * 48 + q, j, p);
+                }
+            }
+            return;
+        }
+        // t+[at][d] = 1/2 sum_c v[at][c] U(y)[c][d];  t-[at][d] = 1/2 sum_c v[at][c] conj(U(y-nu)[d][c])
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            if (e >= 12 * KT) continue;
+            const int at = q / 3;
+            C2<R> tp = {0, 0}, tm = {0, 0};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const C2<R> vv = sm.v[3 * at + c][j];
+                tp = cfma(tp, vv, rg.u[i][c]);
+                tm = cadd(tm, cmulc(vv, rg.u[i][3 + c]));
+            }
+            sm.tp[q][j] = cscale(tp, (R)0.5);
+            sm.tm[q][j] = cscale(tm, (R)0.5);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kT; ++i) {
+            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            if (e >= 48 * KT) continue;
+#pragma unroll
+            for (int at = 0; at < 4; ++at) {
+                C2<R> p = {0, 0};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    p = cfma(p, sm.tp[3 * at + d][j], rg.g[i][d]);
+                    p = csub(p, cmul(sm.tm[3 * at + d][j], rg.g[i][3 + d]));
+                }
+                sink.put(at * 48 + q, j, p);
+            }
+        }
+    }
+};
+
+}  // namespace c3pt

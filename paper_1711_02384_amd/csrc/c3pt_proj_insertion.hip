@@ -1,0 +1,11 @@
+// Projection kernels with the InsertionProducer (one translation unit per producer so
+// that the variants compile in parallel).
+#include "c3pt_proj_impl.h"
+
+namespace c3pt {
+
+hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st) {
+    return dispatch<InsertionProducer>(mode, mt, variant, pg, a, st);
+}
+
+}  // namespace c3pt

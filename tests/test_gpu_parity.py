@@ -193,3 +193,46 @@ def test_runs_on_a_side_stream():
         got = c.spectator_meson(G, e, k, c.Geom(L, 8))
     s.synchronize()
     assert rel_fro(got.cpu().numpy(), oracle.spectator_meson(w.G1, w.eta, L, k)) < TOL32
+
+
+# ---------------------------------------------------------------------------
+# Every compiled kernel variant and every projection arithmetic
+# ---------------------------------------------------------------------------
+MODES = {1: ("f32", 0), 2: ("bf16x2", 2), 3: ("f16x2", 1)}   # mode -> (name, proj flag)
+
+
+@pytest.mark.parametrize("cls,n2", [(0, 3), (1, 5), (2, 8), (3, 9)])
+def test_every_variant_and_precision(cls, n2):
+    c = _lib()
+    L, T, N = (6, 5, 7), 6, 2
+    taus = [0, 4]
+    k = oracle.momenta(n2)
+    assert c.mt_class(len(k)) == cls
+    r = (2, 1, 3)
+    w = Workload(L, T, N, cfg=108, taus=taus, links=True, reduced=True, second_prop=True)
+    want_s = oracle.spectator_meson(w.G1, w.eta, L, k, r)
+    want_b = oracle.spectator_baryon(w.G1, w.G1b, w.eta, L, k, r)
+    want_i = oracle.insertion(w.G3, w.s, taus, L, T, k, r, U_t=w.U, n_ops=5)
+    G1, G1b, eta = dev(w.G1, True), dev(w.G1b, True), dev(w.eta, True)
+    Gd = {t: dev(v, True) for t, v in w.G3.items()}
+    sd = {t: dev(v, True) for t, v in w.s.items()}
+    Ud = {t: dev(v, True) for t, v in w.U.items()}
+    for mode, (mname, proj) in MODES.items():
+        geom = c.Geom(L, T, r, proj=proj)
+        for kind in range(3):
+            prev = c.get_variant(kind, mode, cls)
+            try:
+                for v in range(c.variant_count(kind, mode, cls)):
+                    c.set_variant(kind, mode, cls, v)
+                    _say(f"variant kind={kind} mode={mname} class={cls} v={v}")
+                    if kind == 0:
+                        errs = [rel_fro(c.spectator_meson(G1, eta, k, geom).cpu().numpy(), want_s)]
+                    elif kind == 1:
+                        errs = [rel_fro(c.spectator_baryon(G1, G1b, eta, k, geom).cpu().numpy(), want_b)]
+                    else:
+                        got = c.insertion(Gd, sd, taus, k, geom, U_t=Ud, n_ops=5).cpu().numpy()
+                        errs = per_slice_rel(got, want_i)
+                    _say(f"    max rel err {max(errs):.2e}")
+                    assert max(errs) < TOL32, (kind, mname, v, errs)
+            finally:
+                c.set_variant(kind, mode, cls, prev)
