@@ -32,6 +32,7 @@ if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
@@ -42,7 +43,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-baryon", action="store_true", help="meson only (drop the nucleon spectator)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices", type=int, default=2, help="insertion timeslices in the CPU sample")
+    ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
+    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2"], default="f32",
+                    help="projection arithmetic: FP32 MFMA, or hi+lo BF16 / FP16 MFMA with FP32 accumulation")
+    ap.add_argument("--tune", action="store_true", help="autotune kernel variants on this workload first")
+    ap.add_argument("--tune-out", default=None, help="write the tuning table (JSON) here")
     return ap.parse_args()
 
 
@@ -132,7 +137,9 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
 
-    geom = c3pt.Geom(L, T)
+    proj_flag = {"f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16, "f16x2": c3pt.PROJ_SPLIT_F16}[args.proj]
+    mode = {"f32": 1, "bf16x2": 2, "f16x2": 3}[args.proj]
+    geom = c3pt.Geom(L, T, proj=proj_flag)
     n_tau = len(W.taus)
     S = torch.empty((W.N, n_mom, 192), dtype=torch.complex128, device=dev)
     SB = torch.empty((W.N, n_mom, 3072), dtype=torch.complex128, device=dev)
@@ -152,6 +159,20 @@ def main():
         if baryon:
             c3pt.combine(SB, I, pairs=pairs, op_begin=0, op_end=1, out=C_bar)
 
+    tuning = None
+    if args.tune:
+        from paper_1711_02384_amd import autotune
+        cls = c3pt.mt_class(n_mom)
+        cases = [{"kind": "insertion", "mode": mode, "mt_class": cls,
+                  "call": lambda: c3pt.insertion(G3, s, W.taus, k, geom, U_t=U, n_ops=W.n_ops, out=I)},
+                 {"kind": "spectator_meson", "mode": mode, "mt_class": cls,
+                  "call": lambda: c3pt.spectator_meson(G1, eta, k, geom, out=S)}]
+        if baryon:
+            cases.append({"kind": "spectator_baryon", "mode": mode, "mt_class": cls,
+                          "call": lambda: c3pt.spectator_baryon(G1, G1, eta, k, geom, out=SB)})
+        tuning = autotune.tune(cases, reps=3, log=log)
+        if args.tune_out:
+            autotune.save(tuning, args.tune_out)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -178,15 +199,19 @@ def main():
     value = units / (ms_per_step * 1e-3)
 
     # Dominant kernel: the fused insertion contraction + projection.
+    peak = PEAK_FP32_MFMA_TFLOPS if args.proj == "f32" else PEAK_BF16_MFMA_TFLOPS
     ins_cols = W.N * n_tau * W.n_ops * 192
     flops_ins = 8.0 * n_mom * V3 * ins_cols                  # complex GEMM flops, useful rows only
     pi = prof.get("proj_insertion", {})
     ins_ms = pi.get("avg_ms", float("nan"))
     achieved = flops_ins / (ins_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-                "kernel": "proj_insertion (fused FP32 contraction + FP32 MFMA projection)",
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": f"proj_insertion (fused FP32 contraction + {args.proj} MFMA projection)",
                 "flops_per_launch": flops_ins, "avg_ms": round(ins_ms, 4)}
+    if args.proj != "f32":
+        roofline["note"] = ("flops counted once per complex MAC (8 real flops); the hi+lo split issues "
+                            "3 MFMA products per term, so MFMA issue is 3x the counted flops")
 
     res = {
         "metric": "contracted site*momenta/s (spectator+insertion)",
@@ -199,7 +224,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.proj == "f32" else f"f32 contraction, {args.proj} projection",
         "data": "synthetic",
         "config": {"workload": W.name + (", nucleon spectator" if baryon else ""), "L": list(L), "T": T,
                    "t_f": W.t_f, "n_noise": W.N, "n_tau": n_tau, "n_mom": n_mom, "n_ops": W.n_ops,
@@ -212,7 +237,11 @@ def main():
         "kernels_ms": {kname: round(v["avg_ms"], 4) for kname, v in prof.items()},
         "kernel_launches": {kname: v["count"] for kname, v in prof.items()},
         "roofline": roofline,
+        "variants": {kn: c3pt.get_variant(c3pt.KIND[kn], mode, c3pt.mt_class(n_mom))
+                     for kn in ("spectator_meson", "spectator_baryon", "insertion")},
     }
+    if tuning is not None:
+        res["tuning"] = tuning["entries"]
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a host sample")
         res["cpu_baseline"] = cpu_baseline(W, k, args.cpu_slices)

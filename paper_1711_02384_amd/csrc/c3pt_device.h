@@ -102,10 +102,23 @@ __device__ __forceinline__ void site_xyz(const TileGeom& tg, int n, int& x1, int
     x2 = q - x3 * tg.L2;
 }
 
-// Neighbour n +- mu (mu = 0, 1, 2), periodic.
-__device__ __forceinline__ int site_shift(const TileGeom& tg, int n, int mu, int sgn) {
-    int x1, x2, x3;
-    site_xyz(tg, n, x1, x2, x3);
+// Coordinates of site t0 + j from those of t0 (x0) by carrying, j >= 0.
+__device__ __forceinline__ void site_xyz_from(const TileGeom& tg, const int (&x0)[3], int j, int& x1, int& x2,
+                                              int& x3) {
+    x1 = x0[0] + j;
+    x2 = x0[1];
+    x3 = x0[2];
+    while (x1 >= tg.L1) {
+        x1 -= tg.L1;
+        if (++x2 == tg.L2) {
+            x2 = 0;
+            ++x3;
+        }
+    }
+}
+
+// Neighbour (+- mu, mu = 0, 1, 2, periodic) of the site with coordinates x.
+__device__ __forceinline__ int site_shift_xyz(const TileGeom& tg, int x1, int x2, int x3, int mu, int sgn) {
     if (mu == 0) {
         x1 += sgn;
         x1 = (x1 == tg.L1) ? 0 : (x1 < 0 ? tg.L1 - 1 : x1);

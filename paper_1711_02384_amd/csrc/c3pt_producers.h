@@ -235,6 +235,9 @@ struct InsertionProducer {
             return;
         }
         const int nu = op - 1;
+        // coordinates of the tile's first site (uniform), neighbours by carrying
+        int x0[3];
+        site_xyz(tg, t0, x0[0], x0[1], x0[2]);
         // transport tasks (q = at*3 + d, site j): links at y and y - nu
         {
             const C2<R>* U = (const C2<R>*)a.U[tl] + (size_t)nu * 9 * V3;
@@ -244,7 +247,12 @@ struct InsertionProducer {
                 const int e = tid + i * NT, j = e % KT, q = e / KT, d = q % 3;
                 const bool ok = e < 12 * KT && j < nsite;
                 const int n = t0 + j;
-                const int nm = (ok && nu < 3) ? site_shift(tg, n, nu, -1) : n;
+                int nm = n;
+                if (ok && nu < 3) {
+                    int x1, x2, x3;
+                    site_xyz_from(tg, x0, j, x1, x2, x3);
+                    nm = site_shift_xyz(tg, x1, x2, x3, nu, -1);
+                }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     rg.u[i][c] = ok ? U[(size_t)(c * 3 + d) * V3 + n] : C2<R>{0, 0};
@@ -260,8 +268,13 @@ struct InsertionProducer {
             const int bt = q / 12, rem = q % 12;
             const bool ok = e < 48 * KT && j < nsite;
             const int n = t0 + j;
-            const int np = (ok && nu < 3) ? site_shift(tg, n, nu, +1) : n;
-            const int nm = (ok && nu < 3) ? site_shift(tg, n, nu, -1) : n;
+            int np = n, nm = n;
+            if (ok && nu < 3) {
+                int x1, x2, x3;
+                site_xyz_from(tg, x0, j, x1, x2, x3);
+                np = site_shift_xyz(tg, x1, x2, x3, nu, +1);
+                nm = site_shift_xyz(tg, x1, x2, x3, nu, -1);
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 rg.g[i][d] = ok ? Gf[(size_t)((3 * bt + d) * 12 + rem) * V3 + np] : C2<R>{0, 0};

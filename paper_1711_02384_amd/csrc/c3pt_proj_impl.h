@@ -56,10 +56,11 @@ __device__ __forceinline__ void write_tile(const ProjGrid& pg, int chunk, int cb
 // ---------------------------------------------------------------------------
 // Native consumer: FP32 or FP64 MFMA 16x16x4 on P[col][site] (interleaved).
 // ---------------------------------------------------------------------------
-template <typename R_, int KT_, int MTMAX, int WM, int CT>
+template <typename R_, int KT_, int MTMAX, int WM, int CT, int MINW_ = 1>
 struct NativeCons {
     using R = R_;
     static constexpr int KT = KT_;
+    static constexpr int MINW = MINW_;           // minimum waves per SIMD the compiler must allow
     static constexpr int WN = 12 / CT;           // column groups of CT tiles of 16
     static constexpr int NT = 64 * WN * WM;      // WM waves split the row tiles
     static constexpr int RTW = MTMAX / WM;       // row tiles per wave
@@ -151,10 +152,11 @@ struct NativeCons {
 // K index k = 8*(lane/16) + e of one instruction covers 16 sites: site
 // 4*(lane/16) + e/2, component e&1.  KT must be a multiple of 16.
 // ---------------------------------------------------------------------------
-template <typename T16, int KT_, int MTMAX, int WM, int CT>
+template <typename T16, int KT_, int MTMAX, int WM, int CT, int MINW_ = 1>
 struct SplitCons {
     using R = float;
     static constexpr int KT = KT_;
+    static constexpr int MINW = MINW_;
     static constexpr int WN = 12 / CT;
     static constexpr int NT = 64 * WN * WM;
     static constexpr int RTW = MTMAX / WM;
@@ -272,7 +274,7 @@ struct SplitCons {
 // The fused kernel.
 // ---------------------------------------------------------------------------
 template <class Cons, template <typename, int, int> class ProdT>
-__global__ void __launch_bounds__(Cons::NT)
+__global__ void __launch_bounds__(Cons::NT, Cons::MINW)
 proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::Args pa) {
     using R = typename Cons::R;
     constexpr int KT = Cons::KT;
@@ -313,8 +315,9 @@ proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::A
 
     auto coords = [&](int t0, int buf) {
         if (tid < KT) {
-            int x1, x2, x3;
-            site_xyz(tg, min(t0 + tid, pg.V3 - 1), x1, x2, x3);
+            int x0[3], x1, x2, x3;
+            site_xyz(tg, t0, x0[0], x0[1], x0[2]);
+            site_xyz_from(tg, x0, tid, x1, x2, x3);
             int d1 = x1 - ph.r[0], d2 = x2 - ph.r[1], d3 = x3 - ph.r[2];
             sXr[buf][0][tid] = d1 + ((d1 < 0) ? L1 : 0);
             sXr[buf][1][tid] = d2 + ((d2 < 0) ? L2 : 0);
