@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Throughput of the spin-open three-point hot path on one MI355X.
 
-One step = one pass of every hot-path stage over one batch of synthetic input
-shaped like the 32^3 x 64 meson workload:
+One step = one pass of every hot-path stage over one batch of synthetic input.
+Default workload (``meson32``), shaped like the 32^3 x 64 meson measurement:
 
 * meson spectator at t_f = 16 (Eq. (9)) and a nucleon-type epsilon-tensor
   spectator at the same timeslice,
@@ -13,9 +13,16 @@ shaped like the 32^3 x 64 meson workload:
   derivative operators and the nucleon on the 161 pairs with p' = q or p' = 0.
 
 Inputs: 4 Z2xZ2 noise vectors, Gaussian propagators and stochastic solutions,
-Haar SU(3) links, complex64 in HBM (FP32 contractions and FP32 MFMA
-projection, FP64 split-site accumulation and FP64 combine).  Prints one JSON
-line.  `--gpus` above 1 is refused: this build runs on one GPU.
+Haar SU(3) links, complex64 in HBM (FP32 contractions, FP32 MFMA projection,
+FP64 split-site accumulation and FP64 combine).
+
+Other workloads (``--workload``): ``meson8`` (8^3 x 16, complex128, 27
+momenta, local insertion at tau = 0..8, all-pairs combine) and ``nucleon48``
+(48^3 x 64, two nucleon spectators (u,u) and (u,d), isovector insertion with
+u and d propagators at tau = 0..14, N = 8, 93 or 123 momenta, combine on the
+185 pairs with p' = q or p' = 0).
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -31,8 +38,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
-PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0}   # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
 
@@ -41,10 +47,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-baryon", action="store_true", help="meson only (drop the nucleon spectator)")
+    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48"], default="meson32")
+    ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
+    ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
-    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2"], default="f32",
+    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2"], default=None,
                     help="projection arithmetic: FP32 MFMA, or hi+lo BF16 / FP16 MFMA with FP32 accumulation")
     ap.add_argument("--tune", action="store_true", help="autotune kernel variants on this workload first")
     ap.add_argument("--tune-out", default=None, help="write the tuning table (JSON) here")
@@ -61,8 +69,15 @@ def pairs_diag_or_zero(n_mom):
     return np.array(pr, dtype=np.int32)
 
 
-class Workload:
-    name = "meson+nucleon 3pt, 32^3x64, t_f=16, tau=0..16, N=4, |k|^2<=6 (81 momenta), local+4 D_nu"
+def _up(a, dev, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a.astype(dtype))).to(dev)
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+class Meson32:
     L = (32, 32, 32)
     T = 64
     t_f = 16
@@ -71,36 +86,254 @@ class Workload:
     n2 = 6
     n_ops = 5
     cfg = 2
+    dtype = "c64"
+    default_proj = "f32"
+
+    def __init__(self, args):
+        self.baryon = not args.no_baryon
+        self.name = ("meson+nucleon 3pt, 32^3x64, t_f=16, tau=0..16, N=4, |k|^2<=6 (81 momenta), "
+                     "local+4 D_nu" + (", nucleon spectator" if self.baryon else ""))
+
+    def setup(self, c3pt, syn, dev, geom, k):
+        import torch
+        L, T = self.L, self.T
+        up = lambda a: _up(a, dev, np.complex64)
+        self.G1 = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
+        self.eta = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
+        gsl = sorted({t % T for tau in self.taus for t in (tau - 1, tau, tau + 1)})
+        usl = sorted({t % T for tau in self.taus for t in (tau - 1, tau)})
+        self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
+        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in self.taus}
+        self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
+        n_mom, n_tau = len(k), len(self.taus)
+        mk = lambda *sh: torch.empty(sh, dtype=torch.complex128, device=dev)
+        self.S = mk(self.N, n_mom, 192)
+        self.SB = mk(self.N, n_mom, 3072) if self.baryon else None
+        self.I = mk(self.N, n_tau, self.n_ops, n_mom, 192)
+        self.pairs = pairs_diag_or_zero(n_mom)
+        self.C_loc = mk(n_mom * n_mom, n_tau, 1, 64, 64)
+        self.C_der = mk(len(self.pairs), n_tau, self.n_ops - 1, 64, 64)
+        self.C_bar = mk(len(self.pairs), n_tau, 1, 1024, 64) if self.baryon else None
+        self.c3pt, self.geom, self.k = c3pt, geom, k
+
+    def calls(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        out = [("insertion", lambda: c.insertion(self.G3, self.s, self.taus, k, g, U_t=self.U, n_ops=self.n_ops,
+                                                 out=self.I)),
+               ("spectator_meson", lambda: c.spectator_meson(self.G1, self.eta, k, g, out=self.S))]
+        if self.baryon:
+            out.append(("spectator_baryon",
+                        lambda: c.spectator_baryon(self.G1, self.G1, self.eta, k, g, out=self.SB)))
+        return out
+
+    def step(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        c.spectator_meson(self.G1, self.eta, k, g, out=self.S)
+        if self.baryon:
+            c.spectator_baryon(self.G1, self.G1, self.eta, k, g, out=self.SB)
+        c.insertion(self.G3, self.s, self.taus, k, g, U_t=self.U, n_ops=self.n_ops, out=self.I)
+        c.combine(self.S, self.I, op_begin=0, op_end=1, out=self.C_loc)
+        c.combine(self.S, self.I, pairs=self.pairs, op_begin=1, op_end=self.n_ops, out=self.C_der)
+        if self.baryon:
+            c.combine(self.SB, self.I, pairs=self.pairs, op_begin=0, op_end=1, out=self.C_bar)
+
+    def units(self, n_mom):
+        V3 = int(np.prod(self.L))
+        spec = self.N * V3 * n_mom * (2 if self.baryon else 1)
+        ins = self.N * len(self.taus) * V3 * n_mom
+        return spec + ins
+
+    def components(self, n_mom):
+        V3 = int(np.prod(self.L))
+        return (self.N * V3 * n_mom * (192 + (3072 if self.baryon else 0))
+                + self.N * len(self.taus) * V3 * n_mom * 192 * self.n_ops)
+
+    def dominant(self, n_mom):
+        cols = self.N * len(self.taus) * self.n_ops * 192
+        return "proj_insertion", 8.0 * n_mom * int(np.prod(self.L)) * cols
+
+    def cpu_sample(self, k, n_slices):
+        import c3pt_synth as syn
+        import oracle
+        L, T = self.L, self.T
+        G1 = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
+        eta = syn.round_to_c64(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
+        taus = self.taus[len(self.taus) // 2: len(self.taus) // 2 + n_slices]
+        need = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
+        G3 = {t: syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in need}
+        s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in taus}
+        U = {t % T: syn.round_to_c64(syn.link_slice(L, self.cfg, t % T))
+             for t in sorted({t - 1 for t in taus} | set(taus))}
+        t0 = time.perf_counter()
+        oracle.spectator_meson(G1, eta, L, k)
+        oracle.insertion(G3, s, taus, L, T, k, U_t=U, n_ops=self.n_ops)
+        dt = time.perf_counter() - t0
+        units = self.N * int(np.prod(L)) * len(k) * (1 + len(taus))
+        return units, dt, (f"FP64 numpy oracle: meson spectator + insertion (5 ops) on {len(taus)} of "
+                           f"{len(self.taus)} timeslices, full 32^3 slices, N=4, {len(k)} momenta; nucleon "
+                           f"spectator and combine not in the sample")
+
+
+class Meson8(Meson32):
+    L = (8, 8, 8)
+    T = 16
+    t_f = 8
+    N = 1
+    taus = list(range(0, 9))
+    n2 = 3
+    n_ops = 1
+    cfg = 1
+    dtype = "c128"
+    default_proj = "f64"
+
+    def __init__(self, args):
+        self.baryon = False
+        self.name = "meson 3pt, 8^3x16, complex128, t_f=8, tau=0..8, N=1, |k|^2<=3 (27 momenta), local"
+
+    def setup(self, c3pt, syn, dev, geom, k):
+        import torch
+        L = self.L
+        up = lambda a: _up(a, dev, np.complex128)
+        self.G1 = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
+        self.eta = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
+        self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in self.taus}
+        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in self.taus}
+        n_mom = len(k)
+        mk = lambda *sh: torch.empty(sh, dtype=torch.complex128, device=dev)
+        self.S = mk(self.N, n_mom, 192)
+        self.I = mk(self.N, len(self.taus), 1, n_mom, 192)
+        self.C = mk(n_mom * n_mom, len(self.taus), 1, 64, 64)
+        self.c3pt, self.geom, self.k = c3pt, geom, k
+
+    def calls(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        return [("insertion", lambda: c.insertion(self.G3, self.s, self.taus, k, g, out=self.I)),
+                ("spectator_meson", lambda: c.spectator_meson(self.G1, self.eta, k, g, out=self.S))]
+
+    def step(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        c.spectator_meson(self.G1, self.eta, k, g, out=self.S)
+        c.insertion(self.G3, self.s, self.taus, k, g, out=self.I)
+        c.combine(self.S, self.I, out=self.C)
+
+    def dominant(self, n_mom):
+        cols = self.N * len(self.taus) * 192
+        return "proj_insertion", 8.0 * n_mom * int(np.prod(self.L)) * cols
+
+    def cpu_sample(self, k, n_slices):
+        import c3pt_synth as syn
+        import oracle
+        L, T = self.L, self.T
+        G1 = syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f)
+        eta = syn.z2z2_noise(L, self.N, self.cfg, self.t_f)
+        G3 = {t: syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t) for t in self.taus}
+        s = {t: syn.solution_slice(L, self.N, self.cfg, t) for t in self.taus}
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 10.0:
+            S = oracle.spectator_meson(G1, eta, L, k)
+            I = oracle.insertion(G3, s, self.taus, L, T, k)
+            oracle.combine(S, I)
+            reps += 1
+        dt = time.perf_counter() - t0
+        return self.units(len(k)) * reps, dt, f"FP64 numpy oracle: the whole step, repeated {reps} times"
+
+
+class Nucleon48(Meson32):
+    L = (48, 48, 48)
+    T = 64
+    t_f = 14
+    N = 8
+    taus = list(range(0, 15))
+    n2 = 8
+    n_ops = 1
+    cfg = 3
+    dtype = "c64"
+    default_proj = "bf16x2"
+
+    def __init__(self, args):
+        self.baryon = True
+        self.n2 = args.n2 if args.n2 is not None else 8
+        self.name = (f"nucleon 3pt, 48^3x64, t_f=14, tau=0..14, N=8, |k|^2<={self.n2}, spectators (u,u) and "
+                     f"(u,d), isovector insertion (u and d), local")
+
+    def setup(self, c3pt, syn, dev, geom, k):
+        import torch
+        L = self.L
+        up = lambda a: _up(a, dev, np.complex64)
+        self.Gu = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in self.taus}
+        self.Gd = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, t)) for t in self.taus}
+        self.eta = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
+        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in self.taus}
+        n_mom, n_tau = len(k), len(self.taus)
+        mk = lambda *sh: torch.empty(sh, dtype=torch.complex128, device=dev)
+        self.Suu = mk(self.N, n_mom, 3072)
+        self.Sud = mk(self.N, n_mom, 3072)
+        self.Iu = mk(self.N, n_tau, 1, n_mom, 192)
+        self.Id = mk(self.N, n_tau, 1, n_mom, 192)
+        self.pairs = pairs_diag_or_zero(n_mom)
+        self.Cd = mk(len(self.pairs), n_tau, 1, 1024, 64)
+        self.Cu = mk(len(self.pairs), n_tau, 1, 1024, 64)
+        self.c3pt, self.geom, self.k = c3pt, geom, k
+
+    def calls(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        tf = self.t_f
+        return [("insertion", lambda: c.insertion(self.Gu, self.s, self.taus, k, g, out=self.Iu)),
+                ("spectator_baryon", lambda: c.spectator_baryon(self.Gu[tf], self.Gu[tf], self.eta, k, g,
+                                                                out=self.Suu))]
+
+    def step(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        tf = self.t_f
+        # proton isovector: spectators (u,u) with the d insertion, (u,d) with the u insertion
+        c.spectator_baryon(self.Gu[tf], self.Gu[tf], self.eta, k, g, out=self.Suu)
+        c.spectator_baryon(self.Gu[tf], self.Gd[tf], self.eta, k, g, out=self.Sud)
+        c.insertion(self.Gu, self.s, self.taus, k, g, out=self.Iu)
+        c.insertion(self.Gd, self.s, self.taus, k, g, out=self.Id)
+        c.combine(self.Suu, self.Id, pairs=self.pairs, out=self.Cd)
+        c.combine(self.Sud, self.Iu, pairs=self.pairs, out=self.Cu)
+
+    def units(self, n_mom):
+        V3 = int(np.prod(self.L))
+        return 2 * self.N * V3 * n_mom + 2 * self.N * len(self.taus) * V3 * n_mom
+
+    def components(self, n_mom):
+        V3 = int(np.prod(self.L))
+        return 2 * self.N * V3 * n_mom * 3072 + 2 * self.N * len(self.taus) * V3 * n_mom * 192
+
+    def dominant(self, n_mom):
+        cols = self.N * 3072
+        return "proj_spectator_baryon", 8.0 * n_mom * int(np.prod(self.L)) * cols
+
+    def cpu_sample(self, k, n_slices):
+        import c3pt_synth as syn
+        import oracle
+        L = self.L
+        tau = self.taus[len(self.taus) // 2]
+        Gu = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, tau))
+        s = syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, tau))
+        t0 = time.perf_counter()
+        oracle.insertion({tau: Gu}, {tau: s}, [tau], L, self.T, k)
+        dt = time.perf_counter() - t0
+        units = self.N * int(np.prod(L)) * len(k)
+        return units, dt, (f"FP64 numpy oracle: one insertion timeslice (u), full 48^3, N=8, {len(k)} momenta; "
+                           f"nucleon spectators and combine not in the sample")
+
+
+WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48}
 
 
 def cpu_baseline(W, k, n_slices):
     """Time the FP64 oracle on a bounded sample of the same workload on the host."""
-    import c3pt_synth as syn
-    import oracle
     try:
         from threadpoolctl import threadpool_info
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    L, T = W.L, W.T
-    G1 = syn.round_to_c64(syn.propagator_slice(L, W.cfg, syn.FIELD_G1, W.t_f))
-    eta = syn.round_to_c64(syn.z2z2_noise(L, W.N, W.cfg, W.t_f))
-    taus = W.taus[len(W.taus) // 2: len(W.taus) // 2 + n_slices]
-    need = sorted({t for tau in taus for t in (tau - 1, tau, tau + 1)})
-    G3 = {t % T: syn.round_to_c64(syn.propagator_slice(L, W.cfg, syn.FIELD_G3, t % T)) for t in need}
-    s = {t: syn.round_to_c64(syn.solution_slice(L, W.N, W.cfg, t)) for t in taus}
-    U = {t % T: syn.round_to_c64(syn.link_slice(L, W.cfg, t % T)) for t in sorted({t - 1 for t in taus} | set(taus))}
-    t0 = time.perf_counter()
-    oracle.spectator_meson(G1, eta, L, k)
-    oracle.insertion(G3, s, taus, L, T, k, U_t=U, n_ops=W.n_ops)
-    dt = time.perf_counter() - t0
-    V3 = int(np.prod(L))
-    units = W.N * V3 * len(k) * (1 + len(taus))
+    units, dt, what = W.cpu_sample(k, n_slices)
     return {"value": units / dt, "unit": "site*momenta/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 numpy oracle: meson spectator + insertion (5 ops) on {len(taus)} of 17 "
-                      f"timeslices, full 32^3 slices, N=4, 81 momenta; {units:.3g} units in {dt:.1f} s; "
-                      f"nucleon spectator and combine not in the sample",
-            "seconds": dt}
+            "sample": f"{what}; {units:.3g} units in {dt:.1f} s", "seconds": dt}
 
 
 def main():
@@ -113,68 +346,34 @@ def main():
     import c3pt_synth as syn
     import paper_1711_02384_amd as c3pt
 
-    W = Workload()
-    baryon = not args.no_baryon
+    W = WORKLOADS[args.workload](args)
+    proj = args.proj or W.default_proj
+    if W.dtype == "c128":
+        proj = "f64"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    L, T = W.L, W.T
-    V3 = int(np.prod(L))
     k = c3pt.momentum_list(W.n2)
     n_mom = len(k)
-
-    def up(a):
-        return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).to(dev)
-
+    proj_flag = {"f64": c3pt.PROJ_NATIVE, "f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16,
+                 "f16x2": c3pt.PROJ_SPLIT_F16}[proj]
+    mode = c3pt.MODE[proj]
+    geom = c3pt.Geom(W.L, W.T, proj=proj_flag)
     log(f"[bench] generating inputs for {W.name}")
     t0 = time.perf_counter()
-    G1 = up(syn.propagator_slice(L, W.cfg, syn.FIELD_G1, W.t_f))
-    eta = up(syn.z2z2_noise(L, W.N, W.cfg, W.t_f))
-    g_slices = sorted({t % T for tau in W.taus for t in (tau - 1, tau, tau + 1)})
-    u_slices = sorted({t % T for tau in W.taus for t in (tau - 1, tau)})
-    G3 = {t: up(syn.propagator_slice(L, W.cfg, syn.FIELD_G3, t)) for t in g_slices}
-    s = {t: up(syn.solution_slice(L, W.N, W.cfg, t)) for t in W.taus}
-    U = {t: up(syn.link_slice(L, W.cfg, t)) for t in u_slices}
+    W.setup(c3pt, syn, dev, geom, k)
     torch.cuda.synchronize()
     log(f"[bench] inputs resident in HBM ({time.perf_counter() - t0:.1f} s)")
-
-    proj_flag = {"f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16, "f16x2": c3pt.PROJ_SPLIT_F16}[args.proj]
-    mode = {"f32": 1, "bf16x2": 2, "f16x2": 3}[args.proj]
-    geom = c3pt.Geom(L, T, proj=proj_flag)
-    n_tau = len(W.taus)
-    S = torch.empty((W.N, n_mom, 192), dtype=torch.complex128, device=dev)
-    SB = torch.empty((W.N, n_mom, 3072), dtype=torch.complex128, device=dev)
-    I = torch.empty((W.N, n_tau, W.n_ops, n_mom, 192), dtype=torch.complex128, device=dev)
-    pairs = pairs_diag_or_zero(n_mom)
-    C_loc = torch.empty((n_mom * n_mom, n_tau, 1, 64, 64), dtype=torch.complex128, device=dev)
-    C_der = torch.empty((len(pairs), n_tau, W.n_ops - 1, 64, 64), dtype=torch.complex128, device=dev)
-    C_bar = torch.empty((len(pairs), n_tau, 1, 1024, 64), dtype=torch.complex128, device=dev) if baryon else None
-
-    def step():
-        c3pt.spectator_meson(G1, eta, k, geom, out=S)
-        if baryon:
-            c3pt.spectator_baryon(G1, G1, eta, k, geom, out=SB)
-        c3pt.insertion(G3, s, W.taus, k, geom, U_t=U, n_ops=W.n_ops, out=I)
-        c3pt.combine(S, I, op_begin=0, op_end=1, out=C_loc)
-        c3pt.combine(S, I, pairs=pairs, op_begin=1, op_end=W.n_ops, out=C_der)
-        if baryon:
-            c3pt.combine(SB, I, pairs=pairs, op_begin=0, op_end=1, out=C_bar)
+    cls = c3pt.mt_class(n_mom, proj == "f64")
 
     tuning = None
     if args.tune:
         from paper_1711_02384_amd import autotune
-        cls = c3pt.mt_class(n_mom)
-        cases = [{"kind": "insertion", "mode": mode, "mt_class": cls,
-                  "call": lambda: c3pt.insertion(G3, s, W.taus, k, geom, U_t=U, n_ops=W.n_ops, out=I)},
-                 {"kind": "spectator_meson", "mode": mode, "mt_class": cls,
-                  "call": lambda: c3pt.spectator_meson(G1, eta, k, geom, out=S)}]
-        if baryon:
-            cases.append({"kind": "spectator_baryon", "mode": mode, "mt_class": cls,
-                          "call": lambda: c3pt.spectator_baryon(G1, G1, eta, k, geom, out=SB)})
+        cases = [{"kind": kn, "mode": mode, "mt_class": cls, "call": fn} for kn, fn in W.calls()]
         tuning = autotune.tune(cases, reps=3, log=log)
         if args.tune_out:
             autotune.save(tuning, args.tune_out)
     for _ in range(args.warmup):
-        step()
+        W.step()
     torch.cuda.synchronize()
     c3pt.profile_read(reset=True)
     c3pt.profile_enable(True)
@@ -184,7 +383,7 @@ def main():
     t_start = time.perf_counter()
     for a, b in evs:
         a.record(stream)
-        step()
+        W.step()
         b.record(stream)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
@@ -192,27 +391,20 @@ def main():
     prof = c3pt.profile_read(reset=True)
     lat = sorted(a.elapsed_time(b) for a, b in evs)
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
-
-    units_spec = W.N * V3 * n_mom * (2 if baryon else 1)
-    units_ins = W.N * n_tau * V3 * n_mom
-    units = units_spec + units_ins
+    units = W.units(n_mom)
     value = units / (ms_per_step * 1e-3)
 
-    # Dominant kernel: the fused insertion contraction + projection.
-    peak = PEAK_FP32_MFMA_TFLOPS if args.proj == "f32" else PEAK_BF16_MFMA_TFLOPS
-    ins_cols = W.N * n_tau * W.n_ops * 192
-    flops_ins = 8.0 * n_mom * V3 * ins_cols                  # complex GEMM flops, useful rows only
-    pi = prof.get("proj_insertion", {})
-    ins_ms = pi.get("avg_ms", float("nan"))
-    achieved = flops_ins / (ins_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": f"proj_insertion (fused FP32 contraction + {args.proj} MFMA projection)",
-                "flops_per_launch": flops_ins, "avg_ms": round(ins_ms, 4)}
-    if args.proj != "f32":
+    kname, flops = W.dominant(n_mom)
+    kms = prof.get(kname, {}).get("avg_ms", float("nan"))
+    achieved = flops / (kms * 1e-3) / 1e12
+    peak = PEAK[proj]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": f"{kname} (fused contraction + {proj} MFMA projection)",
+                "flops_per_launch": flops, "avg_ms": round(kms, 4)}
+    if proj in ("bf16x2", "f16x2"):
         roofline["note"] = ("flops counted once per complex MAC (8 real flops); the hi+lo split issues "
                             "3 MFMA products per term, so MFMA issue is 3x the counted flops")
-
     res = {
         "metric": "contracted site*momenta/s (spectator+insertion)",
         "value": value,
@@ -224,20 +416,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.proj == "f32" else f"f32 contraction, {args.proj} projection",
+        "dtype": {"f64": "f64", "f32": "f32", "bf16x2": "f32 contraction, bf16 hi+lo projection",
+                  "f16x2": "f32 contraction, f16 hi+lo projection"}[proj],
         "data": "synthetic",
-        "config": {"workload": W.name + (", nucleon spectator" if baryon else ""), "L": list(L), "T": T,
-                   "t_f": W.t_f, "n_noise": W.N, "n_tau": n_tau, "n_mom": n_mom, "n_ops": W.n_ops,
-                   "units_per_step": units, "combine_pairs": {"local": n_mom * n_mom, "derivative": len(pairs),
-                                                              "nucleon": len(pairs) if baryon else 0}},
+        "config": {"workload": W.name, "L": list(W.L), "T": W.T, "t_f": W.t_f, "n_noise": W.N,
+                   "n_tau": len(W.taus), "n_mom": n_mom, "n_ops": W.n_ops, "units_per_step": units},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "component_rate": {"projected_complex_values_per_s": (W.N * V3 * n_mom * (192 + (3072 if baryon else 0))
-                                                              + W.N * n_tau * V3 * n_mom * 192 * W.n_ops)
-                           / (ms_per_step * 1e-3)},
-        "kernels_ms": {kname: round(v["avg_ms"], 4) for kname, v in prof.items()},
-        "kernel_launches": {kname: v["count"] for kname, v in prof.items()},
+        "component_rate": {"projected_complex_values_per_s": W.components(n_mom) / (ms_per_step * 1e-3)},
+        "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
+        "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
         "roofline": roofline,
-        "variants": {kn: c3pt.get_variant(c3pt.KIND[kn], mode, c3pt.mt_class(n_mom))
+        "variants": {kn: c3pt.get_variant(c3pt.KIND[kn], mode, cls)
                      for kn in ("spectator_meson", "spectator_baryon", "insertion")},
     }
     if tuning is not None:
