@@ -160,7 +160,11 @@ int c3pt_version(void);
 /* Bytes of scratch currently held for `stream` (0 if none). */
 unsigned long long c3pt_scratch_bytes(void* stream);
 
-/* Release the scratch buffers of every stream (synchronizes those streams). */
+/* Release the scratch buffers of every stream and the cached phase tables
+ * (synchronizes the devices involved).  Phase tables (exp(i p.x) per site and
+ * momentum, in the layout the kernels read) are built on first use of a
+ * (geometry, source, sign, momentum group, arithmetic) and cached, up to 2 GiB
+ * per process. */
 int c3pt_release_scratch(void);
 
 /*

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -146,6 +147,35 @@ hipError_t timed(const char* name, hipStream_t st, F fn) {
     return e;
 }
 
+// ---- phase tables ---------------------------------------------------------
+// Built once per (device, geometry, source, sign, arithmetic, layout, momentum
+// group) and kept until c3pt_release_scratch or LRU eviction beyond a cap.
+struct PhaseKey {
+    int dev, L[3], r[3], sigma, mode, mtmax;
+    std::vector<int> k;
+    bool operator<(const PhaseKey& o) const {
+        return std::tie(dev, L[0], L[1], L[2], r[0], r[1], r[2], sigma, mode, mtmax, k) <
+               std::tie(o.dev, o.L[0], o.L[1], o.L[2], o.r[0], o.r[1], o.r[2], o.sigma, o.mode, o.mtmax, o.k);
+    }
+};
+struct PhaseEntry {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ready = nullptr;
+    unsigned long long last_use = 0;
+};
+constexpr size_t kPhaseCacheCap = (size_t)2 << 30;
+std::map<PhaseKey, PhaseEntry> g_phase;
+size_t g_phase_bytes = 0;
+unsigned long long g_phase_clock = 0;
+
+void free_phase_entry(PhaseEntry& e) {
+    if (e.ptr) hipFree(e.ptr);
+    if (e.ready) hipEventDestroy(e.ready);
+    g_phase_bytes -= e.bytes;
+    e = PhaseEntry{};
+}
+
 int check_geom(const c3pt_geom* g) {
     if (!g) return fail(C3PT_EINVAL, "geom is NULL");
     for (int j = 0; j < 3; ++j)
@@ -209,10 +239,65 @@ void fill_phase(PhaseSpec& ph, const c3pt_geom* g, int sigma, const int* k, cons
         ph.r[j] = posmod(g->r[j], g->L[j]);
     }
     ph.sigma = sigma;
-    ph.cubic = (g->L[0] == g->L[1] && g->L[1] == g->L[2]) ? 1 : 0;
     ph.n_mom = mg.n;
     for (int m = 0; m < mg.n; ++m)
         for (int j = 0; j < 3; ++j) ph.k[j][m] = (uint8_t)posmod(k[3 * (mg.off + m) + j], g->L[j]);
+}
+
+// Phase table of one momentum group (built on `st` when missing).
+int phase_table(const c3pt_geom* g, int sigma, int mode, int mtmax, const int* k, const MomGroup& mg,
+                hipStream_t st, const void** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    PhaseSpec ph;
+    fill_phase(ph, g, sigma, k, mg);
+    PhaseKey key;
+    key.dev = dev;
+    for (int j = 0; j < 3; ++j) {
+        key.L[j] = ph.L[j];
+        key.r[j] = ph.r[j];
+    }
+    key.sigma = sigma;
+    key.mode = mode;
+    key.mtmax = mtmax;
+    for (int m = 0; m < mg.n; ++m)
+        for (int j = 0; j < 3; ++j) key.k.push_back(ph.k[j][m]);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_phase.find(key);
+    if (it != g_phase.end()) {
+        it->second.last_use = ++g_phase_clock;
+        if (hipStreamWaitEvent(st, it->second.ready, 0) != hipSuccess)
+            return fail(C3PT_EDEVICE, "waiting for the phase table failed");
+        *out = it->second.ptr;
+        return C3PT_OK;
+    }
+    const int V3 = g->L[0] * g->L[1] * g->L[2];
+    const size_t bytes = phase_table_bytes(mode, V3, mtmax);
+    while (g_phase_bytes + bytes > kPhaseCacheCap && !g_phase.empty()) {
+        auto lru = g_phase.begin();
+        for (auto jt = g_phase.begin(); jt != g_phase.end(); ++jt)
+            if (jt->second.last_use < lru->second.last_use) lru = jt;
+        hipDeviceSynchronize();
+        free_phase_entry(lru->second);
+        g_phase.erase(lru);
+    }
+    PhaseEntry e;
+    if (hipMalloc(&e.ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(C3PT_ENOMEM, "phase table allocation of %zu bytes failed", bytes);
+    }
+    e.bytes = bytes;
+    g_phase_bytes += bytes;
+    if (launch_phase_table(mode, ph, V3, mtmax, e.ptr, st) != hipSuccess ||
+        hipEventCreateWithFlags(&e.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(e.ready, st) != hipSuccess) {
+        free_phase_entry(e);
+        return fail(C3PT_EDEVICE, "building the phase table failed");
+    }
+    e.last_use = ++g_phase_clock;
+    g_phase[key] = e;
+    *out = e.ptr;
+    return C3PT_OK;
 }
 
 // Sites per split-site chunk: enough chunks to fill the chip, never more than
@@ -238,9 +323,9 @@ int to_status(hipError_t e, const char* what) {
 // Runs projection launches over momentum groups and reduces each into `out`.
 // `launch(pg, mt)` enqueues one fused kernel for the grid pg.
 template <class Launch>
-int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, const int* k, int n_mom, int n_colblocks,
-                   int group_cols, int n_groups, int inner, int outer_stride, int off,
-                   void* out, Launch launch) {
+int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, const int* k, int n_mom,
+                   int n_colblocks, int n_share, int n_per_share, int group_cols, int n_groups, int inner,
+                   int outer_stride, int off, void* out, Launch launch) {
     hipStream_t st = (hipStream_t)g->stream;
     const bool f64 = g->dtype == C3PT_C128;
     const int mode = proj_mode(g);
@@ -253,14 +338,20 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
     void* part;
     if (int rc = scratch_dev(st, bytes, &part)) return rc;
     for (const MomGroup& mg : groups) {
+        const int mt = (mg.n + 7) / 8;
+        const int mtmax = f64 ? 4 : (mt <= 4 ? 4 : mt <= 8 ? 8 : mt <= 12 ? 12 : 16);
+        const void* tab;
+        if (int rc = phase_table(g, sigma, mode, mtmax, k, mg, st, &tab)) return rc;
         ProjGrid pg;
-        fill_phase(pg.ph, g, sigma, k, mg);
         pg.V3 = V3;
+        pg.n_mom = mg.n;
         pg.chunk_sites = chunk_sites;
         pg.n_chunks = n_chunks;
         pg.n_colblocks = n_colblocks;
+        pg.n_share = n_share;
+        pg.n_per_share = n_per_share;
+        pg.phase = tab;
         pg.partial = (double2*)part;
-        const int mt = (mg.n + 7) / 8;
         int variant;
         {
             std::lock_guard<std::mutex> lk(g_mu);
@@ -318,6 +409,12 @@ int c3pt_release_scratch(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess) return fail(C3PT_EDEVICE, "hipGetDevice failed");
+    for (auto& kv : g_phase) {
+        hipSetDevice(kv.first.dev);
+        hipDeviceSynchronize();
+        free_phase_entry(kv.second);
+    }
+    g_phase.clear();
     for (auto& kv : g_scratch) {
         hipSetDevice(kv.first.first);
         hipStreamSynchronize(kv.first.second);
@@ -392,9 +489,9 @@ int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* et
     if (int rc = check_momenta(k, n_mom)) return rc;
     if (!G_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
-    MesonSpecArgs a{G_tf, eta};
-    int rc = run_projection("proj_spectator_meson", 0, geom, -1, k, n_mom, n_noise, kBlockCols, n_noise, n_noise, 0,
-                            0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
+    MesonSpecArgs a{{geom->L[0], geom->L[1], geom->L[2]}, G_tf, eta};
+    int rc = run_projection("proj_spectator_meson", 0, geom, -1, k, n_mom, n_noise, 1, n_noise, kBlockCols,
+                            n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
                                 return launch_spectator_meson(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
                             });
     return rc ? rc : ok();
@@ -406,9 +503,9 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
     if (int rc = check_momenta(k, n_mom)) return rc;
     if (!G1_tf || !G2_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
-    BaryonSpecArgs a{G1_tf, G2_tf, eta};
-    int rc = run_projection("proj_spectator_baryon", 1, geom, -1, k, n_mom, n_noise * 16, 3072, n_noise, n_noise,
-                            0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
+    BaryonSpecArgs a{{geom->L[0], geom->L[1], geom->L[2]}, G1_tf, G2_tf, eta};
+    int rc = run_projection("proj_spectator_baryon", 1, geom, -1, k, n_mom, n_noise * 16, 1, n_noise * 16, 3072,
+                            n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
                                 return launch_spectator_baryon(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
                             });
     return rc ? rc : ok();
@@ -441,6 +538,7 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
         InsertionArgs a;
         memset(&a, 0, sizeof(a));
+        for (int j = 0; j < 3; ++j) a.L[j] = geom->L[j];
         a.n_tau = nt;
         a.n_ops = n_ops;
         a.n_noise = n_noise;
@@ -457,8 +555,8 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             }
         }
         const int ncb = n_noise * nt * n_ops;
-        int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, kBlockCols, ncb, nt * n_ops,
-                                n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
+        int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_ops, kBlockCols, ncb,
+                                nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
                                     return launch_insertion(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
                                 });
         if (rc) return rc;

@@ -21,38 +21,46 @@ constexpr int kMaxTauPerLaunch = 24;
 constexpr int kMaxSitesPerChunkF32 = 2048;
 constexpr int kMaxL = 256;
 
-// Momentum list and phase convention of one projection launch.
+// Momentum list and phase convention of one momentum group (phase tables).
 struct PhaseSpec {
     int L[3];
     int r[3];          // source position, already reduced into [0, L_j)
     int sigma;         // -1 spectator, +1 insertion
-    int cubic;         // L1 == L2 == L3: single-table phase lookup
     int n_mom;         // momenta in this group
     uint8_t k[3][kMaxMomGroup];   // components reduced into [0, L_j)
 };
 
+// One launch of the fused contraction + projection kernel.  Work items are
+// (share, chunk, within) with column block cb = colblock(share, within):
+// items that read the same input slice (same share) and chunk are issued to
+// the same XCD so that they meet in its L2.
 struct ProjGrid {
-    PhaseSpec ph;
     int V3;
-    int chunk_sites;   // sites per split-site chunk (multiple of the site tile)
+    int n_mom;         // momenta in this group
+    int chunk_sites;   // sites per split-site chunk (multiple of 32)
     int n_chunks;
     int n_colblocks;
+    int n_share, n_per_share;
+    const void* phase; // phase table of the group, in the consumer's layout
     double2* partial;  // [n_chunks][n_colblocks][n_mom][192] FP64 partial sums
 };
 
 // Producer arguments -------------------------------------------------------
 struct MesonSpecArgs {
+    int L[3];
     const void* G;     // [144][V3]
     const void* eta;   // [N][12][V3]
 };
 
 struct BaryonSpecArgs {
+    int L[3];
     const void* G1;
     const void* G2;
     const void* eta;
 };
 
 struct InsertionArgs {
+    int L[3];
     int n_tau;         // timeslices in this launch
     int n_ops;         // 1 or 5
     int n_noise;
@@ -110,6 +118,12 @@ hipError_t launch_spectator_baryon(int mode, int mt, int variant, const ProjGrid
 hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, const InsertionArgs& a,
                             hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+// Phase tables (c3pt_phase.hip).  Native layout: [Vpad][8*mtmax] complex
+// (double for mode kModeF64, float for kModeF32).  Split layout:
+// [Vpad/16][hi, lo][mtmax][64 lanes][8] 16-bit values in MFMA A-operand order.
+// Vpad = V3 rounded up to 32; padding sites and rows hold zeros.
+size_t phase_table_bytes(int mode, int V3, int mtmax);
+hipError_t launch_phase_table(int mode, const PhaseSpec& ph, int V3, int mtmax, void* out, hipStream_t st);
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
 
 }  // namespace c3pt

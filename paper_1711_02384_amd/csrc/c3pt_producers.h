@@ -24,6 +24,8 @@ struct PerThread {
 template <typename R, int KT, int NT>
 struct MesonSpecProducer {
     using Args = MesonSpecArgs;
+    static_assert(NT % KT == 0, "every thread keeps one site of the tile");
+    static __device__ __forceinline__ int colblock(const Args&, int, int within) { return within; }
     static constexpr int kV = PerThread<12 * KT, NT>::value;
     static constexpr int kT = PerThread<48 * KT, NT>::value;
     struct Regs {
@@ -89,6 +91,8 @@ struct MesonSpecProducer {
 template <typename R, int KT, int NT>
 struct BaryonSpecProducer {
     using Args = BaryonSpecArgs;
+    static_assert(NT % KT == 0, "every thread keeps one site of the tile");
+    static __device__ __forceinline__ int colblock(const Args&, int, int within) { return within; }
     static constexpr int kV = PerThread<21 * KT, NT>::value;
     static constexpr int kT = PerThread<16 * KT, NT>::value;
     struct Regs {
@@ -192,6 +196,12 @@ struct BaryonSpecProducer {
 template <typename R, int KT, int NT>
 struct InsertionProducer {
     using Args = InsertionArgs;
+    static_assert(NT % KT == 0, "every thread keeps one site of the tile");
+    // work items that share a timeslice (share) are adjacent: within = noise * n_ops + op
+    static __device__ __forceinline__ int colblock(const Args& a, int share, int within) {
+        const int noise = within / a.n_ops, op = within % a.n_ops;
+        return (noise * a.n_tau + share) * a.n_ops + op;
+    }
     static constexpr int kV = PerThread<12 * KT, NT>::value;
     static constexpr int kT = PerThread<48 * KT, NT>::value;
     struct Regs {
@@ -235,24 +245,27 @@ struct InsertionProducer {
             return;
         }
         const int nu = op - 1;
-        // coordinates of the tile's first site (uniform), neighbours by carrying
-        int x0[3];
-        site_xyz(tg, t0, x0[0], x0[1], x0[2]);
+        // every thread works on one site j of the tile: its neighbours once
+        const int j = tid % KT;
+        const bool site_ok = j < nsite;
+        const int n = t0 + j;
+        int np = n, nm = n;
+        if (nu < 3) {
+            int x0[3], x1, x2, x3;
+            site_xyz(tg, t0, x0[0], x0[1], x0[2]);
+            site_xyz_from(tg, x0, j, x1, x2, x3);
+            np = site_shift_xyz(tg, x1, x2, x3, nu, +1);
+            nm = site_shift_xyz(tg, x1, x2, x3, nu, -1);
+            if (!site_ok) np = nm = t0;
+        }
         // transport tasks (q = at*3 + d, site j): links at y and y - nu
         {
             const C2<R>* U = (const C2<R>*)a.U[tl] + (size_t)nu * 9 * V3;
             const C2<R>* Um = (nu < 3) ? U : (const C2<R>*)a.Up[tl] + (size_t)3 * 9 * V3;
 #pragma unroll
             for (int i = 0; i < kV; ++i) {
-                const int e = tid + i * NT, j = e % KT, q = e / KT, d = q % 3;
-                const bool ok = e < 12 * KT && j < nsite;
-                const int n = t0 + j;
-                int nm = n;
-                if (ok && nu < 3) {
-                    int x1, x2, x3;
-                    site_xyz_from(tg, x0, j, x1, x2, x3);
-                    nm = site_shift_xyz(tg, x1, x2, x3, nu, -1);
-                }
+                const int e = tid + i * NT, q = e / KT, d = q % 3;
+                const bool ok = e < 12 * KT && site_ok;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     rg.u[i][c] = ok ? U[(size_t)(c * 3 + d) * V3 + n] : C2<R>{0, 0};
@@ -264,21 +277,14 @@ struct InsertionProducer {
         const C2<R>* Gb = (const C2<R>*)((nu < 3) ? a.G[tl] : a.Gp[tl]);
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             const int bt = q / 12, rem = q % 12;
-            const bool ok = e < 48 * KT && j < nsite;
-            const int n = t0 + j;
-            int np = n, nm = n;
-            if (ok && nu < 3) {
-                int x1, x2, x3;
-                site_xyz_from(tg, x0, j, x1, x2, x3);
-                np = site_shift_xyz(tg, x1, x2, x3, nu, +1);
-                nm = site_shift_xyz(tg, x1, x2, x3, nu, -1);
-            }
+            const bool ok = e < 48 * KT && site_ok;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                rg.g[i][d] = ok ? Gf[(size_t)((3 * bt + d) * 12 + rem) * V3 + np] : C2<R>{0, 0};
-                rg.g[i][3 + d] = ok ? Gb[(size_t)((3 * bt + d) * 12 + rem) * V3 + nm] : C2<R>{0, 0};
+                const size_t plane = (size_t)((3 * bt + d) * 12 + rem) * V3;
+                rg.g[i][d] = ok ? Gf[plane + np] : C2<R>{0, 0};
+                rg.g[i][3 + d] = ok ? Gb[plane + nm] : C2<R>{0, 0};
             }
         }
     }
