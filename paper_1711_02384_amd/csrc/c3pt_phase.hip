@@ -80,12 +80,14 @@ int vpad(int V3) { return (V3 + 31) / 32 * 32; }
 
 }  // namespace
 
+// Bytes per (site, momentum row): one complex value (FP64: 16, FP32: 8), or in
+// the split layout four A-operand values x (hi, lo) x 2 bytes = 16.
 size_t phase_table_bytes(int mode, int V3, int mtmax) {
     const size_t rows = (size_t)vpad(V3) * 8 * mtmax;
     switch (mode) {
         case kModeF64: return rows * 16;
         case kModeF32: return rows * 8;
-        default: return rows * 8;   // 4 values x (hi, lo) x 2 bytes per (site, momentum)
+        default: return rows * 16;
     }
 }
 

@@ -1,0 +1,93 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
+
+The GPU computes every part of the step; the FP64 oracle recomputes sampled
+outputs (selected timeslices, noise vectors or momenta) one by one.
+
+* 32^3 x 64 meson step (FP32): spectator (all outputs), insertion with the
+  five operators at tau = 0, 8, 16 (the full 17-slice launch runs on the GPU),
+  and the combine on sampled pairs built from the oracle's own parts.
+* 48^3 x 64 nucleon step with split-precision projection (BF16 and FP16 hi+lo):
+  the nucleon spectator for one noise vector and a momentum subset, and one
+  insertion timeslice.  Tolerance 1e-5 relative (Frobenius), the same as FP32.
+"""
+import numpy as np
+import pytest
+
+import c3pt_synth as syn
+import oracle
+from helpers import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL32 = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _up(a):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).cuda()
+
+
+def test_meson32_step_sampled():
+    import paper_1711_02384_amd as c3pt
+    L, T, N, t_f, cfg = (32, 32, 32), 64, 4, 16, 2
+    taus = list(range(17))
+    k = c3pt.momentum_list(6)
+    _say("meson32: generating inputs")
+    G1 = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G1, t_f))
+    eta = syn.round_to_c64(syn.z2z2_noise(L, N, cfg, t_f))
+    gsl = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
+    usl = sorted({t % T for tau in taus for t in (tau - 1, tau)})
+    G3 = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in gsl}
+    s = {t: syn.round_to_c64(syn.solution_slice(L, N, cfg, t)) for t in taus}
+    U = {t: syn.round_to_c64(syn.link_slice(L, cfg, t)) for t in usl}
+    geom = c3pt.Geom(L, T)
+    _say("meson32: GPU step")
+    S = c3pt.spectator_meson(_up(G1), _up(eta), k, geom)
+    I = c3pt.insertion({t: _up(v) for t, v in G3.items()}, {t: _up(v) for t, v in s.items()}, taus, k, geom,
+                       U_t={t: _up(v) for t, v in U.items()}, n_ops=5)
+    torch.cuda.synchronize()
+    S_o = oracle.spectator_meson(G1, eta, L, k)
+    err = rel_fro(S.cpu().numpy(), S_o)
+    _say(f"meson32: spectator rel err {err:.2e}")
+    assert err < TOL32
+    Ih = I.cpu().numpy()
+    for tau in (0, 8, 16):
+        I_o = oracle.insertion(G3, s, [tau], L, T, k, U_t=U, n_ops=5)
+        for op in range(5):
+            e = rel_fro(Ih[:, tau, op], I_o[:, 0, op])
+            _say(f"meson32: insertion tau={tau} op={op} rel err {e:.2e}")
+            assert e < TOL32
+    # combine on sampled pairs, from the oracle's parts (checks the full-size launch shape)
+    pairs = [(0, 0), (40, 40), (80, 3), (0, 80)]
+    I8 = oracle.insertion(G3, s, [8], L, T, k, U_t=U, n_ops=5)
+    C = c3pt.combine(torch.from_numpy(S_o).cuda(), torch.from_numpy(I8).cuda(), pairs=pairs).cpu().numpy()
+    assert rel_fro(C, oracle.combine(S_o, I8, pairs=pairs)) < 1e-12
+
+
+@pytest.mark.parametrize("proj,name", [(2, "bf16x2"), (1, "f16x2")])
+def test_nucleon48_split_sampled(proj, name):
+    import paper_1711_02384_amd as c3pt
+    L, T, N, t_f, cfg = (48, 48, 48), 64, 8, 14, 3
+    k = c3pt.momentum_list(9)          # 123 momenta: one 128-row group
+    _say(f"nucleon48 {name}: generating inputs")
+    Gu = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t_f))
+    Gd = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G1, t_f))
+    eta = syn.round_to_c64(syn.z2z2_noise(L, N, cfg, t_f))
+    geom = c3pt.Geom(L, T, proj=proj)
+    SB = c3pt.spectator_baryon(_up(Gu), _up(Gd), _up(eta), k, geom).cpu().numpy()
+    sel_m = [0, 1, 30, 92, 122]
+    want = oracle.spectator_baryon(Gu, Gd, eta[3:4], L, k[sel_m])
+    err = rel_fro(SB[3:4, sel_m], want)
+    _say(f"nucleon48 {name}: baryon spectator (noise 3, 5 momenta) rel err {err:.2e}")
+    assert err < TOL32
+    tau = 7
+    G7 = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, tau))
+    s7 = syn.round_to_c64(syn.solution_slice(L, N, cfg, tau))
+    I = c3pt.insertion({tau: _up(G7)}, {tau: _up(s7)}, [tau], k, geom).cpu().numpy()
+    I_o = oracle.insertion({tau: G7}, {tau: s7}, [tau], L, T, k)
+    err = rel_fro(I, I_o)
+    _say(f"nucleon48 {name}: insertion tau={tau} rel err {err:.2e}")
+    assert err < TOL32
