@@ -251,6 +251,7 @@ int phase_table(const c3pt_geom* g, int sigma, int mode, int mtmax, const int* k
     if (int rc = current_device(&dev)) return rc;
     PhaseSpec ph;
     fill_phase(ph, g, sigma, k, mg);
+    ph.r[0] = ph.r[1] = ph.r[2] = 0;   // tables at the origin; the source factor is applied on reduction
     PhaseKey key;
     key.dev = dev;
     for (int j = 0; j < 3; ++j) {
@@ -334,7 +335,7 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
     int chunk_sites, n_chunks;
     plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks);
     const size_t gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
-    const size_t bytes = (size_t)n_chunks * n_colblocks * gmax * kBlockCols * sizeof(double2);
+    const size_t bytes = (size_t)n_chunks * n_colblocks * gmax * kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));
     void* part;
     if (int rc = scratch_dev(st, bytes, &part)) return rc;
     for (const MomGroup& mg : groups) {
@@ -351,7 +352,7 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
         pg.n_share = n_share;
         pg.n_per_share = n_per_share;
         pg.phase = tab;
-        pg.partial = (double2*)part;
+        pg.partial = part;
         int variant;
         {
             std::lock_guard<std::mutex> lk(g_mu);
@@ -360,7 +361,9 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
         if (int rc = to_status(timed(kname, st, [&] { return launch(mode, pg, mt, variant); }), "projection launch"))
             return rc;
         ReduceArgs ra;
-        ra.partial = (const double2*)part;
+        ra.partial = part;
+        ra.f64 = f64 ? 1 : 0;
+        fill_phase(ra.ph, g, sigma, k, mg);
         ra.out = (double2*)out;
         ra.n_chunks = n_chunks;
         ra.n_colblocks = n_colblocks;

@@ -1,15 +1,35 @@
 // FP64 kernels of libc3pt: the deterministic reduction of split-site partial
-// sums and the noise-weighted combine of spectator and insertion parts.
+// sums (single calls and batches) and the noise-weighted combine of spectator
+// and insertion parts.
 #include "c3pt_device.h"
 
 namespace c3pt {
 
+// exp(-sigma 2 pi i k.r / L) for momentum k (components reduced mod L_j):
+// the phase origin moved from 0 to the source position r.
+__device__ __forceinline__ double2 source_factor(const int (&L)[3], const int (&r)[3], int sigma, int k1, int k2,
+                                                 int k3) {
+    const long long V3 = (long long)L[0] * L[1] * L[2];
+    const long long n = (long long)k1 * r[0] * (L[1] * L[2]) + (long long)k2 * r[1] * (L[0] * L[2]) +
+                        (long long)k3 * r[2] * (L[0] * L[1]);
+    double s, c;
+    sincospi(2.0 * (double)(n % V3) / (double)V3, &s, &c);
+    return make_double2(c, -sigma * s);
+}
+
+__device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
 // ---------------------------------------------------------------------------
-// Deterministic FP64 reduction of the split-site partial sums.
+// Deterministic FP64 reduction of the split-site partial sums, times the
+// source factor of each momentum.
 // ---------------------------------------------------------------------------
+template <typename P2>
 __global__ void __launch_bounds__(256) reduce_kernel(ReduceArgs a) {
     const size_t total = (size_t)a.n_groups * a.n_mom_grp * a.group_cols;
     const int blocks_per_group = a.group_cols / kBlockCols;
+    const P2* partial = (const P2*)a.partial;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(idx % a.group_cols);
@@ -20,14 +40,58 @@ __global__ void __launch_bounds__(256) reduce_kernel(ReduceArgs a) {
         const int cc = c % kBlockCols;
         double sx = 0.0, sy = 0.0;
         for (int ch = 0; ch < a.n_chunks; ++ch) {
-            const double2 v =
-                a.partial[(((size_t)ch * a.n_colblocks + cb) * a.n_mom_grp + m) * kBlockCols + cc];
-            sx += v.x;
-            sy += v.y;
+            const P2 v = partial[(((size_t)ch * a.n_colblocks + cb) * a.n_mom_grp + m) * kBlockCols + cc];
+            sx += (double)v.x;
+            sy += (double)v.y;
         }
+        const double2 f = source_factor(a.ph.L, a.ph.r, a.ph.sigma, a.ph.k[0][m], a.ph.k[1][m], a.ph.k[2][m]);
         const size_t G = (size_t)(g / a.inner) * a.outer_stride + a.off + g % a.inner;
-        a.out[(G * a.n_mom_total + a.m_off + m) * (size_t)a.group_cols + c] = make_double2(sx, sy);
+        a.out[(G * a.n_mom_total + a.m_off + m) * (size_t)a.group_cols + c] = cmul_d(f, make_double2(sx, sy));
     }
+}
+
+// ---------------------------------------------------------------------------
+// Batched reduction: thread per output element of any job of the group.  The
+// job of an element is found by binary search in the prefix sums.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) batch_reduce_kernel(BatchReduceArgs a, long long total) {
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int lo = 0, hi = a.n_jobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.out_offset[mid] <= idx) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchJob& job = a.jobs[lo];
+        const long long e = idx - a.out_offset[lo];
+        const int gc = job.group_cols;
+        const int c = (int)(e % gc);
+        const long long rest = e / gc;
+        const int m = (int)(rest % a.n_mom);
+        const int g = (int)(rest / a.n_mom);
+        const int cb = g * (gc / kBlockCols) + c / kBlockCols;
+        const int cc = c % kBlockCols;
+        const float2* partial = (const float2*)job.partial;
+        double sx = 0.0, sy = 0.0;
+        for (int ch = 0; ch < job.n_chunks; ++ch) {
+            const float2 v = partial[(((size_t)ch * job.n_colblocks + cb) * a.n_mom + m) * kBlockCols + cc];
+            sx += (double)v.x;
+            sy += (double)v.y;
+        }
+        int k[3];
+        for (int j = 0; j < 3; ++j) {
+            const int L = job.L[j];
+            k[j] = ((a.k[j][m] % L) + L) % L;
+        }
+        const double2 f = source_factor(job.L, job.r, job.sigma, k[0], k[1], k[2]);
+        job.out[e] = cmul_d(f, make_double2(sx, sy));
+    }
+}
+
+__global__ void reset_kernel(int* counters, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counters[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -105,7 +169,23 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     size_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    if (a.f64)
+        hipLaunchKernelGGL(reduce_kernel<double2>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(reduce_kernel<float2>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const BatchReduceArgs& a, long long total, hipStream_t st) {
+    long long blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(int* counters, int n, hipStream_t st) {
+    hipLaunchKernelGGL(reset_kernel, dim3((n + 255) / 256), dim3(256), 0, st, counters, n);
     return hipGetLastError();
 }
 

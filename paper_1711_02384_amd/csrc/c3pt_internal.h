@@ -21,7 +21,9 @@ constexpr int kMaxTauPerLaunch = 24;
 constexpr int kMaxSitesPerChunkF32 = 2048;
 constexpr int kMaxL = 256;
 
-// Momentum list and phase convention of one momentum group (phase tables).
+// Momentum list and phase convention of one momentum group.  Phase tables
+// are built for the origin r = 0; the source offset of Sec. 2.1 enters as the
+// per-momentum factor exp(-sigma 2 pi i k.r / L) when the sums are written.
 struct PhaseSpec {
     int L[3];
     int r[3];          // source position, already reduced into [0, L_j)
@@ -41,8 +43,9 @@ struct ProjGrid {
     int n_chunks;
     int n_colblocks;
     int n_share, n_per_share;
-    const void* phase; // phase table of the group, in the consumer's layout
-    double2* partial;  // [n_chunks][n_colblocks][n_mom][192] FP64 partial sums
+    const void* phase; // phase table of the group (origin r = 0), in the consumer's layout
+    void* partial;     // [n_chunks][n_colblocks][n_mom][192] partial sums in the accumulator type
+                       // (complex float; complex double for complex128 inputs)
 };
 
 // Producer arguments -------------------------------------------------------
@@ -72,12 +75,49 @@ struct InsertionArgs {
     const void* Up[kMaxTauPerLaunch];    // U(tau-1)
 };
 
+// One job of a batch (device copy): a spectator or an insertion call.
+struct BatchJob {
+    int kind;          // 0 meson spectator, 1 baryon spectator, 2 insertion
+    int V3, L[3], r[3];
+    int sigma;
+    int n_noise, n_tau, n_ops;
+    int n_colblocks, n_chunks, chunk_sites;
+    int group_cols;    // 192 or 3072 output columns per group
+    const void* G;     // spectator propagator (baryon: G1)
+    const void* G2;    // baryon: G2
+    const void* eta;   // spectator noise
+    const void* const* tau_ptrs;   // insertion: device table [n_tau][6] = G, G(+1), G(-1), s, U, U(-1)
+    const void* phase; // phase table (origin r = 0) for (L, sigma, momenta, layout)
+    void* partial;     // [n_chunks][n_colblocks][n_mom][192] (complex float)
+    double2* out;      // output in the layout of the single call
+};
+
+// A persistent projection launch over the items of several jobs of one kind.
+struct BatchGrid {
+    const BatchJob* jobs;
+    const int4* items;     // (job, column block, chunk, 0) in issue order
+    int n_items;
+    int n_mom;
+    int* counter;          // work-queue head, zeroed by the batch's reset kernel
+};
+
+// Batched reduction: one output element per thread over all jobs of a group.
+struct BatchReduceArgs {
+    const BatchJob* jobs;
+    const long long* out_offset;   // prefix sums of output elements per job (n_jobs + 1)
+    int n_jobs;
+    int n_mom;
+    short k[3][kMaxMomGroup];      // momenta (signed); reduced per job
+};
+
 // Reduction of the split-site partial sums: output[G][m][c], c < group_cols,
 // with output group G = (g / inner) * outer_stride + off + g % inner for the
 // launch-local group g (this places a subset of insertion timeslices).
 struct ReduceArgs {
-    const double2* partial;
+    const void* partial;
+    int f64;           // partials are complex double (else complex float)
     double2* out;
+    PhaseSpec ph;      // momenta of the group, source position and sign (for the source factor)
     int n_chunks;
     int n_colblocks;
     int n_groups;      // launch-local groups
@@ -118,6 +158,13 @@ hipError_t launch_spectator_baryon(int mode, int mt, int variant, const ProjGrid
 hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, const InsertionArgs& a,
                             hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+// Persistent batch launch of one producer kind; with bg == nullptr only the
+// occupancy (workgroups per CU) of the variant is returned.
+int batch_meson(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+int batch_baryon(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+int batch_insertion(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+hipError_t launch_batch_reduce(const BatchReduceArgs& a, long long total, hipStream_t st);
+hipError_t launch_reset(int* counters, int n, hipStream_t st);
 // Phase tables (c3pt_phase.hip).  Native layout: [Vpad][8*mtmax] complex
 // (double for mode kModeF64, float for kModeF32).  Split layout:
 // [Vpad/16][hi, lo][mtmax][64 lanes][8] 16-bit values in MFMA A-operand order.

@@ -1,9 +1,10 @@
 // Producers of libc3pt: contract one tile of KT sites into P[col][site] for
-// one 192-column block.  Each producer works in two phases so that the global
-// loads of the next tile are in flight while the current tile is projected:
+// one 192-column block.  A column block is first resolved into a context of
+// plain pointers (Ctx, once per work item); then, per tile:
 //   load(...)  -> registers (Regs), issued before the MFMA loop of the previous tile
 //   store(...) -> contraction from registers (+ LDS staging) into the sink
-// Sites j >= nsite contribute zeros.
+// Every thread keeps one site j = tid % KT of the tile.  Sites j >= nsite
+// contribute zeros.
 #pragma once
 
 #include "c3pt_device.h"
@@ -25,9 +26,12 @@ template <typename R, int KT, int NT>
 struct MesonSpecProducer {
     using Args = MesonSpecArgs;
     static_assert(NT % KT == 0, "every thread keeps one site of the tile");
-    static __device__ __forceinline__ int colblock(const Args&, int, int within) { return within; }
     static constexpr int kV = PerThread<12 * KT, NT>::value;
     static constexpr int kT = PerThread<48 * KT, NT>::value;
+    struct Ctx {
+        const C2<R>* G;
+        const C2<R>* eta;   // this noise vector
+    };
     struct Regs {
         C2<R> v[kV];
         C2<R> g[kT][3];
@@ -35,38 +39,47 @@ struct MesonSpecProducer {
     struct Smem {
         C2<R> v[12][KT];
     };
-    static __device__ __forceinline__ void load(const Args& a, const TileGeom& tg, int cb, int t0, int nsite,
-                                                Regs& rg, int tid) {
+    static __device__ __forceinline__ int colblock(const Args&, int, int within) { return within; }
+    static __device__ __forceinline__ Ctx resolve(const Args& a, int V3, int cb) {
+        return Ctx{(const C2<R>*)a.G, (const C2<R>*)a.eta + (size_t)cb * 12 * V3};
+    }
+    static __device__ __forceinline__ Ctx resolve(const BatchJob& b, int V3, int cb) {
+        return Ctx{(const C2<R>*)b.G, (const C2<R>*)b.eta + (size_t)cb * 12 * V3};
+    }
+    static __device__ __forceinline__ void load(const Ctx& c, const TileGeom& tg, int t0, int nsite, Regs& rg,
+                                                int tid) {
         const size_t V3 = (size_t)tg.V3;
-        const C2<R>* G = (const C2<R>*)a.G;
-        const C2<R>* eta = (const C2<R>*)a.eta + (size_t)cb * 12 * V3;
+        const int j = tid % KT;
+        const bool site_ok = j < nsite;
+        const size_t n = (size_t)t0 + j;
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, A = e / KT, j = e % KT;
-            rg.v[i] = (e < 12 * KT && j < nsite) ? eta[(size_t)A * V3 + t0 + j] : C2<R>{0, 0};
+            const int e = tid + i * NT, A = e / KT;
+            rg.v[i] = (e < 12 * KT && site_ok) ? c.eta[(size_t)A * V3 + n] : C2<R>{0, 0};
         }
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             const int ap = q / 12, rem = q % 12;
-            const bool ok = e < 48 * KT && j < nsite;
+            const bool ok = e < 48 * KT && site_ok;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                rg.g[i][c] = ok ? G[(size_t)((3 * ap + c) * 12 + rem) * V3 + t0 + j] : C2<R>{0, 0};
+            for (int cc = 0; cc < 3; ++cc)
+                rg.g[i][cc] = ok ? c.G[(size_t)((3 * ap + cc) * 12 + rem) * V3 + n] : C2<R>{0, 0};
         }
     }
     template <class Sink>
-    static __device__ __forceinline__ void store(const Args&, const TileGeom&, int, int, int, const Regs& rg,
-                                                 Smem& sm, Sink& sink, int tid) {
+    static __device__ __forceinline__ void store(const Ctx&, const TileGeom&, int, int, const Regs& rg, Smem& sm,
+                                                 Sink& sink, int tid) {
+        const int j = tid % KT;
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            const int e = tid + i * NT, A = e / KT;
             if (e < 12 * KT) sm.v[A][j] = (A >= 6) ? C2<R>{-rg.v[i].x, -rg.v[i].y} : rg.v[i];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             if (e >= 48 * KT) continue;
             const int ap = q / 12, al = (q % 12) / 3;
             const R sg = g5<R>(ap) * g5<R>(al);
@@ -92,9 +105,14 @@ template <typename R, int KT, int NT>
 struct BaryonSpecProducer {
     using Args = BaryonSpecArgs;
     static_assert(NT % KT == 0, "every thread keeps one site of the tile");
-    static __device__ __forceinline__ int colblock(const Args&, int, int within) { return within; }
     static constexpr int kV = PerThread<21 * KT, NT>::value;
     static constexpr int kT = PerThread<16 * KT, NT>::value;
+    struct Ctx {
+        const C2<R>* G1;
+        const C2<R>* G2;
+        const C2<R>* eta;   // this noise vector
+        int a1p, a1;
+    };
     struct Regs {
         C2<R> v[kV];
         C2<R> g2[kT][9];
@@ -103,45 +121,56 @@ struct BaryonSpecProducer {
         C2<R> v[12][KT];
         C2<R> g1[9][KT];
     };
-    static __device__ __forceinline__ void load(const Args& a, const TileGeom& tg, int cb, int t0, int nsite,
-                                                Regs& rg, int tid) {
+    static __device__ __forceinline__ int colblock(const Args&, int, int within) { return within; }
+    static __device__ __forceinline__ Ctx make(const void* G1, const void* G2, const void* eta, int V3, int cb) {
+        const int blk = cb & 15;
+        return Ctx{(const C2<R>*)G1, (const C2<R>*)G2, (const C2<R>*)eta + (size_t)(cb >> 4) * 12 * V3, blk >> 2,
+                   blk & 3};
+    }
+    static __device__ __forceinline__ Ctx resolve(const Args& a, int V3, int cb) {
+        return make(a.G1, a.G2, a.eta, V3, cb);
+    }
+    static __device__ __forceinline__ Ctx resolve(const BatchJob& b, int V3, int cb) {
+        return make(b.G, b.G2, b.eta, V3, cb);
+    }
+    static __device__ __forceinline__ void load(const Ctx& c, const TileGeom& tg, int t0, int nsite, Regs& rg,
+                                                int tid) {
         const size_t V3 = (size_t)tg.V3;
-        const int noise = cb >> 4, blk = cb & 15;
-        const int a1p = blk >> 2, a1 = blk & 3;
-        const C2<R>* G1 = (const C2<R>*)a.G1;
-        const C2<R>* G2 = (const C2<R>*)a.G2;
-        const C2<R>* eta = (const C2<R>*)a.eta + (size_t)noise * 12 * V3;
+        const int j = tid % KT;
+        const bool site_ok = j < nsite;
+        const size_t n = (size_t)t0 + j;
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            const int e = tid + i * NT, A = e / KT;
             C2<R> v = {0, 0};
-            if (e < 21 * KT && j < nsite) {
+            if (e < 21 * KT && site_ok) {
                 if (A < 12) {
-                    v = eta[(size_t)A * V3 + t0 + j];
+                    v = c.eta[(size_t)A * V3 + n];
                 } else {
                     const int cc = A - 12;
-                    v = G1[(size_t)((3 * a1p + cc / 3) * 12 + 3 * a1 + cc % 3) * V3 + t0 + j];
+                    v = c.G1[(size_t)((3 * c.a1p + cc / 3) * 12 + 3 * c.a1 + cc % 3) * V3 + n];
                 }
             }
             rg.v[i] = v;
         }
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             const int a2p = q >> 2, a2 = q & 3;
-            const bool ok = e < 16 * KT && j < nsite;
+            const bool ok = e < 16 * KT && site_ok;
 #pragma unroll
             for (int cc = 0; cc < 9; ++cc)
-                rg.g2[i][cc] = ok ? G2[(size_t)((3 * a2p + cc / 3) * 12 + 3 * a2 + cc % 3) * V3 + t0 + j]
+                rg.g2[i][cc] = ok ? c.G2[(size_t)((3 * a2p + cc / 3) * 12 + 3 * a2 + cc % 3) * V3 + n]
                                   : C2<R>{0, 0};
         }
     }
     template <class Sink>
-    static __device__ __forceinline__ void store(const Args&, const TileGeom&, int, int, int, const Regs& rg,
-                                                 Smem& sm, Sink& sink, int tid) {
+    static __device__ __forceinline__ void store(const Ctx&, const TileGeom&, int, int, const Regs& rg, Smem& sm,
+                                                 Sink& sink, int tid) {
+        const int j = tid % KT;
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            const int e = tid + i * NT, A = e / KT;
             if (e >= 21 * KT) continue;
             if (A < 12) sm.v[A][j] = (A >= 6) ? C2<R>{-rg.v[i].x, -rg.v[i].y} : rg.v[i];
             else sm.g1[A - 12][j] = rg.v[i];
@@ -149,7 +178,7 @@ struct BaryonSpecProducer {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             if (e >= 16 * KT) continue;
             C2<R> g1[9];
 #pragma unroll
@@ -197,13 +226,16 @@ template <typename R, int KT, int NT>
 struct InsertionProducer {
     using Args = InsertionArgs;
     static_assert(NT % KT == 0, "every thread keeps one site of the tile");
-    // work items that share a timeslice (share) are adjacent: within = noise * n_ops + op
-    static __device__ __forceinline__ int colblock(const Args& a, int share, int within) {
-        const int noise = within / a.n_ops, op = within % a.n_ops;
-        return (noise * a.n_tau + share) * a.n_ops + op;
-    }
     static constexpr int kV = PerThread<12 * KT, NT>::value;
     static constexpr int kT = PerThread<48 * KT, NT>::value;
+    struct Ctx {
+        const C2<R>* Gf;    // G at y + nu (local op: G(y))
+        const C2<R>* Gb;    // G at y - nu
+        const C2<R>* s;     // this noise vector at tau
+        const C2<R>* U;     // U_nu(y)
+        const C2<R>* Um;    // U_nu(y - nu) (time: slice tau - 1)
+        int nu;             // -1 for the local operator
+    };
     struct Regs {
         C2<R> v[kV];        // s entries
         C2<R> u[kV][6];     // transport task: U(y)[c][d], U(y-nu)[d][c] for c = 0..2
@@ -214,41 +246,63 @@ struct InsertionProducer {
         C2<R> tp[12][KT];
         C2<R> tm[12][KT];
     };
-    static __device__ __forceinline__ void decode(const Args& a, int cb, int& op, int& tl, int& noise) {
-        op = cb % a.n_ops;
-        const int rest = cb / a.n_ops;
-        tl = rest % a.n_tau;
-        noise = rest / a.n_tau;
+    // work items that share a timeslice (share) are adjacent: within = noise * n_ops + op
+    static __device__ __forceinline__ int colblock(const Args& a, int share, int within) {
+        const int noise = within / a.n_ops, op = within % a.n_ops;
+        return (noise * a.n_tau + share) * a.n_ops + op;
     }
-    static __device__ __forceinline__ void load(const Args& a, const TileGeom& tg, int cb, int t0, int nsite,
-                                                Regs& rg, int tid) {
-        const size_t V3 = (size_t)tg.V3;
-        int op, tl, noise;
-        decode(a, cb, op, tl, noise);
-        const C2<R>* s = (const C2<R>*)a.s[tl] + (size_t)noise * 12 * V3;
-#pragma unroll
-        for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, A = e / KT, j = e % KT;
-            rg.v[i] = (e < 12 * KT && j < nsite) ? s[(size_t)A * V3 + t0 + j] : C2<R>{0, 0};
-        }
+    static __device__ __forceinline__ Ctx make(const void* G, const void* Gn, const void* Gp, const void* s,
+                                               const void* U, const void* Up, int noise, int op, int V3) {
+        Ctx c;
+        c.nu = op - 1;
+        c.s = (const C2<R>*)s + (size_t)noise * 12 * V3;
         if (op == 0) {
-            const C2<R>* G = (const C2<R>*)a.G[tl];
-#pragma unroll
-            for (int i = 0; i < kT; ++i) {
-                const int e = tid + i * NT, j = e % KT, q = e / KT;
-                const int bt = q / 12, rem = q % 12;
-                const bool ok = e < 48 * KT && j < nsite;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    rg.g[i][c] = ok ? G[(size_t)((3 * bt + c) * 12 + rem) * V3 + t0 + j] : C2<R>{0, 0};
-            }
-            return;
+            c.Gf = c.Gb = (const C2<R>*)G;
+            c.U = c.Um = nullptr;
+        } else {
+            const int nu = op - 1;
+            c.Gf = (const C2<R>*)((nu < 3) ? G : Gn);
+            c.Gb = (const C2<R>*)((nu < 3) ? G : Gp);
+            c.U = (const C2<R>*)U + (size_t)nu * 9 * V3;
+            c.Um = (nu < 3) ? c.U : (const C2<R>*)Up + (size_t)3 * 9 * V3;
         }
-        const int nu = op - 1;
-        // every thread works on one site j of the tile: its neighbours once
+        return c;
+    }
+    static __device__ __forceinline__ Ctx resolve(const Args& a, int V3, int cb) {
+        const int op = cb % a.n_ops, rest = cb / a.n_ops;
+        const int tl = rest % a.n_tau, noise = rest / a.n_tau;
+        return make(a.G[tl], a.Gn[tl], a.Gp[tl], a.s[tl], a.U[tl], a.Up[tl], noise, op, V3);
+    }
+    static __device__ __forceinline__ Ctx resolve(const BatchJob& b, int V3, int cb) {
+        const int op = cb % b.n_ops, rest = cb / b.n_ops;
+        const int tl = rest % b.n_tau, noise = rest / b.n_tau;
+        const void* const* t = b.tau_ptrs + (size_t)tl * 6;
+        return make(t[0], t[1], t[2], t[3], t[4], t[5], noise, op, V3);
+    }
+    static __device__ __forceinline__ void load(const Ctx& c, const TileGeom& tg, int t0, int nsite, Regs& rg,
+                                                int tid) {
+        const size_t V3 = (size_t)tg.V3;
         const int j = tid % KT;
         const bool site_ok = j < nsite;
         const int n = t0 + j;
+#pragma unroll
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, A = e / KT;
+            rg.v[i] = (e < 12 * KT && site_ok) ? c.s[(size_t)A * V3 + n] : C2<R>{0, 0};
+        }
+        if (c.nu < 0) {
+#pragma unroll
+            for (int i = 0; i < kT; ++i) {
+                const int e = tid + i * NT, q = e / KT;
+                const int bt = q / 12, rem = q % 12;
+                const bool ok = e < 48 * KT && site_ok;
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc)
+                    rg.g[i][cc] = ok ? c.Gf[(size_t)((3 * bt + cc) * 12 + rem) * V3 + n] : C2<R>{0, 0};
+            }
+            return;
+        }
+        const int nu = c.nu;
         int np = n, nm = n;
         if (nu < 3) {
             int x0[3], x1, x2, x3;
@@ -259,22 +313,16 @@ struct InsertionProducer {
             if (!site_ok) np = nm = t0;
         }
         // transport tasks (q = at*3 + d, site j): links at y and y - nu
-        {
-            const C2<R>* U = (const C2<R>*)a.U[tl] + (size_t)nu * 9 * V3;
-            const C2<R>* Um = (nu < 3) ? U : (const C2<R>*)a.Up[tl] + (size_t)3 * 9 * V3;
 #pragma unroll
-            for (int i = 0; i < kV; ++i) {
-                const int e = tid + i * NT, q = e / KT, d = q % 3;
-                const bool ok = e < 12 * KT && site_ok;
+        for (int i = 0; i < kV; ++i) {
+            const int e = tid + i * NT, q = e / KT, d = q % 3;
+            const bool ok = e < 12 * KT && site_ok;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    rg.u[i][c] = ok ? U[(size_t)(c * 3 + d) * V3 + n] : C2<R>{0, 0};
-                    rg.u[i][3 + c] = ok ? Um[(size_t)(d * 3 + c) * V3 + nm] : C2<R>{0, 0};
-                }
+            for (int cc = 0; cc < 3; ++cc) {
+                rg.u[i][cc] = ok ? c.U[(size_t)(cc * 3 + d) * V3 + n] : C2<R>{0, 0};
+                rg.u[i][3 + cc] = ok ? c.Um[(size_t)(d * 3 + cc) * V3 + nm] : C2<R>{0, 0};
             }
         }
-        const C2<R>* Gf = (const C2<R>*)((nu < 3) ? a.G[tl] : a.Gn[tl]);
-        const C2<R>* Gb = (const C2<R>*)((nu < 3) ? a.G[tl] : a.Gp[tl]);
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
             const int e = tid + i * NT, q = e / KT;
@@ -283,29 +331,28 @@ struct InsertionProducer {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const size_t plane = (size_t)((3 * bt + d) * 12 + rem) * V3;
-                rg.g[i][d] = ok ? Gf[plane + np] : C2<R>{0, 0};
-                rg.g[i][3 + d] = ok ? Gb[plane + nm] : C2<R>{0, 0};
+                rg.g[i][d] = ok ? c.Gf[plane + np] : C2<R>{0, 0};
+                rg.g[i][3 + d] = ok ? c.Gb[plane + nm] : C2<R>{0, 0};
             }
         }
     }
     template <class Sink>
-    static __device__ __forceinline__ void store(const Args& a, const TileGeom&, int cb, int, int,
-                                                 const Regs& rg, Smem& sm, Sink& sink, int tid) {
-        int op, tl, noise;
-        decode(a, cb, op, tl, noise);
+    static __device__ __forceinline__ void store(const Ctx& c, const TileGeom&, int, int, const Regs& rg, Smem& sm,
+                                                 Sink& sink, int tid) {
+        const int j = tid % KT;
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, A = e / KT, j = e % KT;
+            const int e = tid + i * NT, A = e / KT;
             if (e < 12 * KT) {
                 const C2<R> s = rg.v[i];
                 sm.v[A][j] = (A >= 6) ? C2<R>{-s.x, s.y} : C2<R>{s.x, -s.y};   // g[at] conj(s)
             }
         }
         __syncthreads();
-        if (op == 0) {
+        if (c.nu < 0) {
 #pragma unroll
             for (int i = 0; i < kT; ++i) {
-                const int e = tid + i * NT, j = e % KT, q = e / KT;
+                const int e = tid + i * NT, q = e / KT;
                 if (e >= 48 * KT) continue;
 #pragma unroll
                 for (int at = 0; at < 4; ++at) {
@@ -320,15 +367,15 @@ struct InsertionProducer {
         // t+[at][d] = 1/2 sum_c v[at][c] U(y)[c][d];  t-[at][d] = 1/2 sum_c v[at][c] conj(U(y-nu)[d][c])
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             if (e >= 12 * KT) continue;
             const int at = q / 3;
             C2<R> tp = {0, 0}, tm = {0, 0};
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const C2<R> vv = sm.v[3 * at + c][j];
-                tp = cfma(tp, vv, rg.u[i][c]);
-                tm = cadd(tm, cmulc(vv, rg.u[i][3 + c]));
+            for (int cc = 0; cc < 3; ++cc) {
+                const C2<R> vv = sm.v[3 * at + cc][j];
+                tp = cfma(tp, vv, rg.u[i][cc]);
+                tm = cadd(tm, cmulc(vv, rg.u[i][3 + cc]));
             }
             sm.tp[q][j] = cscale(tp, (R)0.5);
             sm.tm[q][j] = cscale(tm, (R)0.5);
@@ -336,7 +383,7 @@ struct InsertionProducer {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
-            const int e = tid + i * NT, j = e % KT, q = e / KT;
+            const int e = tid + i * NT, q = e / KT;
             if (e >= 48 * KT) continue;
 #pragma unroll
             for (int at = 0; at < 4; ++at) {

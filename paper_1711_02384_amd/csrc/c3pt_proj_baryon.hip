@@ -8,4 +8,8 @@ hipError_t launch_spectator_baryon(int mode, int mt, int variant, const ProjGrid
     return dispatch<BaryonSpecProducer>(mode, mt, variant, pg, a, st);
 }
 
+int batch_baryon(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    return batch_dispatch<BaryonSpecProducer>(mode, mt, variant, bg, n_wg, st, err);
+}
+
 }  // namespace c3pt

@@ -19,26 +19,33 @@
 //                       (BF16 or FP16), MFMA 16x16x32 with FP32 accumulation,
 //                       three products hi*hi + hi*lo + lo*hi
 // FP32 accumulators never span more than kMaxSitesPerChunkF32 sites: each
-// workgroup writes its chunk's sums in FP64 and reduce_kernel adds the chunks
-// in a fixed order (deterministic, no floating-point atomics).
+// workgroup stores its chunk's sums in the accumulator type and the reduction
+// adds the chunks in FP64 in a fixed order (deterministic, no floating-point
+// atomics).  Phases are taken at the origin; the reduction applies the source
+// offset as a per-momentum factor.
 #pragma once
 
 #include "c3pt_producers.h"
 
 namespace c3pt {
 
+// Partial sums are stored in the accumulator's own type (complex float or
+// complex double): storing them loses nothing.
+template <typename E> struct PartialT;
+template <> struct PartialT<float> { typedef float2 type; };
+template <> struct PartialT<double> { typedef double2 type; };
+
 // Output rows: lane l, accumulator j of row tile rt hold momentum
 // 8*rt + 2*(l/16) + j/2, part j&1 (0 = re, 1 = im), column l%16.
-template <typename AccT>
-__device__ __forceinline__ void write_tile(const ProjGrid& pg, int chunk, int cb, int rt, int col, int lane,
-                                           const AccT& acc) {
-    const int n_mom = pg.n_mom;
+template <typename E, typename AccT>
+__device__ __forceinline__ void write_tile(void* partial, int n_colblocks, int n_mom, int chunk, int cb, int rt,
+                                           int col, int lane, const AccT& acc) {
+    using P2 = typename PartialT<E>::type;
+    P2* part = (P2*)partial;
     const int m0 = 8 * rt + 2 * (lane >> 4);
-    const size_t base = ((size_t)chunk * pg.n_colblocks + cb) * (size_t)n_mom;
-    if (m0 < n_mom)
-        pg.partial[(base + m0) * kBlockCols + col] = make_double2((double)acc[0], (double)acc[1]);
-    if (m0 + 1 < n_mom)
-        pg.partial[(base + m0 + 1) * kBlockCols + col] = make_double2((double)acc[2], (double)acc[3]);
+    const size_t base = ((size_t)chunk * n_colblocks + cb) * (size_t)n_mom;
+    if (m0 < n_mom) part[(base + m0) * kBlockCols + col] = P2{acc[0], acc[1]};
+    if (m0 + 1 < n_mom) part[(base + m0 + 1) * kBlockCols + col] = P2{acc[2], acc[3]};
 }
 
 // Copy of one tile of the phase table (TB bytes, contiguous) through registers.
@@ -142,8 +149,8 @@ struct NativeCons {
             }
         }
     }
-    static __device__ __forceinline__ void write(const ProjGrid& pg, int chunk, int cb, const Acc& acc, int mt,
-                                                 int tid) {
+    static __device__ __forceinline__ void write(void* partial, int n_colblocks, int n_mom, int chunk, int cb,
+                                                 const Acc& acc, int mt, int tid) {
         const int lane = tid & 63, wave = (tid >> 6) % WN, wm = (tid >> 6) / WN;
 #pragma unroll
         for (int rt = 0; rt < RTW; ++rt) {
@@ -151,7 +158,8 @@ struct NativeCons {
             if (rtg >= mt) continue;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
-                write_tile(pg, chunk, cb, rtg, 16 * (wave * CT + ct) + (lane & 15), lane, acc.a[rt][ct]);
+                write_tile<R>(partial, n_colblocks, n_mom, chunk, cb, rtg, 16 * (wave * CT + ct) + (lane & 15), lane,
+                              acc.a[rt][ct]);
         }
     }
 };
@@ -243,8 +251,8 @@ struct SplitCons {
             }
         }
     }
-    static __device__ __forceinline__ void write(const ProjGrid& pg, int chunk, int cb, const Acc& acc, int mt,
-                                                 int tid) {
+    static __device__ __forceinline__ void write(void* partial, int n_colblocks, int n_mom, int chunk, int cb,
+                                                 const Acc& acc, int mt, int tid) {
         const int lane = tid & 63, wave = (tid >> 6) % WN, wm = (tid >> 6) / WN;
 #pragma unroll
         for (int rt = 0; rt < RTW; ++rt) {
@@ -252,10 +260,42 @@ struct SplitCons {
             if (rtg >= mt) continue;
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
-                write_tile(pg, chunk, cb, rtg, 16 * (wave * CT + ct) + (lane & 15), lane, acc.a[rt][ct]);
+                write_tile<float>(partial, n_colblocks, n_mom, chunk, cb, rtg, 16 * (wave * CT + ct) + (lane & 15), lane,
+                              acc.a[rt][ct]);
         }
     }
 };
+
+// ---------------------------------------------------------------------------
+// Tile loop over sites [s_lo, s_hi) of one column block.
+// ---------------------------------------------------------------------------
+template <class Cons, class Prod>
+__device__ __forceinline__ void tile_loop(const typename Prod::Ctx& ctx, const TileGeom& tg, const void* phase,
+                                          int s_lo, int s_hi, typename Cons::Smem& csm, typename Prod::Smem& psm,
+                                          typename Cons::Acc& acc, int mt, int tid) {
+    constexpr int KT = Cons::KT;
+    using Tab = typename Cons::Tab;
+    typename Prod::Regs rg;
+    typename Tab::Regs tr;
+    if (s_lo < s_hi) {
+        Prod::load(ctx, tg, s_lo, min(KT, s_hi - s_lo), rg, tid);
+        Tab::load(Cons::table_tile(phase, s_lo), tr, tid);
+    }
+    for (int t0 = s_lo; t0 < s_hi; t0 += KT) {
+        const int nsite = min(KT, s_hi - t0);
+        Tab::store(Cons::lds_table(csm), tr, tid);
+        auto sink = Cons::sink(csm);
+        Prod::store(ctx, tg, t0, nsite, rg, psm, sink, tid);
+        const int t1 = t0 + KT;
+        if (t1 < s_hi) {
+            Prod::load(ctx, tg, t1, min(KT, s_hi - t1), rg, tid);
+            Tab::load(Cons::table_tile(phase, t1), tr, tid);
+        }
+        __syncthreads();
+        Cons::mma(csm, acc, mt, tid);
+        __syncthreads();
+    }
+}
 
 // ---------------------------------------------------------------------------
 // The fused kernel.
@@ -267,7 +307,6 @@ proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::A
     constexpr int KT = Cons::KT;
     constexpr int NT = Cons::NT;
     using Prod = ProdT<R, KT, NT>;
-    using Tab = typename Cons::Tab;
 
     __shared__ typename Cons::Smem csm;
     __shared__ typename Prod::Smem psm;
@@ -283,6 +322,7 @@ proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::A
     const int chunk = rest % pg.n_chunks;
     const int share = rest / pg.n_chunks;
     const int cb = Prod::colblock(pa, share, within);
+    const typename Prod::Ctx ctx = Prod::resolve(pa, pg.V3, cb);
     const int mt = (pg.n_mom + 7) >> 3;
     TileGeom tg;
     tg.V3 = pg.V3;
@@ -296,27 +336,53 @@ proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::A
     Cons::zero(acc);
     const int s_lo = chunk * pg.chunk_sites;
     const int s_hi = min(pg.V3, s_lo + pg.chunk_sites);
-    typename Prod::Regs rg;
-    typename Tab::Regs tr;
-    if (s_lo < s_hi) {
-        Prod::load(pa, tg, cb, s_lo, min(KT, s_hi - s_lo), rg, tid);
-        Tab::load(Cons::table_tile(pg.phase, s_lo), tr, tid);
-    }
-    for (int t0 = s_lo; t0 < s_hi; t0 += KT) {
-        const int nsite = min(KT, s_hi - t0);
-        Tab::store(Cons::lds_table(csm), tr, tid);
-        auto sink = Cons::sink(csm);
-        Prod::store(pa, tg, cb, t0, nsite, rg, psm, sink, tid);
-        const int t1 = t0 + KT;
-        if (t1 < s_hi) {
-            Prod::load(pa, tg, cb, t1, min(KT, s_hi - t1), rg, tid);
-            Tab::load(Cons::table_tile(pg.phase, t1), tr, tid);
-        }
+    tile_loop<Cons, Prod>(ctx, tg, pg.phase, s_lo, s_hi, csm, psm, acc, mt, tid);
+    Cons::write(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, acc, mt, tid);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form for batches: every workgroup takes (job, column block,
+// chunk) items from a queue until it is empty.  The queue head is a plain
+// integer counter (no floating-point atomics; each item is summed by exactly
+// one workgroup, so the result does not depend on the schedule).
+// ---------------------------------------------------------------------------
+template <class Cons, template <typename, int, int> class ProdT>
+__global__ void __launch_bounds__(Cons::NT, Cons::MINW) batch_kernel(BatchGrid bg) {
+    using R = typename Cons::R;
+    constexpr int KT = Cons::KT;
+    constexpr int NT = Cons::NT;
+    using Prod = ProdT<R, KT, NT>;
+
+    __shared__ typename Cons::Smem csm;
+    __shared__ typename Prod::Smem psm;
+    __shared__ int s_item;
+
+    const int tid = threadIdx.x;
+    const int mt = (bg.n_mom + 7) >> 3;
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(bg.counter, 1);
         __syncthreads();
-        Cons::mma(csm, acc, mt, tid);
+        const int it = s_item;
         __syncthreads();
+        if (it >= bg.n_items) break;
+        const int4 item = bg.items[it];
+        const BatchJob& job = bg.jobs[item.x];
+        const int cb = item.y, chunk = item.z;
+        const typename Prod::Ctx ctx = Prod::resolve(job, job.V3, cb);
+        TileGeom tg;
+        tg.V3 = job.V3;
+        tg.L1 = job.L[0];
+        tg.L2 = job.L[1];
+        tg.L3 = job.L[2];
+        tg.inv1 = 1.0f / (float)tg.L1;
+        tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+        typename Cons::Acc acc;
+        Cons::zero(acc);
+        const int s_lo = chunk * job.chunk_sites;
+        const int s_hi = min(job.V3, s_lo + job.chunk_sites);
+        tile_loop<Cons, Prod>(ctx, tg, job.phase, s_lo, s_hi, csm, psm, acc, mt, tid);
+        Cons::write(job.partial, job.n_colblocks, bg.n_mom, chunk, cb, acc, mt, tid);
     }
-    Cons::write(pg, chunk, cb, acc, mt, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,6 +416,61 @@ hipError_t launch_variant(int mt, int variant, const ProjGrid& pg, const typenam
         if (variant == 1) return launch_cons<Cons<T, 32, 16, 2, 3, 1>, ProdT>(pg, a, st);
     }
     return hipErrorInvalidValue;
+}
+
+template <class Cons, template <typename, int, int> class ProdT>
+hipError_t launch_batch_cons(const BatchGrid& bg, int n_wg, hipStream_t st) {
+    hipLaunchKernelGGL((batch_kernel<Cons, ProdT>), dim3(n_wg), dim3(Cons::NT), 0, st, bg);
+    return hipGetLastError();
+}
+
+template <class Cons, template <typename, int, int> class ProdT>
+int batch_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_kernel<Cons, ProdT>, Cons::NT, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+// Split / FP32 batch variants mirror launch_variant.
+template <template <typename, int, int> class ProdT, template <typename, int, int, int, int, int> class Cons,
+          typename T>
+int batch_variant(int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+#define C3PT_BV(KT_, MT_, WM_)                                                          \
+    {                                                                                   \
+        using C = Cons<T, KT_, MT_, WM_, 3, 1>;                                         \
+        if (bg) *err = launch_batch_cons<C, ProdT>(*bg, n_wg, st);                      \
+        return batch_occupancy<C, ProdT>();                                             \
+    }
+    if (mt <= 4) {
+        if (variant == 0) C3PT_BV(16, 4, 1)
+        if (variant == 1) C3PT_BV(32, 4, 1)
+    } else if (mt <= 8) {
+        if (variant == 0) C3PT_BV(16, 8, 2)
+        if (variant == 1) C3PT_BV(32, 8, 2)
+        if (variant == 2) C3PT_BV(16, 8, 1)
+    } else if (mt <= 12) {
+        if (variant == 0) C3PT_BV(16, 12, 2)
+        if (variant == 1) C3PT_BV(32, 12, 2)
+        if (variant == 2) C3PT_BV(16, 12, 1)
+    } else if (mt <= 16) {
+        if (variant == 0) C3PT_BV(16, 16, 2)
+        if (variant == 1) C3PT_BV(32, 16, 2)
+    }
+#undef C3PT_BV
+    *err = hipErrorInvalidValue;
+    return 0;
+}
+
+template <template <typename, int, int> class ProdT>
+int batch_dispatch(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    *err = hipSuccess;
+    switch (mode) {
+        case kModeF32: return batch_variant<ProdT, NativeCons, float>(mt, variant, bg, n_wg, st, err);
+        case kModeSplitBF16: return batch_variant<ProdT, SplitCons, __bf16>(mt, variant, bg, n_wg, st, err);
+        case kModeSplitF16: return batch_variant<ProdT, SplitCons, _Float16>(mt, variant, bg, n_wg, st, err);
+        default: *err = hipErrorInvalidValue; return 0;
+    }
 }
 
 // MTMAX (row tiles of the layout) of a momentum-tile class.

@@ -8,4 +8,8 @@ hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, c
     return dispatch<InsertionProducer>(mode, mt, variant, pg, a, st);
 }
 
+int batch_insertion(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    return batch_dispatch<InsertionProducer>(mode, mt, variant, bg, n_wg, st, err);
+}
+
 }  // namespace c3pt

@@ -8,4 +8,8 @@ hipError_t launch_spectator_meson(int mode, int mt, int variant, const ProjGrid&
     return dispatch<MesonSpecProducer>(mode, mt, variant, pg, a, st);
 }
 
+int batch_meson(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    return batch_dispatch<MesonSpecProducer>(mode, mt, variant, bg, n_wg, st, err);
+}
+
 }  // namespace c3pt
