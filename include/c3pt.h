@@ -201,6 +201,101 @@ typedef struct c3pt_kernel_stat {
 int c3pt_profile_enable(int on);
 int c3pt_profile_read(c3pt_kernel_stat* stats, int max, int reset);
 
+/*
+ * Batches.  A measurement evaluates the spectator and insertion parts for
+ * many source positions, sink times and lattices (Sec. 2.2-2.3: the paper
+ * spreads them over MPI ranks); a batch runs many such calls as one unit of
+ * work on one GPU.  c3pt_batch_create validates every job, builds the phase
+ * tables and work queues and records the whole schedule into one HIP graph;
+ * c3pt_batch_run replays it.  The projection work of all jobs of one kind is
+ * executed by one persistent kernel whose workgroups take (job, column block,
+ * site chunk) items from a queue, so lattices of different sizes share the
+ * chip until the last item.  A job's sites are summed in FP32 chunks of at
+ * most 2048 sites (fixed by its own extents) and the chunks in FP64 in a
+ * fixed order, so its output does not depend on the other jobs of the batch
+ * or on the schedule: a job gives bit-identical results alone or in any mix
+ * (with the same kernel variant).  Against the single calls, which split
+ * sites differently to fill the chip, results agree to FP32 rounding order.
+ *
+ *   kind         C3PT_JOB_SPECTATOR_MESON / _BARYON / C3PT_JOB_INSERTION
+ *   L, T, r      extents and source position, as in c3pt_geom.  Batch inputs
+ *                are complex64 (the FP32 or split-precision projection
+ *                selected by `proj` of c3pt_batch_create).
+ *   n_noise      noise vectors of the job.
+ *   G, G2, eta   spectator inputs as for c3pt_spectator_meson (G) or
+ *                c3pt_spectator_baryon (G = G1, G2); device pointers.
+ *   G_t, s_t, U_t, taus, n_tau, n_ops   insertion inputs as for c3pt_insertion
+ *                (host pointer tables, read during c3pt_batch_create only; the
+ *                device buffers they name are read on every run).
+ *   out          device complex128 output in the layout of the single call.
+ *
+ * Combines take the outputs of a spectator job and an insertion job of the
+ * same batch (same n_noise) and run after every projection, as c3pt_combine
+ * with the batch's momentum list for both p' and q:
+ *   spec_job, ins_job  indices into the job list;  op_begin, op_end, pairs,
+ *   n_pairs, w as for c3pt_combine (host arrays, copied at creation);
+ *   out  device complex128 [n_pairs][n_tau][op_end-op_begin][spin][64].
+ *
+ * c3pt_batch_create(jobs, n_jobs, combines, n_combines, k, n_mom, proj,
+ *                   partial_budget, &batch)
+ *   k[n_mom][3]     host momentum list shared by all jobs (1..128 momenta).
+ *   proj            C3PT_PROJ_NATIVE (FP32), _SPLIT_F16 or _SPLIT_BF16.
+ *   partial_budget  bytes of device memory for FP32 split-site partial sums;
+ *                   jobs are grouped so that a group's partial sums fit
+ *                   (0 = 16 GiB).  A job whose own partial sums exceed it is
+ *                   rejected.
+ *  Allocates device memory owned by the batch (queues, phase tables, partial
+ *  sums, parameter tables); synchronizes the device work it enqueues.  On
+ *  error nothing is kept and *batch is NULL.
+ * c3pt_batch_run(batch, stream)    enqueue one replay on `stream`.  Every
+ *  device buffer named at creation must stay allocated; its contents may change
+ *  between runs.  Replays of one batch must not overlap (they share its
+ *  queues and partial sums): use one stream, or synchronize.
+ * c3pt_batch_info(batch, &n_items, &n_groups, &partial_bytes)   queue size,
+ *  number of budget groups, partial-sum bytes held.
+ * c3pt_batch_destroy(batch)   synchronizes the device and frees everything.
+ */
+#define C3PT_JOB_SPECTATOR_MESON   0
+#define C3PT_JOB_SPECTATOR_BARYON  1
+#define C3PT_JOB_INSERTION         2
+
+typedef struct c3pt_job {
+    int   kind;
+    int   L[3];
+    int   T;
+    int   r[3];
+    int   n_noise;
+    const void* G;
+    const void* G2;
+    const void* eta;
+    const void* const* G_t;
+    const void* const* s_t;
+    const void* const* U_t;
+    const int*  taus;
+    int   n_tau;
+    int   n_ops;
+    void* out;
+} c3pt_job;
+
+typedef struct c3pt_combine_job {
+    int   spec_job;
+    int   ins_job;
+    int   op_begin;
+    int   op_end;
+    const double* w;
+    const int*    pairs;
+    int   n_pairs;
+    void* out;
+} c3pt_combine_job;
+
+typedef struct c3pt_batch c3pt_batch;
+
+int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* combines, int n_combines,
+                      const int* k, int n_mom, int proj, unsigned long long partial_budget, c3pt_batch** batch);
+int c3pt_batch_run(c3pt_batch* batch, void* stream);
+int c3pt_batch_info(const c3pt_batch* batch, int* n_items, int* n_groups, unsigned long long* partial_bytes);
+int c3pt_batch_destroy(c3pt_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

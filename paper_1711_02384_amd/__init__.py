@@ -38,7 +38,8 @@ PROJ_SPLIT_BF16 = 2
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
             "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
             "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read", "c3pt_variant_count",
-            "c3pt_set_variant", "c3pt_get_variant")
+            "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
+            "c3pt_batch_destroy")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
 MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3}
@@ -58,6 +59,21 @@ class _KernelStat(ctypes.Structure):
 class _Geom(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int * 3), ("T", ctypes.c_int), ("r", ctypes.c_int * 3),
                 ("dtype", ctypes.c_int), ("proj", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("L", ctypes.c_int * 3), ("T", ctypes.c_int), ("r", ctypes.c_int * 3),
+                ("n_noise", ctypes.c_int), ("G", ctypes.c_void_p), ("G2", ctypes.c_void_p),
+                ("eta", ctypes.c_void_p), ("G_t", ctypes.POINTER(ctypes.c_void_p)),
+                ("s_t", ctypes.POINTER(ctypes.c_void_p)), ("U_t", ctypes.POINTER(ctypes.c_void_p)),
+                ("taus", ctypes.POINTER(ctypes.c_int)), ("n_tau", ctypes.c_int), ("n_ops", ctypes.c_int),
+                ("out", ctypes.c_void_p)]
+
+
+class _CombineJob(ctypes.Structure):
+    _fields_ = [("spec_job", ctypes.c_int), ("ins_job", ctypes.c_int), ("op_begin", ctypes.c_int),
+                ("op_end", ctypes.c_int), ("w", ctypes.POINTER(ctypes.c_double)),
+                ("pairs", ctypes.POINTER(ctypes.c_int)), ("n_pairs", ctypes.c_int), ("out", ctypes.c_void_p)]
 
 
 def _load():
@@ -91,6 +107,13 @@ def _load():
     lib.c3pt_variant_count.argtypes = [i, i, i]
     lib.c3pt_set_variant.argtypes = [i, i, i, i]
     lib.c3pt_get_variant.argtypes = [i, i, i]
+    lib.c3pt_batch_create.argtypes = [ctypes.POINTER(_Job), i, ctypes.POINTER(_CombineJob), i, ip, i, i,
+                                      ctypes.c_ulonglong, ctypes.POINTER(vp)]
+    lib.c3pt_batch_run.argtypes = [vp, vp]
+    lib.c3pt_batch_info.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_ulonglong)]
+    lib.c3pt_batch_destroy.argtypes = [vp]
+    for name in ("c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info", "c3pt_batch_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
     return lib
 
 
@@ -335,3 +358,132 @@ def profile_read(reset: bool = False) -> dict:
         out[s.name.decode()] = {"count": int(s.count), "total_ms": s.total_ms, "min_ms": s.min_ms,
                                 "max_ms": s.max_ms, "avg_ms": s.total_ms / max(1, s.count)}
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batches (c3pt_batch_*): many spectator / insertion calls and their combines,
+# recorded once into a HIP graph and replayed.
+# ---------------------------------------------------------------------------
+JOB_KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
+
+
+class Batch:
+    """A recorded batch of jobs (c3pt_batch_create) replayed by ``run()``.
+
+    ``jobs``: list of dicts with ``kind`` ("spectator_meson", "spectator_baryon",
+    "insertion"), ``L``, ``T``, optional ``r``, and the inputs of the matching
+    single call: ``G``, ``eta`` (meson); ``G1``, ``G2``, ``eta`` (baryon);
+    ``G_t``, ``s_t``, ``taus``, optional ``U_t`` and ``n_ops`` (insertion).
+    ``combines``: list of dicts with ``spec``, ``ins`` (job indices) and the
+    optional ``w``, ``pairs``, ``op_begin``, ``op_end`` of c3pt_combine.
+    All inputs are complex64 device tensors; they are held by the batch and
+    may be refilled in place between runs.  Outputs (complex128, single-call
+    layout) are ``outputs[i]`` and ``combine_outputs[j]``."""
+
+    def __init__(self, jobs, k, proj: int = PROJ_NATIVE, combines=(), partial_budget: int = 0):
+        import numpy as np
+        self._keep = []
+        self._handle = ctypes.c_void_p()
+        ka, kp, n_mom = _momenta(k)
+        self.n_mom = n_mom
+        cjobs = (_Job * len(jobs))()
+        self.outputs = []
+        dt = torch.complex64
+        for i, j in enumerate(jobs):
+            kind = JOB_KIND[j["kind"]]
+            L = [int(x) for x in j["L"]]
+            T = int(j["T"])
+            V3 = L[0] * L[1] * L[2]
+            c = cjobs[i]
+            c.kind = kind
+            for d in range(3):
+                c.L[d] = L[d]
+                c.r[d] = int(j.get("r", (0, 0, 0))[d])
+            c.T = T
+            if kind in (0, 1):
+                eta = j["eta"]
+                N = eta.shape[0]
+                c.eta = _field(eta, "eta", (N, 12, V3), dt)
+                if kind == 0:
+                    c.G = _field(j["G"], "G", (12, 12, V3), dt)
+                    self._keep += [j["G"], eta]
+                    shape = (N, n_mom, 192)
+                else:
+                    c.G = _field(j["G1"], "G1", (12, 12, V3), dt)
+                    c.G2 = _field(j["G2"], "G2", (12, 12, V3), dt)
+                    self._keep += [j["G1"], j["G2"], eta]
+                    shape = (N, n_mom, 3072)
+            else:
+                taus = [int(t) for t in j["taus"]]
+                N = j["s_t"][taus[0]].shape[0]
+                n_ops = int(j.get("n_ops", 1))
+                Gtab = _slice_table(j["G_t"], T, "G_t", (12, 12, V3), dt)
+                stab = _slice_table(j["s_t"], T, "s_t", (N, 12, V3), dt)
+                Utab = _slice_table(j.get("U_t"), T, "U_t", (4, 3, 3, V3), dt)
+                tau_arr = (ctypes.c_int * len(taus))(*taus)
+                self._keep += [Gtab, stab, Utab, tau_arr, j["G_t"], j["s_t"], j.get("U_t")]
+                c.G_t = ctypes.cast(Gtab, ctypes.POINTER(ctypes.c_void_p))
+                c.s_t = ctypes.cast(stab, ctypes.POINTER(ctypes.c_void_p))
+                c.U_t = ctypes.cast(Utab, ctypes.POINTER(ctypes.c_void_p)) if j.get("U_t") is not None else None
+                c.taus = ctypes.cast(tau_arr, ctypes.POINTER(ctypes.c_int))
+                c.n_tau = len(taus)
+                c.n_ops = n_ops
+                shape = (N, len(taus), n_ops, n_mom, 192)
+            c.n_noise = N
+            out = j.get("out")
+            out = torch.empty(shape, dtype=torch.complex128, device="cuda") if out is None else out
+            _field(out, "out", shape, torch.complex128)
+            c.out = out.data_ptr()
+            self.outputs.append(out)
+        ccomb = (_CombineJob * max(1, len(combines)))()
+        self.combine_outputs = []
+        for i, cm in enumerate(combines):
+            s_i, q_i = int(cm["spec"]), int(cm["ins"])
+            spec_out, ins_out = self.outputs[s_i], self.outputs[q_i]
+            N, _, sc = spec_out.shape
+            n_tau, n_ops = ins_out.shape[1], ins_out.shape[2]
+            op_begin = int(cm.get("op_begin", 0))
+            op_end = int(cm.get("op_end", n_ops))
+            c = ccomb[i]
+            c.spec_job, c.ins_job, c.op_begin, c.op_end = s_i, q_i, op_begin, op_end
+            if cm.get("w") is not None:
+                wa = np.ascontiguousarray(np.asarray(cm["w"], dtype=np.float64).reshape(N))
+                self._keep.append(wa)
+                c.w = wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            if cm.get("pairs") is not None:
+                pa = np.ascontiguousarray(np.asarray(cm["pairs"], dtype=np.int32).reshape(-1, 2))
+                self._keep.append(pa)
+                c.pairs = pa.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+                n_pairs = pa.shape[0]
+            else:
+                n_pairs = n_mom * n_mom
+            c.n_pairs = n_pairs
+            out = torch.empty((n_pairs, n_tau, op_end - op_begin, sc // 3, 64), dtype=torch.complex128,
+                              device="cuda")
+            c.out = out.data_ptr()
+            self.combine_outputs.append(out)
+        # inputs written by torch on its current stream must be complete before
+        # creation builds tables and records the graph on a stream of its own
+        torch.cuda.current_stream().synchronize()
+        _check(lib.c3pt_batch_create(cjobs, len(jobs), ccomb if combines else None, len(combines), kp, n_mom,
+                                     int(proj), int(partial_budget), ctypes.byref(self._handle)))
+
+    def run(self, stream: Optional[int] = None) -> None:
+        st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib.c3pt_batch_run(self._handle, ctypes.c_void_p(st)))
+
+    def info(self) -> dict:
+        n_items, n_groups, pb = ctypes.c_int(), ctypes.c_int(), ctypes.c_ulonglong()
+        _check(lib.c3pt_batch_info(self._handle, ctypes.byref(n_items), ctypes.byref(n_groups), ctypes.byref(pb)))
+        return {"items": n_items.value, "groups": n_groups.value, "partial_bytes": pb.value}
+
+    def close(self) -> None:
+        if self._handle:
+            _check(lib.c3pt_batch_destroy(self._handle))
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -383,6 +383,16 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
 
 }  // namespace
 
+// Shared with the batch API (c3pt_batch.hip).
+namespace c3pt {
+int api_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+int api_ok() { return ok(); }
+int api_variant(int kind, int mode, int mt) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_variant[kind][mode][mt_class(mt)];
+}
+}  // namespace c3pt
+
 extern "C" {
 
 int c3pt_version(void) { return 100; }

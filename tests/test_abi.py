@@ -118,3 +118,88 @@ def test_status_strings():
     for s in (0, -1, -2, -3, -4):
         assert c.lib.c3pt_strerror(s)
     assert c.version() >= 100
+
+
+def _job(c, **kw):
+    j = c._Job()
+    j.kind = kw.get("kind", 0)
+    L = kw.get("L", (4, 4, 4))
+    for d in range(3):
+        j.L[d] = L[d]
+        j.r[d] = 0
+    j.T = kw.get("T", 8)
+    j.n_noise = kw.get("n_noise", 1)
+    j.G = kw.get("G", DUMMY)
+    j.G2 = kw.get("G2", DUMMY)
+    j.eta = kw.get("eta", DUMMY)
+    j.n_tau = kw.get("n_tau", 0)
+    j.n_ops = kw.get("n_ops", 1)
+    j.out = kw.get("out", DUMMY)
+    return j
+
+
+@pytest.mark.parametrize("bad", ["empty", "kind", "L0", "T0", "noise0", "out", "G", "baryonG2", "ins_no_tables",
+                                 "ins_ops", "nmom0", "nmom129", "proj", "kbig", "comb_index", "comb_kinds",
+                                 "comb_ops", "budget"])
+def test_batch_rejects_bad_arguments(bad):
+    import paper_1711_02384_amd as c
+    kw, n_jobs, n_mom, proj, budget = {}, 1, 1, 0, 0
+    combs = None
+    n_comb = 0
+    ka = np.zeros((130, 3), dtype=np.int32)
+    if bad == "empty":
+        n_jobs = 0
+    elif bad == "kind":
+        kw["kind"] = 5
+    elif bad == "L0":
+        kw["L"] = (4, 0, 4)
+    elif bad == "T0":
+        kw["T"] = 0
+    elif bad == "noise0":
+        kw["n_noise"] = 0
+    elif bad == "out":
+        kw["out"] = None
+    elif bad == "G":
+        kw["G"] = None
+    elif bad == "baryonG2":
+        kw["kind"], kw["G2"] = 1, None
+    elif bad == "ins_no_tables":
+        kw["kind"], kw["n_tau"] = 2, 1
+    elif bad == "ins_ops":
+        kw["kind"], kw["n_tau"], kw["n_ops"] = 2, 1, 3
+    elif bad == "nmom0":
+        n_mom = 0
+    elif bad == "nmom129":
+        n_mom = 129
+    elif bad == "proj":
+        proj = 7
+    elif bad == "kbig":
+        ka[0, 1] = 40000
+    elif bad == "budget":
+        budget = 1024          # the job's partial sums need more
+    jobs = (c._Job * 2)(_job(c, **kw), _job(c, kind=0))
+    if bad.startswith("comb"):
+        n_jobs = 2
+        combs = (c._CombineJob * 1)()
+        cj = combs[0]
+        cj.spec_job, cj.ins_job, cj.op_begin, cj.op_end, cj.out = 0, 1, 0, 1, DUMMY
+        if bad == "comb_index":
+            cj.ins_job = 2
+        elif bad == "comb_kinds":
+            pass                # job 1 is a spectator, not an insertion
+        elif bad == "comb_ops":
+            cj.op_end = 0
+        n_comb = 1
+    handle = ctypes.c_void_p(0x1)
+    kp = ka.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    rc = c.lib.c3pt_batch_create(jobs, n_jobs, combs, n_comb, kp, n_mom, proj, budget, ctypes.byref(handle))
+    assert rc == c.C3PT_EINVAL, (bad, rc)
+    assert not handle.value
+    assert c.lib.c3pt_last_error().decode()
+
+
+def test_batch_null_handles():
+    import paper_1711_02384_amd as c
+    assert c.lib.c3pt_batch_run(None, None) == c.C3PT_EINVAL
+    assert c.lib.c3pt_batch_info(None, None, None, None) == c.C3PT_EINVAL
+    assert c.lib.c3pt_batch_destroy(None) == c.C3PT_OK
