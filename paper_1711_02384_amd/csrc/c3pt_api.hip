@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <tuple>
 #include <mutex>
@@ -390,6 +391,13 @@ int api_ok() { return ok(); }
 int api_variant(int kind, int mode, int mt) {
     std::lock_guard<std::mutex> lk(g_mu);
     return g_variant[kind][mode][mt_class(mt)];
+}
+bool api_profiling() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+hipError_t api_timed(const char* name, hipStream_t st, const std::function<hipError_t()>& fn) {
+    return timed(name, st, fn);
 }
 }  // namespace c3pt
 

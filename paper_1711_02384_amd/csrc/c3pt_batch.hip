@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <array>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <string>
@@ -28,11 +29,20 @@ namespace c3pt {
 int api_fail(int code, const char* msg);
 int api_ok();
 int api_variant(int kind, int mode, int mt);
+bool api_profiling();
+hipError_t api_timed(const char* name, hipStream_t st, const std::function<hipError_t()>& fn);
 }  // namespace c3pt
 
 using namespace c3pt;
 
 struct c3pt_batch {
+    // The schedule: every launch of one replay, in order.  Recorded into the
+    // graph at creation; run one by one (each timed) while profiling is on.
+    struct Op {
+        const char* name;
+        std::function<hipError_t(hipStream_t)> launch;
+    };
+    std::vector<Op> ops;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<void*> allocations;
@@ -362,43 +372,52 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
         cargs.push_back(a);
     }
 
-    // ---- record the schedule into a graph ----
+    // ---- the schedule ----
     BatchReduceArgs rbase;
     memset(&rbase, 0, sizeof(rbase));
     rbase.n_mom = n_mom;
     for (int m = 0; m < n_mom; ++m)
         for (int j = 0; j < 3; ++j) rbase.k[j][m] = (short)k[3 * m + j];
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return bail(api_fail(C3PT_EDEVICE, "graph capture failed to start"));
-    hipError_t cap = hipSuccess;
     int job_base = 0;
-    for (size_t gi = 0; gi < groups.size() && cap == hipSuccess; ++gi) {
-        cap = launch_reset(counters + 3 * gi, 3, st);
+    static const char* kProjName[3] = {"batch_proj_spectator_meson", "batch_proj_spectator_baryon",
+                                       "batch_proj_insertion"};
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        int* cnt = counters + 3 * gi;
+        b->ops.push_back({"batch_reset", [cnt](hipStream_t s) { return launch_reset(cnt, 3, s); }});
         for (const Queue& q : queues[gi]) {
-            if (cap != hipSuccess) break;
             BatchGrid bg;
             bg.jobs = JD;
             bg.items = q.items;
             bg.n_items = q.n;
             bg.n_mom = n_mom;
             bg.counter = q.counter;
-            hipError_t e = hipSuccess;
-            if (q.kind == 0) batch_meson(mode, mt, q.variant, &bg, q.n_wg, st, &e);
-            else if (q.kind == 1) batch_baryon(mode, mt, q.variant, &bg, q.n_wg, st, &e);
-            else batch_insertion(mode, mt, q.variant, &bg, q.n_wg, st, &e);
-            cap = e;
+            const int kind = q.kind, variant = q.variant, n_wg = q.n_wg;
+            b->ops.push_back({kProjName[kind], [=](hipStream_t s) {
+                                  hipError_t e = hipSuccess;
+                                  if (kind == 0) batch_meson(mode, mt, variant, &bg, n_wg, s, &e);
+                                  else if (kind == 1) batch_baryon(mode, mt, variant, &bg, n_wg, s, &e);
+                                  else batch_insertion(mode, mt, variant, &bg, n_wg, s, &e);
+                                  return e;
+                              }});
         }
-        if (cap != hipSuccess) break;
         BatchReduceArgs ra = rbase;
         ra.jobs = JD + job_base;
         ra.out_offset = out_offsets[gi].first;
         ra.n_jobs = (int)groups[gi].size();
-        cap = launch_batch_reduce(ra, out_offsets[gi].second, st);
+        const long long total = out_offsets[gi].second;
+        b->ops.push_back({"batch_reduce", [ra, total](hipStream_t s) { return launch_batch_reduce(ra, total, s); }});
         job_base += (int)groups[gi].size();
     }
-    for (const CombineArgs& a : cargs) {
+    for (const CombineArgs& a : cargs)
+        b->ops.push_back({"combine", [a](hipStream_t s) { return launch_combine(a, s); }});
+
+    // ---- record it into a graph ----
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(api_fail(C3PT_EDEVICE, "graph capture failed to start"));
+    hipError_t cap = hipSuccess;
+    for (const auto& op : b->ops) {
+        cap = op.launch(st);
         if (cap != hipSuccess) break;
-        cap = launch_combine(a, st);
     }
     hipGraph_t graph = nullptr;
     hipError_t endc = hipStreamEndCapture(st, &graph);
@@ -417,9 +436,15 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
 
 int c3pt_batch_run(c3pt_batch* b, void* stream) {
     if (!b || !b->exec) return api_fail(C3PT_EINVAL, "batch is NULL");
-    if (hipGraphLaunch(b->exec, (hipStream_t)stream) != hipSuccess)
-        return api_fail(C3PT_EDEVICE, "graph launch failed");
-    return C3PT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (api_profiling()) {
+        for (const auto& op : b->ops)
+            if (api_timed(op.name, st, [&] { return op.launch(st); }) != hipSuccess)
+                return api_fail(C3PT_EDEVICE, "batch launch failed");
+        return api_ok();
+    }
+    if (hipGraphLaunch(b->exec, st) != hipSuccess) return api_fail(C3PT_EDEVICE, "graph launch failed");
+    return api_ok();
 }
 
 int c3pt_batch_info(const c3pt_batch* b, int* n_items, int* n_groups, unsigned long long* partial_bytes) {

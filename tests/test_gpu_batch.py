@@ -220,3 +220,28 @@ def test_batch_on_side_stream():
         assert rel_fro(b.outputs[2 * li].cpu().numpy(), S_o) < TOL
         assert rel_fro(b.outputs[2 * li + 1].cpu().numpy(), I_o) < TOL
     b.close()
+
+
+def test_batch_profiled_run_times_each_kernel_and_matches_graph():
+    import paper_1711_02384_amd as c3pt
+    k = c3pt.momentum_list(3)
+    lats = _lattices()
+    b = _batch(c3pt, lats, k, 2)
+    b.run()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in b.outputs + b.combine_outputs]
+    for o in b.outputs + b.combine_outputs:
+        o.zero_()
+    c3pt.profile_read(reset=True)
+    c3pt.profile_enable(True)
+    b.run()                      # eager: the recorded launches one by one, each timed
+    torch.cuda.synchronize()
+    c3pt.profile_enable(False)
+    prof = c3pt.profile_read(reset=True)
+    _say(f"profiled batch: {sorted(prof)}")
+    for name in ("batch_reset", "batch_proj_spectator_meson", "batch_proj_spectator_baryon",
+                 "batch_proj_insertion", "batch_reduce", "combine"):
+        assert prof[name]["count"] >= 1 and prof[name]["total_ms"] > 0
+    for o, r in zip(b.outputs + b.combine_outputs, ref):
+        assert torch.equal(o, r)
+    b.close()
