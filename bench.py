@@ -45,9 +45,9 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48"], default="meson32")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 20; batch64: 3)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 3; batch64: 1)")
+    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "batch64"], default="meson32")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -56,6 +56,11 @@ def parse():
                     help="projection arithmetic: FP32 MFMA, or hi+lo BF16 / FP16 MFMA with FP32 accumulation")
     ap.add_argument("--tune", action="store_true", help="autotune kernel variants on this workload first")
     ap.add_argument("--tune-out", default=None, help="write the tuning table (JSON) here")
+    ap.add_argument("--sources", type=int, default=64, help="batch64: number of source positions")
+    ap.add_argument("--partial-budget-gib", type=float, default=24.0,
+                    help="batch64: device memory for FP32 split-site partial sums")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch64: skip timing the same jobs as plain per-call FP32 launches")
     return ap.parse_args()
 
 
@@ -88,6 +93,8 @@ class Meson32:
     cfg = 2
     dtype = "c64"
     default_proj = "f32"
+    default_steps = 20
+    default_warmup = 3
 
     def __init__(self, args):
         self.baryon = not args.no_baryon
@@ -151,6 +158,11 @@ class Meson32:
     def dominant(self, n_mom):
         cols = self.N * len(self.taus) * self.n_ops * 192
         return "proj_insertion", 8.0 * n_mom * int(np.prod(self.L)) * cols
+
+    def config(self, n_mom):
+        return {"workload": self.name, "L": list(self.L), "T": self.T, "t_f": self.t_f, "n_noise": self.N,
+                "n_tau": len(self.taus), "n_mom": n_mom, "n_ops": self.n_ops,
+                "units_per_step": self.units(n_mom)}
 
     def cpu_sample(self, k, n_slices):
         import c3pt_synth as syn
@@ -320,8 +332,207 @@ class Nucleon48(Meson32):
         return units, dt, (f"FP64 numpy oracle: one insertion timeslice (u), full 48^3, N=8, {len(k)} momenta; "
                            f"nucleon spectators and combine not in the sample")
 
+class Batch64:
+    """Many source positions over uneven lattices in one recorded graph.
 
-WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48}
+    Source j sits on lattice j mod 3 of (24^3 x 48, 32^3 x 64, 48^3 x 96), at a
+    seeded random (r, t_src) with t_f - t_src drawn uniformly from 8..16; even
+    j are mesons (one propagator: spectator at t_f, insertion at every tau of
+    t_src..t_f), odd j nucleons (two spectators (u,u), (u,d) and two insertions
+    with the u and d propagators).  N = 8 noise vectors per source, 93 momenta,
+    local insertion.  Combines: mesons on the 185 pairs with p' = q or p' = 0,
+    nucleons on the 7 pairs with p' = 0, |q|^2 <= 1.
+
+    The inputs (about 100 GB for 64 sources) are drawn on the GPU from seeded
+    torch generators, with the distributions of the seeded host generators
+    (unit complex Gaussians, Z2 x Z2 noise); drawing them on the host would
+    take minutes.  Every source has buffers of its own."""
+    lattices = (((24, 24, 24), 48), ((32, 32, 32), 64), ((48, 48, 48), 96))
+    N = 8
+    n2 = 8
+    n_ops = 1
+    cfg = 4
+    dtype = "c64"
+    default_proj = "f16x2"
+    default_steps = 3
+    default_warmup = 1
+
+    def __init__(self, args):
+        self.n_src = int(args.sources)
+        self.budget = int(args.partial_budget_gib * (1 << 30))
+        self.plain = not args.no_plain
+        self.name = (f"batched 3pt: {self.n_src} sources x N=8 over 24^3x48, 32^3x64, 48^3x96 (source j on lattice "
+                     f"j mod 3), t_f-t_src ~ U{{8..16}}, meson (even j) : nucleon (odd j) = 1:1, |k|^2<=8 "
+                     f"(93 momenta), local insertion, one graph replay per step")
+        self.L = [list(L) for L, _ in self.lattices]
+        self.T = [T for _, T in self.lattices]
+        self.t_f = "t_src + U{8..16}"
+
+    def sources(self):
+        import c3pt_synth as syn
+        out = []
+        for j in range(self.n_src):
+            L, T = self.lattices[j % 3]
+            g = syn.rng(self.cfg, 99, j)
+            r = [int(g.integers(0, L[d])) for d in range(3)]
+            t_src = int(g.integers(0, T))
+            dt = int(g.integers(8, 17))
+            out.append({"j": j, "L": L, "T": T, "r": r, "t_src": t_src, "dt": dt,
+                        "taus": [(t_src + i) % T for i in range(dt + 1)], "t_f": (t_src + dt) % T,
+                        "nucleon": j % 2 == 1})
+        return out
+
+    def setup(self, c3pt, syn, dev, geom, k):
+        import torch
+        gen = torch.Generator(device=dev)
+        N = self.N
+        inv = 1.0 / np.sqrt(2.0)
+
+        def draw(shape, seed):
+            gen.manual_seed(seed)
+            return torch.randn(shape, dtype=torch.complex64, device=dev, generator=gen)
+
+        def noise(V3, seed):
+            gen.manual_seed(seed)
+            b = torch.randint(0, 2, (N, 12, V3, 2), device=dev, generator=gen, dtype=torch.int8)
+            return torch.view_as_complex(((1 - 2 * b).float() * inv).contiguous())
+
+        n_mom = len(k)
+        mk = lambda *sh: torch.empty(sh, dtype=torch.complex128, device=dev)
+        pairs_m = pairs_diag_or_zero(n_mom)
+        pairs_n = np.array([(0, q) for q in range(7)], dtype=np.int32)
+        self.src = self.sources()
+        jobs, combs, self.plain_calls = [], [], []
+        self.flops = {"spectator_meson": 0.0, "spectator_baryon": 0.0, "insertion": 0.0}
+        self.units_total = 0
+        for s in self.src:
+            L, T, V3 = s["L"], s["T"], int(np.prod(s["L"]))
+            seed = lambda field, t: ((self.cfg * 1024 + s["j"]) * 16 + field) * 4096 + t
+            eta = noise(V3, seed(syn.FIELD_ETA, s["t_f"]))
+            sl = {t: draw((N, 12, V3), seed(syn.FIELD_S, t)) for t in s["taus"]}
+            flav = {"u": {t: draw((12, 12, V3), seed(syn.FIELD_G3, t)) for t in s["taus"]}}
+            if s["nucleon"]:
+                flav["d"] = {t: draw((12, 12, V3), seed(syn.FIELD_G1, t)) for t in s["taus"]}
+            base = dict(L=L, T=T, r=s["r"])
+            n_tau, tf = len(s["taus"]), s["t_f"]
+            ins_flops = 8.0 * n_mom * V3 * N * n_tau * 192
+            if not s["nucleon"]:
+                G = flav["u"]
+                jobs.append(dict(kind="spectator_meson", G=G[tf], eta=eta, **base))
+                jobs.append(dict(kind="insertion", G_t=G, s_t=sl, taus=s["taus"], n_ops=1, **base))
+                combs.append({"spec": len(jobs) - 2, "ins": len(jobs) - 1, "pairs": pairs_m})
+                self.flops["spectator_meson"] += 8.0 * n_mom * V3 * N * 192
+                self.flops["insertion"] += ins_flops
+                self.units_total += N * V3 * n_mom * (1 + n_tau)
+            else:
+                Gu, Gd = flav["u"], flav["d"]
+                jobs.append(dict(kind="spectator_baryon", G1=Gu[tf], G2=Gu[tf], eta=eta, **base))
+                jobs.append(dict(kind="spectator_baryon", G1=Gu[tf], G2=Gd[tf], eta=eta, **base))
+                jobs.append(dict(kind="insertion", G_t=Gu, s_t=sl, taus=s["taus"], n_ops=1, **base))
+                jobs.append(dict(kind="insertion", G_t=Gd, s_t=sl, taus=s["taus"], n_ops=1, **base))
+                n = len(jobs)
+                # proton isovector: (u,u) spectator with the d insertion, (u,d) with the u insertion
+                combs.append({"spec": n - 4, "ins": n - 1, "pairs": pairs_n})
+                combs.append({"spec": n - 3, "ins": n - 2, "pairs": pairs_n})
+                self.flops["spectator_baryon"] += 2 * 8.0 * n_mom * V3 * N * 3072
+                self.flops["insertion"] += 2 * ins_flops
+                self.units_total += 2 * N * V3 * n_mom * (1 + n_tau)
+        torch.cuda.synchronize()
+        log(f"[bench] {len(jobs)} jobs, {len(combs)} combines; "
+            f"{torch.cuda.memory_allocated() / 2**30:.1f} GiB of inputs resident")
+        self.jobs, self.combs = jobs, combs
+        self.c3pt, self.k, self.proj = c3pt, k, geom.proj
+        self.record()
+
+    def record(self):
+        """(Re)record the batch graph; kernel variants are fixed at recording."""
+        old = getattr(self, "batch", None)
+        outs = (old.outputs, old.combine_outputs) if old is not None else None
+        if old is not None:
+            old.close()
+        jobs = self.jobs
+        if outs is not None:
+            jobs = [dict(j, out=o) for j, o in zip(self.jobs, outs[0])]
+        self.batch = self.c3pt.Batch(jobs, self.k, proj=self.proj, combines=self.combs,
+                                     partial_budget=self.budget)
+        log(f"[bench] batch recorded: {self.batch.info()}")
+
+    def _single(self, j, g, out):
+        c, k = self.c3pt, self.k
+        if j["kind"] == "spectator_meson":
+            return c.spectator_meson(j["G"], j["eta"], k, g, out=out)
+        if j["kind"] == "spectator_baryon":
+            return c.spectator_baryon(j["G1"], j["G2"], j["eta"], k, g, out=out)
+        return c.insertion(j["G_t"], j["s_t"], j["taus"], k, g, n_ops=1, out=out)
+
+    def calls(self):
+        """Single calls of one 48^3 nucleon source (for the tuner)."""
+        c = self.c3pt
+        nuc = [i for i, s in enumerate(self.src) if s["nucleon"]]
+        big = [i for i in nuc if self.src[i]["L"][0] == 48]
+        idx = (big or nuc or [0])[0]
+        jn = sum(4 if s["nucleon"] else 2 for s in self.src[:idx])
+        out = []
+        for kn, off in (("spectator_baryon", 0), ("insertion", 2)):
+            j = self.jobs[jn + off]
+            g = c.Geom(j["L"], j["T"], r=j["r"], proj=self.proj_flag)
+            o = self.batch.outputs[jn + off]
+            out.append((kn, (lambda j=j, g=g, o=o: self._single(j, g, o))))
+        return out
+
+    def step(self):
+        self.batch.run()
+
+    def plain_step(self):
+        """The same jobs as plain per-call launches with FP32 projection (no graph, no batching)."""
+        c = self.c3pt
+        for j, o in zip(self.jobs, self.batch.outputs):
+            self._single(j, c.Geom(j["L"], j["T"], r=j["r"], proj=c.PROJ_NATIVE), o)
+        for cm, o in zip(self.combs, self.batch.combine_outputs):
+            c.combine(self.batch.outputs[cm["spec"]], self.batch.outputs[cm["ins"]], pairs=cm["pairs"], out=o)
+
+    def units(self, n_mom):
+        return self.units_total
+
+    def components(self, n_mom):
+        tot = 0
+        for s in self.src:
+            V3, nt = int(np.prod(s["L"])), len(s["taus"])
+            if s["nucleon"]:
+                tot += 2 * self.N * V3 * n_mom * (3072 + nt * 192)
+            else:
+                tot += self.N * V3 * n_mom * (192 + nt * 192)
+        return tot
+
+    def kernel_flops(self):
+        return {"batch_proj_" + kn: f for kn, f in self.flops.items()}
+
+    def config(self, n_mom):
+        return {"workload": self.name, "lattices": ["24^3x48", "32^3x64", "48^3x96"], "n_sources": self.n_src,
+                "n_noise": self.N, "n_mom": n_mom, "n_ops": 1, "jobs": len(self.jobs),
+                "combines": len(self.combs), "units_per_step": self.units_total, "batch": self.batch.info()}
+
+    def cpu_sample(self, k, n_slices):
+        import c3pt_synth as syn
+        import oracle
+        L, T = self.lattices[0]
+        src = self.sources()[0]
+        cfg = self.cfg
+        G = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, src["t_f"]))
+        eta = syn.round_to_c64(syn.z2z2_noise(L, self.N, cfg, src["t_f"]))
+        taus = src["taus"][:n_slices]
+        Gt = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in taus}
+        st = {t: syn.round_to_c64(syn.solution_slice(L, self.N, cfg, t)) for t in taus}
+        t0 = time.perf_counter()
+        oracle.spectator_meson(G, eta, L, k, r=src["r"])
+        oracle.insertion(Gt, st, taus, L, T, k, r=src["r"])
+        dt = time.perf_counter() - t0
+        units = self.N * int(np.prod(L)) * len(k) * (1 + len(taus))
+        return units, dt, (f"FP64 numpy oracle: source 0 (24^3 meson), spectator + {len(taus)} insertion "
+                           f"timeslices, N=8, {len(k)} momenta; nucleon sources and combines not in the sample")
+
+
+WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48, "batch64": Batch64}
 
 
 def cpu_baseline(W, k, n_slices):
@@ -347,6 +558,10 @@ def main():
     import paper_1711_02384_amd as c3pt
 
     W = WORKLOADS[args.workload](args)
+    if args.steps is None:
+        args.steps = W.default_steps
+    if args.warmup is None:
+        args.warmup = W.default_warmup
     proj = args.proj or W.default_proj
     if W.dtype == "c128":
         proj = "f64"
@@ -357,7 +572,9 @@ def main():
     proj_flag = {"f64": c3pt.PROJ_NATIVE, "f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16,
                  "f16x2": c3pt.PROJ_SPLIT_F16}[proj]
     mode = c3pt.MODE[proj]
-    geom = c3pt.Geom(W.L, W.T, proj=proj_flag)
+    batched = isinstance(W, Batch64)
+    geom = c3pt.Geom((1, 1, 1) if batched else W.L, 1 if batched else W.T, proj=proj_flag)
+    W.proj_flag = proj_flag
     log(f"[bench] generating inputs for {W.name}")
     t0 = time.perf_counter()
     W.setup(c3pt, syn, dev, geom, k)
@@ -372,13 +589,14 @@ def main():
         tuning = autotune.tune(cases, reps=3, log=log)
         if args.tune_out:
             autotune.save(tuning, args.tune_out)
+        if batched:
+            W.record()
     for _ in range(args.warmup):
         W.step()
     torch.cuda.synchronize()
-    c3pt.profile_read(reset=True)
-    c3pt.profile_enable(True)
     stream = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for a, b in evs:
@@ -387,17 +605,36 @@ def main():
         b.record(stream)
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    c3pt.profile_enable(False)
-    prof = c3pt.profile_read(reset=True)
     lat = sorted(a.elapsed_time(b) for a, b in evs)
     ms_per_step = (t_end - t_start) * 1e3 / args.steps
     units = W.units(n_mom)
     value = units / (ms_per_step * 1e-3)
 
-    kname, flops = W.dominant(n_mom)
-    kms = prof.get(kname, {}).get("avg_ms", float("nan"))
-    achieved = flops / (kms * 1e-3) / 1e12
+    # per-kernel durations: HIP events around every library launch on its
+    # stream, over separate profiled steps (a batch then runs its recorded
+    # launches one by one instead of the graph)
+    prof_steps = max(1, min(args.steps, 3))
+    log(f"[bench] profiling {prof_steps} steps")
+    c3pt.profile_read(reset=True)
+    c3pt.profile_enable(True)
+    for _ in range(prof_steps):
+        W.step()
+    torch.cuda.synchronize()
+    c3pt.profile_enable(False)
+    prof = c3pt.profile_read(reset=True)
+
     peak = PEAK[proj]
+    if batched:
+        # dominant = the projection kernel kind with the most time per step
+        kf = {kn: f for kn, f in W.kernel_flops().items() if kn in prof and f > 0}
+        kname = max(kf, key=lambda kn: prof[kn]["total_ms"])
+        launches = prof[kname]["count"] / prof_steps
+        flops = kf[kname] / launches
+        kms = prof[kname]["total_ms"] / prof[kname]["count"]
+    else:
+        kname, flops = W.dominant(n_mom)
+        kms = prof.get(kname, {}).get("avg_ms", float("nan"))
+    achieved = flops / (kms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
                 "kernel": f"{kname} (fused contraction + {proj} MFMA projection)",
@@ -405,6 +642,21 @@ def main():
     if proj in ("bf16x2", "f16x2"):
         roofline["note"] = ("flops counted once per complex MAC (8 real flops); the hi+lo split issues "
                             "3 MFMA products per term, so MFMA issue is 3x the counted flops")
+
+    plain = None
+    if batched and W.plain:
+        log("[bench] timing the same jobs as plain per-call FP32 launches")
+        W.plain_step()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        W.plain_step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b)
+        plain = {"value": units / (pms * 1e-3), "ms_per_step": pms, "proj": "f32",
+                 "form": "one c3pt_* call per job and per combine, FP32 MFMA projection, no graph",
+                 "batched_speedup": pms / ms_per_step}
     res = {
         "metric": "contracted site*momenta/s (spectator+insertion)",
         "value": value,
@@ -419,8 +671,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "bf16x2": "f32 contraction, bf16 hi+lo projection",
                   "f16x2": "f32 contraction, f16 hi+lo projection"}[proj],
         "data": "synthetic",
-        "config": {"workload": W.name, "L": list(W.L), "T": W.T, "t_f": W.t_f, "n_noise": W.N,
-                   "n_tau": len(W.taus), "n_mom": n_mom, "n_ops": W.n_ops, "units_per_step": units},
+        "config": W.config(n_mom),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "component_rate": {"projected_complex_values_per_s": W.components(n_mom) / (ms_per_step * 1e-3)},
         "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
@@ -429,6 +680,8 @@ def main():
         "variants": {kn: c3pt.get_variant(c3pt.KIND[kn], mode, cls)
                      for kn in ("spectator_meson", "spectator_baryon", "insertion")},
     }
+    if plain is not None:
+        res["plain_form"] = plain
     if tuning is not None:
         res["tuning"] = tuning["entries"]
     if not args.no_cpu_baseline:
