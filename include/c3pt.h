@@ -296,6 +296,98 @@ int c3pt_batch_run(c3pt_batch* batch, void* stream);
 int c3pt_batch_info(const c3pt_batch* batch, int* n_items, int* n_groups, unsigned long long* partial_bytes);
 int c3pt_batch_destroy(c3pt_batch* batch);
 
+/*
+ * Serving: continuous batching of contraction requests.  A request is one
+ * measurement of Eq. (8) on one lattice and source position: the spectator
+ * part at t_f (meson, or the two nucleon spectators (u,u) and (u,d)), the
+ * insertion part at every tau = t_src, t_src+1, ..., t_f (mod T), and the
+ * combines (meson: S x I; nucleon, proton isovector: S(u,u) x I_d and
+ * S(u,d) x I_u).  The propagators, noise and solutions stay resident in the
+ * caller's device memory; requests only name them.
+ *
+ * c3pt_server_create(proj, arena, arena_bytes, step_bytes, max_active, stream, &server)
+ *   proj        C3PT_PROJ_NATIVE (FP32), _SPLIT_F16 or _SPLIT_BF16 projection.
+ *   arena       caller-owned device memory (256-byte aligned) from which the
+ *               outputs of admitted requests are sub-allocated (first fit);
+ *               it must outlive the server.
+ *   step_bytes  device workspace for the FP32 partial sums of one step (>= 1 MiB);
+ *               a request is cut into packets of at most step_bytes/4 (one
+ *               noise vector of one timeslice must fit, else it is rejected).
+ *   max_active  requests in flight at once.
+ *   stream      hipStream_t every launch of the server goes to.
+ * c3pt_server_submit(server, &req, &id)   validate and queue a request (host
+ *   only; enqueues nothing).  Rejected with C3PT_EINVAL when its outputs can
+ *   never fit the arena or one noise vector of one timeslice exceeds a packet.
+ * c3pt_server_step(server, &n_active, &n_queued)   one iteration: admit
+ *   queued requests in arrival order while a slot and arena space are free;
+ *   take packets round-robin from every active request until the step
+ *   workspace is full; enqueue their contraction + projection (persistent
+ *   queue kernels shared by all requests of the step), the FP64 reduction,
+ *   and the combines of every request whose last packet ran, then an event
+ *   marking it complete.  Returns after enqueueing; at most two steps are in
+ *   flight (the call waits for the step before last).
+ * c3pt_server_poll(server, id)   1 when the request's results are complete on
+ *   the device, 0 if not yet, or a negative status.
+ * c3pt_server_result(server, id, &res)   device pointers of the request's
+ *   outputs inside the arena (valid once admitted; complete once polled 1):
+ *     spec[p]  [n_noise][n_mom][192] meson, [n_noise][n_mom][3072] nucleon
+ *     ins[p]   [n_noise][n_tau][n_ops][n_mom][192]
+ *     comb[p]  [n_pairs][n_tau][n_ops][64 or 1024][64]
+ *   p < n_parts (1 meson, 2 nucleon); layouts and orders as the single calls.
+ * c3pt_server_release(server, id)   return the request's arena space (waits
+ *   for its completion); also drops a request still queued.
+ * c3pt_server_info(server, &n_active, &n_queued, &largest_free_arena_bytes)
+ * c3pt_server_destroy(server)   synchronizes the stream, frees the workspace
+ *   and phase tables; the arena stays the caller's.
+ * A request's results do not depend on the other requests in flight: each
+ * output element is summed over the same fixed site chunks in the same order.
+ * One host thread drives a server.
+ */
+#define C3PT_REQ_MESON    0
+#define C3PT_REQ_NUCLEON  1
+
+typedef struct c3pt_request {
+    int   kind;                 /* C3PT_REQ_MESON or C3PT_REQ_NUCLEON                        */
+    int   L[3];
+    int   T;
+    int   r[3];                 /* spatial source position                                   */
+    int   t_src;                /* first insertion timeslice                                 */
+    int   t_f;                  /* sink timeslice (last insertion timeslice)                 */
+    int   n_noise;
+    int   n_ops;                /* 1 (local, 16 Gamma) or 5 (with the four D_nu)             */
+    const void* const* G_t;     /* host [T] device slices: meson propagator, nucleon u       */
+    const void* const* G2_t;    /* nucleon: host [T] device slices of the d propagator       */
+    const void* const* s_t;     /* host [T] device [n_noise][12][V3] solutions               */
+    const void* const* U_t;     /* host [T] device links when n_ops == 5, else NULL          */
+    const void* eta;            /* device [n_noise][12][V3] noise on t_f                     */
+    const int*  k;              /* host [n_mom][3] momenta (1..128), for p' and q            */
+    int   n_mom;
+    const int*  pairs;          /* host [n_pairs][2] (p', q) combine pairs, NULL = all       */
+    int   n_pairs;
+} c3pt_request;
+
+typedef struct c3pt_result {
+    void* spec[2];
+    void* ins[2];
+    void* comb[2];
+    int   n_parts;
+    int   n_tau;
+    int   n_pairs;
+} c3pt_result;
+
+typedef struct c3pt_server c3pt_server;
+
+int c3pt_server_create(int proj, void* arena, unsigned long long arena_bytes, unsigned long long step_bytes,
+                       int max_active, void* stream, c3pt_server** server);
+int c3pt_server_submit(c3pt_server* server, const c3pt_request* req, long long* id);
+int c3pt_server_step(c3pt_server* server, int* n_active, int* n_queued);
+int c3pt_server_poll(c3pt_server* server, long long id);
+int c3pt_server_result(c3pt_server* server, long long id, c3pt_result* res);
+int c3pt_server_release(c3pt_server* server, long long id);
+int c3pt_server_info(const c3pt_server* server, int* n_active, int* n_queued,
+                     unsigned long long* largest_free_arena_bytes);
+int c3pt_server_destroy(c3pt_server* server);
+
 #ifdef __cplusplus
 }
 #endif

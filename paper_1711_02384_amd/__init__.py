@@ -39,7 +39,9 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
             "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
             "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read", "c3pt_variant_count",
             "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
-            "c3pt_batch_destroy")
+            "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
+            "c3pt_server_poll", "c3pt_server_result", "c3pt_server_release", "c3pt_server_info",
+            "c3pt_server_destroy")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
 MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3}
@@ -74,6 +76,20 @@ class _CombineJob(ctypes.Structure):
     _fields_ = [("spec_job", ctypes.c_int), ("ins_job", ctypes.c_int), ("op_begin", ctypes.c_int),
                 ("op_end", ctypes.c_int), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("pairs", ctypes.POINTER(ctypes.c_int)), ("n_pairs", ctypes.c_int), ("out", ctypes.c_void_p)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("L", ctypes.c_int * 3), ("T", ctypes.c_int), ("r", ctypes.c_int * 3),
+                ("t_src", ctypes.c_int), ("t_f", ctypes.c_int), ("n_noise", ctypes.c_int), ("n_ops", ctypes.c_int),
+                ("G_t", ctypes.POINTER(ctypes.c_void_p)), ("G2_t", ctypes.POINTER(ctypes.c_void_p)),
+                ("s_t", ctypes.POINTER(ctypes.c_void_p)), ("U_t", ctypes.POINTER(ctypes.c_void_p)),
+                ("eta", ctypes.c_void_p), ("k", ctypes.POINTER(ctypes.c_int)), ("n_mom", ctypes.c_int),
+                ("pairs", ctypes.POINTER(ctypes.c_int)), ("n_pairs", ctypes.c_int)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("spec", ctypes.c_void_p * 2), ("ins", ctypes.c_void_p * 2), ("comb", ctypes.c_void_p * 2),
+                ("n_parts", ctypes.c_int), ("n_tau", ctypes.c_int), ("n_pairs", ctypes.c_int)]
 
 
 def _load():
@@ -113,6 +129,18 @@ def _load():
     lib.c3pt_batch_info.argtypes = [vp, ip, ip, ctypes.POINTER(ctypes.c_ulonglong)]
     lib.c3pt_batch_destroy.argtypes = [vp]
     for name in ("c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info", "c3pt_batch_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    ull = ctypes.c_ulonglong
+    lib.c3pt_server_create.argtypes = [i, vp, ull, ull, i, vp, ctypes.POINTER(vp)]
+    lib.c3pt_server_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_longlong)]
+    lib.c3pt_server_step.argtypes = [vp, ip, ip]
+    lib.c3pt_server_poll.argtypes = [vp, ctypes.c_longlong]
+    lib.c3pt_server_result.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(_Result)]
+    lib.c3pt_server_release.argtypes = [vp, ctypes.c_longlong]
+    lib.c3pt_server_info.argtypes = [vp, ip, ip, ctypes.POINTER(ull)]
+    lib.c3pt_server_destroy.argtypes = [vp]
+    for name in ("c3pt_server_create", "c3pt_server_submit", "c3pt_server_step", "c3pt_server_poll",
+                 "c3pt_server_result", "c3pt_server_release", "c3pt_server_info", "c3pt_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -480,6 +508,141 @@ class Batch:
     def close(self) -> None:
         if self._handle:
             _check(lib.c3pt_batch_destroy(self._handle))
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Serving (c3pt_server_*): continuous batching of contraction requests.
+# ---------------------------------------------------------------------------
+REQ_KIND = {"meson": 0, "nucleon": 1}
+
+
+class Server:
+    """Continuous-batching engine (c3pt_server_*).
+
+    The arena (outputs of admitted requests) is a torch uint8 tensor owned by
+    this object; results are returned as complex128 views into it, valid until
+    ``release(id)``.  Requests name device tensors that must stay allocated
+    until the request is released; the object keeps references to them."""
+
+    def __init__(self, proj: int = PROJ_NATIVE, arena_bytes: int = 1 << 30, step_bytes: int = 256 << 20,
+                 max_active: int = 8, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        self._handle = ctypes.c_void_p()
+        self._keep = {}
+        self._shapes = {}
+        torch.cuda.current_stream().synchronize()
+        _check(lib.c3pt_server_create(int(proj), self.arena.data_ptr(), int(arena_bytes), int(step_bytes),
+                                      int(max_active), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(self._handle)))
+
+    def submit(self, req: dict) -> int:
+        """req: kind ("meson" | "nucleon"), L, T, r, t_src, t_f, eta [N,12,V3], G_t (dict/list of
+        [12,12,V3] slices), G2_t (nucleon), s_t ([N,12,V3] slices), optional U_t and n_ops (1 or 5),
+        k (momenta [n][3]), optional pairs [n_pairs][2].  All tensors complex64 on the GPU."""
+        import numpy as np
+        dt = torch.complex64
+        L = [int(x) for x in req["L"]]
+        T = int(req["T"])
+        V3 = L[0] * L[1] * L[2]
+        eta = req["eta"]
+        N = eta.shape[0]
+        n_ops = int(req.get("n_ops", 1))
+        c = _Request()
+        c.kind = REQ_KIND[req["kind"]]
+        for d in range(3):
+            c.L[d] = L[d]
+            c.r[d] = int(req.get("r", (0, 0, 0))[d])
+        c.T, c.t_src, c.t_f, c.n_noise, c.n_ops = T, int(req["t_src"]), int(req["t_f"]), N, n_ops
+        c.eta = _field(eta, "eta", (N, 12, V3), dt)
+        Gt = _slice_table(req["G_t"], T, "G_t", (12, 12, V3), dt)
+        G2t = _slice_table(req.get("G2_t"), T, "G2_t", (12, 12, V3), dt)
+        st = _slice_table(req["s_t"], T, "s_t", (N, 12, V3), dt)
+        Ut = _slice_table(req.get("U_t"), T, "U_t", (4, 3, 3, V3), dt)
+        c.G_t = ctypes.cast(Gt, ctypes.POINTER(ctypes.c_void_p))
+        c.G2_t = ctypes.cast(G2t, ctypes.POINTER(ctypes.c_void_p)) if req.get("G2_t") is not None else None
+        c.s_t = ctypes.cast(st, ctypes.POINTER(ctypes.c_void_p))
+        c.U_t = ctypes.cast(Ut, ctypes.POINTER(ctypes.c_void_p)) if req.get("U_t") is not None else None
+        ka, kp, n_mom = _momenta(req["k"])
+        c.k, c.n_mom = kp, n_mom
+        if req.get("pairs") is not None:
+            pa = np.ascontiguousarray(np.asarray(req["pairs"], dtype=np.int32).reshape(-1, 2))
+            c.pairs, c.n_pairs = pa.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), pa.shape[0]
+            n_pairs = pa.shape[0]
+        else:
+            n_pairs = n_mom * n_mom
+        rid = ctypes.c_longlong()
+        _check(lib.c3pt_server_submit(self._handle, ctypes.byref(c), ctypes.byref(rid)))
+        self._keep[rid.value] = (req, Gt, G2t, st, Ut)
+        t0, tf = int(req["t_src"]), int(req["t_f"])
+        n_tau = (tf - t0) % T + 1
+        spin = 64 if c.kind == 0 else 1024
+        self._shapes[rid.value] = {"spec": (N, n_mom, spin * 3), "ins": (N, n_tau, n_ops, n_mom, 192),
+                                   "comb": (n_pairs, n_tau, n_ops, spin, 64), "parts": 1 if c.kind == 0 else 2}
+        return rid.value
+
+    def step(self):
+        na, nq = ctypes.c_int(), ctypes.c_int()
+        _check(lib.c3pt_server_step(self._handle, ctypes.byref(na), ctypes.byref(nq)))
+        return na.value, nq.value
+
+    def poll(self, rid: int) -> bool:
+        rc = int(lib.c3pt_server_poll(self._handle, int(rid)))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    def result(self, rid: int) -> dict:
+        """Views of the request's outputs: spec, ins, comb (lists over parts)."""
+        r = _Result()
+        _check(lib.c3pt_server_result(self._handle, int(rid), ctypes.byref(r)))
+        sh = self._shapes[int(rid)]
+        base = self.arena.data_ptr()
+        out = {}
+        for name in ("spec", "ins", "comb"):
+            views = []
+            for p in range(sh["parts"]):
+                n = 1
+                for x in sh[name]:
+                    n *= x
+                off = getattr(r, name)[p] - base
+                views.append(self.arena[off: off + 16 * n].view(torch.complex128).view(sh[name]))
+            out[name] = views
+        return out
+
+    def release(self, rid: int) -> None:
+        _check(lib.c3pt_server_release(self._handle, int(rid)))
+        self._keep.pop(int(rid), None)
+        self._shapes.pop(int(rid), None)
+
+    def info(self) -> dict:
+        na, nq, lf = ctypes.c_int(), ctypes.c_int(), ctypes.c_ulonglong()
+        _check(lib.c3pt_server_info(self._handle, ctypes.byref(na), ctypes.byref(nq), ctypes.byref(lf)))
+        return {"active": na.value, "queued": nq.value, "largest_free": lf.value}
+
+    def run_until_done(self, ids) -> None:
+        """Step until every request in ids has completed."""
+        pending = set(int(i) for i in ids)
+        while pending:
+            na, nq = self.step()
+            pending = {i for i in pending if not self.poll(i)}
+            if pending and na == 0:
+                self.stream.synchronize()
+                pending = {i for i in pending if not self.poll(i)}
+                if pending and nq > 0 and self.step()[0] == 0:
+                    raise C3ptError(C3PT_ENOMEM, "queued requests cannot be admitted: the arena is held by "
+                                                 "results that were not released")
+
+    def close(self) -> None:
+        if self._handle:
+            _check(lib.c3pt_server_destroy(self._handle))
             self._handle = ctypes.c_void_p()
 
     def __del__(self):

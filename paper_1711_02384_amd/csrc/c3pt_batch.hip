@@ -164,6 +164,10 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
         const int tiles = (d.V3 + kSiteTile - 1) / kSiteTile;
         d.chunk_sites = (tiles + d.n_chunks - 1) / d.n_chunks * kSiteTile;
         d.n_chunks = (d.V3 + d.chunk_sites - 1) / d.chunk_sites;
+        d.n_mom = n_mom;
+        d.out_inner = d.n_colblocks / (d.group_cols / kBlockCols);   // output groups: identity map
+        d.out_stride = d.out_inner;
+        d.out_off = 0;
         hj[i].d = d;
         hj[i].index = i;
         hj[i].cost = (double)d.V3 * d.n_colblocks;
@@ -202,8 +206,12 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
 
     // ---- phase tables (owned by the batch, one per (extents, sign)) and
     //      insertion pointer tables ----
+    int* kdev;
+    if (int rc = dmalloc(b, (void**)&kdev, (size_t)n_mom * 3 * sizeof(int))) return bail(rc);
+    if (int rc = upload_sync(kdev, k, (size_t)n_mom * 3 * sizeof(int), st)) return bail(rc);
     std::map<std::array<int, 4>, const void*> tables;
     for (HostJob& h : hj) {
+        h.d.k = kdev;
         BatchJob& d = h.d;
         const c3pt_job& J = jobs[h.index];
         const std::array<int, 4> key = {d.L[0], d.L[1], d.L[2], d.sigma};
@@ -375,9 +383,6 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     // ---- the schedule ----
     BatchReduceArgs rbase;
     memset(&rbase, 0, sizeof(rbase));
-    rbase.n_mom = n_mom;
-    for (int m = 0; m < n_mom; ++m)
-        for (int j = 0; j < 3; ++j) rbase.k[j][m] = (short)k[3 * m + j];
     int job_base = 0;
     static const char* kProjName[3] = {"batch_proj_spectator_meson", "batch_proj_spectator_baryon",
                                        "batch_proj_insertion"};
@@ -389,7 +394,6 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             bg.jobs = JD;
             bg.items = q.items;
             bg.n_items = q.n;
-            bg.n_mom = n_mom;
             bg.counter = q.counter;
             const int kind = q.kind, variant = q.variant, n_wg = q.n_wg;
             b->ops.push_back({kProjName[kind], [=](hipStream_t s) {

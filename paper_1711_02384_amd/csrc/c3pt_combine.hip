@@ -66,26 +66,28 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(BatchReduceArgs a, lo
         const BatchJob& job = a.jobs[lo];
         const long long e = idx - a.out_offset[lo];
         const int gc = job.group_cols;
+        const int n_mom = job.n_mom;
         const int c = (int)(e % gc);
         const long long rest = e / gc;
-        const int m = (int)(rest % a.n_mom);
-        const int g = (int)(rest / a.n_mom);
+        const int m = (int)(rest % n_mom);
+        const int g = (int)(rest / n_mom);
         const int cb = g * (gc / kBlockCols) + c / kBlockCols;
         const int cc = c % kBlockCols;
         const float2* partial = (const float2*)job.partial;
         double sx = 0.0, sy = 0.0;
         for (int ch = 0; ch < job.n_chunks; ++ch) {
-            const float2 v = partial[(((size_t)ch * job.n_colblocks + cb) * a.n_mom + m) * kBlockCols + cc];
+            const float2 v = partial[(((size_t)ch * job.n_colblocks + cb) * n_mom + m) * kBlockCols + cc];
             sx += (double)v.x;
             sy += (double)v.y;
         }
         int k[3];
         for (int j = 0; j < 3; ++j) {
             const int L = job.L[j];
-            k[j] = ((a.k[j][m] % L) + L) % L;
+            k[j] = ((job.k[3 * m + j] % L) + L) % L;
         }
         const double2 f = source_factor(job.L, job.r, job.sigma, k[0], k[1], k[2]);
-        job.out[e] = cmul_d(f, make_double2(sx, sy));
+        const long long G = (long long)(g / job.out_inner) * job.out_stride + job.out_off + g % job.out_inner;
+        job.out[(G * n_mom + m) * gc + c] = cmul_d(f, make_double2(sx, sy));
     }
 }
 

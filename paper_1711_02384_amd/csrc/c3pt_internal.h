@@ -83,6 +83,11 @@ struct BatchJob {
     int n_noise, n_tau, n_ops;
     int n_colblocks, n_chunks, chunk_sites;
     int group_cols;    // 192 or 3072 output columns per group
+    int n_mom;         // momenta (at most 128)
+    const int* k;      // device [n_mom][3] momentum list (signed; reduced per job)
+    // Output group of job-local group g: (g / out_inner) * out_stride + out_off + g % out_inner
+    // (a job may cover a block of noise vectors or timeslices of a larger output).
+    int out_inner, out_stride, out_off;
     const void* G;     // spectator propagator (baryon: G1)
     const void* G2;    // baryon: G2
     const void* eta;   // spectator noise
@@ -97,17 +102,14 @@ struct BatchGrid {
     const BatchJob* jobs;
     const int4* items;     // (job, column block, chunk, 0) in issue order
     int n_items;
-    int n_mom;
     int* counter;          // work-queue head, zeroed by the batch's reset kernel
 };
 
 // Batched reduction: one output element per thread over all jobs of a group.
 struct BatchReduceArgs {
     const BatchJob* jobs;
-    const long long* out_offset;   // prefix sums of output elements per job (n_jobs + 1)
+    const long long* out_offset;   // prefix sums of the jobs' output elements (n_jobs + 1)
     int n_jobs;
-    int n_mom;
-    short k[3][kMaxMomGroup];      // momenta (signed); reduced per job
 };
 
 // Reduction of the split-site partial sums: output[G][m][c], c < group_cols,

@@ -358,7 +358,6 @@ __global__ void __launch_bounds__(Cons::NT, Cons::MINW) batch_kernel(BatchGrid b
     __shared__ int s_item;
 
     const int tid = threadIdx.x;
-    const int mt = (bg.n_mom + 7) >> 3;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(bg.counter, 1);
         __syncthreads();
@@ -380,8 +379,9 @@ __global__ void __launch_bounds__(Cons::NT, Cons::MINW) batch_kernel(BatchGrid b
         Cons::zero(acc);
         const int s_lo = chunk * job.chunk_sites;
         const int s_hi = min(job.V3, s_lo + job.chunk_sites);
+        const int mt = (job.n_mom + 7) >> 3;
         tile_loop<Cons, Prod>(ctx, tg, job.phase, s_lo, s_hi, csm, psm, acc, mt, tid);
-        Cons::write(job.partial, job.n_colblocks, bg.n_mom, chunk, cb, acc, mt, tid);
+        Cons::write(job.partial, job.n_colblocks, job.n_mom, chunk, cb, acc, mt, tid);
     }
 }
 

@@ -1,0 +1,177 @@
+"""Serving engine (c3pt_server_*): continuous batching of requests.
+
+* every request of a mix (meson with derivative operators and a wrapping
+  timeslice range, nucleon, a multi-chunk lattice) matches the FP64 oracle;
+* each request gives bit-identical results alone, in the mix, and under a
+  different step workspace (different packets and steps);
+* admission by memory: with an arena that holds one request at a time the
+  requests queue and still all complete with the same results;
+* requests that do not fit are rejected at submission.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import Workload, rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _up(a):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).cuda()
+
+
+class Req:
+    def __init__(self, kind, L, T, r, t_src, t_f, N, n_ops, n2, cfg, pairs=None):
+        self.kind, self.L, self.T, self.r = kind, L, T, r
+        self.t_src, self.t_f, self.N, self.n_ops = t_src, t_f, N, n_ops
+        self.taus = [(t_src + i) % T for i in range((t_f - t_src) % T + 1)]
+        import paper_1711_02384_amd as c3pt
+        self.k = c3pt.momentum_list(n2)
+        self.pairs = pairs
+        nuc = kind == "nucleon"
+        self.w = Workload(L, T, N, cfg=cfg, t_f=t_f, taus=self.taus, links=n_ops == 5, reduced=True)
+        if nuc:
+            self.wd = Workload(L, T, N, cfg=cfg + 100, t_f=t_f, taus=self.taus, links=False, reduced=True)
+        w = self.w
+        # one resident propagator per flavour: spectator at t_f and insertion slices
+        self.Gu = dict(w.G3)
+        if t_f not in self.Gu:
+            import c3pt_synth as syn
+            self.Gu[t_f] = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t_f))
+        self.Gd = None
+        if nuc:
+            self.Gd = dict(self.wd.G3)
+            if t_f not in self.Gd:
+                import c3pt_synth as syn
+                self.Gd[t_f] = syn.round_to_c64(syn.propagator_slice(L, cfg + 100, syn.FIELD_G3, t_f))
+        self.dev = {"Gu": {t: _up(v) for t, v in self.Gu.items()},
+                    "Gd": {t: _up(v) for t, v in self.Gd.items()} if nuc else None,
+                    "s": {t: _up(v) for t, v in w.s.items()}, "eta": _up(w.eta),
+                    "U": {t: _up(v) for t, v in w.U.items()} if w.U else None}
+
+    def request(self):
+        d = self.dev
+        return {"kind": self.kind, "L": self.L, "T": self.T, "r": self.r, "t_src": self.t_src, "t_f": self.t_f,
+                "eta": d["eta"], "G_t": d["Gu"], "G2_t": d["Gd"], "s_t": d["s"], "U_t": d["U"],
+                "n_ops": self.n_ops, "k": self.k, "pairs": self.pairs}
+
+    def oracle(self):
+        w, L, T, k, r = self.w, self.L, self.T, self.k, self.r
+        tf = self.t_f
+        if self.kind == "meson":
+            S = [oracle.spectator_meson(self.Gu[tf], w.eta, L, k, r=r)]
+            I = [oracle.insertion(self.Gu, w.s, self.taus, L, T, k, r=r, U_t=w.U, n_ops=self.n_ops)]
+            C = [oracle.combine(S[0], I[0], pairs=self.pairs)]
+        else:
+            S = [oracle.spectator_baryon(self.Gu[tf], self.Gu[tf], w.eta, L, k, r=r),
+                 oracle.spectator_baryon(self.Gu[tf], self.Gd[tf], w.eta, L, k, r=r)]
+            I = [oracle.insertion(self.Gu, w.s, self.taus, L, T, k, r=r, n_ops=1),
+                 oracle.insertion(self.Gd, w.s, self.taus, L, T, k, r=r, n_ops=1)]
+            C = [oracle.combine(S[0], I[1], pairs=self.pairs), oracle.combine(S[1], I[0], pairs=self.pairs)]
+        return S, I, C
+
+
+def _mix():
+    return [Req("meson", (6, 4, 5), 8, (1, 2, 3), 5, 1, 3, 5, 3, cfg=31, pairs=[(0, 0), (2, 7), (26, 1)]),
+            Req("nucleon", (4, 4, 6), 6, (0, 1, 2), 4, 1, 2, 1, 2, cfg=32, pairs=[(0, 0), (0, 3)]),
+            Req("meson", (14, 12, 16), 6, (3, 5, 7), 0, 3, 2, 1, 5, cfg=33, pairs=[(1, 1), (0, 10), (30, 2)]),
+            Req("meson", (5, 3, 4), 6, (4, 1, 2), 2, 2, 1, 1, 1, cfg=34)]
+
+
+def _serve(c3pt, reqs, proj, arena=64 << 20, step=4 << 20, max_active=8):
+    sv = c3pt.Server(proj=proj, arena_bytes=arena, step_bytes=step, max_active=max_active)
+    ids = [sv.submit(q.request()) for q in reqs]
+    return sv, ids
+
+
+def _copy(sv, rid):
+    res = sv.result(rid)
+    return {k: [t.clone() for t in v] for k, v in res.items()}
+
+
+@pytest.mark.parametrize("proj,name", [(0, "f32"), (1, "f16x2")])
+def test_serve_mix_matches_oracle_and_alone(proj, name):
+    import paper_1711_02384_amd as c3pt
+    reqs = _mix()
+    sv, ids = _serve(c3pt, reqs, proj)
+    sv.run_until_done(ids)
+    torch.cuda.synchronize()
+    mix = [_copy(sv, i) for i in ids]
+    for q, got in zip(reqs, mix):
+        S, I, C = q.oracle()
+        for p in range(len(S)):
+            es = rel_fro(got["spec"][p].cpu().numpy(), S[p])
+            ei = rel_fro(got["ins"][p].cpu().numpy(), I[p])
+            ec = rel_fro(got["comb"][p].cpu().numpy(), C[p])
+            _say(f"serve {name}: {q.kind} {q.L} part {p}: spectator {es:.2e} insertion {ei:.2e} combine {ec:.2e}")
+            assert es < TOL and ei < TOL and ec < TOL
+    for i in ids:
+        sv.release(i)
+    sv.close()
+    # each request alone, and the mix again with another step size (other packets)
+    for q, want in zip(reqs, mix):
+        sv1, (i1,) = _serve(c3pt, [q], proj)
+        sv1.run_until_done([i1])
+        torch.cuda.synchronize()
+        got = sv1.result(i1)
+        for key in ("spec", "ins", "comb"):
+            for a, b in zip(got[key], want[key]):
+                assert torch.equal(a, b), (q.kind, q.L, key)
+        sv1.close()
+    sv2, ids2 = _serve(c3pt, reqs, proj, step=2 << 20, max_active=2)
+    sv2.run_until_done(ids2)
+    torch.cuda.synchronize()
+    for i, want in zip(ids2, mix):
+        got = sv2.result(i)
+        for key in ("spec", "ins", "comb"):
+            for a, b in zip(got[key], want[key]):
+                assert torch.equal(a, b)
+    sv2.close()
+
+
+def test_serve_admission_by_memory():
+    import paper_1711_02384_amd as c3pt
+    reqs = [q for q in _mix() if q.kind == "meson"]
+    sizes = []
+    for q in reqs:
+        n_tau, n_mom = len(q.taus), len(q.k)
+        n_pairs = len(q.pairs) if q.pairs is not None else n_mom * n_mom
+        b = 16 * (q.N * n_mom * 192 + q.N * n_tau * q.n_ops * n_mom * 192 + n_pairs * n_tau * q.n_ops * 4096)
+        sizes.append(b + 4096)
+    arena = max(sizes) + (64 << 10)    # room for the largest request only
+    sv, ids = _serve(c3pt, reqs, 0, arena=arena)
+    na, nq = sv.step()
+    _say(f"after the first step: active {na}, queued {nq}")
+    assert nq >= 1
+    done = {}
+    pending = list(ids)
+    while pending:
+        sv.step()
+        for i in list(pending):
+            if sv.poll(i):
+                done[i] = _copy(sv, i)
+                sv.release(i)          # frees the arena for the next request
+                pending.remove(i)
+    torch.cuda.synchronize()
+    for q, i in zip(reqs, ids):
+        S, I, C = q.oracle()
+        assert rel_fro(done[i]["ins"][0].cpu().numpy(), I[0]) < TOL
+        assert rel_fro(done[i]["comb"][0].cpu().numpy(), C[0]) < TOL
+    sv.close()
+
+
+def test_serve_rejects_requests_that_cannot_fit():
+    import paper_1711_02384_amd as c3pt
+    q = _mix()[2]
+    sv = c3pt.Server(proj=0, arena_bytes=1 << 20, step_bytes=1 << 20, max_active=2)
+    with pytest.raises(c3pt.C3ptError):
+        sv.submit(q.request())
+    assert sv.info()["queued"] == 0
+    sv.close()
