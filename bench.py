@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 20; batch64: 3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 3; batch64: 1)")
-    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "batch64"], default="meson32")
+    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "batch64", "serve"], default="meson32")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -61,6 +61,12 @@ def parse():
                     help="batch64: device memory for FP32 split-site partial sums")
     ap.add_argument("--no-plain", action="store_true",
                     help="batch64: skip timing the same jobs as plain per-call FP32 launches")
+    ap.add_argument("--requests", type=int, default=500, help="serve: requests per load level")
+    ap.add_argument("--loads", default="0.5,0.8,0.95", help="serve: arrival rates as fractions of saturation")
+    ap.add_argument("--lattices", default="16,32,48,64", help="serve: spatial extents of the resident lattices")
+    ap.add_argument("--arena-gib", type=float, default=48.0, help="serve: output arena")
+    ap.add_argument("--step-mib", type=float, default=1024.0, help="serve: partial-sum workspace per step")
+    ap.add_argument("--max-active", type=int, default=32, help="serve: requests in flight")
     return ap.parse_args()
 
 
@@ -535,6 +541,238 @@ class Batch64:
 WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48, "batch64": Batch64}
 
 
+# ---------------------------------------------------------------------------
+# Serving: Poisson arrivals of contraction requests (continuous batching)
+# ---------------------------------------------------------------------------
+SERVE_LATTICES = {16: 32, 32: 64, 48: 96, 64: 128}     # L -> T
+SERVE_WEIGHTS = {16: 4, 32: 3, 48: 2, 64: 1}
+
+
+class ServePool:
+    """Resident inputs per lattice: one source's u and d propagators on every
+    timeslice, stochastic solutions of 16 noise vectors on every timeslice,
+    and 16 noise vectors on one sink slice (shared by every t_f).  Drawn on the
+    GPU from seeded torch generators (unit complex Gaussians, Z2 x Z2 noise)."""
+    N_MAX = 16
+
+    def __init__(self, lattices, dev):
+        import torch
+        gen = torch.Generator(device=dev)
+        self.lat = {}
+        inv = 1.0 / np.sqrt(2.0)
+        sd = float(np.sqrt(0.5))
+        for li, Ls in enumerate(lattices):
+            T = SERVE_LATTICES[Ls]
+            V3 = Ls ** 3
+            d = {"T": T, "V3": V3}
+            for fi, name in enumerate(("u", "d")):
+                buf = torch.empty((T, 12, 12, V3), dtype=torch.complex64, device=dev)
+                gen.manual_seed((5 * 1024 + li) * 8 + fi)
+                buf.view(torch.float32).normal_(0.0, sd, generator=gen)
+                d[name] = buf
+            sbuf = torch.empty((T, self.N_MAX, 12, V3), dtype=torch.complex64, device=dev)
+            gen.manual_seed((6 * 1024 + li) * 8)
+            sbuf.view(torch.float32).normal_(0.0, sd, generator=gen)
+            d["s"] = sbuf
+            gen.manual_seed(7 * 1024 + li)
+            b = torch.randint(0, 2, (self.N_MAX, 12, V3, 2), device=dev, generator=gen, dtype=torch.int8)
+            d["eta"] = torch.view_as_complex(((1 - 2 * b).float() * inv).contiguous())
+            self.lat[Ls] = d
+            torch.cuda.synchronize()
+            log(f"[serve] lattice {Ls}^3x{T} resident ({torch.cuda.memory_allocated() / 2**30:.1f} GiB in HBM)")
+        self._k = {}
+
+    def request(self, c3pt, spec):
+        """Request dict for the server from a drawn spec (views into the pool)."""
+        d = self.lat[spec["L"]]
+        T, N = d["T"], spec["N"]
+        G = {t: d["u"][t] for t in range(T)}
+        G2 = {t: d["d"][t] for t in range(T)} if spec["kind"] == "nucleon" else None
+        s_t = {t: d["s"][t, :N] for t in range(T)}
+        if spec["n2"] not in self._k:
+            k = c3pt.momentum_list(spec["n2"])
+            self._k[spec["n2"]] = (k, pairs_diag_or_zero(len(k)))
+        k, pairs = self._k[spec["n2"]]
+        return {"kind": spec["kind"], "L": (spec["L"],) * 3, "T": T, "r": spec["r"], "t_src": spec["t_src"],
+                "t_f": spec["t_f"], "eta": d["eta"][:N], "G_t": G, "G2_t": G2, "s_t": s_t, "n_ops": 1,
+                "k": k, "pairs": pairs}
+
+
+def serve_draw(n, lattices, seed):
+    """Seeded request specs: lattice 4:3:2:1, |k|^2 in 3..9, meson or nucleon,
+    N in 1..16, t_f - t_src in 8..16, uniform source position and t_src."""
+    import c3pt_synth as syn
+    g = syn.rng(5, 98, seed)
+    w = np.array([SERVE_WEIGHTS[L] for L in lattices], dtype=float)
+    w /= w.sum()
+    out = []
+    for _ in range(n):
+        L = int(lattices[g.choice(len(lattices), p=w)])
+        T = SERVE_LATTICES[L]
+        t_src = int(g.integers(0, T))
+        dt = int(g.integers(8, 17))
+        out.append({"L": L, "n2": int(g.integers(3, 10)), "kind": "nucleon" if g.integers(0, 2) else "meson",
+                    "N": int(g.integers(1, 17)), "t_src": t_src, "t_f": (t_src + dt) % T, "n_tau": dt + 1,
+                    "r": [int(g.integers(0, L)) for _ in range(3)]})
+    return out
+
+
+def serve_units(spec, momenta):
+    n_mom = momenta[spec["n2"]]
+    f = 2 if spec["kind"] == "nucleon" else 1
+    return f * spec["N"] * spec["L"] ** 3 * n_mom * (1 + spec["n_tau"])
+
+
+def serve_flops(spec, momenta):
+    """Algorithmic projection flops per producer kind (8 real flops per complex MAC)."""
+    n_mom, V3, N = momenta[spec["n2"]], spec["L"] ** 3, spec["N"]
+    if spec["kind"] == "nucleon":
+        return {"serve_proj_spectator_baryon": 2 * 8.0 * n_mom * V3 * N * 3072,
+                "serve_proj_insertion": 2 * 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
+    return {"serve_proj_spectator_meson": 8.0 * n_mom * V3 * N * 192,
+            "serve_proj_insertion": 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
+
+
+def serve_main(args):
+    import torch
+    import paper_1711_02384_amd as c3pt
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    proj = args.proj or "f16x2"
+    proj_flag = {"f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16, "f16x2": c3pt.PROJ_SPLIT_F16}[proj]
+    lattices = [int(x) for x in args.lattices.split(",")]
+    loads = [float(x) for x in args.loads.split(",")]
+    momenta = {n2: len(c3pt.momentum_list(n2)) for n2 in range(3, 10)}
+    t0 = time.perf_counter()
+    pool = ServePool(lattices, dev)
+    log(f"[serve] inputs resident ({time.perf_counter() - t0:.1f} s)")
+    sv = c3pt.Server(proj=proj_flag, arena_bytes=int(args.arena_gib * 2**30),
+                     step_bytes=int(args.step_mib * 2**20), max_active=args.max_active)
+    clock = time.perf_counter
+
+    def drive(specs, arrivals):
+        """Submit each request at its arrival time (seconds from start), step the
+        engine, and record completion times; returns (latencies, wall seconds)."""
+        order = np.argsort(arrivals, kind="stable")
+        lat = np.zeros(len(specs))
+        pending = {}
+        nxt = 0
+        start = clock()
+        while nxt < len(order) or pending:
+            now = clock() - start
+            while nxt < len(order) and arrivals[order[nxt]] <= now:
+                i = int(order[nxt])
+                rid = sv.submit(pool.request(c3pt, specs[i]))
+                pending[rid] = i
+                nxt += 1
+            na, nq = sv.step() if pending else (0, 0)
+            for rid in list(pending):
+                if sv.poll(rid):
+                    i = pending.pop(rid)
+                    lat[i] = (clock() - start) - arrivals[i]
+                    sv.release(rid)
+            if not pending and nxt < len(order):
+                wait = arrivals[order[nxt]] - (clock() - start)
+                if wait > 0:
+                    time.sleep(min(wait, 0.01))
+            elif pending and na == 0:
+                time.sleep(0.0005)
+        return lat, clock() - start
+
+    # warm-up: one request per (lattice, cutoff, kind) builds every phase table
+    warm = []
+    for L in lattices:
+        for n2 in range(3, 10):
+            for kind in ("meson", "nucleon"):
+                T = SERVE_LATTICES[L]
+                warm.append({"L": L, "n2": n2, "kind": kind, "N": 1, "t_src": 0, "t_f": 8, "n_tau": 9,
+                             "r": [0, 0, 0]})
+    log(f"[serve] warm-up: {len(warm)} requests")
+    drive(warm, np.zeros(len(warm)))
+    torch.cuda.synchronize()
+
+    # saturation: a closed batch of requests all present at t = 0
+    n_sat = max(40, args.requests // 2)
+    sat = serve_draw(n_sat, lattices, seed=1)
+    log(f"[serve] saturation run: {n_sat} requests at once")
+    lat_sat, wall = drive(sat, np.zeros(n_sat))
+    units_sat = sum(serve_units(sp, momenta) for sp in sat)
+    rate = n_sat / wall
+    value = units_sat / wall
+    log(f"[serve] saturated: {rate:.1f} requests/s, {value:.3g} units/s")
+
+    # per-kernel timing on a profiled closed batch
+    prof_specs = serve_draw(max(12, n_sat // 4), lattices, seed=2)
+    c3pt.profile_read(reset=True)
+    c3pt.profile_enable(True)
+    drive(prof_specs, np.zeros(len(prof_specs)))
+    torch.cuda.synchronize()
+    c3pt.profile_enable(False)
+    prof = c3pt.profile_read(reset=True)
+    kflops = {}
+    for sp in prof_specs:
+        for kn, f in serve_flops(sp, momenta).items():
+            kflops[kn] = kflops.get(kn, 0.0) + f
+    kname = max((kn for kn in kflops if kn in prof), key=lambda kn: prof[kn]["total_ms"])
+    achieved = kflops[kname] / (prof[kname]["total_ms"] * 1e-3) / 1e12
+    peak = PEAK[proj]
+
+    levels = []
+    for li, rho in enumerate(loads):
+        specs = serve_draw(args.requests, lattices, seed=10 + li)
+        g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([1711, 2384, 5, 97, li])))
+        arrivals = np.cumsum(g.exponential(1.0 / (rho * rate), size=len(specs)))
+        log(f"[serve] load {rho}: {len(specs)} Poisson arrivals at {rho * rate:.1f} requests/s")
+        lat, wall_l = drive(specs, arrivals)
+        units = sum(serve_units(sp, momenta) for sp in specs)
+        levels.append({"rho": rho, "arrival_rate_per_s": rho * rate, "requests": len(specs),
+                       "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                       "mean_ms": float(lat.mean() * 1e3), "throughput_requests_per_s": len(specs) / wall_l,
+                       "throughput_units_per_s": units / wall_l})
+        log(f"[serve]   p50 {levels[-1]['p50_ms']:.1f} ms  p99 {levels[-1]['p99_ms']:.1f} ms")
+    sv.close()
+    res = {
+        "metric": "contracted site*momenta/s (spectator+insertion)",
+        "value": value,
+        "unit": "site*momenta/s",
+        "n_gpus": 1,
+        "steps": n_sat,
+        "warmup": len(warm),
+        "ms_per_step": wall * 1e3 / n_sat,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16x2": "f32 contraction, bf16 hi+lo projection",
+                  "f16x2": "f32 contraction, f16 hi+lo projection"}[proj],
+        "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals; lattices 16^3x32:32^3x64:48^3x96:64^3x128 = 4:3:2:1, "
+                               "|k|^2 ~ U{3..9}, meson:nucleon 1:1, N ~ U{1..16}, t_f-t_src ~ U{8..16}, local "
+                               "insertion, combine on pairs p'=q or p'=0; one step = one request of the saturated "
+                               "closed batch",
+                   "lattices": lattices, "arena_gib": args.arena_gib, "step_mib": args.step_mib,
+                   "max_active": args.max_active, "saturation_requests": n_sat},
+        "latency_ms": {"p50": levels[-1]["p50_ms"] if levels else None,
+                       "p99": levels[-1]["p99_ms"] if levels else None,
+                       "at_rho": loads[-1] if loads else None},
+        "saturation": {"requests_per_s": rate, "units_per_s": value,
+                       "latency_p50_ms": float(np.percentile(lat_sat, 50) * 1e3),
+                       "latency_p99_ms": float(np.percentile(lat_sat, 99) * 1e3)},
+        "load_levels": levels,
+        "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
+        "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": f"{kname} (fused contraction + {proj} MFMA projection), over a profiled closed batch",
+                     "avg_ms": round(prof[kname]["avg_ms"], 4)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a host sample")
+        W = Meson32(argparse.Namespace(no_baryon=True))
+        res["cpu_baseline"] = cpu_baseline(W, c3pt.momentum_list(6), 2)
+    print(json.dumps(res), flush=True)
+
+
+
 def cpu_baseline(W, k, n_slices):
     """Time the FP64 oracle on a bounded sample of the same workload on the host."""
     try:
@@ -553,6 +791,8 @@ def main():
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "serve":
+        return serve_main(args)
     import torch
     import c3pt_synth as syn
     import paper_1711_02384_amd as c3pt

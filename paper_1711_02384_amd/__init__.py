@@ -634,11 +634,15 @@ class Server:
             na, nq = self.step()
             pending = {i for i in pending if not self.poll(i)}
             if pending and na == 0:
-                self.stream.synchronize()
-                pending = {i for i in pending if not self.poll(i)}
-                if pending and nq > 0 and self.step()[0] == 0:
-                    raise C3ptError(C3PT_ENOMEM, "queued requests cannot be admitted: the arena is held by "
-                                                 "results that were not released")
+                if nq == 0:                 # everything left is enqueued: wait for it
+                    self.stream.synchronize()
+                    pending = {i for i in pending if not self.poll(i)}
+                else:                       # nothing running: the next step must admit
+                    na2, nq2 = self.step()
+                    if na2 == 0 and nq2 == nq:
+                        raise C3ptError(C3PT_ENOMEM, "queued requests cannot be admitted: the arena is held "
+                                                     "by results that were not released")
+                    pending = {i for i in pending if not self.poll(i)}
 
     def close(self) -> None:
         if self._handle:
