@@ -38,7 +38,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0}   # dense MFMA TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0, "fac": 157.3}   # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
 
@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
-    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2"], default=None,
-                    help="projection arithmetic: FP32 MFMA, or hi+lo BF16 / FP16 MFMA with FP32 accumulation")
+    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2", "fac"], default=None,
+                    help="projection: dense FP32 MFMA, dense hi+lo BF16 / FP16 MFMA with FP32 accumulation, "
+                         "or factored (per-direction partial sums, FP32 MFMA)")
     ap.add_argument("--tune", action="store_true", help="autotune kernel variants on this workload first")
     ap.add_argument("--tune-out", default=None, help="write the tuning table (JSON) here")
     ap.add_argument("--sources", type=int, default=64, help="batch64: number of source positions")
@@ -810,7 +811,7 @@ def main():
     k = c3pt.momentum_list(W.n2)
     n_mom = len(k)
     proj_flag = {"f64": c3pt.PROJ_NATIVE, "f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16,
-                 "f16x2": c3pt.PROJ_SPLIT_F16}[proj]
+                 "f16x2": c3pt.PROJ_SPLIT_F16, "fac": c3pt.PROJ_FACTORED}[proj]
     mode = c3pt.MODE[proj]
     batched = isinstance(W, Batch64)
     geom = c3pt.Geom((1, 1, 1) if batched else W.L, 1 if batched else W.T, proj=proj_flag)
@@ -873,6 +874,8 @@ def main():
         kms = prof[kname]["total_ms"] / prof[kname]["count"]
     else:
         kname, flops = W.dominant(n_mom)
+        if proj == "fac":
+            kname = "fac_" + kname[len("proj_"):]
         kms = prof.get(kname, {}).get("avg_ms", float("nan"))
     achieved = flops / (kms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
@@ -909,7 +912,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16x2": "f32 contraction, bf16 hi+lo projection",
-                  "f16x2": "f32 contraction, f16 hi+lo projection"}[proj],
+                  "f16x2": "f32 contraction, f16 hi+lo projection", "fac": "f32"}[proj],
         "data": "synthetic",
         "config": W.config(n_mom),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},

@@ -69,6 +69,10 @@ extern "C" {
 #define C3PT_PROJ_NATIVE      0   /* projection in the input precision (FP32 or FP64 MFMA)     */
 #define C3PT_PROJ_SPLIT_F16   1   /* complex64 only: hi+lo FP16 operands, FP32 MFMA accumulate */
 #define C3PT_PROJ_SPLIT_BF16  2   /* complex64 only: hi+lo BF16 operands, FP32 MFMA accumulate */
+#define C3PT_PROJ_FACTORED    3   /* per-direction partial sums (exp(ip.x) = product over x1, x2,
+                                     x3), stage over x1 on FP32 / FP64 MFMA; momentum groups needing
+                                     more than 8 distinct k1 or 48 (FP64: 24) distinct (k1, k2)
+                                     run on the NATIVE kernel                                    */
 
 #define C3PT_MAX_MOM   256        /* largest momentum list per call        */
 #define C3PT_MAX_L     256        /* largest spatial extent per direction  */
@@ -179,7 +183,10 @@ int c3pt_release_scratch(void);
 /*
  * Kernel variants (tile shapes) of the fused contraction + projection, for
  * the autotuner.  kind: 0 meson spectator, 1 baryon spectator, 2 insertion.
- * mode: 0 FP64 (complex128 inputs), 1 FP32, 2 split BF16, 3 split FP16.
+ * mode: 0 FP64 (complex128 inputs), 1 FP32, 2 split BF16, 3 split FP16;
+ * mode 4 selects the form of the factored projection (C3PT_PROJ_FACTORED):
+ * variant 0 writes every x3 plane's sums as a chunk of its own, variant 1
+ * sums chunks of planes in registers first.
  * mt_class: momentum groups of up to 32, 64, 96, 128 momenta (0..3).
  * c3pt_variant_count returns the number of compiled variants (0 if none);
  * c3pt_set_variant selects one for later calls (process-wide);

@@ -34,6 +34,7 @@ C3PT_C128 = 1
 PROJ_NATIVE = 0
 PROJ_SPLIT_F16 = 1
 PROJ_SPLIT_BF16 = 2
+PROJ_FACTORED = 3
 
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
             "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
@@ -44,7 +45,7 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
             "c3pt_server_destroy")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
-MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3}
+MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4}   # "fac": variant slot of the factored projection
 
 
 class C3ptError(RuntimeError):

@@ -164,6 +164,7 @@ struct PhaseEntry {
     size_t bytes = 0;
     hipEvent_t ready = nullptr;
     unsigned long long last_use = 0;
+    void* pinned = nullptr;   // host copy a factor plan was uploaded from
 };
 constexpr size_t kPhaseCacheCap = (size_t)2 << 30;
 std::map<PhaseKey, PhaseEntry> g_phase;
@@ -172,6 +173,7 @@ unsigned long long g_phase_clock = 0;
 
 void free_phase_entry(PhaseEntry& e) {
     if (e.ptr) hipFree(e.ptr);
+    if (e.pinned) hipHostFree(e.pinned);
     if (e.ready) hipEventDestroy(e.ready);
     g_phase_bytes -= e.bytes;
     e = PhaseEntry{};
@@ -184,9 +186,10 @@ int check_geom(const c3pt_geom* g) {
             return fail(C3PT_EINVAL, "L[%d] = %d outside [1, %d]", j, g->L[j], C3PT_MAX_L);
     if (g->T < 1) return fail(C3PT_EINVAL, "T = %d < 1", g->T);
     if (g->dtype != C3PT_C64 && g->dtype != C3PT_C128) return fail(C3PT_EINVAL, "unknown dtype %d", g->dtype);
-    if (g->proj != C3PT_PROJ_NATIVE && g->proj != C3PT_PROJ_SPLIT_F16 && g->proj != C3PT_PROJ_SPLIT_BF16)
+    if (g->proj != C3PT_PROJ_NATIVE && g->proj != C3PT_PROJ_SPLIT_F16 && g->proj != C3PT_PROJ_SPLIT_BF16 &&
+        g->proj != C3PT_PROJ_FACTORED)
         return fail(C3PT_EINVAL, "unknown projection mode %d", g->proj);
-    if (g->proj != C3PT_PROJ_NATIVE && g->dtype != C3PT_C64)
+    if ((g->proj == C3PT_PROJ_SPLIT_F16 || g->proj == C3PT_PROJ_SPLIT_BF16) && g->dtype != C3PT_C64)
         return fail(C3PT_EINVAL, "split-precision projection needs complex64 inputs");
     return C3PT_OK;
 }
@@ -212,11 +215,14 @@ int proj_mode(const c3pt_geom* g) {
 
 // Kernel variant per (kind, mode, momentum-tile class); 0 = default.
 constexpr int kKinds = 3;   // 0 meson spectator, 1 baryon spectator, 2 insertion
-constexpr int kModes = 4;
+constexpr int kModes = 5;
+constexpr int kModeFacVariants = 4;   // variant slot of the factored projection (not an arithmetic mode)
 int g_variant[kKinds][kModes][kMtClasses] = {};
 
 int variant_count(int kind, int mode, int cls) {
     if (kind < 0 || kind >= kKinds || mode < 0 || mode >= kModes || cls < 0 || cls >= kMtClasses) return 0;
+    // factored: 0 = every x3 plane written as its own chunk, 1 = chunks of planes summed in registers
+    if (mode == kModeFacVariants) return 2;
     if (mode == kModeF64) return cls == 0 ? 1 : 0;
     return kVariantsPerClass[cls];
 }
@@ -302,6 +308,105 @@ int phase_table(const c3pt_geom* g, int sigma, int mode, int mtmax, const int* k
     return C3PT_OK;
 }
 
+// Factor plan of one momentum group (the factored projection): distinct k1
+// values, distinct (k1, k2) pairs grouped by k1, and each momentum's pair and
+// k3, all reduced mod L.  False when the group needs more k1 values or pairs
+// than the kernel holds; the group then runs on the dense kernel.
+bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGroup& mg, bool f64, FactorPlan* p) {
+    memset(p, 0, sizeof(*p));
+    for (int j = 0; j < 3; ++j) p->L[j] = g->L[j];
+    p->sigma = sigma;
+    p->n_mom = mg.n;
+    const int max_pairs = f64 ? kFacMaxPairsF64 : kFacMaxPairsF32;
+    std::vector<int> k1s;
+    std::vector<std::vector<int>> k2s;
+    std::vector<int> am(mg.n), jm(mg.n);
+    for (int m = 0; m < mg.n; ++m) {
+        const int* km = k + 3 * (mg.off + m);
+        const int r1 = posmod(km[0], g->L[0]), r2 = posmod(km[1], g->L[1]);
+        int a = (int)(std::find(k1s.begin(), k1s.end(), r1) - k1s.begin());
+        if (a == (int)k1s.size()) {
+            if ((int)k1s.size() == kFacMaxK1) return false;
+            k1s.push_back(r1);
+            k2s.emplace_back();
+        }
+        int jj = (int)(std::find(k2s[a].begin(), k2s[a].end(), r2) - k2s[a].begin());
+        if (jj == (int)k2s[a].size()) k2s[a].push_back(r2);
+        am[m] = a;
+        jm[m] = jj;
+        p->k3[m] = posmod(km[2], g->L[2]);
+    }
+    int nb = 0;
+    for (size_t a = 0; a < k1s.size(); ++a) {
+        p->k1[a] = k1s[a];
+        p->bstart[a] = nb;
+        for (int v : k2s[a]) {
+            if (nb == max_pairs) return false;
+            p->k2[nb++] = v;
+        }
+    }
+    p->n1 = (int)k1s.size();
+    for (int a = p->n1; a <= kFacMaxK1; ++a) p->bstart[a] = nb;
+    p->n12 = nb;
+    for (int m = 0; m < mg.n; ++m) p->pair_of_m[m] = p->bstart[am[m]] + jm[m];
+    return true;
+}
+
+// Device copy of a factor plan, cached beside the phase tables.
+int factor_plan_table(const FactorPlan& plan, bool f64, hipStream_t st, const void** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    PhaseKey key;
+    key.dev = dev;
+    for (int j = 0; j < 3; ++j) {
+        key.L[j] = plan.L[j];
+        key.r[j] = 0;
+    }
+    key.sigma = plan.sigma;
+    key.mode = 100 + (f64 ? 1 : 0);
+    key.mtmax = 0;
+    const int* words = (const int*)&plan;
+    key.k.assign(words, words + sizeof(FactorPlan) / sizeof(int));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_phase.find(key);
+    if (it != g_phase.end()) {
+        it->second.last_use = ++g_phase_clock;
+        if (hipStreamWaitEvent(st, it->second.ready, 0) != hipSuccess)
+            return fail(C3PT_EDEVICE, "waiting for the factor plan failed");
+        *out = it->second.ptr;
+        return C3PT_OK;
+    }
+    PhaseEntry e;
+    e.bytes = sizeof(FactorPlan);
+    if (hipMalloc(&e.ptr, e.bytes) != hipSuccess ||
+        hipHostMalloc(&e.pinned, e.bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        free_phase_entry(e);
+        return fail(C3PT_ENOMEM, "factor plan allocation failed");
+    }
+    g_phase_bytes += e.bytes;
+    memcpy(e.pinned, &plan, e.bytes);
+    if (hipMemcpyAsync(e.ptr, e.pinned, e.bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventCreateWithFlags(&e.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(e.ready, st) != hipSuccess) {
+        free_phase_entry(e);
+        return fail(C3PT_EDEVICE, "uploading the factor plan failed");
+    }
+    e.last_use = ++g_phase_clock;
+    g_phase[key] = e;
+    *out = e.ptr;
+    return C3PT_OK;
+}
+
+// x3 planes per chunk of the factored projection: enough chunks to give the
+// chip several workgroups per CU.
+void plan_planes(int L3, int n_colblocks, int* chunk_planes, int* n_chunks) {
+    int chunks = std::max(1, (1024 + n_colblocks - 1) / n_colblocks);
+    chunks = std::min(chunks, L3);
+    *chunk_planes = (L3 + chunks - 1) / chunks;
+    *n_chunks = (L3 + *chunk_planes - 1) / *chunk_planes;
+}
+
 // Sites per split-site chunk: enough chunks to fill the chip, never more than
 // kMaxSitesPerChunkF32 sites in one FP32 partial sum.
 void plan_chunks(int V3, int n_colblocks, bool f64, int* chunk_sites, int* n_chunks) {
@@ -322,6 +427,8 @@ int to_status(hipError_t e, const char* what) {
     return fail(C3PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+const char* const fac_names[3] = {"fac_spectator_meson", "fac_spectator_baryon", "fac_insertion"};
+
 // Runs projection launches over momentum groups and reduces each into `out`.
 // `launch(pg, mt)` enqueues one fused kernel for the grid pg.
 template <class Launch>
@@ -333,21 +440,38 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
     const int mode = proj_mode(g);
     const int V3 = g->L[0] * g->L[1] * g->L[2];
     auto groups = momentum_groups(n_mom, f64);
-    int chunk_sites, n_chunks;
-    plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks);
+    const bool want_fac = g->proj == C3PT_PROJ_FACTORED;
+    int chunk_sites, n_chunks_dense, chunk_planes, n_chunks_fac;
+    plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks_dense);
+    plan_planes(g->L[2], n_colblocks, &chunk_planes, &n_chunks_fac);
     const size_t gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
-    const size_t bytes = (size_t)n_chunks * n_colblocks * gmax * kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));
+    const size_t bytes = (size_t)std::max(n_chunks_dense, want_fac ? std::max(n_chunks_fac, g->L[2]) : 0) *
+                         n_colblocks * gmax * kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));
     void* part;
     if (int rc = scratch_dev(st, bytes, &part)) return rc;
     for (const MomGroup& mg : groups) {
         const int mt = (mg.n + 7) / 8;
         const int mtmax = f64 ? 4 : (mt <= 4 ? 4 : mt <= 8 ? 8 : mt <= 12 ? 12 : 16);
+        FactorPlan plan;
+        const bool fac = want_fac && build_factor_plan(g, sigma, k, mg, f64, &plan);
         const void* tab;
-        if (int rc = phase_table(g, sigma, mode, mtmax, k, mg, st, &tab)) return rc;
+        if (fac) {
+            if (int rc = factor_plan_table(plan, f64, st, &tab)) return rc;
+        } else if (int rc = phase_table(g, sigma, mode, mtmax, k, mg, st, &tab)) {
+            return rc;
+        }
+        int fac_variant;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            fac_variant = g_variant[kind][kModeFacVariants][mt_class(mt)];
+        }
+        const bool fac_acc = fac && fac_variant == 1 && chunk_planes > 1;
+        const int n_chunks = fac ? (fac_acc ? n_chunks_fac : g->L[2]) : n_chunks_dense;
         ProjGrid pg;
         pg.V3 = V3;
         pg.n_mom = mg.n;
         pg.chunk_sites = chunk_sites;
+        pg.chunk_planes = fac_acc ? chunk_planes : 1;
         pg.n_chunks = n_chunks;
         pg.n_colblocks = n_colblocks;
         pg.n_share = n_share;
@@ -359,7 +483,9 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
             std::lock_guard<std::mutex> lk(g_mu);
             variant = g_variant[kind][mode][mt_class(mt)];
         }
-        if (int rc = to_status(timed(kname, st, [&] { return launch(mode, pg, mt, variant); }), "projection launch"))
+        if (int rc = to_status(timed(fac ? fac_names[kind] : kname, st,
+                                     [&] { return launch(mode, pg, mt, variant, fac); }),
+                               "projection launch"))
             return rc;
         ReduceArgs ra;
         ra.partial = part;
@@ -512,8 +638,10 @@ int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* et
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     MesonSpecArgs a{{geom->L[0], geom->L[1], geom->L[2]}, G_tf, eta};
     int rc = run_projection("proj_spectator_meson", 0, geom, -1, k, n_mom, n_noise, 1, n_noise, kBlockCols,
-                            n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
-                                return launch_spectator_meson(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
+                            n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
+                                hipStream_t st = (hipStream_t)geom->stream;
+                                return fac ? launch_fac_meson(geom->dtype == C3PT_C128, pg, a, st)
+                                           : launch_spectator_meson(mode, mt, variant, pg, a, st);
                             });
     return rc ? rc : ok();
 }
@@ -526,8 +654,10 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     BaryonSpecArgs a{{geom->L[0], geom->L[1], geom->L[2]}, G1_tf, G2_tf, eta};
     int rc = run_projection("proj_spectator_baryon", 1, geom, -1, k, n_mom, n_noise * 16, 1, n_noise * 16, 3072,
-                            n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
-                                return launch_spectator_baryon(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
+                            n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
+                                hipStream_t st = (hipStream_t)geom->stream;
+                                return fac ? launch_fac_baryon(geom->dtype == C3PT_C128, pg, a, st)
+                                           : launch_spectator_baryon(mode, mt, variant, pg, a, st);
                             });
     return rc ? rc : ok();
 }
@@ -577,8 +707,10 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
         }
         const int ncb = n_noise * nt * n_ops;
         int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_ops, kBlockCols, ncb,
-                                nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant) {
-                                    return launch_insertion(mode, mt, variant, pg, a, (hipStream_t)geom->stream);
+                                nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
+                                    hipStream_t st = (hipStream_t)geom->stream;
+                                    return fac ? launch_fac_insertion(geom->dtype == C3PT_C128, pg, a, st)
+                                               : launch_insertion(mode, mt, variant, pg, a, st);
                                 });
         if (rc) return rc;
     }

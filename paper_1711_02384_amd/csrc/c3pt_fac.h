@@ -1,0 +1,280 @@
+// Factored momentum projection for gfx950 (MI355X).
+//
+// The phase of Eqs. (9)-(10) factorizes over the three directions,
+//   exp(sigma 2 pi i k.x / L) = w1^(k1 x1) w2^(k2 x2) w3^(k3 x3),  w_j = exp(sigma 2 pi i / L_j),
+// so the projection of the contracted tensor P(x, c) onto a momentum list runs
+// as three nested partial sums instead of one dense (momenta x sites) GEMM:
+//   stage 1, per x1 row:    R1[a][c]  = sum_x1 w1^(K1[a] x1) P(x, c)   a over the distinct k1
+//   stage 2, per x3 plane:  R2[b][c] += w2^(k2_b x2) R1[a(b)][c]       b over the distinct (k1, k2)
+//   stage 3, per chunk:     S[m][c]  += w3^(k3_m x3) R2[b(m)][c]       m over the momenta
+// Stage 1 is a complex GEMM on the matrix cores (16 rows = 8 k1 values x
+// (re, im), K = (site, re/im) of a row segment); stages 2 and 3 are small
+// complex multiply-adds.  For a ball of momenta (|k|^2 <= 9: 7 k1 values,
+// 29 (k1, k2) pairs) this is about a tenth of the dense GEMM's arithmetic, and
+// no phase table is read: the workgroup keeps the three root-of-unity tables
+// in LDS.
+//
+// One workgroup owns one column block and one chunk of x3 planes.  Tiles are
+// KT consecutive sites of one x1 row (rows shorter than KT, or the last
+// segment of a row, contribute zeros beyond the row end).  Twelve waves, one
+// per 16-column tile; the producers (c3pt_producers.h) are the ones of the
+// dense kernels.  S is held in registers: thread t owns column t % 192 and the
+// momenta m = t / 192 + 4 i.  The chunk sums are written in the accumulator
+// type and reduced in FP64 with the source factor, as for the dense kernels.
+#pragma once
+
+#include <type_traits>
+
+#include "c3pt_producers.h"
+
+namespace c3pt {
+
+template <typename R> struct FacLimits;
+template <> struct FacLimits<float> {
+    static constexpr int kPairs = kFacMaxPairsF32;
+    static constexpr int kOut = kMaxMomGroupF32 / 4;
+};
+template <> struct FacLimits<double> {
+    static constexpr int kPairs = kFacMaxPairsF64;
+    static constexpr int kOut = kMaxMomGroupF64 / 4;
+};
+
+template <typename R, int KT>
+struct FacSmem {
+    static constexpr int PST = 2 * KT + 2;     // column stride of P (R elements); = 2 mod 32
+    static constexpr int KS = 2 * KT / 4;      // MFMA K steps per tile
+    R P[kBlockCols * PST];                     // P[col][2 * site + re/im]
+    R A1[KS][64];                              // stage-1 A operand of the current tile
+    C2<R> R2[FacLimits<R>::kPairs][kBlockCols];
+    C2<R> root[3][kMaxL];
+    FactorPlan plan;
+};
+
+template <typename R, int KT>
+struct FacSink {
+    R* P;
+    __device__ __forceinline__ void put(int col, int j, C2<R> v) {
+        *(C2<R>*)&P[col * FacSmem<R, KT>::PST + 2 * j] = v;
+    }
+};
+
+// Stage-1 A row r of a 16-row tile -> (k1 index a, part re/im), chosen so that
+// both accumulator layouts hold (re, im) of a = 2g, 2g+1 in registers (0,1), (2,3).
+template <typename R>
+__device__ __forceinline__ void fac_row(int r, int& a, int& part) {
+    if (Mfma<R>::kRowsByRegister) {
+        part = (r >> 2) & 1;
+        a = 2 * (r & 3) + (r >> 3);
+    } else {
+        part = r & 1;
+        a = r >> 1;
+    }
+}
+
+// Plan into LDS, root tables, R2 cleared.  Ends with a barrier.
+template <typename R, int KT>
+__device__ __forceinline__ void fac_setup(FacSmem<R, KT>& sm, const FactorPlan* gplan, int tid, int NT) {
+    const int* src = (const int*)gplan;
+    int* dst = (int*)&sm.plan;
+    for (int i = tid; i < (int)(sizeof(FactorPlan) / sizeof(int)); i += NT) dst[i] = src[i];
+    const int sigma = gplan->sigma;
+    for (int i = tid; i < 3 * kMaxL; i += NT) {
+        const int j = i / kMaxL, x = i % kMaxL;
+        const int L = gplan->L[j];
+        C2<R> w = {0, 0};
+        if (x < L) {
+            double s, c;
+            sincospi(2.0 * (double)x / (double)L, &s, &c);
+            w = {(R)c, (R)(sigma * s)};
+        }
+        sm.root[j][x] = w;
+    }
+    const int n12 = gplan->n12;
+    for (int i = tid; i < n12 * kBlockCols; i += NT) sm.R2[i / kBlockCols][i % kBlockCols] = C2<R>{0, 0};
+    __syncthreads();
+}
+
+// Partial-sum element type.
+template <typename R> using Part2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
+
+// Sum over the tiles of planes [p0, p1).  ACC: into out (thread-owned
+// momenta), written by fac_write at the end; otherwise every plane's sums are
+// written as their own chunk (chunk index = x3) and out is unused.
+template <typename R, int KT, bool ACC, class Prod>
+__device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const TileGeom& tg, FacSmem<R, KT>& sm,
+                                         typename Prod::Smem& psm, int p0, int p1,
+                                         C2<R> (&out)[FacLimits<R>::kOut], void* partial, int n_colblocks,
+                                         int cb, int tid) {
+    using MF = Mfma<R>;
+    using acc_t = typename MF::acc_t;
+    constexpr int NT = kFacThreads;
+    constexpr int KS = FacSmem<R, KT>::KS;
+    constexpr int PST = FacSmem<R, KT>::PST;
+    const int L1 = tg.L1, L2 = tg.L2, L3 = tg.L3;
+    const float inv1 = 1.0f / (float)L1, inv2 = 1.0f / (float)L2, inv3 = 1.0f / (float)L3;
+    const int nseg = (L1 + KT - 1) / KT;
+    const int n_tiles = (p1 - p0) * L2 * nseg;
+    const int lane = tid & 63, wave = tid >> 6, g = lane >> 4;
+    const int col = 16 * wave + (lane & 15);
+    const int n1 = sm.plan.n1, n_mom = sm.plan.n_mom;
+    // stage-3 ownership
+    const int c3 = tid % kBlockCols, q3 = tid / kBlockCols;
+
+    acc_t r1 = acc_t{0, 0, 0, 0};
+    typename Prod::Regs rg;
+    FacSink<R, KT> sink{sm.P};
+    auto tile_of = [&](int T, int& s, int& x2, int& x3) {
+        const int seg = T % nseg, row = T / nseg;
+        s = seg * KT;
+        x2 = row % L2;
+        x3 = p0 + row / L2;
+    };
+    if (n_tiles > 0) {
+        int s, x2, x3;
+        tile_of(0, s, x2, x3);
+        Prod::load(ctx, tg, s + L1 * (x2 + L2 * x3), min(KT, L1 - s), rg, tid);
+    }
+    for (int T = 0; T < n_tiles; ++T) {
+        int s, x2, x3;
+        tile_of(T, s, x2, x3);
+        const int nsite = min(KT, L1 - s);
+        // stage-1 A operand of this segment: value for (K step ks, lane al)
+        for (int e = tid; e < KS * 64; e += NT) {
+            const int ks = e >> 6, al = e & 63;
+            int a, part;
+            fac_row<R>(al & 15, a, part);
+            const int kk = al >> 4;
+            const int j = 2 * ks + (kk >> 1), comp = kk & 1;
+            R v = 0;
+            if (a < n1) {
+                const int x1 = s + j;
+                const C2<R> w = sm.root[0][mod_small(sm.plan.k1[a] * x1, L1, inv1)];
+                v = part == 0 ? (comp == 0 ? w.x : -w.y) : (comp == 0 ? w.y : w.x);
+            }
+            sm.A1[ks][al] = v;
+        }
+        Prod::store(ctx, tg, s + L1 * (x2 + L2 * x3), nsite, rg, psm, sink, tid);
+        if (T + 1 < n_tiles) {
+            int sn, x2n, x3n;
+            tile_of(T + 1, sn, x2n, x3n);
+            Prod::load(ctx, tg, sn + L1 * (x2n + L2 * x3n), min(KT, L1 - sn), rg, tid);
+        }
+        __syncthreads();
+        // stage 1
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) r1 = MF::mac(sm.A1[ks][lane], sm.P[col * PST + 4 * ks + g], r1);
+        const bool row_end = (s + KT >= L1);
+        if (row_end) {
+            // stage 2: this lane owns (k1 index 2g + h, column col)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int a = 2 * g + h;
+                if (a >= n1) continue;
+                const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
+                const int b1 = sm.plan.bstart[a + 1];
+                for (int b = sm.plan.bstart[a]; b < b1; ++b) {
+                    const C2<R> w = sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)];
+                    sm.R2[b][col] = cfma(sm.R2[b][col], w, v);
+                }
+            }
+            r1 = acc_t{0, 0, 0, 0};
+        }
+        __syncthreads();
+        if (row_end && x2 == L2 - 1) {
+            // stage 3: plane x3 done
+            if (ACC) {
+#pragma unroll
+                for (int i = 0; i < FacLimits<R>::kOut; ++i) {
+                    const int m = q3 + 4 * i;
+                    if (m < n_mom) {
+                        const int b = sm.plan.pair_of_m[m];
+                        const C2<R> w = sm.root[2][mod_small(sm.plan.k3[m] * x3, L3, inv3)];
+                        out[i] = cfma(out[i], w, sm.R2[b][c3]);
+                    }
+                }
+            } else {
+                Part2<R>* part = (Part2<R>*)partial;
+                const size_t base = ((size_t)x3 * n_colblocks + cb) * (size_t)n_mom;
+                for (int m = q3; m < n_mom; m += 4) {
+                    const int b = sm.plan.pair_of_m[m];
+                    const C2<R> w = sm.root[2][mod_small(sm.plan.k3[m] * x3, L3, inv3)];
+                    const C2<R> v = cmul(w, sm.R2[b][c3]);
+                    part[(base + m) * kBlockCols + c3] = Part2<R>{v.x, v.y};
+                }
+            }
+            __syncthreads();
+            const int n12 = sm.plan.n12;
+            for (int i = tid; i < n12 * kBlockCols; i += NT) sm.R2[i / kBlockCols][i % kBlockCols] = C2<R>{0, 0};
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void fac_write(void* partial, int n_colblocks, int n_mom, int chunk, int cb,
+                                          const C2<R> (&out)[FacLimits<R>::kOut], int tid) {
+    using P2 = Part2<R>;
+    P2* part = (P2*)partial;
+    const int c = tid % kBlockCols, q = tid / kBlockCols;
+    const size_t base = ((size_t)chunk * n_colblocks + cb) * (size_t)n_mom;
+#pragma unroll
+    for (int i = 0; i < FacLimits<R>::kOut; ++i) {
+        const int m = q + 4 * i;
+        if (m < n_mom) part[(base + m) * kBlockCols + c] = P2{out[i].x, out[i].y};
+    }
+}
+
+template <typename R, int KT, bool ACC, template <typename, int, int> class ProdT>
+__global__ void __launch_bounds__(kFacThreads, 1)
+fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
+    using Prod = ProdT<R, KT, kFacThreads>;
+    __shared__ FacSmem<R, KT> sm;
+    __shared__ typename Prod::Smem psm;
+    const int tid = threadIdx.x;
+    // work item; consecutive items (same input slice and chunk) on one XCD
+    const int nw = gridDim.x, w = blockIdx.x;
+    const int full = (nw / 8) * 8;
+    const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
+    const int within = item % pg.n_per_share;
+    const int rest = item / pg.n_per_share;
+    const int chunk = rest % pg.n_chunks;
+    const int share = rest / pg.n_chunks;
+    const int cb = Prod::colblock(pa, share, within);
+    const typename Prod::Ctx ctx = Prod::resolve(pa, pg.V3, cb);
+    TileGeom tg;
+    tg.V3 = pg.V3;
+    tg.L1 = pa.L[0];
+    tg.L2 = pa.L[1];
+    tg.L3 = pa.L[2];
+    tg.inv1 = 1.0f / (float)tg.L1;
+    tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+    fac_setup<R, KT>(sm, (const FactorPlan*)pg.phase, tid, kFacThreads);
+    C2<R> out[FacLimits<R>::kOut];
+    if (ACC) {
+#pragma unroll
+        for (int i = 0; i < FacLimits<R>::kOut; ++i) out[i] = C2<R>{0, 0};
+    }
+    const int p0 = chunk * pg.chunk_planes;
+    const int p1 = min(tg.L3, p0 + pg.chunk_planes);
+    fac_loop<R, KT, ACC, Prod>(ctx, tg, sm, psm, p0, p1, out, pg.partial, pg.n_colblocks, cb, tid);
+    if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
+}
+
+template <typename R, int KT, bool ACC, template <typename, int, int> class ProdT>
+hipError_t launch_fac_kt(const ProjGrid& pg, const typename ProdT<R, KT, kFacThreads>::Args& a, hipStream_t st) {
+    hipLaunchKernelGGL((fac_kernel<R, KT, ACC, ProdT>), dim3(pg.n_colblocks * pg.n_chunks), dim3(kFacThreads), 0,
+                       st, pg, a);
+    return hipGetLastError();
+}
+
+// FP32: 32-site tiles when whole rows split into them, else 16; FP64: 16.
+// chunk_planes == 1 selects the form without register accumulation.
+template <template <typename, int, int> class ProdT, class Args>
+hipError_t launch_fac(bool f64, const ProjGrid& pg, const Args& a, hipStream_t st) {
+    const bool acc = pg.chunk_planes > 1;
+    if (f64) return acc ? launch_fac_kt<double, 16, true, ProdT>(pg, a, st) : launch_fac_kt<double, 16, false, ProdT>(pg, a, st);
+    if (a.L[0] % 32 == 0)
+        return acc ? launch_fac_kt<float, 32, true, ProdT>(pg, a, st) : launch_fac_kt<float, 32, false, ProdT>(pg, a, st);
+    return acc ? launch_fac_kt<float, 16, true, ProdT>(pg, a, st) : launch_fac_kt<float, 16, false, ProdT>(pg, a, st);
+}
+
+}  // namespace c3pt

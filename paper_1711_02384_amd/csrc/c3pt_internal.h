@@ -32,6 +32,26 @@ struct PhaseSpec {
     uint8_t k[3][kMaxMomGroup];   // components reduced into [0, L_j)
 };
 
+// Factored projection (per-direction partial sums).  The phase factorizes,
+// exp(i p.x) = w1^(k1 x1) w2^(k2 x2) w3^(k3 x3) with w_j = exp(sigma 2 pi i / L_j),
+// so the site sum runs in three stages: over x1 for each distinct k1 (an MFMA
+// GEMM), over x2 for each distinct (k1, k2) pair, over x3 for each momentum.
+constexpr int kFacTile = 16;          // sites per tile: a segment of one x1 row
+constexpr int kFacThreads = 768;      // 12 waves, one 16-column tile each
+constexpr int kFacMaxK1 = 8;          // distinct k1: one MFMA row tile (8 x (re, im))
+constexpr int kFacMaxPairsF32 = 48;   // distinct (k1, k2) pairs held in LDS
+constexpr int kFacMaxPairsF64 = 24;
+struct FactorPlan {
+    int L[3];
+    int sigma;
+    int n_mom, n1, n12;
+    int k1[kFacMaxK1];                // distinct k1 (reduced mod L1); index a
+    int bstart[kFacMaxK1 + 1];        // pairs of k1 index a: b in [bstart[a], bstart[a+1])
+    int k2[kFacMaxPairsF32];          // k2 of pair b (reduced mod L2)
+    int pair_of_m[kMaxMomGroup];      // pair b of momentum m
+    int k3[kMaxMomGroup];             // k3 of momentum m (reduced mod L3)
+};
+
 // One launch of the fused contraction + projection kernel.  Work items are
 // (share, chunk, within) with column block cb = colblock(share, within):
 // items that read the same input slice (same share) and chunk are issued to
@@ -43,9 +63,11 @@ struct ProjGrid {
     int n_chunks;
     int n_colblocks;
     int n_share, n_per_share;
-    const void* phase; // phase table of the group (origin r = 0), in the consumer's layout
+    const void* phase; // phase table of the group (origin r = 0), in the consumer's layout;
+                       // factored launches: the FactorPlan of the group
     void* partial;     // [n_chunks][n_colblocks][n_mom][192] partial sums in the accumulator type
                        // (complex float; complex double for complex128 inputs)
+    int chunk_planes;  // factored launches: x3 planes per chunk (chunk_sites unused)
 };
 
 // Producer arguments -------------------------------------------------------
@@ -160,6 +182,10 @@ hipError_t launch_spectator_baryon(int mode, int mt, int variant, const ProjGrid
 hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, const InsertionArgs& a,
                             hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+// Factored projection launches (f64: complex128 inputs, FP64 MFMA; else FP32).
+hipError_t launch_fac_meson(bool f64, const ProjGrid& pg, const MesonSpecArgs& a, hipStream_t st);
+hipError_t launch_fac_baryon(bool f64, const ProjGrid& pg, const BaryonSpecArgs& a, hipStream_t st);
+hipError_t launch_fac_insertion(bool f64, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st);
 // Persistent batch launch of one producer kind; with bg == nullptr only the
 // occupancy (workgroups per CU) of the variant is returned.
 int batch_meson(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
