@@ -331,7 +331,10 @@ bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGro
             k2s.emplace_back();
         }
         int jj = (int)(std::find(k2s[a].begin(), k2s[a].end(), r2) - k2s[a].begin());
-        if (jj == (int)k2s[a].size()) k2s[a].push_back(r2);
+        if (jj == (int)k2s[a].size()) {
+            if ((int)k2s[a].size() == kFacMaxBPerA) return false;
+            k2s[a].push_back(r2);
+        }
         am[m] = a;
         jm[m] = jj;
         p->k3[m] = posmod(km[2], g->L[2]);
@@ -693,6 +696,8 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
         a.n_tau = nt;
         a.n_ops = n_ops;
         a.n_noise = n_noise;
+        a.op_lo = 0;
+        a.op_cnt = n_ops;
         for (int j = 0; j < nt; ++j) {
             const int t = taus[j0 + j];
             const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
@@ -709,8 +714,23 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
         int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_ops, kBlockCols, ncb,
                                 nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
                                     hipStream_t st = (hipStream_t)geom->stream;
-                                    return fac ? launch_fac_insertion(geom->dtype == C3PT_C128, pg, a, st)
-                                               : launch_insertion(mode, mt, variant, pg, a, st);
+                                    if (!fac) return launch_insertion(mode, mt, variant, pg, a, st);
+                                    // local and derivative operators in separate launches (each
+                                    // kernel keeps only its own path's registers)
+                                    const bool f64 = geom->dtype == C3PT_C128;
+                                    InsertionArgs al = a;
+                                    al.op_lo = 0;
+                                    al.op_cnt = 1;
+                                    ProjGrid pl = pg;
+                                    pl.n_per_share = n_noise;
+                                    hipError_t e = launch_fac_insertion(f64, 1, pl, al, st);
+                                    if (e != hipSuccess || n_ops == 1) return e;
+                                    InsertionArgs ad = a;
+                                    ad.op_lo = 1;
+                                    ad.op_cnt = 4;
+                                    ProjGrid pd = pg;
+                                    pd.n_per_share = n_noise * 4;
+                                    return launch_fac_insertion(f64, 2, pd, ad, st);
                                 });
         if (rc) return rc;
     }

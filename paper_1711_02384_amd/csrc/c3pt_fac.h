@@ -33,10 +33,12 @@ template <typename R> struct FacLimits;
 template <> struct FacLimits<float> {
     static constexpr int kPairs = kFacMaxPairsF32;
     static constexpr int kOut = kMaxMomGroupF32 / 4;
+    static constexpr int kSegs = 4;            // row segments whose A operands are kept in LDS
 };
 template <> struct FacLimits<double> {
     static constexpr int kPairs = kFacMaxPairsF64;
     static constexpr int kOut = kMaxMomGroupF64 / 4;
+    static constexpr int kSegs = 1;
 };
 
 template <typename R, int KT>
@@ -44,8 +46,11 @@ struct FacSmem {
     static constexpr int PST = 2 * KT + 2;     // column stride of P (R elements); = 2 mod 32
     static constexpr int KS = 2 * KT / 4;      // MFMA K steps per tile
     R P[kBlockCols * PST];                     // P[col][2 * site + re/im]
-    R A1[KS][64];                              // stage-1 A operand of the current tile
-    C2<R> R2[FacLimits<R>::kPairs][kBlockCols];
+    // stage-1 A operands [segment][K step][lane]: all segments of a row when
+    // they fit (filled once per work item), else the current tile's (slot 0)
+    R A1[FacLimits<R>::kSegs][KS][64];
+    C2<R> R2[FacLimits<R>::kPairs][kBlockCols];   // stage-2 sums of a plane, gathered for stage 3
+    C2<R> coef2[FacLimits<R>::kPairs];            // w2^(k2_b x2) of the current row
     C2<R> root[3][kMaxL];
     FactorPlan plan;
 };
@@ -89,9 +94,19 @@ __device__ __forceinline__ void fac_setup(FacSmem<R, KT>& sm, const FactorPlan* 
         }
         sm.root[j][x] = w;
     }
-    const int n12 = gplan->n12;
-    for (int i = tid; i < n12 * kBlockCols; i += NT) sm.R2[i / kBlockCols][i % kBlockCols] = C2<R>{0, 0};
     __syncthreads();
+}
+
+// Stage-1 A operand of row segment s: value for (K step ks, lane al).
+template <typename R, int KT>
+__device__ __forceinline__ R fac_a1(const FacSmem<R, KT>& sm, int s, int ks, int al, int L1, float inv1) {
+    int a, part;
+    fac_row<R>(al & 15, a, part);
+    const int kk = al >> 4;
+    const int j = 2 * ks + (kk >> 1), comp = kk & 1;
+    if (a >= sm.plan.n1) return (R)0;
+    const C2<R> w = sm.root[0][mod_small(sm.plan.k1[a] * (s + j), L1, inv1)];
+    return part == 0 ? (comp == 0 ? w.x : -w.y) : (comp == 0 ? w.y : w.x);
 }
 
 // Partial-sum element type.
@@ -113,75 +128,93 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     const int L1 = tg.L1, L2 = tg.L2, L3 = tg.L3;
     const float inv1 = 1.0f / (float)L1, inv2 = 1.0f / (float)L2, inv3 = 1.0f / (float)L3;
     const int nseg = (L1 + KT - 1) / KT;
+    const bool a1_all = nseg <= FacLimits<R>::kSegs;
     const int n_tiles = (p1 - p0) * L2 * nseg;
     const int lane = tid & 63, wave = tid >> 6, g = lane >> 4;
     const int col = 16 * wave + (lane & 15);
-    const int n1 = sm.plan.n1, n_mom = sm.plan.n_mom;
+    const int n_mom = sm.plan.n_mom, n12 = sm.plan.n12;
+    // stage-2 ownership: k1 indices 2g, 2g+1 of column col, their pairs in registers
+    int bs[2], nb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int a = 2 * g + h;
+        bs[h] = a < sm.plan.n1 ? sm.plan.bstart[a] : 0;
+        nb[h] = a < sm.plan.n1 ? sm.plan.bstart[a + 1] - bs[h] : 0;
+    }
+    C2<R> r2[2][kFacMaxBPerA];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < kFacMaxBPerA; ++i) r2[h][i] = C2<R>{0, 0};
     // stage-3 ownership
     const int c3 = tid % kBlockCols, q3 = tid / kBlockCols;
 
+    if (a1_all) {
+        for (int e = tid; e < nseg * KS * 64; e += NT) {
+            const int seg = e / (KS * 64), rem = e % (KS * 64);
+            sm.A1[seg][rem >> 6][rem & 63] = fac_a1<R, KT>(sm, seg * KT, rem >> 6, rem & 63, L1, inv1);
+        }
+    }
     acc_t r1 = acc_t{0, 0, 0, 0};
     typename Prod::Regs rg;
     FacSink<R, KT> sink{sm.P};
-    auto tile_of = [&](int T, int& s, int& x2, int& x3) {
-        const int seg = T % nseg, row = T / nseg;
-        s = seg * KT;
+    auto tile_of = [&](int T, int& seg, int& x2, int& x3) {
+        seg = T % nseg;
+        const int row = T / nseg;
         x2 = row % L2;
         x3 = p0 + row / L2;
     };
     if (n_tiles > 0) {
-        int s, x2, x3;
-        tile_of(0, s, x2, x3);
-        Prod::load(ctx, tg, s + L1 * (x2 + L2 * x3), min(KT, L1 - s), rg, tid);
+        int seg, x2, x3;
+        tile_of(0, seg, x2, x3);
+        Prod::load(ctx, tg, seg * KT + L1 * (x2 + L2 * x3), min(KT, L1 - seg * KT), rg, tid);
     }
     for (int T = 0; T < n_tiles; ++T) {
-        int s, x2, x3;
-        tile_of(T, s, x2, x3);
+        int seg, x2, x3;
+        tile_of(T, seg, x2, x3);
+        const int s = seg * KT;
         const int nsite = min(KT, L1 - s);
-        // stage-1 A operand of this segment: value for (K step ks, lane al)
-        for (int e = tid; e < KS * 64; e += NT) {
-            const int ks = e >> 6, al = e & 63;
-            int a, part;
-            fac_row<R>(al & 15, a, part);
-            const int kk = al >> 4;
-            const int j = 2 * ks + (kk >> 1), comp = kk & 1;
-            R v = 0;
-            if (a < n1) {
-                const int x1 = s + j;
-                const C2<R> w = sm.root[0][mod_small(sm.plan.k1[a] * x1, L1, inv1)];
-                v = part == 0 ? (comp == 0 ? w.x : -w.y) : (comp == 0 ? w.y : w.x);
-            }
-            sm.A1[ks][al] = v;
-        }
+        const bool row_end = (seg == nseg - 1);
+        if (!a1_all)
+            for (int e = tid; e < KS * 64; e += NT) sm.A1[0][e >> 6][e & 63] = fac_a1<R, KT>(sm, s, e >> 6, e & 63, L1, inv1);
+        if (row_end)
+            for (int b = tid; b < n12; b += NT) sm.coef2[b] = sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)];
         Prod::store(ctx, tg, s + L1 * (x2 + L2 * x3), nsite, rg, psm, sink, tid);
         if (T + 1 < n_tiles) {
             int sn, x2n, x3n;
             tile_of(T + 1, sn, x2n, x3n);
-            Prod::load(ctx, tg, sn + L1 * (x2n + L2 * x3n), min(KT, L1 - sn), rg, tid);
+            Prod::load(ctx, tg, sn * KT + L1 * (x2n + L2 * x3n), min(KT, L1 - sn * KT), rg, tid);
         }
         __syncthreads();
         // stage 1
+        const int slot = a1_all ? seg : 0;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) r1 = MF::mac(sm.A1[ks][lane], sm.P[col * PST + 4 * ks + g], r1);
-        const bool row_end = (s + KT >= L1);
+        for (int ks = 0; ks < KS; ++ks) r1 = MF::mac(sm.A1[slot][ks][lane], sm.P[col * PST + 4 * ks + g], r1);
         if (row_end) {
-            // stage 2: this lane owns (k1 index 2g + h, column col)
+            // stage 2, in registers
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int a = 2 * g + h;
-                if (a >= n1) continue;
                 const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
-                const int b1 = sm.plan.bstart[a + 1];
-                for (int b = sm.plan.bstart[a]; b < b1; ++b) {
-                    const C2<R> w = sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)];
-                    sm.R2[b][col] = cfma(sm.R2[b][col], w, v);
-                }
+#pragma unroll
+                for (int i = 0; i < kFacMaxBPerA; ++i)
+                    if (i < nb[h]) r2[h][i] = cfma(r2[h][i], sm.coef2[bs[h] + i], v);
             }
             r1 = acc_t{0, 0, 0, 0};
+            if (x2 == L2 - 1) {
+                // plane x3 done: gather the stage-2 sums for stage 3
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int i = 0; i < kFacMaxBPerA; ++i)
+                        if (i < nb[h]) {
+                            sm.R2[bs[h] + i][col] = r2[h][i];
+                            r2[h][i] = C2<R>{0, 0};
+                        }
+            }
         }
         __syncthreads();
         if (row_end && x2 == L2 - 1) {
-            // stage 3: plane x3 done
+            // stage 3
             if (ACC) {
 #pragma unroll
                 for (int i = 0; i < FacLimits<R>::kOut; ++i) {
@@ -202,9 +235,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
                     part[(base + m) * kBlockCols + c3] = Part2<R>{v.x, v.y};
                 }
             }
-            __syncthreads();
-            const int n12 = sm.plan.n12;
-            for (int i = tid; i < n12 * kBlockCols; i += NT) sm.R2[i / kBlockCols][i % kBlockCols] = C2<R>{0, 0};
+            // R2 is rewritten only at the next plane end, after further barriers
         }
     }
 }
@@ -261,18 +292,19 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
 
 template <typename R, int KT, bool ACC, template <typename, int, int> class ProdT>
 hipError_t launch_fac_kt(const ProjGrid& pg, const typename ProdT<R, KT, kFacThreads>::Args& a, hipStream_t st) {
-    hipLaunchKernelGGL((fac_kernel<R, KT, ACC, ProdT>), dim3(pg.n_colblocks * pg.n_chunks), dim3(kFacThreads), 0,
+    hipLaunchKernelGGL((fac_kernel<R, KT, ACC, ProdT>), dim3(pg.n_share * pg.n_per_share * pg.n_chunks), dim3(kFacThreads), 0,
                        st, pg, a);
     return hipGetLastError();
 }
 
-// FP32: 32-site tiles when whole rows split into them, else 16; FP64: 16.
-// chunk_planes == 1 selects the form without register accumulation.
+// FP32: 32-site tiles when whole rows split into them (and the producer fits
+// its registers at that size), else 16; FP64: 16.  chunk_planes == 1 selects
+// the form without register accumulation.
 template <template <typename, int, int> class ProdT, class Args>
-hipError_t launch_fac(bool f64, const ProjGrid& pg, const Args& a, hipStream_t st) {
+hipError_t launch_fac(bool f64, const ProjGrid& pg, const Args& a, hipStream_t st, bool allow32 = true) {
     const bool acc = pg.chunk_planes > 1;
     if (f64) return acc ? launch_fac_kt<double, 16, true, ProdT>(pg, a, st) : launch_fac_kt<double, 16, false, ProdT>(pg, a, st);
-    if (a.L[0] % 32 == 0)
+    if (allow32 && a.L[0] % 32 == 0)
         return acc ? launch_fac_kt<float, 32, true, ProdT>(pg, a, st) : launch_fac_kt<float, 32, false, ProdT>(pg, a, st);
     return acc ? launch_fac_kt<float, 16, true, ProdT>(pg, a, st) : launch_fac_kt<float, 16, false, ProdT>(pg, a, st);
 }

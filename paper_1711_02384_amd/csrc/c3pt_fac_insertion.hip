@@ -4,8 +4,9 @@
 
 namespace c3pt {
 
-hipError_t launch_fac_insertion(bool f64, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st) {
-    return launch_fac<InsertionProducer>(f64, pg, a, st);
+hipError_t launch_fac_insertion(bool f64, int ops, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st) {
+    return ops == 1 ? launch_fac<InsertionLocalProducer>(f64, pg, a, st)
+                    : launch_fac<InsertionDerivProducer>(f64, pg, a, st, false);
 }
 
 }  // namespace c3pt

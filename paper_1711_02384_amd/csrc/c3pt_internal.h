@@ -40,7 +40,8 @@ constexpr int kFacTile = 16;          // sites per tile: a segment of one x1 row
 constexpr int kFacThreads = 768;      // 12 waves, one 16-column tile each
 constexpr int kFacMaxK1 = 8;          // distinct k1: one MFMA row tile (8 x (re, im))
 constexpr int kFacMaxPairsF32 = 48;   // distinct (k1, k2) pairs held in LDS
-constexpr int kFacMaxPairsF64 = 24;
+constexpr int kFacMaxPairsF64 = 16;
+constexpr int kFacMaxBPerA = 8;       // distinct k2 per k1 (per-lane registers of stage 2)
 struct FactorPlan {
     int L[3];
     int sigma;
@@ -89,6 +90,7 @@ struct InsertionArgs {
     int n_tau;         // timeslices in this launch
     int n_ops;         // 1 or 5
     int n_noise;
+    int op_lo, op_cnt; // operators covered by this launch's work items: [op_lo, op_lo + op_cnt)
     const void* G[kMaxTauPerLaunch];     // G(tau)
     const void* Gn[kMaxTauPerLaunch];    // G(tau+1)  (derivative ops only)
     const void* Gp[kMaxTauPerLaunch];    // G(tau-1)
@@ -185,7 +187,8 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 // Factored projection launches (f64: complex128 inputs, FP64 MFMA; else FP32).
 hipError_t launch_fac_meson(bool f64, const ProjGrid& pg, const MesonSpecArgs& a, hipStream_t st);
 hipError_t launch_fac_baryon(bool f64, const ProjGrid& pg, const BaryonSpecArgs& a, hipStream_t st);
-hipError_t launch_fac_insertion(bool f64, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st);
+// ops: 1 local operator only, 2 derivative operators only (a.op_lo / a.op_cnt select them)
+hipError_t launch_fac_insertion(bool f64, int ops, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st);
 // Persistent batch launch of one producer kind; with bg == nullptr only the
 // occupancy (workgroups per CU) of the variant is returned.
 int batch_meson(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);

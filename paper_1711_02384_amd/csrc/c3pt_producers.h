@@ -222,8 +222,11 @@ struct BaryonSpecProducer {
 // P = sum_d t+[at][d] G(y+nu)[(bt,d)][(b,c)] - t-[at][d] G(y-nu)[(bt,d)][(b,c)].
 // Task (site j, q = bt*12 + b*3 + c) computes the four at columns.
 // ---------------------------------------------------------------------------
-template <typename R, int KT, int NT>
-struct InsertionProducer {
+// OPS selects the operators a kernel instantiation handles: 0 both (column
+// blocks decide), 1 the local operator only, 2 the derivative operators only.
+// Single-kind instantiations keep only the registers of their path.
+template <typename R, int KT, int NT, int OPS>
+struct InsertionProducerT {
     using Args = InsertionArgs;
     static_assert(NT % KT == 0, "every thread keeps one site of the tile");
     static constexpr int kV = PerThread<12 * KT, NT>::value;
@@ -236,10 +239,12 @@ struct InsertionProducer {
         const C2<R>* Um;    // U_nu(y - nu) (time: slice tau - 1)
         int nu;             // -1 for the local operator
     };
+    static constexpr int kG = OPS == 1 ? 3 : 6;
+    static constexpr int kU = OPS == 1 ? 1 : 6;
     struct Regs {
         C2<R> v[kV];        // s entries
-        C2<R> u[kV][6];     // transport task: U(y)[c][d], U(y-nu)[d][c] for c = 0..2
-        C2<R> g[kT][6];     // G entries: local uses [0..2]; derivative (y+nu)[0..2], (y-nu)[3..5]
+        C2<R> u[kV][kU];    // transport task: U(y)[c][d], U(y-nu)[d][c] for c = 0..2
+        C2<R> g[kT][kG];    // G entries: local uses [0..2]; derivative (y+nu)[0..2], (y-nu)[3..5]
     };
     struct Smem {
         C2<R> v[12][KT];
@@ -247,8 +252,9 @@ struct InsertionProducer {
         C2<R> tm[12][KT];
     };
     // work items that share a timeslice (share) are adjacent: within = noise * n_ops + op
+    // work items of one launch cover operators [a.op_lo, a.op_lo + a.op_cnt)
     static __device__ __forceinline__ int colblock(const Args& a, int share, int within) {
-        const int noise = within / a.n_ops, op = within % a.n_ops;
+        const int noise = within / a.op_cnt, op = a.op_lo + within % a.op_cnt;
         return (noise * a.n_tau + share) * a.n_ops + op;
     }
     static __device__ __forceinline__ Ctx make(const void* G, const void* Gn, const void* Gp, const void* s,
@@ -290,7 +296,7 @@ struct InsertionProducer {
             const int e = tid + i * NT, A = e / KT;
             rg.v[i] = (e < 12 * KT && site_ok) ? c.s[(size_t)A * V3 + n] : C2<R>{0, 0};
         }
-        if (c.nu < 0) {
+        if (OPS == 1 || (OPS == 0 && c.nu < 0)) {
 #pragma unroll
             for (int i = 0; i < kT; ++i) {
                 const int e = tid + i * NT, q = e / KT;
@@ -302,6 +308,7 @@ struct InsertionProducer {
             }
             return;
         }
+        if constexpr (OPS != 1) {
         const int nu = c.nu;
         int np = n, nm = n;
         if (nu < 3) {
@@ -335,6 +342,7 @@ struct InsertionProducer {
                 rg.g[i][3 + d] = ok ? c.Gb[plane + nm] : C2<R>{0, 0};
             }
         }
+        }
     }
     template <class Sink>
     static __device__ __forceinline__ void store(const Ctx& c, const TileGeom&, int, int, const Regs& rg, Smem& sm,
@@ -349,7 +357,7 @@ struct InsertionProducer {
             }
         }
         __syncthreads();
-        if (c.nu < 0) {
+        if (OPS == 1 || (OPS == 0 && c.nu < 0)) {
 #pragma unroll
             for (int i = 0; i < kT; ++i) {
                 const int e = tid + i * NT, q = e / KT;
@@ -364,6 +372,7 @@ struct InsertionProducer {
             }
             return;
         }
+        if constexpr (OPS != 1) {
         // t+[at][d] = 1/2 sum_c v[at][c] U(y)[c][d];  t-[at][d] = 1/2 sum_c v[at][c] conj(U(y-nu)[d][c])
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
@@ -396,7 +405,15 @@ struct InsertionProducer {
                 sink.put(at * 48 + q, j, p);
             }
         }
+        }
     }
 };
+
+template <typename R, int KT, int NT>
+using InsertionProducer = InsertionProducerT<R, KT, NT, 0>;
+template <typename R, int KT, int NT>
+using InsertionLocalProducer = InsertionProducerT<R, KT, NT, 1>;
+template <typename R, int KT, int NT>
+using InsertionDerivProducer = InsertionProducerT<R, KT, NT, 2>;
 
 }  // namespace c3pt
