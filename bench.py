@@ -512,7 +512,8 @@ class Batch64:
         return tot
 
     def kernel_flops(self):
-        return {"batch_proj_" + kn: f for kn, f in self.flops.items()}
+        prefix = "batch_fac_" if self.proj == 3 else "batch_proj_"
+        return {prefix + kn: f for kn, f in self.flops.items()}
 
     def config(self, n_mom):
         return {"workload": self.name, "lattices": ["24^3x48", "32^3x64", "48^3x96"], "n_sources": self.n_src,
@@ -624,14 +625,14 @@ def serve_units(spec, momenta):
     return f * spec["N"] * spec["L"] ** 3 * n_mom * (1 + spec["n_tau"])
 
 
-def serve_flops(spec, momenta):
+def serve_flops(spec, momenta, prefix="serve_proj_"):
     """Algorithmic projection flops per producer kind (8 real flops per complex MAC)."""
     n_mom, V3, N = momenta[spec["n2"]], spec["L"] ** 3, spec["N"]
     if spec["kind"] == "nucleon":
-        return {"serve_proj_spectator_baryon": 2 * 8.0 * n_mom * V3 * N * 3072,
-                "serve_proj_insertion": 2 * 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
-    return {"serve_proj_spectator_meson": 8.0 * n_mom * V3 * N * 192,
-            "serve_proj_insertion": 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
+        return {prefix + "spectator_baryon": 2 * 8.0 * n_mom * V3 * N * 3072,
+                prefix + "insertion": 2 * 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
+    return {prefix + "spectator_meson": 8.0 * n_mom * V3 * N * 192,
+            prefix + "insertion": 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
 
 
 def serve_main(args):
@@ -640,7 +641,8 @@ def serve_main(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     proj = args.proj or "f16x2"
-    proj_flag = {"f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16, "f16x2": c3pt.PROJ_SPLIT_F16}[proj]
+    proj_flag = {"f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16, "f16x2": c3pt.PROJ_SPLIT_F16,
+                 "fac": c3pt.PROJ_FACTORED}[proj]
     lattices = [int(x) for x in args.lattices.split(",")]
     loads = [float(x) for x in args.loads.split(",")]
     momenta = {n2: len(c3pt.momentum_list(n2)) for n2 in range(3, 10)}
@@ -712,7 +714,7 @@ def serve_main(args):
     prof = c3pt.profile_read(reset=True)
     kflops = {}
     for sp in prof_specs:
-        for kn, f in serve_flops(sp, momenta).items():
+        for kn, f in serve_flops(sp, momenta, "serve_fac_" if proj == "fac" else "serve_proj_").items():
             kflops[kn] = kflops.get(kn, 0.0) + f
     kname = max((kn for kn in kflops if kn in prof), key=lambda kn: prof[kn]["total_ms"])
     achieved = kflops[kname] / (prof[kname]["total_ms"] * 1e-3) / 1e12
@@ -744,7 +746,7 @@ def serve_main(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "bf16x2": "f32 contraction, bf16 hi+lo projection",
-                  "f16x2": "f32 contraction, f16 hi+lo projection"}[proj],
+                  "f16x2": "f32 contraction, f16 hi+lo projection", "fac": "f32"}[proj],
         "data": "synthetic",
         "config": {"workload": "serving: Poisson arrivals; lattices 16^3x32:32^3x64:48^3x96:64^3x128 = 4:3:2:1, "
                                "|k|^2 ~ U{3..9}, meson:nucleon 1:1, N ~ U{1..16}, t_f-t_src ~ U{8..16}, local "

@@ -515,6 +515,12 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
 
 // Shared with the batch API (c3pt_batch.hip).
 namespace c3pt {
+bool api_factor_plan(const int L[3], int sigma, const int* k, int n_mom, FactorPlan* plan) {
+    c3pt_geom g;
+    memset(&g, 0, sizeof(g));
+    for (int j = 0; j < 3; ++j) g.L[j] = L[j];
+    return build_factor_plan(&g, sigma, k, MomGroup{0, n_mom}, false, plan);
+}
 int api_fail(int code, const char* msg) { return fail(code, "%s", msg); }
 int api_ok() { return ok(); }
 int api_variant(int kind, int mode, int mt) {

@@ -99,8 +99,10 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     if (n_combines < 0 || (n_combines > 0 && !combines)) return api_fail(C3PT_EINVAL, "bad combine list");
     if (!k || n_mom < 1 || n_mom > kMaxMomGroupF32)
         return api_fail(C3PT_EINVAL, "batches take 1..128 momenta");
-    if (proj != C3PT_PROJ_NATIVE && proj != C3PT_PROJ_SPLIT_F16 && proj != C3PT_PROJ_SPLIT_BF16)
+    if (proj != C3PT_PROJ_NATIVE && proj != C3PT_PROJ_SPLIT_F16 && proj != C3PT_PROJ_SPLIT_BF16 &&
+        proj != C3PT_PROJ_FACTORED)
         return api_fail(C3PT_EINVAL, "unknown projection mode");
+    const bool fac = proj == C3PT_PROJ_FACTORED;
     for (int m = 0; m < 3 * n_mom; ++m)
         if (k[m] < -32768 || k[m] > 32767) return api_fail(C3PT_EINVAL, "momentum component outside [-32768, 32767]");
     const int mode = proj == C3PT_PROJ_SPLIT_BF16 ? kModeSplitBF16 : proj == C3PT_PROJ_SPLIT_F16 ? kModeSplitF16 : kModeF32;
@@ -160,10 +162,16 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             d.n_colblocks = J.kind == C3PT_JOB_SPECTATOR_MESON ? J.n_noise : 16 * J.n_noise;
             d.group_cols = J.kind == C3PT_JOB_SPECTATOR_MESON ? kBlockCols : 3072;
         }
-        d.n_chunks = (d.V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
-        const int tiles = (d.V3 + kSiteTile - 1) / kSiteTile;
-        d.chunk_sites = (tiles + d.n_chunks - 1) / d.n_chunks * kSiteTile;
-        d.n_chunks = (d.V3 + d.chunk_sites - 1) / d.chunk_sites;
+        if (fac) {
+            // every x3 plane is a partial-sum chunk; an item covers a few planes
+            d.n_chunks = d.L[2];
+            d.chunk_sites = std::max(1, std::min(d.L[2], 4096 / (d.L[0] * d.L[1])));   // planes per item
+        } else {
+            d.n_chunks = (d.V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
+            const int tiles = (d.V3 + kSiteTile - 1) / kSiteTile;
+            d.chunk_sites = (tiles + d.n_chunks - 1) / d.n_chunks * kSiteTile;
+            d.n_chunks = (d.V3 + d.chunk_sites - 1) / d.chunk_sites;
+        }
         d.n_mom = n_mom;
         d.out_inner = d.n_colblocks / (d.group_cols / kBlockCols);   // output groups: identity map
         d.out_stride = d.out_inner;
@@ -216,7 +224,17 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
         const c3pt_job& J = jobs[h.index];
         const std::array<int, 4> key = {d.L[0], d.L[1], d.L[2], d.sigma};
         auto it = tables.find(key);
-        if (it == tables.end()) {
+        if (it == tables.end() && fac) {
+            FactorPlan plan;
+            if (!api_factor_plan(d.L, d.sigma, k, n_mom, &plan))
+                return bail(api_fail(C3PT_EUNSUPPORTED,
+                                     "the momentum list has too many distinct k1 or (k1, k2) for the factored "
+                                     "projection"));
+            void* dp;
+            if (int rc = dmalloc(b, &dp, sizeof(FactorPlan))) return bail(rc);
+            if (int rc = upload_sync(dp, &plan, sizeof(FactorPlan), st)) return bail(rc);
+            it = tables.emplace(key, dp).first;
+        } else if (it == tables.end()) {
             PhaseSpec ph;
             memset(&ph, 0, sizeof(ph));
             for (int j = 0; j < 3; ++j) ph.L[j] = d.L[j];
@@ -301,23 +319,33 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device);
     std::vector<std::vector<Queue>> queues(groups.size());
     std::vector<std::pair<long long*, long long>> out_offsets(groups.size());
+    // queue kinds: 0 meson spectator, 1 baryon spectator, 2 insertion (factored:
+    // local operator only), 3 factored insertion derivative operators
+    constexpr int kQueueKinds = 4;
     int* counters;
-    if (int rc = dmalloc(b, (void**)&counters, groups.size() * 3 * sizeof(int))) return bail(rc);
+    if (int rc = dmalloc(b, (void**)&counters, groups.size() * kQueueKinds * sizeof(int))) return bail(rc);
     for (size_t gi = 0; gi < groups.size(); ++gi) {
-        for (int kind = 0; kind < 3; ++kind) {
+        for (int kind = 0; kind < kQueueKinds; ++kind) {
+            if (kind == 3 && !fac) continue;
+            bool kt32 = true;
             // Issue order: largest job first; within a job, items that read the
             // same input slice and site chunk are adjacent, so they run together
             // and share its cache lines.
             std::vector<int4> items;
             for (int i : groups[gi]) {
                 const BatchJob& d = hj[i].d;
-                if (d.kind != kind) continue;
+                if (d.kind != std::min(kind, 2)) continue;
+                if (kind == 3 && d.n_ops == 1) continue;
+                kt32 = kt32 && d.L[0] % 32 == 0;
                 const int n_share = d.kind == 2 ? d.n_tau : 1;
                 const int n_within = d.n_colblocks / n_share;
+                const int n_item_chunks = fac ? (d.L[2] + d.chunk_sites - 1) / d.chunk_sites : d.n_chunks;
                 for (int sh = 0; sh < n_share; ++sh)
-                    for (int ch = 0; ch < d.n_chunks; ++ch)
+                    for (int ch = 0; ch < n_item_chunks; ++ch)
                         for (int w = 0; w < n_within; ++w) {
-                            const int cb = d.kind == 2 ? ((w / d.n_ops) * d.n_tau + sh) * d.n_ops + w % d.n_ops : w;
+                            const int op = d.kind == 2 ? w % d.n_ops : 0;
+                            if (fac && d.kind == 2 && (op == 0) != (kind == 2)) continue;
+                            const int cb = d.kind == 2 ? ((w / d.n_ops) * d.n_tau + sh) * d.n_ops + op : w;
                             items.push_back(make_int4(job_pos[i], cb, ch, 0));
                         }
             }
@@ -326,15 +354,22 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             if (int rc = dmalloc(b, &dev, items.size() * sizeof(int4))) return bail(rc);
             if (int rc = upload_sync(dev, items.data(), items.size() * sizeof(int4), st)) return bail(rc);
             // persistent grid: as many workgroups as fit on the chip at once
-            const int variant = api_variant(kind, mode, mt);
+            // (factored queues: variant = 32-site tiles)
+            const int variant = fac ? (kt32 ? 1 : 0) : api_variant(kind, mode, mt);
             hipError_t e = hipSuccess;
-            const int per_cu = kind == 0   ? batch_meson(mode, mt, variant, nullptr, 0, st, &e)
-                               : kind == 1 ? batch_baryon(mode, mt, variant, nullptr, 0, st, &e)
-                                           : batch_insertion(mode, mt, variant, nullptr, 0, st, &e);
+            int per_cu;
+            if (fac)
+                per_cu = kind == 0   ? batch_fac_meson(kt32, nullptr, 0, st, &e)
+                         : kind == 1 ? batch_fac_baryon(kt32, nullptr, 0, st, &e)
+                                     : batch_fac_insertion(kind == 2 ? 1 : 2, kt32, nullptr, 0, st, &e);
+            else
+                per_cu = kind == 0   ? batch_meson(mode, mt, variant, nullptr, 0, st, &e)
+                         : kind == 1 ? batch_baryon(mode, mt, variant, nullptr, 0, st, &e)
+                                     : batch_insertion(mode, mt, variant, nullptr, 0, st, &e);
             if (e != hipSuccess || per_cu < 1) return bail(api_fail(C3PT_EUNSUPPORTED, "no kernel for this batch"));
             const int n_wg = std::max(1, (int)std::min<long long>((long long)items.size(), (long long)per_cu * n_cu));
             queues[gi].push_back(
-                Queue{kind, (int4*)dev, (int)items.size(), counters + 3 * gi + kind, variant, n_wg});
+                Queue{kind, (int4*)dev, (int)items.size(), counters + kQueueKinds * gi + kind, variant, n_wg});
             b->n_items += (int)items.size();
         }
         std::vector<long long> offs(1, 0);
@@ -384,11 +419,13 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     BatchReduceArgs rbase;
     memset(&rbase, 0, sizeof(rbase));
     int job_base = 0;
-    static const char* kProjName[3] = {"batch_proj_spectator_meson", "batch_proj_spectator_baryon",
-                                       "batch_proj_insertion"};
+    static const char* kProjName[4] = {"batch_proj_spectator_meson", "batch_proj_spectator_baryon",
+                                       "batch_proj_insertion", "batch_proj_insertion_deriv"};
+    static const char* kFacName[4] = {"batch_fac_spectator_meson", "batch_fac_spectator_baryon",
+                                      "batch_fac_insertion", "batch_fac_insertion_deriv"};
     for (size_t gi = 0; gi < groups.size(); ++gi) {
-        int* cnt = counters + 3 * gi;
-        b->ops.push_back({"batch_reset", [cnt](hipStream_t s) { return launch_reset(cnt, 3, s); }});
+        int* cnt = counters + kQueueKinds * gi;
+        b->ops.push_back({"batch_reset", [cnt](hipStream_t s) { return launch_reset(cnt, kQueueKinds, s); }});
         for (const Queue& q : queues[gi]) {
             BatchGrid bg;
             bg.jobs = JD;
@@ -396,11 +433,20 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             bg.n_items = q.n;
             bg.counter = q.counter;
             const int kind = q.kind, variant = q.variant, n_wg = q.n_wg;
-            b->ops.push_back({kProjName[kind], [=](hipStream_t s) {
+            b->ops.push_back({fac ? kFacName[kind] : kProjName[kind], [=](hipStream_t s) {
                                   hipError_t e = hipSuccess;
-                                  if (kind == 0) batch_meson(mode, mt, variant, &bg, n_wg, s, &e);
-                                  else if (kind == 1) batch_baryon(mode, mt, variant, &bg, n_wg, s, &e);
-                                  else batch_insertion(mode, mt, variant, &bg, n_wg, s, &e);
+                                  if (fac) {
+                                      const bool kt32 = variant == 1;
+                                      if (kind == 0) batch_fac_meson(kt32, &bg, n_wg, s, &e);
+                                      else if (kind == 1) batch_fac_baryon(kt32, &bg, n_wg, s, &e);
+                                      else batch_fac_insertion(kind == 2 ? 1 : 2, kt32, &bg, n_wg, s, &e);
+                                  } else if (kind == 0) {
+                                      batch_meson(mode, mt, variant, &bg, n_wg, s, &e);
+                                  } else if (kind == 1) {
+                                      batch_baryon(mode, mt, variant, &bg, n_wg, s, &e);
+                                  } else {
+                                      batch_insertion(mode, mt, variant, &bg, n_wg, s, &e);
+                                  }
                                   return e;
                               }});
         }

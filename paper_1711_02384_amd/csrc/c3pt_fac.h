@@ -290,6 +290,57 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
 }
 
+// Persistent form for batches and serving: workgroups take (job, column
+// block, plane chunk) items from a queue; job.phase is the job's FactorPlan,
+// job.chunk_sites the planes per item, and every plane is written as its own
+// chunk (job.n_chunks == L3).
+template <typename R, int KT, template <typename, int, int> class ProdT>
+__global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg) {
+    using Prod = ProdT<R, KT, kFacThreads>;
+    __shared__ FacSmem<R, KT> sm;
+    __shared__ typename Prod::Smem psm;
+    __shared__ int s_item;
+    const int tid = threadIdx.x;
+    C2<R> out[FacLimits<R>::kOut];   // not used by the plane-chunk form
+    for (;;) {
+        if (tid == 0) s_item = atomicAdd(bg.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= bg.n_items) break;
+        const int4 item = bg.items[it];
+        const BatchJob& job = bg.jobs[item.x];
+        const int cb = item.y;
+        const typename Prod::Ctx ctx = Prod::resolve(job, job.V3, cb);
+        TileGeom tg;
+        tg.V3 = job.V3;
+        tg.L1 = job.L[0];
+        tg.L2 = job.L[1];
+        tg.L3 = job.L[2];
+        tg.inv1 = 1.0f / (float)tg.L1;
+        tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+        fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
+        const int p0 = item.z * job.chunk_sites;
+        const int p1 = min(tg.L3, p0 + job.chunk_sites);
+        fac_loop<R, KT, false, Prod>(ctx, tg, sm, psm, p0, p1, out, job.partial, job.n_colblocks, cb, tid);
+        __syncthreads();
+    }
+}
+
+template <typename R, int KT, template <typename, int, int> class ProdT>
+int fac_batch_kt(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    *err = hipSuccess;
+    if (bg) {
+        hipLaunchKernelGGL((fac_batch_kernel<R, KT, ProdT>), dim3(n_wg), dim3(kFacThreads), 0, st, *bg);
+        *err = hipGetLastError();
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fac_batch_kernel<R, KT, ProdT>, kFacThreads, 0) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
 template <typename R, int KT, bool ACC, template <typename, int, int> class ProdT>
 hipError_t launch_fac_kt(const ProjGrid& pg, const typename ProdT<R, KT, kFacThreads>::Args& a, hipStream_t st) {
     hipLaunchKernelGGL((fac_kernel<R, KT, ACC, ProdT>), dim3(pg.n_share * pg.n_per_share * pg.n_chunks), dim3(kFacThreads), 0,

@@ -9,4 +9,11 @@ hipError_t launch_fac_insertion(bool f64, int ops, const ProjGrid& pg, const Ins
                     : launch_fac<InsertionDerivProducer>(f64, pg, a, st, false);
 }
 
+int batch_fac_insertion(int ops, bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    if (ops == 1)
+        return kt32 ? fac_batch_kt<float, 32, InsertionLocalProducer>(bg, n_wg, st, err)
+                    : fac_batch_kt<float, 16, InsertionLocalProducer>(bg, n_wg, st, err);
+    return fac_batch_kt<float, 16, InsertionDerivProducer>(bg, n_wg, st, err);
+}
+
 }  // namespace c3pt

@@ -8,4 +8,8 @@ hipError_t launch_fac_meson(bool f64, const ProjGrid& pg, const MesonSpecArgs& a
     return launch_fac<MesonSpecProducer>(f64, pg, a, st);
 }
 
+int batch_fac_meson(bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+    return kt32 ? fac_batch_kt<float, 32, MesonSpecProducer>(bg, n_wg, st, err) : fac_batch_kt<float, 16, MesonSpecProducer>(bg, n_wg, st, err);
+}
+
 }  // namespace c3pt

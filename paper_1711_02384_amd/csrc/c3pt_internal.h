@@ -189,6 +189,15 @@ hipError_t launch_fac_meson(bool f64, const ProjGrid& pg, const MesonSpecArgs& a
 hipError_t launch_fac_baryon(bool f64, const ProjGrid& pg, const BaryonSpecArgs& a, hipStream_t st);
 // ops: 1 local operator only, 2 derivative operators only (a.op_lo / a.op_cnt select them)
 hipError_t launch_fac_insertion(bool f64, int ops, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st);
+// Persistent factored launches (FP32) over batch items; kt32 selects 32-site
+// tiles (every job's L1 a multiple of 32).  With bg == nullptr only the
+// occupancy (workgroups per CU) is returned.
+int batch_fac_meson(bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+int batch_fac_baryon(bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+int batch_fac_insertion(int ops, bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+// Factor plan of a momentum list for extents L and sign sigma (FP32 limits);
+// false if the list needs more distinct k1 / (k1, k2) than the kernel holds.
+bool api_factor_plan(const int L[3], int sigma, const int* k, int n_mom, FactorPlan* plan);
 // Persistent batch launch of one producer kind; with bg == nullptr only the
 // occupancy (workgroups per CU) of the variant is returned.
 int batch_meson(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);

@@ -137,6 +137,7 @@ struct c3pt_server {
     int device = 0;
     hipStream_t st = nullptr;
     int proj = 0, mode = kModeF32;
+    bool fac = false;          // factored projection
     int max_active = 1;
     char* arena = nullptr;
     size_t arena_bytes = 0;
@@ -217,11 +218,28 @@ int mtmax_of(int n_mom) {
 // built on the server stream at first use.
 int phase_for(c3pt_server* sv, const Request& q, int sigma, const void** out) {
     const int mtmax = mtmax_of(q.n_mom);
-    std::vector<int> key = {q.L[0], q.L[1], q.L[2], sigma, sv->mode, mtmax};
+    std::vector<int> key = {q.L[0], q.L[1], q.L[2], sigma, sv->fac ? 100 : sv->mode, mtmax};
     key.insert(key.end(), q.k.begin(), q.k.end());
     auto it = sv->phase.find(key);
     if (it != sv->phase.end()) {
         *out = it->second;
+        return C3PT_OK;
+    }
+    if (sv->fac) {
+        FactorPlan plan;
+        if (!api_factor_plan(q.L, sigma, q.k.data(), q.n_mom, &plan))
+            return api_fail(C3PT_EUNSUPPORTED, "the momentum list does not factor");
+        void* dp = nullptr;
+        if (hipMalloc(&dp, sizeof(FactorPlan)) != hipSuccess) {
+            (void)hipGetLastError();
+            return api_fail(C3PT_ENOMEM, "factor plan allocation failed");
+        }
+        if (hipMemcpy(dp, &plan, sizeof(FactorPlan), hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(dp);
+            return api_fail(C3PT_EDEVICE, "uploading a factor plan failed");
+        }
+        sv->phase[key] = dp;
+        *out = dp;
         return C3PT_OK;
     }
     PhaseSpec ph;
@@ -402,12 +420,6 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     }
     sv->rr = (sv->rr + 1) % std::max<size_t>(1, n_act);
 
-    // ---- launch groups: (kind, momentum-tile class) ----
-    std::map<std::pair<int, int>, std::vector<int>> groups;
-    for (size_t i = 0; i < chosen.size(); ++i)
-        groups[{chosen[i].p.kind, mt_class((chosen[i].q->n_mom + 7) / 8)}].push_back((int)i);
-    if (groups.size() > (size_t)kMaxLaunches) return api_fail(C3PT_EUNSUPPORTED, "too many launch groups");
-
     // ---- parameter block: jobs | items | tau rows | output offsets ----
     size_t n_tau_rows = 0;
     for (auto& c : chosen)
@@ -427,8 +439,41 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     long long* ho = (long long*)(h + o_offs);
     std::vector<const void*> taus;
     taus.reserve(n_tau_rows);
-    std::vector<int> job_order;   // chosen index in job-table order
+    // Launch groups.  Dense: (producer kind, momentum-tile class).  Factored:
+    // (queue kind, 32-site tiles) with queue kinds 0 meson, 1 baryon,
+    // 2 insertion local operator, 3 insertion derivative operators.
+    std::map<std::pair<int, int>, std::vector<int4>> lists;
+    std::map<std::pair<int, int>, int> list_mt;
     size_t part_off = 0;
+    for (size_t ci = 0; ci < chosen.size(); ++ci) {
+        Chosen& c = chosen[ci];
+        const int ji = (int)ci;
+        BatchJob d = packet_job(sv, *c.q, c.p, taus, o_taus);
+        d.partial = (char*)sv->partial + part_off;
+        part_off += c.bytes;
+        hj[ji] = d;
+        const int mt = (c.q->n_mom + 7) / 8;
+        const int n_share = d.kind == 2 ? d.n_tau : 1;
+        const int n_within = d.n_colblocks / n_share;
+        const int n_item_chunks = sv->fac ? (d.L[2] + d.chunk_sites - 1) / d.chunk_sites : d.n_chunks;
+        for (int sh = 0; sh < n_share; ++sh)
+            for (int ch = 0; ch < n_item_chunks; ++ch)
+                for (int w = 0; w < n_within; ++w) {
+                    const int op = d.kind == 2 ? w % d.n_ops : 0;
+                    const int cb = d.kind == 2 ? ((w / d.n_ops) * d.n_tau + sh) * d.n_ops + op : w;
+                    std::pair<int, int> key;
+                    if (sv->fac) {
+                        const int qk = d.kind < 2 ? d.kind : (op == 0 ? 2 : 3);
+                        key = {qk, (qk != 3 && d.L[0] % 32 == 0) ? 1 : 0};
+                    } else {
+                        key = {d.kind, mt_class(mt)};
+                    }
+                    lists[key].push_back(make_int4(ji, cb, ch, 0));
+                    int& lm = list_mt[key];
+                    lm = std::max(lm, mt);
+                }
+    }
+    if (lists.size() > (size_t)kMaxLaunches) return api_fail(C3PT_EUNSUPPORTED, "too many launch groups");
     size_t n_items = 0;
     struct Launch {
         int kind, mt;
@@ -436,29 +481,16 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         int variant;
     };
     std::vector<Launch> launches;
-    for (auto& g : groups) {
+    for (auto& kv : lists) {
         const size_t item0 = n_items;
-        int mt = 0;
-        for (int ci : g.second) {
-            Chosen& c = chosen[ci];
-            const int ji = (int)job_order.size();
-            job_order.push_back(ci);
-            BatchJob d = packet_job(sv, *c.q, c.p, taus, o_taus);
-            d.partial = (char*)sv->partial + part_off;
-            part_off += c.bytes;
-            hj[ji] = d;
-            mt = std::max(mt, (c.q->n_mom + 7) / 8);
-            const int n_share = d.kind == 2 ? d.n_tau : 1;
-            const int n_within = d.n_colblocks / n_share;
-            for (int sh = 0; sh < n_share; ++sh)
-                for (int ch = 0; ch < d.n_chunks; ++ch)
-                    for (int w = 0; w < n_within; ++w) {
-                        const int cb = d.kind == 2 ? ((w / d.n_ops) * d.n_tau + sh) * d.n_ops + w % d.n_ops : w;
-                        hi[n_items++] = make_int4(ji, cb, ch, 0);
-                    }
-        }
-        launches.push_back({g.first.first, mt, item0, n_items - item0, api_variant(g.first.first, sv->mode, mt)});
+        for (const int4& it4 : kv.second) hi[n_items++] = it4;
+        const int kind = kv.first.first;
+        const int mt = list_mt[kv.first];
+        const int variant = sv->fac ? kv.first.second : api_variant(kind, sv->mode, mt);
+        launches.push_back({kind, mt, item0, n_items - item0, variant});
     }
+    std::vector<int> job_order(chosen.size());
+    for (size_t ci = 0; ci < chosen.size(); ++ci) job_order[ci] = (int)ci;
     memcpy(h + o_taus, taus.data(), taus.size() * sizeof(void*));
     ho[0] = 0;
     for (size_t j = 0; j < job_order.size(); ++j) {
@@ -481,6 +513,8 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     bool okk = run("serve_reset", [&] { return launch_reset(sv->counters, (int)launches.size(), st); });
     static const char* kName[3] = {"serve_proj_spectator_meson", "serve_proj_spectator_baryon",
                                    "serve_proj_insertion"};
+    static const char* kFacName[4] = {"serve_fac_spectator_meson", "serve_fac_spectator_baryon",
+                                      "serve_fac_insertion", "serve_fac_insertion_deriv"};
     for (size_t li = 0; li < launches.size() && okk; ++li) {
         const Launch& L = launches[li];
         BatchGrid bg;
@@ -489,15 +523,30 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         bg.n_items = (int)L.n;
         bg.counter = sv->counters + li;
         hipError_t e = hipSuccess;
-        int per_cu = L.kind == 0   ? batch_meson(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
+        const bool kt32 = L.variant == 1;
+        int per_cu;
+        if (sv->fac)
+            per_cu = L.kind == 0   ? batch_fac_meson(kt32, nullptr, 0, st, &e)
+                     : L.kind == 1 ? batch_fac_baryon(kt32, nullptr, 0, st, &e)
+                                   : batch_fac_insertion(L.kind == 2 ? 1 : 2, kt32, nullptr, 0, st, &e);
+        else
+            per_cu = L.kind == 0   ? batch_meson(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
                      : L.kind == 1 ? batch_baryon(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
                                    : batch_insertion(sv->mode, L.mt, L.variant, nullptr, 0, st, &e);
         const int n_wg = (int)std::max<long long>(1, std::min<long long>((long long)L.n, (long long)per_cu * sv->n_cu));
-        okk = run(kName[L.kind], [&] {
+        okk = run(sv->fac ? kFacName[L.kind] : kName[L.kind], [&] {
             hipError_t e2 = hipSuccess;
-            if (L.kind == 0) batch_meson(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
-            else if (L.kind == 1) batch_baryon(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
-            else batch_insertion(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
+            if (sv->fac) {
+                if (L.kind == 0) batch_fac_meson(kt32, &bg, n_wg, st, &e2);
+                else if (L.kind == 1) batch_fac_baryon(kt32, &bg, n_wg, st, &e2);
+                else batch_fac_insertion(L.kind == 2 ? 1 : 2, kt32, &bg, n_wg, st, &e2);
+            } else if (L.kind == 0) {
+                batch_meson(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
+            } else if (L.kind == 1) {
+                batch_baryon(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
+            } else {
+                batch_insertion(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
+            }
             return e2;
         });
     }
@@ -577,7 +626,8 @@ int c3pt_server_create(int proj, void* arena, unsigned long long arena_bytes, un
                        int max_active, void* stream, c3pt_server** out) {
     if (!out) return api_fail(C3PT_EINVAL, "out is NULL");
     *out = nullptr;
-    if (proj != C3PT_PROJ_NATIVE && proj != C3PT_PROJ_SPLIT_F16 && proj != C3PT_PROJ_SPLIT_BF16)
+    if (proj != C3PT_PROJ_NATIVE && proj != C3PT_PROJ_SPLIT_F16 && proj != C3PT_PROJ_SPLIT_BF16 &&
+        proj != C3PT_PROJ_FACTORED)
         return api_fail(C3PT_EINVAL, "unknown projection mode");
     if (!arena || arena_bytes < kAlign || ((uintptr_t)arena % kAlign) != 0)
         return api_fail(C3PT_EINVAL, "the arena must be device memory of at least 256 bytes, 256-byte aligned");
@@ -589,6 +639,7 @@ int c3pt_server_create(int proj, void* arena, unsigned long long arena_bytes, un
     sv->st = (hipStream_t)stream;
     sv->proj = proj;
     sv->mode = proj == C3PT_PROJ_SPLIT_BF16 ? kModeSplitBF16 : proj == C3PT_PROJ_SPLIT_F16 ? kModeSplitF16 : kModeF32;
+    sv->fac = proj == C3PT_PROJ_FACTORED;
     sv->max_active = max_active;
     sv->arena = (char*)arena;
     sv->arena_bytes = arena_bytes;
@@ -678,10 +729,19 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
                               (q->n_parts == 2 && (!q->G2[tn] || !q->G2[tp]))))
             return reject("missing neighbour slice for the derivative operators");
     }
-    q->n_chunks = (q->V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
-    const int tiles = (q->V3 + kSiteTile - 1) / kSiteTile;
-    q->chunk_sites = (tiles + q->n_chunks - 1) / q->n_chunks * kSiteTile;
-    q->n_chunks = (q->V3 + q->chunk_sites - 1) / q->chunk_sites;
+    if (sv->fac) {
+        // every x3 plane is a partial-sum chunk; an item covers a few planes
+        FactorPlan plan;
+        if (!api_factor_plan(q->L, +1, q->k.data(), q->n_mom, &plan))
+            return reject("the momentum list does not factor (too many distinct k1 or (k1, k2))");
+        q->n_chunks = q->L[2];
+        q->chunk_sites = std::max(1, std::min(q->L[2], 4096 / (q->L[0] * q->L[1])));
+    } else {
+        q->n_chunks = (q->V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
+        const int tiles = (q->V3 + kSiteTile - 1) / kSiteTile;
+        q->chunk_sites = (tiles + q->n_chunks - 1) / q->n_chunks * kSiteTile;
+        q->n_chunks = (q->V3 + q->chunk_sites - 1) / q->chunk_sites;
+    }
     q->bytes = layout(*q);
     if (q->bytes > sv->arena_bytes) return reject("the request's outputs exceed the arena");
     const size_t per_cb = (size_t)q->n_chunks * q->n_mom * kBlockCols * sizeof(float2);

@@ -109,7 +109,7 @@ def _batch(c3pt, lats, k, proj, budget=0, combine_pairs=((0, 0), (3, 5), (26, 1)
     return c3pt.Batch(jobs, k, proj=proj, combines=combs, partial_budget=budget)
 
 
-@pytest.mark.parametrize("proj,name", [(0, "f32"), (2, "bf16x2"), (1, "f16x2")])
+@pytest.mark.parametrize("proj,name", [(0, "f32"), (2, "bf16x2"), (1, "f16x2"), (3, "factored")])
 def test_batch_matches_oracle_and_single_calls(proj, name):
     import paper_1711_02384_amd as c3pt
     k = c3pt.momentum_list(3)          # 27 momenta
@@ -174,14 +174,15 @@ def test_batch_graph_replays_and_refill():
     b.close()
 
 
-def test_batch_alone_vs_mix_and_budget_groups():
+@pytest.mark.parametrize("proj", [2, 3])
+def test_batch_alone_vs_mix_and_budget_groups(proj):
     import paper_1711_02384_amd as c3pt
     k = c3pt.momentum_list(3)
     lats = _lattices()
-    mix = _batch(c3pt, lats, k, 2)
+    mix = _batch(c3pt, lats, k, proj)
     mix.run()
     # each lattice alone
-    alone = [_batch(c3pt, [lat], k, 2) for lat in lats]
+    alone = [_batch(c3pt, [lat], k, proj) for lat in lats]
     for a in alone:
         a.run()
     # the mix again under a budget that forces several groups
@@ -190,9 +191,9 @@ def test_batch_alone_vs_mix_and_budget_groups():
     for lat in lats:
         for kind_cols in ((16 if lat.baryon else 1) * lat.N, lat.N * len(lat.taus) * lat.n_ops):
             V3 = int(np.prod(lat.L))
-            n_chunks = -(-V3 // 2048)
+            n_chunks = lat.L[2] if proj == 3 else -(-V3 // 2048)
             biggest = max(biggest, n_chunks * kind_cols * n_mom * 192 * 8)
-    split = _batch(c3pt, lats, k, 2, budget=biggest)
+    split = _batch(c3pt, lats, k, proj, budget=biggest)
     split.run()
     torch.cuda.synchronize()
     info = split.info()

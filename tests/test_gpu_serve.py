@@ -96,7 +96,7 @@ def _copy(sv, rid):
     return {k: [t.clone() for t in v] for k, v in res.items()}
 
 
-@pytest.mark.parametrize("proj,name", [(0, "f32"), (1, "f16x2")])
+@pytest.mark.parametrize("proj,name", [(0, "f32"), (1, "f16x2"), (3, "factored")])
 def test_serve_mix_matches_oracle_and_alone(proj, name):
     import paper_1711_02384_amd as c3pt
     reqs = _mix()
