@@ -448,8 +448,8 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
     plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks_dense);
     plan_planes(g->L[2], n_colblocks, &chunk_planes, &n_chunks_fac);
     const size_t gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
-    const size_t bytes = (size_t)std::max(n_chunks_dense, want_fac ? std::max(n_chunks_fac, g->L[2]) : 0) *
-                         n_colblocks * gmax * kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));
+    const size_t bytes = (size_t)std::max(n_chunks_dense, want_fac ? n_chunks_fac : 0) * n_colblocks * gmax *
+                         kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));
     void* part;
     if (int rc = scratch_dev(st, bytes, &part)) return rc;
     for (const MomGroup& mg : groups) {
@@ -468,13 +468,13 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
             std::lock_guard<std::mutex> lk(g_mu);
             fac_variant = g_variant[kind][kModeFacVariants][mt_class(mt)];
         }
-        const bool fac_acc = fac && fac_variant == 1 && chunk_planes > 1;
-        const int n_chunks = fac ? (fac_acc ? n_chunks_fac : g->L[2]) : n_chunks_dense;
+        const int n_chunks = fac ? n_chunks_fac : n_chunks_dense;
         ProjGrid pg;
         pg.V3 = V3;
         pg.n_mom = mg.n;
         pg.chunk_sites = chunk_sites;
-        pg.chunk_planes = fac_acc ? chunk_planes : 1;
+        pg.chunk_planes = chunk_planes;
+        pg.fac_acc = fac && fac_variant == 1 ? 1 : 0;
         pg.n_chunks = n_chunks;
         pg.n_colblocks = n_colblocks;
         pg.n_share = n_share;
@@ -649,7 +649,7 @@ int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* et
     int rc = run_projection("proj_spectator_meson", 0, geom, -1, k, n_mom, n_noise, 1, n_noise, kBlockCols,
                             n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
                                 hipStream_t st = (hipStream_t)geom->stream;
-                                return fac ? launch_fac_meson(geom->dtype == C3PT_C128, pg, a, st)
+                                return fac ? launch_fac_meson(geom->dtype == C3PT_C128, pg.fac_acc, pg, a, st)
                                            : launch_spectator_meson(mode, mt, variant, pg, a, st);
                             });
     return rc ? rc : ok();
@@ -665,7 +665,7 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
     int rc = run_projection("proj_spectator_baryon", 1, geom, -1, k, n_mom, n_noise * 16, 1, n_noise * 16, 3072,
                             n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
                                 hipStream_t st = (hipStream_t)geom->stream;
-                                return fac ? launch_fac_baryon(geom->dtype == C3PT_C128, pg, a, st)
+                                return fac ? launch_fac_baryon(geom->dtype == C3PT_C128, pg.fac_acc, pg, a, st)
                                            : launch_spectator_baryon(mode, mt, variant, pg, a, st);
                             });
     return rc ? rc : ok();
@@ -729,14 +729,14 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                     al.op_cnt = 1;
                                     ProjGrid pl = pg;
                                     pl.n_per_share = n_noise;
-                                    hipError_t e = launch_fac_insertion(f64, 1, pl, al, st);
+                                    hipError_t e = launch_fac_insertion(f64, pg.fac_acc, 1, pl, al, st);
                                     if (e != hipSuccess || n_ops == 1) return e;
                                     InsertionArgs ad = a;
                                     ad.op_lo = 1;
                                     ad.op_cnt = 4;
                                     ProjGrid pd = pg;
                                     pd.n_per_share = n_noise * 4;
-                                    return launch_fac_insertion(f64, 2, pd, ad, st);
+                                    return launch_fac_insertion(f64, pg.fac_acc, 2, pd, ad, st);
                                 });
         if (rc) return rc;
     }

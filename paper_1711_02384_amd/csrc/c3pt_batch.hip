@@ -163,9 +163,9 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             d.group_cols = J.kind == C3PT_JOB_SPECTATOR_MESON ? kBlockCols : 3072;
         }
         if (fac) {
-            // every x3 plane is a partial-sum chunk; an item covers a few planes
-            d.n_chunks = d.L[2];
-            d.chunk_sites = std::max(1, std::min(d.L[2], 4096 / (d.L[0] * d.L[1])));   // planes per item
+            // chunks of x3 planes (about 4096 sites), summed in place
+            d.chunk_sites = std::max(1, std::min(d.L[2], 4096 / (d.L[0] * d.L[1])));   // planes per chunk
+            d.n_chunks = (d.L[2] + d.chunk_sites - 1) / d.chunk_sites;
         } else {
             d.n_chunks = (d.V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
             const int tiles = (d.V3 + kSiteTile - 1) / kSiteTile;
@@ -339,7 +339,7 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
                 kt32 = kt32 && d.L[0] % 32 == 0;
                 const int n_share = d.kind == 2 ? d.n_tau : 1;
                 const int n_within = d.n_colblocks / n_share;
-                const int n_item_chunks = fac ? (d.L[2] + d.chunk_sites - 1) / d.chunk_sites : d.n_chunks;
+                const int n_item_chunks = d.n_chunks;
                 for (int sh = 0; sh < n_share; ++sh)
                     for (int ch = 0; ch < n_item_chunks; ++ch)
                         for (int w = 0; w < n_within; ++w) {

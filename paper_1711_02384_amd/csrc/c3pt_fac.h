@@ -113,13 +113,15 @@ __device__ __forceinline__ R fac_a1(const FacSmem<R, KT>& sm, int s, int ks, int
 template <typename R> using Part2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
 
 // Sum over the tiles of planes [p0, p1).  ACC: into out (thread-owned
-// momenta), written by fac_write at the end; otherwise every plane's sums are
-// written as their own chunk (chunk index = x3) and out is unused.
+// momenta), written by fac_write at the end.  Otherwise every plane's sums are
+// added into the chunk's partial sums in global memory (written at the first
+// plane, read back and added at the next ones; each element is owned by one
+// thread of one workgroup, so the order is fixed); out is unused.
 template <typename R, int KT, bool ACC, class Prod>
 __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const TileGeom& tg, FacSmem<R, KT>& sm,
                                          typename Prod::Smem& psm, int p0, int p1,
                                          C2<R> (&out)[FacLimits<R>::kOut], void* partial, int n_colblocks,
-                                         int cb, int tid) {
+                                         int cb, int chunk, int tid) {
     using MF = Mfma<R>;
     using acc_t = typename MF::acc_t;
     constexpr int NT = kFacThreads;
@@ -227,12 +229,19 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
                 }
             } else {
                 Part2<R>* part = (Part2<R>*)partial;
-                const size_t base = ((size_t)x3 * n_colblocks + cb) * (size_t)n_mom;
+                const size_t base = ((size_t)chunk * n_colblocks + cb) * (size_t)n_mom;
+                const bool first = (x3 == p0);
                 for (int m = q3; m < n_mom; m += 4) {
                     const int b = sm.plan.pair_of_m[m];
                     const C2<R> w = sm.root[2][mod_small(sm.plan.k3[m] * x3, L3, inv3)];
-                    const C2<R> v = cmul(w, sm.R2[b][c3]);
-                    part[(base + m) * kBlockCols + c3] = Part2<R>{v.x, v.y};
+                    C2<R> v = cmul(w, sm.R2[b][c3]);
+                    Part2<R>& dst = part[(base + m) * kBlockCols + c3];
+                    if (!first) {
+                        const Part2<R> o = dst;
+                        v.x += o.x;
+                        v.y += o.y;
+                    }
+                    dst = Part2<R>{v.x, v.y};
                 }
             }
             // R2 is rewritten only at the next plane end, after further barriers
@@ -286,14 +295,13 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     }
     const int p0 = chunk * pg.chunk_planes;
     const int p1 = min(tg.L3, p0 + pg.chunk_planes);
-    fac_loop<R, KT, ACC, Prod>(ctx, tg, sm, psm, p0, p1, out, pg.partial, pg.n_colblocks, cb, tid);
+    fac_loop<R, KT, ACC, Prod>(ctx, tg, sm, psm, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
     if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
 }
 
 // Persistent form for batches and serving: workgroups take (job, column
 // block, plane chunk) items from a queue; job.phase is the job's FactorPlan,
-// job.chunk_sites the planes per item, and every plane is written as its own
-// chunk (job.n_chunks == L3).
+// job.chunk_sites the x3 planes per chunk, job.n_chunks the chunks.
 template <typename R, int KT, template <typename, int, int> class ProdT>
 __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg) {
     using Prod = ProdT<R, KT, kFacThreads>;
@@ -322,7 +330,7 @@ __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg)
         fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
         const int p0 = item.z * job.chunk_sites;
         const int p1 = min(tg.L3, p0 + job.chunk_sites);
-        fac_loop<R, KT, false, Prod>(ctx, tg, sm, psm, p0, p1, out, job.partial, job.n_colblocks, cb, tid);
+        fac_loop<R, KT, false, Prod>(ctx, tg, sm, psm, p0, p1, out, job.partial, job.n_colblocks, cb, item.z, tid);
         __syncthreads();
     }
 }
@@ -349,11 +357,10 @@ hipError_t launch_fac_kt(const ProjGrid& pg, const typename ProdT<R, KT, kFacThr
 }
 
 // FP32: 32-site tiles when whole rows split into them (and the producer fits
-// its registers at that size), else 16; FP64: 16.  chunk_planes == 1 selects
-// the form without register accumulation.
+// its registers at that size), else 16; FP64: 16.  acc selects the form that
+// sums a chunk's planes in registers.
 template <template <typename, int, int> class ProdT, class Args>
-hipError_t launch_fac(bool f64, const ProjGrid& pg, const Args& a, hipStream_t st, bool allow32 = true) {
-    const bool acc = pg.chunk_planes > 1;
+hipError_t launch_fac(bool f64, bool acc, const ProjGrid& pg, const Args& a, hipStream_t st, bool allow32 = true) {
     if (f64) return acc ? launch_fac_kt<double, 16, true, ProdT>(pg, a, st) : launch_fac_kt<double, 16, false, ProdT>(pg, a, st);
     if (allow32 && a.L[0] % 32 == 0)
         return acc ? launch_fac_kt<float, 32, true, ProdT>(pg, a, st) : launch_fac_kt<float, 32, false, ProdT>(pg, a, st);

@@ -4,9 +4,10 @@
 
 namespace c3pt {
 
-hipError_t launch_fac_insertion(bool f64, int ops, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st) {
-    return ops == 1 ? launch_fac<InsertionLocalProducer>(f64, pg, a, st)
-                    : launch_fac<InsertionDerivProducer>(f64, pg, a, st, false);
+hipError_t launch_fac_insertion(bool f64, bool acc, int ops, const ProjGrid& pg, const InsertionArgs& a,
+                                hipStream_t st) {
+    return ops == 1 ? launch_fac<InsertionLocalProducer>(f64, acc, pg, a, st)
+                    : launch_fac<InsertionDerivProducer>(f64, acc, pg, a, st, false);
 }
 
 int batch_fac_insertion(int ops, bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {

@@ -4,8 +4,8 @@
 
 namespace c3pt {
 
-hipError_t launch_fac_meson(bool f64, const ProjGrid& pg, const MesonSpecArgs& a, hipStream_t st) {
-    return launch_fac<MesonSpecProducer>(f64, pg, a, st);
+hipError_t launch_fac_meson(bool f64, bool acc, const ProjGrid& pg, const MesonSpecArgs& a, hipStream_t st) {
+    return launch_fac<MesonSpecProducer>(f64, acc, pg, a, st);
 }
 
 int batch_fac_meson(bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {

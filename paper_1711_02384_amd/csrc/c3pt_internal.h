@@ -69,6 +69,7 @@ struct ProjGrid {
     void* partial;     // [n_chunks][n_colblocks][n_mom][192] partial sums in the accumulator type
                        // (complex float; complex double for complex128 inputs)
     int chunk_planes;  // factored launches: x3 planes per chunk (chunk_sites unused)
+    int fac_acc;       // factored launches: sum a chunk's planes in registers
 };
 
 // Producer arguments -------------------------------------------------------
@@ -185,10 +186,12 @@ hipError_t launch_insertion(int mode, int mt, int variant, const ProjGrid& pg, c
                             hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 // Factored projection launches (f64: complex128 inputs, FP64 MFMA; else FP32).
-hipError_t launch_fac_meson(bool f64, const ProjGrid& pg, const MesonSpecArgs& a, hipStream_t st);
-hipError_t launch_fac_baryon(bool f64, const ProjGrid& pg, const BaryonSpecArgs& a, hipStream_t st);
+// acc: sum a chunk's x3 planes in registers (else in the partial sums, in place).
+hipError_t launch_fac_meson(bool f64, bool acc, const ProjGrid& pg, const MesonSpecArgs& a, hipStream_t st);
+hipError_t launch_fac_baryon(bool f64, bool acc, const ProjGrid& pg, const BaryonSpecArgs& a, hipStream_t st);
 // ops: 1 local operator only, 2 derivative operators only (a.op_lo / a.op_cnt select them)
-hipError_t launch_fac_insertion(bool f64, int ops, const ProjGrid& pg, const InsertionArgs& a, hipStream_t st);
+hipError_t launch_fac_insertion(bool f64, bool acc, int ops, const ProjGrid& pg, const InsertionArgs& a,
+                                hipStream_t st);
 // Persistent factored launches (FP32) over batch items; kt32 selects 32-site
 // tiles (every job's L1 a multiple of 32).  With bg == nullptr only the
 // occupancy (workgroups per CU) is returned.

@@ -455,7 +455,7 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         const int mt = (c.q->n_mom + 7) / 8;
         const int n_share = d.kind == 2 ? d.n_tau : 1;
         const int n_within = d.n_colblocks / n_share;
-        const int n_item_chunks = sv->fac ? (d.L[2] + d.chunk_sites - 1) / d.chunk_sites : d.n_chunks;
+        const int n_item_chunks = d.n_chunks;
         for (int sh = 0; sh < n_share; ++sh)
             for (int ch = 0; ch < n_item_chunks; ++ch)
                 for (int w = 0; w < n_within; ++w) {
@@ -730,12 +730,12 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
             return reject("missing neighbour slice for the derivative operators");
     }
     if (sv->fac) {
-        // every x3 plane is a partial-sum chunk; an item covers a few planes
+        // chunks of x3 planes (about 4096 sites), summed in place
         FactorPlan plan;
         if (!api_factor_plan(q->L, +1, q->k.data(), q->n_mom, &plan))
             return reject("the momentum list does not factor (too many distinct k1 or (k1, k2))");
-        q->n_chunks = q->L[2];
         q->chunk_sites = std::max(1, std::min(q->L[2], 4096 / (q->L[0] * q->L[1])));
+        q->n_chunks = (q->L[2] + q->chunk_sites - 1) / q->chunk_sites;
     } else {
         q->n_chunks = (q->V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
         const int tiles = (q->V3 + kSiteTile - 1) / kSiteTile;
