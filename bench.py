@@ -13,14 +13,18 @@ Default workload (``meson32``), shaped like the 32^3 x 64 meson measurement:
   derivative operators and the nucleon on the 161 pairs with p' = q or p' = 0.
 
 Inputs: 4 Z2xZ2 noise vectors, Gaussian propagators and stochastic solutions,
-Haar SU(3) links, complex64 in HBM (FP32 contractions, FP32 MFMA projection,
-FP64 split-site accumulation and FP64 combine).
+Haar SU(3) links, complex64 in HBM.  Arithmetic: FP32 contractions; the
+projection factored over the three directions (``--proj fac``, the default:
+x1 stage on FP32 MFMA) or as one dense (momenta x sites) GEMM (``--proj f32``
+FP32 MFMA, ``bf16x2`` / ``f16x2`` hi+lo 16-bit MFMA with FP32 accumulation);
+FP64 split-site accumulation and FP64 combine.
 
 Other workloads (``--workload``): ``meson8`` (8^3 x 16, complex128, 27
-momenta, local insertion at tau = 0..8, all-pairs combine) and ``nucleon48``
+momenta, local insertion at tau = 0..8, all-pairs combine), ``nucleon48``
 (48^3 x 64, two nucleon spectators (u,u) and (u,d), isovector insertion with
 u and d propagators at tau = 0..14, N = 8, 93 or 123 momenta, combine on the
-185 pairs with p' = q or p' = 0).
+185 pairs with p' = q or p' = 0), ``batch64`` (64 sources in one recorded
+graph) and ``serve`` (Poisson arrivals to the continuous-batching engine).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
 """
@@ -75,6 +79,38 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# FP32 VALU peak without packed FP32 instructions (which this library does not
+# use): 256 CU x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_VALU_F32 = 78.6
+
+# Contraction arithmetic per (site, column block of 192), 8 flops per complex
+# multiply-add: meson spectator and local insertion 192 x 3; baryon 576 for the
+# diquark products plus 192 x 3; derivative insertion 192 x 6 plus the
+# transport of the stochastic vector 12 x 3 x 2.
+CONTRACTION_FLOPS = {"spectator_meson": 8.0 * 576, "spectator_baryon": 8.0 * 1152,
+                     "insertion_local": 8.0 * 576, "insertion_deriv": 8.0 * (1152 + 72)}
+
+
+def roofline_entry(kname, flops, kms, proj):
+    """Roofline object: dense projections are MFMA-bound (projection flops
+    against the MFMA peak of their type); factored ones are bound by the
+    contraction's FP32 arithmetic (against the VALU peak)."""
+    achieved = flops / (kms * 1e-3) / 1e12
+    if proj == "fac":
+        peak, bound = PEAK_VALU_F32, "alu"
+        what = "fused contraction + factored projection; flops = contraction arithmetic"
+    else:
+        peak, bound = PEAK[proj], "mfma"
+        what = f"fused contraction + {proj} MFMA projection; flops = 8 per (site, momentum, column)"
+    r = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+         "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"{kname} ({what})",
+         "flops_per_launch": flops, "avg_ms": round(kms, 4)}
+    if proj in ("bf16x2", "f16x2"):
+        r["note"] = ("flops counted once per complex MAC (8 real flops); the hi+lo split issues "
+                     "3 MFMA products per term, so MFMA issue is 3x the counted flops")
+    return r
+
+
 def pairs_diag_or_zero(n_mom):
     """(p', q) pairs with p' = q or p' = 0 (index 0 is k = 0)."""
     pr = [(p, p) for p in range(n_mom)] + [(0, q) for q in range(1, n_mom)]
@@ -99,7 +135,7 @@ class Meson32:
     n_ops = 5
     cfg = 2
     dtype = "c64"
-    default_proj = "f32"
+    default_proj = "fac"
     default_steps = 20
     default_warmup = 3
 
@@ -162,9 +198,13 @@ class Meson32:
         return (self.N * V3 * n_mom * (192 + (3072 if self.baryon else 0))
                 + self.N * len(self.taus) * V3 * n_mom * 192 * self.n_ops)
 
-    def dominant(self, n_mom):
+    def dominant(self, n_mom, proj):
+        V3 = int(np.prod(self.L))
+        if proj == "fac":
+            per = CONTRACTION_FLOPS["insertion_local"] + (self.n_ops - 1) * CONTRACTION_FLOPS["insertion_deriv"]
+            return "fac_insertion", self.N * len(self.taus) * V3 * per
         cols = self.N * len(self.taus) * self.n_ops * 192
-        return "proj_insertion", 8.0 * n_mom * int(np.prod(self.L)) * cols
+        return "proj_insertion", 8.0 * n_mom * V3 * cols
 
     def config(self, n_mom):
         return {"workload": self.name, "L": list(self.L), "T": self.T, "t_f": self.t_f, "n_noise": self.N,
@@ -235,9 +275,12 @@ class Meson8(Meson32):
         c.insertion(self.G3, self.s, self.taus, k, g, out=self.I)
         c.combine(self.S, self.I, out=self.C)
 
-    def dominant(self, n_mom):
+    def dominant(self, n_mom, proj):
+        V3 = int(np.prod(self.L))
+        if proj == "fac":
+            return "fac_insertion", self.N * len(self.taus) * V3 * CONTRACTION_FLOPS["insertion_local"]
         cols = self.N * len(self.taus) * 192
-        return "proj_insertion", 8.0 * n_mom * int(np.prod(self.L)) * cols
+        return "proj_insertion", 8.0 * n_mom * V3 * cols
 
     def cpu_sample(self, k, n_slices):
         import c3pt_synth as syn
@@ -268,7 +311,7 @@ class Nucleon48(Meson32):
     n_ops = 1
     cfg = 3
     dtype = "c64"
-    default_proj = "bf16x2"
+    default_proj = "fac"
 
     def __init__(self, args):
         self.baryon = True
@@ -321,9 +364,12 @@ class Nucleon48(Meson32):
         V3 = int(np.prod(self.L))
         return 2 * self.N * V3 * n_mom * 3072 + 2 * self.N * len(self.taus) * V3 * n_mom * 192
 
-    def dominant(self, n_mom):
+    def dominant(self, n_mom, proj):
+        V3 = int(np.prod(self.L))
+        if proj == "fac":
+            return "fac_spectator_baryon", 16 * self.N * V3 * CONTRACTION_FLOPS["spectator_baryon"]
         cols = self.N * 3072
-        return "proj_spectator_baryon", 8.0 * n_mom * int(np.prod(self.L)) * cols
+        return "proj_spectator_baryon", 8.0 * n_mom * V3 * cols
 
     def cpu_sample(self, k, n_slices):
         import c3pt_synth as syn
@@ -360,7 +406,7 @@ class Batch64:
     n_ops = 1
     cfg = 4
     dtype = "c64"
-    default_proj = "f16x2"
+    default_proj = "fac"
     default_steps = 3
     default_warmup = 1
 
@@ -409,6 +455,7 @@ class Batch64:
         pairs_m = pairs_diag_or_zero(n_mom)
         pairs_n = np.array([(0, q) for q in range(7)], dtype=np.int32)
         self.src = self.sources()
+        self.proj = geom.proj
         jobs, combs, self.plain_calls = [], [], []
         self.flops = {"spectator_meson": 0.0, "spectator_baryon": 0.0, "insertion": 0.0}
         self.units_total = 0
@@ -422,13 +469,16 @@ class Batch64:
                 flav["d"] = {t: draw((12, 12, V3), seed(syn.FIELD_G1, t)) for t in s["taus"]}
             base = dict(L=L, T=T, r=s["r"])
             n_tau, tf = len(s["taus"]), s["t_f"]
-            ins_flops = 8.0 * n_mom * V3 * N * n_tau * 192
+            dense = self.proj != 3
+            ins_flops = (8.0 * n_mom * 192 if dense else CONTRACTION_FLOPS["insertion_local"]) * V3 * N * n_tau
+            mes_flops = (8.0 * n_mom * 192 if dense else CONTRACTION_FLOPS["spectator_meson"]) * V3 * N
+            bar_flops = (8.0 * n_mom * 3072 if dense else 16 * CONTRACTION_FLOPS["spectator_baryon"]) * V3 * N
             if not s["nucleon"]:
                 G = flav["u"]
                 jobs.append(dict(kind="spectator_meson", G=G[tf], eta=eta, **base))
                 jobs.append(dict(kind="insertion", G_t=G, s_t=sl, taus=s["taus"], n_ops=1, **base))
                 combs.append({"spec": len(jobs) - 2, "ins": len(jobs) - 1, "pairs": pairs_m})
-                self.flops["spectator_meson"] += 8.0 * n_mom * V3 * N * 192
+                self.flops["spectator_meson"] += mes_flops
                 self.flops["insertion"] += ins_flops
                 self.units_total += N * V3 * n_mom * (1 + n_tau)
             else:
@@ -441,7 +491,7 @@ class Batch64:
                 # proton isovector: (u,u) spectator with the d insertion, (u,d) with the u insertion
                 combs.append({"spec": n - 4, "ins": n - 1, "pairs": pairs_n})
                 combs.append({"spec": n - 3, "ins": n - 2, "pairs": pairs_n})
-                self.flops["spectator_baryon"] += 2 * 8.0 * n_mom * V3 * N * 3072
+                self.flops["spectator_baryon"] += 2 * bar_flops
                 self.flops["insertion"] += 2 * ins_flops
                 self.units_total += 2 * N * V3 * n_mom * (1 + n_tau)
         torch.cuda.synchronize()
@@ -625,14 +675,19 @@ def serve_units(spec, momenta):
     return f * spec["N"] * spec["L"] ** 3 * n_mom * (1 + spec["n_tau"])
 
 
-def serve_flops(spec, momenta, prefix="serve_proj_"):
-    """Algorithmic projection flops per producer kind (8 real flops per complex MAC)."""
-    n_mom, V3, N = momenta[spec["n2"]], spec["L"] ** 3, spec["N"]
+def serve_flops(spec, momenta, proj):
+    """Algorithmic flops per producer kind: projection flops (8 per site,
+    momentum and column) for the dense forms, contraction flops for the
+    factored form."""
+    n_mom, V3, N, nt = momenta[spec["n2"]], spec["L"] ** 3, spec["N"], spec["n_tau"]
+    if proj == "fac":
+        p, cm, cb, ci = ("serve_fac_", CONTRACTION_FLOPS["spectator_meson"],
+                         16 * CONTRACTION_FLOPS["spectator_baryon"], CONTRACTION_FLOPS["insertion_local"])
+    else:
+        p, cm, cb, ci = "serve_proj_", 8.0 * n_mom * 192, 8.0 * n_mom * 3072, 8.0 * n_mom * 192
     if spec["kind"] == "nucleon":
-        return {prefix + "spectator_baryon": 2 * 8.0 * n_mom * V3 * N * 3072,
-                prefix + "insertion": 2 * 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
-    return {prefix + "spectator_meson": 8.0 * n_mom * V3 * N * 192,
-            prefix + "insertion": 8.0 * n_mom * V3 * N * spec["n_tau"] * 192}
+        return {p + "spectator_baryon": 2 * cb * V3 * N, p + "insertion": 2 * ci * V3 * N * nt}
+    return {p + "spectator_meson": cm * V3 * N, p + "insertion": ci * V3 * N * nt}
 
 
 def serve_main(args):
@@ -640,7 +695,7 @@ def serve_main(args):
     import paper_1711_02384_amd as c3pt
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    proj = args.proj or "f16x2"
+    proj = args.proj or "fac"
     proj_flag = {"f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16, "f16x2": c3pt.PROJ_SPLIT_F16,
                  "fac": c3pt.PROJ_FACTORED}[proj]
     lattices = [int(x) for x in args.lattices.split(",")]
@@ -714,11 +769,12 @@ def serve_main(args):
     prof = c3pt.profile_read(reset=True)
     kflops = {}
     for sp in prof_specs:
-        for kn, f in serve_flops(sp, momenta, "serve_fac_" if proj == "fac" else "serve_proj_").items():
+        for kn, f in serve_flops(sp, momenta, proj).items():
             kflops[kn] = kflops.get(kn, 0.0) + f
     kname = max((kn for kn in kflops if kn in prof), key=lambda kn: prof[kn]["total_ms"])
-    achieved = kflops[kname] / (prof[kname]["total_ms"] * 1e-3) / 1e12
-    peak = PEAK[proj]
+    launches = prof[kname]["count"]
+    roof = roofline_entry(kname, kflops[kname] / launches, prof[kname]["avg_ms"], proj)
+    roof["kernel"] += ", over a profiled closed batch"
 
     levels = []
     for li, rho in enumerate(loads):
@@ -763,10 +819,7 @@ def serve_main(args):
         "load_levels": levels,
         "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
         "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": f"{kname} (fused contraction + {proj} MFMA projection), over a profiled closed batch",
-                     "avg_ms": round(prof[kname]["avg_ms"], 4)},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a host sample")
@@ -866,7 +919,6 @@ def main():
     c3pt.profile_enable(False)
     prof = c3pt.profile_read(reset=True)
 
-    peak = PEAK[proj]
     if batched:
         # dominant = the projection kernel kind with the most time per step
         kf = {kn: f for kn, f in W.kernel_flops().items() if kn in prof and f > 0}
@@ -875,18 +927,9 @@ def main():
         flops = kf[kname] / launches
         kms = prof[kname]["total_ms"] / prof[kname]["count"]
     else:
-        kname, flops = W.dominant(n_mom)
-        if proj == "fac":
-            kname = "fac_" + kname[len("proj_"):]
+        kname, flops = W.dominant(n_mom, proj)
         kms = prof.get(kname, {}).get("avg_ms", float("nan"))
-    achieved = flops / (kms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": f"{kname} (fused contraction + {proj} MFMA projection)",
-                "flops_per_launch": flops, "avg_ms": round(kms, 4)}
-    if proj in ("bf16x2", "f16x2"):
-        roofline["note"] = ("flops counted once per complex MAC (8 real flops); the hi+lo split issues "
-                            "3 MFMA products per term, so MFMA issue is 3x the counted flops")
+    roofline = roofline_entry(kname, flops, kms, proj)
 
     plain = None
     if batched and W.plain:

@@ -401,13 +401,14 @@ int factor_plan_table(const FactorPlan& plan, bool f64, hipStream_t st, const vo
     return C3PT_OK;
 }
 
-// x3 planes per chunk of the factored projection: enough chunks to give the
-// chip several workgroups per CU.
-void plan_planes(int L3, int n_colblocks, int* chunk_planes, int* n_chunks) {
-    int chunks = std::max(1, (1024 + n_colblocks - 1) / n_colblocks);
-    chunks = std::min(chunks, L3);
-    *chunk_planes = (L3 + chunks - 1) / chunks;
-    *n_chunks = (L3 + *chunk_planes - 1) / *chunk_planes;
+// x3 planes per chunk of the factored projection: about 2048 sites (the
+// workgroups that share a slice then keep its chunk in one XCD's L2), fewer
+// when the launch would otherwise leave CUs idle.
+void plan_planes(const int L[3], int n_colblocks, int* chunk_planes, int* n_chunks) {
+    int cp = std::max(1, std::min(L[2], 2048 / (L[0] * L[1])));
+    while (cp > 1 && (long long)n_colblocks * ((L[2] + cp - 1) / cp) < 2048) cp = (cp + 1) / 2;
+    *chunk_planes = cp;
+    *n_chunks = (L[2] + cp - 1) / cp;
 }
 
 // Sites per split-site chunk: enough chunks to fill the chip, never more than
@@ -446,7 +447,7 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
     const bool want_fac = g->proj == C3PT_PROJ_FACTORED;
     int chunk_sites, n_chunks_dense, chunk_planes, n_chunks_fac;
     plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks_dense);
-    plan_planes(g->L[2], n_colblocks, &chunk_planes, &n_chunks_fac);
+    plan_planes(g->L, n_colblocks, &chunk_planes, &n_chunks_fac);
     const size_t gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
     const size_t bytes = (size_t)std::max(n_chunks_dense, want_fac ? n_chunks_fac : 0) * n_colblocks * gmax *
                          kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));

@@ -163,8 +163,8 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             d.group_cols = J.kind == C3PT_JOB_SPECTATOR_MESON ? kBlockCols : 3072;
         }
         if (fac) {
-            // chunks of x3 planes (about 4096 sites), summed in place
-            d.chunk_sites = std::max(1, std::min(d.L[2], 4096 / (d.L[0] * d.L[1])));   // planes per chunk
+            // chunks of x3 planes (about 2048 sites), summed in place
+            d.chunk_sites = std::max(1, std::min(d.L[2], 2048 / (d.L[0] * d.L[1])));   // planes per chunk
             d.n_chunks = (d.L[2] + d.chunk_sites - 1) / d.chunk_sites;
         } else {
             d.n_chunks = (d.V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;

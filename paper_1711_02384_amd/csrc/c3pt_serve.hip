@@ -730,11 +730,11 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
             return reject("missing neighbour slice for the derivative operators");
     }
     if (sv->fac) {
-        // chunks of x3 planes (about 4096 sites), summed in place
+        // chunks of x3 planes (about 2048 sites), summed in place
         FactorPlan plan;
         if (!api_factor_plan(q->L, +1, q->k.data(), q->n_mom, &plan))
             return reject("the momentum list does not factor (too many distinct k1 or (k1, k2))");
-        q->chunk_sites = std::max(1, std::min(q->L[2], 4096 / (q->L[0] * q->L[1])));
+        q->chunk_sites = std::max(1, std::min(q->L[2], 2048 / (q->L[0] * q->L[1])));
         q->n_chunks = (q->L[2] + q->chunk_sites - 1) / q->chunk_sites;
     } else {
         q->n_chunks = (q->V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;

@@ -191,8 +191,8 @@ def test_batch_alone_vs_mix_and_budget_groups(proj):
     for lat in lats:
         for kind_cols in ((16 if lat.baryon else 1) * lat.N, lat.N * len(lat.taus) * lat.n_ops):
             V3 = int(np.prod(lat.L))
-            if proj == 3:   # factored: chunks of x3 planes of about 4096 sites
-                planes = max(1, min(lat.L[2], 4096 // (lat.L[0] * lat.L[1])))
+            if proj == 3:   # factored: chunks of x3 planes of about 2048 sites
+                planes = max(1, min(lat.L[2], 2048 // (lat.L[0] * lat.L[1])))
                 n_chunks = -(-lat.L[2] // planes)
             else:
                 n_chunks = -(-V3 // 2048)
