@@ -3,7 +3,7 @@
 The GPU computes every part of the step; the FP64 oracle recomputes sampled
 outputs (selected timeslices, noise vectors or momenta) one by one.
 
-* 32^3 x 64 meson step (FP32): spectator (all outputs), insertion with the
+* 32^3 x 64 meson step (FP32, dense and factored projection): spectator (all outputs), insertion with the
   five operators at tau = 0, 8, 16 (the full 17-slice launch runs on the GPU),
   and the combine on sampled pairs built from the oracle's own parts.
 * 48^3 x 64 nucleon step with split-precision projection (BF16 and FP16 hi+lo):
@@ -30,7 +30,8 @@ def _up(a):
     return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64))).cuda()
 
 
-def test_meson32_step_sampled():
+@pytest.mark.parametrize("proj,name", [(0, "dense f32"), (3, "factored")])
+def test_meson32_step_sampled(proj, name):
     import paper_1711_02384_amd as c3pt
     L, T, N, t_f, cfg = (32, 32, 32), 64, 4, 16, 2
     taus = list(range(17))
@@ -43,22 +44,22 @@ def test_meson32_step_sampled():
     G3 = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in gsl}
     s = {t: syn.round_to_c64(syn.solution_slice(L, N, cfg, t)) for t in taus}
     U = {t: syn.round_to_c64(syn.link_slice(L, cfg, t)) for t in usl}
-    geom = c3pt.Geom(L, T)
-    _say("meson32: GPU step")
+    geom = c3pt.Geom(L, T, proj=proj)
+    _say(f"meson32 {name}: GPU step")
     S = c3pt.spectator_meson(_up(G1), _up(eta), k, geom)
     I = c3pt.insertion({t: _up(v) for t, v in G3.items()}, {t: _up(v) for t, v in s.items()}, taus, k, geom,
                        U_t={t: _up(v) for t, v in U.items()}, n_ops=5)
     torch.cuda.synchronize()
     S_o = oracle.spectator_meson(G1, eta, L, k)
     err = rel_fro(S.cpu().numpy(), S_o)
-    _say(f"meson32: spectator rel err {err:.2e}")
+    _say(f"meson32 {name}: spectator rel err {err:.2e}")
     assert err < TOL32
     Ih = I.cpu().numpy()
     for tau in (0, 8, 16):
         I_o = oracle.insertion(G3, s, [tau], L, T, k, U_t=U, n_ops=5)
         for op in range(5):
             e = rel_fro(Ih[:, tau, op], I_o[:, 0, op])
-            _say(f"meson32: insertion tau={tau} op={op} rel err {e:.2e}")
+            _say(f"meson32 {name}: insertion tau={tau} op={op} rel err {e:.2e}")
             assert e < TOL32
     # combine on sampled pairs, from the oracle's parts (checks the full-size launch shape)
     pairs = [(0, 0), (40, 40), (80, 3), (0, 80)]
@@ -67,7 +68,7 @@ def test_meson32_step_sampled():
     assert rel_fro(C, oracle.combine(S_o, I8, pairs=pairs)) < 1e-12
 
 
-@pytest.mark.parametrize("proj,name", [(2, "bf16x2"), (1, "f16x2")])
+@pytest.mark.parametrize("proj,name", [(2, "bf16x2"), (1, "f16x2"), (3, "factored")])
 def test_nucleon48_split_sampled(proj, name):
     import paper_1711_02384_amd as c3pt
     L, T, N, t_f, cfg = (48, 48, 48), 64, 8, 14, 3
