@@ -50,7 +50,7 @@ struct FacSmem {
     // they fit (filled once per work item), else the current tile's (slot 0)
     R A1[FacLimits<R>::kSegs][KS][64];
     C2<R> R2[FacLimits<R>::kPairs][kBlockCols];   // stage-2 sums of a plane, gathered for stage 3
-    C2<R> coef2[FacLimits<R>::kPairs];            // w2^(k2_b x2) of the current row
+    C2<R> coef2[FacLimits<R>::kPairs + kFacMaxBPerA];   // w2^(k2_b x2) of the current row, zero-padded
     C2<R> root[3][kMaxL];
     FactorPlan plan;
 };
@@ -180,7 +180,8 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         if (!a1_all)
             for (int e = tid; e < KS * 64; e += NT) sm.A1[0][e >> 6][e & 63] = fac_a1<R, KT>(sm, s, e >> 6, e & 63, L1, inv1);
         if (row_end)
-            for (int b = tid; b < n12; b += NT) sm.coef2[b] = sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)];
+            for (int b = tid; b < n12 + kFacMaxBPerA; b += NT)
+                sm.coef2[b] = b < n12 ? sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)] : C2<R>{0, 0};
         Prod::store(ctx, tg, s + L1 * (x2 + L2 * x3), nsite, rg, psm, sink, tid);
         if (T + 1 < n_tiles) {
             int sn, x2n, x3n;
@@ -197,9 +198,10 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
+                // all kFacMaxBPerA slots are updated (no divergent branch); slots
+                // beyond this lane's pairs are never gathered
 #pragma unroll
-                for (int i = 0; i < kFacMaxBPerA; ++i)
-                    if (i < nb[h]) r2[h][i] = cfma(r2[h][i], sm.coef2[bs[h] + i], v);
+                for (int i = 0; i < kFacMaxBPerA; ++i) r2[h][i] = cfma(r2[h][i], sm.coef2[bs[h] + i], v);
             }
             r1 = acc_t{0, 0, 0, 0};
             if (x2 == L2 - 1) {
@@ -207,11 +209,10 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
-                    for (int i = 0; i < kFacMaxBPerA; ++i)
-                        if (i < nb[h]) {
-                            sm.R2[bs[h] + i][col] = r2[h][i];
-                            r2[h][i] = C2<R>{0, 0};
-                        }
+                    for (int i = 0; i < kFacMaxBPerA; ++i) {
+                        if (i < nb[h]) sm.R2[bs[h] + i][col] = r2[h][i];
+                        r2[h][i] = C2<R>{0, 0};
+                    }
             }
         }
         __syncthreads();
@@ -313,7 +314,9 @@ __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg)
     for (;;) {
         if (tid == 0) s_item = atomicAdd(bg.counter, 1);
         __syncthreads();
-        const int it = s_item;
+        // the item is the same for the whole workgroup: make that visible to the
+        // compiler so that everything derived from it stays in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it >= bg.n_items) break;
         const int4 item = bg.items[it];

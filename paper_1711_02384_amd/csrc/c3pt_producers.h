@@ -16,6 +16,15 @@ struct PerThread {
     static constexpr int value = (N + NT - 1) / NT;
 };
 
+// Element idx of a field, or zero when !ok, without a branch: the load always
+// runs (at element 0 when it is not wanted) and the value is selected after.
+// Indices are unsigned 32-bit: 144 * V3 < 2^32 for every allowed extent.
+template <typename R>
+__device__ __forceinline__ C2<R> ld_or_zero(const C2<R>* p, unsigned idx, bool ok) {
+    const C2<R> v = p[ok ? idx : 0u];
+    return ok ? v : C2<R>{0, 0};
+}
+
 // ---------------------------------------------------------------------------
 // Meson spectator, Eq. (9):
 //   P[(b',a',a,c)] = g[b'] g[a'] g[a] sum_c' eta[(b',c')] conj(G[(a',c')][(a,c)])
@@ -48,14 +57,14 @@ struct MesonSpecProducer {
     }
     static __device__ __forceinline__ void load(const Ctx& c, const TileGeom& tg, int t0, int nsite, Regs& rg,
                                                 int tid) {
-        const size_t V3 = (size_t)tg.V3;
+        const unsigned V3 = (unsigned)tg.V3;
         const int j = tid % KT;
         const bool site_ok = j < nsite;
-        const size_t n = (size_t)t0 + j;
+        const unsigned n = (unsigned)(t0 + j);
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
             const int e = tid + i * NT, A = e / KT;
-            rg.v[i] = (e < 12 * KT && site_ok) ? c.eta[(size_t)A * V3 + n] : C2<R>{0, 0};
+            rg.v[i] = ld_or_zero(c.eta, (unsigned)A * V3 + n, e < 12 * KT && site_ok);
         }
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
@@ -64,7 +73,7 @@ struct MesonSpecProducer {
             const bool ok = e < 48 * KT && site_ok;
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc)
-                rg.g[i][cc] = ok ? c.G[(size_t)((3 * ap + cc) * 12 + rem) * V3 + n] : C2<R>{0, 0};
+                rg.g[i][cc] = ld_or_zero(c.G, (unsigned)((3 * ap + cc) * 12 + rem) * V3 + n, ok);
         }
     }
     template <class Sink>
@@ -135,23 +144,21 @@ struct BaryonSpecProducer {
     }
     static __device__ __forceinline__ void load(const Ctx& c, const TileGeom& tg, int t0, int nsite, Regs& rg,
                                                 int tid) {
-        const size_t V3 = (size_t)tg.V3;
+        const unsigned V3 = (unsigned)tg.V3;
         const int j = tid % KT;
         const bool site_ok = j < nsite;
-        const size_t n = (size_t)t0 + j;
+        const unsigned n = (unsigned)(t0 + j);
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
             const int e = tid + i * NT, A = e / KT;
-            C2<R> v = {0, 0};
-            if (e < 21 * KT && site_ok) {
-                if (A < 12) {
-                    v = c.eta[(size_t)A * V3 + n];
-                } else {
-                    const int cc = A - 12;
-                    v = c.G1[(size_t)((3 * c.a1p + cc / 3) * 12 + 3 * c.a1 + cc % 3) * V3 + n];
-                }
-            }
-            rg.v[i] = v;
+            const bool ok = e < 21 * KT && site_ok;
+            // entries 0..11: the noise vector; 12..20: the G1 block of (a1', a1)
+            const bool is_eta = A < 12;
+            const int cc = is_eta ? 0 : A - 12;
+            const C2<R>* base = is_eta ? c.eta : c.G1;
+            const unsigned idx = is_eta ? (unsigned)A * V3 + n
+                                        : (unsigned)((3 * c.a1p + cc / 3) * 12 + 3 * c.a1 + cc % 3) * V3 + n;
+            rg.v[i] = ld_or_zero(base, idx, ok);
         }
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
@@ -160,8 +167,7 @@ struct BaryonSpecProducer {
             const bool ok = e < 16 * KT && site_ok;
 #pragma unroll
             for (int cc = 0; cc < 9; ++cc)
-                rg.g2[i][cc] = ok ? c.G2[(size_t)((3 * a2p + cc / 3) * 12 + 3 * a2 + cc % 3) * V3 + n]
-                                  : C2<R>{0, 0};
+                rg.g2[i][cc] = ld_or_zero(c.G2, (unsigned)((3 * a2p + cc / 3) * 12 + 3 * a2 + cc % 3) * V3 + n, ok);
         }
     }
     template <class Sink>
@@ -287,14 +293,14 @@ struct InsertionProducerT {
     }
     static __device__ __forceinline__ void load(const Ctx& c, const TileGeom& tg, int t0, int nsite, Regs& rg,
                                                 int tid) {
-        const size_t V3 = (size_t)tg.V3;
+        const unsigned V3 = (unsigned)tg.V3;
         const int j = tid % KT;
         const bool site_ok = j < nsite;
         const int n = t0 + j;
 #pragma unroll
         for (int i = 0; i < kV; ++i) {
             const int e = tid + i * NT, A = e / KT;
-            rg.v[i] = (e < 12 * KT && site_ok) ? c.s[(size_t)A * V3 + n] : C2<R>{0, 0};
+            rg.v[i] = ld_or_zero(c.s, (unsigned)A * V3 + (unsigned)n, e < 12 * KT && site_ok);
         }
         if (OPS == 1 || (OPS == 0 && c.nu < 0)) {
 #pragma unroll
@@ -304,7 +310,7 @@ struct InsertionProducerT {
                 const bool ok = e < 48 * KT && site_ok;
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
-                    rg.g[i][cc] = ok ? c.Gf[(size_t)((3 * bt + cc) * 12 + rem) * V3 + n] : C2<R>{0, 0};
+                    rg.g[i][cc] = ld_or_zero(c.Gf, (unsigned)((3 * bt + cc) * 12 + rem) * V3 + (unsigned)n, ok);
             }
             return;
         }
@@ -326,8 +332,8 @@ struct InsertionProducerT {
             const bool ok = e < 12 * KT && site_ok;
 #pragma unroll
             for (int cc = 0; cc < 3; ++cc) {
-                rg.u[i][cc] = ok ? c.U[(size_t)(cc * 3 + d) * V3 + n] : C2<R>{0, 0};
-                rg.u[i][3 + cc] = ok ? c.Um[(size_t)(d * 3 + cc) * V3 + nm] : C2<R>{0, 0};
+                rg.u[i][cc] = ld_or_zero(c.U, (unsigned)(cc * 3 + d) * V3 + (unsigned)n, ok);
+                rg.u[i][3 + cc] = ld_or_zero(c.Um, (unsigned)(d * 3 + cc) * V3 + (unsigned)nm, ok);
             }
         }
 #pragma unroll
@@ -337,9 +343,9 @@ struct InsertionProducerT {
             const bool ok = e < 48 * KT && site_ok;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const size_t plane = (size_t)((3 * bt + d) * 12 + rem) * V3;
-                rg.g[i][d] = ok ? c.Gf[plane + np] : C2<R>{0, 0};
-                rg.g[i][3 + d] = ok ? c.Gb[plane + nm] : C2<R>{0, 0};
+                const unsigned plane = (unsigned)((3 * bt + d) * 12 + rem) * V3;
+                rg.g[i][d] = ld_or_zero(c.Gf, plane + (unsigned)np, ok);
+                rg.g[i][3 + d] = ld_or_zero(c.Gb, plane + (unsigned)nm, ok);
             }
         }
         }

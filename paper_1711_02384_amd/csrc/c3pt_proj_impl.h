@@ -361,7 +361,9 @@ __global__ void __launch_bounds__(Cons::NT, Cons::MINW) batch_kernel(BatchGrid b
     for (;;) {
         if (tid == 0) s_item = atomicAdd(bg.counter, 1);
         __syncthreads();
-        const int it = s_item;
+        // the item is the same for the whole workgroup: make that visible to the
+        // compiler so that everything derived from it stays in scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it >= bg.n_items) break;
         const int4 item = bg.items[it];
