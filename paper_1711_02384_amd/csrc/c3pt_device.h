@@ -29,6 +29,11 @@ template <typename R>
 __device__ __forceinline__ C2<R> cfma(C2<R> acc, C2<R> a, C2<R> b) {
     return {acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
 }
+// acc - a * b
+template <typename R>
+__device__ __forceinline__ C2<R> cfnma(C2<R> acc, C2<R> a, C2<R> b) {
+    return {acc.x - a.x * b.x + a.y * b.y, acc.y - a.x * b.y - a.y * b.x};
+}
 template <typename R>
 __device__ __forceinline__ C2<R> cscale(C2<R> a, R s) { return {a.x * s, a.y * s}; }
 
@@ -92,6 +97,10 @@ __device__ __forceinline__ int div_small(int n, int d, float invd) {
 struct TileGeom {
     int V3, L1, L2, L3;
     float inv1, inv12;
+    // Tiles that are one segment of an x1 row set row = 1 and give the
+    // coordinates of the tile's first site; producers then take neighbour
+    // sites from them instead of dividing the site index.
+    int row, x1, x2, x3;
 };
 
 // Site n -> (x1, x2, x3).

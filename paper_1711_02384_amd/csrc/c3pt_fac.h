@@ -166,10 +166,15 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         x2 = row % L2;
         x3 = p0 + row / L2;
     };
+    TileGeom tr = tg;   // tiles are row segments: producers take coordinates from the origin
+    tr.row = 1;
     if (n_tiles > 0) {
         int seg, x2, x3;
         tile_of(0, seg, x2, x3);
-        Prod::load(ctx, tg, seg * KT + L1 * (x2 + L2 * x3), min(KT, L1 - seg * KT), rg, tid);
+        tr.x1 = seg * KT;
+        tr.x2 = x2;
+        tr.x3 = x3;
+        Prod::load(ctx, tr, seg * KT + L1 * (x2 + L2 * x3), min(KT, L1 - seg * KT), rg, tid);
     }
     for (int T = 0; T < n_tiles; ++T) {
         int seg, x2, x3;
@@ -186,7 +191,10 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         if (T + 1 < n_tiles) {
             int sn, x2n, x3n;
             tile_of(T + 1, sn, x2n, x3n);
-            Prod::load(ctx, tg, sn * KT + L1 * (x2n + L2 * x3n), min(KT, L1 - sn * KT), rg, tid);
+            tr.x1 = sn * KT;
+            tr.x2 = x2n;
+            tr.x3 = x3n;
+            Prod::load(ctx, tr, sn * KT + L1 * (x2n + L2 * x3n), min(KT, L1 - sn * KT), rg, tid);
         }
         __syncthreads();
         // stage 1
@@ -288,6 +296,7 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     tg.L3 = pa.L[2];
     tg.inv1 = 1.0f / (float)tg.L1;
     tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+    tg.row = tg.x1 = tg.x2 = tg.x3 = 0;
     fac_setup<R, KT>(sm, (const FactorPlan*)pg.phase, tid, kFacThreads);
     C2<R> out[FacLimits<R>::kOut];
     if (ACC) {
@@ -330,6 +339,7 @@ __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg)
         tg.L3 = job.L[2];
         tg.inv1 = 1.0f / (float)tg.L1;
         tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+        tg.row = tg.x1 = tg.x2 = tg.x3 = 0;
         fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
         const int p0 = item.z * job.chunk_sites;
         const int p1 = min(tg.L3, p0 + job.chunk_sites);

@@ -245,6 +245,7 @@ struct InsertionProducerT {
         const C2<R>* Um;    // U_nu(y - nu) (time: slice tau - 1)
         int nu;             // -1 for the local operator
     };
+    static constexpr bool kFullT = 48 * KT == kT * NT;   // every thread has kT contraction tasks
     static constexpr int kG = OPS == 1 ? 3 : 6;
     static constexpr int kU = OPS == 1 ? 1 : 6;
     struct Regs {
@@ -307,7 +308,7 @@ struct InsertionProducerT {
             for (int i = 0; i < kT; ++i) {
                 const int e = tid + i * NT, q = e / KT;
                 const int bt = q / 12, rem = q % 12;
-                const bool ok = e < 48 * KT && site_ok;
+                const bool ok = (kFullT || e < 48 * KT) && site_ok;
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc)
                     rg.g[i][cc] = ld_or_zero(c.Gf, (unsigned)((3 * bt + cc) * 12 + rem) * V3 + (unsigned)n, ok);
@@ -318,9 +319,16 @@ struct InsertionProducerT {
         const int nu = c.nu;
         int np = n, nm = n;
         if (nu < 3) {
-            int x0[3], x1, x2, x3;
-            site_xyz(tg, t0, x0[0], x0[1], x0[2]);
-            site_xyz_from(tg, x0, j, x1, x2, x3);
+            int x1, x2, x3;
+            if (tg.row) {
+                x1 = tg.x1 + j;
+                x2 = tg.x2;
+                x3 = tg.x3;
+            } else {
+                int x0[3];
+                site_xyz(tg, t0, x0[0], x0[1], x0[2]);
+                site_xyz_from(tg, x0, j, x1, x2, x3);
+            }
             np = site_shift_xyz(tg, x1, x2, x3, nu, +1);
             nm = site_shift_xyz(tg, x1, x2, x3, nu, -1);
             if (!site_ok) np = nm = t0;
@@ -340,7 +348,7 @@ struct InsertionProducerT {
         for (int i = 0; i < kT; ++i) {
             const int e = tid + i * NT, q = e / KT;
             const int bt = q / 12, rem = q % 12;
-            const bool ok = e < 48 * KT && site_ok;
+            const bool ok = (kFullT || e < 48 * KT) && site_ok;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const unsigned plane = (unsigned)((3 * bt + d) * 12 + rem) * V3;
@@ -367,7 +375,7 @@ struct InsertionProducerT {
 #pragma unroll
             for (int i = 0; i < kT; ++i) {
                 const int e = tid + i * NT, q = e / KT;
-                if (e >= 48 * KT) continue;
+                if (!kFullT && e >= 48 * KT) continue;
 #pragma unroll
                 for (int at = 0; at < 4; ++at) {
                     C2<R> p = cmul(sm.v[3 * at][j], rg.g[i][0]);
@@ -399,14 +407,15 @@ struct InsertionProducerT {
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
             const int e = tid + i * NT, q = e / KT;
-            if (e >= 48 * KT) continue;
+            if (!kFullT && e >= 48 * KT) continue;
 #pragma unroll
             for (int at = 0; at < 4; ++at) {
-                C2<R> p = {0, 0};
+                C2<R> p = cmul(sm.tp[3 * at][j], rg.g[i][0]);
+                p = cfnma(p, sm.tm[3 * at][j], rg.g[i][3]);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
+                for (int d = 1; d < 3; ++d) {
                     p = cfma(p, sm.tp[3 * at + d][j], rg.g[i][d]);
-                    p = csub(p, cmul(sm.tm[3 * at + d][j], rg.g[i][3 + d]));
+                    p = cfnma(p, sm.tm[3 * at + d][j], rg.g[i][3 + d]);
                 }
                 sink.put(at * 48 + q, j, p);
             }

@@ -331,6 +331,7 @@ proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::A
     tg.L3 = pa.L[2];
     tg.inv1 = 1.0f / (float)tg.L1;
     tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+    tg.row = tg.x1 = tg.x2 = tg.x3 = 0;
 
     typename Cons::Acc acc;
     Cons::zero(acc);
@@ -377,6 +378,7 @@ __global__ void __launch_bounds__(Cons::NT, Cons::MINW) batch_kernel(BatchGrid b
         tg.L3 = job.L[2];
         tg.inv1 = 1.0f / (float)tg.L1;
         tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+    tg.row = tg.x1 = tg.x2 = tg.x3 = 0;
         typename Cons::Acc acc;
         Cons::zero(acc);
         const int s_lo = chunk * job.chunk_sites;
