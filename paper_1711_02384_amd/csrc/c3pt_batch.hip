@@ -327,7 +327,6 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         for (int kind = 0; kind < kQueueKinds; ++kind) {
             if (kind == 3 && !fac) continue;
-            bool kt32 = true;
             // Issue order: largest job first; within a job, items that read the
             // same input slice and site chunk are adjacent, so they run together
             // and share its cache lines.
@@ -336,7 +335,6 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
                 const BatchJob& d = hj[i].d;
                 if (d.kind != std::min(kind, 2)) continue;
                 if (kind == 3 && d.n_ops == 1) continue;
-                kt32 = kt32 && d.L[0] % 32 == 0;
                 const int n_share = d.kind == 2 ? d.n_tau : 1;
                 const int n_within = d.n_colblocks / n_share;
                 const int n_item_chunks = d.n_chunks;
@@ -354,14 +352,13 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             if (int rc = dmalloc(b, &dev, items.size() * sizeof(int4))) return bail(rc);
             if (int rc = upload_sync(dev, items.data(), items.size() * sizeof(int4), st)) return bail(rc);
             // persistent grid: as many workgroups as fit on the chip at once
-            // (factored queues: variant = 32-site tiles)
-            const int variant = fac ? (kt32 ? 1 : 0) : api_variant(kind, mode, mt);
+            const int variant = fac ? 0 : api_variant(kind, mode, mt);
             hipError_t e = hipSuccess;
             int per_cu;
             if (fac)
-                per_cu = kind == 0   ? batch_fac_meson(kt32, nullptr, 0, st, &e)
-                         : kind == 1 ? batch_fac_baryon(kt32, nullptr, 0, st, &e)
-                                     : batch_fac_insertion(kind == 2 ? 1 : 2, kt32, nullptr, 0, st, &e);
+                per_cu = kind == 0   ? batch_fac_meson(nullptr, 0, st, &e)
+                         : kind == 1 ? batch_fac_baryon(nullptr, 0, st, &e)
+                                     : batch_fac_insertion(kind == 2 ? 1 : 2, nullptr, 0, st, &e);
             else
                 per_cu = kind == 0   ? batch_meson(mode, mt, variant, nullptr, 0, st, &e)
                          : kind == 1 ? batch_baryon(mode, mt, variant, nullptr, 0, st, &e)
@@ -436,10 +433,9 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             b->ops.push_back({fac ? kFacName[kind] : kProjName[kind], [=](hipStream_t s) {
                                   hipError_t e = hipSuccess;
                                   if (fac) {
-                                      const bool kt32 = variant == 1;
-                                      if (kind == 0) batch_fac_meson(kt32, &bg, n_wg, s, &e);
-                                      else if (kind == 1) batch_fac_baryon(kt32, &bg, n_wg, s, &e);
-                                      else batch_fac_insertion(kind == 2 ? 1 : 2, kt32, &bg, n_wg, s, &e);
+                                      if (kind == 0) batch_fac_meson(&bg, n_wg, s, &e);
+                                      else if (kind == 1) batch_fac_baryon(&bg, n_wg, s, &e);
+                                      else batch_fac_insertion(kind == 2 ? 1 : 2, &bg, n_wg, s, &e);
                                   } else if (kind == 0) {
                                       batch_meson(mode, mt, variant, &bg, n_wg, s, &e);
                                   } else if (kind == 1) {

@@ -25,7 +25,7 @@
 
 #include <type_traits>
 
-#include "c3pt_producers.h"
+#include "c3pt_fac_prod.h"
 
 namespace c3pt {
 
@@ -43,24 +43,17 @@ template <> struct FacLimits<double> {
 
 template <typename R, int KT>
 struct FacSmem {
-    static constexpr int PST = 2 * KT + 2;     // column stride of P (R elements); = 2 mod 32
+    static constexpr int PST = 2 * KT + 2;     // slot stride of P (R elements); = 2 mod 32
     static constexpr int KS = 2 * KT / 4;      // MFMA K steps per tile
-    R P[kBlockCols * PST];                     // P[col][2 * site + re/im]
-    // stage-1 A operands [segment][K step][lane]: all segments of a row when
-    // they fit (filled once per work item), else the current tile's (slot 0)
-    R A1[FacLimits<R>::kSegs][KS][64];
+    static constexpr int kA1 = FacLimits<R>::kSegs > 2 ? FacLimits<R>::kSegs : 2;
+    R P[kBlockCols * PST];                     // P[slot][2 * site + re/im], slots owned by waves
+    // stage-1 A operands [slot][K step][lane]: every segment of a row when they
+    // fit (filled once per work item), else two slots alternating by tile
+    R A1[kA1][KS][64];
     C2<R> R2[FacLimits<R>::kPairs][kBlockCols];   // stage-2 sums of a plane, gathered for stage 3
-    C2<R> coef2[FacLimits<R>::kPairs + kFacMaxBPerA];   // w2^(k2_b x2) of the current row, zero-padded
+    C2<R> coef2[2][FacLimits<R>::kPairs + kFacMaxBPerA];   // w2^(k2_b x2), by row parity, zero-padded
     C2<R> root[3][kMaxL];
     FactorPlan plan;
-};
-
-template <typename R, int KT>
-struct FacSink {
-    R* P;
-    __device__ __forceinline__ void put(int col, int j, C2<R> v) {
-        *(C2<R>*)&P[col * FacSmem<R, KT>::PST + 2 * j] = v;
-    }
 };
 
 // Stage-1 A row r of a 16-row tile -> (k1 index a, part re/im), chosen so that
@@ -76,7 +69,7 @@ __device__ __forceinline__ void fac_row(int r, int& a, int& part) {
     }
 }
 
-// Plan into LDS, root tables, R2 cleared.  Ends with a barrier.
+// Plan into LDS, root tables.  Ends with a barrier.
 template <typename R, int KT>
 __device__ __forceinline__ void fac_setup(FacSmem<R, KT>& sm, const FactorPlan* gplan, int tid, int NT) {
     const int* src = (const int*)gplan;
@@ -97,14 +90,15 @@ __device__ __forceinline__ void fac_setup(FacSmem<R, KT>& sm, const FactorPlan* 
     __syncthreads();
 }
 
-// Stage-1 A operand of row segment s: value for (K step ks, lane al).
+// Stage-1 A operand of the row segment starting at x1 = s: value for (K step
+// ks, lane al).  Zero for sites past the row end (their P slots hold copies).
 template <typename R, int KT>
 __device__ __forceinline__ R fac_a1(const FacSmem<R, KT>& sm, int s, int ks, int al, int L1, float inv1) {
     int a, part;
     fac_row<R>(al & 15, a, part);
     const int kk = al >> 4;
     const int j = 2 * ks + (kk >> 1), comp = kk & 1;
-    if (a >= sm.plan.n1) return (R)0;
+    if (a >= sm.plan.n1 || s + j >= L1) return (R)0;
     const C2<R> w = sm.root[0][mod_small(sm.plan.k1[a] * (s + j), L1, inv1)];
     return part == 0 ? (comp == 0 ? w.x : -w.y) : (comp == 0 ? w.y : w.x);
 }
@@ -112,30 +106,54 @@ __device__ __forceinline__ R fac_a1(const FacSmem<R, KT>& sm, int s, int ks, int
 // Partial-sum element type.
 template <typename R> using Part2 = typename std::conditional<sizeof(R) == 8, double2, float2>::type;
 
+// Orders this wave's LDS writes before its later LDS reads of other lanes'
+// data (no workgroup barrier: the data never leaves the wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum over the tiles of planes [p0, p1).  ACC: into out (thread-owned
 // momenta), written by fac_write at the end.  Otherwise every plane's sums are
 // added into the chunk's partial sums in global memory (written at the first
 // plane, read back and added at the next ones; each element is owned by one
 // thread of one workgroup, so the order is fixed); out is unused.
+//
+// Software pipeline, one workgroup barrier per tile T:
+//   contract(T) -> P (own slots) | stage(T+1) -> buf[(T+1)&1] | loads of T+2 |
+//   stage 1 (MFMA on own slots) | stage 2 at row ends | barrier | stage 3 at plane ends
+// The per-site buffers, the row coefficients and (for long rows) the A
+// operands are written one tile ahead into the half not being read.  The
+// contraction inputs are held in two register sets (tiles T and T+1) so that
+// their loads have a whole tile to arrive.
 template <typename R, int KT, bool ACC, class Prod>
 __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const TileGeom& tg, FacSmem<R, KT>& sm,
-                                         typename Prod::Smem& psm, int p0, int p1,
+                                         typename Prod::Buf (&buf)[2], int p0, int p1,
                                          C2<R> (&out)[FacLimits<R>::kOut], void* partial, int n_colblocks,
                                          int cb, int chunk, int tid) {
     using MF = Mfma<R>;
     using acc_t = typename MF::acc_t;
-    constexpr int NT = kFacThreads;
+    using S = typename Prod::S;
     constexpr int KS = FacSmem<R, KT>::KS;
     constexpr int PST = FacSmem<R, KT>::PST;
+    constexpr int NT = kFacThreads;
     const int L1 = tg.L1, L2 = tg.L2, L3 = tg.L3;
     const float inv1 = 1.0f / (float)L1, inv2 = 1.0f / (float)L2, inv3 = 1.0f / (float)L3;
     const int nseg = (L1 + KT - 1) / KT;
     const bool a1_all = nseg <= FacLimits<R>::kSegs;
     const int n_tiles = (p1 - p0) * L2 * nseg;
+    if (n_tiles <= 0) return;
     const int lane = tid & 63, wave = tid >> 6, g = lane >> 4;
-    const int col = 16 * wave + (lane & 15);
+    const int slot = 16 * wave + (lane & 15);     // this lane's MFMA column
+    int lcol;                                     // its column in the block
+    {
+        int X, r;
+        S::of_slot(slot, X, r);
+        lcol = Prod::col(X, r);
+    }
     const int n_mom = sm.plan.n_mom, n12 = sm.plan.n12;
-    // stage-2 ownership: k1 indices 2g, 2g+1 of column col, their pairs in registers
+    // stage-2 ownership: k1 indices 2g, 2g+1 of column lcol, their pairs in registers
     int bs[2], nb[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -151,80 +169,110 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     // stage-3 ownership
     const int c3 = tid % kBlockCols, q3 = tid / kBlockCols;
 
-    if (a1_all) {
-        for (int e = tid; e < nseg * KS * 64; e += NT) {
-            const int seg = e / (KS * 64), rem = e % (KS * 64);
-            sm.A1[seg][rem >> 6][rem & 63] = fac_a1<R, KT>(sm, seg * KT, rem >> 6, rem & 63, L1, inv1);
-        }
-    }
-    acc_t r1 = acc_t{0, 0, 0, 0};
-    typename Prod::Regs rg;
-    FacSink<R, KT> sink{sm.P};
     auto tile_of = [&](int T, int& seg, int& x2, int& x3) {
         seg = T % nseg;
         const int row = T / nseg;
         x2 = row % L2;
         x3 = p0 + row / L2;
     };
-    TileGeom tr = tg;   // tiles are row segments: producers take coordinates from the origin
-    tr.row = 1;
-    if (n_tiles > 0) {
-        int seg, x2, x3;
-        tile_of(0, seg, x2, x3);
-        tr.x1 = seg * KT;
-        tr.x2 = x2;
-        tr.x3 = x3;
-        Prod::load(ctx, tr, seg * KT + L1 * (x2 + L2 * x3), min(KT, L1 - seg * KT), rg, tid);
-    }
-    for (int T = 0; T < n_tiles; ++T) {
+    const int jt = tid % KT;
+    auto site_of = [&](int T) {
         int seg, x2, x3;
         tile_of(T, seg, x2, x3);
-        const int s = seg * KT;
-        const int nsite = min(KT, L1 - s);
+        RowSite rs;
+        rs.x1 = min(seg * KT + jt, L1 - 1);
+        rs.x2 = x2;
+        rs.x3 = x3;
+        rs.n = rs.x1 + L1 * (x2 + L2 * x3);
+        return rs;
+    };
+    auto fill_a1 = [&](int slot_a, int s) {
+        for (int e = tid; e < KS * 64; e += NT) sm.A1[slot_a][e >> 6][e & 63] = fac_a1<R, KT>(sm, s, e >> 6, e & 63, L1, inv1);
+    };
+    auto fill_coef2 = [&](int par, int x2) {
+        for (int b = tid; b < n12 + kFacMaxBPerA; b += NT)
+            sm.coef2[par][b] = b < n12 ? sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)] : C2<R>{0, 0};
+    };
+    FacPut<R, KT> put{sm.P, PST};
+    typename Prod::Pre pre;
+    typename Prod::Main m0, m1;
+
+    // prologue: tile 0 staged, contraction inputs of tiles 0 and 1 and
+    // per-site inputs of tile 1 in flight
+    if (a1_all) {
+        for (int e = tid; e < nseg * KS * 64; e += NT) {
+            const int seg = e / (KS * 64), rem = e % (KS * 64);
+            sm.A1[seg][rem >> 6][rem & 63] = fac_a1<R, KT>(sm, seg * KT, rem >> 6, rem & 63, L1, inv1);
+        }
+    } else {
+        fill_a1(0, 0);
+    }
+    {
+        const RowSite rs0 = site_of(0);
+        fill_coef2(0, rs0.x2);
+        // same issue order as the loop (per-site inputs, then contraction inputs)
+        Prod::load_pre(ctx, tg, rs0, pre, tid);
+        Prod::load_main(ctx, tg, rs0, m0, tid);
+        Prod::stage(ctx, pre, buf[0], tid);
+        const RowSite rs1 = site_of(min(1, n_tiles - 1));
+        Prod::load_pre(ctx, tg, rs1, pre, tid);
+        Prod::load_main(ctx, tg, rs1, m1, tid);
+    }
+    acc_t r1 = acc_t{0, 0, 0, 0};
+    __syncthreads();
+
+    auto step = [&](int T, typename Prod::Main& mc) {
+        const int par = T & 1;
+        int seg, x2, x3;
+        tile_of(T, seg, x2, x3);
         const bool row_end = (seg == nseg - 1);
-        if (!a1_all)
-            for (int e = tid; e < KS * 64; e += NT) sm.A1[0][e >> 6][e & 63] = fac_a1<R, KT>(sm, s, e >> 6, e & 63, L1, inv1);
-        if (row_end)
-            for (int b = tid; b < n12 + kFacMaxBPerA; b += NT)
-                sm.coef2[b] = b < n12 ? sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)] : C2<R>{0, 0};
-        Prod::store(ctx, tg, s + L1 * (x2 + L2 * x3), nsite, rg, psm, sink, tid);
+        const bool plane_end = row_end && x2 == L2 - 1;
+        // contraction of tile T into this wave's slots
+        Prod::contract(ctx, mc, buf[par], put, tid);
+        // tile T+1: per-site buffer, row coefficients, A operands
         if (T + 1 < n_tiles) {
+            Prod::stage(ctx, pre, buf[par ^ 1], tid);
             int sn, x2n, x3n;
             tile_of(T + 1, sn, x2n, x3n);
-            tr.x1 = sn * KT;
-            tr.x2 = x2n;
-            tr.x3 = x3n;
-            Prod::load(ctx, tr, sn * KT + L1 * (x2n + L2 * x3n), min(KT, L1 - sn * KT), rg, tid);
+            if (sn == 0) fill_coef2(((T + 1) / nseg) & 1, x2n);
+            if (!a1_all) fill_a1(par ^ 1, sn * KT);
         }
-        __syncthreads();
-        // stage 1
-        const int slot = a1_all ? seg : 0;
+        // loads for tile T+2 (the last tile again past the end: always in bounds)
+        {
+            const RowSite rs2 = site_of(min(T + 2, n_tiles - 1));
+            Prod::load_pre(ctx, tg, rs2, pre, tid);
+            Prod::load_main(ctx, tg, rs2, mc, tid);
+        }
+        wave_lds_sync();
+        // stage 1 on this wave's own slots
+        const int sa = a1_all ? seg : par;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) r1 = MF::mac(sm.A1[slot][ks][lane], sm.P[col * PST + 4 * ks + g], r1);
+        for (int ks = 0; ks < KS; ++ks) r1 = MF::mac(sm.A1[sa][ks][lane], sm.P[slot * PST + 4 * ks + g], r1);
         if (row_end) {
             // stage 2, in registers
+            const C2<R>* cf = sm.coef2[(T / nseg) & 1];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
                 // all kFacMaxBPerA slots are updated (no divergent branch); slots
                 // beyond this lane's pairs are never gathered
 #pragma unroll
-                for (int i = 0; i < kFacMaxBPerA; ++i) r2[h][i] = cfma(r2[h][i], sm.coef2[bs[h] + i], v);
+                for (int i = 0; i < kFacMaxBPerA; ++i) r2[h][i] = cfma(r2[h][i], cf[bs[h] + i], v);
             }
             r1 = acc_t{0, 0, 0, 0};
-            if (x2 == L2 - 1) {
+            if (plane_end) {
                 // plane x3 done: gather the stage-2 sums for stage 3
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int i = 0; i < kFacMaxBPerA; ++i) {
-                        if (i < nb[h]) sm.R2[bs[h] + i][col] = r2[h][i];
+                        if (i < nb[h]) sm.R2[bs[h] + i][lcol] = r2[h][i];
                         r2[h][i] = C2<R>{0, 0};
                     }
             }
         }
         __syncthreads();
-        if (row_end && x2 == L2 - 1) {
+        if (plane_end) {
             // stage 3
             if (ACC) {
 #pragma unroll
@@ -253,9 +301,18 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
                     dst = Part2<R>{v.x, v.y};
                 }
             }
-            // R2 is rewritten only at the next plane end, after further barriers
+            // R2 is gathered again only after this barrier
+            __syncthreads();
         }
+    };
+    // pairs of tiles without a branch between them (the load counters of the
+    // two register sets are then tracked exactly), an odd last tile after
+    int T = 0;
+    for (; T + 1 < n_tiles; T += 2) {
+        step(T, m0);
+        step(T + 1, m1);
     }
+    if (T < n_tiles) step(T, m0);
 }
 
 template <typename R>
@@ -277,7 +334,7 @@ __global__ void __launch_bounds__(kFacThreads, 1)
 fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     using Prod = ProdT<R, KT, kFacThreads>;
     __shared__ FacSmem<R, KT> sm;
-    __shared__ typename Prod::Smem psm;
+    __shared__ typename Prod::Buf buf[2];
     const int tid = threadIdx.x;
     // work item; consecutive items (same input slice and chunk) on one XCD
     const int nw = gridDim.x, w = blockIdx.x;
@@ -305,7 +362,7 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     }
     const int p0 = chunk * pg.chunk_planes;
     const int p1 = min(tg.L3, p0 + pg.chunk_planes);
-    fac_loop<R, KT, ACC, Prod>(ctx, tg, sm, psm, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
+    fac_loop<R, KT, ACC, Prod>(ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
     if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
 }
 
@@ -316,7 +373,7 @@ template <typename R, int KT, template <typename, int, int> class ProdT>
 __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg) {
     using Prod = ProdT<R, KT, kFacThreads>;
     __shared__ FacSmem<R, KT> sm;
-    __shared__ typename Prod::Smem psm;
+    __shared__ typename Prod::Buf buf[2];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     C2<R> out[FacLimits<R>::kOut];   // not used by the plane-chunk form
@@ -343,7 +400,7 @@ __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg)
         fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
         const int p0 = item.z * job.chunk_sites;
         const int p1 = min(tg.L3, p0 + job.chunk_sites);
-        fac_loop<R, KT, false, Prod>(ctx, tg, sm, psm, p0, p1, out, job.partial, job.n_colblocks, cb, item.z, tid);
+        fac_loop<R, KT, false, Prod>(ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb, item.z, tid);
         __syncthreads();
     }
 }
@@ -369,14 +426,16 @@ hipError_t launch_fac_kt(const ProjGrid& pg, const typename ProdT<R, KT, kFacThr
     return hipGetLastError();
 }
 
-// FP32: 32-site tiles when whole rows split into them (and the producer fits
-// its registers at that size), else 16; FP64: 16.  acc selects the form that
-// sums a chunk's planes in registers.
-template <template <typename, int, int> class ProdT, class Args>
-hipError_t launch_fac(bool f64, bool acc, const ProjGrid& pg, const Args& a, hipStream_t st, bool allow32 = true) {
+// FP32: 32-site tiles when whole rows split into them and the producer keeps
+// its registers at that size (kAllow32), else 16; FP64: 16.  acc selects the
+// form that sums a chunk's planes in registers.
+template <template <typename, int, int> class ProdT, bool kAllow32, class Args>
+hipError_t launch_fac(bool f64, bool acc, const ProjGrid& pg, const Args& a, hipStream_t st) {
     if (f64) return acc ? launch_fac_kt<double, 16, true, ProdT>(pg, a, st) : launch_fac_kt<double, 16, false, ProdT>(pg, a, st);
-    if (allow32 && a.L[0] % 32 == 0)
-        return acc ? launch_fac_kt<float, 32, true, ProdT>(pg, a, st) : launch_fac_kt<float, 32, false, ProdT>(pg, a, st);
+    if constexpr (kAllow32) {
+        if (a.L[0] % 32 == 0)
+            return acc ? launch_fac_kt<float, 32, true, ProdT>(pg, a, st) : launch_fac_kt<float, 32, false, ProdT>(pg, a, st);
+    }
     return acc ? launch_fac_kt<float, 16, true, ProdT>(pg, a, st) : launch_fac_kt<float, 16, false, ProdT>(pg, a, st);
 }
 

@@ -192,12 +192,11 @@ hipError_t launch_fac_baryon(bool f64, bool acc, const ProjGrid& pg, const Baryo
 // ops: 1 local operator only, 2 derivative operators only (a.op_lo / a.op_cnt select them)
 hipError_t launch_fac_insertion(bool f64, bool acc, int ops, const ProjGrid& pg, const InsertionArgs& a,
                                 hipStream_t st);
-// Persistent factored launches (FP32) over batch items; kt32 selects 32-site
-// tiles (every job's L1 a multiple of 32).  With bg == nullptr only the
-// occupancy (workgroups per CU) is returned.
-int batch_fac_meson(bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
-int batch_fac_baryon(bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
-int batch_fac_insertion(int ops, bool kt32, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+// Persistent factored launches (FP32, 16-site tiles) over batch items.  With
+// bg == nullptr only the occupancy (workgroups per CU) is returned.
+int batch_fac_meson(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+int batch_fac_baryon(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+int batch_fac_insertion(int ops, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
 // Factor plan of a momentum list for extents L and sign sigma (FP32 limits);
 // false if the list needs more distinct k1 / (k1, k2) than the kernel holds.
 bool api_factor_plan(const int L[3], int sigma, const int* k, int n_mom, FactorPlan* plan);

@@ -463,8 +463,7 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
                     const int cb = d.kind == 2 ? ((w / d.n_ops) * d.n_tau + sh) * d.n_ops + op : w;
                     std::pair<int, int> key;
                     if (sv->fac) {
-                        const int qk = d.kind < 2 ? d.kind : (op == 0 ? 2 : 3);
-                        key = {qk, (qk != 3 && d.L[0] % 32 == 0) ? 1 : 0};
+                        key = {d.kind < 2 ? d.kind : (op == 0 ? 2 : 3), 0};
                     } else {
                         key = {d.kind, mt_class(mt)};
                     }
@@ -486,7 +485,7 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         for (const int4& it4 : kv.second) hi[n_items++] = it4;
         const int kind = kv.first.first;
         const int mt = list_mt[kv.first];
-        const int variant = sv->fac ? kv.first.second : api_variant(kind, sv->mode, mt);
+        const int variant = sv->fac ? 0 : api_variant(kind, sv->mode, mt);
         launches.push_back({kind, mt, item0, n_items - item0, variant});
     }
     std::vector<int> job_order(chosen.size());
@@ -523,12 +522,11 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         bg.n_items = (int)L.n;
         bg.counter = sv->counters + li;
         hipError_t e = hipSuccess;
-        const bool kt32 = L.variant == 1;
         int per_cu;
         if (sv->fac)
-            per_cu = L.kind == 0   ? batch_fac_meson(kt32, nullptr, 0, st, &e)
-                     : L.kind == 1 ? batch_fac_baryon(kt32, nullptr, 0, st, &e)
-                                   : batch_fac_insertion(L.kind == 2 ? 1 : 2, kt32, nullptr, 0, st, &e);
+            per_cu = L.kind == 0   ? batch_fac_meson(nullptr, 0, st, &e)
+                     : L.kind == 1 ? batch_fac_baryon(nullptr, 0, st, &e)
+                                   : batch_fac_insertion(L.kind == 2 ? 1 : 2, nullptr, 0, st, &e);
         else
             per_cu = L.kind == 0   ? batch_meson(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
                      : L.kind == 1 ? batch_baryon(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
@@ -537,9 +535,9 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         okk = run(sv->fac ? kFacName[L.kind] : kName[L.kind], [&] {
             hipError_t e2 = hipSuccess;
             if (sv->fac) {
-                if (L.kind == 0) batch_fac_meson(kt32, &bg, n_wg, st, &e2);
-                else if (L.kind == 1) batch_fac_baryon(kt32, &bg, n_wg, st, &e2);
-                else batch_fac_insertion(L.kind == 2 ? 1 : 2, kt32, &bg, n_wg, st, &e2);
+                if (L.kind == 0) batch_fac_meson(&bg, n_wg, st, &e2);
+                else if (L.kind == 1) batch_fac_baryon(&bg, n_wg, st, &e2);
+                else batch_fac_insertion(L.kind == 2 ? 1 : 2, &bg, n_wg, st, &e2);
             } else if (L.kind == 0) {
                 batch_meson(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
             } else if (L.kind == 1) {
