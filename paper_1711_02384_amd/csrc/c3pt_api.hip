@@ -318,6 +318,7 @@ bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGro
     p->sigma = sigma;
     p->n_mom = mg.n;
     const int max_pairs = f64 ? kFacMaxPairsF64 : kFacMaxPairsF32;
+    // distinct k1, and the distinct k2 of each
     std::vector<int> k1s;
     std::vector<std::vector<int>> k2s;
     std::vector<int> am(mg.n), jm(mg.n);
@@ -326,32 +327,45 @@ bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGro
         const int r1 = posmod(km[0], g->L[0]), r2 = posmod(km[1], g->L[1]);
         int a = (int)(std::find(k1s.begin(), k1s.end(), r1) - k1s.begin());
         if (a == (int)k1s.size()) {
-            if ((int)k1s.size() == kFacMaxK1) return false;
             k1s.push_back(r1);
             k2s.emplace_back();
         }
         int jj = (int)(std::find(k2s[a].begin(), k2s[a].end(), r2) - k2s[a].begin());
-        if (jj == (int)k2s[a].size()) {
-            if ((int)k2s[a].size() == kFacMaxBPerA) return false;
-            k2s[a].push_back(r2);
-        }
+        if (jj == (int)k2s[a].size()) k2s[a].push_back(r2);
         am[m] = a;
         jm[m] = jj;
         p->k3[m] = posmod(km[2], g->L[2]);
     }
-    int nb = 0;
+    // slots: a k1 with n pairs takes ceil(n / kFacMaxBPerA) slots of nearly equal size
+    std::vector<int> first_slot(k1s.size()), parts(k1s.size());
+    int n_slots = 0, nb = 0;
     for (size_t a = 0; a < k1s.size(); ++a) {
-        p->k1[a] = k1s[a];
-        p->bstart[a] = nb;
-        for (int v : k2s[a]) {
-            if (nb == max_pairs) return false;
-            p->k2[nb++] = v;
+        const int n = (int)k2s[a].size();
+        parts[a] = (n + kFacMaxBPerA - 1) / kFacMaxBPerA;
+        first_slot[a] = n_slots;
+        n_slots += parts[a];
+        nb += n;
+    }
+    if (n_slots > kFacMaxK1 || nb > max_pairs) return false;
+    // pair (a, jj) -> slot first_slot[a] + jj / per, position jj % per
+    nb = 0;
+    for (size_t a = 0; a < k1s.size(); ++a) {
+        const int n = (int)k2s[a].size(), per = (n + parts[a] - 1) / parts[a];
+        for (int s = 0; s < parts[a]; ++s) {
+            const int slot = first_slot[a] + s;
+            p->k1[slot] = k1s[a];
+            p->bstart[slot] = nb;
+            for (int jj = s * per; jj < std::min(n, (s + 1) * per); ++jj) p->k2[nb++] = k2s[a][jj];
+            p->nbmax = std::max(p->nbmax, nb - p->bstart[slot]);
         }
     }
-    p->n1 = (int)k1s.size();
+    p->n1 = n_slots;
     for (int a = p->n1; a <= kFacMaxK1; ++a) p->bstart[a] = nb;
     p->n12 = nb;
-    for (int m = 0; m < mg.n; ++m) p->pair_of_m[m] = p->bstart[am[m]] + jm[m];
+    for (int m = 0; m < mg.n; ++m) {
+        const int a = am[m], n = (int)k2s[a].size(), per = (n + parts[a] - 1) / parts[a];
+        p->pair_of_m[m] = p->bstart[first_slot[a] + jm[m] / per] + jm[m] % per;
+    }
     return true;
 }
 

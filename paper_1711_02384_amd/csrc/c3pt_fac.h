@@ -125,9 +125,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 //   stage 1 (MFMA on own slots) | stage 2 at row ends | barrier | stage 3 at plane ends
 // The per-site buffers, the row coefficients and (for long rows) the A
 // operands are written one tile ahead into the half not being read.  The
-// contraction inputs are held in two register sets (tiles T and T+1) so that
-// their loads have a whole tile to arrive.
-template <typename R, int KT, bool ACC, class Prod>
+// contraction inputs are held in three register sets (tiles T, T+1, T+2) so
+// that their loads have more than a tile to arrive.  EARLY waves issue the
+// loads of tile T+2 before their contraction, the others after it: the
+// address units then work while part of the workgroup computes, instead of
+// all waves issuing their loads at once.
+template <typename R, int KT, bool ACC, bool EARLY, class Prod>
 __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const TileGeom& tg, FacSmem<R, KT>& sm,
                                          typename Prod::Buf (&buf)[2], int p0, int p1,
                                          C2<R> (&out)[FacLimits<R>::kOut], void* partial, int n_colblocks,
@@ -153,6 +156,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         lcol = Prod::col(X, r);
     }
     const int n_mom = sm.plan.n_mom, n12 = sm.plan.n12;
+    const int nbmax = __builtin_amdgcn_readfirstlane(sm.plan.nbmax);
     // stage-2 ownership: k1 indices 2g, 2g+1 of column lcol, their pairs in registers
     int bs[2], nb[2];
 #pragma unroll
@@ -195,7 +199,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     };
     FacPut<R, KT> put{sm.P, PST};
     typename Prod::Pre pre;
-    typename Prod::Main m0, m1;
+    typename Prod::Main m0, m1, m2;
 
     // prologue: tile 0 staged, contraction inputs of tiles 0 and 1 and
     // per-site inputs of tile 1 in flight
@@ -221,12 +225,16 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     acc_t r1 = acc_t{0, 0, 0, 0};
     __syncthreads();
 
-    auto step = [&](int T, typename Prod::Main& mc) {
+    // mc holds tile T's contraction inputs, mn receives those of tile T+2
+    auto step = [&](int T, typename Prod::Main& mc, typename Prod::Main& mn) {
         const int par = T & 1;
         int seg, x2, x3;
         tile_of(T, seg, x2, x3);
         const bool row_end = (seg == nseg - 1);
         const bool plane_end = row_end && x2 == L2 - 1;
+        // tile T+2 (the last tile again past the end: always in bounds)
+        const RowSite rs2 = site_of(min(T + 2, n_tiles - 1));
+        if (EARLY) Prod::load_main(ctx, tg, rs2, mn, tid);
         // contraction of tile T into this wave's slots
         Prod::contract(ctx, mc, buf[par], put, tid);
         // tile T+1: per-site buffer, row coefficients, A operands
@@ -237,12 +245,8 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
             if (sn == 0) fill_coef2(((T + 1) / nseg) & 1, x2n);
             if (!a1_all) fill_a1(par ^ 1, sn * KT);
         }
-        // loads for tile T+2 (the last tile again past the end: always in bounds)
-        {
-            const RowSite rs2 = site_of(min(T + 2, n_tiles - 1));
-            Prod::load_pre(ctx, tg, rs2, pre, tid);
-            Prod::load_main(ctx, tg, rs2, mc, tid);
-        }
+        Prod::load_pre(ctx, tg, rs2, pre, tid);
+        if (!EARLY) Prod::load_main(ctx, tg, rs2, mn, tid);
         wave_lds_sync();
         // stage 1 on this wave's own slots
         const int sa = a1_all ? seg : par;
@@ -254,21 +258,25 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
-                // all kFacMaxBPerA slots are updated (no divergent branch); slots
-                // beyond this lane's pairs are never gathered
+                // the first nbmax registers are updated in every lane (a uniform
+                // bound, no divergent branch); those beyond a lane's pairs are
+                // never gathered
 #pragma unroll
-                for (int i = 0; i < kFacMaxBPerA; ++i) r2[h][i] = cfma(r2[h][i], cf[bs[h] + i], v);
+                for (int i = 0; i < kFacMaxBPerA; ++i)
+                    if (i < nbmax) r2[h][i] = cfma(r2[h][i], cf[bs[h] + i], v);
             }
             r1 = acc_t{0, 0, 0, 0};
             if (plane_end) {
                 // plane x3 done: gather the stage-2 sums for stage 3
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < 2; ++h) {
+                    C2<R>* dst = &sm.R2[bs[h]][lcol];   // pair i at dst[i * kBlockCols]
 #pragma unroll
                     for (int i = 0; i < kFacMaxBPerA; ++i) {
-                        if (i < nb[h]) sm.R2[bs[h] + i][lcol] = r2[h][i];
+                        if (i < nb[h]) dst[i * kBlockCols] = r2[h][i];
                         r2[h][i] = C2<R>{0, 0};
                     }
+                }
             }
         }
         __syncthreads();
@@ -305,14 +313,22 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
             __syncthreads();
         }
     };
-    // pairs of tiles without a branch between them (the load counters of the
-    // two register sets are then tracked exactly), an odd last tile after
+    // three register sets in turn, without a branch between the steps (the
+    // load counters are then tracked exactly), the last one or two tiles after
     int T = 0;
-    for (; T + 1 < n_tiles; T += 2) {
-        step(T, m0);
-        step(T + 1, m1);
+    for (; T + 2 < n_tiles; T += 3) {
+        step(T, m0, m2);
+        step(T + 1, m1, m0);
+        step(T + 2, m2, m1);
     }
-    if (T < n_tiles) step(T, m0);
+    if (T < n_tiles) step(T, m0, m2);
+    if (T + 1 < n_tiles) step(T + 1, m1, m0);
+}
+
+// Waves 4..7 (one on each SIMD) load early.  Uniform per wave; both loop
+// forms pass the same workgroup barriers in the same order.
+__device__ __forceinline__ bool fac_early_wave(int tid) {
+    return __builtin_amdgcn_readfirstlane(tid >> 6) / 4 == 1;
 }
 
 template <typename R>
@@ -362,7 +378,10 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     }
     const int p0 = chunk * pg.chunk_planes;
     const int p1 = min(tg.L3, p0 + pg.chunk_planes);
-    fac_loop<R, KT, ACC, Prod>(ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
+    if (fac_early_wave(tid))
+        fac_loop<R, KT, ACC, true, Prod>(ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
+    else
+        fac_loop<R, KT, ACC, false, Prod>(ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
     if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
 }
 
@@ -400,7 +419,12 @@ __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg)
         fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
         const int p0 = item.z * job.chunk_sites;
         const int p1 = min(tg.L3, p0 + job.chunk_sites);
-        fac_loop<R, KT, false, Prod>(ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb, item.z, tid);
+        if (fac_early_wave(tid))
+            fac_loop<R, KT, false, true, Prod>(ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb,
+                                               item.z, tid);
+        else
+            fac_loop<R, KT, false, false, Prod>(ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb,
+                                                item.z, tid);
         __syncthreads();
     }
 }

@@ -38,16 +38,18 @@ struct PhaseSpec {
 // GEMM), over x2 for each distinct (k1, k2) pair, over x3 for each momentum.
 constexpr int kFacTile = 16;          // sites per tile: a segment of one x1 row
 constexpr int kFacThreads = 768;      // 12 waves, one 16-column tile each
-constexpr int kFacMaxK1 = 8;          // distinct k1: one MFMA row tile (8 x (re, im))
+constexpr int kFacMaxK1 = 8;          // k1 slots: one MFMA row tile (8 x (re, im))
 constexpr int kFacMaxPairsF32 = 48;   // distinct (k1, k2) pairs held in LDS
 constexpr int kFacMaxPairsF64 = 16;
-constexpr int kFacMaxBPerA = 8;       // distinct k2 per k1 (per-lane registers of stage 2)
+constexpr int kFacMaxBPerA = 6;       // pairs per k1 slot (per-lane registers of stage 2); a k1
+                                      // with more distinct k2 takes several slots
 struct FactorPlan {
     int L[3];
     int sigma;
     int n_mom, n1, n12;
-    int k1[kFacMaxK1];                // distinct k1 (reduced mod L1); index a
-    int bstart[kFacMaxK1 + 1];        // pairs of k1 index a: b in [bstart[a], bstart[a+1])
+    int nbmax;                        // largest number of pairs in one slot
+    int k1[kFacMaxK1];                // k1 of slot a (reduced mod L1)
+    int bstart[kFacMaxK1 + 1];        // pairs of slot a: b in [bstart[a], bstart[a+1])
     int k2[kFacMaxPairsF32];          // k2 of pair b (reduced mod L2)
     int pair_of_m[kMaxMomGroup];      // pair b of momentum m
     int k3[kMaxMomGroup];             // k3 of momentum m (reduced mod L3)
