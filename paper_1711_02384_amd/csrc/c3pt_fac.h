@@ -173,21 +173,30 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     // stage-3 ownership
     const int c3 = tid % kBlockCols, q3 = tid / kBlockCols;
 
-    auto tile_of = [&](int T, int& seg, int& x2, int& x3) {
-        seg = T % nseg;
-        const int row = T / nseg;
-        x2 = row % L2;
-        x3 = p0 + row / L2;
+    // Tile positions advance by counting (no division per tile): segment,
+    // row of the chunk (x2, x3) and row number (its parity picks the row
+    // coefficients).  Uniform, so they stay in scalar registers.
+    struct TilePos {
+        int seg, x2, x3, row;
+    };
+    auto advance = [&](TilePos q) {
+        if (++q.seg == nseg) {
+            q.seg = 0;
+            ++q.row;
+            if (++q.x2 == L2) {
+                q.x2 = 0;
+                ++q.x3;
+            }
+        }
+        return q;
     };
     const int jt = tid % KT;
-    auto site_of = [&](int T) {
-        int seg, x2, x3;
-        tile_of(T, seg, x2, x3);
+    auto site_of = [&](const TilePos& q) {
         RowSite rs;
-        rs.x1 = min(seg * KT + jt, L1 - 1);
-        rs.x2 = x2;
-        rs.x3 = x3;
-        rs.n = rs.x1 + L1 * (x2 + L2 * x3);
+        rs.x1 = min(q.seg * KT + jt, L1 - 1);
+        rs.x2 = q.x2;
+        rs.x3 = q.x3;
+        rs.n = rs.x1 + L1 * (q.x2 + L2 * q.x3);
         return rs;
     };
     auto fill_a1 = [&](int slot_a, int s) {
@@ -211,14 +220,18 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     } else {
         fill_a1(0, 0);
     }
+    // positions of tiles T, T+1, T+2 (the last tile again past the end)
+    TilePos pa = {0, 0, p0, 0};
+    TilePos pb = n_tiles > 1 ? advance(pa) : pa;
+    TilePos pc = n_tiles > 2 ? advance(pb) : pb;
     {
-        const RowSite rs0 = site_of(0);
+        const RowSite rs0 = site_of(pa);
         fill_coef2(0, rs0.x2);
         // same issue order as the loop (per-site inputs, then contraction inputs)
         Prod::load_pre(ctx, tg, rs0, pre, tid);
         Prod::load_main(ctx, tg, rs0, m0, tid);
         Prod::stage(ctx, pre, buf[0], tid);
-        const RowSite rs1 = site_of(min(1, n_tiles - 1));
+        const RowSite rs1 = site_of(pb);
         Prod::load_pre(ctx, tg, rs1, pre, tid);
         Prod::load_main(ctx, tg, rs1, m1, tid);
     }
@@ -228,22 +241,19 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     // mc holds tile T's contraction inputs, mn receives those of tile T+2
     auto step = [&](int T, typename Prod::Main& mc, typename Prod::Main& mn) {
         const int par = T & 1;
-        int seg, x2, x3;
-        tile_of(T, seg, x2, x3);
+        const int seg = pa.seg, x2 = pa.x2, x3 = pa.x3, row = pa.row;
         const bool row_end = (seg == nseg - 1);
         const bool plane_end = row_end && x2 == L2 - 1;
         // tile T+2 (the last tile again past the end: always in bounds)
-        const RowSite rs2 = site_of(min(T + 2, n_tiles - 1));
+        const RowSite rs2 = site_of(pc);
         if (EARLY) Prod::load_main(ctx, tg, rs2, mn, tid);
         // contraction of tile T into this wave's slots
         Prod::contract(ctx, mc, buf[par], put, tid);
         // tile T+1: per-site buffer, row coefficients, A operands
         if (T + 1 < n_tiles) {
             Prod::stage(ctx, pre, buf[par ^ 1], tid);
-            int sn, x2n, x3n;
-            tile_of(T + 1, sn, x2n, x3n);
-            if (sn == 0) fill_coef2(((T + 1) / nseg) & 1, x2n);
-            if (!a1_all) fill_a1(par ^ 1, sn * KT);
+            if (pb.seg == 0) fill_coef2(pb.row & 1, pb.x2);
+            if (!a1_all) fill_a1(par ^ 1, pb.seg * KT);
         }
         Prod::load_pre(ctx, tg, rs2, pre, tid);
         if (!EARLY) Prod::load_main(ctx, tg, rs2, mn, tid);
@@ -254,7 +264,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         for (int ks = 0; ks < KS; ++ks) r1 = MF::mac(sm.A1[sa][ks][lane], sm.P[slot * PST + 4 * ks + g], r1);
         if (row_end) {
             // stage 2, in registers
-            const C2<R>* cf = sm.coef2[(T / nseg) & 1];
+            const C2<R>* cf = sm.coef2[row & 1];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
@@ -312,6 +322,9 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
             // R2 is gathered again only after this barrier
             __syncthreads();
         }
+        pa = pb;
+        pb = pc;
+        if (T + 3 < n_tiles) pc = advance(pc);
     };
     // three register sets in turn, without a branch between the steps (the
     // load counters are then tracked exactly), the last one or two tiles after

@@ -299,7 +299,8 @@ struct FacInsDerivProd : InsertionProducerT<R, KT, NT, 2> {
         C2<R> tm[12][KT];
     };
     static __device__ __forceinline__ int col(int X, int r) { return X * 48 + r; }
-    // neighbour sites y +- nu (nu < 3; the time direction reads the adjacent slices at y)
+    // neighbour sites y +- nu (nu < 3, periodic; the time direction reads the
+    // adjacent slices at y itself)
     static __device__ __forceinline__ void nbr(const Ctx& c, const TileGeom& tg, const RowSite& rs, unsigned& np,
                                                unsigned& nm) {
         if (c.nu >= 3) {

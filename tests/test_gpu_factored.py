@@ -5,7 +5,9 @@ variant 1: chunks of planes summed in registers), 32-site tiles (x1 rows of
 32) and 16-site tiles (rows of 24, and rows shorter than a tile), complex128
 (FP64 MFMA, 1e-12) and complex64 (FP32 MFMA, 1e-5), several FP64 momentum
 groups, a source off the origin, and a momentum list with more distinct k1
-than the kernel holds (that group runs on the dense kernel).
+than the kernel holds (that group runs on the dense kernel).  The |k|^2 <= 9
+list has a k1 with seven distinct k2, more than one stage-1 slot keeps: it is
+split over two slots.
 """
 import numpy as np
 import pytest
@@ -32,6 +34,7 @@ CASES = [
     ((6, 5, 4), 6, [0, 3], 1, 3, True, (1, 0, 3)),       # rows shorter than a tile
     ((8, 8, 8), 6, [2], 1, 3, False, (3, 5, 1)),         # complex128, one FP64 group
     ((6, 5, 4), 6, [0, 4], 2, 5, False, (0, 1, 2)),      # complex128, two FP64 groups (57 momenta)
+    ((12, 8, 6), 4, [0, 2], 1, 9, True, (3, 1, 2)),      # |k|^2 <= 9: k1 = 0 has seven k2, two stage-1 slots
 ]
 
 
