@@ -197,6 +197,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         rs.x2 = q.x2;
         rs.x3 = q.x3;
         rs.n = rs.x1 + L1 * (q.x2 + L2 * q.x3);
+        Prod::prepare(ctx, rs);
         return rs;
     };
     auto fill_a1 = [&](int slot_a, int s) {

@@ -46,6 +46,7 @@ struct FacSlots {
 struct RowSite {
     int n;            // site index x1 + L1 (x2 + L2 x3)
     int x1, x2, x3;
+    unsigned np, nm;  // neighbours along the derivative direction (set by its prepare)
 };
 
 template <typename R, int KT>
@@ -70,6 +71,7 @@ struct FacMesonProd : MesonSpecProducer<R, KT, NT> {
     struct Main { C2<R> g[kT][3]; };
     struct Buf { C2<R> v[12][KT]; };
     static __device__ __forceinline__ int col(int X, int r) { return X * 48 + r; }
+    static __device__ __forceinline__ void prepare(const Ctx&, RowSite&) {}
     static __device__ __forceinline__ void load_pre(const Ctx& c, const TileGeom& tg, const RowSite& rs, Pre& p,
                                                     int tid) {
 #pragma unroll
@@ -137,6 +139,7 @@ struct FacBaryonProd : BaryonSpecProducer<R, KT, NT> {
         C2<R> g1[9][KT];
     };
     static __device__ __forceinline__ int col(int X, int r) { return ((r / 3) * 4 + X) * 3 + r % 3; }
+    static __device__ __forceinline__ void prepare(const Ctx&, RowSite&) {}
     static __device__ __forceinline__ void load_pre(const Ctx& c, const TileGeom& tg, const RowSite& rs, Pre& p,
                                                     int tid) {
         const unsigned V3 = (unsigned)tg.V3, n = (unsigned)rs.n;
@@ -227,6 +230,7 @@ struct FacInsLocalProd : InsertionProducerT<R, KT, NT, 1> {
     struct Main { C2<R> g[kT][3]; };
     struct Buf { C2<R> v[12][KT]; };
     static __device__ __forceinline__ int col(int X, int r) { return X * 48 + r; }
+    static __device__ __forceinline__ void prepare(const Ctx&, RowSite&) {}
     static __device__ __forceinline__ void load_pre(const Ctx& c, const TileGeom& tg, const RowSite& rs, Pre& p,
                                                     int tid) {
 #pragma unroll
@@ -285,7 +289,28 @@ template <typename R, int KT, int NT>
 struct FacInsDerivProd : InsertionProducerT<R, KT, NT, 2> {
     using Base = InsertionProducerT<R, KT, NT, 2>;
     using Args = typename Base::Args;
-    using Ctx = typename Base::Ctx;
+    // the base context plus the stride, extent and wrap (stride x extent) of
+    // direction nu in the site index (stride 0 for the time direction)
+    struct Ctx : Base::Ctx {
+        int st, ext, wrap;
+    };
+    static __device__ __forceinline__ Ctx with_dir(const typename Base::Ctx& b, const int (&L)[3]) {
+        Ctx c;
+        static_cast<typename Base::Ctx&>(c) = b;
+        // sums of products with direction flags: a select chain on nu would
+        // become a lookup table in memory
+        const int f0 = c.nu == 0, f1 = c.nu == 1, f2 = c.nu == 2;
+        c.st = f0 + f1 * L[0] + f2 * L[0] * L[1];
+        c.ext = f0 * L[0] + f1 * L[1] + (1 - f0 - f1) * L[2];
+        c.wrap = c.st * c.ext;
+        return c;
+    }
+    static __device__ __forceinline__ Ctx resolve(const Args& a, int V3, int cb) {
+        return with_dir(Base::resolve(a, V3, cb), a.L);
+    }
+    static __device__ __forceinline__ Ctx resolve(const BatchJob& b, int V3, int cb) {
+        return with_dir(Base::resolve(b, V3, cb), b.L);
+    }
     using S = FacSlots<KT, NT>;
     static constexpr int kP = PerThread<12 * KT, NT>::value;
     static constexpr int kT = S::kT;
@@ -299,22 +324,17 @@ struct FacInsDerivProd : InsertionProducerT<R, KT, NT, 2> {
         C2<R> tm[12][KT];
     };
     static __device__ __forceinline__ int col(int X, int r) { return X * 48 + r; }
-    // neighbour sites y +- nu (nu < 3, periodic; the time direction reads the
-    // adjacent slices at y itself)
-    static __device__ __forceinline__ void nbr(const Ctx& c, const TileGeom& tg, const RowSite& rs, unsigned& np,
-                                               unsigned& nm) {
-        if (c.nu >= 3) {
-            np = nm = (unsigned)rs.n;
-            return;
-        }
-        np = (unsigned)site_shift_xyz(tg, rs.x1, rs.x2, rs.x3, c.nu, +1);
-        nm = (unsigned)site_shift_xyz(tg, rs.x1, rs.x2, rs.x3, c.nu, -1);
+    // neighbour sites y +- nu of the thread's site, once per tile (periodic;
+    // the time direction reads the adjacent slices at y itself)
+    static __device__ __forceinline__ void prepare(const Ctx& c, RowSite& rs) {
+        const int f0 = c.nu == 0, f1 = c.nu == 1;
+        const int x = f0 * rs.x1 + f1 * rs.x2 + (1 - f0 - f1) * rs.x3;
+        rs.np = (unsigned)(rs.n + c.st - (x == c.ext - 1 ? c.wrap : 0));
+        rs.nm = (unsigned)(rs.n - c.st + (x == 0 ? c.wrap : 0));
     }
     static __device__ __forceinline__ void load_pre(const Ctx& c, const TileGeom& tg, const RowSite& rs, Pre& p,
                                                     int tid) {
-        const unsigned V3 = (unsigned)tg.V3, n = (unsigned)rs.n;
-        unsigned np, nm;
-        nbr(c, tg, rs, np, nm);
+        const unsigned V3 = (unsigned)tg.V3, n = (unsigned)rs.n, nm = rs.nm;
 #pragma unroll
         for (int i = 0; i < kP; ++i) {
             const int e = tid + i * NT, q = e / KT, at = q / 3, d = q % 3;
@@ -348,9 +368,7 @@ struct FacInsDerivProd : InsertionProducerT<R, KT, NT, 2> {
     }
     static __device__ __forceinline__ void load_main(const Ctx& c, const TileGeom& tg, const RowSite& rs, Main& m,
                                                      int tid) {
-        const unsigned V3 = (unsigned)tg.V3;
-        unsigned np, nm;
-        nbr(c, tg, rs, np, nm);
+        const unsigned V3 = (unsigned)tg.V3, np = rs.np, nm = rs.nm;
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
             const int r = (tid + i * NT) / KT, bt = r / 12, rem = r % 12;
