@@ -91,7 +91,41 @@ CONTRACTION_FLOPS = {"spectator_meson": 8.0 * 576, "spectator_baryon": 8.0 * 115
                      "insertion_local": 8.0 * 576, "insertion_deriv": 8.0 * (1152 + 72)}
 
 
-def roofline_entry(kname, flops, kms, proj):
+# HBM bytes per launch of the dominant kernel, measured with rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch, scaled by the plain-copy
+# calibration: x2 for FETCH_SIZE, x1 for WRITE_SIZE) on the workload's default
+# command; the summary with the full commands is in profiles/ under the kernel
+# and workload names.  Each entry carries a hash of the kernel sources it was
+# measured with and is reported only while they are unchanged.
+TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_device.h", "c3pt_internal.h",
+                   "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip", "c3pt_api.hip"]
+MEASURED_TRAFFIC = {
+    # workload, projection, timed kernel name -> (bytes per launch, source hash)
+    # 32^3 step: local (484219 + 264384 KiB) and derivative (1962840 + 1074940 KiB) dispatches of one call
+    ("meson32", "fac", "fac_insertion"): ((484219 + 1962840) * 2048 + (264384 + 1074940) * 1024, "4a944929d21525ba"),
+    # 48^3 step: one nucleon spectator dispatch (414787 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon"): (414787 * 2048 + 857088 * 1024, "4a944929d21525ba"),
+}
+
+
+def sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_02384_amd", "csrc")
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(base, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, proj, kname):
+    e = MEASURED_TRAFFIC.get((workload, proj, kname))
+    if e is None or e[1] != sources_hash():
+        return None
+    return e[0]
+
+
+def roofline_entry(kname, flops, kms, proj, traffic=None):
     """Roofline object: dense projections are MFMA-bound (projection flops
     against the MFMA peak of their type); factored ones are bound by the
     contraction's FP32 arithmetic (against the VALU peak)."""
@@ -103,7 +137,7 @@ def roofline_entry(kname, flops, kms, proj):
         peak, bound = PEAK[proj], "mfma"
         what = f"fused contraction + {proj} MFMA projection; flops = 8 per (site, momentum, column)"
     r = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-         "frac": round(achieved / peak, 4), "traffic": None, "kernel": f"{kname} ({what})",
+         "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": f"{kname} ({what})",
          "flops_per_launch": flops, "avg_ms": round(kms, 4)}
     if proj in ("bf16x2", "f16x2"):
         r["note"] = ("flops counted once per complex MAC (8 real flops); the hi+lo split issues "
@@ -929,7 +963,10 @@ def main():
     else:
         kname, flops = W.dominant(n_mom, proj)
         kms = prof.get(kname, {}).get("avg_ms", float("nan"))
-    roofline = roofline_entry(kname, flops, kms, proj)
+    roofline = roofline_entry(kname, flops, kms, proj, measured_traffic(args.workload, proj, kname))
+    if roofline["traffic"] is not None:
+        roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1 "
+                                    "(copy-calibrated), measured on these kernel sources")
 
     plain = None
     if batched and W.plain:
