@@ -152,6 +152,38 @@ int c3pt_combine(const void* spec, int spec_spin, const void* ins, int n_noise, 
                  int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
                  int n_pairs, void* out, void* stream);
 
+/*
+ * One meson measurement with time-partitioned noise, forward and backward
+ * diagrams together (Sec. 2.3, Fig. 6): the noise vectors are zero except on
+ * the two sink timeslices t_fwd = x'_4 and t_bwd = x''_4 on either side of the
+ * source timeslice t_src = r_4, and one stochastic solution per noise vector
+ * serves both diagrams.  The call runs
+ *   spectators : c3pt_spectator_meson at t_fwd (G_fwd, eta_fwd) and at t_bwd
+ *                (G_bwd, eta_bwd);
+ *   insertion  : c3pt_insertion at tau = t_fwd, t_fwd+1, ..., t_bwd (modulo T,
+ *                n_span = n_fwd + n_bwd - 1 slices);
+ *   combines   : forward  = S(t_fwd) x I(tau), tau = t_fwd .. t_src (n_fwd slices),
+ *                backward = S(t_bwd) x I(tau), tau = t_src .. t_bwd (n_bwd slices),
+ *                each as c3pt_combine over all n_ops operators;
+ * with n_fwd = ((t_src - t_fwd) mod T) + 1 and n_bwd = ((t_bwd - t_src) mod T) + 1,
+ * n_fwd + n_bwd - 1 <= T.  The source timeslice is in both windows.
+ *   G_fwd, G_bwd     : device propagator slices at the two sinks [12][12][V3].
+ *   eta_fwd, eta_bwd : device noise slices at the two sinks [n_noise][12][V3].
+ *   G_t, s_t, U_t, n_ops, k, n_mom : as for c3pt_insertion, needed on the span.
+ *   w, pairs, n_pairs : as for c3pt_combine with n_p = n_q = n_mom.
+ *   spec    : device complex128 [2][n_noise][n_mom][192], forward then backward
+ *             spectator (order as c3pt_spectator_meson).
+ *   ins     : device complex128 [n_noise][n_span][n_ops][n_mom][192].
+ *   out_fwd : device complex128 [n_pairs][n_fwd][n_ops][64][64].
+ *   out_bwd : device complex128 [n_pairs][n_bwd][n_ops][64][64].
+ * Every argument is checked before anything is enqueued.
+ */
+int c3pt_two_sink_meson(const c3pt_geom* geom, const void* G_fwd, const void* eta_fwd, int t_fwd,
+                        const void* G_bwd, const void* eta_bwd, int t_bwd, int t_src, int n_noise,
+                        const void* const* G_t, const void* const* s_t, const void* const* U_t, int n_ops,
+                        const int* k, int n_mom, const double* w, const int* pairs, int n_pairs, void* spec,
+                        void* ins, void* out_fwd, void* out_bwd);
+
 /* Static description of a status code. */
 const char* c3pt_strerror(int status);
 

@@ -313,3 +313,30 @@ def combine(S, I, w=None, pairs=None, op_begin: int = 0, op_end=None) -> np.ndar
     for j, (p, q) in enumerate(pairs):
         out[j] = np.einsum('isc,ijouc->josu', Sr[:, p], Ir[:, :, :, q], optimize=True)
     return out
+
+
+# --------------------------------------------------------------------------
+# Forward and backward diagrams of one measurement (Sec. 2.3, Fig. 6).
+# --------------------------------------------------------------------------
+def two_sink_meson(G1_fwd, eta_fwd, t_fwd, G1_bwd, eta_bwd, t_bwd, t_src, G_t, s_t, L, T: int, k,
+                   r=(0, 0, 0), U_t=None, n_ops: int = 1, w=None, pairs=None) -> dict:
+    """The noise is time partitioned: zero except on the sink timeslices x'_4
+    (t_fwd) and x''_4 (t_bwd) around the source timeslice r_4 (t_src), so one
+    solution s per noise vector serves the forward diagram (sink x'_4,
+    insertion between x'_4 and r_4) and the backward one (sink x''_4,
+    insertion between r_4 and x''_4), estimated together.  Each diagram is a
+    spectator at its sink (Eq. (9) with that sink's propagator and noise
+    slice), the insertion (Eq. (10)) on its timeslices, and their noise
+    average (Eq. (5) in Eq. (8)).  Timeslices run forward in time modulo T:
+    forward t_fwd .. t_src, backward t_src .. t_bwd; the source timeslice is
+    in both.  Returns spec [2][N][n_mom][192] (forward, backward), ins on the
+    span t_fwd .. t_bwd, and fwd / bwd as combine() returns them."""
+    n_fwd = (t_src - t_fwd) % T + 1
+    n_bwd = (t_bwd - t_src) % T + 1
+    taus = [(t_fwd + j) % T for j in range(n_fwd + n_bwd - 1)]
+    S_f = spectator_meson(G1_fwd, eta_fwd, L, k, r=r)
+    S_b = spectator_meson(G1_bwd, eta_bwd, L, k, r=r)
+    I = insertion(G_t, s_t, taus, L, T, k, r=r, U_t=U_t, n_ops=n_ops)
+    return {"spec": np.stack([S_f, S_b]), "ins": I, "taus": taus,
+            "fwd": combine(S_f, I[:, :n_fwd], w=w, pairs=pairs),
+            "bwd": combine(S_b, I[:, n_fwd - 1:], w=w, pairs=pairs)}

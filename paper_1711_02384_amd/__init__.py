@@ -37,7 +37,7 @@ PROJ_SPLIT_BF16 = 2
 PROJ_FACTORED = 3
 
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
-            "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
+            "c3pt_two_sink_meson", "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
             "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read", "c3pt_variant_count",
             "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
             "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
@@ -105,7 +105,11 @@ def _load():
                                    ctypes.POINTER(vp), i, ip, i, vp]
     lib.c3pt_combine.argtypes = [vp, i, vp, i, i, i, i, i, i, i, ctypes.POINTER(ctypes.c_double), ip, i,
                                  vp, vp]
-    for name in ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine"):
+    lib.c3pt_two_sink_meson.argtypes = [gp, vp, vp, i, vp, vp, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), i, ip, i, ctypes.POINTER(ctypes.c_double), ip, i,
+                                        vp, vp, vp, vp]
+    for name in ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
+                 "c3pt_two_sink_meson"):
         getattr(lib, name).restype = ctypes.c_int
     lib.c3pt_strerror.argtypes = [i]
     lib.c3pt_strerror.restype = ctypes.c_char_p
@@ -301,10 +305,56 @@ def c3pt_combine(spec: torch.Tensor, ins: torch.Tensor, w=None, pairs=None, op_b
     return out
 
 
+def c3pt_two_sink_meson(G_fwd: torch.Tensor, eta_fwd: torch.Tensor, t_fwd: int, G_bwd: torch.Tensor,
+                        eta_bwd: torch.Tensor, t_bwd: int, t_src: int, G_t, s_t, k, geom: Geom, U_t=None,
+                        n_ops: int = 1, w=None, pairs=None) -> dict:
+    """Forward and backward meson diagrams with time-partitioned noise (one
+    call of c3pt_two_sink_meson).  Returns {"spec": [2, N, n_mom, 192],
+    "ins": [N, n_span, n_ops, n_mom, 192], "fwd": [n_pairs, n_fwd, n_ops, 64, 64],
+    "bwd": [n_pairs, n_bwd, n_ops, 64, 64], "taus": span timeslices}, complex128."""
+    import numpy as np
+    V3, T = geom.V3, int(geom.T)
+    N = eta_fwd.shape[0]
+    dtype = eta_fwd.dtype
+    _field(G_fwd, "G_fwd", (12, 12, V3), dtype)
+    _field(G_bwd, "G_bwd", (12, 12, V3), dtype)
+    _field(eta_fwd, "eta_fwd", (N, 12, V3), dtype)
+    _field(eta_bwd, "eta_bwd", (N, 12, V3), dtype)
+    t_fwd, t_src, t_bwd = int(t_fwd), int(t_src), int(t_bwd)
+    n_fwd = (t_src - t_fwd) % T + 1
+    n_bwd = (t_bwd - t_src) % T + 1
+    n_span = n_fwd + n_bwd - 1
+    Gtab = _slice_table(G_t, T, "G_t", (12, 12, V3), dtype)
+    stab = _slice_table(s_t, T, "s_t", (N, 12, V3), dtype)
+    Utab = _slice_table(U_t, T, "U_t", (4, 3, 3, V3), dtype) if U_t is not None else None
+    ka, kp, n_mom = _momenta(k)
+    wp = None
+    if w is not None:
+        wa = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(N))
+        wp = wa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if pairs is None:
+        n_pairs, pp = n_mom * n_mom, None
+    else:
+        pa = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        n_pairs, pp = pa.shape[0], pa.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    spec = _out(None, (2, N, n_mom, 192), eta_fwd)
+    ins = _out(None, (N, n_span, n_ops, n_mom, 192), eta_fwd)
+    fwd = _out(None, (n_pairs, n_fwd, n_ops, 64, 64), eta_fwd)
+    bwd = _out(None, (n_pairs, n_bwd, n_ops, 64, 64), eta_fwd)
+    g = geom.c(dtype)
+    _check(lib.c3pt_two_sink_meson(ctypes.byref(g), G_fwd.data_ptr(), eta_fwd.data_ptr(), t_fwd, G_bwd.data_ptr(),
+                                   eta_bwd.data_ptr(), t_bwd, t_src, N, Gtab, stab,
+                                   Utab if Utab is not None else None, n_ops, kp, n_mom, wp, pp, n_pairs,
+                                   spec.data_ptr(), ins.data_ptr(), fwd.data_ptr(), bwd.data_ptr()))
+    taus = [(t_fwd + j) % T for j in range(n_span)]
+    return {"spec": spec, "ins": ins, "fwd": fwd, "bwd": bwd, "taus": taus}
+
+
 spectator_meson = c3pt_spectator_meson
 spectator_baryon = c3pt_spectator_baryon
 insertion = c3pt_insertion
 combine = c3pt_combine
+two_sink_meson = c3pt_two_sink_meson
 
 
 def momentum_list(n2max: int):

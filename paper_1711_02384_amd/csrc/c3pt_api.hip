@@ -551,6 +551,66 @@ hipError_t api_timed(const char* name, hipStream_t st, const std::function<hipEr
 }
 }  // namespace c3pt
 
+// c3pt_combine over the insertion timeslices [tau0, tau0 + n_tau) of an
+// insertion output holding n_tau_in slices.
+static int combine_impl(const void* spec, int spec_spin, const void* ins, int n_noise, int n_p, int n_q, int n_tau_in,
+                 int tau0, int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
+                 int n_pairs, void* out, void* stream) {
+    if (!spec || !ins || !out) return fail(C3PT_EINVAL, "NULL input or output pointer");
+    if (spec_spin != 64 && spec_spin != 1024) return fail(C3PT_EINVAL, "spec_spin = %d (64 or 1024)", spec_spin);
+    if (n_noise < 1 || n_p < 1 || n_q < 1 || n_tau < 1 || n_ops < 1)
+        return fail(C3PT_EINVAL, "extents must be >= 1");
+    if (tau0 < 0 || tau0 + n_tau > n_tau_in)
+        return fail(C3PT_EINVAL, "timeslice window [%d, %d) outside the %d insertion slices", tau0, tau0 + n_tau,
+                    n_tau_in);
+    if (op_begin < 0 || op_end > n_ops || op_begin >= op_end)
+        return fail(C3PT_EINVAL, "operator range [%d, %d) invalid for n_ops = %d", op_begin, op_end, n_ops);
+    if (!pairs) {
+        if (n_pairs != n_p * n_q) return fail(C3PT_EINVAL, "n_pairs must be n_p*n_q when pairs is NULL");
+    } else {
+        if (n_pairs < 1) return fail(C3PT_EINVAL, "n_pairs = %d < 1", n_pairs);
+        for (int j = 0; j < n_pairs; ++j)
+            if (pairs[2 * j] < 0 || pairs[2 * j] >= n_p || pairs[2 * j + 1] < 0 || pairs[2 * j + 1] >= n_q)
+                return fail(C3PT_EINVAL, "pair %d = (%d, %d) out of range", j, pairs[2 * j], pairs[2 * j + 1]);
+    }
+    if ((long long)n_pairs * n_tau * (op_end - op_begin) > 0x7fffffffLL)
+        return fail(C3PT_EINVAL, "too many (pair, tau, op) tiles");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> wv(n_noise);
+    for (int i = 0; i < n_noise; ++i) wv[i] = w ? w[i] : 1.0 / n_noise;
+    const size_t wbytes = (size_t)n_noise * sizeof(double);
+    const size_t pbytes = pairs ? (size_t)n_pairs * 2 * sizeof(int) : 0;
+    const size_t woff = 0, poff = (wbytes + 255) & ~(size_t)255;
+    // Weights and pairs go to the start of this stream's scratch; kernels of
+    // earlier calls on the same stream that use it are ordered before the upload.
+    void* base;
+    if (int rc = scratch_dev(st, poff + pbytes + 256, &base)) return rc;
+    std::vector<char> host(poff + pbytes);
+    memcpy(host.data() + woff, wv.data(), wbytes);
+    if (pairs) memcpy(host.data() + poff, pairs, pbytes);
+    if (int rc = upload(st, base, 0, host.data(), host.size())) return rc;
+    CombineArgs a;
+    a.S = (const double2*)spec;
+    a.I = (const double2*)ins;
+    a.w = (const double*)base;
+    a.pairs = pairs ? (const int*)((char*)base + poff) : nullptr;
+    a.out = (double2*)out;
+    a.n_noise = n_noise;
+    a.n_p = n_p;
+    a.n_q = n_q;
+    a.n_tau = n_tau;
+    a.n_ops = n_ops;
+    a.op_begin = op_begin;
+    a.n_sel = op_end - op_begin;
+    a.spin = spec_spin;
+    a.n_pairs = n_pairs;
+    a.tau0 = tau0;
+    a.n_tau_in = n_tau_in;
+    if (int rc = to_status(timed("combine", st, [&] { return launch_combine(a, st); }), "combine launch"))
+        return rc;
+    return ok();
+}
+
 extern "C" {
 
 int c3pt_version(void) { return 100; }
@@ -761,54 +821,63 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
 int c3pt_combine(const void* spec, int spec_spin, const void* ins, int n_noise, int n_p, int n_q,
                  int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
                  int n_pairs, void* out, void* stream) {
-    if (!spec || !ins || !out) return fail(C3PT_EINVAL, "NULL input or output pointer");
-    if (spec_spin != 64 && spec_spin != 1024) return fail(C3PT_EINVAL, "spec_spin = %d (64 or 1024)", spec_spin);
-    if (n_noise < 1 || n_p < 1 || n_q < 1 || n_tau < 1 || n_ops < 1)
-        return fail(C3PT_EINVAL, "extents must be >= 1");
-    if (op_begin < 0 || op_end > n_ops || op_begin >= op_end)
-        return fail(C3PT_EINVAL, "operator range [%d, %d) invalid for n_ops = %d", op_begin, op_end, n_ops);
-    if (!pairs) {
-        if (n_pairs != n_p * n_q) return fail(C3PT_EINVAL, "n_pairs must be n_p*n_q when pairs is NULL");
-    } else {
+    return combine_impl(spec, spec_spin, ins, n_noise, n_p, n_q, n_tau, 0, n_tau, n_ops, op_begin, op_end, w, pairs,
+                        n_pairs, out, stream);
+}
+
+int c3pt_two_sink_meson(const c3pt_geom* geom, const void* G_fwd, const void* eta_fwd, int t_fwd,
+                        const void* G_bwd, const void* eta_bwd, int t_bwd, int t_src, int n_noise,
+                        const void* const* G_t, const void* const* s_t, const void* const* U_t, int n_ops,
+                        const int* k, int n_mom, const double* w, const int* pairs, int n_pairs, void* spec,
+                        void* ins, void* out_fwd, void* out_bwd) {
+    // every check of the composed calls first: on error nothing is enqueued
+    if (int rc = check_geom(geom)) return rc;
+    if (int rc = check_momenta(k, n_mom)) return rc;
+    if (!G_fwd || !eta_fwd || !G_bwd || !eta_bwd || !G_t || !s_t || !spec || !ins || !out_fwd || !out_bwd)
+        return fail(C3PT_EINVAL, "NULL field, table or output pointer");
+    if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    if (n_ops != 1 && n_ops != 5) return fail(C3PT_EINVAL, "n_ops = %d (must be 1 or 5)", n_ops);
+    if (n_ops == 5 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
+    const int T = geom->T;
+    if (t_fwd < 0 || t_fwd >= T || t_src < 0 || t_src >= T || t_bwd < 0 || t_bwd >= T)
+        return fail(C3PT_EINVAL, "timeslices (%d, %d, %d) outside [0, %d)", t_fwd, t_src, t_bwd, T);
+    const int d1 = (t_src - t_fwd + T) % T, d2 = (t_bwd - t_src + T) % T;
+    if (d1 + d2 >= T) return fail(C3PT_EINVAL, "the two sinks overlap around the periodic time direction");
+    const int n_span = d1 + d2 + 1;
+    std::vector<int> taus(n_span);
+    for (int j = 0; j < n_span; ++j) {
+        const int t = (t_fwd + j) % T;
+        taus[j] = t;
+        if (!G_t[t]) return fail(C3PT_EINVAL, "propagator slice %d missing", t);
+        if (!s_t[t]) return fail(C3PT_EINVAL, "stochastic solution slice %d missing", t);
+        if (n_ops == 5) {
+            const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
+            if (!G_t[tn] || !G_t[tp])
+                return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp, tn, t);
+            if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
+        }
+    }
+    if (pairs) {
         if (n_pairs < 1) return fail(C3PT_EINVAL, "n_pairs = %d < 1", n_pairs);
         for (int j = 0; j < n_pairs; ++j)
-            if (pairs[2 * j] < 0 || pairs[2 * j] >= n_p || pairs[2 * j + 1] < 0 || pairs[2 * j + 1] >= n_q)
+            if (pairs[2 * j] < 0 || pairs[2 * j] >= n_mom || pairs[2 * j + 1] < 0 || pairs[2 * j + 1] >= n_mom)
                 return fail(C3PT_EINVAL, "pair %d = (%d, %d) out of range", j, pairs[2 * j], pairs[2 * j + 1]);
+    } else if (n_pairs != n_mom * n_mom) {
+        return fail(C3PT_EINVAL, "n_pairs must be n_mom*n_mom when pairs is NULL");
     }
-    if ((long long)n_pairs * n_tau * (op_end - op_begin) > 0x7fffffffLL)
-        return fail(C3PT_EINVAL, "too many (pair, tau, op) tiles");
-    hipStream_t st = (hipStream_t)stream;
-    std::vector<double> wv(n_noise);
-    for (int i = 0; i < n_noise; ++i) wv[i] = w ? w[i] : 1.0 / n_noise;
-    const size_t wbytes = (size_t)n_noise * sizeof(double);
-    const size_t pbytes = pairs ? (size_t)n_pairs * 2 * sizeof(int) : 0;
-    const size_t woff = 0, poff = (wbytes + 255) & ~(size_t)255;
-    // Weights and pairs go to the start of this stream's scratch; kernels of
-    // earlier calls on the same stream that use it are ordered before the upload.
-    void* base;
-    if (int rc = scratch_dev(st, poff + pbytes + 256, &base)) return rc;
-    std::vector<char> host(poff + pbytes);
-    memcpy(host.data() + woff, wv.data(), wbytes);
-    if (pairs) memcpy(host.data() + poff, pairs, pbytes);
-    if (int rc = upload(st, base, 0, host.data(), host.size())) return rc;
-    CombineArgs a;
-    a.S = (const double2*)spec;
-    a.I = (const double2*)ins;
-    a.w = (const double*)base;
-    a.pairs = pairs ? (const int*)((char*)base + poff) : nullptr;
-    a.out = (double2*)out;
-    a.n_noise = n_noise;
-    a.n_p = n_p;
-    a.n_q = n_q;
-    a.n_tau = n_tau;
-    a.n_ops = n_ops;
-    a.op_begin = op_begin;
-    a.n_sel = op_end - op_begin;
-    a.spin = spec_spin;
-    a.n_pairs = n_pairs;
-    if (int rc = to_status(timed("combine", st, [&] { return launch_combine(a, st); }), "combine launch"))
+    // spectators at both sinks, one insertion over the whole span, two windowed combines
+    char* spec_bwd = (char*)spec + (size_t)n_noise * n_mom * kBlockCols * sizeof(double2);
+    if (int rc = c3pt_spectator_meson(geom, G_fwd, eta_fwd, n_noise, k, n_mom, spec)) return rc;
+    if (int rc = c3pt_spectator_meson(geom, G_bwd, eta_bwd, n_noise, k, n_mom, spec_bwd)) return rc;
+    if (int rc = c3pt_insertion(geom, G_t, s_t, n_noise, taus.data(), n_span, U_t, n_ops, k, n_mom, ins)) return rc;
+    if (int rc = combine_impl(spec, 64, ins, n_noise, n_mom, n_mom, n_span, 0, d1 + 1, n_ops, 0, n_ops, w, pairs,
+                              n_pairs, out_fwd, geom->stream))
+        return rc;
+    if (int rc = combine_impl(spec_bwd, 64, ins, n_noise, n_mom, n_mom, n_span, d1, d2 + 1, n_ops, 0, n_ops, w, pairs,
+                              n_pairs, out_bwd, geom->stream))
         return rc;
     return ok();
 }
+
 
 }  // extern "C"

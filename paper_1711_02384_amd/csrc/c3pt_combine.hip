@@ -124,6 +124,7 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
     }
     const int op = a.op_begin + o;
     const size_t spin3 = (size_t)a.spin * 3;
+    const int n_tau_in = a.n_tau_in > 0 ? a.n_tau_in : a.n_tau;
 
     double2 acc[4][4];
 #pragma unroll
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
             const double w = a.w[i];
             const double2 sv = a.S[((size_t)i * a.n_p + p) * spin3 + (size_t)(sb * 64 + x) * 3 + c];
             sA[kk][x] = make_double2(w * sv.x, w * sv.y);
-            sB[kk][x] = a.I[((((size_t)i * a.n_tau + tau) * a.n_ops + op) * a.n_q + q) * kBlockCols +
+            sB[kk][x] = a.I[((((size_t)i * n_tau_in + a.tau0 + tau) * a.n_ops + op) * a.n_q + q) * kBlockCols +
                             x * 3 + c];
         }
         __syncthreads();

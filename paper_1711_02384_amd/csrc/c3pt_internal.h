@@ -159,11 +159,14 @@ struct ReduceArgs {
 
 struct CombineArgs {
     const double2* S;     // [N][n_p][spin*3]
-    const double2* I;     // [N][n_tau][n_ops][n_q][192]
+    const double2* I;     // [N][n_tau_in][n_ops][n_q][192]
     const double* w;      // device [N]
     const int* pairs;     // device [n_pairs][2] or null (all pairs)
     double2* out;         // [n_pairs][n_tau][n_sel][spin][64]
     int n_noise, n_p, n_q, n_tau, n_ops, op_begin, n_sel, spin, n_pairs;
+    // timeslice window of the insertion: output tau reads insertion slice
+    // tau0 + tau of n_tau_in (0: the insertion holds exactly the n_tau slices)
+    int tau0 = 0, n_tau_in = 0;
 };
 
 // Arithmetic of a projection launch.

@@ -1,0 +1,133 @@
+"""Forward and backward meson diagrams with time-partitioned noise
+(c3pt_two_sink_meson, Sec. 2.3 and Fig. 6) against the FP64 oracle: the
+composition of the pinned oracle parts, and the direct trace under full
+time-partitioned dilution.  Cases cover complex128 (1e-12), complex64 with
+the factored projection (1e-5), the derivative operators, and sinks that
+wrap around the periodic time direction."""
+import numpy as np
+import pytest
+
+import c3pt_synth as syn
+import oracle
+from helpers import rel_fro
+from oracle import brute
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _dev(a, reduced):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex64 if reduced else np.complex128))).cuda()
+
+
+def _inputs(L, T, N, t_fwd, t_src, t_bwd, cfg, reduced, links):
+    cast = syn.round_to_c64 if reduced else (lambda a: a)
+    n_span = (t_src - t_fwd) % T + (t_bwd - t_src) % T + 1
+    taus = [(t_fwd + j) % T for j in range(n_span)]
+    need = set(taus)
+    if links:
+        for t in taus:
+            need |= {(t + 1) % T, (t - 1) % T}
+    G1f = cast(syn.propagator_slice(L, cfg, syn.FIELD_G1, t_fwd))
+    G1b = cast(syn.propagator_slice(L, cfg, syn.FIELD_G1, t_bwd))
+    eta_f = cast(syn.z2z2_noise(L, N, cfg, t_fwd))
+    eta_b = cast(syn.z2z2_noise(L, N, cfg, t_bwd))
+    G3 = {t: cast(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in sorted(need)}
+    s = {t: cast(syn.solution_slice(L, N, cfg, t)) for t in taus}
+    U = None
+    if links:
+        U = {t: cast(syn.link_slice(L, cfg, t)) for t in sorted(set(taus) | {(t - 1) % T for t in taus})}
+    return G1f, G1b, eta_f, eta_b, G3, s, U
+
+
+CASES = [
+    # L, T, N, (t_fwd, t_src, t_bwd), reduced, n_ops, n2, proj
+    ((6, 5, 4), 12, 2, (2, 5, 9), False, 5, 3, "native"),     # complex128, derivatives
+    ((8, 6, 5), 10, 3, (7, 1, 4), True, 1, 5, "factored"),    # complex64 factored, wraps around T
+    ((8, 6, 5), 12, 2, (3, 6, 8), True, 5, 3, "factored"),    # complex64 factored, derivatives
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_two_sink_matches_oracle(case):
+    import paper_1711_02384_amd as c3pt
+    L, T, N, (tf, ts, tb), reduced, n_ops, n2, proj = CASES[case]
+    tol = 1e-5 if reduced else 1e-12
+    _say(f"two-sink case {case}: L={L} T={T} sinks {tf}/{tb} source {ts} ops {n_ops} {proj}")
+    k = c3pt.momentum_list(n2)
+    G1f, G1b, eta_f, eta_b, G3, s, U = _inputs(L, T, N, tf, ts, tb, 60 + case, reduced, n_ops == 5)
+    r = (1, 2, 0)
+    geom = c3pt.Geom(L, T, r=r, proj=c3pt.PROJ_FACTORED if proj == "factored" else c3pt.PROJ_NATIVE)
+    pairs = [(p, p) for p in range(len(k))] + [(0, q) for q in range(1, len(k))]
+    w = np.linspace(0.5, 1.5, N) / N
+    res = c3pt.two_sink_meson(_dev(G1f, reduced), _dev(eta_f, reduced), tf, _dev(G1b, reduced),
+                              _dev(eta_b, reduced), tb, ts, {t: _dev(v, reduced) for t, v in G3.items()},
+                              {t: _dev(v, reduced) for t, v in s.items()}, k, geom,
+                              U_t=None if U is None else {t: _dev(v, reduced) for t, v in U.items()},
+                              n_ops=n_ops, w=w, pairs=pairs)
+    torch.cuda.synchronize()
+    want = oracle.two_sink_meson(G1f, eta_f, tf, G1b, eta_b, tb, ts, G3, s, L, T, k, r=r, U_t=U, n_ops=n_ops,
+                                 w=w, pairs=pairs)
+    assert res["taus"] == want["taus"]
+    errs = {key: rel_fro(res[key].cpu().numpy(), want[key]) for key in ("spec", "ins", "fwd", "bwd")}
+    _say(f"   errors {errs}")
+    assert max(errs.values()) < tol
+
+
+def test_two_sink_full_dilution_equals_direct_trace():
+    """Through the GPU: noise fully diluted one sink slice at a time, solutions
+    from exact propagators to each sink; both diagrams must equal the direct
+    trace (complex128)."""
+    import paper_1711_02384_amd as c3pt
+    _say("two-sink full dilution vs direct trace")
+    L, T, V3 = (2, 2, 2), 6, 8
+    tf, ts, tb = 1, 3, 5
+    g = np.random.default_rng(43)
+    taus = [1, 2, 3, 4, 5]
+    G1f = syn.gaussian((12, 12, V3), g)
+    G1b = syn.gaussian((12, 12, V3), g)
+    G3 = {t: syn.gaussian((12, 12, V3), g) for t in taus}
+    G2f = {t: syn.gaussian((V3, V3, 12, 12), g) for t in taus}
+    G2b = {t: syn.gaussian((V3, V3, 12, 12), g) for t in taus}
+    M = 12 * V3
+    eta_f = np.zeros((2 * M, 12, V3), dtype=np.complex128)
+    eta_b = np.zeros((2 * M, 12, V3), dtype=np.complex128)
+    for j in range(M):
+        eta_f[j, j % 12, j // 12] = 1.0
+        eta_b[M + j, j % 12, j // 12] = 1.0
+    s = {t: np.einsum('yxAB,jBx->jAy', G2f[t], eta_f) + np.einsum('yxAB,jBx->jAy', G2b[t], eta_b) for t in taus}
+    k = oracle.momenta(1)
+    pairs = [(2, 5), (0, 0)]
+    res = c3pt.two_sink_meson(_dev(G1f, False), _dev(eta_f, False), tf, _dev(G1b, False), _dev(eta_b, False), tb,
+                              ts, {t: _dev(v, False) for t, v in G3.items()},
+                              {t: _dev(v, False) for t, v in s.items()}, k, c3pt.Geom(L, T),
+                              w=np.ones(2 * M), pairs=pairs)
+    fwd, bwd = res["fwd"].cpu().numpy(), res["bwd"].cpu().numpy()
+    for j, (p, q) in enumerate(pairs):
+        for it, t in enumerate([1, 2, 3]):
+            Cb = brute.meson_spin_open(G1f, G2f[t], G3[t], L, k[p], k[q])
+            assert rel_fro(fwd[j, it, 0].reshape((4,) * 6), Cb) < 1e-12
+        for it, t in enumerate([3, 4, 5]):
+            Cb = brute.meson_spin_open(G1b, G2b[t], G3[t], L, k[p], k[q])
+            assert rel_fro(bwd[j, it, 0].reshape((4,) * 6), Cb) < 1e-12
+
+
+def test_two_sink_rejects_bad_arguments():
+    import paper_1711_02384_amd as c3pt
+    _say("two-sink argument checks")
+    L, T, N = (4, 4, 4), 8, 1
+    G1f, G1b, eta_f, eta_b, G3, s, _ = _inputs(L, T, N, 1, 3, 5, 70, False, False)
+    args = lambda tb, G: (_dev(G1f, False), _dev(eta_f, False), 1, _dev(G1b, False), _dev(eta_b, False), tb, 3,
+                          {t: _dev(v, False) for t, v in G.items()}, {t: _dev(v, False) for t, v in s.items()},
+                          [[0, 0, 0]], c3pt.Geom(L, T))
+    with pytest.raises(c3pt.C3ptError):          # sinks overlap around T
+        c3pt.two_sink_meson(*args(1, G3))
+    G_missing = {t: v for t, v in G3.items() if t != 4}
+    with pytest.raises(c3pt.C3ptError):          # a propagator slice of the span is missing
+        c3pt.two_sink_meson(*args(5, G_missing))
+    with pytest.raises(c3pt.C3ptError):          # derivatives without links
+        c3pt.two_sink_meson(*args(5, G3), n_ops=5)

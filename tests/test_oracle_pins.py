@@ -500,3 +500,49 @@ def test_planted_mistake_fails_bruteforce(monkeypatch, mutation):
     Ghat = np.einsum('i,iAy,iBx->yxAB', w, s[1], np.conj(eta))
     Cb = brute.meson_spin_open(G1, Ghat, G3[1], L, kp[0], q[0])
     assert not np.allclose(C[0, 0, 0].reshape((4,) * 6), Cb, atol=1e-6 * np.abs(Cb).max())
+
+
+# ----------------------------------------------------------------------------
+# Forward and backward diagrams with time-partitioned noise
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("t_fwd,t_src,t_bwd", [(1, 3, 5), (4, 0, 2)])
+def test_two_sink_full_dilution_reproduces_both_diagrams(t_fwd, t_src, t_bwd):
+    """Noise on the two sink slices only, fully diluted one slice at a time
+    (unit vectors on x'_4 for the first 12 V3 noise vectors, on x''_4 for the
+    rest; w = 1); the solution of each is the exact propagator's column to its
+    sink.  The forward result must equal the direct trace with the exact
+    G2(y, x') for x' on x'_4 at every tau from x'_4 to r_4, the backward one
+    with x'' on x''_4 from r_4 to x''_4 (second case wraps around T)."""
+    L, T = (2, 2, 2), 6
+    V3 = 8
+    g = np.random.default_rng(41)
+    n_fwd = (t_src - t_fwd) % T + 1
+    n_bwd = (t_bwd - t_src) % T + 1
+    taus = [(t_fwd + j) % T for j in range(n_fwd + n_bwd - 1)]
+    G1f = syn.gaussian((12, 12, V3), g)
+    G1b = syn.gaussian((12, 12, V3), g)
+    G3 = {t: syn.gaussian((12, 12, V3), g) for t in taus}
+    G2f = {t: syn.gaussian((V3, V3, 12, 12), g) for t in taus}   # exact G2(y on t, x' on x'_4)
+    G2b = {t: syn.gaussian((V3, V3, 12, 12), g) for t in taus}   # exact G2(y on t, x'' on x''_4)
+    M = 12 * V3
+    eta_f = np.zeros((2 * M, 12, V3), dtype=np.complex128)
+    eta_b = np.zeros((2 * M, 12, V3), dtype=np.complex128)
+    for j in range(M):
+        eta_f[j, j % 12, j // 12] = 1.0
+        eta_b[M + j, j % 12, j // 12] = 1.0
+    s = {t: np.einsum('yxAB,jBx->jAy', G2f[t], eta_f) + np.einsum('yxAB,jBx->jAy', G2b[t], eta_b) for t in taus}
+    kp = oracle.momenta(1)
+    q = oracle.momenta(1)
+    pairs = [(2, 5), (0, 0)]
+    res = oracle.two_sink_meson(G1f, eta_f, t_fwd, G1b, eta_b, t_bwd, t_src, G3, s, L, T, kp, w=np.ones(2 * M),
+                                pairs=pairs)
+    assert res["taus"] == taus and res["fwd"].shape[1] == n_fwd and res["bwd"].shape[1] == n_bwd
+    for j, (p, qq) in enumerate(pairs):
+        for it in range(n_fwd):
+            t = taus[it]
+            Cb = brute.meson_spin_open(G1f, G2f[t], G3[t], L, kp[p], kp[qq])
+            assert np.allclose(res["fwd"][j, it, 0].reshape((4,) * 6), Cb, atol=1e-12 * np.abs(Cb).max())
+        for it in range(n_bwd):
+            t = taus[n_fwd - 1 + it]
+            Cb = brute.meson_spin_open(G1b, G2b[t], G3[t], L, kp[p], kp[qq])
+            assert np.allclose(res["bwd"][j, it, 0].reshape((4,) * 6), Cb, atol=1e-12 * np.abs(Cb).max())
