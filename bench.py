@@ -23,7 +23,9 @@ Other workloads (``--workload``): ``meson8`` (8^3 x 16, complex128, 27
 momenta, local insertion at tau = 0..8, all-pairs combine), ``nucleon48``
 (48^3 x 64, two nucleon spectators (u,u) and (u,d), isovector insertion with
 u and d propagators at tau = 0..14, N = 8, 93 or 123 momenta, combine on the
-185 pairs with p' = q or p' = 0), ``batch64`` (64 sources in one recorded
+185 pairs with p' = q or p' = 0), ``twosink32`` (forward and backward
+diagrams with time-partitioned noise, 32^3 x 96, r_4 = 30, sinks at 20 and
+40, N = 50, 93 momenta, local + 4 D_nu), ``batch64`` (64 sources in one recorded
 graph) and ``serve`` (Poisson arrivals to the continuous-batching engine).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one GPU.
@@ -51,7 +53,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 20; batch64: 3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 3; batch64: 1)")
-    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "batch64", "serve"], default="meson32")
+    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "twosink32", "batch64", "serve"], default="meson32")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -101,10 +103,13 @@ TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_de
                    "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip", "c3pt_api.hip"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name -> (bytes per launch, source hash)
-    # 32^3 step: local (484219 + 264384 KiB) and derivative (1962840 + 1074940 KiB) dispatches of one call
-    ("meson32", "fac", "fac_insertion"): ((484219 + 1962840) * 2048 + (264384 + 1074940) * 1024, "4a944929d21525ba"),
-    # 48^3 step: one nucleon spectator dispatch (414787 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon"): (414787 * 2048 + 857088 * 1024, "4a944929d21525ba"),
+    # 32^3 step: local (484218 + 264384 KiB) and derivative (1968476 + 1074944 KiB) dispatches of one call
+    ("meson32", "fac", "fac_insertion"): ((484218 + 1968476) * 2048 + (264384 + 1074944) * 1024, "776c052143630254"),
+    # 48^3 step: one nucleon spectator dispatch (414934 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon"): (414934 * 2048 + 857088 * 1024, "776c052143630254"),
+    # two-sink 32^3 x 96 step: local (3755090 + 4687200 KiB) and derivative (21429519 + 19017600 KiB)
+    ("twosink32", "fac", "fac_insertion"): ((3755090 + 21429519) * 2048 + (4687200 + 19017600) * 1024,
+                                           "776c052143630254"),
 }
 
 
@@ -419,6 +424,97 @@ class Nucleon48(Meson32):
         return units, dt, (f"FP64 numpy oracle: one insertion timeslice (u), full 48^3, N=8, {len(k)} momenta; "
                            f"nucleon spectators and combine not in the sample")
 
+class TwoSink32(Meson32):
+    """Forward and backward meson diagrams with time-partitioned noise in the
+    shape of the paper's measurement (Sec. 3): 32^3 x 96, source r_4 = 30,
+    sinks x'_4 = 20 and x''_4 = 40, N = 50 noise vectors with support on both
+    sink timeslices, momenta |k|^2 <= 8 (93).  One step = spectators at both
+    sinks, the insertion (local and the four D_nu) on the 21 timeslices
+    20..40, and the forward / backward combines on the 185 pairs with p' = q or
+    p' = 0, all in one c3pt_two_sink_meson call."""
+    L = (32, 32, 32)
+    T = 96
+    t_src, t_fwd, t_bwd = 30, 20, 40
+    N = 50
+    n2 = 8
+    n_ops = 5
+    cfg = 5
+    dtype = "c64"
+    default_proj = "fac"
+    default_steps = 10
+    default_warmup = 2
+
+    def __init__(self, args):
+        self.baryon = False
+        self.taus = [(self.t_fwd + j) % self.T for j in range((self.t_bwd - self.t_fwd) % self.T + 1)]
+        self.name = ("meson 3pt forward + backward with time-partitioned noise, 32^3x96, r_4=30, x'_4=20, "
+                     "x''_4=40, N=50, |k|^2<=8 (93 momenta), local+4 D_nu, 185 pairs")
+
+    def setup(self, c3pt, syn, dev, geom, k):
+        L, T = self.L, self.T
+        up = lambda a: _up(a, dev, np.complex64)
+        self.Gf = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_fwd))
+        self.Gb = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_bwd))
+        self.eta_f = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_fwd))
+        self.eta_b = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_bwd))
+        gsl = sorted({t % T for tau in self.taus for t in (tau - 1, tau, tau + 1)})
+        usl = sorted({t % T for tau in self.taus for t in (tau - 1, tau)})
+        self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
+        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in self.taus}
+        self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
+        self.pairs = pairs_diag_or_zero(len(k))
+        self.c3pt, self.geom, self.k = c3pt, geom, k
+
+    def _run(self):
+        return self.c3pt.two_sink_meson(self.Gf, self.eta_f, self.t_fwd, self.Gb, self.eta_b, self.t_bwd,
+                                        self.t_src, self.G3, self.s, self.k, self.geom, U_t=self.U,
+                                        n_ops=self.n_ops, pairs=self.pairs)
+
+    def calls(self):
+        c, g, k = self.c3pt, self.geom, self.k
+        return [("insertion", lambda: c.insertion(self.G3, self.s, self.taus, k, g, U_t=self.U, n_ops=self.n_ops)),
+                ("spectator_meson", lambda: c.spectator_meson(self.Gf, self.eta_f, k, g))]
+
+    def step(self):
+        self.out = self._run()
+
+    def units(self, n_mom):
+        return self.N * int(np.prod(self.L)) * n_mom * (2 + len(self.taus))
+
+    def components(self, n_mom):
+        return self.N * int(np.prod(self.L)) * n_mom * 192 * (2 + len(self.taus) * self.n_ops)
+
+    def config(self, n_mom):
+        return {"workload": self.name, "L": list(self.L), "T": self.T, "t_src": self.t_src, "t_fwd": self.t_fwd,
+                "t_bwd": self.t_bwd, "n_noise": self.N, "n_tau": len(self.taus), "n_mom": n_mom,
+                "n_ops": self.n_ops, "n_pairs": len(self.pairs), "units_per_step": self.units(n_mom)}
+
+    def cpu_sample(self, k, n_slices):
+        import c3pt_synth as syn
+        import oracle
+        L, T, n = self.L, self.T, 12
+        c64 = syn.round_to_c64
+        Gf = c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_fwd))
+        Gb = c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_bwd))
+        eta_f = c64(syn.z2z2_noise(L, self.N, self.cfg, self.t_fwd))[:n]
+        eta_b = c64(syn.z2z2_noise(L, self.N, self.cfg, self.t_bwd))[:n]
+        ns = max(1, n_slices // 2)
+        taus = [(self.t_src + j) % T for j in range(ns)]
+        need = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
+        G3 = {t: c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in need}
+        s = {t: c64(syn.solution_slice(L, self.N, self.cfg, t))[:n] for t in taus}
+        U = {t % T: c64(syn.link_slice(L, self.cfg, t % T)) for t in sorted({t - 1 for t in taus} | set(taus))}
+        t0 = time.perf_counter()
+        oracle.spectator_meson(Gf, eta_f, L, k)
+        oracle.spectator_meson(Gb, eta_b, L, k)
+        oracle.insertion(G3, s, taus, L, T, k, U_t=U, n_ops=self.n_ops)
+        dt = time.perf_counter() - t0
+        units = n * int(np.prod(L)) * len(k) * (2 + len(taus))
+        return units, dt, (f"FP64 numpy oracle: meson spectators at both sinks + insertion (5 ops) on {len(taus)} "
+                           f"of {len(self.taus)} timeslices, full 32^3 slices, {n} of {self.N} noise vectors, "
+                           f"{len(k)} momenta; combines not in the sample")
+
+
 class Batch64:
     """Many source positions over uneven lattices in one recorded graph.
 
@@ -624,7 +720,8 @@ class Batch64:
                            f"timeslices, N=8, {len(k)} momenta; nucleon sources and combines not in the sample")
 
 
-WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48, "batch64": Batch64}
+WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48, "twosink32": TwoSink32,
+             "batch64": Batch64}
 
 
 # ---------------------------------------------------------------------------
