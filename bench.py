@@ -100,17 +100,34 @@ CONTRACTION_FLOPS = {"spectator_meson": 8.0 * 576, "spectator_baryon": 8.0 * 115
 # and workload names.  Each entry carries a hash of the kernel sources it was
 # measured with and is reported only while they are unchanged.
 TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_device.h", "c3pt_internal.h",
-                   "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip", "c3pt_api.hip"]
+                   "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip"]
+# host functions of c3pt_api.hip that plan and launch the factored kernels
+TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table", "plan_planes", "plan_chunks",
+                     "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name -> (bytes per launch, source hash)
-    # 32^3 step: local (484218 + 264384 KiB) and derivative (1968476 + 1074944 KiB) dispatches of one call
-    ("meson32", "fac", "fac_insertion"): ((484218 + 1968476) * 2048 + (264384 + 1074944) * 1024, "776c052143630254"),
-    # 48^3 step: one nucleon spectator dispatch (414934 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon"): (414934 * 2048 + 857088 * 1024, "776c052143630254"),
-    # two-sink 32^3 x 96 step: local (3755090 + 4687200 KiB) and derivative (21429519 + 19017600 KiB)
-    ("twosink32", "fac", "fac_insertion"): ((3755090 + 21429519) * 2048 + (4687200 + 19017600) * 1024,
-                                           "776c052143630254"),
+    # 32^3 step: local (484218 + 264384 KiB) and derivative (1971678 + 1074944 KiB) dispatches of one call
+    ("meson32", "fac", "fac_insertion"): ((484218 + 1971678) * 2048 + (264384 + 1074944) * 1024, "a1cad2471bd3ac3a"),
+    # 48^3 step: one nucleon spectator dispatch (415053 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon"): (415053 * 2048 + 857088 * 1024, "a1cad2471bd3ac3a"),
+    # two-sink 32^3 x 96 step: local (3757005 + 4687200 KiB) and derivative (21666167 + 19017600 KiB)
+    ("twosink32", "fac", "fac_insertion"): ((3757005 + 21666167) * 2048 + (4687200 + 19017600) * 1024, "a1cad2471bd3ac3a"),
 }
+
+
+def _function_text(src: str, name: str) -> str:
+    """Text of a top-level function definition: from the line that starts it
+    (return type and name at column 0, or its template line) to the first
+    closing brace at column 0."""
+    lines = src.splitlines()
+    for i, ln in enumerate(lines):
+        if ln[:1].isalpha() and f" {name}(" in ln:
+            j = i
+            while lines[j] != "}":
+                j += 1
+            start = i - 1 if i > 0 and lines[i - 1].startswith("template") else i
+            return "\n".join(lines[start:j + 1])
+    raise KeyError(name)
 
 
 def sources_hash():
@@ -120,6 +137,10 @@ def sources_hash():
     for name in TRAFFIC_SOURCES:
         with open(os.path.join(base, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(base, "c3pt_api.hip")) as f:
+        api = f.read()
+    for name in TRAFFIC_FUNCTIONS:
+        h.update(_function_text(api, name).encode())
     return h.hexdigest()[:16]
 
 
@@ -431,7 +452,8 @@ class TwoSink32(Meson32):
     sink timeslices, momenta |k|^2 <= 8 (93).  One step = spectators at both
     sinks, the insertion (local and the four D_nu) on the 21 timeslices
     20..40, and the forward / backward combines on the 185 pairs with p' = q or
-    p' = 0, all in one c3pt_two_sink_meson call."""
+    p' = 0, all in one c3pt_two_sink_meson call; then the 16 x 16 x 16 Gamma
+    channels of both diagrams (c3pt_gamma_meson)."""
     L = (32, 32, 32)
     T = 96
     t_src, t_fwd, t_bwd = 30, 20, 40
@@ -448,7 +470,7 @@ class TwoSink32(Meson32):
         self.baryon = False
         self.taus = [(self.t_fwd + j) % self.T for j in range((self.t_bwd - self.t_fwd) % self.T + 1)]
         self.name = ("meson 3pt forward + backward with time-partitioned noise, 32^3x96, r_4=30, x'_4=20, "
-                     "x''_4=40, N=50, |k|^2<=8 (93 momenta), local+4 D_nu, 185 pairs")
+                     "x''_4=40, N=50, |k|^2<=8 (93 momenta), local+4 D_nu, 185 pairs, 16^3 Gamma channels")
 
     def setup(self, c3pt, syn, dev, geom, k):
         L, T = self.L, self.T
@@ -477,6 +499,9 @@ class TwoSink32(Meson32):
 
     def step(self):
         self.out = self._run()
+        # analysis stage: every Gamma_snk x Gamma_ins x Gamma_src channel of both diagrams
+        self.ch_fwd = self.c3pt.gamma_meson(self.out["fwd"])
+        self.ch_bwd = self.c3pt.gamma_meson(self.out["bwd"])
 
     def units(self, n_mom):
         return self.N * int(np.prod(self.L)) * n_mom * (2 + len(self.taus))

@@ -9,6 +9,8 @@
  *   spectator part, Eq. (9)      c3pt_spectator_meson / c3pt_spectator_baryon
  *   insertion part, Eq. (10)     c3pt_insertion
  *   noise-averaged product of the two parts (Eq. (5) in Eq. (8))   c3pt_combine
+ *   forward + backward diagrams, time-partitioned noise (Sec. 2.3)  c3pt_two_sink_meson
+ *   Gamma channels of the spin-open data (Eq. (1), Sec. 3)  c3pt_gamma_meson / c3pt_gamma_nucleon
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -183,6 +185,53 @@ int c3pt_two_sink_meson(const c3pt_geom* geom, const void* G_fwd, const void* et
                         const void* const* G_t, const void* const* s_t, const void* const* U_t, int n_ops,
                         const int* k, int n_mom, const double* w, const int* pairs, int n_pairs, void* spec,
                         void* ins, void* out_fwd, void* out_bwd);
+
+/*
+ * Analysis stage: Gamma channels of the spin-open meson data.  The trace of
+ * Eq. (1) for any Gamma_snk, Gamma_ins and source matrix follows from the
+ * combine output by contracting its open spins (Sec. 1, Sec. 3):
+ *   out[blk][i][j][l] = sum Gsnk_i[a'][b'] Gins_j[at][bt] Gsrc_l[b][a] C[blk][b'][a'][a][at][bt][b]
+ *   C     : device complex128 [n_blk][64][64], rows (b', a', a), columns
+ *           (at, bt, b): any number of blocks of c3pt_combine's meson output
+ *           (pair, timeslice, operator).  For a derivative operator D_nu,
+ *           Gins = gamma_mu gives gamma_mu D_nu.
+ *   g_snk, g_ins, g_src : host complex128 [n][4][4] (interleaved re, im; row
+ *           index first), 1 <= n <= 16; NULL selects the 16 Gamma_n =
+ *           g1^b0 g2^b1 g3^b2 g4^b3 (n = b0 + 2 b1 + 4 b2 + 8 b3) for g_snk and
+ *           g_ins and the creation matrices gamma4 Gamma_n^dag gamma4 of
+ *           Eq. (3) for g_src (then the count must be 16).
+ *   out   : device complex128 [n_blk][n_snk][n_ins][n_src].
+ * FP64 throughout.
+ */
+int c3pt_gamma_meson(const void* C, int n_blk, const double* g_snk, int n_snk, const double* g_ins, int n_ins,
+                     const double* g_src, int n_src, void* out, void* stream);
+
+#define C3PT_PROTON_D  0   /* current on the d quark: spectators (G1, G2) = (u, u)  */
+#define C3PT_PROTON_U  1   /* current on a u quark: spectators (G1, G2) = (u, d)    */
+
+/*
+ * Analysis stage for the nucleon data (the paper times a baryon measurement,
+ * Sec. 3, without printing its contraction; the reading used here): proton
+ * chi_g = eps_abc (u_a^T A d_b) u_c^g at the sink, chibar = chi^dag gamma4 =
+ * eps_abc ubar_c (dbar_b Abar ubar_a^T) at the source, current J_j =
+ * qbar Gins_j q; connected Wick contractions with the proton's two (d
+ * current) or four (u current) pairings of the identical u quarks:
+ *   out[blk][p][j] = tr[P_p G_j],  G_j[g][d] = <chi_g(x') J_j(y) chibar_d(r)>,
+ * evaluated from the combine's nucleon output of the matching spectator pair.
+ *   C       : device complex128 [n_blk][1024][64] (rows a1', a1, a2', a2, b';
+ *             columns at, bt, b), blocks of c3pt_combine's nucleon output.
+ *   channel : C3PT_PROTON_D or C3PT_PROTON_U.
+ *   A, Abar : host complex128 [4][4] or NULL for A = C gamma5 with
+ *             C = gamma2 gamma4 and Abar = gamma4 A^dag gamma4.
+ *   P       : host complex128 [n_proj][4][4] (1 <= n_proj <= 16), or NULL for
+ *             (1 + gamma4)/2 and (1 - gamma4)/2 (n_proj = 2).
+ *   g_ins   : host complex128 [n_ins][4][4] (1 <= n_ins <= 16) or NULL for the
+ *             16 Gamma_n (n_ins = 16).
+ *   out     : device complex128 [n_blk][n_proj][n_ins].
+ * FP64 throughout.  Only rows of C with a non-zero weight are read.
+ */
+int c3pt_gamma_nucleon(const void* C, int n_blk, int channel, const double* A, const double* Abar,
+                       const double* P, int n_proj, const double* g_ins, int n_ins, void* out, void* stream);
 
 /* Static description of a status code. */
 const char* c3pt_strerror(int status);

@@ -340,3 +340,91 @@ def two_sink_meson(G1_fwd, eta_fwd, t_fwd, G1_bwd, eta_bwd, t_bwd, t_src, G_t, s
     return {"spec": np.stack([S_f, S_b]), "ins": I, "taus": taus,
             "fwd": combine(S_f, I[:, :n_fwd], w=w, pairs=pairs),
             "bwd": combine(S_b, I[:, n_fwd - 1:], w=w, pairs=pairs)}
+
+
+# --------------------------------------------------------------------------
+# Analysis stage: Gamma channels of the spin-open data (Sec. 1 and Sec. 3:
+# every source / sink Gamma and every Gamma_ins follow from one measurement).
+# --------------------------------------------------------------------------
+def creation_matrix(G) -> np.ndarray:
+    """gamma4 G^dag gamma4: the matrix of the creation operator, Eq. (3)."""
+    return GAMMA[3] @ np.conj(np.asarray(G, dtype=np.complex128)).T @ GAMMA[3]
+
+
+def charge_conjugation() -> np.ndarray:
+    """C = gamma2 gamma4, for which C gamma_mu C^-1 = -gamma_mu^T in this basis."""
+    return GAMMA[1] @ GAMMA[3]
+
+
+def _mats(m, default):
+    if m is None:
+        m = default
+    return np.asarray(m, dtype=np.complex128).reshape(-1, 4, 4)
+
+
+def gamma_project_meson(C, g_snk=None, g_ins=None, g_src=None) -> np.ndarray:
+    """Eq. (1) with the spins of the combine output contracted:
+    out[..., i, j, l] = sum Gsnk_i^{a' b'} Gins_j^{at bt} Gsrc_l^{b a} C[..., b', a', a, at, bt, b].
+
+    C: [..., 64, 64], rows (b', a', a), columns (at, bt, b) as combine()
+    returns them for the meson.  Defaults: Gsnk = Gins = the 16 Gamma_n of
+    gamma_basis16(); Gsrc_l = gamma4 Gamma_l^dag gamma4 (the creation operator
+    of Eq. (3) with Gamma = Gamma_l)."""
+    C = np.asarray(C, dtype=np.complex128)
+    g16 = gamma_basis16()
+    Gs = _mats(g_snk, g16)
+    Gi = _mats(g_ins, g16)
+    Gc = _mats(g_src, [creation_matrix(g) for g in g16])
+    T6 = C.reshape(C.shape[:-2] + (4,) * 6)
+    return np.einsum('...BAaxyb,iAB,jxy,lba->...ijl', T6, Gs, Gi, Gc, optimize=True)
+
+
+# Wick contractions of the proton three-point function with the spin-open
+# nucleon data.  Proton chi_g = eps_abc (u_a^T A d_b) u_c^g, its conjugate
+# chibar_d = chi^dag gamma4 = eps_abc ubar_c^d (dbar_b Abar ubar_a^T) with
+# Abar = gamma4 A^dag gamma4; current J = qbar Gamma q; connected diagrams.
+# The data C[a1'][a1][a2'][a2][b'][at][bt][b] carry the sink (a1', a2', b') and
+# source (a1, a2, b) spins of the spectator lines G1, G2 and of the active line.
+# A term is (sign, sink roles, source roles): the sink roles name the tensor
+# spins of (u_a, d_b, u_c) -- the two diquark spins of A, then the nucleon
+# spin -- and the source roles those of (dbar_b, ubar_a, ubar_c).
+#   "d": spectators (G1, G2) = (u, u), the d quark active (two u pairings);
+#   "u": spectators (G1, G2) = (u, d), a u quark active (four pairings).
+PROTON_TERMS = {
+    "d": [(+1, ("a1'", "b'", "a2'"), ("b", "a1", "a2")),
+          (+1, ("a1'", "b'", "a2'"), ("b", "a2", "a1"))],
+    "u": [(+1, ("b'", "a2'", "a1'"), ("a2", "b", "a1")),
+          (+1, ("b'", "a2'", "a1'"), ("a2", "a1", "b")),
+          (+1, ("a1'", "a2'", "b'"), ("a2", "b", "a1")),
+          (+1, ("a1'", "a2'", "b'"), ("a2", "a1", "b"))],
+}
+_NUC_LABEL = {"a1'": 'A', "a1": 'B', "a2'": 'C', "a2": 'D', "b'": 'E', "b": 'H'}
+
+
+def parity_projectors() -> np.ndarray:
+    """(1 + gamma4)/2 and (1 - gamma4)/2."""
+    one = np.eye(4, dtype=np.complex128)
+    return np.stack([(one + GAMMA[3]) / 2, (one - GAMMA[3]) / 2])
+
+
+def gamma_project_nucleon(C, channel: str, A=None, Abar=None, P=None, g_ins=None) -> np.ndarray:
+    """out[..., p, j] = tr[P_p G_j] with G_j[g][d] = <chi_g(x') J_j(y) chibar_d(r)>,
+    J_j = qbar Gamma_j q, summed over the Wick terms of PROTON_TERMS[channel]:
+    sum_t sign_t sum A[s1][s2] Abar[r1][r2] P_p[d][g] Gins_j[at][bt] C[...].
+
+    C: [..., 1024, 64] as combine() returns it for the nucleon.  Defaults:
+    A = C gamma5, Abar = gamma4 A^dag gamma4, P = the two parity projectors,
+    Gins = the 16 Gamma_n."""
+    C = np.asarray(C, dtype=np.complex128)
+    A = charge_conjugation() @ GAMMA5 if A is None else np.asarray(A, dtype=np.complex128)
+    Abar = creation_matrix(A) if Abar is None else np.asarray(Abar, dtype=np.complex128)
+    Ps = parity_projectors() if P is None else np.asarray(P, dtype=np.complex128).reshape(-1, 4, 4)
+    Gi = _mats(g_ins, gamma_basis16())
+    T8 = C.reshape(C.shape[:-2] + (4,) * 8)      # [a1'][a1][a2'][a2][b'][at][bt][b]
+    out = np.zeros(C.shape[:-2] + (len(Ps), len(Gi)), dtype=np.complex128)
+    for sign, snk, src in PROTON_TERMS[channel]:
+        s1, s2, sn = (_NUC_LABEL[x] for x in snk)
+        r1, r2, rn = (_NUC_LABEL[x] for x in src)
+        expr = f'...ABCDEFGH,{s1}{s2},{r1}{r2},p{rn}{sn},jFG->...pj'
+        out += sign * np.einsum(expr, T8, A, Abar, Ps, Gi, optimize=True)
+    return out

@@ -35,9 +35,11 @@ PROJ_NATIVE = 0
 PROJ_SPLIT_F16 = 1
 PROJ_SPLIT_BF16 = 2
 PROJ_FACTORED = 3
+PROTON_D = 0   # current on the d quark; nucleon data of spectators (u, u)
+PROTON_U = 1   # current on a u quark; nucleon data of spectators (u, d)
 
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
-            "c3pt_two_sink_meson", "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
+            "c3pt_two_sink_meson", "c3pt_gamma_meson", "c3pt_gamma_nucleon", "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
             "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read", "c3pt_variant_count",
             "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
             "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
@@ -108,8 +110,11 @@ def _load():
     lib.c3pt_two_sink_meson.argtypes = [gp, vp, vp, i, vp, vp, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                         ctypes.POINTER(vp), i, ip, i, ctypes.POINTER(ctypes.c_double), ip, i,
                                         vp, vp, vp, vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.c3pt_gamma_meson.argtypes = [vp, i, dp, i, dp, i, dp, i, vp, vp]
+    lib.c3pt_gamma_nucleon.argtypes = [vp, i, i, dp, dp, dp, i, dp, i, vp, vp]
     for name in ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
-                 "c3pt_two_sink_meson"):
+                 "c3pt_two_sink_meson", "c3pt_gamma_meson", "c3pt_gamma_nucleon"):
         getattr(lib, name).restype = ctypes.c_int
     lib.c3pt_strerror.argtypes = [i]
     lib.c3pt_strerror.restype = ctypes.c_char_p
@@ -350,11 +355,66 @@ def c3pt_two_sink_meson(G_fwd: torch.Tensor, eta_fwd: torch.Tensor, t_fwd: int, 
     return {"spec": spec, "ins": ins, "fwd": fwd, "bwd": bwd, "taus": taus}
 
 
+def _mats(m, name):
+    """Host complex matrices [n][4][4] as (pointer, count, keep-alive array), or NULL."""
+    import numpy as np
+    if m is None:
+        return None, 0, None
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128).reshape(-1, 4, 4))
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), a.shape[0], a
+
+
+def _stream(stream):
+    return ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+
+
+def c3pt_gamma_meson(C: torch.Tensor, g_snk=None, g_ins=None, g_src=None, out=None, stream=None) -> torch.Tensor:
+    """Gamma channels of meson combine output C [..., 64, 64] (c3pt_gamma_meson).
+    Returns [..., n_snk, n_ins, n_src]; None selects the 16 Gamma_n (sink and
+    insertion) and gamma4 Gamma_n^dag gamma4 (source)."""
+    if C.shape[-2:] != (64, 64):
+        raise ValueError(f"C: shape {tuple(C.shape)}, expected [..., 64, 64]")
+    _field(C, "C", tuple(C.shape), torch.complex128)
+    n_blk = C.numel() // 4096
+    ps, ns, ks = _mats(g_snk, "g_snk")
+    pi, ni, ki = _mats(g_ins, "g_ins")
+    pc, nc, kc = _mats(g_src, "g_src")
+    ns, ni, nc = ns or 16, ni or 16, nc or 16
+    shape = tuple(C.shape[:-2]) + (ns, ni, nc)
+    out = _out(out, shape, C)
+    _check(lib.c3pt_gamma_meson(C.data_ptr(), n_blk, ps, ns, pi, ni, pc, nc, out.data_ptr(), _stream(stream)))
+    return out
+
+
+def c3pt_gamma_nucleon(C: torch.Tensor, channel: int, A=None, Abar=None, P=None, g_ins=None, out=None,
+                       stream=None) -> torch.Tensor:
+    """Proton channels of nucleon combine output C [..., 1024, 64] (c3pt_gamma_nucleon).
+    Returns [..., n_proj, n_ins]."""
+    if C.shape[-2:] != (1024, 64):
+        raise ValueError(f"C: shape {tuple(C.shape)}, expected [..., 1024, 64]")
+    _field(C, "C", tuple(C.shape), torch.complex128)
+    n_blk = C.numel() // 65536
+    pa, na, ka = _mats(A, "A")
+    pb, nb, kb = _mats(Abar, "Abar")
+    if na not in (0, 1) or nb not in (0, 1):
+        raise ValueError("A and Abar are single 4x4 matrices")
+    pp, npj, kp = _mats(P, "P")
+    pi, ni, ki = _mats(g_ins, "g_ins")
+    npj, ni = npj or 2, ni or 16
+    shape = tuple(C.shape[:-2]) + (npj, ni)
+    out = _out(out, shape, C)
+    _check(lib.c3pt_gamma_nucleon(C.data_ptr(), n_blk, int(channel), pa, pb, pp, npj, pi, ni, out.data_ptr(),
+                                  _stream(stream)))
+    return out
+
+
 spectator_meson = c3pt_spectator_meson
 spectator_baryon = c3pt_spectator_baryon
 insertion = c3pt_insertion
 combine = c3pt_combine
 two_sink_meson = c3pt_two_sink_meson
+gamma_meson = c3pt_gamma_meson
+gamma_nucleon = c3pt_gamma_nucleon
 
 
 def momentum_list(n2max: int):

@@ -15,6 +15,7 @@
 
 #include "../../include/c3pt.h"
 #include "c3pt_internal.h"
+#include "c3pt_analysis.h"
 
 using namespace c3pt;
 
@@ -879,5 +880,85 @@ int c3pt_two_sink_meson(const c3pt_geom* geom, const void* G_fwd, const void* et
     return ok();
 }
 
+
+int c3pt_gamma_meson(const void* C, int n_blk, const double* g_snk, int n_snk, const double* g_ins, int n_ins,
+                     const double* g_src, int n_src, void* out, void* stream) {
+    if (!C || !out) return fail(C3PT_EINVAL, "NULL data or output pointer");
+    if (n_blk < 1) return fail(C3PT_EINVAL, "n_blk = %d < 1", n_blk);
+    const int n[3] = {n_snk, n_ins, n_src};
+    const double* m[3] = {g_snk, g_ins, g_src};
+    for (int s = 0; s < 3; ++s) {
+        if (n[s] < 1 || n[s] > 16) return fail(C3PT_EINVAL, "matrix count %d outside [1, 16]", n[s]);
+        if (!m[s] && n[s] != 16) return fail(C3PT_EINVAL, "the default matrix lists hold 16 matrices");
+    }
+    std::vector<double2> mats(3 * 256, make_double2(0.0, 0.0));
+    for (int s = 0; s < 3; ++s) {
+        if (m[s])
+            memcpy(mats.data() + 256 * s, m[s], (size_t)n[s] * 16 * sizeof(double2));
+        else
+            c3pt::gamma_default_matrices(s, mats.data() + 256 * s);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    void* base;
+    if (int rc = scratch_dev(st, mats.size() * sizeof(double2), &base)) return rc;
+    if (int rc = upload(st, base, 0, mats.data(), mats.size() * sizeof(double2))) return rc;
+    GammaMesonArgs a;
+    a.C = (const double2*)C;
+    a.mats = (const double2*)base;
+    a.out = (double2*)out;
+    a.n_blk = n_blk;
+    a.n_snk = n_snk;
+    a.n_ins = n_ins;
+    a.n_src = n_src;
+    if (int rc = to_status(timed("gamma_meson", st, [&] { return launch_gamma_meson(a, st); }), "gamma launch"))
+        return rc;
+    return ok();
+}
+
+int c3pt_gamma_nucleon(const void* C, int n_blk, int channel, const double* A, const double* Abar,
+                       const double* P, int n_proj, const double* g_ins, int n_ins, void* out, void* stream) {
+    if (!C || !out) return fail(C3PT_EINVAL, "NULL data or output pointer");
+    if (n_blk < 1) return fail(C3PT_EINVAL, "n_blk = %d < 1", n_blk);
+    if (channel != C3PT_PROTON_D && channel != C3PT_PROTON_U) return fail(C3PT_EINVAL, "unknown channel %d", channel);
+    if (n_proj < 1 || n_proj > kMaxNucProj) return fail(C3PT_EINVAL, "n_proj = %d outside [1, 16]", n_proj);
+    if (!P && n_proj != 2) return fail(C3PT_EINVAL, "the default projectors are two");
+    if (n_ins < 1 || n_ins > 16) return fail(C3PT_EINVAL, "n_ins = %d outside [1, 16]", n_ins);
+    if (!g_ins && n_ins != 16) return fail(C3PT_EINVAL, "the default insertion list holds 16 matrices");
+    std::vector<int> rows;
+    std::vector<double2> w;
+    c3pt::nucleon_weights(channel == C3PT_PROTON_D ? 0 : 1, A, Abar, P, n_proj, &rows, &w);
+    std::vector<double2> gi(256, make_double2(0.0, 0.0));
+    if (g_ins)
+        memcpy(gi.data(), g_ins, (size_t)n_ins * 16 * sizeof(double2));
+    else
+        c3pt::gamma_default_matrices(1, gi.data());
+    // device table: Gins, rows, weights (256-byte aligned pieces)
+    const size_t gbytes = gi.size() * sizeof(double2);
+    const size_t roff = (gbytes + 255) & ~(size_t)255;
+    const size_t rbytes = std::max<size_t>(rows.size(), 1) * sizeof(int);
+    const size_t woff = (roff + rbytes + 255) & ~(size_t)255;
+    const size_t wbytes = w.size() * sizeof(double2);
+    std::vector<char> host(woff + wbytes);
+    memcpy(host.data(), gi.data(), gbytes);
+    if (!rows.empty()) memcpy(host.data() + roff, rows.data(), rows.size() * sizeof(int));
+    if (wbytes) memcpy(host.data() + woff, w.data(), wbytes);
+    hipStream_t st = (hipStream_t)stream;
+    void* base;
+    if (int rc = scratch_dev(st, host.size() + 256, &base)) return rc;
+    if (int rc = upload(st, base, 0, host.data(), host.size())) return rc;
+    GammaNucleonArgs a;
+    a.C = (const double2*)C;
+    a.gins = (const double2*)base;
+    a.rows = (const int*)((char*)base + roff);
+    a.w = (const double2*)((char*)base + woff);
+    a.out = (double2*)out;
+    a.n_blk = n_blk;
+    a.n_rows = (int)rows.size();
+    a.n_proj = n_proj;
+    a.n_ins = n_ins;
+    if (int rc = to_status(timed("gamma_nucleon", st, [&] { return launch_gamma_nucleon(a, st); }), "gamma launch"))
+        return rc;
+    return ok();
+}
 
 }  // extern "C"

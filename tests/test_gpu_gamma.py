@@ -1,0 +1,103 @@
+"""Gamma channels of the spin-open data on the GPU (c3pt_gamma_meson,
+c3pt_gamma_nucleon) against the FP64 oracle (pinned by the trace of Eq. (1)
+and by a brute-force Wick contraction): random blocks with the default and
+with random matrix lists, the two proton currents, a composed two-sink
+measurement, and argument errors.  Tolerance 1e-12 (FP64 throughout)."""
+import numpy as np
+import pytest
+
+import c3pt_synth as syn
+import oracle
+from helpers import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a.astype(np.complex128))).cuda()
+
+
+@pytest.mark.parametrize("counts", [None, (3, 5, 7), (16, 1, 16), (1, 16, 2)])
+def test_gamma_meson_matches_oracle(counts):
+    import paper_1711_02384_amd as c3pt
+    _say(f"gamma meson, matrix counts {counts}")
+    g = np.random.default_rng(21)
+    C = syn.gaussian((3, 2, 5, 64, 64), g)
+    if counts is None:
+        mats = (None, None, None)
+    else:
+        mats = tuple(syn.gaussian((n, 4, 4), g) for n in counts)
+    got = c3pt.gamma_meson(_dev(C), *mats)
+    torch.cuda.synchronize()
+    want = oracle.gamma_project_meson(C, *mats)
+    assert got.shape == want.shape
+    assert rel_fro(got.cpu().numpy(), want) < 1e-12
+
+
+@pytest.mark.parametrize("channel", ["d", "u"])
+@pytest.mark.parametrize("custom", [False, True])
+def test_gamma_nucleon_matches_oracle(channel, custom):
+    import paper_1711_02384_amd as c3pt
+    _say(f"gamma nucleon, channel {channel}, custom matrices {custom}")
+    g = np.random.default_rng(22 + custom)
+    C = syn.gaussian((2, 3, 1024, 64), g)
+    kw = {}
+    if custom:
+        kw = dict(A=syn.gaussian((4, 4), g), Abar=syn.gaussian((4, 4), g), P=syn.gaussian((3, 4, 4), g),
+                  g_ins=syn.gaussian((5, 4, 4), g))
+    ch = c3pt.PROTON_D if channel == "d" else c3pt.PROTON_U
+    got = c3pt.gamma_nucleon(_dev(C), ch, **kw)
+    torch.cuda.synchronize()
+    want = oracle.gamma_project_nucleon(C, channel, **kw)
+    assert got.shape == want.shape
+    assert rel_fro(got.cpu().numpy(), want) < 1e-12
+
+
+def test_gamma_meson_after_two_sink_measurement():
+    """The channels of a complete two-sink measurement (complex128) equal the
+    oracle's channels of the oracle's measurement."""
+    import paper_1711_02384_amd as c3pt
+    _say("gamma meson on two-sink output")
+    L, T, N = (4, 4, 3), 8, 2
+    tf, ts, tb = 1, 3, 6
+    cfg = 80
+    n_span = 6
+    taus = [(tf + j) % T for j in range(n_span)]
+    G1f = syn.propagator_slice(L, cfg, syn.FIELD_G1, tf)
+    G1b = syn.propagator_slice(L, cfg, syn.FIELD_G1, tb)
+    eta_f = syn.z2z2_noise(L, N, cfg, tf)
+    eta_b = syn.z2z2_noise(L, N, cfg, tb)
+    G3 = {t: syn.propagator_slice(L, cfg, syn.FIELD_G3, t) for t in taus}
+    s = {t: syn.solution_slice(L, N, cfg, t) for t in taus}
+    k = c3pt.momentum_list(1)
+    pairs = [(0, 0), (1, 1), (0, 3)]
+    res = c3pt.two_sink_meson(_dev(G1f), _dev(eta_f), tf, _dev(G1b), _dev(eta_b), tb, ts,
+                              {t: _dev(v) for t, v in G3.items()}, {t: _dev(v) for t, v in s.items()}, k,
+                              c3pt.Geom(L, T), pairs=pairs)
+    ch_f = c3pt.gamma_meson(res["fwd"])
+    ch_b = c3pt.gamma_meson(res["bwd"])
+    torch.cuda.synchronize()
+    want = oracle.two_sink_meson(G1f, eta_f, tf, G1b, eta_b, tb, ts, G3, s, L, T, k, pairs=pairs)
+    assert rel_fro(ch_f.cpu().numpy(), oracle.gamma_project_meson(want["fwd"])) < 1e-12
+    assert rel_fro(ch_b.cpu().numpy(), oracle.gamma_project_meson(want["bwd"])) < 1e-12
+
+
+def test_gamma_rejects_bad_arguments():
+    import paper_1711_02384_amd as c3pt
+    _say("gamma argument checks")
+    g = np.random.default_rng(23)
+    C = _dev(syn.gaussian((1, 64, 64), g))
+    with pytest.raises(c3pt.C3ptError):
+        c3pt.gamma_meson(C, g_snk=syn.gaussian((17, 4, 4), g))
+    Cn = _dev(syn.gaussian((1, 1024, 64), g))
+    with pytest.raises(c3pt.C3ptError):
+        c3pt.gamma_nucleon(Cn, 7)
+    with pytest.raises(c3pt.C3ptError):
+        c3pt.gamma_nucleon(Cn, c3pt.PROTON_U, P=syn.gaussian((17, 4, 4), g))
+    with pytest.raises(ValueError):
+        c3pt.gamma_nucleon(C, c3pt.PROTON_D)
