@@ -89,12 +89,13 @@ def meson_trace(G1_tf, G2_yx, G3_tau, L, kp, q, g_snk, g_ins, g_src, r=(0, 0, 0)
 
 
 def derivative_field(G_t, U_t, L, T, tau, nu) -> np.ndarray:
-    """(D_nu G)(y) = 1/2 [U_nu(y) G(y+nu) - U_nu(y-nu)^dag G(y-nu)] as [V3][12][12],
-    using explicit neighbour lookup and kron(1_spin, U) matrices."""
+    """(D_nu G)(y) = 1/2 [U_nu(y) G(y+nu) - U_nu(y-nu)^dag G(y-nu)] as [V3][12][M]
+    for G_t: t -> [12][M][V3] (row index at y), using explicit neighbour lookup
+    and kron(1_spin, U) matrices."""
     L1, L2, L3 = (int(v) for v in L)
     x = site_coords(L)
     V3 = x.shape[0]
-    out = np.zeros((V3, 12, 12), dtype=np.complex128)
+    out = np.zeros((V3, 12, np.asarray(G_t[tau]).shape[1]), dtype=np.complex128)
 
     def idx(c):
         return int(c[0] % L1 + L1 * ((c[1] % L2) + L2 * (c[2] % L3)))

@@ -256,26 +256,60 @@ def _insertion_local(G, s, L, k, r):
     return np.ascontiguousarray(out.transpose(0, 2, 1))
 
 
+def covariant_derivative_vector(v_t, U_t, L, T: int, tau: int, nu: int) -> np.ndarray:
+    """(D_nu v)(y) = 1/2 [U_nu(y) v(y+nu) - U_nu(y-nu)^dag v(y-nu)] for the
+    colour vectors v_t: t -> [N][12][V3] (spin and noise index untouched), the
+    same lattice derivative as covariant_derivative.  Returns [N][12][V3]."""
+    v = np.asarray(v_t[tau], dtype=np.complex128)
+    N, V3 = v.shape[0], v.shape[-1]
+    if nu < 3:
+        vp = _neighbour(v_t[tau], L, nu, +1)
+        vm = _neighbour(v_t[tau], L, nu, -1)
+        Uy = U_t[tau][nu]
+        Um = _neighbour(U_t[tau][nu], L, nu, -1)
+    else:
+        vp = v_t[(tau + 1) % T]
+        vm = v_t[(tau - 1) % T]
+        Uy = U_t[tau][3]
+        Um = U_t[(tau - 1) % T][3]
+    vp = np.asarray(vp, dtype=np.complex128).reshape(N, 4, 3, V3)
+    vm = np.asarray(vm, dtype=np.complex128).reshape(N, 4, 3, V3)
+    fwd = np.einsum('cdx,isdx->iscx', Uy, vp)
+    bwd = np.einsum('dcx,isdx->iscx', np.conj(Um), vm)
+    return (0.5 * (fwd - bwd)).reshape(N, 12, V3)
+
+
 def insertion(G_t, s_t, taus, L, T: int, k, r=(0, 0, 0), U_t=None, n_ops: int = 1) -> np.ndarray:
     """Insertion part, Eq. (10), at every tau in ``taus``.
 
     G_t: mapping t -> [12][12][V3] propagator slice; s_t: t -> [N][12][V3];
-    U_t: t -> [4][3][3][V3] (needed when n_ops == 5).
+    U_t: t -> [4][3][3][V3] (needed when n_ops > 1).
     Operators: op 0 is local (all 16 Gamma stay open in (at, bt)); ops 1..4 are
     the derivative D_nu for nu = x, y, z, t applied to G before the same
-    contraction (gamma_mu D_nu follows by contracting (at, bt) with gamma_mu).
+    contraction (gamma_mu D_nu follows by contracting (at, bt) with gamma_mu);
+    with n_ops = 9, ops 5..8 are the symmetrized derivative
+    <->D_nu = 1/2 (->D_nu - <-D_nu).  The left derivative acts on the
+    antiquark field of the insertion, whose factorized form is the conjugated
+    gamma5 s (Eq. (10)); moving it there turns it into D_nu applied to s, so
+    <-D_nu is the local contraction of G(y) with D_nu s (s needed on tau +- 1
+    for nu = t).
     Returns [N][n_tau][n_ops][n_mom][192]."""
-    assert n_ops in (1, 5)
+    assert n_ops in (1, 5, 9)
     taus = list(taus)
     N = np.asarray(s_t[taus[0]]).shape[0]
     n_mom = len(np.asarray(k).reshape(-1, 3))
     out = np.zeros((N, len(taus), n_ops, n_mom, 192), dtype=np.complex128)
     for j, tau in enumerate(taus):
         out[:, j, 0] = _insertion_local(G_t[tau], s_t[tau], L, k, r)
-        if n_ops == 5:
+        if n_ops >= 5:
             for nu in range(4):
                 DG = covariant_derivative(G_t, U_t, L, T, tau, nu)
                 out[:, j, 1 + nu] = _insertion_local(DG, s_t[tau], L, k, r)
+        if n_ops == 9:
+            for nu in range(4):
+                Ds = covariant_derivative_vector(s_t, U_t, L, T, tau, nu)
+                left = _insertion_local(G_t[tau], Ds, L, k, r)
+                out[:, j, 5 + nu] = 0.5 * (out[:, j, 1 + nu] - left)
     return out
 
 

@@ -305,6 +305,75 @@ def test_derivative_trace_against_bruteforce():
             assert np.allclose(C[j, 0, 1 + nu].reshape((4,) * 6), Cb, atol=1e-12 * np.abs(Cb).max())
 
 
+def _left_derivative_G2(Ghat_t, U, L, T, tau, nu):
+    """(D_nu G2)(y, x') on the y index of G2(y, x') = [V3_y][V3_x'][12][12] per
+    timeslice, through brute.derivative_field with (x', column) as the columns."""
+    V3 = Ghat_t[tau].shape[0]
+    F = {t: np.ascontiguousarray(g.transpose(2, 1, 3, 0).reshape(12, V3 * 12, V3)) for t, g in Ghat_t.items()}
+    D = brute.derivative_field(F, U, L, T, tau, nu)                   # [V3_y][12][V3_x' * 12]
+    return D.reshape(V3, 12, V3, 12).transpose(0, 2, 1, 3)
+
+
+@pytest.mark.parametrize("r", [(0, 0, 0), (1, 0, 1)])
+def test_symmetric_derivative_trace_against_bruteforce(r):
+    """<->D_nu = 1/2 (->D_nu - <-D_nu): the left derivative acts on the end of
+    G_f2(x', y) at the insertion, (G_f2 <-D)(x', y) = 1/2 [G_f2(x', y+nu) U_nu(y)^dag
+    - G_f2(x', y-nu) U_nu(y-nu)], built here on the stochastic estimate of G2 with
+    explicit neighbour lookups and kron(1, U) matrices, then traced as Eq. (1)."""
+    L = (3, 3, 3)
+    T = 4
+    N = 2
+    V3, G1, G3, eta, s, U = _meson_setup(L, N, 57, T=T)
+    kp = oracle.momenta(1)[[0, 2]]
+    q = oracle.momenta(1)[[3, 5]]
+    tau = 3
+    S = oracle.spectator_meson(G1, eta, L, kp, r)
+    I = oracle.insertion(G3, s, [tau], L, T, q, r=r, U_t=U, n_ops=9)
+    C = oracle.combine(S, I, pairs=[(1, 0), (0, 1)])
+    w = np.full(N, 1.0 / N)
+    Ghat = {t: np.einsum('i,iAy,iBx->yxAB', w, s[t], np.conj(eta)) for t in range(T)}
+    for j, (p, qq) in enumerate([(1, 0), (0, 1)]):
+        for nu in range(4):
+            DG3 = np.moveaxis(brute.derivative_field(G3, U, L, T, tau, nu), 0, -1)
+            right = brute.meson_spin_open(G1, Ghat[tau], DG3, L, kp[p], q[qq], r=r)
+            left = brute.meson_spin_open(G1, _left_derivative_G2(Ghat, U, L, T, tau, nu), G3[tau], L, kp[p],
+                                         q[qq], r=r)
+            Cb = 0.5 * (right - left)
+            got = C[j, 0, 5 + nu].reshape((4,) * 6)
+            assert np.allclose(got, Cb, atol=1e-12 * np.abs(Cb).max())
+            assert np.allclose(C[j, 0, 1 + nu].reshape((4,) * 6), right, atol=1e-12 * np.abs(right).max())
+
+
+def test_symmetric_derivative_total_derivative_identity():
+    """Summation by parts over a periodic direction: at insertion momentum
+    q_nu = 0 the site sum of ->D_nu + <-D_nu vanishes (a total derivative), so
+    <->D_nu = ->D_nu there; at q_nu != 0 it does not."""
+    L = (3, 4, 3)
+    T = 4
+    V3, _, G3, _, s, U = _meson_setup(L, 2, 59, T=T)
+    q = np.array([[0, 0, 0], [0, 1, 0], [1, 0, 2], [2, 3, 0]])
+    I = oracle.insertion(G3, s, [2], L, T, q, U_t=U, n_ops=9)
+    for m, qm in enumerate(q):
+        for nu in range(3):
+            fwd, sym = I[:, 0, 1 + nu, m], I[:, 0, 5 + nu, m]
+            if qm[nu] == 0:
+                assert np.allclose(sym, fwd, atol=1e-12 * np.abs(fwd).max())
+            else:
+                assert not np.allclose(sym, fwd, atol=1e-3 * np.abs(fwd).max())
+
+
+def test_vector_derivative_matches_propagator_derivative():
+    """D_nu on the colour vectors of s equals D_nu on a propagator whose columns are them."""
+    L = (3, 2, 2)
+    T = 3
+    V3, _, _, _, s, U = _meson_setup(L, 2, 58, T=T)
+    for nu in range(4):
+        Dv = oracle.covariant_derivative_vector(s, U, L, T, 1, nu)         # [N][12][V3]
+        Gs = {t: np.ascontiguousarray(np.moveaxis(v, 0, 1)) for t, v in s.items()}   # [12][N][V3]
+        Dg = brute.derivative_field(Gs, U, L, T, 1, nu)                    # [V3][12][N]
+        assert np.allclose(np.moveaxis(Dv, -1, 0), np.moveaxis(Dg, 2, 1), atol=1e-13)
+
+
 # ----------------------------------------------------------------------------
 # Symmetries: translation covariance and gauge invariance
 # ----------------------------------------------------------------------------
@@ -389,7 +458,7 @@ def test_gauge_invariance_of_combine():
     def run(G1, G1b, G3, eta, s, U):
         S = oracle.spectator_meson(G1, eta, L, kp)
         B = oracle.spectator_baryon(G1, G1b, eta, L, kp)
-        I = oracle.insertion(G3, s, taus, L, T, q, U_t=U, n_ops=5)
+        I = oracle.insertion(G3, s, taus, L, T, q, U_t=U, n_ops=9)
         return oracle.combine(S, I), oracle.combine(B, I), S, I
 
     C, CB, S, I = run(G1, G1b, G3, eta, s, U)
