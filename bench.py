@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "twosink32", "batch64", "serve"], default="meson32")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
+    ap.add_argument("--ops", type=int, choices=[5, 9], default=None,
+                    help="meson32 / twosink32 insertion operators: 5 = local + 4 D_nu (default), "
+                         "9 = also the 4 symmetrized <->D_nu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
     ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2", "fac"], default=None,
@@ -88,9 +91,11 @@ PEAK_VALU_F32 = 78.6
 # Contraction arithmetic per (site, column block of 192), 8 flops per complex
 # multiply-add: meson spectator and local insertion 192 x 3; baryon 576 for the
 # diquark products plus 192 x 3; derivative insertion 192 x 6 plus the
-# transport of the stochastic vector 12 x 3 x 2.
+# transport of the stochastic vector 12 x 3 x 2; the left derivative of the
+# symmetrized one 192 x 3 plus its transport 12 x 3 x 2.
 CONTRACTION_FLOPS = {"spectator_meson": 8.0 * 576, "spectator_baryon": 8.0 * 1152,
-                     "insertion_local": 8.0 * 576, "insertion_deriv": 8.0 * (1152 + 72)}
+                     "insertion_local": 8.0 * 576, "insertion_deriv": 8.0 * (1152 + 72),
+                     "insertion_left": 8.0 * (576 + 72)}
 
 
 # HBM bytes per launch of the dominant kernel, measured with rocprofv3
@@ -105,13 +110,18 @@ TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_de
 TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table", "plan_planes", "plan_chunks",
                      "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion"]
 MEASURED_TRAFFIC = {
-    # workload, projection, timed kernel name -> (bytes per launch, source hash)
-    # 32^3 step: local (484218 + 264384 KiB) and derivative (1971678 + 1074944 KiB) dispatches of one call
-    ("meson32", "fac", "fac_insertion"): ((484218 + 1971678) * 2048 + (264384 + 1074944) * 1024, "a1cad2471bd3ac3a"),
-    # 48^3 step: one nucleon spectator dispatch (415053 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon"): (415053 * 2048 + 857088 * 1024, "a1cad2471bd3ac3a"),
-    # two-sink 32^3 x 96 step: local (3757005 + 4687200 KiB) and derivative (21666167 + 19017600 KiB)
-    ("twosink32", "fac", "fac_insertion"): ((3757005 + 21666167) * 2048 + (4687200 + 19017600) * 1024, "a1cad2471bd3ac3a"),
+    # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
+    # 32^3 step: local (484219 + 264384 KiB) and derivative (1962253 + 1074944 KiB) dispatches of one call
+    ("meson32", "fac", "fac_insertion", 5): ((484219 + 1962253) * 2048 + (264384 + 1074944) * 1024,
+                                             "d27cf80589d07087"),
+    # the same with the symmetrized derivative: + left-derivative dispatch (1170077 + 1057536 KiB)
+    ("meson32", "fac", "fac_insertion", 9): ((484280 + 1991999 + 1170077) * 2048
+                                             + (264384 + 1074944 + 1057536) * 1024, "d27cf80589d07087"),
+    # 48^3 step: one nucleon spectator dispatch (414763 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414763 * 2048 + 857088 * 1024, "d27cf80589d07087"),
+    # two-sink 32^3 x 96 step: local (3759436 + 4687200 KiB) and derivative (21411653 + 19017600 KiB)
+    ("twosink32", "fac", "fac_insertion", 5): ((3759436 + 21411653) * 2048 + (4687200 + 19017600) * 1024,
+                                               "d27cf80589d07087"),
 }
 
 
@@ -144,8 +154,8 @@ def sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, proj, kname):
-    e = MEASURED_TRAFFIC.get((workload, proj, kname))
+def measured_traffic(workload, proj, kname, n_ops):
+    e = MEASURED_TRAFFIC.get((workload, proj, kname, n_ops))
     if e is None or e[1] != sources_hash():
         return None
     return e[0]
@@ -201,8 +211,10 @@ class Meson32:
 
     def __init__(self, args):
         self.baryon = not args.no_baryon
+        self.n_ops = args.ops or 5
         self.name = ("meson+nucleon 3pt, 32^3x64, t_f=16, tau=0..16, N=4, |k|^2<=6 (81 momenta), "
-                     "local+4 D_nu" + (", nucleon spectator" if self.baryon else ""))
+                     "local+4 D_nu" + (" + 4 symmetrized <->D_nu" if self.n_ops == 9 else "")
+                     + (", nucleon spectator" if self.baryon else ""))
 
     def setup(self, c3pt, syn, dev, geom, k):
         import torch
@@ -213,7 +225,8 @@ class Meson32:
         gsl = sorted({t % T for tau in self.taus for t in (tau - 1, tau, tau + 1)})
         usl = sorted({t % T for tau in self.taus for t in (tau - 1, tau)})
         self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
-        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in self.taus}
+        ssl = gsl if self.n_ops == 9 else self.taus
+        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
         self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
         n_mom, n_tau = len(k), len(self.taus)
         mk = lambda *sh: torch.empty(sh, dtype=torch.complex128, device=dev)
@@ -261,7 +274,8 @@ class Meson32:
     def dominant(self, n_mom, proj):
         V3 = int(np.prod(self.L))
         if proj == "fac":
-            per = CONTRACTION_FLOPS["insertion_local"] + (self.n_ops - 1) * CONTRACTION_FLOPS["insertion_deriv"]
+            per = (CONTRACTION_FLOPS["insertion_local"] + min(self.n_ops - 1, 4) * CONTRACTION_FLOPS["insertion_deriv"]
+                   + max(self.n_ops - 5, 0) * CONTRACTION_FLOPS["insertion_left"])
             return "fac_insertion", self.N * len(self.taus) * V3 * per
         cols = self.N * len(self.taus) * self.n_ops * 192
         return "proj_insertion", 8.0 * n_mom * V3 * cols
@@ -280,7 +294,8 @@ class Meson32:
         taus = self.taus[len(self.taus) // 2: len(self.taus) // 2 + n_slices]
         need = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
         G3 = {t: syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in need}
-        s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in taus}
+        s_sl = need if self.n_ops == 9 else taus
+        s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in s_sl}
         U = {t % T: syn.round_to_c64(syn.link_slice(L, self.cfg, t % T))
              for t in sorted({t - 1 for t in taus} | set(taus))}
         t0 = time.perf_counter()
@@ -468,9 +483,11 @@ class TwoSink32(Meson32):
 
     def __init__(self, args):
         self.baryon = False
+        self.n_ops = args.ops or 5
         self.taus = [(self.t_fwd + j) % self.T for j in range((self.t_bwd - self.t_fwd) % self.T + 1)]
         self.name = ("meson 3pt forward + backward with time-partitioned noise, 32^3x96, r_4=30, x'_4=20, "
-                     "x''_4=40, N=50, |k|^2<=8 (93 momenta), local+4 D_nu, 185 pairs, 16^3 Gamma channels")
+                     "x''_4=40, N=50, |k|^2<=8 (93 momenta), local+4 D_nu"
+                     + (" + 4 symmetrized <->D_nu" if self.n_ops == 9 else "") + ", 185 pairs, 16^3 Gamma channels")
 
     def setup(self, c3pt, syn, dev, geom, k):
         L, T = self.L, self.T
@@ -482,7 +499,8 @@ class TwoSink32(Meson32):
         gsl = sorted({t % T for tau in self.taus for t in (tau - 1, tau, tau + 1)})
         usl = sorted({t % T for tau in self.taus for t in (tau - 1, tau)})
         self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
-        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in self.taus}
+        ssl = gsl if self.n_ops == 9 else self.taus
+        self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
         self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
         self.pairs = pairs_diag_or_zero(len(k))
         self.c3pt, self.geom, self.k = c3pt, geom, k
@@ -527,7 +545,8 @@ class TwoSink32(Meson32):
         taus = [(self.t_src + j) % T for j in range(ns)]
         need = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
         G3 = {t: c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in need}
-        s = {t: c64(syn.solution_slice(L, self.N, self.cfg, t))[:n] for t in taus}
+        s_sl = need if self.n_ops == 9 else taus
+        s = {t: c64(syn.solution_slice(L, self.N, self.cfg, t))[:n] for t in s_sl}
         U = {t % T: c64(syn.link_slice(L, self.cfg, t % T)) for t in sorted({t - 1 for t in taus} | set(taus))}
         t0 = time.perf_counter()
         oracle.spectator_meson(Gf, eta_f, L, k)
@@ -1085,7 +1104,7 @@ def main():
     else:
         kname, flops = W.dominant(n_mom, proj)
         kms = prof.get(kname, {}).get("avg_ms", float("nan"))
-    roofline = roofline_entry(kname, flops, kms, proj, measured_traffic(args.workload, proj, kname))
+    roofline = roofline_entry(kname, flops, kms, proj, measured_traffic(args.workload, proj, kname, getattr(W, "n_ops", 1)))
     if roofline["traffic"] is not None:
         roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1 "
                                     "(copy-calibrated), measured on these kernel sources")

@@ -119,15 +119,22 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
  * Insertion part, Eq. (10), at every timeslice tau in taus[0..n_tau):
  *   I_i(q,tau)[op][at][bt][b][c] = sum_y exp(+i q.(y-r)) g[at]
  *        sum_c' conj(s_i(y)[(at,c')]) (O_op G)(y)[(bt,c')][(b,c)]
- * with O_0 = 1 (all 16 Gamma stay open in (at, bt)) and, when n_ops == 5,
- * O_{1+nu} = D_nu, nu = x, y, z, t:
+ * with O_0 = 1 (all 16 Gamma stay open in (at, bt)) and, when n_ops >= 5,
+ * O_{1+nu} = D_nu, nu = x, y, z, t (the local derivatives of Sec. 2.1):
  *   (D_nu G)(y) = 1/2 [U_nu(y) G(y+nu) - U_nu(y-nu)^dag G(y-nu)],
  * spatial neighbours periodic in L_j, time neighbours taken modulo T.
+ * With n_ops == 9, ops 5+nu are the symmetrized derivative
+ *   <->D_nu = 1/2 (->D_nu - <-D_nu),
+ * where the left derivative acts on the insertion's antiquark; in the
+ * factorized form it is D_nu applied to s: op 5+nu = 1/2 (op 1+nu - I[s -> D_nu s]).
+ * n_ops == 9 runs on the factored projection only (C3PT_PROJ_FACTORED and a
+ * momentum list it factors; C3PT_EUNSUPPORTED otherwise).
  *   G_t : host array of T device pointers (slice t of the propagator, or NULL
- *         where not needed).  Needed: every tau; with n_ops == 5 also tau+-1.
- *   s_t : host array of T device pointers to [n_noise][12][V3]; needed at every tau.
+ *         where not needed).  Needed: every tau; with n_ops >= 5 also tau+-1.
+ *   s_t : host array of T device pointers to [n_noise][12][V3]; needed at every
+ *         tau; with n_ops == 9 also at tau+-1.
  *   U_t : host array of T device pointers to [4][3][3][V3], or NULL when
- *         n_ops == 1.  With n_ops == 5 needed at every tau and tau-1.
+ *         n_ops == 1.  With n_ops >= 5 needed at every tau and tau-1.
  *   out : device complex128 [n_noise][n_tau][n_ops][n_mom][192],
  *         order (at, bt, b, c).
  */

@@ -35,6 +35,13 @@ void gamma_default_matrices(int which, double2* out);
 void nucleon_weights(int channel, const double* A, const double* Abar, const double* P, int n_proj,
                      std::vector<int>* rows, std::vector<double2>* w);
 
+// Symmetrized derivative insertion (n_ops = 9): the left-derivative launch and
+// the in-place assembly of ops 5..8 from ops 1..4 (out: [n_outer][9][n_mom][192]).
+struct InsertionLeftArgs;
+hipError_t launch_fac_insertion_left(bool f64, bool acc, const ProjGrid& pg, const InsertionLeftArgs& a,
+                                     hipStream_t st);
+hipError_t launch_symmetrize(double2* out, long long n_outer, int n_mom, hipStream_t st);
+
 }  // namespace c3pt
 
 #endif

@@ -16,6 +16,7 @@
 #include "../../include/c3pt.h"
 #include "c3pt_internal.h"
 #include "c3pt_analysis.h"
+#include "c3pt_fac_left.h"
 
 using namespace c3pt;
 
@@ -554,6 +555,20 @@ hipError_t api_timed(const char* name, hipStream_t st, const std::function<hipEr
 
 // c3pt_combine over the insertion timeslices [tau0, tau0 + n_tau) of an
 // insertion output holding n_tau_in slices.
+// The symmetrized derivative runs on the factored projection only: every
+// momentum group of the list must factor.
+static int check_symmetric(const c3pt_geom* g, const int* k, int n_mom) {
+    if (g->proj != C3PT_PROJ_FACTORED)
+        return fail(C3PT_EUNSUPPORTED, "n_ops = 9 needs the factored projection (C3PT_PROJ_FACTORED)");
+    const bool f64 = g->dtype == C3PT_C128;
+    for (const MomGroup& mg : momentum_groups(n_mom, f64)) {
+        FactorPlan plan;
+        if (!build_factor_plan(g, +1, k, mg, f64, &plan))
+            return fail(C3PT_EUNSUPPORTED, "n_ops = 9: the momentum list does not factor (too many distinct k1)");
+    }
+    return C3PT_OK;
+}
+
 static int combine_impl(const void* spec, int spec_spin, const void* ins, int n_noise, int n_p, int n_q, int n_tau_in,
                  int tau0, int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
                  int n_pairs, void* out, void* stream) {
@@ -755,24 +770,29 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
     if (!G_t || !s_t || !out) return fail(C3PT_EINVAL, "NULL pointer table or output");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     if (n_tau < 1 || !taus) return fail(C3PT_EINVAL, "empty timeslice list");
-    if (n_ops != 1 && n_ops != 5) return fail(C3PT_EINVAL, "n_ops = %d (must be 1 or 5)", n_ops);
-    if (n_ops == 5 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
+    if (n_ops != 1 && n_ops != 5 && n_ops != 9) return fail(C3PT_EINVAL, "n_ops = %d (must be 1, 5 or 9)", n_ops);
+    if (n_ops > 1 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
     const int T = geom->T;
     for (int j = 0; j < n_tau; ++j) {
         const int t = taus[j];
         if (t < 0 || t >= T) return fail(C3PT_EINVAL, "taus[%d] = %d outside [0, %d)", j, t, T);
         if (!G_t[t]) return fail(C3PT_EINVAL, "propagator slice %d missing", t);
         if (!s_t[t]) return fail(C3PT_EINVAL, "stochastic solution slice %d missing", t);
-        if (n_ops == 5) {
+        if (n_ops > 1) {
             const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
             if (!G_t[tn] || !G_t[tp])
                 return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp, tn, t);
             if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
+            if (n_ops == 9 && (!s_t[tn] || !s_t[tp]))
+                return fail(C3PT_EINVAL, "stochastic solution slices %d and %d needed around %d", tp, tn, t);
         }
+    }
+    if (n_ops == 9) {
+        if (int rc = check_symmetric(geom, k, n_mom)) return rc;
     }
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
-        InsertionArgs a;
+        InsertionLeftArgs a;
         memset(&a, 0, sizeof(a));
         for (int j = 0; j < 3; ++j) a.L[j] = geom->L[j];
         a.n_tau = nt;
@@ -785,18 +805,25 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
             a.G[j] = G_t[t];
             a.s[j] = s_t[t];
-            if (n_ops == 5) {
+            if (n_ops > 1) {
                 a.Gn[j] = G_t[tn];
                 a.Gp[j] = G_t[tp];
                 a.U[j] = U_t[t];
                 a.Up[j] = U_t[tp];
+            }
+            if (n_ops == 9) {
+                a.sn[j] = s_t[tn];
+                a.sp[j] = s_t[tp];
             }
         }
         const int ncb = n_noise * nt * n_ops;
         int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_ops, kBlockCols, ncb,
                                 nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
                                     hipStream_t st = (hipStream_t)geom->stream;
-                                    if (!fac) return launch_insertion(mode, mt, variant, pg, a, st);
+                                    if (!fac) {
+                                        if (n_ops == 9) return hipErrorNotSupported;
+                                        return launch_insertion(mode, mt, variant, pg, a, st);
+                                    }
                                     // local and derivative operators in separate launches (each
                                     // kernel keeps only its own path's registers)
                                     const bool f64 = geom->dtype == C3PT_C128;
@@ -812,9 +839,22 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                     ad.op_cnt = 4;
                                     ProjGrid pd = pg;
                                     pd.n_per_share = n_noise * 4;
-                                    return launch_fac_insertion(f64, pg.fac_acc, 2, pd, ad, st);
+                                    e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, ad, st);
+                                    if (e != hipSuccess || n_ops == 5) return e;
+                                    InsertionLeftArgs ab = a;
+                                    ab.op_lo = 5;
+                                    ab.op_cnt = 4;
+                                    return launch_fac_insertion_left(f64, pg.fac_acc, pd, ab, st);
                                 });
         if (rc) return rc;
+    }
+    if (n_ops == 9) {
+        hipStream_t st = (hipStream_t)geom->stream;
+        if (int rc = to_status(timed("symmetrize", st, [&] {
+                                   return launch_symmetrize((double2*)out, (long long)n_noise * n_tau, n_mom, st);
+                               }),
+                               "symmetrize launch"))
+            return rc;
     }
     return ok();
 }
@@ -837,8 +877,8 @@ int c3pt_two_sink_meson(const c3pt_geom* geom, const void* G_fwd, const void* et
     if (!G_fwd || !eta_fwd || !G_bwd || !eta_bwd || !G_t || !s_t || !spec || !ins || !out_fwd || !out_bwd)
         return fail(C3PT_EINVAL, "NULL field, table or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
-    if (n_ops != 1 && n_ops != 5) return fail(C3PT_EINVAL, "n_ops = %d (must be 1 or 5)", n_ops);
-    if (n_ops == 5 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
+    if (n_ops != 1 && n_ops != 5 && n_ops != 9) return fail(C3PT_EINVAL, "n_ops = %d (must be 1, 5 or 9)", n_ops);
+    if (n_ops > 1 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
     const int T = geom->T;
     if (t_fwd < 0 || t_fwd >= T || t_src < 0 || t_src >= T || t_bwd < 0 || t_bwd >= T)
         return fail(C3PT_EINVAL, "timeslices (%d, %d, %d) outside [0, %d)", t_fwd, t_src, t_bwd, T);
@@ -851,12 +891,17 @@ int c3pt_two_sink_meson(const c3pt_geom* geom, const void* G_fwd, const void* et
         taus[j] = t;
         if (!G_t[t]) return fail(C3PT_EINVAL, "propagator slice %d missing", t);
         if (!s_t[t]) return fail(C3PT_EINVAL, "stochastic solution slice %d missing", t);
-        if (n_ops == 5) {
+        if (n_ops > 1) {
             const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
             if (!G_t[tn] || !G_t[tp])
                 return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp, tn, t);
             if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
+            if (n_ops == 9 && (!s_t[tn] || !s_t[tp]))
+                return fail(C3PT_EINVAL, "stochastic solution slices %d and %d needed around %d", tp, tn, t);
         }
+    }
+    if (n_ops == 9) {
+        if (int rc = check_symmetric(geom, k, n_mom)) return rc;
     }
     if (pairs) {
         if (n_pairs < 1) return fail(C3PT_EINVAL, "n_pairs = %d < 1", n_pairs);

@@ -1,0 +1,103 @@
+"""Symmetrized derivative insertion (n_ops = 9: ops 5..8 = 1/2 (->D_nu - <-D_nu))
+on the factored projection against the FP64 oracle (pinned by the trace of
+Eq. (1) with the left derivative on G_f2, the total-derivative identity and
+gauge invariance).  complex128 at 1e-12, complex64 at 1e-5; 32-site and
+16-site tiles, ragged rows, timeslices at both ends of the periodic time
+direction, a source off the origin; argument errors."""
+import numpy as np
+import pytest
+
+import c3pt_synth as syn
+import oracle
+from helpers import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _inputs(L, T, N, taus, cfg, reduced):
+    cast = syn.round_to_c64 if reduced else (lambda a: a)
+    need = sorted({(t + d) % T for t in taus for d in (-1, 0, 1)})
+    G = {t: cast(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in need}
+    s = {t: cast(syn.solution_slice(L, N, cfg, t)) for t in need}
+    U = {t: cast(syn.link_slice(L, cfg, t)) for t in need}
+    return G, s, U
+
+
+def _dev(d, reduced):
+    dt = np.complex64 if reduced else np.complex128
+    return {t: torch.from_numpy(np.ascontiguousarray(v.astype(dt))).cuda() for t, v in d.items()}
+
+
+CASES = [
+    # L, T, taus, N, n2, reduced, r
+    ((32, 4, 3), 6, [0, 5], 2, 3, True, (5, 1, 2)),     # 32-site tiles for the local part, both time ends
+    ((24, 3, 2), 6, [1, 4], 2, 6, True, (0, 2, 1)),     # second row segment ragged
+    ((6, 5, 4), 5, [0, 2], 1, 3, True, (1, 0, 3)),      # rows shorter than a tile
+    ((6, 5, 4), 5, [4, 1], 2, 5, False, (0, 1, 2)),     # complex128, two FP64 momentum groups
+    ((8, 8, 8), 4, [3], 1, 3, False, (3, 5, 1)),        # complex128
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_symmetric_derivative_matches_oracle(case):
+    import paper_1711_02384_amd as c3pt
+    L, T, taus, N, n2, reduced, r = CASES[case]
+    tol = 1e-5 if reduced else 1e-12
+    _say(f"symmetric derivative case {case}: L={L} T={T} taus={taus} N={N} |k|^2<={n2} reduced={reduced}")
+    k = c3pt.momentum_list(n2)
+    G, s, U = _inputs(L, T, N, taus, 90 + case, reduced)
+    geom = c3pt.Geom(L, T, r=r, proj=c3pt.PROJ_FACTORED)
+    got = c3pt.insertion(_dev(G, reduced), _dev(s, reduced), taus, k, geom, U_t=_dev(U, reduced), n_ops=9)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = oracle.insertion(G, s, taus, L, T, k, r=r, U_t=U, n_ops=9)
+    errs = [rel_fro(got[:, :, op], want[:, :, op]) for op in range(9)]
+    _say(f"   errors per op {['%.1e' % e for e in errs]}")
+    assert max(errs) < tol
+
+
+def test_symmetric_two_sink_matches_oracle():
+    """The two-sink measurement with n_ops = 9 (complex128)."""
+    import paper_1711_02384_amd as c3pt
+    _say("two-sink with the symmetrized derivative")
+    L, T, N = (6, 4, 4), 8, 2
+    tf, ts, tb = 6, 0, 2
+    cfg = 97
+    span = [(tf + j) % T for j in range(5)]
+    G, s, U = _inputs(L, T, N, span, cfg, False)
+    G1f = syn.propagator_slice(L, cfg, syn.FIELD_G1, tf)
+    G1b = syn.propagator_slice(L, cfg, syn.FIELD_G1, tb)
+    eta_f = syn.z2z2_noise(L, N, cfg, tf)
+    eta_b = syn.z2z2_noise(L, N, cfg, tb)
+    k = c3pt.momentum_list(2)
+    pairs = [(p, p) for p in range(len(k))]
+    one = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    res = c3pt.two_sink_meson(one(G1f), one(eta_f), tf, one(G1b), one(eta_b), tb, ts, _dev(G, False),
+                              _dev(s, False), k, c3pt.Geom(L, T, proj=c3pt.PROJ_FACTORED), U_t=_dev(U, False),
+                              n_ops=9, pairs=pairs)
+    torch.cuda.synchronize()
+    want = oracle.two_sink_meson(G1f, eta_f, tf, G1b, eta_b, tb, ts, G, s, L, T, k, U_t=U, n_ops=9, pairs=pairs)
+    for key in ("ins", "fwd", "bwd"):
+        assert rel_fro(res[key].cpu().numpy(), want[key]) < 1e-12
+
+
+def test_symmetric_rejects_unsupported():
+    import paper_1711_02384_amd as c3pt
+    _say("symmetric derivative argument checks")
+    L, T, N = (4, 4, 4), 6, 1
+    G, s, U = _inputs(L, T, N, [2], 99, False)
+    k = c3pt.momentum_list(1)
+    with pytest.raises(c3pt.C3ptError):          # dense projection
+        c3pt.insertion(_dev(G, False), _dev(s, False), [2], k, c3pt.Geom(L, T), U_t=_dev(U, False), n_ops=9)
+    s_missing = {t: v for t, v in s.items() if t != 3}
+    with pytest.raises(c3pt.C3ptError):          # s(tau + 1) missing
+        c3pt.insertion(_dev(G, False), _dev(s_missing, False), [2], k, c3pt.Geom(L, T, proj=c3pt.PROJ_FACTORED),
+                       U_t=_dev(U, False), n_ops=9)
+    with pytest.raises(c3pt.C3ptError):          # n_ops outside 1, 5, 9
+        c3pt.insertion(_dev(G, False), _dev(s, False), [2], k, c3pt.Geom(L, T, proj=c3pt.PROJ_FACTORED),
+                       U_t=_dev(U, False), n_ops=7)
