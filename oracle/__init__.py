@@ -10,5 +10,5 @@ from .c3pt_oracle import (  # noqa: F401
     GAMMA, GAMMA5_DIAG, gamma_basis16, momenta, site_coords, phase_matrix,
     spectator_meson, spectator_baryon, insertion, covariant_derivative, covariant_derivative_vector, combine,
     all_pairs, EPS, two_sink_meson, creation_matrix, charge_conjugation, parity_projectors,
-    gamma_project_meson, gamma_project_nucleon, PROTON_TERMS,
+    gamma_project_meson, gamma_project_nucleon, PROTON_TERMS, smear,
 )

@@ -462,3 +462,32 @@ def gamma_project_nucleon(C, channel: str, A=None, Abar=None, P=None, g_ins=None
         expr = f'...ABCDEFGH,{s1}{s2},{r1}{r2},p{rn}{sn},jFG->...pj'
         out += sign * np.einsum(expr, T8, A, Abar, Ps, Gi, optimize=True)
     return out
+
+
+# --------------------------------------------------------------------------
+# Quark smearing of the inputs (Sec. 2.1: A and C may contain quark smearing;
+# Sec. 3: the spectator's propagators are smeared at source and sink).
+# --------------------------------------------------------------------------
+def smear(field, U, L, kappa: float, n_iter: int, n_outer: int, n_inner: int) -> np.ndarray:
+    """Gauge-covariant (Wuppertal-type) smearing of colour vectors on one timeslice,
+    applied n_iter times:
+        psi'(x) = [psi(x) + kappa sum_{j=1..3} (U_j(x) psi(x+j) + U_j(x-j)^dag psi(x-j))] / (1 + 6 kappa).
+    The paper names smearing but gives no kernel or parameters; this is the
+    usual choice.  field: n_outer * 3 * n_inner * V3 values laid out as
+    [n_outer][3 colour][n_inner][V3] (a propagator slice [12][12][V3] smeared on
+    its row index is n_outer = 4 spins, n_inner = 12 columns; noise or solution
+    vectors [N][12][V3] are n_outer = 4 N, n_inner = 1).  U: [4][3][3][V3]."""
+    V3 = int(np.prod(L))
+    psi = np.asarray(field, dtype=np.complex128).reshape(n_outer, 3, n_inner, V3).copy()
+    U = np.asarray(U, dtype=np.complex128)
+    Um = [_neighbour(U[j], L, j, -1) for j in range(3)]
+    norm = 1.0 / (1.0 + 6.0 * kappa)
+    for _ in range(n_iter):
+        hop = np.zeros_like(psi)
+        for j in range(3):
+            fwd = _neighbour(psi, L, j, +1)
+            bwd = _neighbour(psi, L, j, -1)
+            hop += np.einsum('cdx,odix->ocix', U[j], fwd)
+            hop += np.einsum('dcx,odix->ocix', np.conj(Um[j]), bwd)
+        psi = norm * (psi + kappa * hop)
+    return psi.reshape(np.asarray(field).shape)
