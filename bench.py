@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "twosink32", "batch64", "serve"], default="meson32")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
+    ap.add_argument("--smear", type=int, default=0,
+                    help="twosink32: steps of gauge-covariant smearing (kappa 0.25) of the sink propagators "
+                         "and noise vectors, in the timed step")
     ap.add_argument("--ops", type=int, choices=[5, 9], default=None,
                     help="meson32 / twosink32 insertion operators: 5 = local + 4 D_nu (default), "
                          "9 = also the 4 symmetrized <->D_nu")
@@ -485,9 +488,11 @@ class TwoSink32(Meson32):
         self.baryon = False
         self.n_ops = args.ops or 5
         self.taus = [(self.t_fwd + j) % self.T for j in range((self.t_bwd - self.t_fwd) % self.T + 1)]
+        self.smear_iter, self.kappa = args.smear, 0.25
         self.name = ("meson 3pt forward + backward with time-partitioned noise, 32^3x96, r_4=30, x'_4=20, "
                      "x''_4=40, N=50, |k|^2<=8 (93 momenta), local+4 D_nu"
-                     + (" + 4 symmetrized <->D_nu" if self.n_ops == 9 else "") + ", 185 pairs, 16^3 Gamma channels")
+                     + (" + 4 symmetrized <->D_nu" if self.n_ops == 9 else "") + ", 185 pairs, 16^3 Gamma channels"
+                     + (f", sink smearing {self.smear_iter} x kappa {self.kappa}" if self.smear_iter else ""))
 
     def setup(self, c3pt, syn, dev, geom, k):
         L, T = self.L, self.T
@@ -503,10 +508,20 @@ class TwoSink32(Meson32):
         self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
         self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
         self.pairs = pairs_diag_or_zero(len(k))
+        import torch
+        self.sm = [torch.empty_like(x) for x in (self.Gf, self.Gb, self.eta_f, self.eta_b)]
         self.c3pt, self.geom, self.k = c3pt, geom, k
 
     def _run(self):
-        return self.c3pt.two_sink_meson(self.Gf, self.eta_f, self.t_fwd, self.Gb, self.eta_b, self.t_bwd,
+        Gf, Gb, ef, eb = self.Gf, self.Gb, self.eta_f, self.eta_b
+        if self.smear_iter:
+            # sink smearing of the spectator's propagator and of the noise at both sinks
+            c, g, n, kap = self.c3pt, self.geom, self.smear_iter, self.kappa
+            Gf = c.smear_propagator(self.Gf, self.U[self.t_fwd], g, kap, n, out=self.sm[0])
+            Gb = c.smear_propagator(self.Gb, self.U[self.t_bwd], g, kap, n, out=self.sm[1])
+            ef = c.smear_vectors(self.eta_f, self.U[self.t_fwd], g, kap, n, out=self.sm[2])
+            eb = c.smear_vectors(self.eta_b, self.U[self.t_bwd], g, kap, n, out=self.sm[3])
+        return self.c3pt.two_sink_meson(Gf, ef, self.t_fwd, Gb, eb, self.t_bwd,
                                         self.t_src, self.G3, self.s, self.k, self.geom, U_t=self.U,
                                         n_ops=self.n_ops, pairs=self.pairs)
 
@@ -530,7 +545,8 @@ class TwoSink32(Meson32):
     def config(self, n_mom):
         return {"workload": self.name, "L": list(self.L), "T": self.T, "t_src": self.t_src, "t_fwd": self.t_fwd,
                 "t_bwd": self.t_bwd, "n_noise": self.N, "n_tau": len(self.taus), "n_mom": n_mom,
-                "n_ops": self.n_ops, "n_pairs": len(self.pairs), "units_per_step": self.units(n_mom)}
+                "n_ops": self.n_ops, "n_pairs": len(self.pairs), "smear_steps": self.smear_iter,
+                "units_per_step": self.units(n_mom)}
 
     def cpu_sample(self, k, n_slices):
         import c3pt_synth as syn

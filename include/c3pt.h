@@ -11,6 +11,7 @@
  *   noise-averaged product of the two parts (Eq. (5) in Eq. (8))   c3pt_combine
  *   forward + backward diagrams, time-partitioned noise (Sec. 2.3)  c3pt_two_sink_meson
  *   Gamma channels of the spin-open data (Eq. (1), Sec. 3)  c3pt_gamma_meson / c3pt_gamma_nucleon
+ *   gauge-covariant smearing of the inputs (Sec. 2.1, Sec. 3)  c3pt_smear
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -239,6 +240,25 @@ int c3pt_gamma_meson(const void* C, int n_blk, const double* g_snk, int n_snk, c
  */
 int c3pt_gamma_nucleon(const void* C, int n_blk, int channel, const double* A, const double* Abar,
                        const double* P, int n_proj, const double* g_ins, int n_ins, void* out, void* stream);
+
+/*
+ * Gauge-covariant quark smearing of colour vectors on one timeslice, n_iter
+ * steps of (Wuppertal form; the paper smears the spectator's propagators at
+ * source and sink, Sec. 3, and lets the operators contain smearing, Sec. 2.1,
+ * without giving the kernel or its parameters):
+ *   psi'(x) = [psi(x) + kappa sum_{j=x,y,z} (U_j(x) psi(x+j) + U_j(x-j)^dag psi(x-j))] / (1 + 6 kappa)
+ * with periodic spatial neighbours.
+ *   in, out : device fields [n_outer][3][n_inner][V3] (c3pt_geom.dtype), colour
+ *             the second index: a propagator slice [12][12][V3] smeared on its
+ *             row (field) index is n_outer = 4, n_inner = 12; noise or solution
+ *             vectors [N][12][V3] are n_outer = 4 N, n_inner = 1.  in == out is
+ *             allowed; otherwise the two must not overlap.
+ *   U       : device links of the timeslice [4][3][3][V3] (the time links unused).
+ *   kappa   : hopping weight, 0 <= kappa < 1e6;  n_iter >= 0 (0 copies).
+ * Uses this stream's scratch for the intermediate steps (one field).
+ */
+int c3pt_smear(const c3pt_geom* geom, const void* in, void* out, int n_outer, int n_inner, const void* U,
+               double kappa, int n_iter);
 
 /* Static description of a status code. */
 const char* c3pt_strerror(int status);

@@ -39,7 +39,7 @@ PROTON_D = 0   # current on the d quark; nucleon data of spectators (u, u)
 PROTON_U = 1   # current on a u quark; nucleon data of spectators (u, d)
 
 EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
-            "c3pt_two_sink_meson", "c3pt_gamma_meson", "c3pt_gamma_nucleon", "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
+            "c3pt_two_sink_meson", "c3pt_gamma_meson", "c3pt_gamma_nucleon", "c3pt_smear", "c3pt_strerror", "c3pt_last_error", "c3pt_version", "c3pt_scratch_bytes",
             "c3pt_release_scratch", "c3pt_profile_enable", "c3pt_profile_read", "c3pt_variant_count",
             "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
             "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
@@ -113,8 +113,9 @@ def _load():
     dp = ctypes.POINTER(ctypes.c_double)
     lib.c3pt_gamma_meson.argtypes = [vp, i, dp, i, dp, i, dp, i, vp, vp]
     lib.c3pt_gamma_nucleon.argtypes = [vp, i, i, dp, dp, dp, i, dp, i, vp, vp]
+    lib.c3pt_smear.argtypes = [gp, vp, vp, i, i, vp, ctypes.c_double, i]
     for name in ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "c3pt_combine",
-                 "c3pt_two_sink_meson", "c3pt_gamma_meson", "c3pt_gamma_nucleon"):
+                 "c3pt_two_sink_meson", "c3pt_gamma_meson", "c3pt_gamma_nucleon", "c3pt_smear"):
         getattr(lib, name).restype = ctypes.c_int
     lib.c3pt_strerror.argtypes = [i]
     lib.c3pt_strerror.restype = ctypes.c_char_p
@@ -406,6 +407,35 @@ def c3pt_gamma_nucleon(C: torch.Tensor, channel: int, A=None, Abar=None, P=None,
     _check(lib.c3pt_gamma_nucleon(C.data_ptr(), n_blk, int(channel), pa, pb, pp, npj, pi, ni, out.data_ptr(),
                                   _stream(stream)))
     return out
+
+
+def _smear(field, U, geom: Geom, kappa: float, n_iter: int, n_outer: int, n_inner: int, out=None):
+    V3 = geom.V3
+    dtype = field.dtype
+    _field(field, "field", tuple(field.shape), dtype)
+    _field(U, "U", (4, 3, 3, V3), dtype)
+    if out is None:
+        out = torch.empty_like(field)
+    else:
+        _field(out, "out", tuple(field.shape), dtype)
+    g = geom.c(dtype)
+    _check(lib.c3pt_smear(ctypes.byref(g), field.data_ptr(), out.data_ptr(), n_outer, n_inner, U.data_ptr(),
+                          float(kappa), int(n_iter)))
+    return out
+
+
+def smear_propagator(G: torch.Tensor, U: torch.Tensor, geom: Geom, kappa: float, n_iter: int, out=None):
+    """Smear a propagator slice [12, 12, V3] on its row (field point) index (c3pt_smear)."""
+    if tuple(G.shape) != (12, 12, geom.V3):
+        raise ValueError(f"G: shape {tuple(G.shape)}, expected (12, 12, {geom.V3})")
+    return _smear(G, U, geom, kappa, n_iter, 4, 12, out)
+
+
+def smear_vectors(v: torch.Tensor, U: torch.Tensor, geom: Geom, kappa: float, n_iter: int, out=None):
+    """Smear noise or solution vectors [N, 12, V3] (c3pt_smear)."""
+    if v.dim() != 3 or tuple(v.shape[1:]) != (12, geom.V3):
+        raise ValueError(f"v: shape {tuple(v.shape)}, expected (N, 12, {geom.V3})")
+    return _smear(v, U, geom, kappa, n_iter, 4 * v.shape[0], 1, out)
 
 
 spectator_meson = c3pt_spectator_meson

@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libc3pt.so")
 SOURCES = ["c3pt_api.hip", "c3pt_proj_meson.hip", "c3pt_proj_baryon.hip", "c3pt_proj_insertion.hip",
            "c3pt_combine.hip", "c3pt_phase.hip", "c3pt_batch.hip",
            "c3pt_serve.hip", "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip",
-           "c3pt_gamma.hip", "c3pt_fac_left.hip"]
+           "c3pt_gamma.hip", "c3pt_fac_left.hip",
+           "c3pt_smear.hip"]
 
 
 def hipcc() -> str:

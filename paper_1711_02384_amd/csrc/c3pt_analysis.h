@@ -42,6 +42,18 @@ hipError_t launch_fac_insertion_left(bool f64, bool acc, const ProjGrid& pg, con
                                      hipStream_t st);
 hipError_t launch_symmetrize(double2* out, long long n_outer, int n_mom, hipStream_t st);
 
+// Gauge-covariant smearing step of colour vectors [n_outer][3][n_inner][V3].
+struct SmearArgs {
+    const void* in;
+    void* out;
+    const void* U;          // [4][3][3][V3] links of the timeslice (j = 0..2 used)
+    int L[3], V3;
+    int n_outer, n_inner;
+    double norm;            // 1 / (1 + 6 kappa)
+    double kappa_norm;      // kappa / (1 + 6 kappa)
+};
+hipError_t launch_smear(bool f64, const SmearArgs& a, hipStream_t st);
+
 }  // namespace c3pt
 
 #endif

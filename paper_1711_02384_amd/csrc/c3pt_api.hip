@@ -1006,4 +1006,50 @@ int c3pt_gamma_nucleon(const void* C, int n_blk, int channel, const double* A, c
     return ok();
 }
 
+int c3pt_smear(const c3pt_geom* geom, const void* in, void* out, int n_outer, int n_inner, const void* U,
+               double kappa, int n_iter) {
+    if (int rc = check_geom(geom)) return rc;
+    if (!in || !out || !U) return fail(C3PT_EINVAL, "NULL field or link pointer");
+    if (n_outer < 1 || n_inner < 1) return fail(C3PT_EINVAL, "n_outer = %d, n_inner = %d (must be >= 1)", n_outer,
+                                                n_inner);
+    if (n_iter < 0) return fail(C3PT_EINVAL, "n_iter = %d < 0", n_iter);
+    if (!(kappa >= 0.0) || !(kappa < 1e6)) return fail(C3PT_EINVAL, "kappa = %g outside [0, 1e6)", kappa);
+    const long long V3 = (long long)geom->L[0] * geom->L[1] * geom->L[2];
+    const long long n_val = (long long)n_outer * 3 * n_inner * V3;
+    if (n_val > 0xffffffffLL) return fail(C3PT_EINVAL, "field of %lld values exceeds 32-bit indexing", n_val);
+    const bool f64 = geom->dtype == C3PT_C128;
+    const size_t bytes = (size_t)n_val * (f64 ? sizeof(double2) : sizeof(float2));
+    hipStream_t st = (hipStream_t)geom->stream;
+    if (n_iter == 0) {
+        if (in != out && hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return fail(C3PT_EDEVICE, "field copy failed");
+        return ok();
+    }
+    void* tmp;
+    if (int rc = scratch_dev(st, bytes, &tmp)) return rc;
+    SmearArgs a;
+    for (int j = 0; j < 3; ++j) a.L[j] = geom->L[j];
+    a.V3 = (int)V3;
+    a.U = U;
+    a.n_outer = n_outer;
+    a.n_inner = n_inner;
+    a.norm = 1.0 / (1.0 + 6.0 * kappa);
+    a.kappa_norm = kappa / (1.0 + 6.0 * kappa);
+    // step i writes the buffer that is not its input; the last step writes out
+    // unless the input is out itself, then the result is copied at the end
+    const void* src = in;
+    for (int i = 1; i <= n_iter; ++i) {
+        void* dst = ((n_iter - i) % 2 == 0) ? out : tmp;
+        if (dst == src) dst = (dst == out) ? tmp : out;
+        a.in = src;
+        a.out = dst;
+        if (int rc = to_status(timed("smear", st, [&] { return launch_smear(f64, a, st); }), "smear launch"))
+            return rc;
+        src = dst;
+    }
+    if (src != out && hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(C3PT_EDEVICE, "field copy failed");
+    return ok();
+}
+
 }  // extern "C"

@@ -1,0 +1,112 @@
+// Gauge-covariant quark smearing of colour-vector fields on one timeslice
+// (the paper smears the spectator's propagators at source and sink, Sec. 3;
+// the operators of Sec. 2.1 may contain quark smearing).  One launch per step:
+//   psi'(x) = [psi(x) + kappa sum_{j=1..3} (U_j(x) psi(x+j) + U_j(x-j)^dag psi(x-j))] / (1 + 6 kappa)
+// Field layout [n_outer][3][n_inner][V3] (site fastest): the rows of a
+// propagator slice (n_outer = 4 spins, n_inner = 12 columns) or noise and
+// solution vectors (n_outer = 4 N, n_inner = 1).
+//
+// A workgroup takes 64 consecutive sites and 8 vectors, one (site, vector)
+// per thread: the six links of each site go to LDS once and serve all 8;
+// lanes run over sites, so every field read (centre and the six neighbours)
+// is a coalesced row.  Work items
+// are dealt to the eight XCDs in contiguous ranges of sites, so that the
+// x2 / x3 neighbours a workgroup reads were mostly fetched into the same L2.
+#include "c3pt_device.h"
+#include "c3pt_analysis.h"
+
+namespace c3pt {
+
+namespace {
+constexpr int kSmSites = 64;
+constexpr int kSmVecs = 8;
+constexpr int kSmThreads = kSmSites * kSmVecs;   // one (site, vector) per thread
+}  // namespace
+
+template <typename R>
+__global__ void __launch_bounds__(kSmThreads) smear_kernel(SmearArgs a) {
+    __shared__ C2<R> uf[3][9][kSmSites];   // U_j(x)[c][d]
+    __shared__ C2<R> ub[3][9][kSmSites];   // U_j(x - j)[c][d]
+    const int tid = threadIdx.x;
+    const int gx = (a.V3 + kSmSites - 1) / kSmSites;
+    const int nw = gridDim.x, w = blockIdx.x;
+    const int full = (nw / 8) * 8;
+    const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
+    const int tile = item % gx, vb = item / gx;
+    const int s0 = tile * kSmSites;
+    const C2<R>* U = (const C2<R>*)a.U;
+    const unsigned V3 = (unsigned)a.V3;
+    const int L1 = a.L[0], L2 = a.L[1], L3 = a.L[2];
+    // neighbour sites of site s (periodic)
+    auto nbr = [&](int s, int j, int dir) {
+        const int x1 = s % L1, q = s / L1, x2 = q % L2, x3 = q / L2;
+        int y1 = x1, y2 = x2, y3 = x3;
+        if (j == 0) y1 = (x1 + dir + L1) % L1;
+        if (j == 1) y2 = (x2 + dir + L2) % L2;
+        if (j == 2) y3 = (x3 + dir + L3) % L3;
+        return y1 + L1 * (y2 + L2 * y3);
+    };
+    for (int e = tid; e < 3 * 9 * kSmSites; e += kSmThreads) {
+        const int j = e / (9 * kSmSites), r = e % (9 * kSmSites), cd = r / kSmSites, i = r % kSmSites;
+        const int s = min(s0 + i, a.V3 - 1);
+        uf[j][cd][i] = U[(unsigned)(j * 9 + cd) * V3 + (unsigned)s];
+        ub[j][cd][i] = U[(unsigned)(j * 9 + cd) * V3 + (unsigned)nbr(s, j, -1)];
+    }
+    __syncthreads();
+    const int i = tid % kSmSites;
+    const int s = s0 + i;
+    if (s >= a.V3) return;
+    int np[3], nm[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        np[j] = nbr(s, j, +1);
+        nm[j] = nbr(s, j, -1);
+    }
+    const R norm = (R)a.norm, kn = (R)a.kappa_norm;
+    const C2<R>* in = (const C2<R>*)a.in;
+    C2<R>* out = (C2<R>*)a.out;
+    const int n_vec = a.n_outer * a.n_inner;
+    const int v = vb * kSmVecs + tid / kSmSites;
+    if (v < n_vec) {
+        const int o = v / a.n_inner, in_i = v - o * a.n_inner;
+        unsigned base[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) base[c] = (unsigned)((o * 3 + c) * a.n_inner + in_i) * V3;
+        C2<R> hop[3] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C2<R> f[3], b[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                f[d] = in[base[d] + (unsigned)np[j]];
+                b[d] = in[base[d] + (unsigned)nm[j]];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    hop[c] = cfma(hop[c], uf[j][c * 3 + d][i], f[d]);
+                    hop[c] = cadd(hop[c], cmulc(b[d], ub[j][d * 3 + c][i]));   // conj(U(x-j)[d][c]) psi_d
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const C2<R> x = in[base[c] + (unsigned)s];
+            out[base[c] + (unsigned)s] = C2<R>{norm * x.x + kn * hop[c].x, norm * x.y + kn * hop[c].y};
+        }
+    }
+}
+
+hipError_t launch_smear(bool f64, const SmearArgs& a, hipStream_t st) {
+    const long long gx = (a.V3 + kSmSites - 1) / kSmSites;
+    const long long gy = (a.n_outer * (long long)a.n_inner + kSmVecs - 1) / kSmVecs;
+    const dim3 grid((unsigned)(gx * gy));
+    if (f64)
+        hipLaunchKernelGGL(smear_kernel<double>, grid, dim3(kSmThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(smear_kernel<float>, grid, dim3(kSmThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace c3pt
