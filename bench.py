@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "twosink32", "batch64", "serve"], default="meson32")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
+    ap.add_argument("--analysis", action="store_true",
+                    help="nucleon48: add the proton channels of both combines (c3pt_gamma_nucleon) to the step")
     ap.add_argument("--smear", type=int, default=0,
                     help="twosink32: steps of gauge-covariant smearing (kappa 0.25) of the sink propagators "
                          "and noise vectors, in the timed step")
@@ -394,8 +396,10 @@ class Nucleon48(Meson32):
     def __init__(self, args):
         self.baryon = True
         self.n2 = args.n2 if args.n2 is not None else 8
+        self.analysis = args.analysis
         self.name = (f"nucleon 3pt, 48^3x64, t_f=14, tau=0..14, N=8, |k|^2<={self.n2}, spectators (u,u) and "
-                     f"(u,d), isovector insertion (u and d), local")
+                     f"(u,d), isovector insertion (u and d), local"
+                     + (", proton channels (C gamma5, parity projectors, 16 Gamma_ins)" if self.analysis else ""))
 
     def setup(self, c3pt, syn, dev, geom, k):
         import torch
@@ -433,6 +437,10 @@ class Nucleon48(Meson32):
         c.insertion(self.Gd, self.s, self.taus, k, g, out=self.Id)
         c.combine(self.Suu, self.Id, pairs=self.pairs, out=self.Cd)
         c.combine(self.Sud, self.Iu, pairs=self.pairs, out=self.Cu)
+        if self.analysis:
+            # proton channels of both currents: tr[P_pm G] for the 16 Gamma_ins
+            self.ch_d = c.gamma_nucleon(self.Cd, c.PROTON_D)
+            self.ch_u = c.gamma_nucleon(self.Cu, c.PROTON_U)
 
     def units(self, n_mom):
         V3 = int(np.prod(self.L))

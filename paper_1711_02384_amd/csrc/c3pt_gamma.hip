@@ -4,7 +4,8 @@
 // Eq. (1) at source, sink and insertion follows afterwards (Sec. 1, Sec. 3).
 //
 // Meson: out[i][j][l] = sum Gsnk_i[a'][b'] Gins_j[at][bt] Gsrc_l[b][a] C[b'][a'][a][at][bt][b]
-// as three 4x4 contractions in LDS.  Nucleon: the proton's Wick terms (the
+// as three 4x4 contractions, intermediates in LDS and the matrices read
+// with workgroup-uniform addresses (scalar loads).  Nucleon: the proton's Wick terms (the
 // diquark matrix at sink and source, a projector between the nucleon spins)
 // become one weight per (row, b) of the [1024][64] data, built on the host;
 // the kernel streams the weighted rows and applies Gins last.
@@ -35,7 +36,6 @@ constexpr int kX1G = 4 * kX1A;
 constexpr int kX2S = 17;
 
 struct GammaMesonSmem {
-    double2 M[3][16][16];           // Gsnk, Gins, Gsrc, rows beyond the counts unused
     double2 X1[16 * kX1G];          // [g1][a][at bt b]; reused for the output stage
     double2 X2[256 * kX2S];         // [g1 g2][a b]
 };
@@ -46,7 +46,8 @@ __global__ void __launch_bounds__(256) gamma_meson_kernel(GammaMesonArgs a) {
     __shared__ GammaMesonSmem sm;
     const int tid = threadIdx.x;
     const double2* Cb = a.C + (size_t)blockIdx.x * 4096;
-    for (int i = tid; i < 3 * 256; i += 256) (&sm.M[0][0][0])[i] = a.mats[i];
+    // the matrices are read with workgroup-uniform addresses: scalar loads
+    const double2* __restrict__ M = a.mats;
     // stage 1 (sink): thread = (a, at, bt, b); X1[g1] = sum_{a', b'} Gsnk[g1][a'][b'] C[b'][a'][.]
     double2 c[16];
 #pragma unroll
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(256) gamma_meson_kernel(GammaMesonArgs a) {
 #pragma unroll
         for (int bp = 0; bp < 4; ++bp)
 #pragma unroll
-            for (int ap = 0; ap < 4; ++ap) s = cfma(sm.M[0][g1][ap * 4 + bp], c[bp * 4 + ap], s);
+            for (int ap = 0; ap < 4; ++ap) s = cfma(M[g1 * 16 + ap * 4 + bp], c[bp * 4 + ap], s);
         sm.X1[g1 * kX1G + x1off] = s;
     }
     __syncthreads();
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(256) gamma_meson_kernel(GammaMesonArgs a) {
         for (int g2 = 0; g2 < a.n_ins; ++g2) {
             double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) s = cfma(sm.M[1][g2][k], x[k], s);
+            for (int k = 0; k < 16; ++k) s = cfma(M[256 + g2 * 16 + k], x[k], s);
             sm.X2[(g1 * 16 + g2) * kX2S + ab] = s;
         }
     }
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(256) gamma_meson_kernel(GammaMesonArgs a) {
 #pragma unroll
             for (int aa = 0; aa < 4; ++aa)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) s = cfma(sm.M[2][g3][b * 4 + aa], y[aa * 4 + b], s);
+                for (int b = 0; b < 4; ++b) s = cfma(M[512 + g3 * 16 + b * 4 + aa], y[aa * 4 + b], s);
             sm.X1[idx * kX2S + g3] = s;
         }
     }

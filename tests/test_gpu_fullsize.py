@@ -6,6 +6,8 @@ outputs (selected timeslices, noise vectors or momenta) one by one.
 * 32^3 x 64 meson step (FP32, dense and factored projection): spectator (all outputs), insertion with the
   five operators at tau = 0, 8, 16 (the full 17-slice launch runs on the GPU),
   and the combine on sampled pairs built from the oracle's own parts.
+* the same insertion with the symmetrized derivative (n_ops = 9), checked at
+  the first and last timeslice;
 * 48^3 x 64 nucleon step with split-precision projection (BF16 and FP16 hi+lo):
   the nucleon spectator for one noise vector and a momentum subset, and one
   insertion timeslice.  Tolerance 1e-5 relative (Frobenius), the same as FP32.
@@ -66,6 +68,32 @@ def test_meson32_step_sampled(proj, name):
     I8 = oracle.insertion(G3, s, [8], L, T, k, U_t=U, n_ops=5)
     C = c3pt.combine(torch.from_numpy(S_o).cuda(), torch.from_numpy(I8).cuda(), pairs=pairs).cpu().numpy()
     assert rel_fro(C, oracle.combine(S_o, I8, pairs=pairs)) < 1e-12
+
+
+def test_meson32_symmetric_sampled():
+    """The 32^3 insertion with the symmetrized derivative (n_ops = 9, factored
+    FP32) over tau = 0..16 as bench.py --ops 9 launches it; the oracle checks
+    the first and last timeslice (their s(tau -+ 1) lie outside the range)."""
+    import paper_1711_02384_amd as c3pt
+    L, T, N, cfg = (32, 32, 32), 64, 4, 2
+    taus = list(range(17))
+    k = c3pt.momentum_list(6)
+    _say("meson32 symmetric: generating inputs")
+    gsl = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
+    usl = sorted({t % T for tau in taus for t in (tau - 1, tau)})
+    G3 = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in gsl}
+    s = {t: syn.round_to_c64(syn.solution_slice(L, N, cfg, t)) for t in gsl}
+    U = {t: syn.round_to_c64(syn.link_slice(L, cfg, t)) for t in usl}
+    geom = c3pt.Geom(L, T, proj=3)
+    _say("meson32 symmetric: GPU insertion")
+    I = c3pt.insertion({t: _up(v) for t, v in G3.items()}, {t: _up(v) for t, v in s.items()}, taus, k, geom,
+                       U_t={t: _up(v) for t, v in U.items()}, n_ops=9).cpu().numpy()
+    for tau in (0, 16):
+        I_o = oracle.insertion(G3, s, [tau], L, T, k, U_t=U, n_ops=9)
+        for op in range(9):
+            e = rel_fro(I[:, tau, op], I_o[:, 0, op])
+            _say(f"meson32 symmetric: tau={tau} op={op} rel err {e:.2e}")
+            assert e < TOL32
 
 
 @pytest.mark.parametrize("proj,name", [(2, "bf16x2"), (1, "f16x2"), (3, "factored")])
