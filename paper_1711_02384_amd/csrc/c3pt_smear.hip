@@ -37,30 +37,45 @@ __global__ void __launch_bounds__(kSmThreads) smear_kernel(SmearArgs a) {
     const C2<R>* U = (const C2<R>*)a.U;
     const unsigned V3 = (unsigned)a.V3;
     const int L1 = a.L[0], L2 = a.L[1], L3 = a.L[2];
-    // neighbour sites of site s (periodic)
-    auto nbr = [&](int s, int j, int dir) {
-        const int x1 = s % L1, q = s / L1, x2 = q % L2, x3 = q / L2;
-        int y1 = x1, y2 = x2, y3 = x3;
-        if (j == 0) y1 = (x1 + dir + L1) % L1;
-        if (j == 1) y2 = (x2 + dir + L2) % L2;
-        if (j == 2) y3 = (x3 + dir + L3) % L3;
-        return y1 + L1 * (y2 + L2 * y3);
+    // coordinates once per site; neighbours by compare and select (no
+    // division per neighbour)
+    struct Nbr {
+        int p[3], m[3];
     };
-    for (int e = tid; e < 3 * 9 * kSmSites; e += kSmThreads) {
-        const int j = e / (9 * kSmSites), r = e % (9 * kSmSites), cd = r / kSmSites, i = r % kSmSites;
-        const int s = min(s0 + i, a.V3 - 1);
-        uf[j][cd][i] = U[(unsigned)(j * 9 + cd) * V3 + (unsigned)s];
-        ub[j][cd][i] = U[(unsigned)(j * 9 + cd) * V3 + (unsigned)nbr(s, j, -1)];
+    auto neighbours = [&](int n) {
+        const int q = n / L1, x1 = n - q * L1, x3 = q / L2, x2 = q - x3 * L2;
+        const int s2 = L1, s3 = L1 * L2;
+        Nbr r;
+        r.p[0] = n + (x1 == L1 - 1 ? 1 - L1 : 1);
+        r.m[0] = n - (x1 == 0 ? 1 - L1 : 1);
+        r.p[1] = n + (x2 == L2 - 1 ? (1 - L2) * s2 : s2);
+        r.m[1] = n - (x2 == 0 ? (1 - L2) * s2 : s2);
+        r.p[2] = n + (x3 == L3 - 1 ? (1 - L3) * s3 : s3);
+        r.m[2] = n - (x3 == 0 ? (1 - L3) * s3 : s3);
+        return r;
+    };
+    // links of the tile: thread (site i, direction j) among the first 192
+    if (tid < 3 * kSmSites) {
+        const int i = tid % kSmSites, j = tid / kSmSites;
+        const int n = min(s0 + i, a.V3 - 1);
+        const Nbr nb = neighbours(n);
+        const int nmj = j == 0 ? nb.m[0] : (j == 1 ? nb.m[1] : nb.m[2]);
+#pragma unroll
+        for (int cd = 0; cd < 9; ++cd) {
+            uf[j][cd][i] = U[(unsigned)(j * 9 + cd) * V3 + (unsigned)n];
+            ub[j][cd][i] = U[(unsigned)(j * 9 + cd) * V3 + (unsigned)nmj];
+        }
     }
     __syncthreads();
     const int i = tid % kSmSites;
     const int s = s0 + i;
     if (s >= a.V3) return;
+    const Nbr nb = neighbours(s);
     int np[3], nm[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        np[j] = nbr(s, j, +1);
-        nm[j] = nbr(s, j, -1);
+        np[j] = nb.p[j];
+        nm[j] = nb.m[j];
     }
     const R norm = (R)a.norm, kn = (R)a.kappa_norm;
     const C2<R>* in = (const C2<R>*)a.in;
