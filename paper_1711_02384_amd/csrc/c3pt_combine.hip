@@ -160,11 +160,17 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
                 }
         }
     }
-    double2* out = a.out + ((((size_t)pr * a.n_tau + tau) * a.n_sel + o) * a.spin + (size_t)sb * 64) * 64;
+    // the output is written once and not read again by this step: streaming
+    // (non-temporal) stores keep it from displacing the inputs in the caches
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    d2v* out = (d2v*)(a.out + ((((size_t)pr * a.n_tau + tau) * a.n_sel + o) * a.spin + (size_t)sb * 64) * 64);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) out[(size_t)(ty + 16 * i) * 64 + tx + 16 * j] = acc[i][j];
+        for (int j = 0; j < 4; ++j) {
+            const d2v v = {acc[i][j].x, acc[i][j].y};
+            __builtin_nontemporal_store(v, &out[(size_t)(ty + 16 * i) * 64 + tx + 16 * j]);
+        }
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
