@@ -362,6 +362,59 @@ def test_symmetric_derivative_total_derivative_identity():
                 assert not np.allclose(sym, fwd, atol=1e-3 * np.abs(fwd).max())
 
 
+def test_two_derivatives_trace_against_bruteforce():
+    """Ops 5 + 4 rho + nu = D_nu D_rho: the brute-force matrix form of the
+    covariant derivative applied twice (to a dict of once-derived slices),
+    traced as Eq. (1) against the factorized estimator."""
+    L = (3, 2, 3)
+    T = 6
+    N = 2
+    V3, G1, G3, eta, s, U = _meson_setup(L, N, 53, T=T)
+    kp = oracle.momenta(1)[[0, 4]]
+    q = oracle.momenta(1)[[2, 6]]
+    tau = 2
+    S = oracle.spectator_meson(G1, eta, L, kp)
+    I = oracle.insertion(G3, s, [tau], L, T, q, U_t=U, n_ops=21)
+    C = oracle.combine(S, I, pairs=[(1, 0), (0, 1)])
+    w = np.full(N, 1.0 / N)
+    Ghat = np.einsum('i,iAy,iBx->yxAB', w, s[tau], np.conj(eta))
+    for rho in range(4):
+        D1 = {t: np.ascontiguousarray(np.moveaxis(brute.derivative_field(G3, U, L, T, t, rho), 0, -1))
+              for t in (tau - 1, tau, tau + 1)}
+        for nu in range(4):
+            DD = brute.derivative_field(D1, U, L, T, tau, nu)          # [V3][12][12]
+            for j, (p, qq) in enumerate([(1, 0), (0, 1)]):
+                Cb = brute.meson_spin_open(G1, Ghat, np.moveaxis(DD, 0, -1), L, kp[p], q[qq])
+                got = C[j, 0, 5 + 4 * rho + nu].reshape((4,) * 6)
+                assert np.allclose(got, Cb, atol=1e-12 * np.abs(Cb).max())
+
+
+def test_two_derivatives_commute_with_unit_links():
+    """With unit links the lattice derivatives are commuting difference
+    operators: D_nu D_rho = D_rho D_nu, and D_nu D_nu is the second difference
+    over two sites, (G(y+2nu) - 2 G(y) + G(y-2nu)) / 4."""
+    L = (4, 5, 4)
+    T = 6
+    V3, _, G3, _, s, _ = _meson_setup(L, 1, 54, T=T)
+    U1 = {t: syn.unit_links(L) for t in range(T)}
+    k = oracle.momenta(2)
+    I = oracle.insertion(G3, s, [2], L, T, k, U_t=U1, n_ops=21)[:, 0]
+    for rho in range(4):
+        for nu in range(4):
+            assert np.allclose(I[:, 5 + 4 * rho + nu], I[:, 5 + 4 * nu + rho], atol=1e-12)
+    for nu in range(4):
+        if nu < 3:
+            arr = G3[2].reshape(12, 12, L[2], L[1], L[0])
+            ax = {0: -1, 1: -2, 2: -3}[nu]
+            Gp2 = np.roll(arr, -2, axis=ax).reshape(12, 12, V3)
+            Gm2 = np.roll(arr, +2, axis=ax).reshape(12, 12, V3)
+        else:
+            Gp2, Gm2 = G3[4], G3[0]
+        D2 = (Gp2 - 2 * G3[2] + Gm2) / 4
+        want = oracle.insertion({0: D2}, {0: s[2]}, [0], L, 1, k)[:, 0, 0]
+        assert np.allclose(I[:, 5 + 5 * nu], want, atol=1e-12)
+
+
 def test_vector_derivative_matches_propagator_derivative():
     """D_nu on the colour vectors of s equals D_nu on a propagator whose columns are them."""
     L = (3, 2, 2)
