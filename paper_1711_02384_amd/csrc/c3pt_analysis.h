@@ -54,6 +54,20 @@ struct SmearArgs {
 };
 hipError_t launch_smear(bool f64, const SmearArgs& a, hipStream_t st);
 
+// One covariant derivative of a colour-vector field (two-derivative
+// insertion operators): out = 1/2 [U_rho(x) fp(x+rho) - U_rho(x-rho)^dag fm(x-rho)].
+struct DerivStencilArgs {
+    const void* fp;         // field read at x + rho (time: the slice above)
+    const void* fm;         // field read at x - rho (time: the slice below)
+    const void* U;          // links [4][3][3][V3] giving U_rho(x)
+    const void* Um;         // links giving U_rho(x - rho) (time: the slice below; spatial: = U)
+    void* out;
+    int L[3], V3;
+    int n_outer, n_inner;
+    int rho;
+};
+hipError_t launch_cov_deriv(bool f64, const DerivStencilArgs& a, hipStream_t st);
+
 }  // namespace c3pt
 
 #endif

@@ -555,16 +555,16 @@ hipError_t api_timed(const char* name, hipStream_t st, const std::function<hipEr
 
 // c3pt_combine over the insertion timeslices [tau0, tau0 + n_tau) of an
 // insertion output holding n_tau_in slices.
-// The symmetrized derivative runs on the factored projection only: every
-// momentum group of the list must factor.
+// The symmetrized and the two-derivative operators run on the factored
+// projection only: every momentum group of the list must factor.
 static int check_symmetric(const c3pt_geom* g, const int* k, int n_mom) {
     if (g->proj != C3PT_PROJ_FACTORED)
-        return fail(C3PT_EUNSUPPORTED, "n_ops = 9 needs the factored projection (C3PT_PROJ_FACTORED)");
+        return fail(C3PT_EUNSUPPORTED, "n_ops = 9 and 21 need the factored projection (C3PT_PROJ_FACTORED)");
     const bool f64 = g->dtype == C3PT_C128;
     for (const MomGroup& mg : momentum_groups(n_mom, f64)) {
         FactorPlan plan;
         if (!build_factor_plan(g, +1, k, mg, f64, &plan))
-            return fail(C3PT_EUNSUPPORTED, "n_ops = 9: the momentum list does not factor (too many distinct k1)");
+            return fail(C3PT_EUNSUPPORTED, "n_ops = 9 or 21: the momentum list does not factor (too many distinct k1)");
     }
     return C3PT_OK;
 }
@@ -770,7 +770,8 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
     if (!G_t || !s_t || !out) return fail(C3PT_EINVAL, "NULL pointer table or output");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     if (n_tau < 1 || !taus) return fail(C3PT_EINVAL, "empty timeslice list");
-    if (n_ops != 1 && n_ops != 5 && n_ops != 9) return fail(C3PT_EINVAL, "n_ops = %d (must be 1, 5 or 9)", n_ops);
+    if (n_ops != 1 && n_ops != 5 && n_ops != 9 && n_ops != 21)
+        return fail(C3PT_EINVAL, "n_ops = %d (must be 1, 5, 9 or 21)", n_ops);
     if (n_ops > 1 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
     const int T = geom->T;
     for (int j = 0; j < n_tau; ++j) {
@@ -785,9 +786,15 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
             if (n_ops == 9 && (!s_t[tn] || !s_t[tp]))
                 return fail(C3PT_EINVAL, "stochastic solution slices %d and %d needed around %d", tp, tn, t);
+            if (n_ops == 21) {
+                const int tn2 = (t + 2) % T, tp2 = (t - 2 + 2 * T) % T;
+                if (!G_t[tn2] || !G_t[tp2])
+                    return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp2, tn2, t);
+                if (!U_t[tn] || !U_t[tp2]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp2, tn);
+            }
         }
     }
-    if (n_ops == 9) {
+    if (n_ops == 9 || n_ops == 21) {
         if (int rc = check_symmetric(geom, k, n_mom)) return rc;
     }
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
@@ -816,12 +823,57 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                 a.sp[j] = s_t[tp];
             }
         }
+        // two-derivative operators: D_rho G on every slice next to a timeslice of
+        // this launch, in stream-ordered memory freed after the projection
+        std::vector<int> dsl;
+        void* dbuf = nullptr;
+        size_t dslice = 0;
+        hipStream_t dst = (hipStream_t)geom->stream;
+        auto dslot = [&](int t) { return (int)(std::find(dsl.begin(), dsl.end(), t) - dsl.begin()); };
+        if (n_ops == 21) {
+            for (int j = 0; j < nt; ++j)
+                for (int d = -1; d <= 1; ++d) {
+                    const int t = ((taus[j0 + j] + d) % T + T) % T;
+                    if (dslot(t) == (int)dsl.size()) dsl.push_back(t);
+                }
+            const long long V3 = (long long)geom->L[0] * geom->L[1] * geom->L[2];
+            dslice = (size_t)144 * V3 * (geom->dtype == C3PT_C128 ? sizeof(double2) : sizeof(float2));
+            if (hipMallocAsync(&dbuf, 4 * dsl.size() * dslice, dst) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(C3PT_ENOMEM, "no device memory for the derived propagator slices");
+            }
+            for (int rho = 0; rho < 4; ++rho)
+                for (size_t m = 0; m < dsl.size(); ++m) {
+                    const int t = dsl[m], tn = (t + 1) % T, tp = (t - 1 + T) % T;
+                    DerivStencilArgs da;
+                    da.fp = G_t[rho < 3 ? t : tn];
+                    da.fm = G_t[rho < 3 ? t : tp];
+                    da.U = U_t[t];
+                    da.Um = U_t[rho < 3 ? t : tp];
+                    da.out = (char*)dbuf + (rho * dsl.size() + m) * dslice;
+                    for (int q = 0; q < 3; ++q) da.L[q] = geom->L[q];
+                    da.V3 = (int)V3;
+                    da.n_outer = 4;
+                    da.n_inner = 12;
+                    da.rho = rho;
+                    if (int rc = to_status(timed("cov_deriv", dst, [&] {
+                                               return launch_cov_deriv(geom->dtype == C3PT_C128, da, dst);
+                                           }),
+                                           "derivative stencil launch")) {
+                        (void)hipFreeAsync(dbuf, dst);
+                        return rc;
+                    }
+                }
+        }
+        auto dfield = [&](int rho, int t) {
+            return (const void*)((char*)dbuf + (rho * dsl.size() + dslot(((t % T) + T) % T)) * dslice);
+        };
         const int ncb = n_noise * nt * n_ops;
         int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_ops, kBlockCols, ncb,
                                 nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
                                     hipStream_t st = (hipStream_t)geom->stream;
                                     if (!fac) {
-                                        if (n_ops == 9) return hipErrorNotSupported;
+                                        if (n_ops >= 9) return hipErrorNotSupported;
                                         return launch_insertion(mode, mt, variant, pg, a, st);
                                     }
                                     // local and derivative operators in separate launches (each
@@ -841,11 +893,28 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                     pd.n_per_share = n_noise * 4;
                                     e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, ad, st);
                                     if (e != hipSuccess || n_ops == 5) return e;
+                                    if (n_ops == 21) {
+                                        // D_nu of the field D_rho G: the derivative producer on it
+                                        for (int rho = 0; rho < 4 && e == hipSuccess; ++rho) {
+                                            InsertionArgs ar = a;
+                                            ar.op_lo = 5 + 4 * rho;
+                                            ar.op_cnt = 4;
+                                            for (int j = 0; j < nt; ++j) {
+                                                const int t = taus[j0 + j];
+                                                ar.G[j] = dfield(rho, t);
+                                                ar.Gn[j] = dfield(rho, t + 1);
+                                                ar.Gp[j] = dfield(rho, t - 1);
+                                            }
+                                            e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, ar, st);
+                                        }
+                                        return e;
+                                    }
                                     InsertionLeftArgs ab = a;
                                     ab.op_lo = 5;
                                     ab.op_cnt = 4;
                                     return launch_fac_insertion_left(f64, pg.fac_acc, pd, ab, st);
                                 });
+        if (dbuf) (void)hipFreeAsync(dbuf, dst);
         if (rc) return rc;
     }
     if (n_ops == 9) {

@@ -267,13 +267,15 @@ struct InsertionProducerT {
     static __device__ __forceinline__ Ctx make(const void* G, const void* Gn, const void* Gp, const void* s,
                                                const void* U, const void* Up, int noise, int op, int V3) {
         Ctx c;
-        c.nu = op - 1;
+        // -1 for the local operator (kernels that take both kinds branch on it);
+        // ops 1 + nu, and 5 + 4 rho + nu of the two-derivative launches
+        c.nu = op == 0 ? -1 : ((op - 1) & 3);
         c.s = (const C2<R>*)s + (size_t)noise * 12 * V3;
         if (op == 0) {
             c.Gf = c.Gb = (const C2<R>*)G;
             c.U = c.Um = nullptr;
         } else {
-            const int nu = op - 1;
+            const int nu = c.nu;
             c.Gf = (const C2<R>*)((nu < 3) ? G : Gn);
             c.Gb = (const C2<R>*)((nu < 3) ? G : Gp);
             c.U = (const C2<R>*)U + (size_t)nu * 9 * V3;

@@ -124,4 +124,70 @@ hipError_t launch_smear(bool f64, const SmearArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// One covariant derivative of a field of colour vectors (layout as above):
+//   out(x) = 1/2 [U_rho(x) f(x + rho) - U_rho(x - rho)^dag f(x - rho)].
+// Spatial rho: fp = fm = the slice, U = Um = U_rho of the slice, neighbours
+// in the slice; time: fp, fm the adjacent slices at the same site, U = U_t of
+// the slice, Um = U_t of the slice below.  One (site, vector) per thread; the
+// two links of a site are read by the 8 vector threads of that site (cache).
+template <typename R>
+__global__ void __launch_bounds__(kSmThreads) cov_deriv_kernel(DerivStencilArgs a) {
+    const int tid = threadIdx.x;
+    const int gx = (a.V3 + kSmSites - 1) / kSmSites;
+    const int nw = gridDim.x, w = blockIdx.x;
+    const int full = (nw / 8) * 8;
+    const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
+    const int tile = item % gx, vb = item / gx;
+    const int n = tile * kSmSites + tid % kSmSites;
+    const int v = vb * kSmVecs + tid / kSmSites;
+    if (n >= a.V3 || v >= a.n_outer * a.n_inner) return;
+    const int L1 = a.L[0], L2 = a.L[1], L3 = a.L[2];
+    int np = n, nm = n;
+    if (a.rho < 3) {
+        const int q = n / L1, x1 = n - q * L1, x3 = q / L2, x2 = q - x3 * L2;
+        const int x = a.rho == 0 ? x1 : (a.rho == 1 ? x2 : x3);
+        const int ext = a.rho == 0 ? L1 : (a.rho == 1 ? L2 : L3);
+        const int st = a.rho == 0 ? 1 : (a.rho == 1 ? L1 : L1 * L2);
+        np = n + (x == ext - 1 ? (1 - ext) * st : st);
+        nm = n - (x == 0 ? (1 - ext) * st : st);
+    }
+    const unsigned V3 = (unsigned)a.V3;
+    const int d = a.rho < 3 ? a.rho : 3;
+    const C2<R>* U = (const C2<R>*)a.U + (size_t)d * 9 * V3;
+    const C2<R>* Um = (const C2<R>*)a.Um + (size_t)d * 9 * V3;
+    const C2<R>* fp = (const C2<R>*)a.fp;
+    const C2<R>* fm = (const C2<R>*)a.fm;
+    C2<R>* out = (C2<R>*)a.out;
+    const int o = v / a.n_inner, in_i = v - o * a.n_inner;
+    unsigned base[3];
+    C2<R> f[3], b[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        base[c] = (unsigned)((o * 3 + c) * a.n_inner + in_i) * V3;
+        f[c] = fp[base[c] + (unsigned)np];
+        b[c] = fm[base[c] + (unsigned)nm];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        C2<R> acc = {0, 0};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            acc = cfma(acc, U[(unsigned)(c * 3 + e) * V3 + (unsigned)n], f[e]);
+            acc = csub(acc, cmulc(b[e], Um[(unsigned)(e * 3 + c) * V3 + (unsigned)nm]));
+        }
+        out[base[c] + (unsigned)n] = cscale(acc, (R)0.5);
+    }
+}
+
+hipError_t launch_cov_deriv(bool f64, const DerivStencilArgs& a, hipStream_t st) {
+    const long long gx = (a.V3 + kSmSites - 1) / kSmSites;
+    const long long gy = (a.n_outer * (long long)a.n_inner + kSmVecs - 1) / kSmVecs;
+    const dim3 grid((unsigned)(gx * gy));
+    if (f64)
+        hipLaunchKernelGGL(cov_deriv_kernel<double>, grid, dim3(kSmThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL(cov_deriv_kernel<float>, grid, dim3(kSmThreads), 0, st, a);
+    return hipGetLastError();
+}
+
 }  // namespace c3pt
