@@ -61,9 +61,9 @@ def parse():
     ap.add_argument("--smear", type=int, default=0,
                     help="twosink32: steps of gauge-covariant smearing (kappa 0.25) of the sink propagators "
                          "and noise vectors, in the timed step")
-    ap.add_argument("--ops", type=int, choices=[5, 9], default=None,
+    ap.add_argument("--ops", type=int, choices=[5, 9, 21], default=None,
                     help="meson32 / twosink32 insertion operators: 5 = local + 4 D_nu (default), "
-                         "9 = also the 4 symmetrized <->D_nu")
+                         "9 = also the 4 symmetrized <->D_nu, 21 (meson32) = also the 16 D_nu D_rho")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
     ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2", "fac"], default=None,
@@ -218,7 +218,7 @@ class Meson32:
         self.baryon = not args.no_baryon
         self.n_ops = args.ops or 5
         self.name = ("meson+nucleon 3pt, 32^3x64, t_f=16, tau=0..16, N=4, |k|^2<=6 (81 momenta), "
-                     "local+4 D_nu" + (" + 4 symmetrized <->D_nu" if self.n_ops == 9 else "")
+                     "local+4 D_nu" + {5: "", 9: " + 4 symmetrized <->D_nu", 21: " + 16 D_nu D_rho"}[self.n_ops]
                      + (", nucleon spectator" if self.baryon else ""))
 
     def setup(self, c3pt, syn, dev, geom, k):
@@ -227,8 +227,9 @@ class Meson32:
         up = lambda a: _up(a, dev, np.complex64)
         self.G1 = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
         self.eta = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
-        gsl = sorted({t % T for tau in self.taus for t in (tau - 1, tau, tau + 1)})
-        usl = sorted({t % T for tau in self.taus for t in (tau - 1, tau)})
+        wide = self.n_ops == 21          # D_rho G on tau +- 1 needs G on tau +- 2
+        gsl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 2 + wide)})
+        usl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 1 + wide)})
         self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
         ssl = gsl if self.n_ops == 9 else self.taus
         self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
@@ -279,8 +280,10 @@ class Meson32:
     def dominant(self, n_mom, proj):
         V3 = int(np.prod(self.L))
         if proj == "fac":
-            per = (CONTRACTION_FLOPS["insertion_local"] + min(self.n_ops - 1, 4) * CONTRACTION_FLOPS["insertion_deriv"]
-                   + max(self.n_ops - 5, 0) * CONTRACTION_FLOPS["insertion_left"])
+            n_deriv = {1: 0, 5: 4, 9: 4, 21: 20}[self.n_ops]     # launches of the derivative producer
+            n_left = 4 if self.n_ops == 9 else 0
+            per = (CONTRACTION_FLOPS["insertion_local"] + n_deriv * CONTRACTION_FLOPS["insertion_deriv"]
+                   + n_left * CONTRACTION_FLOPS["insertion_left"])
             return "fac_insertion", self.N * len(self.taus) * V3 * per
         cols = self.N * len(self.taus) * self.n_ops * 192
         return "proj_insertion", 8.0 * n_mom * V3 * cols
@@ -296,19 +299,22 @@ class Meson32:
         L, T = self.L, self.T
         G1 = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
         eta = syn.round_to_c64(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
+        if self.n_ops == 21:
+            n_slices = max(1, n_slices // 4)      # the oracle's 21 operators cost about 4x the 5
         taus = self.taus[len(self.taus) // 2: len(self.taus) // 2 + n_slices]
-        need = sorted({t % T for tau in taus for t in (tau - 1, tau, tau + 1)})
+        wide = self.n_ops == 21
+        need = sorted({t % T for tau in taus for t in range(tau - 1 - wide, tau + 2 + wide)})
         G3 = {t: syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in need}
         s_sl = need if self.n_ops == 9 else taus
         s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in s_sl}
         U = {t % T: syn.round_to_c64(syn.link_slice(L, self.cfg, t % T))
-             for t in sorted({t - 1 for t in taus} | set(taus))}
+             for t in sorted({t + d for t in taus for d in range(-1 - wide, 1 + wide)})}
         t0 = time.perf_counter()
         oracle.spectator_meson(G1, eta, L, k)
         oracle.insertion(G3, s, taus, L, T, k, U_t=U, n_ops=self.n_ops)
         dt = time.perf_counter() - t0
         units = self.N * int(np.prod(L)) * len(k) * (1 + len(taus))
-        return units, dt, (f"FP64 numpy oracle: meson spectator + insertion (5 ops) on {len(taus)} of "
+        return units, dt, (f"FP64 numpy oracle: meson spectator + insertion ({self.n_ops} ops) on {len(taus)} of "
                            f"{len(self.taus)} timeslices, full 32^3 slices, N=4, {len(k)} momenta; nucleon "
                            f"spectator and combine not in the sample")
 
@@ -495,6 +501,8 @@ class TwoSink32(Meson32):
     def __init__(self, args):
         self.baryon = False
         self.n_ops = args.ops or 5
+        if self.n_ops == 21:
+            raise SystemExit("twosink32 takes --ops 5 or 9")
         self.taus = [(self.t_fwd + j) % self.T for j in range((self.t_bwd - self.t_fwd) % self.T + 1)]
         self.smear_iter, self.kappa = args.smear, 0.25
         self.name = ("meson 3pt forward + backward with time-partitioned noise, 32^3x96, r_4=30, x'_4=20, "
@@ -509,8 +517,9 @@ class TwoSink32(Meson32):
         self.Gb = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_bwd))
         self.eta_f = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_fwd))
         self.eta_b = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_bwd))
-        gsl = sorted({t % T for tau in self.taus for t in (tau - 1, tau, tau + 1)})
-        usl = sorted({t % T for tau in self.taus for t in (tau - 1, tau)})
+        wide = self.n_ops == 21          # D_rho G on tau +- 1 needs G on tau +- 2
+        gsl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 2 + wide)})
+        usl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 1 + wide)})
         self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
         ssl = gsl if self.n_ops == 9 else self.taus
         self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
