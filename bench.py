@@ -116,17 +116,18 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
                      "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
-    # 32^3 step: local (484219 + 264384 KiB) and derivative (1962253 + 1074944 KiB) dispatches of one call
-    ("meson32", "fac", "fac_insertion", 5): ((484219 + 1962253) * 2048 + (264384 + 1074944) * 1024,
-                                             "d27cf80589d07087"),
-    # the same with the symmetrized derivative: + left-derivative dispatch (1170077 + 1057536 KiB)
-    ("meson32", "fac", "fac_insertion", 9): ((484280 + 1991999 + 1170077) * 2048
-                                             + (264384 + 1074944 + 1057536) * 1024, "d27cf80589d07087"),
-    # 48^3 step: one nucleon spectator dispatch (414763 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414763 * 2048 + 857088 * 1024, "d27cf80589d07087"),
-    # two-sink 32^3 x 96 step: local (3759436 + 4687200 KiB) and derivative (21411653 + 19017600 KiB)
-    ("twosink32", "fac", "fac_insertion", 5): ((3759436 + 21411653) * 2048 + (4687200 + 19017600) * 1024,
-                                               "d27cf80589d07087"),
+    # 32^3 step: local (484217 + 264384 KiB) and derivative (1950582 + 1074944 KiB) dispatches of one call
+    ("meson32", "fac", "fac_insertion", 5): ((484217 + 1950582) * 2048 + (264384 + 1074944) * 1024, "1b6cb26c053fe5f8"),
+    # the same with the symmetrized derivative: + left-derivative dispatch (1170017 + 1057536 KiB)
+    ("meson32", "fac", "fac_insertion", 9): ((484275 + 1984729 + 1170017) * 2048
+                                             + (264384 + 1074944 + 1057536) * 1024, "1b6cb26c053fe5f8"),
+    # with the two-derivative operators: local + five derivative-producer dispatches (1989158 + 1074944 KiB each)
+    ("meson32", "fac", "fac_insertion", 21): ((484248 + 5 * 1989158) * 2048 + (264384 + 5 * 1074944) * 1024,
+                                              "1b6cb26c053fe5f8"),
+    # 48^3 step: one nucleon spectator dispatch (414622 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414622 * 2048 + 857088 * 1024, "1b6cb26c053fe5f8"),
+    # two-sink 32^3 x 96 step: local (3765287 + 4687200 KiB) and derivative (21539205 + 19017600 KiB)
+    ("twosink32", "fac", "fac_insertion", 5): ((3765287 + 21539205) * 2048 + (4687200 + 19017600) * 1024, "1b6cb26c053fe5f8"),
 }
 
 

@@ -9,8 +9,13 @@ they are also exported as ``spectator_meson`` etc.):
 
 * ``c3pt_spectator_meson(G_tf, eta, k, geom)``      Eq. (9) spectator part
 * ``c3pt_spectator_baryon(G1_tf, G2_tf, eta, k, geom)``  epsilon-tensor spectator
-* ``c3pt_insertion(G_t, s_t, taus, k, geom, U_t=None, n_ops=1)``  Eq. (10)
+* ``c3pt_insertion(G_t, s_t, taus, k, geom, U_t=None, n_ops=1)``  Eq. (10);
+  n_ops 5: + D_nu, 9: + symmetrized <->D_nu, 21: + D_nu D_rho
 * ``c3pt_combine(spec, ins, ...)``                 noise-weighted product
+* ``c3pt_two_sink_meson(...)``                     forward + backward diagrams, time-partitioned noise
+* ``c3pt_gamma_meson(C, ...)`` / ``c3pt_gamma_nucleon(C, channel, ...)``  Gamma channels
+* ``smear_propagator(G, U, geom, kappa, n)`` / ``smear_vectors(v, ...)``  (c3pt_smear) quark smearing
+* ``Batch`` and ``Server``: many sources in one recorded graph; continuous batching
 """
 from __future__ import annotations
 
