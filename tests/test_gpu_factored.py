@@ -7,7 +7,8 @@ variant 1: chunks of planes summed in registers), 32-site tiles (x1 rows of
 groups, a source off the origin, and a momentum list with more distinct k1
 than the kernel holds (that group runs on the dense kernel).  The |k|^2 <= 9
 list has a k1 with seven distinct k2, more than one stage-1 slot keeps: it is
-split over two slots.
+split over two slots.  Rows of five 16-site segments (more than the stage-1
+operands kept in LDS) and an extent of 1 are covered too.
 """
 import numpy as np
 import pytest
@@ -35,6 +36,9 @@ CASES = [
     ((8, 8, 8), 6, [2], 1, 3, False, (3, 5, 1)),         # complex128, one FP64 group
     ((6, 5, 4), 6, [0, 4], 2, 5, False, (0, 1, 2)),      # complex128, two FP64 groups (57 momenta)
     ((12, 8, 6), 4, [0, 2], 1, 9, True, (3, 1, 2)),      # |k|^2 <= 9: k1 = 0 has seven k2, two stage-1 slots
+    ((72, 3, 2), 4, [1], 1, 3, True, (0, 1, 1)),         # five row segments: stage-1 operands refilled per tile
+    ((80, 2, 3), 4, [0, 3], 1, 2, False, (7, 1, 0)),     # complex128, five segments, last one ragged
+    ((6, 1, 5), 4, [2], 2, 3, True, (2, 0, 4)),          # extent 1 in x2: neighbours are the site itself
 ]
 
 
