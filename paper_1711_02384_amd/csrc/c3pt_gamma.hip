@@ -102,28 +102,42 @@ __global__ void __launch_bounds__(256) gamma_meson_kernel(GammaMesonArgs a) {
     }
 }
 
-// One workgroup per block of nucleon data; wave w takes rows w, w+4, ...; lane
+// One workgroup per block of nucleon data; wave w of kNucWaves takes rows w,
+// w + kNucWaves, ..., four at a time (four row loads in flight); lane
 // = (at, bt, b) reads one complex of the row (a row is 64 consecutive values).
-__global__ void __launch_bounds__(256) gamma_nucleon_kernel(GammaNucleonArgs a) {
-    __shared__ double2 Z[4][kMaxNucProj][kX2S];
+// NP: the largest projector count of the instantiation (4 keeps the
+// accumulators of the usual parity projectors in few registers).
+constexpr int kNucWaves = 8;
+
+template <int NP>
+__global__ void __launch_bounds__(64 * kNucWaves) gamma_nucleon_kernel(GammaNucleonArgs a) {
+    constexpr int NT = 64 * kNucWaves;
+    __shared__ double2 Z[kNucWaves][NP][kX2S];
     __shared__ double2 Gi[16][16];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, b = lane & 3;
-    for (int i = tid; i < a.n_ins * 16; i += 256) (&Gi[0][0])[i] = a.gins[i];
+    for (int i = tid; i < a.n_ins * 16; i += NT) (&Gi[0][0])[i] = a.gins[i];
     const double2* Cb = a.C + (size_t)blockIdx.x * 65536 + lane;
-    double2 acc[kMaxNucProj];
+    double2 acc[NP];
 #pragma unroll
-    for (int p = 0; p < kMaxNucProj; ++p) acc[p] = make_double2(0.0, 0.0);
-#pragma unroll 4
-    for (int k = wave; k < a.n_rows; k += 4) {
-        const double2 v = Cb[(size_t)a.rows[k] * 64];
+    for (int p = 0; p < NP; ++p) acc[p] = make_double2(0.0, 0.0);
+    auto add_row = [&](int k, double2 v) {
         const double2* wk = a.w + (size_t)k * a.n_proj * 4 + b;
 #pragma unroll
-        for (int p = 0; p < kMaxNucProj; ++p)
+        for (int p = 0; p < NP; ++p)
             if (p < a.n_proj) acc[p] = cfma(wk[p * 4], v, acc[p]);
+    };
+    int k = wave;
+    for (; k + 3 * kNucWaves < a.n_rows; k += 4 * kNucWaves) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = Cb[(size_t)a.rows[k + u * kNucWaves] * 64];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add_row(k + u * kNucWaves, v[u]);
     }
+    for (; k < a.n_rows; k += kNucWaves) add_row(k, Cb[(size_t)a.rows[k] * 64]);
     // sum the four lanes of one (at, bt): b is the lowest two bits of the lane
 #pragma unroll
-    for (int p = 0; p < kMaxNucProj; ++p) {
+    for (int p = 0; p < NP; ++p) {
         if (p < a.n_proj) {
             acc[p].x += __shfl_xor(acc[p].x, 1);
             acc[p].y += __shfl_xor(acc[p].y, 1);
@@ -135,13 +149,16 @@ __global__ void __launch_bounds__(256) gamma_nucleon_kernel(GammaNucleonArgs a) 
     __syncthreads();
     const int total = a.n_proj * a.n_ins;
     double2* ob = a.out + (size_t)blockIdx.x * total;
-    for (int i = tid; i < total; i += 256) {
+    for (int i = tid; i < total; i += NT) {
         const int p = i / a.n_ins, j = i - p * a.n_ins;
         double2 s = make_double2(0.0, 0.0);
         for (int t = 0; t < 16; ++t) {
-            double2 z = Z[0][p][t];
-            z.x += Z[1][p][t].x + Z[2][p][t].x + Z[3][p][t].x;
-            z.y += Z[1][p][t].y + Z[2][p][t].y + Z[3][p][t].y;
+            double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int w = 0; w < kNucWaves; ++w) {
+                z.x += Z[w][p][t].x;
+                z.y += Z[w][p][t].y;
+            }
             s = cfma(Gi[j][t], z, s);
         }
         ob[i] = s;
@@ -154,7 +171,10 @@ hipError_t launch_gamma_meson(const GammaMesonArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_gamma_nucleon(const GammaNucleonArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(gamma_nucleon_kernel, dim3((unsigned)a.n_blk), dim3(256), 0, st, a);
+    if (a.n_proj <= 4)
+        hipLaunchKernelGGL(gamma_nucleon_kernel<4>, dim3((unsigned)a.n_blk), dim3(64 * kNucWaves), 0, st, a);
+    else
+        hipLaunchKernelGGL(gamma_nucleon_kernel<kMaxNucProj>, dim3((unsigned)a.n_blk), dim3(64 * kNucWaves), 0, st, a);
     return hipGetLastError();
 }
 

@@ -40,15 +40,17 @@ def test_gamma_meson_matches_oracle(counts):
 
 
 @pytest.mark.parametrize("channel", ["d", "u"])
-@pytest.mark.parametrize("custom", [False, True])
+@pytest.mark.parametrize("custom", [0, 3, 6])
 def test_gamma_nucleon_matches_oracle(channel, custom):
+    """custom = 0: the default matrices; else random A, Abar, Gins and that many
+    random projectors (6 takes the kernel form for more than four)."""
     import paper_1711_02384_amd as c3pt
-    _say(f"gamma nucleon, channel {channel}, custom matrices {custom}")
+    _say(f"gamma nucleon, channel {channel}, custom projectors {custom}")
     g = np.random.default_rng(22 + custom)
     C = syn.gaussian((2, 3, 1024, 64), g)
     kw = {}
     if custom:
-        kw = dict(A=syn.gaussian((4, 4), g), Abar=syn.gaussian((4, 4), g), P=syn.gaussian((3, 4, 4), g),
+        kw = dict(A=syn.gaussian((4, 4), g), Abar=syn.gaussian((4, 4), g), P=syn.gaussian((custom, 4, 4), g),
                   g_ins=syn.gaussian((5, 4, 4), g))
     ch = c3pt.PROTON_D if channel == "d" else c3pt.PROTON_U
     got = c3pt.gamma_nucleon(_dev(C), ch, **kw)
