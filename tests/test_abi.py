@@ -43,7 +43,7 @@ def _k(n=1):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
 
-DUMMY = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+DUMMY = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
 
 
 @pytest.mark.parametrize("bad", ["L0", "Lbig", "T0", "dtype", "proj", "split_c128", "nmom0", "nmombig",
@@ -203,3 +203,82 @@ def test_batch_null_handles():
     assert c.lib.c3pt_batch_run(None, None) == c.C3PT_EINVAL
     assert c.lib.c3pt_batch_info(None, None, None, None) == c.C3PT_EINVAL
     assert c.lib.c3pt_batch_destroy(None) == c.C3PT_OK
+
+
+def test_two_sink_rejects_bad_arguments():
+    import paper_1711_02384_amd as c
+    g = _geom(c, T=8)
+    ka, kp = _k(1)
+    full = (ctypes.c_void_p * 8)(*([0x1000] * 8))
+    L = c.lib
+    args = lambda t_fwd, t_src, t_bwd, n_ops=1, G=full: (ctypes.byref(g), DUMMY, DUMMY, t_fwd, DUMMY, DUMMY, t_bwd,
+                                                       t_src, 1, G, full, full, n_ops, kp, 1, None, None, 1,
+                                                       DUMMY, DUMMY, DUMMY, DUMMY)
+    assert L.c3pt_two_sink_meson(*args(1, 4, 1)) == c.C3PT_EINVAL          # the sinks overlap around T
+    assert "overlap" in L.c3pt_last_error().decode()
+    assert L.c3pt_two_sink_meson(*args(1, 3, 9)) == c.C3PT_EINVAL          # timeslice outside [0, T)
+    assert L.c3pt_two_sink_meson(*args(1, 3, 5, n_ops=21)) == c.C3PT_EINVAL
+    holes = (ctypes.c_void_p * 8)(0x1000, 0x1000, None, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
+    assert L.c3pt_two_sink_meson(*args(1, 3, 5, G=holes)) == c.C3PT_EINVAL
+    assert "missing" in L.c3pt_last_error().decode()
+
+
+def test_insertion_symmetric_and_two_derivative_need_factored_projection_and_slices():
+    import paper_1711_02384_amd as c
+    L = c.lib
+    ka, kp = _k(2)
+    taus = (ctypes.c_int * 1)(3)
+    full = (ctypes.c_void_p * 8)(*([0x1000] * 8))
+    for n_ops in (9, 21):
+        g = _geom(c, T=8, proj=0)
+        assert L.c3pt_insertion(ctypes.byref(g), full, full, 1, taus, 1, full, n_ops, kp, 2, DUMMY) \
+            == c.C3PT_EUNSUPPORTED
+    g = _geom(c, T=8, proj=3)
+    s_holes = (ctypes.c_void_p * 8)(*[0x1000 if t != 4 else None for t in range(8)])
+    assert L.c3pt_insertion(ctypes.byref(g), full, s_holes, 1, taus, 1, full, 9, kp, 2, DUMMY) == c.C3PT_EINVAL
+    G_holes = (ctypes.c_void_p * 8)(*[0x1000 if t != 1 else None for t in range(8)])
+    assert L.c3pt_insertion(ctypes.byref(g), G_holes, full, 1, taus, 1, full, 21, kp, 2, DUMMY) == c.C3PT_EINVAL
+    assert L.c3pt_insertion(ctypes.byref(g), full, full, 1, taus, 1, full, 7, kp, 2, DUMMY) == c.C3PT_EINVAL
+
+
+def test_gamma_and_smear_reject_bad_arguments():
+    import paper_1711_02384_amd as c
+    L = c.lib
+    m = np.zeros((17, 4, 4), dtype=np.complex128)
+    mp = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    # meson: counts outside [1, 16], NULL with a count other than 16, NULL data
+    assert L.c3pt_gamma_meson(DUMMY, 1, mp, 17, None, 16, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_gamma_meson(DUMMY, 1, None, 4, None, 16, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_gamma_meson(None, 1, None, 16, None, 16, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_gamma_meson(DUMMY, 0, None, 16, None, 16, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    # nucleon: unknown channel, projector counts, NULL projectors with a count other than 2
+    assert L.c3pt_gamma_nucleon(DUMMY, 1, 5, None, None, None, 2, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_gamma_nucleon(DUMMY, 1, c.PROTON_D, None, None, mp, 17, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    assert L.c3pt_gamma_nucleon(DUMMY, 1, c.PROTON_U, None, None, None, 3, None, 16, DUMMY, None) == c.C3PT_EINVAL
+    # smearing: negative steps or kappa, missing links, empty field
+    g = _geom(c)
+    assert L.c3pt_smear(ctypes.byref(g), DUMMY, DUMMY, 4, 12, DUMMY, 0.25, -1) == c.C3PT_EINVAL
+    assert L.c3pt_smear(ctypes.byref(g), DUMMY, DUMMY, 4, 12, DUMMY, -0.1, 3) == c.C3PT_EINVAL
+    assert L.c3pt_smear(ctypes.byref(g), DUMMY, DUMMY, 4, 12, None, 0.25, 3) == c.C3PT_EINVAL
+    assert L.c3pt_smear(ctypes.byref(g), DUMMY, DUMMY, 0, 12, DUMMY, 0.25, 3) == c.C3PT_EINVAL
+
+
+def test_bench_host_logic():
+    """bench.py's host-side helpers: the traffic hash covers the factored
+    kernels' planning functions, the recorded traffic matches the sources, the
+    two-sink pair list has the 185 pairs of 93 momenta."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    api = open(os.path.join(ROOT, "paper_1711_02384_amd", "csrc", "c3pt_api.hip")).read()
+    for name in bench.TRAFFIC_FUNCTIONS:
+        txt = bench._function_text(api, name)
+        assert name + "(" in txt and txt.rstrip().endswith("}")
+    h = bench.sources_hash()
+    assert len(h) == 16
+    for key, (nbytes, hsh) in bench.MEASURED_TRAFFIC.items():
+        assert nbytes > 0 and len(hsh) == 16
+        assert (bench.measured_traffic(*key) == nbytes) == (hsh == h)
+    assert len(bench.pairs_diag_or_zero(93)) == 185
+    r = bench.roofline_entry("fac_insertion", 1.0e12, 50.0, "fac", traffic=None)
+    assert r["bound"] == "alu" and abs(r["achieved"] - 20.0) < 1e-9 and abs(r["frac"] - 20.0 / 78.6) < 1e-4
