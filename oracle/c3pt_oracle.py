@@ -13,7 +13,7 @@ indices" (Lattice 2017):
 * the noise-weighted product of the two parts (the estimate of Eq. (5) inserted
   into Eq. (8)), with the source colour delta of Eq. (1) summed.
 
-Readings where the paper is silent (all listed in the design doc):
+Readings where the paper is silent:
 
 * gamma basis: DeGrand-Rossi, so gamma5 = diag(1, 1, -1, -1) and is real;
 * memory orders: A = 3*spin + colour; propagator G[A_row][A_col][site] with the
@@ -23,7 +23,17 @@ Readings where the paper is silent (all listed in the design doc):
   (stochastic) line carries gamma5 eta at the sink exactly as for the meson;
 * derivative insertion: D_nu psi(y) = 1/2 [U_nu(y) psi(y+nu) - U_nu(y-nu)^dag psi(y-nu)]
   acting on the propagator G_f3, periodic boundaries in all directions;
-* noise weights w_i, default 1/N (Eq. (5) carries 1/N, Eq. (8) drops it).
+* noise weights w_i, default 1/N (Eq. (5) carries 1/N, Eq. (8) drops it);
+* two sinks: the noise lives on x'_4 and x''_4, the forward diagram takes the
+  insertion timeslices from x'_4 to r_4, the backward one those from r_4 to
+  x''_4 (both inclusive, forward in time modulo T);
+* symmetrized derivative 1/2 (->D - <-D), the left derivative acting on the
+  insertion's antiquark (D applied to s in the factorized form); two
+  derivatives D_nu D_rho act on the quark field, D_rho first;
+* Gamma channels: the creation operator carries gamma4 Gamma^dag gamma4
+  (Eq. (3)); the proton is eps (u^T C gamma5 d) u with C = gamma2 gamma4,
+  its conjugate chi^dag gamma4, connected Wick contractions, tr[P G];
+* smearing: Wuppertal form, spatial, periodic, kappa and the step count free.
 
 Everything is complex128.  Sums over sites are done as a phase-matrix product
 (numpy matmul) over site chunks; colour sums as einsum.
