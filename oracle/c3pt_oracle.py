@@ -299,6 +299,8 @@ def insertion(G_t, s_t, taus, L, T: int, k, r=(0, 0, 0), U_t=None, n_ops: int = 
     contraction (gamma_mu D_nu follows by contracting (at, bt) with gamma_mu);
     with n_ops = 21, ops 5 + 4 rho + nu are the two-derivative operators
     D_nu D_rho (D_rho applied first; G needed on tau +- 2 for rho = nu = t);
+    with n_ops = 37, ops 21 + 4 mu + nu are in addition the symmetrized
+    <->D_mu <->D_nu (s needed on tau +- 2 as well);
     with n_ops = 9, ops 5..8 are the symmetrized derivative
     <->D_nu = 1/2 (->D_nu - <-D_nu).  The left derivative acts on the
     antiquark field of the insertion, whose factorized form is the conjugated
@@ -306,7 +308,7 @@ def insertion(G_t, s_t, taus, L, T: int, k, r=(0, 0, 0), U_t=None, n_ops: int = 
     <-D_nu is the local contraction of G(y) with D_nu s (s needed on tau +- 1
     for nu = t).
     Returns [N][n_tau][n_ops][n_mom][192]."""
-    assert n_ops in (1, 5, 9, 21)
+    assert n_ops in (1, 5, 9, 21, 37)
     taus = list(taus)
     N = np.asarray(s_t[taus[0]]).shape[0]
     n_mom = len(np.asarray(k).reshape(-1, 3))
@@ -322,13 +324,27 @@ def insertion(G_t, s_t, taus, L, T: int, k, r=(0, 0, 0), U_t=None, n_ops: int = 
                 Ds = covariant_derivative_vector(s_t, U_t, L, T, tau, nu)
                 left = _insertion_local(G_t[tau], Ds, L, k, r)
                 out[:, j, 5 + nu] = 0.5 * (out[:, j, 1 + nu] - left)
-        if n_ops == 21:
+        if n_ops >= 21:
             for rho in range(4):
                 # D_rho G on tau and its two neighbouring slices, then D_nu of that field
                 DG = {t % T: covariant_derivative(G_t, U_t, L, T, t % T, rho) for t in (tau - 1, tau, tau + 1)}
                 for nu in range(4):
                     DDG = covariant_derivative(DG, U_t, L, T, tau, nu)
                     out[:, j, 5 + 4 * rho + nu] = _insertion_local(DDG, s_t[tau], L, k, r)
+        if n_ops == 37:
+            # <->D_mu <->D_nu = 1/4 (->D_mu ->D_nu - ->D_mu <-D_nu - <-D_mu ->D_nu + <-D_mu <-D_nu);
+            # left derivatives act on the antiquark: D applied to s, <-D_mu first
+            Ds = {mu: {t % T: covariant_derivative_vector(s_t, U_t, L, T, t % T, mu) for t in (tau - 1, tau, tau + 1)}
+                  for mu in range(4)}
+            DG = {nu: covariant_derivative(G_t, U_t, L, T, tau, nu) for nu in range(4)}
+            for mu in range(4):
+                for nu in range(4):
+                    rr = out[:, j, 5 + 4 * nu + mu]                       # D_mu (D_nu G)
+                    lr = _insertion_local(DG[nu], Ds[mu][tau], L, k, r)   # (psibar <-D_mu)(->D_nu psi)
+                    rl = _insertion_local(DG[mu], Ds[nu][tau], L, k, r)   # (psibar <-D_nu)(->D_mu psi)
+                    ll = _insertion_local(G_t[tau], covariant_derivative_vector(Ds[mu], U_t, L, T, tau, nu),
+                                          L, k, r)
+                    out[:, j, 21 + 4 * mu + nu] = 0.25 * (rr - lr - rl + ll)
     return out
 
 

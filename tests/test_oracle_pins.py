@@ -389,6 +389,63 @@ def test_two_derivatives_trace_against_bruteforce():
                 assert np.allclose(got, Cb, atol=1e-12 * np.abs(Cb).max())
 
 
+def test_symmetrized_two_derivatives_trace_against_bruteforce():
+    """Ops 21 + 4 mu + nu = <->D_mu <->D_nu = 1/4 (->->  - ->D_mu <-D_nu - <-D_mu ->D_nu + <-<-):
+    every term traced as Eq. (1) with the right derivatives on G_f3 and the left
+    ones on the end of G_f2(x', y) at the insertion (matrix form, applied to
+    the stochastic estimate of G2 in the order they act)."""
+    L = (3, 3, 2)
+    T = 7
+    N = 2
+    V3, G1, G3, eta, s, U = _meson_setup(L, N, 56, T=T)
+    kp = oracle.momenta(1)[[0, 5]]
+    q = oracle.momenta(1)[[1, 6]]
+    tau = 3
+    S = oracle.spectator_meson(G1, eta, L, kp)
+    I = oracle.insertion(G3, s, [tau], L, T, q, U_t=U, n_ops=37)
+    C = oracle.combine(S, I, pairs=[(1, 0), (0, 1)])
+    w = np.full(N, 1.0 / N)
+    Ghat = {t: np.einsum('i,iAy,iBx->yxAB', w, s[t], np.conj(eta)) for t in range(T)}
+    DG3 = {nu: {t: np.ascontiguousarray(np.moveaxis(brute.derivative_field(G3, U, L, T, t, nu), 0, -1))
+                for t in (tau - 1, tau, tau + 1)} for nu in range(4)}
+    # left derivative mu on G2's y end, on the slices next to tau
+    DG2 = {mu: {t: _left_derivative_G2(Ghat, U, L, T, t, mu) for t in (tau - 1, tau, tau + 1)} for mu in range(4)}
+    for mu in range(4):
+        for nu in range(4):
+            DDG3 = np.moveaxis(brute.derivative_field(DG3[nu], U, L, T, tau, mu), 0, -1)   # D_mu D_nu G3
+            DDG2 = _left_derivative_G2(DG2[mu], U, L, T, tau, nu)                          # <-D_mu then <-D_nu
+            for j, (p, qq) in enumerate([(1, 0), (0, 1)]):
+                args = (L, kp[p], q[qq])
+                rr = brute.meson_spin_open(G1, Ghat[tau], DDG3, *args)
+                lr = brute.meson_spin_open(G1, DG2[mu][tau], DG3[nu][tau], *args)
+                rl = brute.meson_spin_open(G1, DG2[nu][tau], DG3[mu][tau], *args)
+                ll = brute.meson_spin_open(G1, DDG2, G3[tau], *args)
+                Cb = 0.25 * (rr - lr - rl + ll)
+                got = C[j, 0, 21 + 4 * mu + nu].reshape((4,) * 6)
+                assert np.allclose(got, Cb, atol=1e-12 * np.abs(Cb).max())
+
+
+def test_symmetrized_two_derivatives_summation_by_parts():
+    """At insertion momentum with q_mu = q_nu = 0 (spatial mu, nu) a left
+    derivative moves onto the right with a minus sign, so
+    <->D_mu <->D_nu = 1/4 (3 D_mu D_nu + D_nu D_mu) there (random links: the two
+    orders differ)."""
+    L = (3, 4, 3)
+    T = 7
+    V3, _, G3, _, s, U = _meson_setup(L, 2, 58, T=T)
+    q = np.array([[0, 0, 0], [0, 0, 1]])
+    I = oracle.insertion(G3, s, [3], L, T, q, U_t=U, n_ops=37)[:, 0]
+    for m, qm in enumerate(q):
+        for mu in range(3):
+            for nu in range(3):
+                if qm[mu] or qm[nu]:
+                    continue
+                dd = I[:, 5 + 4 * nu + mu, m]          # D_mu D_nu
+                dd_rev = I[:, 5 + 4 * mu + nu, m]      # D_nu D_mu
+                want = 0.25 * (3 * dd + dd_rev)
+                assert np.allclose(I[:, 21 + 4 * mu + nu, m], want, atol=1e-12 * np.abs(want).max())
+
+
 def test_two_derivatives_commute_with_unit_links():
     """With unit links the lattice derivatives are commuting difference
     operators: D_nu D_rho = D_rho D_nu, and D_nu D_nu is the second difference
