@@ -131,16 +131,20 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
  * With n_ops == 21, ops 5 + 4 rho + nu are the two-derivative operators
  * D_nu D_rho (D_rho applied first): D_rho G is formed on tau-1 .. tau+1 by a
  * stencil in stream-ordered device memory, then D_nu of it is contracted.
- * n_ops == 9 and 21 run on the factored projection only (C3PT_PROJ_FACTORED
- * and a momentum list it factors; C3PT_EUNSUPPORTED otherwise).
+ * With n_ops == 37, ops 21 + 4 mu + nu are in addition the symmetrized
+ *   <->D_mu <->D_nu = 1/4 (->D_mu ->D_nu - ->D_mu <-D_nu - <-D_mu ->D_nu + <-D_mu <-D_nu),
+ * the left derivatives acting on the antiquark (D applied to s, <-D_mu first).
+ * n_ops == 9, 21 and 37 run on the factored projection only
+ * (C3PT_PROJ_FACTORED and a momentum list it factors; C3PT_EUNSUPPORTED
+ * otherwise).
  *   G_t : host array of T device pointers (slice t of the propagator, or NULL
  *         where not needed).  Needed: every tau; with n_ops >= 5 also tau+-1;
- *         with n_ops == 21 also tau+-2.
+ *         with n_ops >= 21 also tau+-2.
  *   s_t : host array of T device pointers to [n_noise][12][V3]; needed at every
- *         tau; with n_ops == 9 also at tau+-1.
+ *         tau; with n_ops == 9 also at tau+-1; with n_ops == 37 at tau+-1, tau+-2.
  *   U_t : host array of T device pointers to [4][3][3][V3], or NULL when
  *         n_ops == 1.  With n_ops >= 5 needed at every tau and tau-1; with
- *         n_ops == 21 also tau+1 and tau-2.
+ *         n_ops >= 21 also tau+1 and tau-2.
  *   out : device complex128 [n_noise][n_tau][n_ops][n_mom][192],
  *         order (at, bt, b, c).
  */

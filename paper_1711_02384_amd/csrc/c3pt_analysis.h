@@ -41,6 +41,8 @@ struct InsertionLeftArgs;
 hipError_t launch_fac_insertion_left(bool f64, bool acc, const ProjGrid& pg, const InsertionLeftArgs& a,
                                      hipStream_t st);
 hipError_t launch_symmetrize(double2* out, long long n_outer, int n_mom, hipStream_t st);
+// n_ops = 37: the 37 operators [n_outer][37][n_mom][192] from the 53 internal ones.
+hipError_t launch_assemble_sym2(const double2* in, double2* out, long long n_outer, int n_mom, hipStream_t st);
 
 // Gauge-covariant smearing step of colour vectors [n_outer][3][n_inner][V3].
 struct SmearArgs {

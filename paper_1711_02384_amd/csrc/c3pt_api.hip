@@ -770,8 +770,8 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
     if (!G_t || !s_t || !out) return fail(C3PT_EINVAL, "NULL pointer table or output");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
     if (n_tau < 1 || !taus) return fail(C3PT_EINVAL, "empty timeslice list");
-    if (n_ops != 1 && n_ops != 5 && n_ops != 9 && n_ops != 21)
-        return fail(C3PT_EINVAL, "n_ops = %d (must be 1, 5, 9 or 21)", n_ops);
+    if (n_ops != 1 && n_ops != 5 && n_ops != 9 && n_ops != 21 && n_ops != 37)
+        return fail(C3PT_EINVAL, "n_ops = %d (must be 1, 5, 9, 21 or 37)", n_ops);
     if (n_ops > 1 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
     const int T = geom->T;
     for (int j = 0; j < n_tau; ++j) {
@@ -784,29 +784,70 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             if (!G_t[tn] || !G_t[tp])
                 return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp, tn, t);
             if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
-            if (n_ops == 9 && (!s_t[tn] || !s_t[tp]))
+            if ((n_ops == 9 || n_ops == 37) && (!s_t[tn] || !s_t[tp]))
                 return fail(C3PT_EINVAL, "stochastic solution slices %d and %d needed around %d", tp, tn, t);
-            if (n_ops == 21) {
+            if (n_ops >= 21) {
                 const int tn2 = (t + 2) % T, tp2 = (t - 2 + 2 * T) % T;
                 if (!G_t[tn2] || !G_t[tp2])
                     return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp2, tn2, t);
                 if (!U_t[tn] || !U_t[tp2]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp2, tn);
+                if (n_ops == 37 && (!s_t[tn2] || !s_t[tp2]))
+                    return fail(C3PT_EINVAL, "stochastic solution slices %d and %d needed around %d", tp2, tn2, t);
             }
         }
     }
-    if (n_ops == 9 || n_ops == 21) {
+    if (n_ops >= 9) {
         if (int rc = check_symmetric(geom, k, n_mom)) return rc;
     }
+    // n_ops = 37 runs 53 internal operators: 0..20 as n_ops = 21, then the
+    // mixed terms (D_mu s with D_nu G, ops 21 + 4 mu + nu) and the left-left
+    // terms (D_nu D_mu s with G, ops 37 + 4 mu + nu); the symmetrized operators
+    // are assembled from them at the end
+    const int n_int = n_ops == 37 ? 53 : n_ops;
+    const bool f64 = geom->dtype == C3PT_C128;
+    const size_t elem = f64 ? sizeof(double2) : sizeof(float2);
+    const long long V3 = (long long)geom->L[0] * geom->L[1] * geom->L[2];
+    hipStream_t dst = (hipStream_t)geom->stream;
+    void* outp = out;
+    void* iout = nullptr;
+    if (n_ops == 37) {
+        const size_t ibytes = (size_t)n_noise * n_tau * n_int * n_mom * kBlockCols * sizeof(double2);
+        if (hipMallocAsync(&iout, ibytes, dst) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(C3PT_ENOMEM, "no device memory for the internal operator parts");
+        }
+        outp = iout;
+    }
+    auto release = [&](int rc) {
+        if (iout) (void)hipFreeAsync(iout, dst);
+        return rc;
+    };
+    auto stencil = [&](const void* fp, const void* fm, const void* U, const void* Um, void* o, int n_outer,
+                       int n_inner, int rho) {
+        DerivStencilArgs da;
+        da.fp = fp;
+        da.fm = fm;
+        da.U = U;
+        da.Um = Um;
+        da.out = o;
+        for (int q = 0; q < 3; ++q) da.L[q] = geom->L[q];
+        da.V3 = (int)V3;
+        da.n_outer = n_outer;
+        da.n_inner = n_inner;
+        da.rho = rho;
+        return to_status(timed("cov_deriv", dst, [&] { return launch_cov_deriv(f64, da, dst); }),
+                         "derivative stencil launch");
+    };
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
         InsertionLeftArgs a;
         memset(&a, 0, sizeof(a));
         for (int j = 0; j < 3; ++j) a.L[j] = geom->L[j];
         a.n_tau = nt;
-        a.n_ops = n_ops;
+        a.n_ops = n_int;
         a.n_noise = n_noise;
         a.op_lo = 0;
-        a.op_cnt = n_ops;
+        a.op_cnt = n_int;
         for (int j = 0; j < nt; ++j) {
             const int t = taus[j0 + j];
             const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
@@ -823,54 +864,57 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                 a.sp[j] = s_t[tp];
             }
         }
-        // two-derivative operators: D_rho G on every slice next to a timeslice of
-        // this launch, in stream-ordered memory freed after the projection
+        // derived fields in stream-ordered memory freed after the projection:
+        // D_rho G on every slice next to a timeslice of this launch; with
+        // n_ops = 37 also D_mu s there and D_nu D_mu s on the timeslices
         std::vector<int> dsl;
         void* dbuf = nullptr;
-        size_t dslice = 0;
-        hipStream_t dst = (hipStream_t)geom->stream;
-        auto dslot = [&](int t) { return (int)(std::find(dsl.begin(), dsl.end(), t) - dsl.begin()); };
-        if (n_ops == 21) {
+        const size_t gslice = (size_t)144 * V3 * elem, sslice = (size_t)n_noise * 12 * V3 * elem;
+        auto dslot = [&](int t) { return (int)(std::find(dsl.begin(), dsl.end(), ((t % T) + T) % T) - dsl.begin()); };
+        auto dG = [&](int rho, int t) { return (char*)dbuf + (rho * dsl.size() + dslot(t)) * gslice; };
+        auto dS = [&](int mu, int t) {
+            return (char*)dbuf + 4 * dsl.size() * gslice + (mu * dsl.size() + dslot(t)) * sslice;
+        };
+        auto ddS = [&](int mu, int nu, int j) {
+            return (char*)dbuf + 4 * dsl.size() * (gslice + sslice) + ((size_t)(4 * mu + nu) * nt + j) * sslice;
+        };
+        if (n_ops >= 21) {
             for (int j = 0; j < nt; ++j)
                 for (int d = -1; d <= 1; ++d) {
                     const int t = ((taus[j0 + j] + d) % T + T) % T;
                     if (dslot(t) == (int)dsl.size()) dsl.push_back(t);
                 }
-            const long long V3 = (long long)geom->L[0] * geom->L[1] * geom->L[2];
-            dslice = (size_t)144 * V3 * (geom->dtype == C3PT_C128 ? sizeof(double2) : sizeof(float2));
-            if (hipMallocAsync(&dbuf, 4 * dsl.size() * dslice, dst) != hipSuccess) {
+            size_t bytes = 4 * dsl.size() * gslice;
+            if (n_ops == 37) bytes += 4 * dsl.size() * sslice + (size_t)16 * nt * sslice;
+            if (hipMallocAsync(&dbuf, bytes, dst) != hipSuccess) {
                 (void)hipGetLastError();
-                return fail(C3PT_ENOMEM, "no device memory for the derived propagator slices");
+                return release(fail(C3PT_ENOMEM, "no device memory for the derived slices"));
             }
-            for (int rho = 0; rho < 4; ++rho)
-                for (size_t m = 0; m < dsl.size(); ++m) {
+            int rc = 0;
+            for (int rho = 0; rho < 4 && !rc; ++rho)
+                for (size_t m = 0; m < dsl.size() && !rc; ++m) {
                     const int t = dsl[m], tn = (t + 1) % T, tp = (t - 1 + T) % T;
-                    DerivStencilArgs da;
-                    da.fp = G_t[rho < 3 ? t : tn];
-                    da.fm = G_t[rho < 3 ? t : tp];
-                    da.U = U_t[t];
-                    da.Um = U_t[rho < 3 ? t : tp];
-                    da.out = (char*)dbuf + (rho * dsl.size() + m) * dslice;
-                    for (int q = 0; q < 3; ++q) da.L[q] = geom->L[q];
-                    da.V3 = (int)V3;
-                    da.n_outer = 4;
-                    da.n_inner = 12;
-                    da.rho = rho;
-                    if (int rc = to_status(timed("cov_deriv", dst, [&] {
-                                               return launch_cov_deriv(geom->dtype == C3PT_C128, da, dst);
-                                           }),
-                                           "derivative stencil launch")) {
-                        (void)hipFreeAsync(dbuf, dst);
-                        return rc;
-                    }
+                    rc = stencil(G_t[rho < 3 ? t : tn], G_t[rho < 3 ? t : tp], U_t[t], U_t[rho < 3 ? t : tp],
+                                 dG(rho, t), 4, 12, rho);
+                    if (!rc && n_ops == 37)
+                        rc = stencil(s_t[rho < 3 ? t : tn], s_t[rho < 3 ? t : tp], U_t[t], U_t[rho < 3 ? t : tp],
+                                     dS(rho, t), 4 * n_noise, 1, rho);
                 }
+            for (int mu = 0; mu < 4 && !rc && n_ops == 37; ++mu)
+                for (int nu = 0; nu < 4 && !rc; ++nu)
+                    for (int j = 0; j < nt && !rc; ++j) {
+                        const int t = taus[j0 + j], tn = (t + 1) % T, tp = (t - 1 + T) % T;
+                        rc = stencil(dS(mu, nu < 3 ? t : tn), dS(mu, nu < 3 ? t : tp), U_t[t],
+                                     U_t[nu < 3 ? t : tp], ddS(mu, nu, j), 4 * n_noise, 1, nu);
+                    }
+            if (rc) {
+                (void)hipFreeAsync(dbuf, dst);
+                return release(rc);
+            }
         }
-        auto dfield = [&](int rho, int t) {
-            return (const void*)((char*)dbuf + (rho * dsl.size() + dslot(((t % T) + T) % T)) * dslice);
-        };
-        const int ncb = n_noise * nt * n_ops;
-        int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_ops, kBlockCols, ncb,
-                                nt * n_ops, n_tau * n_ops, j0 * n_ops, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
+        const int ncb = n_noise * nt * n_int;
+        int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_int, kBlockCols, ncb,
+                                nt * n_int, n_tau * n_int, j0 * n_int, outp, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
                                     hipStream_t st = (hipStream_t)geom->stream;
                                     if (!fac) {
                                         if (n_ops >= 9) return hipErrorNotSupported;
@@ -878,7 +922,6 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                     }
                                     // local and derivative operators in separate launches (each
                                     // kernel keeps only its own path's registers)
-                                    const bool f64 = geom->dtype == C3PT_C128;
                                     InsertionArgs al = a;
                                     al.op_lo = 0;
                                     al.op_cnt = 1;
@@ -893,37 +936,66 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                     pd.n_per_share = n_noise * 4;
                                     e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, ad, st);
                                     if (e != hipSuccess || n_ops == 5) return e;
-                                    if (n_ops == 21) {
-                                        // D_nu of the field D_rho G: the derivative producer on it
-                                        for (int rho = 0; rho < 4 && e == hipSuccess; ++rho) {
-                                            InsertionArgs ar = a;
-                                            ar.op_lo = 5 + 4 * rho;
-                                            ar.op_cnt = 4;
-                                            for (int j = 0; j < nt; ++j) {
-                                                const int t = taus[j0 + j];
-                                                ar.G[j] = dfield(rho, t);
-                                                ar.Gn[j] = dfield(rho, t + 1);
-                                                ar.Gp[j] = dfield(rho, t - 1);
-                                            }
-                                            e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, ar, st);
-                                        }
-                                        return e;
+                                    if (n_ops == 9) {
+                                        InsertionLeftArgs ab = a;
+                                        ab.op_lo = 5;
+                                        ab.op_cnt = 4;
+                                        return launch_fac_insertion_left(f64, pg.fac_acc, pd, ab, st);
                                     }
-                                    InsertionLeftArgs ab = a;
-                                    ab.op_lo = 5;
-                                    ab.op_cnt = 4;
-                                    return launch_fac_insertion_left(f64, pg.fac_acc, pd, ab, st);
+                                    // D_nu of the field D_rho G: the derivative producer on it
+                                    for (int rho = 0; rho < 4 && e == hipSuccess; ++rho) {
+                                        InsertionArgs ar = a;
+                                        ar.op_lo = 5 + 4 * rho;
+                                        ar.op_cnt = 4;
+                                        for (int j = 0; j < nt; ++j) {
+                                            const int t = taus[j0 + j];
+                                            ar.G[j] = dG(rho, t);
+                                            ar.Gn[j] = dG(rho, t + 1);
+                                            ar.Gp[j] = dG(rho, t - 1);
+                                        }
+                                        e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, ar, st);
+                                    }
+                                    if (e != hipSuccess || n_ops == 21) return e;
+                                    // mixed terms: D_nu G contracted with D_mu s
+                                    for (int mu = 0; mu < 4 && e == hipSuccess; ++mu) {
+                                        InsertionArgs am = a;
+                                        am.op_lo = 21 + 4 * mu;
+                                        am.op_cnt = 4;
+                                        for (int j = 0; j < nt; ++j) am.s[j] = dS(mu, taus[j0 + j]);
+                                        e = launch_fac_insertion(f64, pg.fac_acc, 2, pd, am, st);
+                                    }
+                                    // left-left terms: G contracted with D_nu D_mu s (local producer;
+                                    // its neighbour pointers are G itself)
+                                    for (int mn = 0; mn < 16 && e == hipSuccess; ++mn) {
+                                        InsertionArgs aw = a;
+                                        aw.op_lo = 37 + mn;
+                                        aw.op_cnt = 1;
+                                        for (int j = 0; j < nt; ++j) {
+                                            aw.s[j] = ddS(mn / 4, mn % 4, j);
+                                            aw.Gn[j] = aw.Gp[j] = aw.G[j];
+                                        }
+                                        e = launch_fac_insertion(f64, pg.fac_acc, 1, pl, aw, st);
+                                    }
+                                    return e;
                                 });
         if (dbuf) (void)hipFreeAsync(dbuf, dst);
-        if (rc) return rc;
+        if (rc) return release(rc);
     }
     if (n_ops == 9) {
-        hipStream_t st = (hipStream_t)geom->stream;
-        if (int rc = to_status(timed("symmetrize", st, [&] {
-                                   return launch_symmetrize((double2*)out, (long long)n_noise * n_tau, n_mom, st);
+        if (int rc = to_status(timed("symmetrize", dst, [&] {
+                                   return launch_symmetrize((double2*)out, (long long)n_noise * n_tau, n_mom, dst);
                                }),
                                "symmetrize launch"))
             return rc;
+    }
+    if (n_ops == 37) {
+        if (int rc = to_status(timed("symmetrize", dst, [&] {
+                                   return launch_assemble_sym2((const double2*)iout, (double2*)out,
+                                                               (long long)n_noise * n_tau, n_mom, dst);
+                               }),
+                               "assembly launch"))
+            return release(rc);
+        release(0);
     }
     return ok();
 }

@@ -33,4 +33,37 @@ hipError_t launch_symmetrize(double2* out, long long n_outer, int n_mom, hipStre
     return hipGetLastError();
 }
 
+// n_ops = 37: out[o][op][w] (37 operators) from the 53 internal ones in[o][op][w]:
+// ops 0..20 copied; op 21 + 4 mu + nu = 1/4 (D_mu D_nu - mixed(mu, nu) - mixed(nu, mu) + left-left(mu, nu)),
+// with D_mu D_nu = internal op 5 + 4 nu + mu, mixed(mu, nu) = 21 + 4 mu + nu, left-left = 37 + 4 mu + nu.
+__global__ void __launch_bounds__(256) assemble_sym2_kernel(const double2* in, double2* out, long long n_outer,
+                                                            int n_mom) {
+    const long long per = (long long)n_mom * 192;
+    const long long total = n_outer * 37 * per;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long w = i % per, r = i / per;
+        const int op = (int)(r % 37);
+        const long long o = r / 37;
+        const double2* b = in + o * 53 * per + w;
+        double2 v;
+        if (op < 21) {
+            v = b[op * per];
+        } else {
+            const int mu = (op - 21) / 4, nu = (op - 21) % 4;
+            const double2 rr = b[(5 + 4 * nu + mu) * per], lr = b[(21 + 4 * mu + nu) * per];
+            const double2 rl = b[(21 + 4 * nu + mu) * per], ll = b[(37 + 4 * mu + nu) * per];
+            v = make_double2(0.25 * (rr.x - lr.x - rl.x + ll.x), 0.25 * (rr.y - lr.y - rl.y + ll.y));
+        }
+        out[i] = v;
+    }
+}
+
+hipError_t launch_assemble_sym2(const double2* in, double2* out, long long n_outer, int n_mom, hipStream_t st) {
+    const long long total = n_outer * 37 * n_mom * 192;
+    const unsigned blocks = (unsigned)std::min<long long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(assemble_sym2_kernel, dim3(blocks), dim3(256), 0, st, in, out, n_outer, n_mom);
+    return hipGetLastError();
+}
+
 }  // namespace c3pt

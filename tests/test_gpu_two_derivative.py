@@ -1,4 +1,5 @@
-"""Two-derivative insertion operators (n_ops = 21: ops 5 + 4 rho + nu = D_nu D_rho)
+"""Two-derivative insertion operators (n_ops = 21: ops 5 + 4 rho + nu = D_nu D_rho;
+n_ops = 37: also ops 21 + 4 mu + nu = <->D_mu <->D_nu)
 on the factored projection against the FP64 oracle (pinned by the doubly
 applied matrix-form derivative traced as Eq. (1) and by the unit-link
 identities).  complex128 at 1e-12, complex64 at 1e-5; timeslices at both ends
@@ -19,12 +20,12 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _inputs(L, T, N, taus, cfg, reduced):
+def _inputs(L, T, N, taus, cfg, reduced, wide_s=False):
     cast = syn.round_to_c64 if reduced else (lambda a: a)
     gsl = sorted({(t + d) % T for t in taus for d in (-2, -1, 0, 1, 2)})
     usl = sorted({(t + d) % T for t in taus for d in (-2, -1, 0, 1)})
     G = {t: cast(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in gsl}
-    s = {t: cast(syn.solution_slice(L, N, cfg, t)) for t in taus}
+    s = {t: cast(syn.solution_slice(L, N, cfg, t)) for t in (gsl if wide_s else taus)}
     U = {t: cast(syn.link_slice(L, cfg, t)) for t in usl}
     return G, s, U
 
@@ -56,6 +57,30 @@ def test_two_derivatives_match_oracle(case):
     got = got.cpu().numpy()
     want = oracle.insertion(G, s, taus, L, T, k, r=r, U_t=U, n_ops=21)
     errs = [rel_fro(got[:, :, op], want[:, :, op]) for op in range(21)]
+    _say(f"   max error {max(errs):.1e} (op {int(np.argmax(errs))})")
+    assert max(errs) < tol
+
+
+CASES37 = [
+    ((6, 5, 4), 7, [0, 3], 2, 3, True, (1, 0, 3)),      # complex64, a timeslice at the time boundary
+    ((5, 4, 4), 6, [4], 1, 3, False, (0, 2, 1)),        # complex128
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES37)))
+def test_symmetrized_two_derivatives_match_oracle(case):
+    import paper_1711_02384_amd as c3pt
+    L, T, taus, N, n2, reduced, r = CASES37[case]
+    tol = 1e-5 if reduced else 1e-12
+    _say(f"symmetrized two-derivative case {case}: L={L} T={T} taus={taus} N={N} reduced={reduced}")
+    k = c3pt.momentum_list(n2)
+    G, s, U = _inputs(L, T, N, taus, 160 + case, reduced, wide_s=True)
+    geom = c3pt.Geom(L, T, r=r, proj=c3pt.PROJ_FACTORED)
+    got = c3pt.insertion(_dev(G, reduced), _dev(s, reduced), taus, k, geom, U_t=_dev(U, reduced), n_ops=37)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = oracle.insertion(G, s, taus, L, T, k, r=r, U_t=U, n_ops=37)
+    errs = [rel_fro(got[:, :, op], want[:, :, op]) for op in range(37)]
     _say(f"   max error {max(errs):.1e} (op {int(np.argmax(errs))})")
     assert max(errs) < tol
 
