@@ -61,9 +61,10 @@ def parse():
     ap.add_argument("--smear", type=int, default=0,
                     help="twosink32: steps of gauge-covariant smearing (kappa 0.25) of the sink propagators "
                          "and noise vectors, in the timed step")
-    ap.add_argument("--ops", type=int, choices=[5, 9, 21], default=None,
+    ap.add_argument("--ops", type=int, choices=[5, 9, 21, 37], default=None,
                     help="meson32 / twosink32 insertion operators: 5 = local + 4 D_nu (default), "
-                         "9 = also the 4 symmetrized <->D_nu, 21 (meson32) = also the 16 D_nu D_rho")
+                         "9 = also the 4 symmetrized <->D_nu, 21 (meson32) = also the 16 D_nu D_rho, "
+                         "37 (meson32) = also the 16 <->D_mu <->D_nu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
     ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2", "fac"], default=None,
@@ -219,7 +220,8 @@ class Meson32:
         self.baryon = not args.no_baryon
         self.n_ops = args.ops or 5
         self.name = ("meson+nucleon 3pt, 32^3x64, t_f=16, tau=0..16, N=4, |k|^2<=6 (81 momenta), "
-                     "local+4 D_nu" + {5: "", 9: " + 4 symmetrized <->D_nu", 21: " + 16 D_nu D_rho"}[self.n_ops]
+                     "local+4 D_nu" + {5: "", 9: " + 4 symmetrized <->D_nu", 21: " + 16 D_nu D_rho",
+                                       37: " + 16 D_nu D_rho + 16 <->D_mu <->D_nu"}[self.n_ops]
                      + (", nucleon spectator" if self.baryon else ""))
 
     def setup(self, c3pt, syn, dev, geom, k):
@@ -228,11 +230,11 @@ class Meson32:
         up = lambda a: _up(a, dev, np.complex64)
         self.G1 = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
         self.eta = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
-        wide = self.n_ops == 21          # D_rho G on tau +- 1 needs G on tau +- 2
+        wide = self.n_ops >= 21          # D_rho G on tau +- 1 needs G on tau +- 2
         gsl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 2 + wide)})
         usl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 1 + wide)})
         self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
-        ssl = gsl if self.n_ops == 9 else self.taus
+        ssl = gsl if self.n_ops in (9, 37) else self.taus
         self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
         self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
         n_mom, n_tau = len(k), len(self.taus)
@@ -281,9 +283,11 @@ class Meson32:
     def dominant(self, n_mom, proj):
         V3 = int(np.prod(self.L))
         if proj == "fac":
-            n_deriv = {1: 0, 5: 4, 9: 4, 21: 20}[self.n_ops]     # launches of the derivative producer
+            # column blocks per (noise, timeslice) of each producer
+            n_local = {1: 1, 5: 1, 9: 1, 21: 1, 37: 17}[self.n_ops]
+            n_deriv = {1: 0, 5: 4, 9: 4, 21: 20, 37: 36}[self.n_ops]
             n_left = 4 if self.n_ops == 9 else 0
-            per = (CONTRACTION_FLOPS["insertion_local"] + n_deriv * CONTRACTION_FLOPS["insertion_deriv"]
+            per = (n_local * CONTRACTION_FLOPS["insertion_local"] + n_deriv * CONTRACTION_FLOPS["insertion_deriv"]
                    + n_left * CONTRACTION_FLOPS["insertion_left"])
             return "fac_insertion", self.N * len(self.taus) * V3 * per
         cols = self.N * len(self.taus) * self.n_ops * 192
@@ -300,13 +304,13 @@ class Meson32:
         L, T = self.L, self.T
         G1 = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_f))
         eta = syn.round_to_c64(syn.z2z2_noise(L, self.N, self.cfg, self.t_f))
-        if self.n_ops == 21:
-            n_slices = max(1, n_slices // 4)      # the oracle's 21 operators cost about 4x the 5
+        if self.n_ops >= 21:
+            n_slices = max(1, n_slices // (4 if self.n_ops == 21 else 8))   # the oracle's cost grows with the operators
         taus = self.taus[len(self.taus) // 2: len(self.taus) // 2 + n_slices]
-        wide = self.n_ops == 21
+        wide = self.n_ops >= 21
         need = sorted({t % T for tau in taus for t in range(tau - 1 - wide, tau + 2 + wide)})
         G3 = {t: syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in need}
-        s_sl = need if self.n_ops == 9 else taus
+        s_sl = need if self.n_ops in (9, 37) else taus
         s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in s_sl}
         U = {t % T: syn.round_to_c64(syn.link_slice(L, self.cfg, t % T))
              for t in sorted({t + d for t in taus for d in range(-1 - wide, 1 + wide)})}
@@ -502,7 +506,7 @@ class TwoSink32(Meson32):
     def __init__(self, args):
         self.baryon = False
         self.n_ops = args.ops or 5
-        if self.n_ops == 21:
+        if self.n_ops >= 21:
             raise SystemExit("twosink32 takes --ops 5 or 9")
         self.taus = [(self.t_fwd + j) % self.T for j in range((self.t_bwd - self.t_fwd) % self.T + 1)]
         self.smear_iter, self.kappa = args.smear, 0.25
@@ -518,11 +522,11 @@ class TwoSink32(Meson32):
         self.Gb = up(syn.propagator_slice(L, self.cfg, syn.FIELD_G1, self.t_bwd))
         self.eta_f = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_fwd))
         self.eta_b = up(syn.z2z2_noise(L, self.N, self.cfg, self.t_bwd))
-        wide = self.n_ops == 21          # D_rho G on tau +- 1 needs G on tau +- 2
+        wide = self.n_ops >= 21          # D_rho G on tau +- 1 needs G on tau +- 2
         gsl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 2 + wide)})
         usl = sorted({t % T for tau in self.taus for t in range(tau - 1 - wide, tau + 1 + wide)})
         self.G3 = {t: up(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in gsl}
-        ssl = gsl if self.n_ops == 9 else self.taus
+        ssl = gsl if self.n_ops in (9, 37) else self.taus
         self.s = {t: up(syn.solution_slice(L, self.N, self.cfg, t)) for t in ssl}
         self.U = {t: up(syn.link_slice(L, self.cfg, t)) for t in usl}
         self.pairs = pairs_diag_or_zero(len(k))
