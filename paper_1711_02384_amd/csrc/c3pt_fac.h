@@ -266,15 +266,33 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         if (row_end) {
             // stage 2, in registers
             const C2<R>* cf = sm.coef2[row & 1];
+            if constexpr (sizeof(R) == 4) {
+                // every register of both slots is updated: the coefficient
+                // table is zero-padded by kFacMaxBPerA entries, so all reads
+                // are in bounds, and registers beyond a lane's pairs are never
+                // gathered.  No branch between the reads: all are in flight
+                // at once.
+                C2<R> cw[2][kFacMaxBPerA];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
-                // the first nbmax registers are updated in every lane (a uniform
-                // bound, no divergent branch); those beyond a lane's pairs are
-                // never gathered
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int i = 0; i < kFacMaxBPerA; ++i)
-                    if (i < nbmax) r2[h][i] = cfma(r2[h][i], cf[bs[h] + i], v);
+                    for (int i = 0; i < kFacMaxBPerA; ++i) cw[h][i] = cf[bs[h] + i];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
+#pragma unroll
+                    for (int i = 0; i < kFacMaxBPerA; ++i) r2[h][i] = cfma(r2[h][i], cw[h][i], v);
+                }
+            } else {
+                // FP64: twice the registers per coefficient; the first nbmax
+                // registers are updated one pair at a time (a uniform bound)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const C2<R> v = h == 0 ? C2<R>{r1[0], r1[1]} : C2<R>{r1[2], r1[3]};
+#pragma unroll
+                    for (int i = 0; i < kFacMaxBPerA; ++i)
+                        if (i < nbmax) r2[h][i] = cfma(r2[h][i], cf[bs[h] + i], v);
+                }
             }
             r1 = acc_t{0, 0, 0, 0};
             if (plane_end) {
