@@ -116,10 +116,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Sum over the tiles of planes [p0, p1).  ACC: into out (thread-owned
 // momenta), written by fac_write at the end.  Otherwise every plane's sums are
-// added into the chunk's partial sums in global memory (stored at the first
-// plane, added by no-return atomics at the next ones; each element is owned by
-// one thread of one workgroup, which issues its store and adds in plane order
-// to the same address, so the order of the sum is fixed); out is unused.
+// added into the chunk's partial sums in global memory (written at the first
+// plane, read back and added at the next ones; each element is owned by one
+// thread of one workgroup, so the order is fixed); out is unused.
 //
 // Software pipeline, one workgroup barrier per tile T:
 //   contract(T) -> P (own slots) | stage(T+1) -> buf[(T+1)&1] | loads of T+2 |
@@ -326,19 +325,17 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
                 Part2<R>* part = (Part2<R>*)partial;
                 const size_t base = ((size_t)chunk * n_colblocks + cb) * (size_t)n_mom;
                 const bool first = (x3 == p0);
-                // the first plane stores, later ones add with no-return
-                // atomics, which nothing waits for
                 for (int m = q3; m < n_mom; m += 4) {
                     const int b = sm.plan.pair_of_m[m];
                     const C2<R> w = sm.root[2][mod_small(sm.plan.k3[m] * x3, L3, inv3)];
-                    const C2<R> v = cmul(w, sm.R2[b][c3]);
-                    Part2<R>* dst = &part[(base + m) * kBlockCols + c3];
-                    if (first) {
-                        *dst = Part2<R>{v.x, v.y};
-                    } else {
-                        unsafeAtomicAdd(&dst->x, v.x);
-                        unsafeAtomicAdd(&dst->y, v.y);
+                    C2<R> v = cmul(w, sm.R2[b][c3]);
+                    Part2<R>& dst = part[(base + m) * kBlockCols + c3];
+                    if (!first) {
+                        const Part2<R> o = dst;
+                        v.x += o.x;
+                        v.y += o.y;
                     }
+                    dst = Part2<R>{v.x, v.y};
                 }
             }
             // R2 is gathered again only after this barrier
