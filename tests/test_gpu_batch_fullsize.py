@@ -1,0 +1,113 @@
+"""Parity of the batched form at full lattice sizes, in the launch
+configuration bench.py times for its batch workload: the workload class
+itself draws the inputs on the GPU (seeded) and records the persistent,
+graph-replayed batch with the factored projection and the default
+partial-sum budget; here with 6 sources instead of 64, so that every
+lattice size (24^3 x 48, 32^3 x 64, 48^3 x 96) and both kinds (meson,
+nucleon) are in the one launch.  The FP64 oracle recomputes sampled outputs
+from the same inputs, copied back to the host:
+
+* source 0 (24^3 meson): the spectator (all noise vectors and momenta), the
+  insertion at its first and last timeslice, and the recorded combine on its
+  185 (p', q) pairs at those timeslices;
+* source 5 (48^3 nucleon): the (u, d) spectator for one noise vector and five
+  momenta, and the d-quark insertion at its first timeslice for two noise
+  vectors.
+
+Tolerance 1e-5 relative (Frobenius), the FP32 bar.
+"""
+import argparse
+
+import numpy as np
+import pytest
+
+import c3pt_synth as syn
+import oracle
+from helpers import rel_fro
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    import bench
+    import paper_1711_02384_amd as c3pt
+    args = argparse.Namespace(sources=6, partial_budget_gib=24.0, no_plain=True)
+    W = bench.Batch64(args)
+    k = c3pt.momentum_list(W.n2)
+    W.proj_flag = c3pt.PROJ_FACTORED
+    geom = c3pt.Geom((1, 1, 1), 1, proj=c3pt.PROJ_FACTORED)
+    _say("batch full size: drawing inputs and recording 6 sources")
+    W.setup(c3pt, syn, torch.device("cuda:0"), geom, k)
+    _say(f"batch full size: {W.batch.info()}")
+    W.step()
+    torch.cuda.synchronize()
+    _say("batch full size: replayed")
+    yield W, k, bench.pairs_diag_or_zero(len(k))
+    W.batch.close()
+    del W
+    torch.cuda.empty_cache()
+
+
+def _first_job(W, j):
+    return sum(4 if s["nucleon"] else 2 for s in W.src[:j])
+
+
+def test_batch_fullsize_meson_source(batch):
+    W, k, pairs = batch
+    s = W.src[0]
+    assert not s["nucleon"] and tuple(s["L"]) == (24, 24, 24)
+    L, T, r = s["L"], s["T"], s["r"]
+    js, ji = W.jobs[0], W.jobs[1]
+    _say(f"batch meson 24^3: r={r} taus={s['taus'][0]}..{s['taus'][-1]}")
+    G_tf, eta = _host(js["G"]), _host(js["eta"])
+    S_o = oracle.spectator_meson(G_tf, eta, L, k, r=r)
+    S = W.batch.outputs[0].cpu().numpy()
+    err = rel_fro(S, S_o)
+    _say(f"batch meson 24^3: spectator rel err {err:.2e}")
+    assert err < TOL
+    I = W.batch.outputs[1].cpu().numpy()
+    C = W.batch.combine_outputs[0].cpu().numpy()
+    for tl in (0, len(s["taus"]) - 1):
+        tau = s["taus"][tl]
+        I_o = oracle.insertion({tau: _host(ji["G_t"][tau])}, {tau: _host(ji["s_t"][tau])}, [tau], L, T, k, r=r)
+        err = rel_fro(I[:, tl], I_o[:, 0])
+        _say(f"batch meson 24^3: insertion tau={tau} rel err {err:.2e}")
+        assert err < TOL
+        C_o = oracle.combine(S_o, I_o, pairs=pairs)
+        err = rel_fro(C[:, tl], C_o[:, 0])
+        _say(f"batch meson 24^3: combine tau={tau} ({len(pairs)} pairs) rel err {err:.2e}")
+        assert err < TOL
+
+
+def test_batch_fullsize_nucleon_source(batch):
+    W, k, _ = batch
+    s = W.src[5]
+    assert s["nucleon"] and tuple(s["L"]) == (48, 48, 48)
+    L, T, r = s["L"], s["T"], s["r"]
+    j0 = _first_job(W, 5)
+    jud, jd = W.jobs[j0 + 1], W.jobs[j0 + 3]
+    assert jud["kind"] == "spectator_baryon" and jd["kind"] == "insertion"
+    _say(f"batch nucleon 48^3: r={r} t_f={s['t_f']}")
+    sel_m = [0, 1, 30, 60, 92]
+    want = oracle.spectator_baryon(_host(jud["G1"]), _host(jud["G2"]), _host(jud["eta"])[3:4], L, k[sel_m], r=r)
+    SB = W.batch.outputs[j0 + 1].cpu().numpy()
+    err = rel_fro(SB[3:4, sel_m], want)
+    _say(f"batch nucleon 48^3: (u,d) spectator (noise 3, 5 momenta) rel err {err:.2e}")
+    assert err < TOL
+    tau = s["taus"][0]
+    I_o = oracle.insertion({tau: _host(jd["G_t"][tau])}, {tau: _host(jd["s_t"][tau])[2:4]}, [tau], L, T, k, r=r)
+    I = W.batch.outputs[j0 + 3].cpu().numpy()
+    err = rel_fro(I[2:4, 0], I_o[:, 0])
+    _say(f"batch nucleon 48^3: d insertion tau={tau} (noise 2, 3) rel err {err:.2e}")
+    assert err < TOL
