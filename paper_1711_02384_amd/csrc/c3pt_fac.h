@@ -126,11 +126,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 // The per-site buffers, the row coefficients and (for long rows) the A
 // operands are written one tile ahead into the half not being read.  The
 // contraction inputs are held in three register sets (tiles T, T+1, T+2) so
-// that their loads have more than a tile to arrive.  EARLY waves issue the
-// loads of tile T+2 before their contraction, the others after it: the
-// address units then work while part of the workgroup computes, instead of
-// all waves issuing their loads at once.
-template <typename R, int KT, bool ACC, bool EARLY, class Prod>
+// that their loads have more than a tile to arrive.  PHASE staggers the
+// loads of tile T+2 over the waves: before the contraction (1), in its middle
+// (2, producers that split it) or after it (0), so that the address units
+// work while part of the workgroup computes, instead of all waves issuing
+// their loads at once.
+template <typename R, int KT, bool ACC, int PHASE, class Prod>
 __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const TileGeom& tg, FacSmem<R, KT>& sm,
                                          typename Prod::Buf (&buf)[2], int p0, int p1,
                                          C2<R> (&out)[FacLimits<R>::kOut], void* partial, int n_colblocks,
@@ -247,9 +248,15 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         const bool plane_end = row_end && x2 == L2 - 1;
         // tile T+2 (the last tile again past the end: always in bounds)
         const RowSite rs2 = site_of(pc);
-        if (EARLY) Prod::load_main(ctx, tg, rs2, mn, tid);
+        if (PHASE == 1) Prod::load_main(ctx, tg, rs2, mn, tid);
         // contraction of tile T into this wave's slots
-        Prod::contract(ctx, mc, buf[par], put, tid);
+        if constexpr (PHASE == 2) {
+            Prod::template contract_part<0, 2>(ctx, mc, buf[par], put, tid);
+            Prod::load_main(ctx, tg, rs2, mn, tid);
+            Prod::template contract_part<2, 4>(ctx, mc, buf[par], put, tid);
+        } else {
+            Prod::contract(ctx, mc, buf[par], put, tid);
+        }
         // tile T+1: per-site buffer, row coefficients, A operands
         if (T + 1 < n_tiles) {
             Prod::stage(ctx, pre, buf[par ^ 1], tid);
@@ -257,7 +264,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
             if (!a1_all) fill_a1(par ^ 1, pb.seg * KT);
         }
         Prod::load_pre(ctx, tg, rs2, pre, tid);
-        if (!EARLY) Prod::load_main(ctx, tg, rs2, mn, tid);
+        if (PHASE == 0) Prod::load_main(ctx, tg, rs2, mn, tid);
         wave_lds_sync();
         // stage 1 on this wave's own slots
         const int sa = a1_all ? seg : par;
@@ -357,10 +364,37 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     if (T + 1 < n_tiles) step(T + 1, m1, m0);
 }
 
-// Waves 4..7 (one on each SIMD) load early.  Uniform per wave; both loop
-// forms pass the same workgroup barriers in the same order.
-__device__ __forceinline__ bool fac_early_wave(int tid) {
-    return __builtin_amdgcn_readfirstlane(tid >> 6) / 4 == 1;
+// Producers whose contraction splits at X = 2 (contract_part<X0, X1>).
+template <class Prod, class = void>
+struct FacSplit : std::false_type {};
+template <class Prod>
+struct FacSplit<Prod, std::void_t<decltype(Prod::kSplitContract)>> : std::integral_constant<bool, Prod::kSplitContract> {};
+
+// Load phase of a wave: waves 4..7 (one on each SIMD) issue the loads of tile
+// T+2 before their contraction, waves 8..11 in its middle when the producer
+// splits it, the others after it.  Uniform per wave; every form passes the
+// same workgroup barriers in the same order.
+template <class Prod>
+__device__ __forceinline__ int fac_load_phase(int tid) {
+    const int g = __builtin_amdgcn_readfirstlane(tid >> 6) / 4;
+    return g == 1 ? 1 : (g == 2 && FacSplit<Prod>::value ? 2 : 0);
+}
+
+// Runs the tile loop in the form of the wave's load phase.
+template <typename R, int KT, bool ACC, class Prod, class... A>
+__device__ __forceinline__ void fac_loop_phased(int tid, A&&... args) {
+    const int ph = fac_load_phase<Prod>(tid);
+    if (ph == 1) {
+        fac_loop<R, KT, ACC, 1, Prod>(args..., tid);
+    } else {
+        if constexpr (FacSplit<Prod>::value) {
+            if (ph == 2) {
+                fac_loop<R, KT, ACC, 2, Prod>(args..., tid);
+                return;
+            }
+        }
+        fac_loop<R, KT, ACC, 0, Prod>(args..., tid);
+    }
 }
 
 template <typename R>
@@ -410,10 +444,7 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     }
     const int p0 = chunk * pg.chunk_planes;
     const int p1 = min(tg.L3, p0 + pg.chunk_planes);
-    if (fac_early_wave(tid))
-        fac_loop<R, KT, ACC, true, Prod>(ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
-    else
-        fac_loop<R, KT, ACC, false, Prod>(ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk, tid);
+    fac_loop_phased<R, KT, ACC, Prod>(tid, ctx, tg, sm, buf, p0, p1, out, pg.partial, pg.n_colblocks, cb, chunk);
     if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
 }
 
@@ -451,12 +482,8 @@ __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg)
         fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
         const int p0 = item.z * job.chunk_sites;
         const int p1 = min(tg.L3, p0 + job.chunk_sites);
-        if (fac_early_wave(tid))
-            fac_loop<R, KT, false, true, Prod>(ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb,
-                                               item.z, tid);
-        else
-            fac_loop<R, KT, false, false, Prod>(ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb,
-                                                item.z, tid);
+        fac_loop_phased<R, KT, false, Prod>(tid, ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb,
+                                            item.z);
         __syncthreads();
     }
 }

@@ -380,14 +380,18 @@ struct FacInsDerivProd : InsertionProducerT<R, KT, NT, 2> {
             }
         }
     }
-    template <class Put>
-    static __device__ __forceinline__ void contract(const Ctx&, const Main& m, const Buf& b, Put& out, int tid) {
+    // the contraction of spins at in [X0, X1): a wave may issue loads between
+    // two parts
+    static constexpr bool kSplitContract = true;
+    template <int X0, int X1, class Put>
+    static __device__ __forceinline__ void contract_part(const Ctx&, const Main& m, const Buf& b, Put& out,
+                                                         int tid) {
         const int j = tid % KT;
 #pragma unroll
         for (int i = 0; i < kT; ++i) {
             const int r = (tid + i * NT) / KT;
 #pragma unroll
-            for (int at = 0; at < 4; ++at) {
+            for (int at = X0; at < X1; ++at) {
                 C2<R> p = cmul(b.tp[3 * at][j], m.g[i][0]);
                 p = cfnma(p, b.tm[3 * at][j], m.g[i][3]);
 #pragma unroll
@@ -398,6 +402,10 @@ struct FacInsDerivProd : InsertionProducerT<R, KT, NT, 2> {
                 out.put(S::slot(at, r), j, p);
             }
         }
+    }
+    template <class Put>
+    static __device__ __forceinline__ void contract(const Ctx& c, const Main& m, const Buf& b, Put& out, int tid) {
+        contract_part<0, 4>(c, m, b, out, tid);
     }
 };
 
