@@ -117,23 +117,23 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
                      "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
-    # 32^3 step: local (484188 + 264384 KiB) and derivative (1948827 + 1114112 KiB) dispatches of one call
-    ("meson32", "fac", "fac_insertion", 5): ((484188 + 1948827) * 2048 + (264384 + 1114112) * 1024, "d03f673d484a21a5"),
-    # the same with the symmetrized derivative: + left-derivative dispatch (1169969 + 1057536 KiB)
-    ("meson32", "fac", "fac_insertion", 9): ((484265 + 1975701 + 1169969) * 2048
-                                             + (264384 + 1114112 + 1057536) * 1024, "d03f673d484a21a5"),
-    # with the two-derivative operators: local + five derivative-producer dispatches (1954871 + 1114112 KiB each)
-    ("meson32", "fac", "fac_insertion", 21): ((484217 + 5 * 1954871) * 2048 + (264384 + 5 * 1114112) * 1024,
-                                              "d03f673d484a21a5"),
+    # 32^3 step: local (484189 + 264384 KiB) and derivative (1940642 + 1114112 KiB) dispatches of one call
+    ("meson32", "fac", "fac_insertion", 5): ((484189 + 1940642) * 2048 + (264384 + 1114112) * 1024, "d9861a908adb74c3"),
+    # the same with the symmetrized derivative: + left-derivative dispatch (1169850 + 1057536 KiB)
+    ("meson32", "fac", "fac_insertion", 9): ((484190 + 1947661 + 1169850) * 2048
+                                             + (264384 + 1114112 + 1057536) * 1024, "d9861a908adb74c3"),
+    # with the two-derivative operators: local + five derivative-producer dispatches (1941550 + 1114112 KiB each)
+    ("meson32", "fac", "fac_insertion", 21): ((484218 + 5 * 1941550) * 2048 + (264384 + 5 * 1114112) * 1024,
+                                              "d9861a908adb74c3"),
     # with the symmetrized two-derivative operators: 17 local-producer dispatches (484185 + 264384 KiB each)
-    # and 9 derivative-producer dispatches (1981464 + 1114112 KiB each) per call
-    ("meson32", "fac", "fac_insertion", 37): ((17 * 484185 + 9 * 1981464) * 2048 + (17 * 264384 + 9 * 1114112) * 1024,
-                                              "d03f673d484a21a5"),
-    # 48^3 step: one nucleon spectator dispatch (415121 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (415121 * 2048 + 857088 * 1024, "d03f673d484a21a5"),
-    # two-sink 32^3 x 96 step: local (3780199 + 4687200 KiB) and derivative (24615943 + 19622400 KiB)
-    ("twosink32", "fac", "fac_insertion", 5): ((3780199 + 24615943) * 2048 + (4687200 + 19622400) * 1024,
-                                               "d03f673d484a21a5"),
+    # and 9 derivative-producer dispatches (1958778 + 1114112 KiB each) per call
+    ("meson32", "fac", "fac_insertion", 37): ((17 * 484185 + 9 * 1958778) * 2048 + (17 * 264384 + 9 * 1114112) * 1024,
+                                              "d9861a908adb74c3"),
+    # 48^3 step: one nucleon spectator dispatch (414814 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414814 * 2048 + 857088 * 1024, "d9861a908adb74c3"),
+    # two-sink 32^3 x 96 step: local (3771200 + 4687200 KiB) and derivative (32728293 + 19622400 KiB)
+    ("twosink32", "fac", "fac_insertion", 5): ((3771200 + 32728293) * 2048 + (4687200 + 19622400) * 1024,
+                                               "d9861a908adb74c3"),
 }
 
 

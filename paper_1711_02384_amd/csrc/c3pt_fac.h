@@ -251,9 +251,9 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
         if (PHASE == 1) Prod::load_main(ctx, tg, rs2, mn, tid);
         // contraction of tile T into this wave's slots
         if constexpr (PHASE == 2) {
-            Prod::template contract_part<0, 2>(ctx, mc, buf[par], put, tid);
+            Prod::template contract_part<0, 1>(ctx, mc, buf[par], put, tid);
             Prod::load_main(ctx, tg, rs2, mn, tid);
-            Prod::template contract_part<2, 4>(ctx, mc, buf[par], put, tid);
+            Prod::template contract_part<1, 4>(ctx, mc, buf[par], put, tid);
         } else {
             Prod::contract(ctx, mc, buf[par], put, tid);
         }
@@ -364,7 +364,7 @@ __device__ __forceinline__ void fac_loop(const typename Prod::Ctx& ctx, const Ti
     if (T + 1 < n_tiles) step(T + 1, m1, m0);
 }
 
-// Producers whose contraction splits at X = 2 (contract_part<X0, X1>).
+// Producers whose contraction splits into parts (contract_part<X0, X1>).
 template <class Prod, class = void>
 struct FacSplit : std::false_type {};
 template <class Prod>
