@@ -109,19 +109,6 @@ def phase_matrix(L, k, r, sigma: int, sites=None) -> np.ndarray:
     return np.exp(1j * sigma * arg)
 
 
-def _project(P: np.ndarray, L, k, r, sigma: int, chunk: int = 4096) -> np.ndarray:
-    """sum_x phi^sigma_k(x) P[..., x] -> [..., n_mom] (plain site sum)."""
-    V3 = P.shape[-1]
-    lead = P.shape[:-1]
-    Pm = P.reshape(-1, V3)
-    out = np.zeros((Pm.shape[0], len(np.asarray(k).reshape(-1, 3))), dtype=np.complex128)
-    for s0 in range(0, V3, chunk):
-        sl = np.arange(s0, min(V3, s0 + chunk))
-        ph = phase_matrix(L, k, r, sigma, sites=sl)
-        out += Pm[:, sl] @ ph.T
-    return out.reshape(lead + (out.shape[-1],))
-
-
 # --------------------------------------------------------------------------
 # Spectator parts.
 # --------------------------------------------------------------------------

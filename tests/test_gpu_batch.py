@@ -13,7 +13,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import Workload, rel_fro
+from helpers import Workload, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -122,16 +122,16 @@ def test_batch_matches_oracle_and_single_calls(proj, name):
     for li, lat in enumerate(lats):
         S_o, I_o = lat.oracle_parts(k)
         S, I = b.outputs[2 * li].cpu().numpy(), b.outputs[2 * li + 1].cpu().numpy()
-        es, ei = rel_fro(S, S_o), rel_fro(I, I_o)
+        es, ei = rel_err(S, S_o), rel_err(I, I_o)
         _say(f"batch {name}: lattice {lat.L} spectator {es:.2e} insertion {ei:.2e}")
         assert es < TOL and ei < TOL
         for tl in range(len(lat.taus)):
             for op in range(lat.n_ops):
-                assert rel_fro(I[:, tl, op], I_o[:, tl, op]) < TOL
+                assert rel_err(I[:, tl, op], I_o[:, tl, op]) < TOL
         Ss, Is = lat.single_calls(c3pt, k, proj)
         torch.cuda.synchronize()
-        assert rel_fro(S, Ss.cpu().numpy()) < SAME
-        assert rel_fro(I, Is.cpu().numpy()) < SAME
+        assert rel_err(S, Ss.cpu().numpy()) < SAME
+        assert rel_err(I, Is.cpu().numpy()) < SAME
         C_ref = c3pt.combine(b.outputs[2 * li], b.outputs[2 * li + 1], pairs=[(0, 0), (3, 5), (26, 1)])
         torch.cuda.synchronize()
         assert torch.equal(b.combine_outputs[li], C_ref)
@@ -168,8 +168,8 @@ def test_batch_graph_replays_and_refill():
     for li, lat in enumerate(lats):
         Ss, Is = lat.single_calls(c3pt, k, 0)
         torch.cuda.synchronize()
-        assert rel_fro(b.outputs[2 * li].cpu().numpy(), Ss.cpu().numpy()) < SAME
-        assert rel_fro(b.outputs[2 * li + 1].cpu().numpy(), Is.cpu().numpy()) < SAME
+        assert rel_err(b.outputs[2 * li].cpu().numpy(), Ss.cpu().numpy()) < SAME
+        assert rel_err(b.outputs[2 * li + 1].cpu().numpy(), Is.cpu().numpy()) < SAME
         assert not torch.equal(b.outputs[2 * li], first[2 * li])
     b.close()
 
@@ -222,8 +222,8 @@ def test_batch_on_side_stream():
     side.synchronize()
     for li, lat in enumerate(lats):
         S_o, I_o = lat.oracle_parts(k)
-        assert rel_fro(b.outputs[2 * li].cpu().numpy(), S_o) < TOL
-        assert rel_fro(b.outputs[2 * li + 1].cpu().numpy(), I_o) < TOL
+        assert rel_err(b.outputs[2 * li].cpu().numpy(), S_o) < TOL
+        assert rel_err(b.outputs[2 * li + 1].cpu().numpy(), I_o) < TOL
     b.close()
 
 

@@ -23,7 +23,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -73,7 +73,7 @@ def test_batch_fullsize_meson_source(batch):
     G_tf, eta = _host(js["G"]), _host(js["eta"])
     S_o = oracle.spectator_meson(G_tf, eta, L, k, r=r)
     S = W.batch.outputs[0].cpu().numpy()
-    err = rel_fro(S, S_o)
+    err = rel_err(S, S_o)
     _say(f"batch meson 24^3: spectator rel err {err:.2e}")
     assert err < TOL
     I = W.batch.outputs[1].cpu().numpy()
@@ -81,11 +81,11 @@ def test_batch_fullsize_meson_source(batch):
     for tl in (0, len(s["taus"]) - 1):
         tau = s["taus"][tl]
         I_o = oracle.insertion({tau: _host(ji["G_t"][tau])}, {tau: _host(ji["s_t"][tau])}, [tau], L, T, k, r=r)
-        err = rel_fro(I[:, tl], I_o[:, 0])
+        err = rel_err(I[:, tl], I_o[:, 0])
         _say(f"batch meson 24^3: insertion tau={tau} rel err {err:.2e}")
         assert err < TOL
         C_o = oracle.combine(S_o, I_o, pairs=pairs)
-        err = rel_fro(C[:, tl], C_o[:, 0])
+        err = rel_err(C[:, tl], C_o[:, 0])
         _say(f"batch meson 24^3: combine tau={tau} ({len(pairs)} pairs) rel err {err:.2e}")
         assert err < TOL
 
@@ -102,12 +102,12 @@ def test_batch_fullsize_nucleon_source(batch):
     sel_m = [0, 1, 30, 60, 92]
     want = oracle.spectator_baryon(_host(jud["G1"]), _host(jud["G2"]), _host(jud["eta"])[3:4], L, k[sel_m], r=r)
     SB = W.batch.outputs[j0 + 1].cpu().numpy()
-    err = rel_fro(SB[3:4, sel_m], want)
+    err = rel_err(SB[3:4, sel_m], want)
     _say(f"batch nucleon 48^3: (u,d) spectator (noise 3, 5 momenta) rel err {err:.2e}")
     assert err < TOL
     tau = s["taus"][0]
     I_o = oracle.insertion({tau: _host(jd["G_t"][tau])}, {tau: _host(jd["s_t"][tau])[2:4]}, [tau], L, T, k, r=r)
     I = W.batch.outputs[j0 + 3].cpu().numpy()
-    err = rel_fro(I[2:4, 0], I_o[:, 0])
+    err = rel_err(I[2:4, 0], I_o[:, 0])
     _say(f"batch nucleon 48^3: d insertion tau={tau} (noise 2, 3) rel err {err:.2e}")
     assert err < TOL

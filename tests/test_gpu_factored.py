@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import Workload, rel_fro
+from helpers import Workload, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,8 +70,8 @@ def test_factored_parts(case, variant):
     S_o = oracle.spectator_meson(w.G1, w.eta, L, k, r=r)
     SB_o = oracle.spectator_baryon(w.G1, w.G1b, w.eta, L, k, r=r)
     I_o = oracle.insertion(w.G3, w.s, taus, L, T, k, r=r, U_t=w.U, n_ops=5)
-    es, eb = rel_fro(S, S_o), rel_fro(SB, SB_o)
-    ei = [rel_fro(I[:, j, op], I_o[:, j, op]) for j in range(len(taus)) for op in range(5)]
+    es, eb = rel_err(S, S_o), rel_err(SB, SB_o)
+    ei = [rel_err(I[:, j, op], I_o[:, j, op]) for j in range(len(taus)) for op in range(5)]
     _say(f"factored case {case} variant {variant} L={L}: meson {es:.2e} baryon {eb:.2e} insertion max {max(ei):.2e}")
     assert es < tol and eb < tol and max(ei) < tol
 
@@ -85,8 +85,8 @@ def test_factored_falls_back_for_wide_momentum_lists():
     geom = c3pt.Geom(L, T, r=(2, 1, 0), proj=c3pt.PROJ_FACTORED)
     S = c3pt.spectator_meson(_t(w.G1, True), _t(w.eta, True), k, geom).cpu().numpy()
     I = c3pt.insertion({1: _t(w.G3[1], True)}, {1: _t(w.s[1], True)}, [1], k, geom).cpu().numpy()
-    assert rel_fro(S, oracle.spectator_meson(w.G1, w.eta, L, k, r=(2, 1, 0))) < 1e-5
-    assert rel_fro(I, oracle.insertion(w.G3, w.s, [1], L, T, k, r=(2, 1, 0))) < 1e-5
+    assert rel_err(S, oracle.spectator_meson(w.G1, w.eta, L, k, r=(2, 1, 0))) < 1e-5
+    assert rel_err(I, oracle.insertion(w.G3, w.s, [1], L, T, k, r=(2, 1, 0))) < 1e-5
 
 
 def test_factored_is_deterministic():

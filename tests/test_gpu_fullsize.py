@@ -17,7 +17,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,21 +53,21 @@ def test_meson32_step_sampled(proj, name):
                        U_t={t: _up(v) for t, v in U.items()}, n_ops=5)
     torch.cuda.synchronize()
     S_o = oracle.spectator_meson(G1, eta, L, k)
-    err = rel_fro(S.cpu().numpy(), S_o)
+    err = rel_err(S.cpu().numpy(), S_o)
     _say(f"meson32 {name}: spectator rel err {err:.2e}")
     assert err < TOL32
     Ih = I.cpu().numpy()
     for tau in (0, 8, 16):
         I_o = oracle.insertion(G3, s, [tau], L, T, k, U_t=U, n_ops=5)
         for op in range(5):
-            e = rel_fro(Ih[:, tau, op], I_o[:, 0, op])
+            e = rel_err(Ih[:, tau, op], I_o[:, 0, op])
             _say(f"meson32 {name}: insertion tau={tau} op={op} rel err {e:.2e}")
             assert e < TOL32
     # combine on sampled pairs, from the oracle's parts (checks the full-size launch shape)
     pairs = [(0, 0), (40, 40), (80, 3), (0, 80)]
     I8 = oracle.insertion(G3, s, [8], L, T, k, U_t=U, n_ops=5)
     C = c3pt.combine(torch.from_numpy(S_o).cuda(), torch.from_numpy(I8).cuda(), pairs=pairs).cpu().numpy()
-    assert rel_fro(C, oracle.combine(S_o, I8, pairs=pairs)) < 1e-12
+    assert rel_err(C, oracle.combine(S_o, I8, pairs=pairs)) < 1e-12
 
 
 def test_meson32_symmetric_sampled():
@@ -91,7 +91,7 @@ def test_meson32_symmetric_sampled():
     for tau in (0, 16):
         I_o = oracle.insertion(G3, s, [tau], L, T, k, U_t=U, n_ops=9)
         for op in range(9):
-            e = rel_fro(I[:, tau, op], I_o[:, 0, op])
+            e = rel_err(I[:, tau, op], I_o[:, 0, op])
             _say(f"meson32 symmetric: tau={tau} op={op} rel err {e:.2e}")
             assert e < TOL32
 
@@ -109,7 +109,7 @@ def test_nucleon48_split_sampled(proj, name):
     SB = c3pt.spectator_baryon(_up(Gu), _up(Gd), _up(eta), k, geom).cpu().numpy()
     sel_m = [0, 1, 30, 92, 122]
     want = oracle.spectator_baryon(Gu, Gd, eta[3:4], L, k[sel_m])
-    err = rel_fro(SB[3:4, sel_m], want)
+    err = rel_err(SB[3:4, sel_m], want)
     _say(f"nucleon48 {name}: baryon spectator (noise 3, 5 momenta) rel err {err:.2e}")
     assert err < TOL32
     tau = 7
@@ -117,6 +117,6 @@ def test_nucleon48_split_sampled(proj, name):
     s7 = syn.round_to_c64(syn.solution_slice(L, N, cfg, tau))
     I = c3pt.insertion({tau: _up(G7)}, {tau: _up(s7)}, [tau], k, geom).cpu().numpy()
     I_o = oracle.insertion({tau: G7}, {tau: s7}, [tau], L, T, k)
-    err = rel_fro(I, I_o)
+    err = rel_err(I, I_o)
     _say(f"nucleon48 {name}: insertion tau={tau} rel err {err:.2e}")
     assert err < TOL32

@@ -8,7 +8,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,7 +36,7 @@ def test_gamma_meson_matches_oracle(counts):
     torch.cuda.synchronize()
     want = oracle.gamma_project_meson(C, *mats)
     assert got.shape == want.shape
-    assert rel_fro(got.cpu().numpy(), want) < 1e-12
+    assert rel_err(got.cpu().numpy(), want) < 1e-12
 
 
 @pytest.mark.parametrize("channel", ["d", "u"])
@@ -57,7 +57,7 @@ def test_gamma_nucleon_matches_oracle(channel, custom):
     torch.cuda.synchronize()
     want = oracle.gamma_project_nucleon(C, channel, **kw)
     assert got.shape == want.shape
-    assert rel_fro(got.cpu().numpy(), want) < 1e-12
+    assert rel_err(got.cpu().numpy(), want) < 1e-12
 
 
 def test_gamma_meson_after_two_sink_measurement():
@@ -85,8 +85,8 @@ def test_gamma_meson_after_two_sink_measurement():
     ch_b = c3pt.gamma_meson(res["bwd"])
     torch.cuda.synchronize()
     want = oracle.two_sink_meson(G1f, eta_f, tf, G1b, eta_b, tb, ts, G3, s, L, T, k, pairs=pairs)
-    assert rel_fro(ch_f.cpu().numpy(), oracle.gamma_project_meson(want["fwd"])) < 1e-12
-    assert rel_fro(ch_b.cpu().numpy(), oracle.gamma_project_meson(want["bwd"])) < 1e-12
+    assert rel_err(ch_f.cpu().numpy(), oracle.gamma_project_meson(want["fwd"])) < 1e-12
+    assert rel_err(ch_b.cpu().numpy(), oracle.gamma_project_meson(want["bwd"])) < 1e-12
 
 
 def test_gamma_rejects_bad_arguments():

@@ -12,7 +12,7 @@ import pytest
 import c3pt_synth as syn
 import oracle
 from oracle import brute
-from helpers import Workload, rel_fro, per_slice_rel
+from helpers import Workload, rel_err, per_slice_rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -54,7 +54,7 @@ def test_spectator_meson(L, N, n2, reduced, r):
     k = oracle.momenta(n2)
     got = c.spectator_meson(dev(w.G1, reduced), dev(w.eta, reduced), k, c.Geom(L, 8, r)).cpu().numpy()
     want = oracle.spectator_meson(w.G1, w.eta, L, k, r)
-    err = rel_fro(got, want)
+    err = rel_err(got, want)
     assert err < (TOL32 if reduced else TOL64), err
 
 
@@ -71,7 +71,7 @@ def test_spectator_baryon(L, N, n2, reduced):
     got = c.spectator_baryon(dev(w.G1, reduced), dev(w.G1b, reduced), dev(w.eta, reduced), k,
                              c.Geom(L, 8, r)).cpu().numpy()
     want = oracle.spectator_baryon(w.G1, w.G1b, w.eta, L, k, r)
-    err = rel_fro(got, want)
+    err = rel_err(got, want)
     assert err < (TOL32 if reduced else TOL64), err
 
 
@@ -98,7 +98,7 @@ def test_insertion(L, T, N, taus, n_ops, n2, reduced):
     errs = per_slice_rel(got, want)
     assert max(errs) < (TOL32 if reduced else TOL64), errs
     for op in range(n_ops):
-        assert rel_fro(got[:, :, op], want[:, :, op]) < (TOL32 if reduced else TOL64)
+        assert rel_err(got[:, :, op], want[:, :, op]) < (TOL32 if reduced else TOL64)
 
 
 # ---------------------------------------------------------------------------
@@ -115,12 +115,12 @@ def test_combine_from_oracle_parts():
     w = rng.random(N)
     Sd, SBd, Id = (torch.from_numpy(x).cuda() for x in (S, SB, I))
     got = c.combine(Sd, Id, w=w).cpu().numpy()
-    assert rel_fro(got, oracle.combine(S, I, w=w)) < TOL64
+    assert rel_err(got, oracle.combine(S, I, w=w)) < TOL64
     pairs = [(3, 2), (0, 0), (1, 2), (3, 2)]
     got = c.combine(SBd, Id, pairs=pairs, op_begin=1, op_end=4).cpu().numpy()
-    assert rel_fro(got, oracle.combine(SB, I, pairs=pairs, op_begin=1, op_end=4)) < TOL64
+    assert rel_err(got, oracle.combine(SB, I, pairs=pairs, op_begin=1, op_end=4)) < TOL64
     got = c.combine(Sd, Id).cpu().numpy()   # default weights 1/N
-    assert rel_fro(got, oracle.combine(S, I)) < TOL64
+    assert rel_err(got, oracle.combine(S, I)) < TOL64
 
 
 def test_end_to_end_against_bruteforce_trace():
@@ -144,7 +144,7 @@ def test_end_to_end_against_bruteforce_trace():
         for it, tau in enumerate([0, 1, 2]):
             Ghat = brute.stochastic_all_to_all(w.s[tau], w.eta, wts)
             Cb = brute.meson_spin_open(w.G1, Ghat, w.G3[tau], L, kp[p], q[qq], r)
-            assert rel_fro(C[j, it, 0].reshape((4,) * 6), Cb) < TOL64
+            assert rel_err(C[j, it, 0].reshape((4,) * 6), Cb) < TOL64
 
 
 # ---------------------------------------------------------------------------
@@ -192,7 +192,7 @@ def test_runs_on_a_side_stream():
     with torch.cuda.stream(s):
         got = c.spectator_meson(G, e, k, c.Geom(L, 8))
     s.synchronize()
-    assert rel_fro(got.cpu().numpy(), oracle.spectator_meson(w.G1, w.eta, L, k)) < TOL32
+    assert rel_err(got.cpu().numpy(), oracle.spectator_meson(w.G1, w.eta, L, k)) < TOL32
 
 
 # ---------------------------------------------------------------------------
@@ -226,9 +226,9 @@ def test_every_variant_and_precision(cls, n2):
                     c.set_variant(kind, mode, cls, v)
                     _say(f"variant kind={kind} mode={mname} class={cls} v={v}")
                     if kind == 0:
-                        errs = [rel_fro(c.spectator_meson(G1, eta, k, geom).cpu().numpy(), want_s)]
+                        errs = [rel_err(c.spectator_meson(G1, eta, k, geom).cpu().numpy(), want_s)]
                     elif kind == 1:
-                        errs = [rel_fro(c.spectator_baryon(G1, G1b, eta, k, geom).cpu().numpy(), want_b)]
+                        errs = [rel_err(c.spectator_baryon(G1, G1b, eta, k, geom).cpu().numpy(), want_b)]
                     else:
                         got = c.insertion(Gd, sd, taus, k, geom, U_t=Ud, n_ops=5).cpu().numpy()
                         errs = per_slice_rel(got, want_i)

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import Workload, rel_fro
+from helpers import Workload, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -107,9 +107,9 @@ def test_serve_mix_matches_oracle_and_alone(proj, name):
     for q, got in zip(reqs, mix):
         S, I, C = q.oracle()
         for p in range(len(S)):
-            es = rel_fro(got["spec"][p].cpu().numpy(), S[p])
-            ei = rel_fro(got["ins"][p].cpu().numpy(), I[p])
-            ec = rel_fro(got["comb"][p].cpu().numpy(), C[p])
+            es = rel_err(got["spec"][p].cpu().numpy(), S[p])
+            ei = rel_err(got["ins"][p].cpu().numpy(), I[p])
+            ec = rel_err(got["comb"][p].cpu().numpy(), C[p])
             _say(f"serve {name}: {q.kind} {q.L} part {p}: spectator {es:.2e} insertion {ei:.2e} combine {ec:.2e}")
             assert es < TOL and ei < TOL and ec < TOL
     for i in ids:
@@ -162,8 +162,8 @@ def test_serve_admission_by_memory():
     torch.cuda.synchronize()
     for q, i in zip(reqs, ids):
         S, I, C = q.oracle()
-        assert rel_fro(done[i]["ins"][0].cpu().numpy(), I[0]) < TOL
-        assert rel_fro(done[i]["comb"][0].cpu().numpy(), C[0]) < TOL
+        assert rel_err(done[i]["ins"][0].cpu().numpy(), I[0]) < TOL
+        assert rel_err(done[i]["comb"][0].cpu().numpy(), C[0]) < TOL
     sv.close()
 
 

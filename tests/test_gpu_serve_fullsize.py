@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,17 +70,17 @@ def _meson_check(q, got, taus_checked, name):
     tf = q["t_f"]
     taus = [(q["t_src"] + i) % T for i in range((tf - q["t_src"]) % T + 1)]
     S_o = oracle.spectator_meson(_host(q["G_t"][tf]), _host(q["eta"]), L, k, r=r)
-    err = rel_fro(got["spec"][0], S_o)
+    err = rel_err(got["spec"][0], S_o)
     _say(f"{name}: spectator rel err {err:.2e}")
     assert err < TOL
     for tl in taus_checked:
         tau = taus[tl]
         I_o = oracle.insertion({tau: _host(q["G_t"][tau])}, {tau: _host(q["s_t"][tau])}, [tau], L, T, k, r=r)
-        err = rel_fro(got["ins"][0][:, tl], I_o[:, 0])
+        err = rel_err(got["ins"][0][:, tl], I_o[:, 0])
         _say(f"{name}: insertion tau={tau} rel err {err:.2e}")
         assert err < TOL
         C_o = oracle.combine(S_o, I_o, pairs=q["pairs"])
-        err = rel_fro(got["comb"][0][:, tl], C_o[:, 0])
+        err = rel_err(got["comb"][0][:, tl], C_o[:, 0])
         _say(f"{name}: combine tau={tau} ({len(q['pairs'])} pairs) rel err {err:.2e}")
         assert err < TOL
 
@@ -99,12 +99,12 @@ def test_serve_fullsize_nucleon64(served):
     tf = q["t_f"]
     sel_m = [0, 1, 7, 20, len(k) - 1]
     want = oracle.spectator_baryon(_host(q["G_t"][tf]), _host(q["G2_t"][tf]), _host(q["eta"])[1:2], L, k[sel_m], r=r)
-    err = rel_fro(got["spec"][1][1:2, sel_m], want)
+    err = rel_err(got["spec"][1][1:2, sel_m], want)
     _say(f"serve nucleon 64^3: (u,d) spectator (noise 1, 5 momenta) rel err {err:.2e}")
     assert err < TOL
     tau = q["t_src"]
     I_o = oracle.insertion({tau: _host(q["G2_t"][tau])}, {tau: _host(q["s_t"][tau])}, [tau], L, T, k, r=r)
-    err = rel_fro(got["ins"][1][:, 0], I_o[:, 0])
+    err = rel_err(got["ins"][1][:, 0], I_o[:, 0])
     _say(f"serve nucleon 64^3: d insertion tau={tau} rel err {err:.2e}")
     assert err < TOL
 

@@ -9,7 +9,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -55,7 +55,7 @@ def test_smear_matches_oracle(case):
     got = fn(fd, _dev(U, reduced), geom, kappa, n_iter, out=fd if in_place else None)
     torch.cuda.synchronize()
     want = oracle.smear(f, U, L, kappa, n_iter, n_outer, n_inner)
-    err = rel_fro(got.cpu().numpy(), want)
+    err = rel_err(got.cpu().numpy(), want)
     _say(f"   error {err:.2e}")
     assert err < tol
 
@@ -69,7 +69,7 @@ def test_smear_identities():
     geom = c3pt.Geom(L, 1)
     vd = _dev(v, False)
     assert torch.equal(c3pt.smear_vectors(vd, U, geom, 0.3, 0), vd)
-    assert rel_fro(c3pt.smear_vectors(vd, U, geom, 0.0, 6).cpu().numpy(), v) < 1e-15
+    assert rel_err(c3pt.smear_vectors(vd, U, geom, 0.0, 6).cpu().numpy(), v) < 1e-15
 
 
 def test_smear_rejects_bad_arguments():

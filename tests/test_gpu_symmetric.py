@@ -9,7 +9,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def test_symmetric_derivative_matches_oracle(case):
     torch.cuda.synchronize()
     got = got.cpu().numpy()
     want = oracle.insertion(G, s, taus, L, T, k, r=r, U_t=U, n_ops=9)
-    errs = [rel_fro(got[:, :, op], want[:, :, op]) for op in range(9)]
+    errs = [rel_err(got[:, :, op], want[:, :, op]) for op in range(9)]
     _say(f"   errors per op {['%.1e' % e for e in errs]}")
     assert max(errs) < tol
 
@@ -83,7 +83,7 @@ def test_symmetric_two_sink_matches_oracle():
     torch.cuda.synchronize()
     want = oracle.two_sink_meson(G1f, eta_f, tf, G1b, eta_b, tb, ts, G, s, L, T, k, U_t=U, n_ops=9, pairs=pairs)
     for key in ("ins", "fwd", "bwd"):
-        assert rel_fro(res[key].cpu().numpy(), want[key]) < 1e-12
+        assert rel_err(res[key].cpu().numpy(), want[key]) < 1e-12
 
 
 def test_symmetric_rejects_unsupported():

@@ -10,7 +10,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def test_two_derivatives_match_oracle(case):
     torch.cuda.synchronize()
     got = got.cpu().numpy()
     want = oracle.insertion(G, s, taus, L, T, k, r=r, U_t=U, n_ops=21)
-    errs = [rel_fro(got[:, :, op], want[:, :, op]) for op in range(21)]
+    errs = [rel_err(got[:, :, op], want[:, :, op]) for op in range(21)]
     _say(f"   max error {max(errs):.1e} (op {int(np.argmax(errs))})")
     assert max(errs) < tol
 
@@ -80,7 +80,7 @@ def test_symmetrized_two_derivatives_match_oracle(case):
     torch.cuda.synchronize()
     got = got.cpu().numpy()
     want = oracle.insertion(G, s, taus, L, T, k, r=r, U_t=U, n_ops=37)
-    errs = [rel_fro(got[:, :, op], want[:, :, op]) for op in range(37)]
+    errs = [rel_err(got[:, :, op], want[:, :, op]) for op in range(37)]
     _say(f"   max error {max(errs):.1e} (op {int(np.argmax(errs))})")
     assert max(errs) < tol
 

@@ -9,7 +9,7 @@ import pytest
 
 import c3pt_synth as syn
 import oracle
-from helpers import rel_fro
+from helpers import rel_err
 from oracle import brute
 
 torch = pytest.importorskip("torch")
@@ -73,7 +73,7 @@ def test_two_sink_matches_oracle(case):
     want = oracle.two_sink_meson(G1f, eta_f, tf, G1b, eta_b, tb, ts, G3, s, L, T, k, r=r, U_t=U, n_ops=n_ops,
                                  w=w, pairs=pairs)
     assert res["taus"] == want["taus"]
-    errs = {key: rel_fro(res[key].cpu().numpy(), want[key]) for key in ("spec", "ins", "fwd", "bwd")}
+    errs = {key: rel_err(res[key].cpu().numpy(), want[key]) for key in ("spec", "ins", "fwd", "bwd")}
     _say(f"   errors {errs}")
     assert max(errs.values()) < tol
 
@@ -110,10 +110,10 @@ def test_two_sink_full_dilution_equals_direct_trace():
     for j, (p, q) in enumerate(pairs):
         for it, t in enumerate([1, 2, 3]):
             Cb = brute.meson_spin_open(G1f, G2f[t], G3[t], L, k[p], k[q])
-            assert rel_fro(fwd[j, it, 0].reshape((4,) * 6), Cb) < 1e-12
+            assert rel_err(fwd[j, it, 0].reshape((4,) * 6), Cb) < 1e-12
         for it, t in enumerate([3, 4, 5]):
             Cb = brute.meson_spin_open(G1b, G2b[t], G3[t], L, k[p], k[q])
-            assert rel_fro(bwd[j, it, 0].reshape((4,) * 6), Cb) < 1e-12
+            assert rel_err(bwd[j, it, 0].reshape((4,) * 6), Cb) < 1e-12
 
 
 def test_two_sink_rejects_bad_arguments():

@@ -83,3 +83,35 @@ def current(point, flavour, spins, colour, group="J"):
     """qbar^s1 Gamma_{s1 s2} q^s2 with one colour index (summed)."""
     s1, s2 = spins
     return [Field(True, flavour, point, s1, colour, group), Field(False, flavour, point, s2, colour, group)]
+
+
+def barred_conjugate(fields, coeffs, free_spin, bar_spin, gamma4):
+    """Fields and coefficients of Obar = O^dag gamma4 for an operator
+    O_{free_spin} = coeffs * prod(fields), built field by field from
+    qbar = q^dag gamma4 alone:
+
+    * the product is reversed and every coefficient is complex conjugated
+      ((AB)^dag = B^dag A^dag);
+    * a quark field q_s becomes q^dag_s = sum_t qbar_t (gamma4^-1)_{t s};
+    * an antiquark field qbar_s becomes (qbar_s)^dag = sum_t conj(gamma4)_{t s} q_t;
+    * the free spin is barred: Obar_{bar_spin} = sum_g (O_g)^dag gamma4_{g, bar_spin}
+      (free_spin None: a scalar operator, whose conjugate O^dag is returned).
+
+    No matrix of the hadron operators (A, Gamma) is transformed as a whole:
+    whatever the correct creation matrix is follows from the contraction."""
+    inv4 = np.linalg.inv(gamma4)
+    out_f = []
+    out_c = [(np.conj(arr), labels) for arr, labels in coeffs]
+    for f in reversed(fields):
+        t = f.spin + "~"
+        out_f.append(Field(not f.bar, f.flavour, f.point, t, f.colour, f.group))
+        out_c.append((np.conj(gamma4) if f.bar else inv4, (t, f.spin)))
+    if free_spin is not None:
+        out_c.append((gamma4, (free_spin, bar_spin)))
+    return out_f, out_c
+
+
+def bilinear(point, flavour_bar, flavour, spins, colour, group):
+    """qbar_{flavour_bar}^s1 M_{s1 s2} q_{flavour}^s2 (one colour, summed): the fields."""
+    s1, s2 = spins
+    return [Field(True, flavour_bar, point, s1, colour, group), Field(False, flavour, point, s2, colour, group)]
