@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 20; batch64: 3)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 3; batch64: 1)")
-    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "twosink32", "batch64", "serve"], default="meson32")
+    ap.add_argument("--workload", choices=["meson32", "meson8", "nucleon48", "twosink32", "batch64", "serve"],
+                    default="nucleon48")
     ap.add_argument("--n2", type=int, default=None, help="momentum cutoff |k|^2 (nucleon48: 8 or 9)")
     ap.add_argument("--no-baryon", action="store_true", help="meson32: drop the nucleon spectator")
     ap.add_argument("--analysis", action="store_true",
@@ -474,18 +475,30 @@ class Nucleon48(Meson32):
         return "proj_spectator_baryon", 8.0 * n_mom * V3 * cols
 
     def cpu_sample(self, k, n_slices):
+        """One noise vector of the (u,u) nucleon spectator, the u insertion on
+        one timeslice with all 8 noise vectors, and the combine of that noise
+        vector's spectator with its insertion on the step's pairs."""
         import c3pt_synth as syn
         import oracle
         L = self.L
         tau = self.taus[len(self.taus) // 2]
-        Gu = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, tau))
-        s = syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, tau))
+        Gf = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, self.t_f))
+        ns, nt = 2, 2
+        eta = syn.round_to_c64(syn.z2z2_noise(L, ns, self.cfg, self.t_f))
+        ts = self.taus[len(self.taus) // 2: len(self.taus) // 2 + nt]
+        Gu = {t: syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in ts}
+        s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in ts}
+        pairs = pairs_diag_or_zero(len(k))
         t0 = time.perf_counter()
-        oracle.insertion({tau: Gu}, {tau: s}, [tau], L, self.T, k)
+        S = oracle.spectator_baryon(Gf, Gf, eta, L, k)
+        I = oracle.insertion(Gu, s, ts, L, self.T, k)
+        oracle.combine(S, I[:ns], pairs=pairs)
         dt = time.perf_counter() - t0
-        units = self.N * int(np.prod(L)) * len(k)
-        return units, dt, (f"FP64 numpy oracle: one insertion timeslice (u), full 48^3, N=8, {len(k)} momenta; "
-                           f"nucleon spectators and combine not in the sample")
+        V3 = int(np.prod(L))
+        units = ns * V3 * len(k) + self.N * nt * V3 * len(k)
+        return units, dt, (f"FP64 numpy oracle: (u,u) nucleon spectator with {ns} of 8 noise vectors, u "
+                           f"insertion on {nt} of 15 timeslices with N=8, and the combine of those {ns} noise "
+                           f"vectors on {len(pairs)} pairs; full 48^3 slices, {len(k)} momenta")
 
 class TwoSink32(Meson32):
     """Forward and backward meson diagrams with time-partitioned noise in the
@@ -1040,10 +1053,56 @@ def serve_main(args):
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 oracle on a host sample")
-        W = Meson32(argparse.Namespace(no_baryon=True))
-        res["cpu_baseline"] = cpu_baseline(W, c3pt.momentum_list(6), 2)
+        log("[bench] timing the FP64 oracle on served requests")
+        res["cpu_baseline"] = serve_cpu_baseline(min(lattices), momenta)
     print(json.dumps(res), flush=True)
+
+
+def serve_cpu_baseline(L, momenta, budget_s=12.0):
+    """The FP64 oracle on whole requests of the seeded serving draw on the
+    smallest resident lattice, one after the other until about budget_s of
+    host time: spectator(s) at t_f, insertion(s) on every timeslice from t_src
+    to t_f, and the combines, as the server computes them.  Inputs are drawn
+    on the host with the pool's distributions and shapes."""
+    import c3pt_synth as syn
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    T = SERVE_LATTICES[L]
+    Ls = (L, L, L)
+    specs = [sp for sp in serve_draw(400, [L], seed=3)]
+    Gu = {t: syn.round_to_c64(syn.propagator_slice(Ls, 5, syn.FIELD_G3, t)) for t in range(T)}
+    Gd = {t: syn.round_to_c64(syn.propagator_slice(Ls, 5, syn.FIELD_G1, t)) for t in range(T)}
+    s_all = {t: syn.round_to_c64(syn.solution_slice(Ls, ServePool.N_MAX, 5, t)) for t in range(T)}
+    eta_all = syn.round_to_c64(syn.z2z2_noise(Ls, ServePool.N_MAX, 5, 0))
+    done, units, dt = 0, 0, 0.0
+    for sp in specs:
+        k = oracle.momenta(sp["n2"])
+        N, r = sp["N"], sp["r"]
+        taus = [(sp["t_src"] + j) % T for j in range(sp["n_tau"])]
+        s = {t: s_all[t][:N] for t in taus}
+        eta = eta_all[:N]
+        pairs = pairs_diag_or_zero(len(k))
+        t0 = time.perf_counter()
+        if sp["kind"] == "nucleon":
+            for G2, Gi in ((Gu, Gd), (Gd, Gu)):
+                S = oracle.spectator_baryon(Gu[sp["t_f"]], G2[sp["t_f"]], eta, Ls, k, r=r)
+                oracle.combine(S, oracle.insertion(Gi, s, taus, Ls, T, k, r=r), pairs=pairs)
+        else:
+            S = oracle.spectator_meson(Gu[sp["t_f"]], eta, Ls, k, r=r)
+            oracle.combine(S, oracle.insertion(Gu, s, taus, Ls, T, k, r=r), pairs=pairs)
+        dt += time.perf_counter() - t0
+        units += serve_units(sp, momenta)
+        done += 1
+        if dt > budget_s:
+            break
+    return {"value": units / dt, "unit": "site*momenta/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 numpy oracle on {done} whole requests of the seeded serving draw on {L}^3x{T} "
+                       f"(spectators, insertions on every timeslice t_src..t_f, combines); {units:.3g} units "
+                       f"in {dt:.1f} s"), "seconds": dt}
 
 
 
