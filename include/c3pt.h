@@ -153,6 +153,30 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                    const int* k, int n_mom, void* out);
 
 /*
+ * c3pt_insertion without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, layouts and results as c3pt_insertion,
+ * restricted to n_ops 1 or 5, geom->proj == C3PT_PROJ_FACTORED and momentum
+ * lists the factored projection takes (else C3PT_EUNSUPPORTED).
+ * Its FP32 (FP64) partial sums and the factor plan live in one fixed device
+ * array of C3PT_NOALLOC_SCRATCH_BYTES, which each GPU the library runs on
+ * holds from the first call until the process ends; the call runs its
+ * timeslices in launch groups whose partial sums fit the array.  A request
+ * whose single timeslice needs more is rejected with C3PT_EINVAL before
+ * anything is enqueued (its message gives both sizes).  The call enqueues
+ * only kernels: no hipMalloc, hipFree, host copy or event.
+ * Every call on one GPU shares that GPU's array, whose contents are what the
+ * last call left: calls that overlap on one GPU (different streams, or host
+ * threads) race and must be ordered by the caller.  c3pt_noalloc_scratch_bytes()
+ * returns the array's size.
+ */
+#define C3PT_NOALLOC_SCRATCH_BYTES (128u << 20)
+unsigned long long c3pt_noalloc_scratch_bytes(void);
+int c3pt_insertion_noalloc(const c3pt_geom* geom, const void* const* G_t, const void* const* s_t,
+                           int n_noise, const int* taus, int n_tau, const void* const* U_t, int n_ops,
+                           const int* k, int n_mom, void* out);
+
+/*
  * Noise-weighted product of spectator and insertion (Eq. (5) inserted into
  * Eq. (8)), summing the source colour shared by the two parts (the delta of
  * Eq. (1)):

@@ -49,7 +49,7 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
             "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
             "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
             "c3pt_server_poll", "c3pt_server_result", "c3pt_server_release", "c3pt_server_info",
-            "c3pt_server_destroy")
+            "c3pt_server_destroy", "c3pt_insertion_noalloc", "c3pt_noalloc_scratch_bytes")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
 MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4}   # "fac": variant slot of the factored projection
@@ -110,6 +110,10 @@ def _load():
     lib.c3pt_spectator_baryon.argtypes = [gp, vp, vp, vp, i, ip, i, vp]
     lib.c3pt_insertion.argtypes = [gp, ctypes.POINTER(vp), ctypes.POINTER(vp), i, ip, i,
                                    ctypes.POINTER(vp), i, ip, i, vp]
+    lib.c3pt_insertion_noalloc.argtypes = lib.c3pt_insertion.argtypes
+    lib.c3pt_insertion_noalloc.restype = ctypes.c_int
+    lib.c3pt_noalloc_scratch_bytes.argtypes = []
+    lib.c3pt_noalloc_scratch_bytes.restype = ctypes.c_ulonglong
     lib.c3pt_combine.argtypes = [vp, i, vp, i, i, i, i, i, i, i, ctypes.POINTER(ctypes.c_double), ip, i,
                                  vp, vp]
     lib.c3pt_two_sink_meson.argtypes = [gp, vp, vp, i, vp, vp, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -272,6 +276,21 @@ def c3pt_insertion(G_t, s_t, taus, k, geom: Geom, U_t=None, n_ops: int = 1, out=
     G_t, s_t, U_t: dict or list indexed by timeslice t (missing / None allowed
     where not needed); G_t[t] [12,12,V3], s_t[t] [N,12,V3], U_t[t] [4,3,3,V3].
     Returns [N, n_tau, n_ops, n_mom, 192] complex128."""
+    return _insertion_call(lib.c3pt_insertion, G_t, s_t, taus, k, geom, U_t, n_ops, out)
+
+
+def c3pt_insertion_noalloc(G_t, s_t, taus, k, geom: Geom, U_t=None, n_ops: int = 1, out=None) -> torch.Tensor:
+    """c3pt_insertion through the entry point that allocates no device memory
+    in the library (fixed scratch array; n_ops 1 or 5, factored projection).
+    With out given, the call itself allocates nothing anywhere."""
+    return _insertion_call(lib.c3pt_insertion_noalloc, G_t, s_t, taus, k, geom, U_t, n_ops, out)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib.c3pt_noalloc_scratch_bytes())
+
+
+def _insertion_call(fn, G_t, s_t, taus, k, geom: Geom, U_t, n_ops: int, out):
     V3, T = geom.V3, int(geom.T)
     taus = [int(t) for t in taus]
     first = (s_t[taus[0]])
@@ -284,8 +303,8 @@ def c3pt_insertion(G_t, s_t, taus, k, geom: Geom, U_t=None, n_ops: int = 1, out=
     out = _out(out, (N, len(taus), n_ops, n_mom, 192), first)
     tau_arr = (ctypes.c_int * len(taus))(*taus)
     g = geom.c(dtype)
-    _check(lib.c3pt_insertion(ctypes.byref(g), Gtab, stab, N, tau_arr, len(taus),
-                              Utab if Utab is not None else None, n_ops, kp, n_mom, out.data_ptr()))
+    _check(fn(ctypes.byref(g), Gtab, stab, N, tau_arr, len(taus), Utab if Utab is not None else None, n_ops, kp,
+              n_mom, out.data_ptr()))
     return out
 
 
@@ -446,6 +465,7 @@ def smear_vectors(v: torch.Tensor, U: torch.Tensor, geom: Geom, kappa: float, n_
 spectator_meson = c3pt_spectator_meson
 spectator_baryon = c3pt_spectator_baryon
 insertion = c3pt_insertion
+insertion_noalloc = c3pt_insertion_noalloc
 combine = c3pt_combine
 two_sink_meson = c3pt_two_sink_meson
 gamma_meson = c3pt_gamma_meson

@@ -1000,6 +1000,208 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
     return ok();
 }
 
+}  // extern "C"
+
+// ---- the insertion entry point that allocates nothing ----------------------
+// Its partial sums and the factor plan of each launch live in one fixed
+// device array instead of the per-stream scratch and the plan cache.  On the
+// host, `scratch` names a host-side stand-in; its device address, one per
+// GPU, comes from hipGetSymbolAddress at the first call on that GPU and is the
+// only form passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[C3PT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr size_t kNoAllocBytes = (size_t)C3PT_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kNoAllocPlanOff = 0;       // FactorPlan of the running launch
+constexpr size_t kNoAllocPartOff = 4096;    // split-site partial sums
+static_assert(sizeof(FactorPlan) <= kNoAllocPartOff, "the factor plan slot is too small");
+
+std::mutex g_na_mu;
+std::map<int, unsigned char*> g_na_ptr;   // device ordinal -> device address of scratch on it
+
+int noalloc_scratch(unsigned char** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    auto it = g_na_ptr.find(dev);
+    if (it == g_na_ptr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return fail(C3PT_EDEVICE, "hipGetSymbolAddress of the fixed scratch failed: %s", hipGetErrorString(e));
+        }
+        it = g_na_ptr.emplace(dev, (unsigned char*)ptr).first;
+    }
+    *out = it->second;
+    return C3PT_OK;
+}
+
+// The factor plan travels by value in the kernel arguments and is written
+// into the plan slot by one workgroup (no host copy, no allocation).
+struct PlanWords {
+    int w[sizeof(FactorPlan) / sizeof(int)];
+};
+__global__ void __launch_bounds__(256) put_plan_kernel(PlanWords pw, int* dst) {
+    for (int i = threadIdx.x; i < (int)(sizeof(FactorPlan) / sizeof(int)); i += blockDim.x) dst[i] = pw.w[i];
+}
+
+// One launch group of the no-alloc insertion: a momentum group and a block
+// of timeslices, with the chunking of its partial sums.
+struct NoAllocPiece {
+    int mg, j0, nt, chunk_planes, n_chunks;
+    FactorPlan plan;
+};
+}  // namespace
+
+extern "C" {
+
+unsigned long long c3pt_noalloc_scratch_bytes(void) { return (unsigned long long)kNoAllocBytes; }
+
+int c3pt_insertion_noalloc(const c3pt_geom* geom, const void* const* G_t, const void* const* s_t, int n_noise,
+                           const int* taus, int n_tau, const void* const* U_t, int n_ops, const int* k, int n_mom,
+                           void* out) {
+    if (int rc = check_geom(geom)) return rc;
+    if (int rc = check_momenta(k, n_mom)) return rc;
+    if (geom->proj != C3PT_PROJ_FACTORED)
+        return fail(C3PT_EUNSUPPORTED, "c3pt_insertion_noalloc runs the factored projection only (C3PT_PROJ_FACTORED)");
+    if (!G_t || !s_t || !out) return fail(C3PT_EINVAL, "NULL pointer table or output");
+    if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    if (n_tau < 1 || !taus) return fail(C3PT_EINVAL, "empty timeslice list");
+    if (n_ops != 1 && n_ops != 5) return fail(C3PT_EINVAL, "n_ops = %d (c3pt_insertion_noalloc: 1 or 5)", n_ops);
+    if (n_ops > 1 && !U_t) return fail(C3PT_EINVAL, "derivative operators need gauge links");
+    const int T = geom->T;
+    for (int j = 0; j < n_tau; ++j) {
+        const int t = taus[j];
+        if (t < 0 || t >= T) return fail(C3PT_EINVAL, "taus[%d] = %d outside [0, %d)", j, t, T);
+        if (!G_t[t]) return fail(C3PT_EINVAL, "propagator slice %d missing", t);
+        if (!s_t[t]) return fail(C3PT_EINVAL, "stochastic solution slice %d missing", t);
+        if (n_ops > 1) {
+            const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
+            if (!G_t[tn] || !G_t[tp])
+                return fail(C3PT_EINVAL, "propagator slices %d and %d needed around %d", tp, tn, t);
+            if (!U_t[t] || !U_t[tp]) return fail(C3PT_EINVAL, "link slices %d and %d needed", tp, t);
+        }
+    }
+    const bool f64 = geom->dtype == C3PT_C128;
+    const size_t elem = f64 ? sizeof(double2) : sizeof(float2);
+    const auto groups = momentum_groups(n_mom, f64);
+    const size_t cap = kNoAllocBytes - kNoAllocPartOff;
+    // plan every launch before anything is enqueued
+    std::vector<NoAllocPiece> pieces;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        FactorPlan plan;
+        if (!build_factor_plan(geom, +1, k, groups[gi], f64, &plan))
+            return fail(C3PT_EUNSUPPORTED, "the momentum list does not factor (too many distinct k1 or (k1, k2))");
+        const int max_planes =
+            f64 ? geom->L[2] : std::max(1, std::min(geom->L[2], kMaxSitesPerChunkF32 / (geom->L[0] * geom->L[1])));
+        for (int j0 = 0; j0 < n_tau;) {
+            const int nt_max = std::min(kMaxTauPerLaunch, n_tau - j0);
+            int nt = 0, cp = 0, nc = 0;
+            for (int cand = nt_max; cand >= 1 && nt == 0; --cand) {
+                const int ncb = n_noise * cand * n_ops;
+                int c, n;
+                plan_planes(geom->L, ncb, &c, &n);
+                // one timeslice that does not fit: fewer, larger chunks (within the FP32 limit)
+                while (cand == 1 && (size_t)n * ncb * groups[gi].n * kBlockCols * elem > cap && c < max_planes) {
+                    c = std::min(max_planes, 2 * c);
+                    n = (geom->L[2] + c - 1) / c;
+                }
+                if ((size_t)n * ncb * groups[gi].n * kBlockCols * elem <= cap) {
+                    nt = cand;
+                    cp = c;
+                    nc = n;
+                }
+            }
+            if (nt == 0) {
+                int c = max_planes, n = (geom->L[2] + c - 1) / c;
+                const size_t need = (size_t)n * n_noise * n_ops * groups[gi].n * kBlockCols * elem;
+                return fail(C3PT_EINVAL,
+                            "one timeslice needs %zu bytes of partial sums; the fixed scratch of "
+                            "c3pt_insertion_noalloc holds %zu",
+                            need, cap);
+            }
+            pieces.push_back(NoAllocPiece{(int)gi, j0, nt, cp, nc, plan});
+            j0 += nt;
+        }
+    }
+    unsigned char* base;
+    if (int rc = noalloc_scratch(&base)) return rc;
+    int* plan_dev = (int*)(base + kNoAllocPlanOff);
+    void* part = base + kNoAllocPartOff;
+    hipStream_t st = (hipStream_t)geom->stream;
+    const int V3 = geom->L[0] * geom->L[1] * geom->L[2];
+    for (const NoAllocPiece& pc : pieces) {
+        const MomGroup& mg = groups[pc.mg];
+        PlanWords pw;
+        memcpy(pw.w, &pc.plan, sizeof(FactorPlan));
+        hipLaunchKernelGGL(put_plan_kernel, dim3(1), dim3(256), 0, st, pw, plan_dev);
+        if (hipError_t e = hipGetLastError(); e != hipSuccess) return to_status(e, "plan launch");
+        const int ncb = n_noise * pc.nt * n_ops;
+        ProjGrid pg;
+        pg.V3 = V3;
+        pg.n_mom = mg.n;
+        pg.chunk_sites = 0;
+        pg.chunk_planes = pc.chunk_planes;
+        pg.fac_acc = 0;
+        pg.n_chunks = pc.n_chunks;
+        pg.n_colblocks = ncb;
+        pg.n_share = pc.nt;
+        pg.n_per_share = n_noise * n_ops;
+        pg.phase = plan_dev;
+        pg.partial = part;
+        InsertionArgs a;
+        memset(&a, 0, sizeof(a));
+        for (int j = 0; j < 3; ++j) a.L[j] = geom->L[j];
+        a.n_tau = pc.nt;
+        a.n_ops = n_ops;
+        a.n_noise = n_noise;
+        for (int j = 0; j < pc.nt; ++j) {
+            const int t = taus[pc.j0 + j];
+            const int tn = (t + 1) % T, tp = (t - 1 + T) % T;
+            a.G[j] = G_t[t];
+            a.s[j] = s_t[t];
+            if (n_ops > 1) {
+                a.Gn[j] = G_t[tn];
+                a.Gp[j] = G_t[tp];
+                a.U[j] = U_t[t];
+                a.Up[j] = U_t[tp];
+            }
+        }
+        InsertionArgs al = a;
+        al.op_lo = 0;
+        al.op_cnt = 1;
+        ProjGrid pl = pg;
+        pl.n_per_share = n_noise;
+        if (int rc = to_status(launch_fac_insertion(f64, false, 1, pl, al, st), "projection launch")) return rc;
+        if (n_ops == 5) {
+            InsertionArgs ad = a;
+            ad.op_lo = 1;
+            ad.op_cnt = 4;
+            ProjGrid pd = pg;
+            pd.n_per_share = n_noise * 4;
+            if (int rc = to_status(launch_fac_insertion(f64, false, 2, pd, ad, st), "projection launch")) return rc;
+        }
+        ReduceArgs ra;
+        ra.partial = part;
+        ra.f64 = f64 ? 1 : 0;
+        fill_phase(ra.ph, geom, +1, k, mg);
+        ra.out = (double2*)out;
+        ra.n_chunks = pc.n_chunks;
+        ra.n_colblocks = ncb;
+        ra.n_groups = ncb;
+        ra.group_cols = kBlockCols;
+        ra.n_mom_grp = mg.n;
+        ra.n_mom_total = n_mom;
+        ra.m_off = mg.off;
+        ra.inner = pc.nt * n_ops;
+        ra.outer_stride = n_tau * n_ops;
+        ra.off = pc.j0 * n_ops;
+        if (int rc = to_status(launch_reduce(ra, st), "reduction launch")) return rc;
+    }
+    return ok();
+}
+
 int c3pt_combine(const void* spec, int spec_spin, const void* ins, int n_noise, int n_p, int n_q,
                  int n_tau, int n_ops, int op_begin, int op_end, const double* w, const int* pairs,
                  int n_pairs, void* out, void* stream) {

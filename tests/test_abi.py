@@ -101,6 +101,38 @@ def test_insertion_rejects_missing_slices():
     assert c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus, 0, None, 1, kp, 2, DUMMY) == c.C3PT_EINVAL
 
 
+def test_insertion_noalloc_rejects_before_enqueueing():
+    """The no-alloc insertion validates and plans on the host: unsupported
+    modes and requests whose one timeslice exceeds the fixed scratch are
+    rejected before any device call."""
+    import paper_1711_02384_amd as c
+    assert c.noalloc_scratch_bytes() == 128 << 20
+    ka, kp = _k(2)
+    Gt = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    st = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    Ut = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    taus = (ctypes.c_int * 2)(0, 1)
+    g = _geom(c, T=4)
+    g.proj = c.PROJ_NATIVE
+    assert c.lib.c3pt_insertion_noalloc(ctypes.byref(g), Gt, st, 1, taus, 2, None, 1, kp, 2, DUMMY) == \
+        c.C3PT_EUNSUPPORTED
+    g.proj = c.PROJ_FACTORED
+    assert c.lib.c3pt_insertion_noalloc(ctypes.byref(g), Gt, st, 1, taus, 2, Ut, 9, kp, 2, DUMMY) == c.C3PT_EINVAL
+    assert c.lib.c3pt_insertion_noalloc(ctypes.byref(g), Gt, st, 1, taus, 2, None, 5, kp, 2, DUMMY) == c.C3PT_EINVAL
+    Gm = (ctypes.c_void_p * 4)(0x1000, 0x1000, None, 0x1000)
+    assert c.lib.c3pt_insertion_noalloc(ctypes.byref(g), Gm, st, 1, taus, 2, Ut, 5, kp, 2, DUMMY) == c.C3PT_EINVAL
+    # 256^3 with 64 noise vectors, 5 operators and 123 momenta: one timeslice
+    # needs far more partial sums than the fixed array holds
+    big = _geom(c, L=(256, 256, 256), T=4)
+    big.proj = c.PROJ_FACTORED
+    kb = np.ascontiguousarray(np.array(c.momentum_list(9), dtype=np.int32))
+    rc = c.lib.c3pt_insertion_noalloc(ctypes.byref(big), Gt, st, 64, taus, 2, Ut, 5,
+                                      kb.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(kb), DUMMY)
+    assert rc == c.C3PT_EINVAL
+    msg = c.lib.c3pt_last_error().decode()
+    assert "fixed scratch" in msg and str(c.noalloc_scratch_bytes() - 4096) in msg
+
+
 def test_combine_rejects_bad_arguments():
     import paper_1711_02384_amd as c
     L = c.lib
