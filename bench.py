@@ -44,7 +44,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0, "fac": 157.3}   # dense MFMA TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0, "fac": 157.3, "fs16": 2500.0,
+        "fsbf16": 2500.0}   # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
 
@@ -68,7 +69,7 @@ def parse():
                          "37 (meson32) = also the 16 <->D_mu <->D_nu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=6, help="insertion timeslices in the CPU sample")
-    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2", "fac"], default=None,
+    ap.add_argument("--proj", choices=["f32", "bf16x2", "f16x2", "fac", "fs16", "fsbf16"], default=None,
                     help="projection: dense FP32 MFMA, dense hi+lo BF16 / FP16 MFMA with FP32 accumulation, "
                          "or factored (per-direction partial sums, FP32 MFMA)")
     ap.add_argument("--tune", action="store_true", help="autotune kernel variants on this workload first")
@@ -1143,8 +1144,9 @@ def main():
     k = c3pt.momentum_list(W.n2)
     n_mom = len(k)
     proj_flag = {"f64": c3pt.PROJ_NATIVE, "f32": c3pt.PROJ_NATIVE, "bf16x2": c3pt.PROJ_SPLIT_BF16,
-                 "f16x2": c3pt.PROJ_SPLIT_F16, "fac": c3pt.PROJ_FACTORED}[proj]
-    mode = c3pt.MODE[proj]
+                 "f16x2": c3pt.PROJ_SPLIT_F16, "fac": c3pt.PROJ_FACTORED, "fs16": c3pt.PROJ_FACTORED_F16,
+                 "fsbf16": c3pt.PROJ_FACTORED_BF16}[proj]
+    mode = c3pt.MODE.get(proj, c3pt.MODE["fac"])
     batched = isinstance(W, Batch64)
     geom = c3pt.Geom((1, 1, 1) if batched else W.L, 1 if batched else W.T, proj=proj_flag)
     W.proj_flag = proj_flag
@@ -1237,7 +1239,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16x2": "f32 contraction, bf16 hi+lo projection",
-                  "f16x2": "f32 contraction, f16 hi+lo projection", "fac": "f32"}[proj],
+                  "f16x2": "f32 contraction, f16 hi+lo projection", "fac": "f32",
+                  "fs16": "f16 hi+lo MFMA (contraction folded into the projection), f32 accumulation",
+                  "fsbf16": "bf16 hi+lo MFMA (contraction folded into the projection), f32 accumulation"}[proj],
         "data": "synthetic",
         "config": W.config(n_mom),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},

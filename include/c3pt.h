@@ -77,6 +77,13 @@ extern "C" {
                                      more than 8 distinct k1 or 48 (FP64: 24) distinct (k1, k2)
                                      run on the NATIVE kernel                                    */
 
+#define C3PT_PROJ_FACTORED_F16  4   /* complex64 only: factored projection with the colour
+                                       contraction folded into its x1 stage, which runs on
+                                       hi+lo FP16 MFMA with FP32 accumulation (B operand split
+                                       once per call); spectators and n_ops 1 / 5 insertions,
+                                       momentum lists that factor (else C3PT_EUNSUPPORTED)   */
+#define C3PT_PROJ_FACTORED_BF16 5   /* the same with hi+lo BF16 operands                        */
+
 #define C3PT_MAX_MOM   256        /* largest momentum list per call        */
 #define C3PT_MAX_L     256        /* largest spatial extent per direction  */
 
@@ -327,7 +334,12 @@ int c3pt_release_scratch(void);
  * mode: 0 FP64 (complex128 inputs), 1 FP32, 2 split BF16, 3 split FP16;
  * mode 4 selects the form of the factored projection (C3PT_PROJ_FACTORED):
  * variant 0 writes every x3 plane's sums as a chunk of its own, variant 1
- * sums chunks of planes in registers first.
+ * sums chunks of planes in registers first.  Mode 5 selects the form of the
+ * split-precision fused projection (C3PT_PROJ_FACTORED_F16 / _BF16) for the
+ * meson spectator and the insertion: variant 0 splits each propagator tile
+ * into hi + lo parts in the kernel, variant 1 splits the call's slices once
+ * in a pass before it (the nucleon spectator always forms its diquark in a
+ * pass: one variant).
  * mt_class: momentum groups of up to 32, 64, 96, 128 momenta (0..3).
  * c3pt_variant_count returns the number of compiled variants (0 if none);
  * c3pt_set_variant selects one for later calls (process-wide);

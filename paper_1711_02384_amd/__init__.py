@@ -40,6 +40,8 @@ PROJ_NATIVE = 0
 PROJ_SPLIT_F16 = 1
 PROJ_SPLIT_BF16 = 2
 PROJ_FACTORED = 3
+PROJ_FACTORED_F16 = 4
+PROJ_FACTORED_BF16 = 5
 PROTON_D = 0   # current on the d quark; nucleon data of spectators (u, u)
 PROTON_U = 1   # current on a u quark; nucleon data of spectators (u, d)
 
@@ -52,7 +54,8 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
             "c3pt_server_destroy", "c3pt_insertion_noalloc", "c3pt_noalloc_scratch_bytes")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
-MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4}   # "fac": variant slot of the factored projection
+MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4, "fs16": 5, "fsbf16": 5}
+# "fac", "fs16" / "fsbf16": variant slots of the factored and the split-precision fused projections
 
 
 class C3ptError(RuntimeError):

@@ -22,7 +22,7 @@ SOURCES = ["c3pt_api.hip", "c3pt_proj_meson.hip", "c3pt_proj_baryon.hip", "c3pt_
            "c3pt_combine.hip", "c3pt_phase.hip", "c3pt_batch.hip",
            "c3pt_serve.hip", "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip",
            "c3pt_gamma.hip", "c3pt_fac_left.hip",
-           "c3pt_smear.hip"]
+           "c3pt_smear.hip", "c3pt_fs.hip"]
 
 
 def hipcc() -> str:

@@ -17,6 +17,7 @@
 #include "c3pt_internal.h"
 #include "c3pt_analysis.h"
 #include "c3pt_fac_left.h"
+#include "c3pt_fs_api.h"
 
 using namespace c3pt;
 
@@ -189,9 +190,11 @@ int check_geom(const c3pt_geom* g) {
     if (g->T < 1) return fail(C3PT_EINVAL, "T = %d < 1", g->T);
     if (g->dtype != C3PT_C64 && g->dtype != C3PT_C128) return fail(C3PT_EINVAL, "unknown dtype %d", g->dtype);
     if (g->proj != C3PT_PROJ_NATIVE && g->proj != C3PT_PROJ_SPLIT_F16 && g->proj != C3PT_PROJ_SPLIT_BF16 &&
-        g->proj != C3PT_PROJ_FACTORED)
+        g->proj != C3PT_PROJ_FACTORED && g->proj != C3PT_PROJ_FACTORED_F16 && g->proj != C3PT_PROJ_FACTORED_BF16)
         return fail(C3PT_EINVAL, "unknown projection mode %d", g->proj);
-    if ((g->proj == C3PT_PROJ_SPLIT_F16 || g->proj == C3PT_PROJ_SPLIT_BF16) && g->dtype != C3PT_C64)
+    if ((g->proj == C3PT_PROJ_SPLIT_F16 || g->proj == C3PT_PROJ_SPLIT_BF16 || g->proj == C3PT_PROJ_FACTORED_F16 ||
+         g->proj == C3PT_PROJ_FACTORED_BF16) &&
+        g->dtype != C3PT_C64)
         return fail(C3PT_EINVAL, "split-precision projection needs complex64 inputs");
     return C3PT_OK;
 }
@@ -217,14 +220,18 @@ int proj_mode(const c3pt_geom* g) {
 
 // Kernel variant per (kind, mode, momentum-tile class); 0 = default.
 constexpr int kKinds = 3;   // 0 meson spectator, 1 baryon spectator, 2 insertion
-constexpr int kModes = 5;
+constexpr int kModes = 6;
 constexpr int kModeFacVariants = 4;   // variant slot of the factored projection (not an arithmetic mode)
+constexpr int kModeFsVariants = 5;    // variant slot of the split-precision fused projection
 int g_variant[kKinds][kModes][kMtClasses] = {};
 
 int variant_count(int kind, int mode, int cls) {
     if (kind < 0 || kind >= kKinds || mode < 0 || mode >= kModes || cls < 0 || cls >= kMtClasses) return 0;
     // factored: 0 = every x3 plane written as its own chunk, 1 = chunks of planes summed in registers
     if (mode == kModeFacVariants) return 2;
+    // fused: 0 = propagator tiles split in the kernel, 1 = slices split by a pass first
+    // (the nucleon's diquark always has its pass)
+    if (mode == kModeFsVariants) return kind == 1 ? 1 : 2;
     if (mode == kModeF64) return cls == 0 ? 1 : 0;
     return kVariantsPerClass[cls];
 }
@@ -368,6 +375,14 @@ bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGro
         const int a = am[m], n = (int)k2s[a].size(), per = (n + parts[a] - 1) / parts[a];
         p->pair_of_m[m] = p->bstart[first_slot[a] + jm[m] / per] + jm[m] % per;
     }
+    // momenta grouped by pair, in increasing m within a pair
+    int pos = 0;
+    for (int b = 0; b < p->n12; ++b) {
+        p->mstart[b] = pos;
+        for (int m = 0; m < mg.n; ++m)
+            if (p->pair_of_m[m] == b) p->m_of[pos++] = m;
+    }
+    for (int b = p->n12; b <= kFacMaxPairsF32; ++b) p->mstart[b] = pos;
     return true;
 }
 
@@ -524,6 +539,285 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
         ra.off = off;
         if (int rc = to_status(timed("reduce", st, [&] { return launch_reduce(ra, st); }), "reduction launch"))
             return rc;
+    }
+    return C3PT_OK;
+}
+
+}  // namespace
+
+// ---- split-precision fused projection (C3PT_PROJ_FACTORED_F16 / _BF16) ----
+namespace {
+
+bool is_fused(const c3pt_geom* g) {
+    return g->proj == C3PT_PROJ_FACTORED_F16 || g->proj == C3PT_PROJ_FACTORED_BF16;
+}
+
+// Factor plans of every momentum group (FP32 limits); false if one does not factor.
+bool fs_plans(const c3pt_geom* g, int sigma, const int* k, int n_mom, std::vector<MomGroup>* groups,
+              std::vector<FactorPlan>* plans) {
+    *groups = momentum_groups(n_mom, false);
+    plans->resize(groups->size());
+    for (size_t i = 0; i < groups->size(); ++i)
+        if (!build_factor_plan(g, sigma, k, (*groups)[i], false, &(*plans)[i])) return false;
+    return true;
+}
+
+// Partial sums then split B blocks in this stream's scratch.
+int fs_scratch(hipStream_t st, size_t part_bytes, size_t b_bytes, void** part, void** B) {
+    const size_t off = (part_bytes + 255) & ~(size_t)255;
+    void* base;
+    if (int rc = scratch_dev(st, off + b_bytes, &base)) return rc;
+    *part = base;
+    *B = (char*)base + off;
+    return C3PT_OK;
+}
+
+// Spectators on the fused path: meson (G1 only) or nucleon (G1, G2).
+int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void* G2, const void* eta, int N,
+                 const int* k, int n_mom, void* out) {
+    std::vector<MomGroup> groups;
+    std::vector<FactorPlan> plans;
+    if (!fs_plans(geom, -1, k, n_mom, &groups, &plans))
+        return fail(C3PT_EUNSUPPORTED, "the momentum list does not factor (too many distinct k1 or (k1, k2))");
+    hipStream_t st = (hipStream_t)geom->stream;
+    const bool bf16 = geom->proj == C3PT_PROJ_FACTORED_BF16;
+    const int KT = fs_kt(geom->L), Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
+    const int V3 = geom->L[0] * rows;
+    const size_t bb = fs_block_bytes(geom->L);
+    const int n_slots = baryon ? 16 : 1;
+    const int ncb = N * n_slots;
+    const int n_per_share = n_slots * ((N + 1) / 2);
+    int cp, nch;
+    plan_planes(geom->L, n_per_share, &cp, &nch);
+    const size_t part_bytes = (size_t)nch * ncb * kMaxMomGroupF32 * kBlockCols * sizeof(float2);
+    void *part, *B;
+    if (int rc = fs_scratch(st, part_bytes, (size_t)n_slots * bb, &part, &B)) return rc;
+    int fs_variant;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        fs_variant = g_variant[baryon ? 1 : 0][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
+    }
+    const bool bsplit = baryon || fs_variant == 1;
+    if (!baryon && bsplit) {
+        FsSplitArgs sa;
+        memset(&sa, 0, sizeof(sa));
+        for (int j = 0; j < 3; ++j) sa.L[j] = geom->L[j];
+        sa.Lp = Lp;
+        sa.rows = rows;
+        sa.n_slices = 1;
+        sa.conj_sign = 1;
+        sa.G[0] = (const float2*)G1;
+        sa.out = B;
+        if (int rc = to_status(timed("fs_split", st, [&] { return launch_fs_split(bf16, sa, st); }), "split launch"))
+            return rc;
+    }
+    if (baryon) {
+        FsDiquarkArgs da;
+        for (int j = 0; j < 3; ++j) da.L[j] = geom->L[j];
+        da.Lp = Lp;
+        da.rows = rows;
+        da.G1 = (const float2*)G1;
+        da.G2 = (const float2*)G2;
+        da.out = B;
+        if (int rc = to_status(timed("fs_diquark", st, [&] { return launch_fs_diquark(bf16, da, st); }),
+                               "diquark launch"))
+            return rc;
+    }
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const MomGroup& mg = groups[gi];
+        const void* tab;
+        if (int rc = factor_plan_table(plans[gi], false, st, &tab)) return rc;
+        ProjGrid pg;
+        memset(&pg, 0, sizeof(pg));
+        pg.V3 = V3;
+        pg.n_mom = mg.n;
+        pg.chunk_planes = cp;
+        pg.n_chunks = nch;
+        pg.n_colblocks = ncb;
+        pg.n_share = 1;
+        pg.n_per_share = n_per_share;
+        pg.phase = tab;
+        pg.partial = part;
+        FsArgs fa;
+        memset(&fa, 0, sizeof(fa));
+        for (int j = 0; j < 3; ++j) fa.L[j] = geom->L[j];
+        fa.Lp = Lp;
+        fa.rows = rows;
+        fa.N = N;
+        fa.n_share = 1;
+        fa.n_slots = n_slots;
+        fa.colmap = baryon ? 1 : 0;
+        fa.conj_sign = baryon ? 0 : 1;
+        fa.B = B;
+        fa.b_stride = bb;
+        fa.G[0][0] = G1;
+        fa.u0[0] = eta;
+        if (int rc = to_status(timed(baryon ? "fs_spectator_baryon" : "fs_spectator_meson", st,
+                                     [&] { return launch_fs(bf16, KT, 0, bsplit, pg, fa, st); }),
+                               "projection launch"))
+            return rc;
+        ReduceArgs ra;
+        ra.partial = part;
+        ra.f64 = 0;
+        fill_phase(ra.ph, geom, -1, k, mg);
+        ra.out = (double2*)out;
+        ra.n_chunks = nch;
+        ra.n_colblocks = ncb;
+        ra.n_groups = N;
+        ra.group_cols = baryon ? 3072 : kBlockCols;
+        ra.n_mom_grp = mg.n;
+        ra.n_mom_total = n_mom;
+        ra.m_off = mg.off;
+        ra.inner = N;
+        ra.outer_stride = 0;
+        ra.off = 0;
+        if (int rc = to_status(timed("reduce", st, [&] { return launch_reduce(ra, st); }), "reduction launch"))
+            return rc;
+    }
+    return C3PT_OK;
+}
+
+// The insertion on the fused path (n_ops 1 or 5; arguments already checked).
+int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* const* s_t, int N, const int* taus,
+                 int n_tau, const void* const* U_t, int n_ops, const int* k, int n_mom, void* out) {
+    std::vector<MomGroup> groups;
+    std::vector<FactorPlan> plans;
+    if (!fs_plans(geom, +1, k, n_mom, &groups, &plans))
+        return fail(C3PT_EUNSUPPORTED, "the momentum list does not factor (too many distinct k1 or (k1, k2))");
+    hipStream_t st = (hipStream_t)geom->stream;
+    const bool bf16 = geom->proj == C3PT_PROJ_FACTORED_BF16;
+    const int KT = fs_kt(geom->L), Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
+    const int V3 = geom->L[0] * rows;
+    const int T = geom->T;
+    const int kind = n_ops == 5 ? 2 : 1;
+    const int n_slots = n_ops == 5 ? 9 : 1;
+    const size_t bb = fs_block_bytes(geom->L);
+    int fs_variant;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        fs_variant = g_variant[2][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
+    }
+    const bool bsplit = fs_variant == 1;
+    for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
+        const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
+        FsArgs fa;
+        memset(&fa, 0, sizeof(fa));
+        for (int j = 0; j < nt; ++j) {
+            const int t = taus[j0 + j];
+            fa.G[j][0] = G_t[t];
+            if (n_ops == 5) {
+                fa.G[j][1] = G_t[(t + 1) % T];
+                fa.G[j][2] = G_t[(t - 1 + T) % T];
+                fa.U[j] = U_t[t];
+                fa.Up[j] = U_t[(t - 1 + T) % T];
+            }
+            fa.u0[j] = s_t[t];
+        }
+        const int ncb = N * nt * n_slots;
+        const int n_per_share = n_slots * ((N + 1) / 2);
+        int cp, nch;
+        plan_planes(geom->L, n_per_share * nt, &cp, &nch);
+        const size_t part_bytes = (size_t)nch * ncb * kMaxMomGroupF32 * kBlockCols * sizeof(float2);
+        // with the split pass: the distinct slices of the launch and the block of each role
+        std::vector<int> sl;
+        if (bsplit) {
+            auto slot_of = [&](int t) {
+                t = ((t % T) + T) % T;
+                auto it = std::find(sl.begin(), sl.end(), t);
+                if (it != sl.end()) return (int)(it - sl.begin());
+                sl.push_back(t);
+                return (int)sl.size() - 1;
+            };
+            for (int j = 0; j < nt; ++j) {
+                const int t = taus[j0 + j];
+                fa.bidx[j][0] = slot_of(t);
+                if (n_ops == 5) {
+                    fa.bidx[j][1] = slot_of(t + 1);
+                    fa.bidx[j][2] = slot_of(t - 1);
+                }
+            }
+        }
+        void *part, *B;
+        if (int rc = fs_scratch(st, part_bytes, sl.size() * bb, &part, &B)) return rc;
+        for (size_t s0 = 0; s0 < sl.size(); s0 += kMaxTauPerLaunch + 2) {
+            FsSplitArgs sa;
+            memset(&sa, 0, sizeof(sa));
+            for (int j = 0; j < 3; ++j) sa.L[j] = geom->L[j];
+            sa.Lp = Lp;
+            sa.rows = rows;
+            sa.n_slices = (int)std::min(sl.size() - s0, (size_t)kMaxTauPerLaunch + 2);
+            sa.conj_sign = 0;
+            for (int j = 0; j < sa.n_slices; ++j) sa.G[j] = (const float2*)G_t[sl[s0 + j]];
+            sa.out = (char*)B + s0 * bb;
+            if (int rc = to_status(timed("fs_split", st, [&] { return launch_fs_split(bf16, sa, st); }),
+                                   "split launch"))
+                return rc;
+        }
+        fa.B = B;
+        fa.b_stride = bb;
+        for (int j = 0; j < 3; ++j) fa.L[j] = geom->L[j];
+        fa.Lp = Lp;
+        fa.rows = rows;
+        fa.N = N;
+        fa.n_share = nt;
+        fa.n_slots = n_slots;
+        fa.colmap = 0;
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const MomGroup& mg = groups[gi];
+            const void* tab;
+            if (int rc = factor_plan_table(plans[gi], false, st, &tab)) return rc;
+            ProjGrid pg;
+            memset(&pg, 0, sizeof(pg));
+            pg.V3 = V3;
+            pg.n_mom = mg.n;
+            pg.chunk_planes = cp;
+            pg.n_chunks = nch;
+            pg.n_colblocks = ncb;
+            pg.n_share = nt;
+            pg.n_per_share = n_per_share;
+            pg.phase = tab;
+            pg.partial = part;
+            if (int rc = to_status(timed("fs_insertion", st,
+                                         [&] { return launch_fs(bf16, KT, kind, bsplit, pg, fa, st); }),
+                                   "projection launch"))
+                return rc;
+            if (kind == 1) {
+                ReduceArgs ra;
+                ra.partial = part;
+                ra.f64 = 0;
+                fill_phase(ra.ph, geom, +1, k, mg);
+                ra.out = (double2*)out;
+                ra.n_chunks = nch;
+                ra.n_colblocks = ncb;
+                ra.n_groups = ncb;
+                ra.group_cols = kBlockCols;
+                ra.n_mom_grp = mg.n;
+                ra.n_mom_total = n_mom;
+                ra.m_off = mg.off;
+                ra.inner = nt;
+                ra.outer_stride = n_tau;
+                ra.off = j0;
+                if (int rc = to_status(timed("reduce", st, [&] { return launch_reduce(ra, st); }), "reduction launch"))
+                    return rc;
+            } else {
+                FsReduceArgs ra;
+                ra.partial = (const float2*)part;
+                ra.out = (double2*)out;
+                fill_phase(ra.ph, geom, +1, k, mg);
+                ra.n_chunks = nch;
+                ra.n_colblocks = ncb;
+                ra.N = N;
+                ra.nt = nt;
+                ra.j0 = j0;
+                ra.n_tau_total = n_tau;
+                ra.n_mom_grp = mg.n;
+                ra.n_mom_total = n_mom;
+                ra.m_off = mg.off;
+                if (int rc = to_status(timed("reduce", st, [&] { return launch_fs_reduce(ra, st); }),
+                                       "reduction launch"))
+                    return rc;
+            }
+        }
     }
     return C3PT_OK;
 }
@@ -736,6 +1030,10 @@ int c3pt_spectator_meson(const c3pt_geom* geom, const void* G_tf, const void* et
     if (int rc = check_momenta(k, n_mom)) return rc;
     if (!G_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    if (is_fused(geom)) {
+        const int rc = fs_spectator(geom, false, G_tf, nullptr, eta, n_noise, k, n_mom, out);
+        return rc ? rc : ok();
+    }
     MesonSpecArgs a{{geom->L[0], geom->L[1], geom->L[2]}, G_tf, eta};
     int rc = run_projection("proj_spectator_meson", 0, geom, -1, k, n_mom, n_noise, 1, n_noise, kBlockCols,
                             n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
@@ -752,6 +1050,10 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
     if (int rc = check_momenta(k, n_mom)) return rc;
     if (!G1_tf || !G2_tf || !eta || !out) return fail(C3PT_EINVAL, "NULL field or output pointer");
     if (n_noise < 1) return fail(C3PT_EINVAL, "n_noise = %d < 1", n_noise);
+    if (is_fused(geom)) {
+        const int rc = fs_spectator(geom, true, G1_tf, G2_tf, eta, n_noise, k, n_mom, out);
+        return rc ? rc : ok();
+    }
     BaryonSpecArgs a{{geom->L[0], geom->L[1], geom->L[2]}, G1_tf, G2_tf, eta};
     int rc = run_projection("proj_spectator_baryon", 1, geom, -1, k, n_mom, n_noise * 16, 1, n_noise * 16, 3072,
                             n_noise, n_noise, 0, 0, out, [&](int mode, const ProjGrid& pg, int mt, int variant, bool fac) {
@@ -795,6 +1097,12 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                     return fail(C3PT_EINVAL, "stochastic solution slices %d and %d needed around %d", tp2, tn2, t);
             }
         }
+    }
+    if (is_fused(geom)) {
+        if (n_ops != 1 && n_ops != 5)
+            return fail(C3PT_EUNSUPPORTED, "the split-precision fused projection takes n_ops 1 or 5");
+        const int rc = fs_insertion(geom, G_t, s_t, n_noise, taus, n_tau, U_t, n_ops, k, n_mom, out);
+        return rc ? rc : ok();
     }
     if (n_ops >= 9) {
         if (int rc = check_symmetric(geom, k, n_mom)) return rc;

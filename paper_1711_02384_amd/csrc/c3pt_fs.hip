@@ -1,0 +1,220 @@
+// Split-precision fused projection: the passes that split propagator slices
+// and form the nucleon diquark, the kernel instantiations and the FP64
+// reduction of the derivative slots.  The kernel
+// itself is in c3pt_fs.h.
+#include "c3pt_fs.h"
+#include "c3pt_fs_api.h"
+
+namespace c3pt {
+
+// ---------------------------------------------------------------------------
+// Propagator slices -> split B blocks.  Plane p' = 48 c + X of block s holds
+// B[c][X] = G_s[(bt, c)][(b, c0)] with X = 12 bt + 3 b + c0 (times
+// g[bt] g[b] and conjugated for the meson spectator), rows of Lp sites
+// (zero beyond L1), four sites per group.  One thread per site.
+// ---------------------------------------------------------------------------
+template <typename T16>
+__global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
+    const int Lp = a.Lp;
+    const long long total = (long long)kFsPlanes * a.rows * Lp * a.n_slices;
+    const int L1 = a.L[0];
+    const unsigned V3 = (unsigned)(a.L[0] * a.L[1] * a.L[2]);
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int x1 = (int)(idx % Lp);
+        long long rest = idx / Lp;
+        const int row = (int)(rest % a.rows);
+        rest /= a.rows;
+        const int p = (int)(rest % kFsPlanes);
+        const int sl = (int)(rest / kFsPlanes);
+        const int X = p % 48, cs = p / 48;
+        const int bt = X / 12, rem = X % 12;
+        const float2 v = a.G[sl][(unsigned)((3 * bt + cs) * 12 + rem) * V3 + (unsigned)(min(x1, L1 - 1) + L1 * row)];
+        const float sg = a.conj_sign ? (bt < 2 ? 1.f : -1.f) * (rem / 3 < 2 ? 1.f : -1.f) : 1.f;
+        const float sy = a.conj_sign ? -sg : sg;
+        unsigned hw, lw;
+        fs_split2<T16>(x1 < L1 ? f32x2{sg * v.x, sy * v.y} : f32x2{0.f, 0.f}, hw, lw);
+        unsigned* dst = (unsigned*)a.out + (((size_t)sl * kFsPlanes + p) * a.rows + row) * (size_t)(Lp / 4) * 8 +
+                        (size_t)(x1 >> 2) * 8 + (x1 & 3);
+        dst[0] = hw;
+        dst[4] = lw;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Nucleon diquark -> split B blocks.  Block (a1', a1), plane p' = 48 c + 3 q + c'
+// with q = 4 a2' + a2:
+//   Q[q][c][c'] = sum eps_{abc} eps_{a'b'c'} G1[(a1',a)][(a1,a')] G2[(a2',b)][(a2,b')]
+// One thread per (block, q, site x1 of a padded row): consecutive lanes read
+// consecutive sites of each propagator plane and write the hi and lo words of
+// their site into the four-site groups.
+// ---------------------------------------------------------------------------
+template <typename T16>
+__global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
+    const int Lp = a.Lp;
+    const long long total = 256LL * a.rows * Lp;
+    const int L1 = a.L[0];
+    const unsigned V3 = (unsigned)(a.L[0] * a.L[1] * a.L[2]);
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int x1 = (int)(idx % Lp);
+        long long rest = idx / Lp;
+        const int row = (int)(rest % a.rows);
+        rest /= a.rows;
+        const int q = (int)(rest % 16);
+        const int blk = (int)(rest / 16);
+        const int a1p = blk >> 2, a1 = blk & 3, a2p = q >> 2, a2 = q & 3;
+        const bool ok = x1 < L1;
+        const unsigned n = (unsigned)(min(x1, L1 - 1) + L1 * row);
+        C2<float> g1[3][3], g2[3][3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const float2 x = a.G1[(unsigned)((3 * a1p + u) * 12 + 3 * a1 + v) * V3 + n];
+                const float2 y = a.G2[(unsigned)((3 * a2p + u) * 12 + 3 * a2 + v) * V3 + n];
+                g1[u][v] = {x.x, x.y};
+                g2[u][v] = {y.x, y.y};
+            }
+        unsigned* out = (unsigned*)((FsGroup*)a.out + (size_t)blk * kFsPlanes * a.rows * (Lp / 4));
+        const size_t gw = (size_t)(x1 >> 2) * 8 + (x1 & 3);   // the site's hi word in its group; lo is 4 words on
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+#pragma unroll
+            for (int cp = 0; cp < 3; ++cp) {
+                const int d1 = (cp + 1) % 3, d2 = (cp + 2) % 3;
+                C2<float> t = cmul(g1[c1][d1], g2[c2][d2]);
+                t = cfnma(t, g1[c1][d2], g2[c2][d1]);
+                t = cfnma(t, g1[c2][d1], g2[c1][d2]);
+                t = cfma(t, g1[c2][d2], g2[c1][d1]);
+                unsigned hw, lw;
+                fs_split2<T16>(ok ? f32x2{t.x, t.y} : f32x2{0.f, 0.f}, hw, lw);
+                unsigned* dst = out + ((size_t)(48 * c + 3 * q + cp) * a.rows + row) * (size_t)(Lp / 4) * 8 + gw;
+                dst[0] = hw;
+                dst[4] = lw;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reduction of the insertion's nine slots into its five operators:
+//   op 0        = slot 0
+//   op 1 + nu   = e^{-i sigma p_nu} slot(1 + 2 nu) - e^{+i sigma p_nu} slot(2 + 2 nu)   (nu = x, y, z)
+//   op 4        = slot 7 - slot 8                                                      (nu = t)
+// each summed over the chunks in fixed order, times the source factor.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 fs_source_factor(const int (&L)[3], const int (&r)[3], int sigma, int k1, int k2,
+                                                    int k3) {
+    const long long V3 = (long long)L[0] * L[1] * L[2];
+    const long long n = (long long)k1 * r[0] * (L[1] * L[2]) + (long long)k2 * r[1] * (L[0] * L[2]) +
+                        (long long)k3 * r[2] * (L[0] * L[1]);
+    double s, c;
+    sincospi(2.0 * (double)(n % V3) / (double)V3, &s, &c);
+    return make_double2(c, -sigma * s);
+}
+
+__global__ void __launch_bounds__(256) fs_reduce_kernel(FsReduceArgs a) {
+    const long long total = (long long)a.N * a.nt * 5 * a.n_mom_grp * kBlockCols;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % kBlockCols);
+        long long rest = idx / kBlockCols;
+        const int m = (int)(rest % a.n_mom_grp);
+        rest /= a.n_mom_grp;
+        const int op = (int)(rest % 5);
+        rest /= 5;
+        const int j = (int)(rest % a.nt);
+        const int i = (int)(rest / a.nt);
+        const int cb0 = (i * a.nt + j) * 9;
+        auto slot_sum = [&](int s) {
+            double sx = 0.0, sy = 0.0;
+            for (int ch = 0; ch < a.n_chunks; ++ch) {
+                const float2 v =
+                    a.partial[(((size_t)ch * a.n_colblocks + cb0 + s) * a.n_mom_grp + m) * kBlockCols + c];
+                sx += (double)v.x;
+                sy += (double)v.y;
+            }
+            return make_double2(sx, sy);
+        };
+        double2 v;
+        if (op == 0) {
+            v = slot_sum(0);
+        } else {
+            const int nu = op - 1;
+            const double2 jp = slot_sum(1 + 2 * nu), jm = slot_sum(2 + 2 * nu);
+            if (nu == 3) {
+                v = make_double2(jp.x - jm.x, jp.y - jm.y);
+            } else {
+                double s, cs;
+                sincospi(2.0 * (double)a.ph.k[nu][m] / (double)a.ph.L[nu], &s, &cs);
+                const double sg = (double)a.ph.sigma * s;
+                // e^{-i sg} jp - e^{+i sg} jm
+                v = make_double2(cs * jp.x + sg * jp.y - (cs * jm.x - sg * jm.y),
+                                 cs * jp.y - sg * jp.x - (cs * jm.y + sg * jm.x));
+            }
+        }
+        const double2 f = fs_source_factor(a.ph.L, a.ph.r, a.ph.sigma, a.ph.k[0][m], a.ph.k[1][m], a.ph.k[2][m]);
+        const size_t G = ((size_t)i * a.n_tau_total + a.j0 + j) * 5 + op;
+        a.out[(G * a.n_mom_total + a.m_off + m) * kBlockCols + c] =
+            make_double2(f.x * v.x - f.y * v.y, f.x * v.y + f.y * v.x);
+    }
+}
+
+namespace {
+int grid_for(long long total) {
+    long long b = (total + 255) / 256;
+    return (int)std::min<long long>(std::max<long long>(b, 1), 65536);
+}
+}  // namespace
+
+hipError_t launch_fs_split(bool bf16, const FsSplitArgs& a, hipStream_t st) {
+    const long long total = (long long)kFsPlanes * a.rows * a.Lp * a.n_slices;
+    if (bf16)
+        hipLaunchKernelGGL(fs_split_kernel<__bf16>, dim3(grid_for(total)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(fs_split_kernel<_Float16>, dim3(grid_for(total)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fs_diquark(bool bf16, const FsDiquarkArgs& a, hipStream_t st) {
+    const long long total = 256LL * a.rows * a.Lp;
+    if (bf16)
+        hipLaunchKernelGGL(fs_diquark_kernel<__bf16>, dim3(grid_for(total)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(fs_diquark_kernel<_Float16>, dim3(grid_for(total)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fs_reduce(const FsReduceArgs& a, hipStream_t st) {
+    const long long total = (long long)a.N * a.nt * 5 * a.n_mom_grp * kBlockCols;
+    hipLaunchKernelGGL(fs_reduce_kernel, dim3(grid_for(total)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T16, int KT>
+static hipError_t launch_fs_t(int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+    const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(kFsThreads);
+    if (kind == 0 && bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true>), grid, block, 0, st, pg, a);
+    else if (kind == 0)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, false>), grid, block, 0, st, pg, a);
+    else if (kind == 1 && bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true>), grid, block, 0, st, pg, a);
+    else if (kind == 1)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, false>), grid, block, 0, st, pg, a);
+    else if (bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true>), grid, block, 0, st, pg, a);
+    else
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, false>), grid, block, 0, st, pg, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+    if (bf16)
+        return KT == 32 ? launch_fs_t<__bf16, 32>(kind, bsplit, pg, a, st) : launch_fs_t<__bf16, 16>(kind, bsplit, pg, a, st);
+    return KT == 32 ? launch_fs_t<_Float16, 32>(kind, bsplit, pg, a, st) : launch_fs_t<_Float16, 16>(kind, bsplit, pg, a, st);
+}
+
+}  // namespace c3pt

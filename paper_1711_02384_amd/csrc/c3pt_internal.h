@@ -53,6 +53,8 @@ struct FactorPlan {
     int k2[kFacMaxPairsF32];          // k2 of pair b (reduced mod L2)
     int pair_of_m[kMaxMomGroup];      // pair b of momentum m
     int k3[kMaxMomGroup];             // k3 of momentum m (reduced mod L3)
+    int mstart[kFacMaxPairsF32 + 1];  // momenta of pair b: m_of[mstart[b] .. mstart[b+1])
+    int m_of[kMaxMomGroup];
 };
 
 // One launch of the fused contraction + projection kernel.  Work items are

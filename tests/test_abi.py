@@ -133,6 +133,24 @@ def test_insertion_noalloc_rejects_before_enqueueing():
     assert "fixed scratch" in msg and str(c.noalloc_scratch_bytes() - 4096) in msg
 
 
+def test_fused_projection_modes_are_validated():
+    """The split-precision fused modes need complex64 inputs and take n_ops 1 or 5."""
+    import paper_1711_02384_amd as c
+    ka, kp = _k(2)
+    Gt = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    st = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    Ut = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    taus = (ctypes.c_int * 2)(0, 1)
+    for proj in (c.PROJ_FACTORED_F16, c.PROJ_FACTORED_BF16):
+        g = _geom(c, T=4, proj=proj, dtype=1)
+        assert c.lib.c3pt_spectator_meson(ctypes.byref(g), DUMMY, DUMMY, 1, kp, 2, DUMMY) == c.C3PT_EINVAL
+        g = _geom(c, T=4, proj=proj)
+        assert c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 1, taus, 2, Ut, 9, kp, 2, DUMMY) == \
+            c.C3PT_EUNSUPPORTED
+    g = _geom(c, T=4, proj=6)
+    assert c.lib.c3pt_spectator_meson(ctypes.byref(g), DUMMY, DUMMY, 1, kp, 2, DUMMY) == c.C3PT_EINVAL
+
+
 def test_combine_rejects_bad_arguments():
     import paper_1711_02384_amd as c
     L = c.lib
