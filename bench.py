@@ -113,10 +113,12 @@ CONTRACTION_FLOPS = {"spectator_meson": 8.0 * 576, "spectator_baryon": 8.0 * 115
 # and workload names.  Each entry carries a hash of the kernel sources it was
 # measured with and is reported only while they are unchanged.
 TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_device.h", "c3pt_internal.h",
-                   "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip"]
-# host functions of c3pt_api.hip that plan and launch the factored kernels
+                   "c3pt_fac_meson.hip", "c3pt_fac_baryon.hip", "c3pt_fac_insertion.hip",
+                   "c3pt_fs.h", "c3pt_fs_api.h", "c3pt_fs.hip"]
+# host functions of c3pt_api.hip that plan and launch the factored and fused kernels
 TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table", "plan_planes", "plan_chunks",
-                     "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion"]
+                     "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion",
+                     "fs_plans", "fs_scratch", "fs_spectator", "fs_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
     # 32^3 step: local (484189 + 264384 KiB) and derivative (1940642 + 1114112 KiB) dispatches of one call
@@ -133,6 +135,8 @@ MEASURED_TRAFFIC = {
                                               "d9861a908adb74c3"),
     # 48^3 step: one nucleon spectator dispatch (414814 + 857088 KiB)
     ("nucleon48", "fac", "fac_spectator_baryon", 1): (414814 * 2048 + 857088 * 1024, "d9861a908adb74c3"),
+    # 48^3 step, split-precision fused form: one local insertion dispatch (1555470 + 803520 KiB)
+    ("nucleon48", "fs16", "fs_insertion", 1): (1555470 * 2048 + 803520 * 1024, "0b4eb1b293354a4e"),
     # two-sink 32^3 x 96 step: local (3771200 + 4687200 KiB) and derivative (32728293 + 19622400 KiB)
     ("twosink32", "fac", "fac_insertion", 5): ((3771200 + 32728293) * 2048 + (4687200 + 19622400) * 1024,
                                                "d9861a908adb74c3"),
@@ -183,6 +187,11 @@ def roofline_entry(kname, flops, kms, proj, traffic=None):
     if proj == "fac":
         peak, bound = PEAK_VALU_F32, "alu"
         what = "fused contraction + factored projection; flops = contraction arithmetic"
+    elif proj in ("fs16", "fsbf16"):
+        peak, bound = PEAK_VALU_F32, "alu"
+        what = ("contraction folded into the x1 stage of the factored projection on hi+lo 16-bit MFMA; "
+                "flops = the contraction arithmetic (the plain form's count); the kernel is bound by "
+                "VALU issue (A operands, hi+lo splits, stage 2)")
     else:
         peak, bound = PEAK[proj], "mfma"
         what = f"fused contraction + {proj} MFMA projection; flops = 8 per (site, momentum, column)"
@@ -409,7 +418,12 @@ class Nucleon48(Meson32):
     n_ops = 1
     cfg = 3
     dtype = "c64"
-    default_proj = "fac"
+    default_proj = "fs16"
+    plain_proj = "fac"
+    # outputs the CPU-baseline sample recomputes with the oracle (2 of 8 noise
+    # vectors of the (u,u) spectator, the u insertion on 2 of 15 timeslices)
+    sample_noise = 2
+    sample_taus = [7, 8]
 
     def __init__(self, args):
         self.baryon = True
@@ -437,6 +451,9 @@ class Nucleon48(Meson32):
         self.Cd = mk(len(self.pairs), n_tau, 1, 1024, 64)
         self.Cu = mk(len(self.pairs), n_tau, 1, 1024, 64)
         self.c3pt, self.geom, self.k = c3pt, geom, k
+        j0, j1 = self.taus.index(self.sample_taus[0]), self.taus.index(self.sample_taus[-1]) + 1
+        self.sample_outputs = {"spectator_baryon": lambda: self.Suu[:self.sample_noise],
+                               "insertion": lambda: self.Iu[:, j0:j1]}
 
     def calls(self):
         c, g, k = self.c3pt, self.geom, self.k
@@ -469,9 +486,15 @@ class Nucleon48(Meson32):
         return 2 * self.N * V3 * n_mom * 3072 + 2 * self.N * len(self.taus) * V3 * n_mom * 192
 
     def dominant(self, n_mom, proj):
+        """Candidate kernels and their contraction flops per launch; the one with
+        the most time per step is reported."""
         V3 = int(np.prod(self.L))
+        spec = 16 * self.N * V3 * CONTRACTION_FLOPS["spectator_baryon"]
+        ins = self.N * len(self.taus) * V3 * CONTRACTION_FLOPS["insertion_local"]
         if proj == "fac":
-            return "fac_spectator_baryon", 16 * self.N * V3 * CONTRACTION_FLOPS["spectator_baryon"]
+            return {"fac_spectator_baryon": spec, "fac_insertion": ins}
+        if proj in ("fs16", "fsbf16"):
+            return {"fs_spectator_baryon": spec, "fs_insertion": ins}
         cols = self.N * 3072
         return "proj_spectator_baryon", 8.0 * n_mom * V3 * cols
 
@@ -484,9 +507,9 @@ class Nucleon48(Meson32):
         L = self.L
         tau = self.taus[len(self.taus) // 2]
         Gf = syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, self.t_f))
-        ns, nt = 2, 2
+        ns, ts = self.sample_noise, self.sample_taus
+        nt = len(ts)
         eta = syn.round_to_c64(syn.z2z2_noise(L, ns, self.cfg, self.t_f))
-        ts = self.taus[len(self.taus) // 2: len(self.taus) // 2 + nt]
         Gu = {t: syn.round_to_c64(syn.propagator_slice(L, self.cfg, syn.FIELD_G3, t)) for t in ts}
         s = {t: syn.round_to_c64(syn.solution_slice(L, self.N, self.cfg, t)) for t in ts}
         pairs = pairs_diag_or_zero(len(k))
@@ -495,6 +518,8 @@ class Nucleon48(Meson32):
         I = oracle.insertion(Gu, s, ts, L, self.T, k)
         oracle.combine(S, I[:ns], pairs=pairs)
         dt = time.perf_counter() - t0
+        # the same outputs as the step's (u,u) spectator noise 0..ns-1 and u insertion at ts
+        self.oracle_ref = {"spectator_baryon": S, "insertion": I}
         V3 = int(np.prod(L))
         units = ns * V3 * len(k) + self.N * nt * V3 * len(k)
         return units, dt, (f"FP64 numpy oracle: (u,u) nucleon spectator with {ns} of 8 noise vectors, u "
@@ -1206,7 +1231,13 @@ def main():
         flops = kf[kname] / launches
         kms = prof[kname]["total_ms"] / prof[kname]["count"]
     else:
-        kname, flops = W.dominant(n_mom, proj)
+        dom = W.dominant(n_mom, proj)
+        if isinstance(dom, dict):
+            cand = {kn: f for kn, f in dom.items() if kn in prof}
+            kname = max(cand, key=lambda kn: prof[kn]["total_ms"]) if cand else next(iter(dom))
+            flops = dom[kname]
+        else:
+            kname, flops = dom
         kms = prof.get(kname, {}).get("avg_ms", float("nan"))
     roofline = roofline_entry(kname, flops, kms, proj, measured_traffic(args.workload, proj, kname, getattr(W, "n_ops", 1)))
     if roofline["traffic"] is not None:
@@ -1214,6 +1245,30 @@ def main():
                                     "(copy-calibrated), measured on these kernel sources")
 
     plain = None
+    plain_proj = getattr(W, "plain_proj", None)
+    if not batched and plain_proj and plain_proj != proj:
+        # the plain FP32 form of the same step, timed the same way
+        pflag = {"fac": c3pt.PROJ_FACTORED, "f32": c3pt.PROJ_NATIVE}[plain_proj]
+        head_geom = W.geom
+        W.geom = c3pt.Geom(W.L, W.T, proj=pflag)
+        n_plain = max(3, min(args.steps, 10))
+        log(f"[bench] timing {n_plain} steps of the plain form ({plain_proj})")
+        W.step()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n_plain):
+            W.step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b) / n_plain
+        plain = {"proj": plain_proj, "ms_per_step": pms, "value": units / (pms * 1e-3),
+                 "form": "the same step with the FP32 factored projection (FP32 contraction on the VALU)",
+                 "speedup_of_headline": pms / ms_per_step}
+        W.plain_outputs = {kn: fn().cpu().numpy() for kn, fn in getattr(W, "sample_outputs", {}).items()}
+        W.geom = head_geom
+        W.step()
+        torch.cuda.synchronize()
     if batched and W.plain:
         log("[bench] timing the same jobs as plain per-call FP32 launches")
         W.plain_step()
@@ -1259,7 +1314,33 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a host sample")
         res["cpu_baseline"] = cpu_baseline(W, k, args.cpu_slices)
+        acc = sample_accuracy(W, proj, plain)
+        if acc:
+            res["accuracy"] = acc
     print(json.dumps(res), flush=True)
+
+
+def rel_err(got, want) -> float:
+    """The larger of ||got - want||_F / ||want||_F and max|got - want| / max|want|."""
+    d = (np.asarray(got) - np.asarray(want)).ravel()
+    w = np.asarray(want).ravel()
+    return float(max(np.linalg.norm(d) / np.linalg.norm(w), np.abs(d).max() / np.abs(w).max()))
+
+
+def sample_accuracy(W, proj, plain):
+    """Error of the headline form (and of the plain form, when timed) against
+    the FP64 oracle on the outputs the CPU-baseline sample computed; inputs
+    are the same seeded values, rounded to complex64 for both."""
+    ref = getattr(W, "oracle_ref", None)
+    if not ref:
+        return None
+    out = {"metric": "max(||d||_F/||ref||_F, max|d|/max|ref|) per part", proj: {}}
+    for kn, fn in W.sample_outputs.items():
+        out[proj][kn] = rel_err(fn().cpu().numpy(), ref[kn])
+    if plain is not None:
+        # the plain form's outputs were captured when it ran
+        out[plain["proj"]] = {kn: rel_err(v, ref[kn]) for kn, v in getattr(W, "plain_outputs", {}).items()}
+    return out
 
 
 if __name__ == "__main__":
