@@ -335,11 +335,12 @@ int c3pt_release_scratch(void);
  * mode 4 selects the form of the factored projection (C3PT_PROJ_FACTORED):
  * variant 0 writes every x3 plane's sums as a chunk of its own, variant 1
  * sums chunks of planes in registers first.  Mode 5 selects the form of the
- * split-precision fused projection (C3PT_PROJ_FACTORED_F16 / _BF16) for the
- * meson spectator and the insertion: variant 0 splits each propagator tile
- * into hi + lo parts in the kernel, variant 1 splits the call's slices once
- * in a pass before it (the nucleon spectator always forms its diquark in a
- * pass: one variant).
+ * split-precision fused projection (C3PT_PROJ_FACTORED_F16 / _BF16):
+ * variant 0 splits each propagator tile into hi + lo parts in the kernel and
+ * runs two column blocks per workgroup, variant 1 splits the call's slices
+ * once in a pass before it, variant 2 does that and runs one column block per
+ * workgroup (two workgroups per CU).  The nucleon spectator always forms its
+ * diquark in a pass (variants 0 and 1 are the same for it).
  * mt_class: momentum groups of up to 32, 64, 96, 128 momenta (0..3).
  * c3pt_variant_count returns the number of compiled variants (0 if none);
  * c3pt_set_variant selects one for later calls (process-wide);

@@ -229,9 +229,10 @@ int variant_count(int kind, int mode, int cls) {
     if (kind < 0 || kind >= kKinds || mode < 0 || mode >= kModes || cls < 0 || cls >= kMtClasses) return 0;
     // factored: 0 = every x3 plane written as its own chunk, 1 = chunks of planes summed in registers
     if (mode == kModeFacVariants) return 2;
-    // fused: 0 = propagator tiles split in the kernel, 1 = slices split by a pass first
-    // (the nucleon's diquark always has its pass)
-    if (mode == kModeFsVariants) return kind == 1 ? 1 : 2;
+    // fused: 0 = propagator tiles split in the kernel, two column blocks per workgroup;
+    // 1 = slices split by a pass first, two blocks; 2 = split pass, one block per
+    // workgroup (two workgroups per CU).  The nucleon's diquark always has its pass.
+    if (mode == kModeFsVariants) return 3;
     if (mode == kModeF64) return cls == 0 ? 1 : 0;
     return kVariantsPerClass[cls];
 }
@@ -586,18 +587,19 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
     const size_t bb = fs_block_bytes(geom->L);
     const int n_slots = baryon ? 16 : 1;
     const int ncb = N * n_slots;
-    const int n_per_share = n_slots * ((N + 1) / 2);
-    int cp, nch;
-    plan_planes(geom->L, n_per_share, &cp, &nch);
-    const size_t part_bytes = (size_t)nch * ncb * kMaxMomGroupF32 * kBlockCols * sizeof(float2);
-    void *part, *B;
-    if (int rc = fs_scratch(st, part_bytes, (size_t)n_slots * bb, &part, &B)) return rc;
     int fs_variant;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         fs_variant = g_variant[baryon ? 1 : 0][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
     }
-    const bool bsplit = baryon || fs_variant == 1;
+    const bool bsplit = baryon || fs_variant >= 1;
+    const int cbw = fs_variant == 2 ? 1 : 2;
+    const int n_per_share = n_slots * ((N + cbw - 1) / cbw);
+    int cp, nch;
+    plan_planes(geom->L, n_per_share, &cp, &nch);
+    const size_t part_bytes = (size_t)nch * ncb * kMaxMomGroupF32 * kBlockCols * sizeof(float2);
+    void *part, *B;
+    if (int rc = fs_scratch(st, part_bytes, (size_t)n_slots * bb, &part, &B)) return rc;
     if (!baryon && bsplit) {
         FsSplitArgs sa;
         memset(&sa, 0, sizeof(sa));
@@ -653,7 +655,7 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
         fa.G[0][0] = G1;
         fa.u0[0] = eta;
         if (int rc = to_status(timed(baryon ? "fs_spectator_baryon" : "fs_spectator_meson", st,
-                                     [&] { return launch_fs(bf16, KT, 0, bsplit, pg, fa, st); }),
+                                     [&] { return launch_fs(bf16, KT, 0, bsplit, cbw, pg, fa, st); }),
                                "projection launch"))
             return rc;
         ReduceArgs ra;
@@ -697,7 +699,8 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
         std::lock_guard<std::mutex> lk(g_mu);
         fs_variant = g_variant[2][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
     }
-    const bool bsplit = fs_variant == 1;
+    const bool bsplit = fs_variant >= 1;
+    const int cbw = fs_variant == 2 ? 1 : 2;
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
         FsArgs fa;
@@ -714,7 +717,7 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
             fa.u0[j] = s_t[t];
         }
         const int ncb = N * nt * n_slots;
-        const int n_per_share = n_slots * ((N + 1) / 2);
+        const int n_per_share = n_slots * ((N + cbw - 1) / cbw);
         int cp, nch;
         plan_planes(geom->L, n_per_share * nt, &cp, &nch);
         const size_t part_bytes = (size_t)nch * ncb * kMaxMomGroupF32 * kBlockCols * sizeof(float2);
@@ -778,7 +781,7 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
             pg.phase = tab;
             pg.partial = part;
             if (int rc = to_status(timed("fs_insertion", st,
-                                         [&] { return launch_fs(bf16, KT, kind, bsplit, pg, fa, st); }),
+                                         [&] { return launch_fs(bf16, KT, kind, bsplit, cbw, pg, fa, st); }),
                                    "projection launch"))
                 return rc;
             if (kind == 1) {

@@ -31,9 +31,10 @@
 // Each (nu, +-) is its own column block ("slot") of partial sums; the FP64
 // reduction applies the per-momentum factors and forms the difference.
 //
-// Workgroup: 8 waves = two column blocks (two noise vectors of one slot,
-// sharing the B tile in LDS) x four A indices; a wave owns one A index and all
-// 48 B columns as three 16-column MFMA tiles.  The tile loop is the factored
+// Workgroup: 4 CB waves = CB column blocks (CB = 2: two noise vectors of one
+// slot, sharing the B tile in LDS) x four A indices; a wave owns one A index
+// and all 48 B columns as three 16-column MFMA tiles.  With CB = 1 two
+// workgroups fit a CU and run their phases independently.  The tile loop is the factored
 // kernel's: tiles are KT sites of one x1 row, one workgroup barrier per tile,
 // B and u of the next tile staged while the current one is computed.
 #pragma once
@@ -96,40 +97,42 @@ __device__ __forceinline__ void fs_unroll(F&& f) {
     fs_expand(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int KT>
+template <int KT, int CB>
 struct FsShape {
+    static constexpr int NT = 256 * CB;            // threads: CB column blocks x four A indices
     static constexpr int GB = KT / 4;              // four-site groups per tile
     static constexpr int PSTR = GB * 32 + 16;      // LDS bytes per B plane (padded against bank conflicts)
     static constexpr int HS = KT / 16;             // MFMA K steps per summed colour (16 sites x re/im)
     static constexpr int MAXSEG = kMaxL / KT;      // row segments of the longest row
     static constexpr int W1S = KT + 2;             // W1 row stride (complex), padded
     static constexpr int NB16 = kFsPlanes * GB * 2;          // 16-byte pieces of a B tile
-    static constexpr int KB = (NB16 + kFsThreads - 1) / kFsThreads;
-    static_assert(KB * kFsThreads <= 2 * NB16, "repeated B pieces stay within the tile");
+    static constexpr int KB = (NB16 + NT - 1) / NT;
+    static_assert(KB * NT <= 2 * NB16, "repeated B pieces stay within the tile");
     static constexpr int NG = kFsPlanes * GB;      // four-site groups of a tile (FP32 source)
-    static constexpr int KG = (NG + kFsThreads - 1) / kFsThreads;
-    static_assert(KG * kFsThreads <= 2 * NG, "repeated groups stay within the tile");
-    static constexpr int NU = 24 * KT;             // staged u values per tile (2 blocks x 12 x KT)
-    static constexpr int KU = (NU + kFsThreads - 1) / kFsThreads;
+    static constexpr int KG = (NG + NT - 1) / NT;
+    static_assert(KG * NT <= 2 * NG, "repeated groups stay within the tile");
+    static constexpr int NU = 12 * CB * KT;        // staged u values per tile (CB blocks x 12 x KT)
+    static constexpr int KU = (NU + NT - 1) / NT;
 };
 
-template <int KT>
+template <int KT, int CB>
 struct FsSmem {
-    using S = FsShape<KT>;
+    using S = FsShape<KT, CB>;
     alignas(16) unsigned char B[2][kFsPlanes * S::PSTR];
-    alignas(16) C2<float> U[2][2][12][KT];                   // [buffer][block of the pair][3 at + c][x1]
+    alignas(16) C2<float> U[2][CB][12][KT];                  // [buffer][block][3 at + c][x1]
     alignas(16) C2<float> W1[S::MAXSEG][kFacMaxK1][S::W1S];  // w1^(k1 (seg KT + x1)); zero for unused slots
     C2<float> coef2[2][kFacMaxPairsF32 + kFacMaxBPerA];
     C2<float> root[3][kMaxL];
     FactorPlan plan;
 };
 
-template <typename T16, int KT, int KIND, bool BSPLIT>
-__global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs fa) {
-    using S = FsShape<KT>;
+template <typename T16, int KT, int KIND, bool BSPLIT, int CB>
+__global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
+    using S = FsShape<KT, CB>;
+    constexpr int NT = S::NT;
     using MF = Mfma16<T16>;
     using vec_t = typename MF::vec_t;
-    __shared__ FsSmem<KT> sm;
+    __shared__ FsSmem<KT, CB> sm;
     const int tid = threadIdx.x;
     const int lane = tid & 63, g = lane >> 4, cl = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -143,9 +146,9 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
     const int chunk = rest % pg.n_chunks;
     const int share = rest / pg.n_chunks;
     const int N = fa.N;
-    const int npair = (N + 1) >> 1;
-    const int slot = within / npair;
-    const int i0 = 2 * (within % npair);
+    const int ngroup = (N + CB - 1) / CB;
+    const int slot = within / ngroup;
+    const int i0 = CB * (within % ngroup);
     const bool valid = i0 + cbj < N;   // an odd noise count leaves the second block of the last pair empty
     const int cb = ((min(i0 + cbj, N - 1) * fa.n_share + share) * fa.n_slots + slot);
     const int L1 = fa.L[0], L2 = fa.L[1], L3 = fa.L[2];
@@ -168,9 +171,9 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
     {
         const int* src = (const int*)pg.phase;
         int* dst = (int*)&sm.plan;
-        for (int i = tid; i < (int)(sizeof(FactorPlan) / sizeof(int)); i += kFsThreads) dst[i] = src[i];
+        for (int i = tid; i < (int)(sizeof(FactorPlan) / sizeof(int)); i += NT) dst[i] = src[i];
         const int sigma = ((const FactorPlan*)pg.phase)->sigma;
-        for (int i = tid; i < 3 * kMaxL; i += kFsThreads) {
+        for (int i = tid; i < 3 * kMaxL; i += NT) {
             const int j = i / kMaxL, x = i % kMaxL;
             const int L = fa.L[j];
             C2<float> wv = {0.f, 0.f};
@@ -183,7 +186,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
         }
     }
     __syncthreads();
-    for (int e = tid; e < nseg * kFacMaxK1 * KT; e += kFsThreads) {
+    for (int e = tid; e < nseg * kFacMaxK1 * KT; e += NT) {
         const int seg = e / (kFacMaxK1 * KT), rem = e % (kFacMaxK1 * KT);
         const int a = rem / KT, x = rem % KT;
         const int x1 = seg * KT + x;
@@ -236,7 +239,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
     if constexpr (!BSPLIT) {
         fs_unroll<S::KG>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            const int e0 = tid + k * kFsThreads;
+            const int e0 = tid + k * NT;
             const int e = e0 < S::NG ? e0 : e0 - S::NG;
             const int p = e / S::GB, X = p % 48, cs = p / 48;
             goff[k] = (unsigned)((3 * (X / 12) + cs) * 12 + X % 12) * (unsigned)V3;
@@ -252,7 +255,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
                 constexpr int k = decltype(kc)::value;
                 // pieces past the tile's end repeat earlier ones (the same value is
                 // stored twice), so every thread loads and stores unconditionally
-                const int e0 = tid + k * kFsThreads;
+                const int e0 = tid + k * NT;
                 const int e = e0 < S::NB16 ? e0 : e0 - S::NB16;
                 const int p = e / (2 * S::GB), r = e % (2 * S::GB);
                 breg[k] = *(const u32x4*)(Bg + (((size_t)p * fa.rows) * (size_t)(fa.Lp / 4) + rowoff) * 32 + r * 16);
@@ -269,7 +272,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
         }
         fs_unroll<S::KU>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            const int e = tid + k * kFsThreads;
+            const int e = tid + k * NT;
             if (e >= S::NU) return;
             const int bj = e / (12 * KT), rem = e % (12 * KT);
             const int A = rem / KT, xl = rem % KT;
@@ -311,7 +314,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
         if constexpr (BSPLIT) {
             fs_unroll<S::KB>([&](auto kc) __attribute__((always_inline)) {
                 constexpr int k = decltype(kc)::value;
-                const int e0 = tid + k * kFsThreads;
+                const int e0 = tid + k * NT;
                 const int e = e0 < S::NB16 ? e0 : e0 - S::NB16;
                 const int p = e / (2 * S::GB), r = e % (2 * S::GB);
                 *(u32x4*)(sm.B[buf] + p * S::PSTR + r * 16) = breg[k];
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
         } else {
             fs_unroll<S::KG>([&](auto kc) __attribute__((always_inline)) {
                 constexpr int k = decltype(kc)::value;
-                const int e0 = tid + k * kFsThreads;
+                const int e0 = tid + k * NT;
                 const int e = e0 < S::NG ? e0 : e0 - S::NG;
                 const int p = e / S::GB, gi = e % S::GB;
                 const int X = p % 48;
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
         }
         fs_unroll<S::KU>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            const int e = tid + k * kFsThreads;
+            const int e = tid + k * NT;
             if (e >= S::NU) return;
             const int bj = e / (12 * KT), rem = e % (12 * KT);
             const int A = rem / KT, xl = rem % KT;
@@ -368,7 +371,7 @@ __global__ void __launch_bounds__(kFsThreads, 1) fs_kernel(ProjGrid pg, FsArgs f
         });
     };
     auto fill_coef2 = [&](int par, int x2) __attribute__((always_inline)) {
-        for (int b = tid; b < n12 + kFacMaxBPerA; b += kFsThreads)
+        for (int b = tid; b < n12 + kFacMaxBPerA; b += NT)
             sm.coef2[par][b] = b < n12 ? sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)] : C2<float>{0.f, 0.f};
     };
 

@@ -194,27 +194,42 @@ hipError_t launch_fs_reduce(const FsReduceArgs& a, hipStream_t st) {
 }
 
 template <typename T16, int KT>
-static hipError_t launch_fs_t(int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
-    const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(kFsThreads);
+static hipError_t launch_fs_t(int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+    const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks);
+    if (cb == 1) {
+        if (!bsplit) return hipErrorInvalidValue;
+        const dim3 block(256);
+        if (kind == 0)
+            hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true, 1>), grid, block, 0, st, pg, a);
+        else if (kind == 1)
+            hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true, 1>), grid, block, 0, st, pg, a);
+        else
+            hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true, 1>), grid, block, 0, st, pg, a);
+        return hipGetLastError();
+    }
+    const dim3 block(512);
     if (kind == 0 && bsplit)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true>), grid, block, 0, st, pg, a);
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true, 2>), grid, block, 0, st, pg, a);
     else if (kind == 0)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, false>), grid, block, 0, st, pg, a);
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, false, 2>), grid, block, 0, st, pg, a);
     else if (kind == 1 && bsplit)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true>), grid, block, 0, st, pg, a);
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true, 2>), grid, block, 0, st, pg, a);
     else if (kind == 1)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, false>), grid, block, 0, st, pg, a);
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, false, 2>), grid, block, 0, st, pg, a);
     else if (bsplit)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true>), grid, block, 0, st, pg, a);
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true, 2>), grid, block, 0, st, pg, a);
     else
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, false>), grid, block, 0, st, pg, a);
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, false, 2>), grid, block, 0, st, pg, a);
     return hipGetLastError();
 }
 
-hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a,
+                     hipStream_t st) {
     if (bf16)
-        return KT == 32 ? launch_fs_t<__bf16, 32>(kind, bsplit, pg, a, st) : launch_fs_t<__bf16, 16>(kind, bsplit, pg, a, st);
-    return KT == 32 ? launch_fs_t<_Float16, 32>(kind, bsplit, pg, a, st) : launch_fs_t<_Float16, 16>(kind, bsplit, pg, a, st);
+        return KT == 32 ? launch_fs_t<__bf16, 32>(kind, bsplit, cb, pg, a, st)
+                        : launch_fs_t<__bf16, 16>(kind, bsplit, cb, pg, a, st);
+    return KT == 32 ? launch_fs_t<_Float16, 32>(kind, bsplit, cb, pg, a, st)
+                    : launch_fs_t<_Float16, 16>(kind, bsplit, cb, pg, a, st);
 }
 
 }  // namespace c3pt

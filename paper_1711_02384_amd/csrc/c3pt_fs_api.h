@@ -5,7 +5,6 @@
 
 namespace c3pt {
 
-constexpr int kFsThreads = 512;
 constexpr int kFsPlanes = 144;   // 3 summed colours x 48 B columns
 
 // Kernel arguments besides the grid.
@@ -71,7 +70,9 @@ inline size_t fs_block_bytes(const int L[3]) { return (size_t)kFsPlanes * L[1] *
 
 hipError_t launch_fs_split(bool bf16, const FsSplitArgs& a, hipStream_t st);
 hipError_t launch_fs_diquark(bool bf16, const FsDiquarkArgs& a, hipStream_t st);
-hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st);
+// cb: column blocks per workgroup (1 or 2; 2 needs bsplit or kind 0 .. 2 alike, 1 needs bsplit)
+hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a,
+                     hipStream_t st);
 hipError_t launch_fs_reduce(const FsReduceArgs& a, hipStream_t st);
 
 }  // namespace c3pt

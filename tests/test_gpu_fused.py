@@ -45,15 +45,16 @@ CASES = [
 
 
 def _set_fused_variant(c3pt, v):
-    for kind in (0, 2):
+    for kind in (0, 1, 2):
         for cls in range(4):
             c3pt.set_variant(kind, c3pt.MODE["fs16"], cls, v)
 
 
-@pytest.mark.parametrize("prec,variant", [("f16", 0), ("f16", 1), ("bf16", 0)])
+@pytest.mark.parametrize("prec,variant", [("f16", 0), ("f16", 1), ("f16", 2), ("bf16", 0)])
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_fused_parts(case, prec, variant):
-    """variant 0 splits the propagator tiles in the kernel, 1 in a pass first."""
+    """variant 0 splits the propagator tiles in the kernel, 1 in a pass first, 2 with one
+    column block per workgroup."""
     import paper_1711_02384_amd as c3pt
     L, T, taus, N, n2, r = CASES[case]
     k = c3pt.momentum_list(n2)
