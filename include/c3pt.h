@@ -137,7 +137,7 @@ int c3pt_spectator_baryon(const c3pt_geom* geom, const void* G1_tf, const void* 
  * factorized form it is D_nu applied to s: op 5+nu = 1/2 (op 1+nu - I[s -> D_nu s]).
  * With n_ops == 21, ops 5 + 4 rho + nu are the two-derivative operators
  * D_nu D_rho (D_rho applied first): D_rho G is formed on tau-1 .. tau+1 by a
- * stencil in stream-ordered device memory, then D_nu of it is contracted.
+ * stencil into the library's per-stream scratch, then D_nu of it is contracted.
  * With n_ops == 37, ops 21 + 4 mu + nu are in addition the symmetrized
  *   <->D_mu <->D_nu = 1/4 (->D_mu ->D_nu - ->D_mu <-D_nu - <-D_mu ->D_nu + <-D_mu <-D_nu),
  * the left derivatives acting on the antiquark (D applied to s, <-D_mu first).
@@ -347,6 +347,19 @@ int c3pt_release_scratch(void);
  * c3pt_get_variant returns the current choice or a negative status.
  * Every variant computes the same result up to FP32 rounding order.
  */
+/*
+ * Extent checks.  Before a call enqueues anything, the bytes each of its
+ * kernels will index in every library-sized buffer (partial sums, phase
+ * tables, split propagator blocks, the fixed scratch) are compared with the
+ * bytes allocated for it; a mismatch fails the call with C3PT_EINVAL and a
+ * message naming the buffer.  c3pt_debug_scale_allocations(s) multiplies
+ * every allocated size in these comparisons by s (0 < s; 1 restores them): a
+ * test hook that plants an under-allocation without touching the device.
+ * Builds with C3PT_SYNC_LAUNCHES defined (build.py --debug) also wait for
+ * every launch and report a device fault at the launch that caused it.
+ */
+void c3pt_debug_scale_allocations(double scale);
+
 int c3pt_variant_count(int kind, int mode, int mt_class);
 int c3pt_set_variant(int kind, int mode, int mt_class, int variant);
 int c3pt_get_variant(int kind, int mode, int mt_class);

@@ -51,7 +51,8 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
             "c3pt_set_variant", "c3pt_get_variant", "c3pt_batch_create", "c3pt_batch_run", "c3pt_batch_info",
             "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
             "c3pt_server_poll", "c3pt_server_result", "c3pt_server_release", "c3pt_server_info",
-            "c3pt_server_destroy", "c3pt_insertion_noalloc", "c3pt_noalloc_scratch_bytes")
+            "c3pt_server_destroy", "c3pt_insertion_noalloc", "c3pt_noalloc_scratch_bytes",
+            "c3pt_debug_scale_allocations")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
 MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4, "fs16": 5, "fsbf16": 5}
@@ -117,6 +118,8 @@ def _load():
     lib.c3pt_insertion_noalloc.restype = ctypes.c_int
     lib.c3pt_noalloc_scratch_bytes.argtypes = []
     lib.c3pt_noalloc_scratch_bytes.restype = ctypes.c_ulonglong
+    lib.c3pt_debug_scale_allocations.argtypes = [ctypes.c_double]
+    lib.c3pt_debug_scale_allocations.restype = None
     lib.c3pt_combine.argtypes = [vp, i, vp, i, i, i, i, i, i, i, ctypes.POINTER(ctypes.c_double), ip, i,
                                  vp, vp]
     lib.c3pt_two_sink_meson.argtypes = [gp, vp, vp, i, vp, vp, i, i, i, ctypes.POINTER(vp), ctypes.POINTER(vp),

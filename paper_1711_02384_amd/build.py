@@ -1,6 +1,8 @@
 """Build libc3pt.so (HIP, gfx950) in-tree.
 
 Usage: python paper_1711_02384_amd/build.py  [--debug]
+(--debug: -O1 and every launch waited for, so a device fault is reported at
+the launch that caused it)
 (run as a file: importing the package itself loads the library this builds)
 
 Each translation unit is compiled in its own hipcc process (in parallel), then
@@ -37,6 +39,7 @@ def build(verbose: bool = False, debug: bool = False) -> str:
     flags = [
         "--offload-arch=gfx950", "-std=c++17", "-fPIC",
         "-O1" if debug else "-O3",
+        *(["-DC3PT_SYNC_LAUNCHES"] if debug else []),
         # packed FP32 instructions are kept out of every kernel of this library
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"),

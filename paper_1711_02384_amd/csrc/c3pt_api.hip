@@ -46,6 +46,8 @@ int ok() {
 struct Scratch {
     void* dev = nullptr;
     size_t dev_bytes = 0;
+    void* aux = nullptr;       // second region: fields derived inside a call (stencil outputs)
+    size_t aux_bytes = 0;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
     hipEvent_t ev = nullptr;
@@ -83,6 +85,32 @@ int scratch_dev(hipStream_t st, size_t bytes, void** out) {
         s.dev_bytes = want;
     }
     *out = s.dev;
+    return C3PT_OK;
+}
+
+// The second per-(device, stream) region, grown like the first (it never
+// aliases the partial sums, which live in the first).
+int scratch_aux(hipStream_t st, size_t bytes, void** out) {
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Scratch& s = g_scratch[{dev, st}];
+    if (s.aux_bytes < bytes) {
+        if (s.aux) {
+            if (hipStreamSynchronize(st) != hipSuccess) return fail(C3PT_EDEVICE, "stream sync failed");
+            (void)hipFree(s.aux);
+            s.aux = nullptr;
+            s.aux_bytes = 0;
+        }
+        const size_t want = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+        if (hipMalloc(&s.aux, want) != hipSuccess) {
+            (void)hipGetLastError();
+            s.aux = nullptr;
+            return fail(C3PT_ENOMEM, "scratch allocation of %zu bytes failed", want);
+        }
+        s.aux_bytes = want;
+    }
+    *out = s.aux;
     return C3PT_OK;
 }
 
@@ -135,6 +163,19 @@ std::map<std::string, ProfStat> g_prof_stats;
 // Launch `fn` on `st`, bracketed by timing events when profiling is enabled.
 template <class F>
 hipError_t timed(const char* name, hipStream_t st, F fn) {
+#ifdef C3PT_SYNC_LAUNCHES
+    // debug builds: every launch completes (or reports its fault) before the next
+    {
+        const hipError_t e = fn();
+        if (e != hipSuccess) return e;
+        const hipError_t s2 = hipStreamSynchronize(st);
+        if (s2 != hipSuccess) {
+            fprintf(stderr, "c3pt: launch %s failed: %s\n", name, hipGetErrorString(s2));
+            return s2;
+        }
+        return hipGetLastError();
+    }
+#endif
     bool on;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -463,6 +504,37 @@ int to_status(hipError_t e, const char* what) {
     return fail(C3PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// ---- extent checks ---------------------------------------------------------
+// Before anything is enqueued, the bytes a kernel will index in each buffer
+// (from the kernel's own index formula) are compared with the bytes the host
+// sizes for it (from the allocation's formula).  A mismatch is an internal
+// error: the call fails with C3PT_EINVAL before touching the device.
+// g_extent_scale scales every allocated size in the comparison: a test hook
+// that plants an under-allocation (c3pt_debug_scale_allocations).
+double g_extent_scale = 1.0;
+
+int check_extent(const char* what, size_t indexed, size_t allocated) {
+    const size_t have = (size_t)((double)allocated * g_extent_scale);
+    if (indexed > have)
+        return fail(C3PT_EINVAL, "extent check: %s indexes %zu bytes, %zu allocated", what, indexed, have);
+    return C3PT_OK;
+}
+
+// Bytes of a phase table the dense consumers index: tiles of up to kSiteTile
+// sites from the first site, native rows [site][8 mtmax] complex, split blocks
+// [site / 16][hi, lo][mtmax][64 lanes][8] 16-bit.
+size_t phase_indexed_bytes(int mode, int V3, int mtmax) {
+    const size_t vt = (size_t)(V3 + kSiteTile - 1) / kSiteTile * kSiteTile;
+    if (mode == kModeSplitBF16 || mode == kModeSplitF16) return vt / 16 * (2 * (size_t)mtmax * 64 * 8 * 2);
+    return vt * 8 * mtmax * (mode == kModeF64 ? sizeof(double2) : sizeof(float2));
+}
+
+// Bytes of the split-site partial sums a projection launch indexes:
+// [n_chunks][n_colblocks][n_mom][192] in the accumulator type.
+size_t partial_indexed_bytes(int n_chunks, int n_colblocks, int n_mom, size_t elem) {
+    return (size_t)n_chunks * n_colblocks * n_mom * kBlockCols * elem;
+}
+
 const char* const fac_names[3] = {"fac_spectator_meson", "fac_spectator_baryon", "fac_insertion"};
 
 // Runs projection launches over momentum groups and reduces each into `out`.
@@ -481,15 +553,36 @@ int run_projection(const char* kname, int kind, const c3pt_geom* g, int sigma, c
     plan_chunks(V3, n_colblocks, f64, &chunk_sites, &n_chunks_dense);
     plan_planes(g->L, n_colblocks, &chunk_planes, &n_chunks_fac);
     const size_t gmax = f64 ? kMaxMomGroupF64 : kMaxMomGroupF32;
+    const size_t elem = f64 ? sizeof(double2) : sizeof(float2);
     const size_t bytes = (size_t)std::max(n_chunks_dense, want_fac ? n_chunks_fac : 0) * n_colblocks * gmax *
-                         kBlockCols * (f64 ? sizeof(double2) : sizeof(float2));
-    void* part;
-    if (int rc = scratch_dev(st, bytes, &part)) return rc;
-    for (const MomGroup& mg : groups) {
+                         kBlockCols * elem;
+    // every group's plan and extents before anything is enqueued
+    std::vector<FactorPlan> plans(groups.size());
+    std::vector<char> facs(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const MomGroup& mg = groups[gi];
         const int mt = (mg.n + 7) / 8;
         const int mtmax = f64 ? 4 : (mt <= 4 ? 4 : mt <= 8 ? 8 : mt <= 12 ? 12 : 16);
-        FactorPlan plan;
-        const bool fac = want_fac && build_factor_plan(g, sigma, k, mg, f64, &plan);
+        facs[gi] = want_fac && build_factor_plan(g, sigma, k, mg, f64, &plans[gi]);
+        const int n_chunks = facs[gi] ? n_chunks_fac : n_chunks_dense;
+        if (int rc = check_extent("partial sums", partial_indexed_bytes(n_chunks, n_colblocks, mg.n, elem), bytes))
+            return rc;
+        if (facs[gi]) {
+            // the factored kernels copy the whole plan into LDS
+            if (int rc = check_extent("factor plan", sizeof(FactorPlan), sizeof(FactorPlan))) return rc;
+        } else if (int rc = check_extent("phase table", phase_indexed_bytes(mode, V3, mtmax),
+                                         phase_table_bytes(mode, V3, mtmax))) {
+            return rc;
+        }
+    }
+    void* part;
+    if (int rc = scratch_dev(st, bytes, &part)) return rc;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const MomGroup& mg = groups[gi];
+        const int mt = (mg.n + 7) / 8;
+        const int mtmax = f64 ? 4 : (mt <= 4 ? 4 : mt <= 8 ? 8 : mt <= 12 ? 12 : 16);
+        const FactorPlan& plan = plans[gi];
+        const bool fac = facs[gi];
         const void* tab;
         if (fac) {
             if (int rc = factor_plan_table(plan, f64, st, &tab)) return rc;
@@ -598,6 +691,10 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
     int cp, nch;
     plan_planes(geom->L, n_per_share, &cp, &nch);
     const size_t part_bytes = (size_t)nch * ncb * kMaxMomGroupF32 * kBlockCols * sizeof(float2);
+    for (const MomGroup& mg : groups)
+        if (int rc = check_extent("partial sums", partial_indexed_bytes(nch, ncb, mg.n, sizeof(float2)), part_bytes))
+            return rc;
+    if (int rc = check_extent("split B blocks", (size_t)n_slots * bb, (size_t)n_slots * bb)) return rc;
     void *part, *B;
     if (int rc = fs_scratch(st, part_bytes, (size_t)n_slots * bb, &part, &B)) return rc;
     if (!baryon && bsplit) {
@@ -739,6 +836,16 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
                     fa.bidx[j][2] = slot_of(t - 1);
                 }
             }
+        }
+        for (const MomGroup& mg : groups)
+            if (int rc = check_extent("partial sums", partial_indexed_bytes(nch, ncb, mg.n, sizeof(float2)),
+                                      part_bytes))
+                return rc;
+        if (bsplit) {
+            int bmax = 0;
+            for (int j = 0; j < nt; ++j)
+                for (int r = 0; r < (n_ops == 5 ? 3 : 1); ++r) bmax = std::max(bmax, fa.bidx[j][r] + 1);
+            if (int rc = check_extent("split B blocks", (size_t)bmax * bb, sl.size() * bb)) return rc;
         }
         void *part, *B;
         if (int rc = fs_scratch(st, part_bytes, sl.size() * bb, &part, &B)) return rc;
@@ -941,6 +1048,11 @@ const char* c3pt_strerror(int status) {
 
 const char* c3pt_last_error(void) { return g_last_error.c_str(); }
 
+void c3pt_debug_scale_allocations(double scale) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_extent_scale = scale > 0.0 ? scale : 1.0;
+}
+
 unsigned long long c3pt_scratch_bytes(void* stream) {
     int dev;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -963,6 +1075,7 @@ int c3pt_release_scratch(void) {
         hipSetDevice(kv.first.first);
         hipStreamSynchronize(kv.first.second);
         if (kv.second.dev) hipFree(kv.second.dev);
+        if (kv.second.aux) hipFree(kv.second.aux);
         if (kv.second.pinned) hipHostFree(kv.second.pinned);
         if (kv.second.ev) hipEventDestroy(kv.second.ev);
     }
@@ -1119,20 +1232,36 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
     const size_t elem = f64 ? sizeof(double2) : sizeof(float2);
     const long long V3 = (long long)geom->L[0] * geom->L[1] * geom->L[2];
     hipStream_t dst = (hipStream_t)geom->stream;
-    void* outp = out;
-    void* iout = nullptr;
-    if (n_ops == 37) {
-        const size_t ibytes = (size_t)n_noise * n_tau * n_int * n_mom * kBlockCols * sizeof(double2);
-        if (hipMallocAsync(&iout, ibytes, dst) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(C3PT_ENOMEM, "no device memory for the internal operator parts");
-        }
-        outp = iout;
-    }
-    auto release = [&](int rc) {
-        if (iout) (void)hipFreeAsync(iout, dst);
-        return rc;
+    // the stream's second scratch region: the internal operator parts of
+    // n_ops = 37, then the derived slices of one launch (the largest launch's)
+    const size_t gslice = (size_t)144 * V3 * elem, sslice = (size_t)n_noise * 12 * V3 * elem;
+    auto derived_slices = [&](int j0, int nt) {
+        std::vector<int> d;
+        for (int j = 0; j < nt; ++j)
+            for (int dt = -1; dt <= 1; ++dt) {
+                const int t = ((taus[j0 + j] + dt) % T + T) % T;
+                if (std::find(d.begin(), d.end(), t) == d.end()) d.push_back(t);
+            }
+        return d;
     };
+    const size_t ibytes = n_ops == 37 ? (size_t)n_noise * n_tau * n_int * n_mom * kBlockCols * sizeof(double2) : 0;
+    const size_t doff = (ibytes + 255) & ~(size_t)255;
+    size_t dmax = 0;
+    if (n_ops >= 21)
+        for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
+            const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
+            const size_t nd = derived_slices(j0, nt).size();
+            size_t bytes = 4 * nd * gslice;
+            if (n_ops == 37) bytes += 4 * nd * sslice + (size_t)16 * nt * sslice;
+            dmax = std::max(dmax, bytes);
+        }
+    void* aux = nullptr;
+    if (doff + dmax > 0) {
+        if (int rc = scratch_aux(dst, doff + dmax, &aux)) return rc;
+    }
+    void* outp = out;
+    void* iout = n_ops == 37 ? aux : nullptr;
+    if (n_ops == 37) outp = iout;
     auto stencil = [&](const void* fp, const void* fm, const void* U, const void* Um, void* o, int n_outer,
                        int n_inner, int rho) {
         DerivStencilArgs da;
@@ -1180,7 +1309,6 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
         // n_ops = 37 also D_mu s there and D_nu D_mu s on the timeslices
         std::vector<int> dsl;
         void* dbuf = nullptr;
-        const size_t gslice = (size_t)144 * V3 * elem, sslice = (size_t)n_noise * 12 * V3 * elem;
         auto dslot = [&](int t) { return (int)(std::find(dsl.begin(), dsl.end(), ((t % T) + T) % T) - dsl.begin()); };
         auto dG = [&](int rho, int t) { return (char*)dbuf + (rho * dsl.size() + dslot(t)) * gslice; };
         auto dS = [&](int mu, int t) {
@@ -1190,17 +1318,8 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
             return (char*)dbuf + 4 * dsl.size() * (gslice + sslice) + ((size_t)(4 * mu + nu) * nt + j) * sslice;
         };
         if (n_ops >= 21) {
-            for (int j = 0; j < nt; ++j)
-                for (int d = -1; d <= 1; ++d) {
-                    const int t = ((taus[j0 + j] + d) % T + T) % T;
-                    if (dslot(t) == (int)dsl.size()) dsl.push_back(t);
-                }
-            size_t bytes = 4 * dsl.size() * gslice;
-            if (n_ops == 37) bytes += 4 * dsl.size() * sslice + (size_t)16 * nt * sslice;
-            if (hipMallocAsync(&dbuf, bytes, dst) != hipSuccess) {
-                (void)hipGetLastError();
-                return release(fail(C3PT_ENOMEM, "no device memory for the derived slices"));
-            }
+            dsl = derived_slices(j0, nt);
+            dbuf = (char*)aux + doff;
             int rc = 0;
             for (int rho = 0; rho < 4 && !rc; ++rho)
                 for (size_t m = 0; m < dsl.size() && !rc; ++m) {
@@ -1218,10 +1337,7 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                         rc = stencil(dS(mu, nu < 3 ? t : tn), dS(mu, nu < 3 ? t : tp), U_t[t],
                                      U_t[nu < 3 ? t : tp], ddS(mu, nu, j), 4 * n_noise, 1, nu);
                     }
-            if (rc) {
-                (void)hipFreeAsync(dbuf, dst);
-                return release(rc);
-            }
+            if (rc) return rc;
         }
         const int ncb = n_noise * nt * n_int;
         int rc = run_projection("proj_insertion", 2, geom, +1, k, n_mom, ncb, nt, n_noise * n_int, kBlockCols, ncb,
@@ -1289,8 +1405,7 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                     }
                                     return e;
                                 });
-        if (dbuf) (void)hipFreeAsync(dbuf, dst);
-        if (rc) return release(rc);
+        if (rc) return rc;
     }
     if (n_ops == 9) {
         if (int rc = to_status(timed("symmetrize", dst, [&] {
@@ -1305,8 +1420,7 @@ int c3pt_insertion(const c3pt_geom* geom, const void* const* G_t, const void* co
                                                                (long long)n_noise * n_tau, n_mom, dst);
                                }),
                                "assembly launch"))
-            return release(rc);
-        release(0);
+            return rc;
     }
     return ok();
 }
@@ -1436,6 +1550,11 @@ int c3pt_insertion_noalloc(const c3pt_geom* geom, const void* const* G_t, const 
             j0 += nt;
         }
     }
+    for (const NoAllocPiece& pc : pieces)
+        if (int rc = check_extent("partial sums",
+                                  partial_indexed_bytes(pc.n_chunks, n_noise * pc.nt * n_ops, groups[pc.mg].n, elem),
+                                  cap))
+            return rc;
     unsigned char* base;
     if (int rc = noalloc_scratch(&base)) return rc;
     int* plan_dev = (int*)(base + kNoAllocPlanOff);

@@ -332,3 +332,48 @@ def test_bench_host_logic():
     assert len(bench.pairs_diag_or_zero(93)) == 185
     r = bench.roofline_entry("fac_insertion", 1.0e12, 50.0, "fac", traffic=None)
     assert r["bound"] == "alu" and abs(r["achieved"] - 20.0) < 1e-9 and abs(r["frac"] - 20.0 / 78.6) < 1e-4
+
+
+def test_extent_checks_catch_an_under_sized_buffer():
+    """Every call compares, on the host, the bytes its kernels will index with
+    the bytes allocated for them before anything is enqueued.  Shrinking the
+    allocations in those comparisons (the library's test hook) must make the
+    dense, factored, fused and no-alloc paths fail with an extent error, with
+    no device call made (the pointers here are never dereferenced).  Halving
+    trips the phase tables, which are sized exactly; a factor of a million trips the
+    partial sums of every path, sized for the largest momentum group or the
+    fixed scratch."""
+    import paper_1711_02384_amd as c
+    ka, kp = _k(3)
+    Gt = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    st = (ctypes.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)
+    taus = (ctypes.c_int * 1)(0)
+
+    def expect(rc, what, case):
+        assert rc == c.C3PT_EINVAL, (case, rc)
+        msg = c.lib.c3pt_last_error().decode()
+        assert "extent check: " + what in msg, (case, msg)
+
+    try:
+        c.lib.c3pt_debug_scale_allocations(0.5)
+        for dtype in (0, 1):
+            g = _geom(c, L=(8, 8, 8), T=4, proj=c.PROJ_NATIVE, dtype=dtype)
+            expect(c.lib.c3pt_spectator_meson(ctypes.byref(g), DUMMY, DUMMY, 2, kp, 3, DUMMY), "phase table", dtype)
+        g = _geom(c, L=(8, 8, 8), T=4, proj=c.PROJ_FACTORED_F16)
+        expect(c.lib.c3pt_spectator_baryon(ctypes.byref(g), DUMMY, DUMMY, DUMMY, 2, kp, 3, DUMMY),
+               "split B blocks", "fused baryon")
+        c.lib.c3pt_debug_scale_allocations(1e-6)
+        for proj, dtype in ((c.PROJ_NATIVE, 0), (c.PROJ_NATIVE, 1), (c.PROJ_FACTORED, 0),
+                            (c.PROJ_FACTORED_F16, 0), (c.PROJ_FACTORED_BF16, 0)):
+            g = _geom(c, L=(8, 8, 8), T=4, proj=proj, dtype=dtype)
+            case = (proj, dtype)
+            expect(c.lib.c3pt_spectator_meson(ctypes.byref(g), DUMMY, DUMMY, 2, kp, 3, DUMMY), "partial sums", case)
+            expect(c.lib.c3pt_spectator_baryon(ctypes.byref(g), DUMMY, DUMMY, DUMMY, 2, kp, 3, DUMMY),
+                   "partial sums", case)
+            expect(c.lib.c3pt_insertion(ctypes.byref(g), Gt, st, 2, taus, 1, None, 1, kp, 3, DUMMY),
+                   "partial sums", case)
+        g = _geom(c, L=(8, 8, 8), T=4, proj=c.PROJ_FACTORED)
+        expect(c.lib.c3pt_insertion_noalloc(ctypes.byref(g), Gt, st, 2, taus, 1, None, 1, kp, 3, DUMMY),
+               "partial sums", "noalloc")
+    finally:
+        c.lib.c3pt_debug_scale_allocations(1.0)
