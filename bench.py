@@ -204,6 +204,22 @@ def roofline_entry(kname, flops, kms, proj, traffic=None):
     return r
 
 
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_F16 = 2500.0   # dense FP16 / BF16 MFMA, TFLOP/s
+
+
+def fused_mfma_flops(L, N, n_slots, n_share, n_groups=1, cb=2):
+    """MFMA flops the fused split-precision kernel issues in one launch: every
+    wave (four per column block, CB blocks per workgroup, ceil(N / CB)
+    workgroups per slot and share) runs, per tile of KT sites of one (x2, x3)
+    row, 3 summed colours x KT / 16 K steps x 3 column tiles x 3 products
+    (lo.hi, hi.lo, hi.hi) of a 16x16x32 MFMA (16384 flops)."""
+    kt = 32 if L[0] % 32 == 0 else 16
+    tiles = L[1] * L[2] * ((L[0] + kt - 1) // kt)
+    waves = 4 * cb * ((N + cb - 1) // cb) * n_slots * n_share * n_groups
+    return float(waves) * tiles * 27 * (kt // 16) * 16384
+
+
 def pairs_diag_or_zero(n_mom):
     """(p', q) pairs with p' = q or p' = 0 (index 0 is k = 0)."""
     pr = [(p, p) for p in range(n_mom)] + [(0, q) for q in range(1, n_mom)]
@@ -498,6 +514,19 @@ class Nucleon48(Meson32):
         cols = self.N * 3072
         return "proj_spectator_baryon", 8.0 * n_mom * V3 * cols
 
+    def mfma_flops(self, kname, proj):
+        """MFMA flops issued per launch of the fused kernels (one momentum group)."""
+        if proj not in ("fs16", "fsbf16") or len(self.k) > 128:
+            return None
+        c = self.c3pt
+        kind = 1 if kname == "fs_spectator_baryon" else 2
+        cb = 1 if c.get_variant(kind, c.MODE[proj], c.mt_class(len(self.k))) == 2 else 2
+        if kname == "fs_insertion":
+            return fused_mfma_flops(self.L, self.N, 1, len(self.taus), cb=cb)
+        if kname == "fs_spectator_baryon":
+            return fused_mfma_flops(self.L, self.N, 16, 1, cb=cb)
+        return None
+
     def cpu_sample(self, k, n_slices):
         """One noise vector of the (u,u) nucleon spectator, the u insertion on
         one timeslice with all 8 noise vectors, and the combine of that noise
@@ -665,6 +694,7 @@ class Batch64:
     default_proj = "fac"
     default_steps = 3
     default_warmup = 1
+    sample_slices = 4
 
     def __init__(self, args):
         self.n_src = int(args.sources)
@@ -756,6 +786,11 @@ class Batch64:
         self.jobs, self.combs = jobs, combs
         self.c3pt, self.k, self.proj = c3pt, k, geom.proj
         self.record()
+        # outputs the CPU-baseline sample recomputes with the oracle: source 0's
+        # spectator and its first insertion timeslices
+        nt = min(self.sample_slices, len(self.src[0]["taus"]))
+        self.sample_outputs = {"spectator_meson": lambda: self.batch.outputs[0],
+                               "insertion": lambda: self.batch.outputs[1][:, :nt]}
 
     def record(self):
         """(Re)record the batch graph; kernel variants are fixed at recording."""
@@ -796,11 +831,11 @@ class Batch64:
     def step(self):
         self.batch.run()
 
-    def plain_step(self):
-        """The same jobs as plain per-call launches with FP32 projection (no graph, no batching)."""
+    def plain_step(self, proj_flag):
+        """The same jobs as plain per-call launches with projection proj_flag (no graph, no batching)."""
         c = self.c3pt
         for j, o in zip(self.jobs, self.batch.outputs):
-            self._single(j, c.Geom(j["L"], j["T"], r=j["r"], proj=c.PROJ_NATIVE), o)
+            self._single(j, c.Geom(j["L"], j["T"], r=j["r"], proj=proj_flag), o)
         for cm, o in zip(self.combs, self.batch.combine_outputs):
             c.combine(self.batch.outputs[cm["spec"]], self.batch.outputs[cm["ins"]], pairs=cm["pairs"], out=o)
 
@@ -827,23 +862,27 @@ class Batch64:
                 "combines": len(self.combs), "units_per_step": self.units_total, "batch": self.batch.info()}
 
     def cpu_sample(self, k, n_slices):
-        import c3pt_synth as syn
+        """Source 0 (a 24^3 meson) from the batch's own resident inputs: its
+        spectator and its first sample_slices insertion timeslices; the outputs
+        are kept as the reference for the accuracy of every form."""
         import oracle
         L, T = self.lattices[0]
-        src = self.sources()[0]
-        cfg = self.cfg
-        G = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, src["t_f"]))
-        eta = syn.round_to_c64(syn.z2z2_noise(L, self.N, cfg, src["t_f"]))
-        taus = src["taus"][:n_slices]
-        Gt = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in taus}
-        st = {t: syn.round_to_c64(syn.solution_slice(L, self.N, cfg, t)) for t in taus}
+        src = self.src[0]
+        js, ji = self.jobs[0], self.jobs[1]
+        G = js["G"].cpu().numpy()
+        eta = js["eta"].cpu().numpy()
+        taus = src["taus"][:self.sample_slices]
+        Gt = {t: ji["G_t"][t].cpu().numpy() for t in taus}
+        st = {t: ji["s_t"][t].cpu().numpy() for t in taus}
         t0 = time.perf_counter()
-        oracle.spectator_meson(G, eta, L, k, r=src["r"])
-        oracle.insertion(Gt, st, taus, L, T, k, r=src["r"])
+        S = oracle.spectator_meson(G, eta, L, k, r=src["r"])
+        I = oracle.insertion(Gt, st, taus, L, T, k, r=src["r"])
         dt = time.perf_counter() - t0
+        self.oracle_ref = {"spectator_meson": S, "insertion": I}
         units = self.N * int(np.prod(L)) * len(k) * (1 + len(taus))
-        return units, dt, (f"FP64 numpy oracle: source 0 (24^3 meson), spectator + {len(taus)} insertion "
-                           f"timeslices, N=8, {len(k)} momenta; nucleon sources and combines not in the sample")
+        return units, dt, (f"FP64 numpy oracle: source 0 (24^3 meson) on the batch's own inputs, spectator + "
+                           f"{len(taus)} insertion timeslices, N=8, {len(k)} momenta; nucleon sources and "
+                           f"combines not in the sample")
 
 
 WORKLOADS = {"meson32": Meson32, "meson8": Meson8, "nucleon48": Nucleon48, "twosink32": TwoSink32,
@@ -1075,6 +1114,7 @@ def serve_main(args):
                        "latency_p99_ms": float(np.percentile(lat_sat, 99) * 1e3)},
         "load_levels": levels,
         "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
+        "kernels_ms_per_step": {kn: round(v["total_ms"] / prof_steps, 3) for kn, v in prof.items()},
         "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
         "roofline": roof,
     }
@@ -1187,10 +1227,15 @@ def main():
         from paper_1711_02384_amd import autotune
         cases = [{"kind": kn, "mode": mode, "mt_class": cls, "call": fn} for kn, fn in W.calls()]
         tuning = autotune.tune(cases, reps=3, log=log)
+        if batched and proj == "fac":
+            # the batch's own kernels: 32-site tiles and chunk size per producer kind
+            tb = autotune.tune_recorded(["spectator_meson", "spectator_baryon", "insertion"], "batchfac", cls,
+                                        W.record, W.step, reps=3, log=log)
+            tuning["entries"] += tb["entries"]
+        elif batched:
+            W.record()
         if args.tune_out:
             autotune.save(tuning, args.tune_out)
-        if batched:
-            W.record()
     for _ in range(args.warmup):
         W.step()
     torch.cuda.synchronize()
@@ -1243,6 +1288,12 @@ def main():
     if roofline["traffic"] is not None:
         roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1 "
                                     "(copy-calibrated), measured on these kernel sources")
+        roofline["hbm_frac"] = round(roofline["traffic"] / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    mf = getattr(W, "mfma_flops", lambda kn, pj: None)(kname, proj)
+    if mf is not None:
+        roofline["mfma_frac"] = round(mf / (kms * 1e-3) / 1e12 / PEAK_MFMA_F16, 4)
+        roofline["mfma_note"] = ("MFMA flops the kernel issues (16x16x32 16-bit products, 3 per hi+lo term) "
+                                 "per launch over its average duration, against the dense FP16/BF16 peak")
 
     plain = None
     plain_proj = getattr(W, "plain_proj", None)
@@ -1269,19 +1320,44 @@ def main():
         W.geom = head_geom
         W.step()
         torch.cuda.synchronize()
+    plain_dense = None
     if batched and W.plain:
-        log("[bench] timing the same jobs as plain per-call FP32 launches")
-        W.plain_step()
+        # the same jobs as plain per-call launches: first with the batch's own
+        # projection (isolates batching), then with the dense FP32 projection
+        forms = [(proj, proj_flag, f"one c3pt_* call per job and per combine, the batch's own ({proj}) "
+                                   "projection, no graph")]
+        if proj != "f32":
+            forms.append(("f32", c3pt.PROJ_NATIVE, "one c3pt_* call per job and per combine, dense FP32 MFMA "
+                                                   "projection, no graph"))
+        W.plain_outputs = {}
+        got = []
+        for pj, pflag, what in forms:
+            log(f"[bench] timing the same jobs as plain per-call launches ({pj})")
+            W.plain_step(pflag)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            W.plain_step(pflag)
+            b.record(stream)
+            torch.cuda.synchronize()
+            pms = a.elapsed_time(b)
+            # per-kernel time of one profiled plain step, beside the batch's kernels_ms
+            c3pt.profile_read(reset=True)
+            c3pt.profile_enable(True)
+            W.plain_step(pflag)
+            torch.cuda.synchronize()
+            c3pt.profile_enable(False)
+            pprof = c3pt.profile_read(reset=True)
+            got.append({"value": units / (pms * 1e-3), "ms_per_step": pms, "proj": pj, "form": what,
+                        "batched_speedup": pms / ms_per_step,
+                        "kernels_ms_per_step": {kn: round(v["total_ms"], 3) for kn, v in pprof.items()}})
+            W.plain_outputs[f"{pj} per call"] = {kn: fn().cpu().numpy()
+                                                 for kn, fn in getattr(W, "sample_outputs", {}).items()}
+        plain = got[0]
+        plain_dense = got[1] if len(got) > 1 else None
+        # the batch's own outputs again, for its accuracy below
+        W.step()
         torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        W.plain_step()
-        b.record(stream)
-        torch.cuda.synchronize()
-        pms = a.elapsed_time(b)
-        plain = {"value": units / (pms * 1e-3), "ms_per_step": pms, "proj": "f32",
-                 "form": "one c3pt_* call per job and per combine, FP32 MFMA projection, no graph",
-                 "batched_speedup": pms / ms_per_step}
     res = {
         "metric": "contracted site*momenta/s (spectator+insertion)",
         "value": value,
@@ -1309,6 +1385,8 @@ def main():
     }
     if plain is not None:
         res["plain_form"] = plain
+    if plain_dense is not None:
+        res["plain_form_dense"] = plain_dense
     if tuning is not None:
         res["tuning"] = tuning["entries"]
     if not args.no_cpu_baseline:
@@ -1337,9 +1415,14 @@ def sample_accuracy(W, proj, plain):
     out = {"metric": "max(||d||_F/||ref||_F, max|d|/max|ref|) per part", proj: {}}
     for kn, fn in W.sample_outputs.items():
         out[proj][kn] = rel_err(fn().cpu().numpy(), ref[kn])
-    if plain is not None:
+    po = getattr(W, "plain_outputs", {})
+    if po and all(isinstance(v, dict) for v in po.values()):
+        # several plain forms, keyed by name (captured when each ran)
+        for name, outs in po.items():
+            out[name] = {kn: rel_err(v, ref[kn]) for kn, v in outs.items()}
+    elif plain is not None:
         # the plain form's outputs were captured when it ran
-        out[plain["proj"]] = {kn: rel_err(v, ref[kn]) for kn, v in getattr(W, "plain_outputs", {}).items()}
+        out[plain["proj"]] = {kn: rel_err(v, ref[kn]) for kn, v in po.items()}
     return out
 
 

@@ -340,7 +340,12 @@ int c3pt_release_scratch(void);
  * runs two column blocks per workgroup, variant 1 splits the call's slices
  * once in a pass before it, variant 2 does that and runs one column block per
  * workgroup (two workgroups per CU).  The nucleon spectator always forms its
- * diquark in a pass (variants 0 and 1 are the same for it).
+ * diquark in a pass (variants 0 and 1 are the same for it).  Mode 6 selects
+ * the factored kernels of batches and of the server (read when a batch is
+ * created and when the server plans a step), as two bits: 1 takes 32-site
+ * tiles for jobs with L1 % 32 == 0 (meson spectator and local insertion; the
+ * other producers keep 16), 2 makes chunks of about 4096 instead of 2048
+ * sites.
  * mt_class: momentum groups of up to 32, 64, 96, 128 momenta (0..3).
  * c3pt_variant_count returns the number of compiled variants (0 if none);
  * c3pt_set_variant selects one for later calls (process-wide);

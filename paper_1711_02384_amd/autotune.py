@@ -66,3 +66,35 @@ def tune(cases: List[dict], reps: int = 3, log=print) -> dict:
 def save(table: dict, path: str) -> None:
     with open(path, "w") as f:
         json.dump(table, f, indent=1)
+
+
+def tune_recorded(kinds: List, mode, cls: int, record: Callable[[], object], run: Callable[[], object],
+                  reps: int = 3, log=print) -> dict:
+    """Tune variants that are fixed when work is recorded (batches: read by
+    c3pt_batch_create).  For each kind in turn (the others at their current
+    choice), every variant is selected, the work is recorded again with
+    record() and its replay run() timed; the fastest stays selected and the
+    work is left recorded with it."""
+    mode = MODE.get(mode, mode)
+    entries = []
+    for kn in kinds:
+        kind = KIND.get(kn, kn)
+        n = variant_count(kind, mode, cls)
+        if n == 0:
+            continue
+        before = get_variant(kind, mode, cls)
+        ms = []
+        for v in range(n):
+            set_variant(kind, mode, cls, v)
+            record()
+            ms.append(time_call(run, reps))
+        best = min(range(n), key=lambda v: ms[v])
+        set_variant(kind, mode, cls, best)
+        entries.append({"kind": kind, "mode": mode, "mt_class": cls, "variant": best,
+                        "ms": [round(x, 4) for x in ms], "previous": before})
+        if log:
+            log(f"[autotune] recorded kind={kind} mode={mode} class={cls}: ms={['%.3f' % x for x in ms]} "
+                f"-> variant {best}")
+    record()
+    return {"device": torch.cuda.get_device_name(0), "when": time.strftime("%Y-%m-%d %H:%M:%S"),
+            "entries": entries}

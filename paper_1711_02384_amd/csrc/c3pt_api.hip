@@ -261,7 +261,7 @@ int proj_mode(const c3pt_geom* g) {
 
 // Kernel variant per (kind, mode, momentum-tile class); 0 = default.
 constexpr int kKinds = 3;   // 0 meson spectator, 1 baryon spectator, 2 insertion
-constexpr int kModes = 6;
+constexpr int kModes = 7;
 constexpr int kModeFacVariants = 4;   // variant slot of the factored projection (not an arithmetic mode)
 constexpr int kModeFsVariants = 5;    // variant slot of the split-precision fused projection
 int g_variant[kKinds][kModes][kMtClasses] = {};
@@ -274,6 +274,10 @@ int variant_count(int kind, int mode, int cls) {
     // 1 = slices split by a pass first, two blocks; 2 = split pass, one block per
     // workgroup (two workgroups per CU).  The nucleon's diquark always has its pass.
     if (mode == kModeFsVariants) return 3;
+    // persistent factored (batches and serving): bit 0 chunk planes summed in
+    // registers, bit 1 32-site tiles where they apply, bit 2 chunks of about
+    // 4096 instead of 2048 sites
+    if (mode == kModeBatchFacVariants) return kBatchFacVariants;
     if (mode == kModeF64) return cls == 0 ? 1 : 0;
     return kVariantsPerClass[cls];
 }

@@ -163,8 +163,8 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             d.group_cols = J.kind == C3PT_JOB_SPECTATOR_MESON ? kBlockCols : 3072;
         }
         if (fac) {
-            // chunks of x3 planes (about 2048 sites), summed in place
-            d.chunk_sites = std::max(1, std::min(d.L[2], 2048 / (d.L[0] * d.L[1])));   // planes per chunk
+            // chunks of x3 planes (about 2048 or 4096 sites, the kind's tuned variant)
+            d.chunk_sites = batch_fac_chunk_planes(d.L, api_variant(d.kind, kModeBatchFacVariants, mt));
             d.n_chunks = (d.L[2] + d.chunk_sites - 1) / d.chunk_sites;
         } else {
             d.n_chunks = (d.V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
@@ -320,13 +320,23 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     std::vector<std::vector<Queue>> queues(groups.size());
     std::vector<std::pair<long long*, long long>> out_offsets(groups.size());
     // queue kinds: 0 meson spectator, 1 baryon spectator, 2 insertion (factored:
-    // local operator only), 3 factored insertion derivative operators
+    // local operator only), 3 factored insertion derivative operators; factored
+    // queues split further into jobs on 16- and on 32-site tiles (slot
+    // 2 * kind + t32) when the kind's variant asks for 32-site tiles
     constexpr int kQueueKinds = 4;
+    constexpr int kQueueSlots = 2 * kQueueKinds;
     int* counters;
-    if (int rc = dmalloc(b, (void**)&counters, groups.size() * kQueueKinds * sizeof(int))) return bail(rc);
+    if (int rc = dmalloc(b, (void**)&counters, groups.size() * kQueueSlots * sizeof(int))) return bail(rc);
     for (size_t gi = 0; gi < groups.size(); ++gi) {
-        for (int kind = 0; kind < kQueueKinds; ++kind) {
+        for (int qs = 0; qs < kQueueSlots; ++qs) {
+            const int kind = qs / 2, t32 = qs % 2;
             if (kind == 3 && !fac) continue;
+            if (t32 && !fac) continue;
+            // factored variant of this queue: the producer kind's tuned choice,
+            // with 32-site tiles for the jobs whose rows split into them
+            const int fv = fac ? api_variant(std::min(kind, 2), kModeBatchFacVariants, mt) : 0;
+            const bool want32 = fac && (fv & kBatchFacKT32) && batch_fac_allows32(kind);
+            if (t32 && !want32) continue;
             // Issue order: largest job first; within a job, items that read the
             // same input slice and site chunk are adjacent, so they run together
             // and share its cache lines.
@@ -335,6 +345,7 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
                 const BatchJob& d = hj[i].d;
                 if (d.kind != std::min(kind, 2)) continue;
                 if (kind == 3 && d.n_ops == 1) continue;
+                if (fac && (want32 && d.L[0] % 32 == 0) != (t32 == 1)) continue;
                 const int n_share = d.kind == 2 ? d.n_tau : 1;
                 const int n_within = d.n_colblocks / n_share;
                 const int n_item_chunks = d.n_chunks;
@@ -352,13 +363,13 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             if (int rc = dmalloc(b, &dev, items.size() * sizeof(int4))) return bail(rc);
             if (int rc = upload_sync(dev, items.data(), items.size() * sizeof(int4), st)) return bail(rc);
             // persistent grid: as many workgroups as fit on the chip at once
-            const int variant = fac ? 0 : api_variant(kind, mode, mt);
+            const int variant = fac ? (t32 ? kBatchFacKT32 : 0) : api_variant(kind, mode, mt);
             hipError_t e = hipSuccess;
             int per_cu;
             if (fac)
-                per_cu = kind == 0   ? batch_fac_meson(nullptr, 0, st, &e)
-                         : kind == 1 ? batch_fac_baryon(nullptr, 0, st, &e)
-                                     : batch_fac_insertion(kind == 2 ? 1 : 2, nullptr, 0, st, &e);
+                per_cu = kind == 0   ? batch_fac_meson(variant, nullptr, st, &e)
+                         : kind == 1 ? batch_fac_baryon(variant, nullptr, st, &e)
+                                     : batch_fac_insertion(variant, kind == 2 ? 1 : 2, nullptr, st, &e);
             else
                 per_cu = kind == 0   ? batch_meson(mode, mt, variant, nullptr, 0, st, &e)
                          : kind == 1 ? batch_baryon(mode, mt, variant, nullptr, 0, st, &e)
@@ -366,7 +377,7 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             if (e != hipSuccess || per_cu < 1) return bail(api_fail(C3PT_EUNSUPPORTED, "no kernel for this batch"));
             const int n_wg = std::max(1, (int)std::min<long long>((long long)items.size(), (long long)per_cu * n_cu));
             queues[gi].push_back(
-                Queue{kind, (int4*)dev, (int)items.size(), counters + kQueueKinds * gi + kind, variant, n_wg});
+                Queue{kind, (int4*)dev, (int)items.size(), counters + kQueueSlots * gi + qs, variant, n_wg});
             b->n_items += (int)items.size();
         }
         std::vector<long long> offs(1, 0);
@@ -421,8 +432,8 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
     static const char* kFacName[4] = {"batch_fac_spectator_meson", "batch_fac_spectator_baryon",
                                       "batch_fac_insertion", "batch_fac_insertion_deriv"};
     for (size_t gi = 0; gi < groups.size(); ++gi) {
-        int* cnt = counters + kQueueKinds * gi;
-        b->ops.push_back({"batch_reset", [cnt](hipStream_t s) { return launch_reset(cnt, kQueueKinds, s); }});
+        int* cnt = counters + kQueueSlots * gi;
+        b->ops.push_back({"batch_reset", [cnt](hipStream_t s) { return launch_reset(cnt, kQueueSlots, s); }});
         for (const Queue& q : queues[gi]) {
             BatchGrid bg;
             bg.jobs = JD;
@@ -433,9 +444,9 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             b->ops.push_back({fac ? kFacName[kind] : kProjName[kind], [=](hipStream_t s) {
                                   hipError_t e = hipSuccess;
                                   if (fac) {
-                                      if (kind == 0) batch_fac_meson(&bg, n_wg, s, &e);
-                                      else if (kind == 1) batch_fac_baryon(&bg, n_wg, s, &e);
-                                      else batch_fac_insertion(kind == 2 ? 1 : 2, &bg, n_wg, s, &e);
+                                      if (kind == 0) batch_fac_meson(variant, &bg, s, &e);
+                                      else if (kind == 1) batch_fac_baryon(variant, &bg, s, &e);
+                                      else batch_fac_insertion(variant, kind == 2 ? 1 : 2, &bg, s, &e);
                                   } else if (kind == 0) {
                                       batch_meson(mode, mt, variant, &bg, n_wg, s, &e);
                                   } else if (kind == 1) {

@@ -448,51 +448,47 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     if (ACC) fac_write<R>(pg.partial, pg.n_colblocks, pg.n_mom, chunk, cb, out, tid);
 }
 
-// Persistent form for batches and serving: workgroups take (job, column
-// block, plane chunk) items from a queue; job.phase is the job's FactorPlan,
-// job.chunk_sites the x3 planes per chunk, job.n_chunks the chunks.
+// Form for batches and serving: one workgroup per (job, column block, plane
+// chunk) item of the launch's item list; job.phase is the job's FactorPlan,
+// job.chunk_sites the x3 planes per chunk, job.n_chunks the chunks.  The
+// hardware hands out workgroups in order as CUs free up, which balances the
+// uneven items as a work queue would; consecutive items (the same input slice
+// and chunk) are mapped onto one XCD, so they share its L2.
 template <typename R, int KT, template <typename, int, int> class ProdT>
 __global__ void __launch_bounds__(kFacThreads, 1) fac_batch_kernel(BatchGrid bg) {
     using Prod = ProdT<R, KT, kFacThreads>;
     __shared__ FacSmem<R, KT> sm;
     __shared__ typename Prod::Buf buf[2];
-    __shared__ int s_item;
     const int tid = threadIdx.x;
+    const int nw = gridDim.x, w = blockIdx.x;
+    const int full = (nw / 8) * 8;
+    const int it = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
+    const int4 item = bg.items[it];
+    const BatchJob& job = bg.jobs[item.x];
+    const int cb = item.y;
+    const typename Prod::Ctx ctx = Prod::resolve(job, job.V3, cb);
+    TileGeom tg;
+    tg.V3 = job.V3;
+    tg.L1 = job.L[0];
+    tg.L2 = job.L[1];
+    tg.L3 = job.L[2];
+    tg.inv1 = 1.0f / (float)tg.L1;
+    tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
+    tg.row = tg.x1 = tg.x2 = tg.x3 = 0;
+    fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
     C2<R> out[FacLimits<R>::kOut];   // not used by the plane-chunk form
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(bg.counter, 1);
-        __syncthreads();
-        // the item is the same for the whole workgroup: make that visible to the
-        // compiler so that everything derived from it stays in scalar registers
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (it >= bg.n_items) break;
-        const int4 item = bg.items[it];
-        const BatchJob& job = bg.jobs[item.x];
-        const int cb = item.y;
-        const typename Prod::Ctx ctx = Prod::resolve(job, job.V3, cb);
-        TileGeom tg;
-        tg.V3 = job.V3;
-        tg.L1 = job.L[0];
-        tg.L2 = job.L[1];
-        tg.L3 = job.L[2];
-        tg.inv1 = 1.0f / (float)tg.L1;
-        tg.inv12 = 1.0f / (float)(tg.L1 * tg.L2);
-        tg.row = tg.x1 = tg.x2 = tg.x3 = 0;
-        fac_setup<R, KT>(sm, (const FactorPlan*)job.phase, tid, kFacThreads);
-        const int p0 = item.z * job.chunk_sites;
-        const int p1 = min(tg.L3, p0 + job.chunk_sites);
-        fac_loop_phased<R, KT, false, Prod>(tid, ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb,
-                                            item.z);
-        __syncthreads();
-    }
+    const int p0 = item.z * job.chunk_sites;
+    const int p1 = min(tg.L3, p0 + job.chunk_sites);
+    fac_loop_phased<R, KT, false, Prod>(tid, ctx, tg, sm, buf, p0, p1, out, job.partial, job.n_colblocks, cb, item.z);
 }
 
+// Launches one workgroup per item (bg->n_items); with bg == nullptr only the
+// occupancy (workgroups per CU) is returned.
 template <typename R, int KT, template <typename, int, int> class ProdT>
-int fac_batch_kt(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
+int fac_batch_kt(const BatchGrid* bg, hipStream_t st, hipError_t* err) {
     *err = hipSuccess;
     if (bg) {
-        hipLaunchKernelGGL((fac_batch_kernel<R, KT, ProdT>), dim3(n_wg), dim3(kFacThreads), 0, st, *bg);
+        hipLaunchKernelGGL((fac_batch_kernel<R, KT, ProdT>), dim3(bg->n_items), dim3(kFacThreads), 0, st, *bg);
         *err = hipGetLastError();
     }
     int nb = 0;
@@ -500,6 +496,16 @@ int fac_batch_kt(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err)
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
+}
+
+// Launch in the form the variant selects: 32-site tiles (kBatchFacKT32) only
+// where the producer allows them.
+template <template <typename, int, int> class ProdT, bool kAllow32>
+int fac_batch(int variant, const BatchGrid* bg, hipStream_t st, hipError_t* err) {
+    if constexpr (kAllow32) {
+        if (variant & kBatchFacKT32) return fac_batch_kt<float, 32, ProdT>(bg, st, err);
+    }
+    return fac_batch_kt<float, 16, ProdT>(bg, st, err);
 }
 
 template <typename R, int KT, bool ACC, template <typename, int, int> class ProdT>

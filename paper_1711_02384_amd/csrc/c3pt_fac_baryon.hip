@@ -8,8 +8,8 @@ hipError_t launch_fac_baryon(bool f64, bool acc, const ProjGrid& pg, const Baryo
     return launch_fac<FacBaryonProd, false>(f64, acc, pg, a, st);   // 32-site tiles spill
 }
 
-int batch_fac_baryon(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
-    return fac_batch_kt<float, 16, FacBaryonProd>(bg, n_wg, st, err);
+int batch_fac_baryon(int variant, const BatchGrid* bg, hipStream_t st, hipError_t* err) {
+    return fac_batch<FacBaryonProd, false>(variant, bg, st, err);
 }
 
 }  // namespace c3pt

@@ -10,9 +10,9 @@ hipError_t launch_fac_insertion(bool f64, bool acc, int ops, const ProjGrid& pg,
                     : launch_fac<FacInsDerivProd, false>(f64, acc, pg, a, st);
 }
 
-int batch_fac_insertion(int ops, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
-    if (ops == 1) return fac_batch_kt<float, 16, FacInsLocalProd>(bg, n_wg, st, err);
-    return fac_batch_kt<float, 16, FacInsDerivProd>(bg, n_wg, st, err);
+int batch_fac_insertion(int variant, int ops, const BatchGrid* bg, hipStream_t st, hipError_t* err) {
+    if (ops == 1) return fac_batch<FacInsLocalProd, true>(variant, bg, st, err);
+    return fac_batch<FacInsDerivProd, false>(variant, bg, st, err);
 }
 
 }  // namespace c3pt

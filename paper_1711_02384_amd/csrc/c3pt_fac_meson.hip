@@ -8,8 +8,8 @@ hipError_t launch_fac_meson(bool f64, bool acc, const ProjGrid& pg, const MesonS
     return launch_fac<FacMesonProd, true>(f64, acc, pg, a, st);
 }
 
-int batch_fac_meson(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err) {
-    return fac_batch_kt<float, 16, FacMesonProd>(bg, n_wg, st, err);
+int batch_fac_meson(int variant, const BatchGrid* bg, hipStream_t st, hipError_t* err) {
+    return fac_batch<FacMesonProd, true>(variant, bg, st, err);
 }
 
 }  // namespace c3pt

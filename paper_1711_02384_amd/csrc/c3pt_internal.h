@@ -199,11 +199,27 @@ hipError_t launch_fac_baryon(bool f64, bool acc, const ProjGrid& pg, const Baryo
 // ops: 1 local operator only, 2 derivative operators only (a.op_lo / a.op_cnt select them)
 hipError_t launch_fac_insertion(bool f64, bool acc, int ops, const ProjGrid& pg, const InsertionArgs& a,
                                 hipStream_t st);
-// Persistent factored launches (FP32, 16-site tiles) over batch items.  With
-// bg == nullptr only the occupancy (workgroups per CU) is returned.
-int batch_fac_meson(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
-int batch_fac_baryon(const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
-int batch_fac_insertion(int ops, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
+// Factored launches (FP32) over batch items, one workgroup per item.  With
+// bg == nullptr only the occupancy (workgroups per CU) is returned.  variant
+// bits: kBatchFacKT32 takes 32-site tiles, honoured only by producers whose
+// registers allow them (batch_fac_allows32) and passed by the caller only when
+// every job of the launch has L1 % 32 == 0; kBatchFacWide is read by the
+// planner, which then puts about 4096 instead of 2048 sites in a chunk
+// (batch_fac_chunk_planes).
+constexpr int kBatchFacKT32 = 1, kBatchFacWide = 2, kBatchFacVariants = 4;
+// variant slot ("mode" of c3pt_set_variant) that holds these choices per producer kind
+constexpr int kModeBatchFacVariants = 6;
+// queue kinds: 0 meson spectator, 1 baryon spectator, 2 insertion local operator,
+// 3 insertion derivative operators
+inline bool batch_fac_allows32(int queue_kind) { return queue_kind == 0 || queue_kind == 2; }
+inline int batch_fac_chunk_planes(const int L[3], int variant) {
+    const int sites = (variant & kBatchFacWide) ? 4096 : 2048;
+    const int p = sites / (L[0] * L[1]);
+    return p < 1 ? 1 : (p > L[2] ? L[2] : p);
+}
+int batch_fac_meson(int variant, const BatchGrid* bg, hipStream_t st, hipError_t* err);
+int batch_fac_baryon(int variant, const BatchGrid* bg, hipStream_t st, hipError_t* err);
+int batch_fac_insertion(int variant, int ops, const BatchGrid* bg, hipStream_t st, hipError_t* err);
 // Factor plan of a momentum list for extents L and sign sigma (FP32 limits);
 // false if the list needs more distinct k1 / (k1, k2) than the kernel holds.
 bool api_factor_plan(const int L[3], int sigma, const int* k, int n_mom, FactorPlan* plan);

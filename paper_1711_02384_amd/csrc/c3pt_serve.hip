@@ -463,7 +463,10 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
                     const int cb = d.kind == 2 ? ((w / d.n_ops) * d.n_tau + sh) * d.n_ops + op : w;
                     std::pair<int, int> key;
                     if (sv->fac) {
-                        key = {d.kind < 2 ? d.kind : (op == 0 ? 2 : 3), 0};
+                        const int qk = d.kind < 2 ? d.kind : (op == 0 ? 2 : 3);
+                        const int fv = api_variant(d.kind, kModeBatchFacVariants, mt);
+                        const bool t32 = (fv & kBatchFacKT32) && batch_fac_allows32(qk) && d.L[0] % 32 == 0;
+                        key = {qk, t32 ? 1 : 0};
                     } else {
                         key = {d.kind, mt_class(mt)};
                     }
@@ -485,7 +488,8 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         for (const int4& it4 : kv.second) hi[n_items++] = it4;
         const int kind = kv.first.first;
         const int mt = list_mt[kv.first];
-        const int variant = sv->fac ? 0 : api_variant(kind, sv->mode, mt);
+        const int variant =
+            sv->fac ? (kv.first.second ? kBatchFacKT32 : 0) : api_variant(kind, sv->mode, mt);
         launches.push_back({kind, mt, item0, n_items - item0, variant});
     }
     std::vector<int> job_order(chosen.size());
@@ -524,9 +528,9 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         hipError_t e = hipSuccess;
         int per_cu;
         if (sv->fac)
-            per_cu = L.kind == 0   ? batch_fac_meson(nullptr, 0, st, &e)
-                     : L.kind == 1 ? batch_fac_baryon(nullptr, 0, st, &e)
-                                   : batch_fac_insertion(L.kind == 2 ? 1 : 2, nullptr, 0, st, &e);
+            per_cu = L.kind == 0   ? batch_fac_meson(L.variant, nullptr, st, &e)
+                     : L.kind == 1 ? batch_fac_baryon(L.variant, nullptr, st, &e)
+                                   : batch_fac_insertion(L.variant, L.kind == 2 ? 1 : 2, nullptr, st, &e);
         else
             per_cu = L.kind == 0   ? batch_meson(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
                      : L.kind == 1 ? batch_baryon(sv->mode, L.mt, L.variant, nullptr, 0, st, &e)
@@ -535,9 +539,9 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
         okk = run(sv->fac ? kFacName[L.kind] : kName[L.kind], [&] {
             hipError_t e2 = hipSuccess;
             if (sv->fac) {
-                if (L.kind == 0) batch_fac_meson(&bg, n_wg, st, &e2);
-                else if (L.kind == 1) batch_fac_baryon(&bg, n_wg, st, &e2);
-                else batch_fac_insertion(L.kind == 2 ? 1 : 2, &bg, n_wg, st, &e2);
+                if (L.kind == 0) batch_fac_meson(L.variant, &bg, st, &e2);
+                else if (L.kind == 1) batch_fac_baryon(L.variant, &bg, st, &e2);
+                else batch_fac_insertion(L.variant, L.kind == 2 ? 1 : 2, &bg, st, &e2);
             } else if (L.kind == 0) {
                 batch_meson(sv->mode, L.mt, L.variant, &bg, n_wg, st, &e2);
             } else if (L.kind == 1) {
@@ -728,11 +732,12 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
             return reject("missing neighbour slice for the derivative operators");
     }
     if (sv->fac) {
-        // chunks of x3 planes (about 2048 sites), summed in place
         FactorPlan plan;
         if (!api_factor_plan(q->L, +1, q->k.data(), q->n_mom, &plan))
             return reject("the momentum list does not factor (too many distinct k1 or (k1, k2))");
-        q->chunk_sites = std::max(1, std::min(q->L[2], 2048 / (q->L[0] * q->L[1])));
+        // chunks of about 2048 or 4096 sites: the insertion's tuned variant (its
+        // work dominates a request) sets them for every part of the request
+        q->chunk_sites = batch_fac_chunk_planes(q->L, api_variant(2, kModeBatchFacVariants, (q->n_mom + 7) / 8));
         q->n_chunks = (q->L[2] + q->chunk_sites - 1) / q->chunk_sites;
     } else {
         q->n_chunks = (q->V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;

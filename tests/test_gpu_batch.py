@@ -250,3 +250,39 @@ def test_batch_profiled_run_times_each_kernel_and_matches_graph():
     for o, r in zip(b.outputs + b.combine_outputs, ref):
         assert torch.equal(o, r)
     b.close()
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_batch_factored_variants(variant):
+    """The factored batch's tunable forms (32-site tiles for jobs whose L1 is a
+    multiple of 32, chunks of about 4096 sites) against the oracle and against
+    the default form; lattices with L1 = 32 (meson with the derivative
+    operators, baryon, which keeps 16-site tiles) beside ones that keep 16."""
+    import paper_1711_02384_amd as c3pt
+    k = c3pt.momentum_list(3)
+    cls = c3pt.mt_class(len(k))
+    lats = [Lattice((32, 6, 24), 6, (5, 1, 9), 2, [0, 2], 5, False, cfg=21),
+            Lattice((32, 4, 3), 6, (1, 2, 0), 2, [1], 1, True, cfg=22)] + _lattices()[:1]
+    kinds = ("spectator_meson", "spectator_baryon", "insertion")
+    before = {kn: c3pt.get_variant(c3pt.KIND[kn], c3pt.MODE["batchfac"], cls) for kn in kinds}
+    outs = {}
+    try:
+        for v in (0, variant):
+            for kn in kinds:
+                c3pt.set_variant(c3pt.KIND[kn], c3pt.MODE["batchfac"], cls, v)
+            _say(f"batch factored variant {v}: create")
+            b = _batch(c3pt, lats, k, c3pt.PROJ_FACTORED)
+            b.run()
+            torch.cuda.synchronize()
+            outs[v] = [o.cpu().numpy() for o in b.outputs]
+            b.close()
+    finally:
+        for kn in kinds:
+            c3pt.set_variant(c3pt.KIND[kn], c3pt.MODE["batchfac"], cls, before[kn])
+    for li, lat in enumerate(lats):
+        S_o, I_o = lat.oracle_parts(k)
+        S, I = outs[variant][2 * li], outs[variant][2 * li + 1]
+        es, ei = rel_err(S, S_o), rel_err(I, I_o)
+        _say(f"batch factored variant {variant}: lattice {lat.L} spectator {es:.2e} insertion {ei:.2e}")
+        assert es < TOL and ei < TOL
+        assert rel_err(S, outs[0][2 * li]) < SAME and rel_err(I, outs[0][2 * li + 1]) < SAME

@@ -175,3 +175,36 @@ def test_serve_rejects_requests_that_cannot_fit():
         sv.submit(q.request())
     assert sv.info()["queued"] == 0
     sv.close()
+
+
+def test_serve_factored_variant_with_32_site_tiles_and_wide_chunks():
+    """The server's factored launches in the tuned form with 32-site tiles and
+    chunks of about 4096 sites: a request on an L1 = 32 lattice (meson with the
+    derivative operators) beside ones that keep 16-site tiles, against the
+    oracle."""
+    import paper_1711_02384_amd as c3pt
+    reqs = [Req("meson", (32, 6, 24), 6, (5, 1, 9), 0, 2, 2, 5, 3, cfg=35, pairs=[(0, 0), (2, 7)]),
+            Req("nucleon", (32, 4, 3), 6, (1, 2, 0), 1, 2, 2, 1, 2, cfg=36, pairs=[(0, 0)])] + _mix()[2:3]
+    kinds = ("spectator_meson", "spectator_baryon", "insertion")
+    before = {kn: [c3pt.get_variant(c3pt.KIND[kn], c3pt.MODE["batchfac"], c) for c in range(4)] for kn in kinds}
+    try:
+        for kn in kinds:
+            for c in range(4):
+                c3pt.set_variant(c3pt.KIND[kn], c3pt.MODE["batchfac"], c, 3)
+        sv, ids = _serve(c3pt, reqs, c3pt.PROJ_FACTORED, arena=128 << 20, step=8 << 20)
+        sv.run_until_done(ids)
+        torch.cuda.synchronize()
+        for q, i in zip(reqs, ids):
+            got = sv.result(i)
+            S, I, C = q.oracle()
+            for p in range(len(S)):
+                es = rel_err(got["spec"][p].cpu().numpy(), S[p])
+                ei = rel_err(got["ins"][p].cpu().numpy(), I[p])
+                ec = rel_err(got["comb"][p].cpu().numpy(), C[p])
+                _say(f"serve factored variant 3: {q.kind} {q.L} part {p}: {es:.2e} {ei:.2e} {ec:.2e}")
+                assert es < TOL and ei < TOL and ec < TOL
+        sv.close()
+    finally:
+        for kn in kinds:
+            for c in range(4):
+                c3pt.set_variant(c3pt.KIND[kn], c3pt.MODE["batchfac"], c, before[kn][c])
