@@ -750,7 +750,6 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
         fa.n_share = 1;
         fa.n_slots = n_slots;
         fa.colmap = baryon ? 1 : 0;
-        fa.conj_sign = baryon ? 0 : 1;
         fa.B = B;
         fa.b_stride = bb;
         fa.G[0][0] = G1;

@@ -66,15 +66,25 @@ struct FsHalf2 {
     typedef T16 type __attribute__((ext_vector_type(2)));
 };
 
-// Split of two FP32 values into packed hi and lo 16-bit pairs (paired
-// conversions, two FP32 subtractions).
+// Split of two FP32 values into packed hi and lo 16-bit pairs.  The
+// residuals v - hi are exact in FP32; for FP16 each is one mixed-precision
+// FMA that reads its half of the packed hi directly (v_fma_mix_f32:
+// -hi * 1 + v), instead of a conversion back to FP32 and a subtraction.
 template <typename T16>
 __device__ __forceinline__ void fs_split2(f32x2 v, unsigned& hi, unsigned& lo) {
     using h2 = typename FsHalf2<T16>::type;
     const h2 h = __builtin_convertvector(v, h2);
-    const f32x2 r = v - __builtin_convertvector(h, f32x2);
-    const h2 l = __builtin_convertvector(r, h2);
     __builtin_memcpy(&hi, &h, 4);
+    f32x2 r;
+    if constexpr (__is_same(T16, _Float16)) {
+        float r0, r1;
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r0) : "v"(hi), "v"(v.x));
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r1) : "v"(hi), "v"(v.y));
+        r = f32x2{r0, r1};
+    } else {
+        r = v - __builtin_convertvector(h, f32x2);
+    }
+    const h2 l = __builtin_convertvector(r, h2);
     __builtin_memcpy(&lo, &l, 4);
 }
 
@@ -195,7 +205,11 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         sm.W1[seg][a][x] = wv;
     }
     const int n_mom = sm.plan.n_mom, n12 = sm.plan.n12;
-    // stage-2 ownership: k1 slots 2g, 2g+1 of the lane's three columns
+    // stage-2 ownership: k1 slots 2g, 2g+1 of the lane's three columns; nbmax
+    // (uniform) bounds the stage-2 updates of every lane
+    int nbmax = 0;
+    for (int a = 0; a < sm.plan.n1; ++a) nbmax = max(nbmax, sm.plan.bstart[a + 1] - sm.plan.bstart[a]);
+    nbmax = __builtin_amdgcn_readfirstlane(nbmax);
     int bs[2], nb[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -326,14 +340,17 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
                 const int e = e0 < S::NG ? e0 : e0 - S::NG;
                 const int p = e / S::GB, gi = e % S::GB;
                 const int X = p % 48;
-                // meson spectator: g[a'] g[a] conj(G)
-                const float sg = fa.conj_sign ? (X / 12 < 2 ? 1.f : -1.f) * ((X % 12) / 3 < 2 ? 1.f : -1.f) : 1.f;
-                const float sy = fa.conj_sign ? -sg : sg;
+                // Sites past the row's end hold copies of its last site (finite):
+                // their A entries are zero (W1 and u vanish there), so they add nothing.
                 u32x4 hi, lo;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const bool in = q.seg * KT + 4 * gi + j < L1;
-                    const f32x2 v = in ? f32x2{sg * greg[k][j].x, sy * greg[k][j].y} : f32x2{0.f, 0.f};
+                    f32x2 v = {greg[k][j].x, greg[k][j].y};
+                    if constexpr (KIND == 0) {
+                        // meson spectator (the only in-kernel split of KIND 0): g[a'] g[a] conj(G)
+                        const float sg = (X / 12 < 2 ? 1.f : -1.f) * ((X % 12) / 3 < 2 ? 1.f : -1.f);
+                        v = f32x2{sg * v.x, -sg * v.y};
+                    }
                     unsigned h, l;
                     fs_split2<T16>(v, h, l);
                     hi[j] = h;
@@ -447,21 +464,22 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         if (row_end) {
             // ---- stage 2: over x2, in registers -------------------------
             const C2<float>* cf = sm.coef2[row & 1];
-            C2<float> cw[2][kFacMaxBPerA];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int i = 0; i < kFacMaxBPerA; ++i) cw[h][i] = cf[bs[h] + i];
-#pragma unroll
-            for (int ct = 0; ct < 3; ++ct) {
+            for (int i = 0; i < kFacMaxBPerA; ++i) {
+                if (i >= nbmax) break;   // uniform
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const C2<float> v = h == 0 ? C2<float>{acc[ct][0], acc[ct][1]} : C2<float>{acc[ct][2], acc[ct][3]};
+                    const C2<float> cw = cf[bs[h] + i];
 #pragma unroll
-                    for (int i = 0; i < kFacMaxBPerA; ++i) r2[ct][h][i] = cfma(r2[ct][h][i], cw[h][i], v);
+                    for (int ct = 0; ct < 3; ++ct) {
+                        const C2<float> v =
+                            h == 0 ? C2<float>{acc[ct][0], acc[ct][1]} : C2<float>{acc[ct][2], acc[ct][3]};
+                        r2[ct][h][i] = cfma(r2[ct][h][i], cw, v);
+                    }
                 }
-                acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
+#pragma unroll
+            for (int ct = 0; ct < 3; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
             if (plane_end) {
                 // ---- stage 3: over x3, into the chunk's partial sums ----
                 float2* part_out = (float2*)pg.partial;

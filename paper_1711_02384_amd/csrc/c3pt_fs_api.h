@@ -18,11 +18,11 @@ struct FsArgs {
     int N;                 // noise vectors
     int n_share, n_slots;  // shares (timeslices of the launch; 1 for spectators), slots per share
     int colmap;            // 0: column at*48 + X; 1: nucleon (X/3)*12 + at*3 + X%3
-    int conj_sign;         // FP32 B source: B = g[a'] g[a] conj(G) (the meson spectator)
     const void* B;         // split B source: blocks b_stride bytes apart; spectators: block = slot,
     size_t b_stride;       // insertion: block bidx[tau_j][role]
     int bidx[kMaxTauPerLaunch][3];
-    const void* G[kMaxTauPerLaunch][3];   // FP32 B source: G(tau_j), G(tau_j + 1), G(tau_j - 1)
+    const void* G[kMaxTauPerLaunch][3];   // FP32 B source: G(tau_j), G(tau_j + 1), G(tau_j - 1);
+                                          // the meson spectator's (KIND 0) is conjugated with g[a'] g[a]
     const void* u0[kMaxTauPerLaunch];   // spectators: eta [N][12][V3] (entry 0); insertion: s(tau_j)
     const void* U[kMaxTauPerLaunch];    // U(tau_j) [4][3][3][V3]
     const void* Up[kMaxTauPerLaunch];   // U(tau_j - 1)
