@@ -520,7 +520,7 @@ class Nucleon48(Meson32):
             return None
         c = self.c3pt
         kind = 1 if kname == "fs_spectator_baryon" else 2
-        cb = 1 if c.get_variant(kind, c.MODE[proj], c.mt_class(len(self.k))) == 2 else 2
+        cb = 1 if c.get_variant(kind, c.MODE[proj], c.mt_class(len(self.k))) >= 2 else 2
         if kname == "fs_insertion":
             return fused_mfma_flops(self.L, self.N, 1, len(self.taus), cb=cb)
         if kname == "fs_spectator_baryon":

@@ -339,8 +339,10 @@ int c3pt_release_scratch(void);
  * variant 0 splits each propagator tile into hi + lo parts in the kernel and
  * runs two column blocks per workgroup, variant 1 splits the call's slices
  * once in a pass before it, variant 2 does that and runs one column block per
- * workgroup (two workgroups per CU).  The nucleon spectator always forms its
- * diquark in a pass (variants 0 and 1 are the same for it).  Mode 6 selects
+ * workgroup, variant 3 splits in the kernel with one column block per
+ * workgroup.  The nucleon spectator
+ * always forms its diquark in a pass (variants 0 and 1, and 2 and 3, are the
+ * same for it).  Mode 6 selects
  * the factored kernels of batches and of the server (read when a batch is
  * created and when the server plans a step), as two bits: 1 takes 32-site
  * tiles for jobs with L1 % 32 == 0 (meson spectator and local insertion; the

@@ -272,8 +272,9 @@ int variant_count(int kind, int mode, int cls) {
     if (mode == kModeFacVariants) return 2;
     // fused: 0 = propagator tiles split in the kernel, two column blocks per workgroup;
     // 1 = slices split by a pass first, two blocks; 2 = split pass, one block per
-    // workgroup (two workgroups per CU).  The nucleon's diquark always has its pass.
-    if (mode == kModeFsVariants) return 3;
+    // workgroup; 3 = split in the kernel, one block per workgroup.  The
+    // nucleon's diquark always has its pass.
+    if (mode == kModeFsVariants) return 4;
     // persistent factored (batches and serving): bit 0 chunk planes summed in
     // registers, bit 1 32-site tiles where they apply, bit 2 chunks of about
     // 4096 instead of 2048 sites
@@ -689,8 +690,8 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
         std::lock_guard<std::mutex> lk(g_mu);
         fs_variant = g_variant[baryon ? 1 : 0][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
     }
-    const bool bsplit = baryon || fs_variant >= 1;
-    const int cbw = fs_variant == 2 ? 1 : 2;
+    const bool bsplit = baryon || fs_variant == 1 || fs_variant == 2;
+    const int cbw = fs_variant >= 2 ? 1 : 2;
     const int n_per_share = n_slots * ((N + cbw - 1) / cbw);
     int cp, nch;
     plan_planes(geom->L, n_per_share, &cp, &nch);
@@ -799,8 +800,8 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
         std::lock_guard<std::mutex> lk(g_mu);
         fs_variant = g_variant[2][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
     }
-    const bool bsplit = fs_variant >= 1;
-    const int cbw = fs_variant == 2 ? 1 : 2;
+    const bool bsplit = fs_variant == 1 || fs_variant == 2;
+    const int cbw = fs_variant >= 2 ? 1 : 2;
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
         FsArgs fa;

@@ -113,8 +113,7 @@ struct FsShape {
     static constexpr int GB = KT / 4;              // four-site groups per tile
     static constexpr int PSTR = GB * 32 + 16;      // LDS bytes per B plane (padded against bank conflicts)
     static constexpr int HS = KT / 16;             // MFMA K steps per summed colour (16 sites x re/im)
-    static constexpr int MAXSEG = kMaxL / KT;      // row segments of the longest row
-    static constexpr int W1S = KT + 2;             // W1 row stride (complex), padded
+    static constexpr int W1S = KT + 2;             // W1 row stride (complex), padded (fs_dyn_bytes)
     static constexpr int NB16 = kFsPlanes * GB * 2;          // 16-byte pieces of a B tile
     static constexpr int KB = (NB16 + NT - 1) / NT;
     static_assert(KB * NT <= 2 * NB16, "repeated B pieces stay within the tile");
@@ -130,11 +129,12 @@ struct FsSmem {
     using S = FsShape<KT, CB>;
     alignas(16) unsigned char B[2][kFsPlanes * S::PSTR];
     alignas(16) C2<float> U[2][CB][12][KT];                  // [buffer][block][3 at + c][x1]
-    alignas(16) C2<float> W1[S::MAXSEG][kFacMaxK1][S::W1S];  // w1^(k1 (seg KT + x1)); zero for unused slots
     C2<float> coef2[2][kFacMaxPairsF32 + kFacMaxBPerA];
-    C2<float> root[3][kMaxL];
     FactorPlan plan;
 };
+// The lattice-sized tables follow in dynamic LDS (fs_dyn_bytes): W1
+// [nseg][kFacMaxK1][W1S], w1^(k1 (seg KT + x1)), zero for unused slots and
+// sites past the row; then the root tables w_j^x for x < L_j, j = 1, 2, 3.
 
 template <typename T16, int KT, int KIND, bool BSPLIT, int CB>
 __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
@@ -143,6 +143,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     using MF = Mfma16<T16>;
     using vec_t = typename MF::vec_t;
     __shared__ FsSmem<KT, CB> sm;
+    extern __shared__ __attribute__((aligned(16))) float2 fs_dyn[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, g = lane >> 4, cl = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -165,6 +166,10 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     const int V3 = L1 * L2 * L3;
     const float inv1 = 1.0f / (float)L1, inv2 = 1.0f / (float)L2, inv3 = 1.0f / (float)L3;
     const int nseg = (L1 + KT - 1) / KT;
+    C2<float>* const W1 = (C2<float>*)fs_dyn;                        // [nseg][kFacMaxK1][W1S]
+    C2<float>* const root0 = W1 + nseg * kFacMaxK1 * S::W1S;         // [L1], then [L2], [L3]
+    C2<float>* const root1 = root0 + L1;
+    C2<float>* const root2 = root1 + L2;
     // B source of this work item: a split block, or the FP32 propagator slice
     // of the slot (tau_j, tau_j + 1 for (t, +), tau_j - 1 for (t, -))
     const int role = KIND == 2 && slot == 7 ? 1 : (KIND == 2 && slot == 8 ? 2 : 0);
@@ -183,16 +188,13 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         int* dst = (int*)&sm.plan;
         for (int i = tid; i < (int)(sizeof(FactorPlan) / sizeof(int)); i += NT) dst[i] = src[i];
         const int sigma = ((const FactorPlan*)pg.phase)->sigma;
-        for (int i = tid; i < 3 * kMaxL; i += NT) {
-            const int j = i / kMaxL, x = i % kMaxL;
+        for (int i = tid; i < L1 + L2 + L3; i += NT) {
+            const int j = i < L1 ? 0 : (i < L1 + L2 ? 1 : 2);
+            const int x = i - (j == 0 ? 0 : (j == 1 ? L1 : L1 + L2));
             const int L = fa.L[j];
-            C2<float> wv = {0.f, 0.f};
-            if (x < L) {
-                double sn, cs;
-                sincospi(2.0 * (double)x / (double)L, &sn, &cs);
-                wv = {(float)cs, (float)(sigma * sn)};
-            }
-            sm.root[j][x] = wv;
+            double sn, cs;
+            sincospi(2.0 * (double)x / (double)L, &sn, &cs);
+            root0[i] = C2<float>{(float)cs, (float)(sigma * sn)};
         }
     }
     __syncthreads();
@@ -201,8 +203,8 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         const int a = rem / KT, x = rem % KT;
         const int x1 = seg * KT + x;
         C2<float> wv = {0.f, 0.f};
-        if (a < sm.plan.n1 && x1 < L1) wv = sm.root[0][mod_small(sm.plan.k1[a] * x1, L1, inv1)];
-        sm.W1[seg][a][x] = wv;
+        if (a < sm.plan.n1 && x1 < L1) wv = root0[mod_small(sm.plan.k1[a] * x1, L1, inv1)];
+        W1[(seg * kFacMaxK1 + a) * S::W1S + x] = wv;
     }
     const int n_mom = sm.plan.n_mom, n12 = sm.plan.n12;
     // stage-2 ownership: k1 slots 2g, 2g+1 of the lane's three columns; nbmax
@@ -389,7 +391,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     };
     auto fill_coef2 = [&](int par, int x2) __attribute__((always_inline)) {
         for (int b = tid; b < n12 + kFacMaxBPerA; b += NT)
-            sm.coef2[par][b] = b < n12 ? sm.root[1][mod_small(sm.plan.k2[b] * x2, L2, inv2)] : C2<float>{0.f, 0.f};
+            sm.coef2[par][b] = b < n12 ? root1[mod_small(sm.plan.k2[b] * x2, L2, inv2)] : C2<float>{0.f, 0.f};
     };
 
     f32x4 acc[3];
@@ -428,7 +430,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         for (int h = 0; h < S::HS; ++h)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const C2<float> wv = sm.W1[seg][a_row][16 * h + 4 * g + j];
+                const C2<float> wv = W1[(seg * kFacMaxK1 + a_row) * S::W1S + 16 * h + 4 * g + j];
                 cf[h][j][0] = part ? wv.y : wv.x;
                 cf[h][j][1] = part ? wv.x : -wv.y;
                 cf[h][j][2] = part ? wv.x : -wv.y;
@@ -495,7 +497,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
                                 const int b = bs[h] + i;
                                 for (int jm = sm.plan.mstart[b]; jm < sm.plan.mstart[b + 1]; ++jm) {
                                     const int m = sm.plan.m_of[jm];
-                                    const C2<float> w3 = sm.root[2][mod_small(sm.plan.k3[m] * x3, L3, inv3)];
+                                    const C2<float> w3 = root2[mod_small(sm.plan.k3[m] * x3, L3, inv3)];
                                     C2<float> v = cmul(w3, r2[ct][h][i]);
                                     if (valid) {
                                         float2& dst = part_out[(base + m) * kBlockCols + colX[ct]];

@@ -193,34 +193,28 @@ hipError_t launch_fs_reduce(const FsReduceArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <typename T16, int KT, int CB>
+static hipError_t launch_fs_cb(int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+    const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(256 * CB);
+    const size_t dyn = fs_dyn_bytes(a.L);
+    if (kind == 0 && bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true, CB>), grid, block, dyn, st, pg, a);
+    else if (kind == 0)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, false, CB>), grid, block, dyn, st, pg, a);
+    else if (kind == 1 && bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true, CB>), grid, block, dyn, st, pg, a);
+    else if (kind == 1)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, false, CB>), grid, block, dyn, st, pg, a);
+    else if (bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true, CB>), grid, block, dyn, st, pg, a);
+    else
+        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, false, CB>), grid, block, dyn, st, pg, a);
+    return hipGetLastError();
+}
+
 template <typename T16, int KT>
 static hipError_t launch_fs_t(int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
-    const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks);
-    if (cb == 1) {
-        if (!bsplit) return hipErrorInvalidValue;
-        const dim3 block(256);
-        if (kind == 0)
-            hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true, 1>), grid, block, 0, st, pg, a);
-        else if (kind == 1)
-            hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true, 1>), grid, block, 0, st, pg, a);
-        else
-            hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true, 1>), grid, block, 0, st, pg, a);
-        return hipGetLastError();
-    }
-    const dim3 block(512);
-    if (kind == 0 && bsplit)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true, 2>), grid, block, 0, st, pg, a);
-    else if (kind == 0)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 0, false, 2>), grid, block, 0, st, pg, a);
-    else if (kind == 1 && bsplit)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, true, 2>), grid, block, 0, st, pg, a);
-    else if (kind == 1)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 1, false, 2>), grid, block, 0, st, pg, a);
-    else if (bsplit)
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, true, 2>), grid, block, 0, st, pg, a);
-    else
-        hipLaunchKernelGGL((fs_kernel<T16, KT, 2, false, 2>), grid, block, 0, st, pg, a);
-    return hipGetLastError();
+    return cb == 1 ? launch_fs_cb<T16, KT, 1>(kind, bsplit, pg, a, st) : launch_fs_cb<T16, KT, 2>(kind, bsplit, pg, a, st);
 }
 
 hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a,
