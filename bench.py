@@ -1080,10 +1080,16 @@ def serve_main(args):
         log(f"[serve] load {rho}: {len(specs)} Poisson arrivals at {rho * rate:.1f} requests/s")
         lat, wall_l = drive(specs, arrivals)
         units = sum(serve_units(sp, momenta) for sp in specs)
+        per_L = {}
+        for L in lattices:
+            sel = np.array([sp["L"] == L for sp in specs])
+            if sel.any():
+                per_L[f"{L}^3"] = {"requests": int(sel.sum()), "p50_ms": float(np.percentile(lat[sel], 50) * 1e3),
+                                   "p99_ms": float(np.percentile(lat[sel], 99) * 1e3)}
         levels.append({"rho": rho, "arrival_rate_per_s": rho * rate, "requests": len(specs),
                        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                        "mean_ms": float(lat.mean() * 1e3), "throughput_requests_per_s": len(specs) / wall_l,
-                       "throughput_units_per_s": units / wall_l})
+                       "throughput_units_per_s": units / wall_l, "per_lattice": per_L})
         log(f"[serve]   p50 {levels[-1]['p50_ms']:.1f} ms  p99 {levels[-1]['p99_ms']:.1f} ms")
     sv.close()
     res = {
@@ -1114,7 +1120,6 @@ def serve_main(args):
                        "latency_p99_ms": float(np.percentile(lat_sat, 99) * 1e3)},
         "load_levels": levels,
         "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
-        "kernels_ms_per_step": {kn: round(v["total_ms"] / prof_steps, 3) for kn, v in prof.items()},
         "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
         "roofline": roof,
     }
@@ -1378,6 +1383,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "component_rate": {"projected_complex_values_per_s": W.components(n_mom) / (ms_per_step * 1e-3)},
         "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
+        "kernels_ms_per_step": {kn: round(v["total_ms"] / prof_steps, 3) for kn, v in prof.items()},
         "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
         "roofline": roofline,
         "variants": {kn: c3pt.get_variant(c3pt.KIND[kn], mode, cls)

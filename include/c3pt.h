@@ -487,7 +487,8 @@ int c3pt_batch_destroy(c3pt_batch* batch);
  * caller's device memory; requests only name them.
  *
  * c3pt_server_create(proj, arena, arena_bytes, step_bytes, max_active, stream, &server)
- *   proj        C3PT_PROJ_NATIVE (FP32), _SPLIT_F16 or _SPLIT_BF16 projection.
+ *   proj        C3PT_PROJ_FACTORED, C3PT_PROJ_NATIVE (FP32), _SPLIT_F16 or
+ *               _SPLIT_BF16 projection.
  *   arena       caller-owned device memory (256-byte aligned) from which the
  *               outputs of admitted requests are sub-allocated (first fit);
  *               it must outlive the server.
@@ -497,18 +498,30 @@ int c3pt_batch_destroy(c3pt_batch* batch);
  *   max_active  requests in flight at once.
  *   stream      hipStream_t every launch of the server goes to.
  * c3pt_server_submit(server, &req, &id)   validate and queue a request (host
- *   only; enqueues nothing).  Rejected with C3PT_EINVAL when its outputs can
- *   never fit the arena or one noise vector of one timeslice exceeds a packet.
+ *   only; enqueues nothing).  Rejected with C3PT_EINVAL when its outputs (and,
+ *   for the dense projections, its two phase tables) can never fit the arena,
+ *   one noise vector of one timeslice exceeds a packet, or (factored) the
+ *   momentum list does not factor.
  * c3pt_server_step(server, &n_active, &n_queued)   one iteration: admit
- *   queued requests in arrival order while a slot and arena space are free;
- *   take packets round-robin from every active request until the step
- *   workspace is full; enqueue their contraction + projection (persistent
- *   queue kernels shared by all requests of the step), the FP64 reduction,
+ *   queued requests while a slot and arena space are free, the one with the
+ *   least work first (the one first in line is taken in turn once later ones
+ *   have passed it 2 * max_active times); take packets from the active
+ *   requests with the least remaining work first, each as many as fit, until
+ *   the step workspace is full (a request that had no packet for four steps
+ *   goes first); enqueue their contraction + projection (one launch per
+ *   producer kind shared by all requests of the step), the FP64 reduction,
  *   and the combines of every request whose last packet ran, then an event
  *   marking it complete.  Returns after enqueueing; at most two steps are in
- *   flight (the call waits for the step before last).
+ *   flight (the call waits for the step before last).  The dense projections'
+ *   phase tables live in the arena: built at the first admission that needs
+ *   them, held while a request using them is active, then kept as a cache
+ *   and evicted (least recently used first) when the arena needs the space.
+ *   A request that cannot be admitted for a reason of its own (its tables
+ *   cannot be built, or cannot fit even with nothing else active) leaves the
+ *   queue as failed.
  * c3pt_server_poll(server, id)   1 when the request's results are complete on
- *   the device, 0 if not yet, or a negative status.
+ *   the device, 0 if not yet, or a negative status (a failed request: the
+ *   status of its failure, with its message in c3pt_last_error).
  * c3pt_server_result(server, id, &res)   device pointers of the request's
  *   outputs inside the arena (valid once admitted; complete once polled 1):
  *     spec[p]  [n_noise][n_mom][192] meson, [n_noise][n_mom][3072] nucleon
@@ -516,10 +529,11 @@ int c3pt_batch_destroy(c3pt_batch* batch);
  *     comb[p]  [n_pairs][n_tau][n_ops][64 or 1024][64]
  *   p < n_parts (1 meson, 2 nucleon); layouts and orders as the single calls.
  * c3pt_server_release(server, id)   return the request's arena space (waits
- *   for its completion); also drops a request still queued.
+ *   for its completion); also drops a request still queued or failed.
  * c3pt_server_info(server, &n_active, &n_queued, &largest_free_arena_bytes)
- * c3pt_server_destroy(server)   synchronizes the stream, frees the workspace
- *   and phase tables; the arena stays the caller's.
+ * c3pt_server_destroy(server)   synchronizes the stream and frees the
+ *   workspace; the arena (with the phase tables cached in it) stays the
+ *   caller's.
  * A request's results do not depend on the other requests in flight: each
  * output element is summed over the same fixed site chunks in the same order.
  * One host thread drives a server.

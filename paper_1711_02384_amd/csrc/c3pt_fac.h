@@ -418,14 +418,17 @@ fac_kernel(ProjGrid pg, typename ProdT<R, KT, kFacThreads>::Args pa) {
     __shared__ FacSmem<R, KT> sm;
     __shared__ typename Prod::Buf buf[2];
     const int tid = threadIdx.x;
-    // work item; consecutive items (same input slice and chunk) on one XCD
+    // work item (within, share, chunk), chunk outermost; consecutive items run
+    // on one XCD: those of one (share, chunk) read the same input slice, and
+    // neighbouring shares (timeslices) of a chunk read each other's slice as
+    // the derivative's t +- 1 neighbours while it is still in that XCD's L2
     const int nw = gridDim.x, w = blockIdx.x;
     const int full = (nw / 8) * 8;
     const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
     const int within = item % pg.n_per_share;
     const int rest = item / pg.n_per_share;
-    const int chunk = rest % pg.n_chunks;
-    const int share = rest / pg.n_chunks;
+    const int share = rest % pg.n_share;
+    const int chunk = rest / pg.n_share;
     const int cb = Prod::colblock(pa, share, within);
     const typename Prod::Ctx ctx = Prod::resolve(pa, pg.V3, cb);
     TileGeom tg;

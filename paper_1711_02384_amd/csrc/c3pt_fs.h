@@ -148,14 +148,16 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     const int lane = tid & 63, g = lane >> 4, cl = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int cbj = wave >> 2, at = wave & 3;
-    // work item; consecutive items (same share and chunk) on one XCD
+    // work item (within, share, chunk), chunk outermost; consecutive items run
+    // on one XCD (one share and chunk read the same slice; neighbouring
+    // shares read each other's as the time derivative's neighbours)
     const int nw = gridDim.x, w = blockIdx.x;
     const int full = (nw / 8) * 8;
     const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
     const int within = item % pg.n_per_share;
     const int rest = item / pg.n_per_share;
-    const int chunk = rest % pg.n_chunks;
-    const int share = rest / pg.n_chunks;
+    const int share = rest % pg.n_share;
+    const int chunk = rest / pg.n_share;
     const int N = fa.N;
     const int ngroup = (N + CB - 1) / CB;
     const int slot = within / ngroup;

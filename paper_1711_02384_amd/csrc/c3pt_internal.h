@@ -58,8 +58,9 @@ struct FactorPlan {
 };
 
 // One launch of the fused contraction + projection kernel.  Work items are
-// (share, chunk, within) with column block cb = colblock(share, within):
-// items that read the same input slice (same share) and chunk are issued to
+// (chunk, share, within), chunk outermost, with column block
+// cb = colblock(share, within): items that read the same input slice (same
+// share) and chunk, and the neighbouring shares of a chunk, are issued to
 // the same XCD so that they meet in its L2.
 struct ProjGrid {
     int V3;

@@ -319,8 +319,8 @@ proj_kernel(ProjGrid pg, typename ProdT<typename Cons::R, Cons::KT, Cons::NT>::A
     const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
     const int within = item % pg.n_per_share;
     const int rest = item / pg.n_per_share;
-    const int chunk = rest % pg.n_chunks;
-    const int share = rest / pg.n_chunks;
+    const int share = rest % pg.n_share;
+    const int chunk = rest / pg.n_share;
     const int cb = Prod::colblock(pa, share, within);
     const typename Prod::Ctx ctx = Prod::resolve(pa, pg.V3, cb);
     const int mt = (pg.n_mom + 7) >> 3;

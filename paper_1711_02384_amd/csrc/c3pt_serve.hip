@@ -120,6 +120,8 @@ struct Request {
     // arena
     size_t off = 0, bytes = 0;
     size_t o_spec[2], o_ins[2], o_comb[2], o_k, o_pairs, o_w;
+    size_t o_plan[2] = {0, 0};   // factored: FactorPlan for sigma = -1 (spectators), +1 (insertions)
+    std::vector<int> tab_key[2];  // dense: phase tables held while active (sigma = -1, +1)
     size_t spec_elems, ins_elems, comb_elems;
     int n_parts;
     char* pinned = nullptr;   // host copy of k | pairs | w, uploaded asynchronously at admission
@@ -129,6 +131,18 @@ struct Request {
     bool combines_enqueued = false;
     hipEvent_t done = nullptr;
     ReqState state = kQueued;
+    int error = 0;                // status of a request that failed at admission, and its message
+    std::string error_msg;
+    double work = 0;              // all packets: column blocks x sites
+    int bypassed = 0;             // admissions that passed it while it was first in line
+    int idle_steps = 0;           // steps since it last had a packet in one
+};
+
+// A dense phase table in the arena, shared by the requests that use it.
+struct PhaseEntry {
+    size_t off = 0, bytes = 0;
+    int refs = 0;                 // active requests holding it
+    long long last_use = 0;
 };
 
 }  // namespace
@@ -152,12 +166,12 @@ struct c3pt_server {
     bool staged_used[2] = {false, false};
     int step_no = 0;
     int* counters = nullptr;   // device [kMaxLaunches]
-    std::map<std::vector<int>, void*> phase;   // (L, sigma, mode, mtmax, k...) -> table
+    std::map<std::vector<int>, PhaseEntry> phase;   // dense: (L, sigma, mode, mtmax, k...) -> table in the arena
+    long long clock = 0;
     std::deque<Request*> queue;
     std::vector<Request*> active;
     std::map<long long, Request*> all;
     long long next_id = 1;
-    size_t rr = 0;             // round-robin start
     int n_cu = 256;
 };
 
@@ -214,57 +228,91 @@ int mtmax_of(int n_mom) {
     return mt <= 4 ? 4 : mt <= 8 ? 8 : mt <= 12 ? 12 : 16;
 }
 
-// Phase table for (extents, sign, momentum list) in the server's layout;
-// built on the server stream at first use.
-int phase_for(c3pt_server* sv, const Request& q, int sigma, const void** out) {
-    const int mtmax = mtmax_of(q.n_mom);
-    std::vector<int> key = {q.L[0], q.L[1], q.L[2], sigma, sv->fac ? 100 : sv->mode, mtmax};
+// Work of a packet for scheduling: column blocks x sites.
+double packet_work(const Request& q, const Packet& p) {
+    const double cbs = p.kind == 2 ? (double)p.nn * p.nt * q.n_ops : (double)p.nn * (p.kind == 1 ? 16 : 1);
+    return cbs * q.V3;
+}
+
+std::vector<int> phase_key(const c3pt_server* sv, const Request& q, int sigma) {
+    std::vector<int> key = {q.L[0], q.L[1], q.L[2], sigma, sv->mode, mtmax_of(q.n_mom)};
     key.insert(key.end(), q.k.begin(), q.k.end());
+    return key;
+}
+
+size_t phase_bytes(const c3pt_server* sv, const Request& q) {
+    return align_up(phase_table_bytes(sv->mode, q.V3, mtmax_of(q.n_mom)));
+}
+
+// Arena allocation that evicts cached phase tables no active request holds
+// (least recently used first) until the block fits; false if it cannot fit
+// with every such table gone.
+bool arena_alloc(c3pt_server* sv, size_t bytes, size_t* off) {
+    while (!sv->alloc.alloc(bytes, off)) {
+        auto victim = sv->phase.end();
+        for (auto e = sv->phase.begin(); e != sv->phase.end(); ++e)
+            if (e->second.refs == 0 && (victim == sv->phase.end() || e->second.last_use < victim->second.last_use))
+                victim = e;
+        if (victim == sv->phase.end()) return false;
+        sv->alloc.release(victim->second.off, victim->second.bytes);
+        sv->phase.erase(victim);
+    }
+    return true;
+}
+
+// Dense modes: hold the phase table for (extents, sign, momentum list),
+// building it in the arena at first use (on the server stream, before the
+// request's packets).  Tables no active request holds stay cached and are
+// evicted, least recently used first, when the arena needs their space.
+// Returns C3PT_OK, 1 when the arena has no room now, or a negative status.
+int hold_phase(c3pt_server* sv, Request& q, int sigma) {
+    std::vector<int> key = phase_key(sv, q, sigma);
     auto it = sv->phase.find(key);
-    if (it != sv->phase.end()) {
-        *out = it->second;
-        return C3PT_OK;
-    }
-    if (sv->fac) {
-        FactorPlan plan;
-        if (!api_factor_plan(q.L, sigma, q.k.data(), q.n_mom, &plan))
-            return api_fail(C3PT_EUNSUPPORTED, "the momentum list does not factor");
-        void* dp = nullptr;
-        if (hipMalloc(&dp, sizeof(FactorPlan)) != hipSuccess) {
-            (void)hipGetLastError();
-            return api_fail(C3PT_ENOMEM, "factor plan allocation failed");
+    if (it == sv->phase.end()) {
+        const size_t bytes = phase_bytes(sv, q);
+        size_t off;
+        if (!arena_alloc(sv, bytes, &off)) return 1;
+        PhaseSpec ph;
+        memset(&ph, 0, sizeof(ph));
+        for (int j = 0; j < 3; ++j) ph.L[j] = q.L[j];
+        ph.sigma = sigma;
+        ph.n_mom = q.n_mom;
+        for (int m = 0; m < q.n_mom; ++m)
+            for (int j = 0; j < 3; ++j) ph.k[j][m] = (uint8_t)(((q.k[3 * m + j] % q.L[j]) + q.L[j]) % q.L[j]);
+        if (launch_phase_table(sv->mode, ph, q.V3, mtmax_of(q.n_mom), sv->arena + off, sv->st) != hipSuccess) {
+            sv->alloc.release(off, bytes);
+            return api_fail(C3PT_EDEVICE, "building a phase table failed");
         }
-        if (hipMemcpy(dp, &plan, sizeof(FactorPlan), hipMemcpyHostToDevice) != hipSuccess) {
-            hipFree(dp);
-            return api_fail(C3PT_EDEVICE, "uploading a factor plan failed");
-        }
-        sv->phase[key] = dp;
-        *out = dp;
-        return C3PT_OK;
+        PhaseEntry e;
+        e.off = off;
+        e.bytes = bytes;
+        it = sv->phase.emplace(key, e).first;
     }
-    PhaseSpec ph;
-    memset(&ph, 0, sizeof(ph));
-    for (int j = 0; j < 3; ++j) ph.L[j] = q.L[j];
-    ph.sigma = sigma;
-    ph.n_mom = q.n_mom;
-    for (int m = 0; m < q.n_mom; ++m)
-        for (int j = 0; j < 3; ++j) ph.k[j][m] = (uint8_t)(((q.k[3 * m + j] % q.L[j]) + q.L[j]) % q.L[j]);
-    void* tab = nullptr;
-    if (hipMalloc(&tab, phase_table_bytes(sv->mode, q.V3, mtmax)) != hipSuccess) {
-        (void)hipGetLastError();
-        return api_fail(C3PT_ENOMEM, "phase table allocation failed");
-    }
-    if (launch_phase_table(sv->mode, ph, q.V3, mtmax, tab, sv->st) != hipSuccess) {
-        hipFree(tab);
-        return api_fail(C3PT_EDEVICE, "building a phase table failed");
-    }
-    sv->phase[key] = tab;
-    *out = tab;
+    it->second.refs += 1;
+    it->second.last_use = ++sv->clock;
+    q.tab_key[sigma > 0 ? 1 : 0] = key;
     return C3PT_OK;
 }
 
-// Arena layout of a request's outputs and parameter tables.
-size_t layout(Request& q) {
+void drop_phases(c3pt_server* sv, Request& q) {
+    for (auto& key : q.tab_key) {
+        if (key.empty()) continue;
+        auto it = sv->phase.find(key);
+        if (it != sv->phase.end() && it->second.refs > 0) it->second.refs -= 1;
+        key.clear();
+    }
+}
+
+// Device address of the request's phase data for sign sigma: its own factor
+// plan (factored) or the held table (dense).
+const void* phase_of(const c3pt_server* sv, const Request& q, int sigma) {
+    if (sv->fac) return sv->arena + q.off + q.o_plan[sigma > 0 ? 1 : 0];
+    return sv->arena + sv->phase.at(q.tab_key[sigma > 0 ? 1 : 0]).off;
+}
+
+// Arena layout of a request's outputs and parameter tables (factored: and its
+// two factor plans, uploaded with the parameters).
+size_t layout(Request& q, bool fac) {
     const int n_tau = (int)q.taus.size();
     const int spin = spin_of(q);
     q.spec_elems = (size_t)q.n_noise * q.n_mom * spin * 3;
@@ -282,6 +330,10 @@ size_t layout(Request& q) {
     q.o_k = take(q.k.size() * sizeof(int));
     q.o_pairs = take(q.pairs.size() * sizeof(int));
     q.o_w = take((size_t)q.n_noise * sizeof(double));
+    if (fac) {
+        q.o_plan[0] = take(sizeof(FactorPlan));
+        q.o_plan[1] = take(sizeof(FactorPlan));
+    }
     return o;
 }
 
@@ -291,32 +343,74 @@ void destroy_request(Request* q) {
     delete q;
 }
 
-// Admit queued requests in arrival order while a slot and arena space are free.
+// True when some admitted request (running, or done and not yet released)
+// holds arena space that will be returned.
+bool arena_held(const c3pt_server* sv) {
+    for (const auto& kv : sv->all)
+        if (kv.second->state == kActive || kv.second->state == kDone) return true;
+    return false;
+}
+
+// A request that cannot be admitted for a reason of its own leaves the queue
+// as failed; poll and result report its status.
+void fail_queued(c3pt_server* sv, Request* q, int rc) {
+    q->state = kFailed;
+    q->error = rc;
+    q->error_msg = c3pt_last_error();
+    sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), q));
+}
+
+// Admission while a slot is free: the queued request with the least work
+// first, except that the one first in line is taken in turn once later ones
+// have passed it 2 * max_active times.  Outputs (and dense phase tables)
+// must fit the arena; when the chosen request does not fit now, admission
+// stops until space is released.
 int admit(c3pt_server* sv) {
     while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active) {
-        Request* q = sv->queue.front();
+        Request* head = sv->queue.front();
+        Request* q = head;
+        if (head->bypassed < 2 * sv->max_active)
+            for (Request* c : sv->queue)
+                if (c->work < q->work) q = c;
         size_t off;
-        if (!sv->alloc.alloc(q->bytes, &off)) break;
+        if (!arena_alloc(sv, q->bytes, &off)) {
+            if (!arena_held(sv)) {
+                // nothing will release space: the request can never fit
+                fail_queued(sv, q, api_fail(C3PT_ENOMEM, "the request's outputs do not fit the arena"));
+                continue;
+            }
+            break;
+        }
         q->off = off;
         char* base = sv->arena + off;
-        // parameter tables of the request, stream-ordered before its packets
-        if (hipMemcpyAsync(base + q->o_k, q->pinned, q->o_w - q->o_k + (size_t)q->n_noise * sizeof(double),
-                           hipMemcpyHostToDevice, sv->st) != hipSuccess) {
+        if (!sv->fac) {
+            int rc = hold_phase(sv, *q, -1);
+            if (rc == C3PT_OK) rc = hold_phase(sv, *q, +1);
+            if (rc != C3PT_OK) {
+                drop_phases(sv, *q);
+                sv->alloc.release(off, q->bytes);
+                if (rc < 0) {
+                    fail_queued(sv, q, rc);
+                    continue;
+                }
+                if (!arena_held(sv)) {
+                    // nothing will release space: the request can never fit
+                    fail_queued(sv, q, api_fail(C3PT_ENOMEM, "outputs and phase tables exceed the arena"));
+                    continue;
+                }
+                break;
+            }
+        }
+        // parameter tables (and factor plans) of the request, stream-ordered before its packets
+        if (hipMemcpyAsync(base + q->o_k, q->pinned, q->pinned_bytes, hipMemcpyHostToDevice, sv->st) != hipSuccess) {
+            drop_phases(sv, *q);
             sv->alloc.release(off, q->bytes);
             return api_fail(C3PT_EDEVICE, "uploading request parameters failed");
         }
-        const void* tab;
-        if (int rc = phase_for(sv, *q, -1, &tab)) {
-            sv->alloc.release(off, q->bytes);
-            return rc;
-        }
-        if (int rc = phase_for(sv, *q, +1, &tab)) {
-            sv->alloc.release(off, q->bytes);
-            return rc;
-        }
         make_packets(*q, sv->packet_cap);
         q->state = kActive;
-        sv->queue.pop_front();
+        if (q != head) head->bypassed += 1;
+        sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), q));
         sv->active.push_back(q);
     }
     return C3PT_OK;
@@ -377,7 +471,7 @@ BatchJob packet_job(c3pt_server* sv, const Request& q, const Packet& p, std::vec
         d.out_off = p.n0;
         d.out = (double2*)(sv->arena + q.off + q.o_spec[p.part]);
     }
-    phase_for(sv, q, d.sigma, &tab);   // cached at admission
+    tab = phase_of(sv, q, d.sigma);   // held since admission
     d.phase = tab;
     return d;
 }
@@ -388,7 +482,10 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     if (int rc = admit(sv)) return rc;
     if (sv->active.empty()) return C3PT_OK;
 
-    // ---- choose packets round-robin under the workspace budget ----
+    // ---- choose packets under the workspace budget ----
+    // Requests with the least remaining work first, each taking as many of
+    // its packets as fit, so short requests finish in few steps; a request
+    // that has had no packet for four steps goes first.
     struct Chosen {
         Request* q;
         Packet p;
@@ -396,29 +493,37 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     };
     std::vector<Chosen> chosen;
     size_t used = 0, items = 0, tau_rows = 0;
-    const size_t n_act = sv->active.size();
-    bool progress = true;
-    while (progress) {
-        progress = false;
-        for (size_t i = 0; i < n_act; ++i) {
-            Request* q = sv->active[(sv->rr + i) % n_act];
-            if (q->todo.empty()) continue;
+    std::vector<std::pair<double, Request*>> order;
+    for (Request* q : sv->active) {
+        if (q->todo.empty()) continue;
+        double rem = 0;
+        for (const Packet& p : q->todo) rem += packet_work(*q, p);
+        order.push_back({q->idle_steps >= 4 ? -1.0 / (1 + q->idle_steps) : rem, q});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, Request*>& a, const std::pair<double, Request*>& b) {
+                         return a.first < b.first;
+                     });
+    for (auto& oq : order) {
+        Request* q = oq.second;
+        bool took = false;
+        while (!q->todo.empty()) {
             const Packet& p = q->todo.front();
             const size_t b = packet_partial(*q, p);
             const size_t it = b / ((size_t)q->n_mom * kBlockCols * sizeof(float2));
             const size_t tr = p.kind == 2 ? (size_t)p.nt : 0;
             if (!chosen.empty() && (used + b > sv->step_bytes || items + it > kMaxStepItems ||
                                     tau_rows + tr > (size_t)kMaxStepTau || chosen.size() >= (size_t)kMaxStepJobs))
-                continue;
+                break;
             chosen.push_back({q, p, b});
             used += b;
             items += it;
             tau_rows += tr;
             q->todo.pop_front();
-            progress = true;
+            took = true;
         }
+        q->idle_steps = took ? 0 : q->idle_steps + 1;
     }
-    sv->rr = (sv->rr + 1) % std::max<size_t>(1, n_act);
 
     // ---- parameter block: jobs | items | tau rows | output offsets ----
     size_t n_tau_rows = 0;
@@ -599,8 +704,12 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     // their arena space until released)
     std::vector<Request*> still;
     for (Request* q : sv->active) {
-        if (q->combines_enqueued) q->state = kDone;
-        else still.push_back(q);
+        if (q->combines_enqueued) {
+            q->state = kDone;
+            drop_phases(sv, *q);   // its launches are enqueued; the tables stay cached
+        } else {
+            still.push_back(q);
+        }
     }
     sv->active.swap(still);
     return C3PT_OK;
@@ -609,7 +718,6 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
 void free_server(c3pt_server* sv) {
     if (!sv) return;
     for (auto& kv : sv->all) destroy_request(kv.second);
-    for (auto& kv : sv->phase) hipFree(kv.second);
     for (int i = 0; i < 2; ++i) {
         if (sv->staging[i]) hipHostFree(sv->staging[i]);
         if (sv->staged[i]) hipEventDestroy(sv->staged[i]);
@@ -731,9 +839,10 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
                               (q->n_parts == 2 && (!q->G2[tn] || !q->G2[tp]))))
             return reject("missing neighbour slice for the derivative operators");
     }
+    FactorPlan plans[2];
     if (sv->fac) {
-        FactorPlan plan;
-        if (!api_factor_plan(q->L, +1, q->k.data(), q->n_mom, &plan))
+        if (!api_factor_plan(q->L, -1, q->k.data(), q->n_mom, &plans[0]) ||
+            !api_factor_plan(q->L, +1, q->k.data(), q->n_mom, &plans[1]))
             return reject("the momentum list does not factor (too many distinct k1 or (k1, k2))");
         // chunks of about 2048 or 4096 sites: the insertion's tuned variant (its
         // work dominates a request) sets them for every part of the request
@@ -745,8 +854,9 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
         q->chunk_sites = (tiles + q->n_chunks - 1) / q->n_chunks * kSiteTile;
         q->n_chunks = (q->V3 + q->chunk_sites - 1) / q->chunk_sites;
     }
-    q->bytes = layout(*q);
-    if (q->bytes > sv->arena_bytes) return reject("the request's outputs exceed the arena");
+    q->bytes = layout(*q, sv->fac);
+    if (q->bytes + (sv->fac ? 0 : 2 * phase_bytes(sv, *q)) > sv->arena_bytes)
+        return reject("the request's outputs (and phase tables) exceed the arena");
     const size_t per_cb = (size_t)q->n_chunks * q->n_mom * kBlockCols * sizeof(float2);
     const size_t cap = request_cap(*q, sv->packet_cap);
     if (per_cb * q->n_ops > cap || per_cb * (q->kind == C3PT_REQ_NUCLEON ? 16 : 1) > cap)
@@ -756,7 +866,8 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
         destroy_request(q);
         return api_fail(C3PT_EDEVICE, "event creation failed");
     }
-    q->pinned_bytes = q->o_w - q->o_k + (size_t)q->n_noise * sizeof(double);
+    q->pinned_bytes = sv->fac ? q->o_plan[1] + sizeof(FactorPlan) - q->o_k
+                              : q->o_w - q->o_k + (size_t)q->n_noise * sizeof(double);
     if (hipHostMalloc((void**)&q->pinned, q->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         q->pinned = nullptr;
@@ -767,6 +878,11 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
     memcpy(q->pinned + (q->o_pairs - q->o_k), q->pairs.data(), q->pairs.size() * sizeof(int));
     double* w = (double*)(q->pinned + (q->o_w - q->o_k));
     for (int i = 0; i < q->n_noise; ++i) w[i] = 1.0 / q->n_noise;
+    if (sv->fac)
+        for (int sg = 0; sg < 2; ++sg) memcpy(q->pinned + (q->o_plan[sg] - q->o_k), &plans[sg], sizeof(FactorPlan));
+    make_packets(*q, sv->packet_cap);
+    for (const Packet& pk : q->todo) q->work += packet_work(*q, pk);
+    q->todo.clear();
     q->id = sv->next_id++;
     sv->all[q->id] = q;
     sv->queue.push_back(q);
@@ -788,6 +904,7 @@ int c3pt_server_poll(c3pt_server* sv, long long id) {
     auto it = sv->all.find(id);
     if (it == sv->all.end()) return api_fail(C3PT_EINVAL, "unknown request id");
     Request* q = it->second;
+    if (q->state == kFailed) return api_fail(q->error, q->error_msg.c_str());
     if (q->state != kDone) return 0;
     const hipError_t e = hipEventQuery(q->done);
     if (e == hipSuccess) return 1;
@@ -801,6 +918,7 @@ int c3pt_server_result(c3pt_server* sv, long long id, c3pt_result* res) {
     if (it == sv->all.end()) return api_fail(C3PT_EINVAL, "unknown request id");
     Request* q = it->second;
     if (q->state == kQueued) return api_fail(C3PT_EINVAL, "request not admitted yet");
+    if (q->state == kFailed) return api_fail(q->error, q->error_msg.c_str());
     memset(res, 0, sizeof(*res));
     char* base = sv->arena + q->off;
     for (int p = 0; p < q->n_parts; ++p) {
@@ -823,7 +941,7 @@ int c3pt_server_release(c3pt_server* sv, long long id) {
     if (q->state == kDone) {
         if (hipEventSynchronize(q->done) != hipSuccess) return api_fail(C3PT_EDEVICE, "event sync failed");
         sv->alloc.release(q->off, q->bytes);
-    } else {
+    } else if (q->state == kQueued) {
         sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), q));
     }
     sv->all.erase(it);

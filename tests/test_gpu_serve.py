@@ -136,34 +136,80 @@ def test_serve_mix_matches_oracle_and_alone(proj, name):
     sv2.close()
 
 
-def test_serve_admission_by_memory():
+def _request_bytes(q, proj):
+    """Arena bytes of a request: its outputs and parameter tables (factored:
+    and its two factor plans, under 4 KB), and for the dense FP32 projection
+    its two phase tables ([sites rounded to 32][8 x momentum tiles] complex64)."""
+    n_tau, n_mom = len(q.taus), len(q.k)
+    n_pairs = len(q.pairs) if q.pairs is not None else n_mom * n_mom
+    b = 16 * (q.N * n_mom * 192 + q.N * n_tau * q.n_ops * n_mom * 192 + n_pairs * n_tau * q.n_ops * 4096) + 8192
+    if proj == 0:
+        V3 = q.L[0] * q.L[1] * q.L[2]
+        mt = (n_mom + 7) // 8
+        mtmax = 4 if mt <= 4 else 8 if mt <= 8 else 12 if mt <= 12 else 16
+        b += 2 * ((V3 + 31) // 32 * 32 * 8 * mtmax * 8 + 256)
+    return b
+
+
+@pytest.mark.parametrize("proj", [0, 3])
+def test_serve_admission_by_memory(proj):
+    """An arena with room for the largest request only: requests wait for
+    space (dense: outputs and the request's two phase tables, which stay
+    cached and are evicted when another request needs the room) and all
+    finish with the right results."""
     import paper_1711_02384_amd as c3pt
     reqs = [q for q in _mix() if q.kind == "meson"]
-    sizes = []
-    for q in reqs:
-        n_tau, n_mom = len(q.taus), len(q.k)
-        n_pairs = len(q.pairs) if q.pairs is not None else n_mom * n_mom
-        b = 16 * (q.N * n_mom * 192 + q.N * n_tau * q.n_ops * n_mom * 192 + n_pairs * n_tau * q.n_ops * 4096)
-        sizes.append(b + 4096)
-    arena = max(sizes) + (64 << 10)    # room for the largest request only
-    sv, ids = _serve(c3pt, reqs, 0, arena=arena)
+    arena = max(_request_bytes(q, proj) for q in reqs) + (64 << 10)
+    sv, ids = _serve(c3pt, reqs, proj, arena=arena)
     na, nq = sv.step()
-    _say(f"after the first step: active {na}, queued {nq}")
+    _say(f"proj {proj}: after the first step: active {na}, queued {nq}")
     assert nq >= 1
     done = {}
     pending = list(ids)
-    while pending:
+    for _ in range(5000):
+        if not pending:
+            break
         sv.step()
+        sv.stream.synchronize()
         for i in list(pending):
             if sv.poll(i):
                 done[i] = _copy(sv, i)
                 sv.release(i)          # frees the arena for the next request
                 pending.remove(i)
+    assert not pending, f"requests {pending} made no progress"
     torch.cuda.synchronize()
     for q, i in zip(reqs, ids):
         S, I, C = q.oracle()
         assert rel_err(done[i]["ins"][0].cpu().numpy(), I[0]) < TOL
         assert rel_err(done[i]["comb"][0].cpu().numpy(), C[0]) < TOL
+    sv.close()
+
+
+def test_serve_short_requests_first():
+    """Size-aware scheduling: a short request submitted after a long one
+    finishes first (the long one is cut into many packets over several
+    steps), and both results match the oracle."""
+    import paper_1711_02384_amd as c3pt
+    long_q = Req("meson", (14, 12, 16), 8, (3, 5, 7), 0, 7, 4, 5, 5, cfg=37, pairs=[(1, 1), (0, 10)])
+    short_q = Req("meson", (5, 3, 4), 6, (4, 1, 2), 2, 2, 1, 1, 1, cfg=38)
+    sv, (i_long, i_short) = _serve(c3pt, [long_q, short_q], 3, step=4 << 20)
+    finished = []
+    for _ in range(5000):
+        if len(finished) == 2:
+            break
+        sv.step()
+        sv.stream.synchronize()
+        for i in (i_long, i_short):
+            if i not in finished and sv.poll(i):
+                finished.append(i)
+    assert len(finished) == 2, "requests made no progress"
+    torch.cuda.synchronize()
+    assert finished[0] == i_short, finished
+    for q, i in ((long_q, i_long), (short_q, i_short)):
+        got = sv.result(i)
+        S, I, C = q.oracle()
+        assert rel_err(got["ins"][0].cpu().numpy(), I[0]) < TOL
+        assert rel_err(got["comb"][0].cpu().numpy(), C[0]) < TOL
     sv.close()
 
 
