@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--arena-gib", type=float, default=48.0, help="serve: output arena")
     ap.add_argument("--step-mib", type=float, default=1024.0, help="serve: partial-sum workspace per step")
     ap.add_argument("--max-active", type=int, default=32, help="serve: requests in flight")
+    ap.add_argument("--step-work", type=float, default=0.0,
+                    help="serve: cap on a step's work in column blocks x sites (0: none)")
     return ap.parse_args()
 
 
@@ -1001,7 +1003,7 @@ def serve_main(args):
     pool = ServePool(lattices, dev)
     log(f"[serve] inputs resident ({time.perf_counter() - t0:.1f} s)")
     sv = c3pt.Server(proj=proj_flag, arena_bytes=int(args.arena_gib * 2**30),
-                     step_bytes=int(args.step_mib * 2**20), max_active=args.max_active)
+                     step_bytes=int(args.step_mib * 2**20), max_active=args.max_active, step_work=args.step_work)
     clock = time.perf_counter
 
     def drive(specs, arrivals):
@@ -1086,10 +1088,14 @@ def serve_main(args):
             if sel.any():
                 per_L[f"{L}^3"] = {"requests": int(sel.sum()), "p50_ms": float(np.percentile(lat[sel], 50) * 1e3),
                                    "p99_ms": float(np.percentile(lat[sel], 99) * 1e3)}
+        # slowdown: latency over the request's own share of the saturated rate
+        # (its units / the saturated units per second)
+        slow = lat / np.array([serve_units(sp, momenta) / value for sp in specs])
         levels.append({"rho": rho, "arrival_rate_per_s": rho * rate, "requests": len(specs),
                        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                        "mean_ms": float(lat.mean() * 1e3), "throughput_requests_per_s": len(specs) / wall_l,
-                       "throughput_units_per_s": units / wall_l, "per_lattice": per_L})
+                       "throughput_units_per_s": units / wall_l, "per_lattice": per_L,
+                       "slowdown_p50": float(np.percentile(slow, 50)), "slowdown_p99": float(np.percentile(slow, 99))})
         log(f"[serve]   p50 {levels[-1]['p50_ms']:.1f} ms  p99 {levels[-1]['p99_ms']:.1f} ms")
     sv.close()
     res = {
@@ -1111,7 +1117,7 @@ def serve_main(args):
                                "insertion, combine on pairs p'=q or p'=0; one step = one request of the saturated "
                                "closed batch",
                    "lattices": lattices, "arena_gib": args.arena_gib, "step_mib": args.step_mib,
-                   "max_active": args.max_active, "saturation_requests": n_sat},
+                   "max_active": args.max_active, "step_work": args.step_work, "saturation_requests": n_sat},
         "latency_ms": {"p50": levels[-1]["p50_ms"] if levels else None,
                        "p99": levels[-1]["p99_ms"] if levels else None,
                        "at_rho": loads[-1] if loads else None},

@@ -519,6 +519,13 @@ int c3pt_batch_destroy(c3pt_batch* batch);
  *   A request that cannot be admitted for a reason of its own (its tables
  *   cannot be built, or cannot fit even with nothing else active) leaves the
  *   queue as failed.
+ * c3pt_server_set_step_work(server, max_work)   cap a step's work at max_work
+ *   column blocks x sites (0, the default: no cap beyond the workspace).  A
+ *   step ends where the next packet would pass the cap (it always takes one),
+ *   and requests admitted afterwards are cut into packets of at most a
+ *   quarter of it where one noise vector (of one timeslice) allows; shorter
+ *   steps bound how long a newly admitted request waits for the steps in
+ *   flight.  C3PT_EINVAL for a negative cap.
  * c3pt_server_poll(server, id)   1 when the request's results are complete on
  *   the device, 0 if not yet, or a negative status (a failed request: the
  *   status of its failure, with its message in c3pt_last_error).
@@ -575,6 +582,7 @@ typedef struct c3pt_server c3pt_server;
 int c3pt_server_create(int proj, void* arena, unsigned long long arena_bytes, unsigned long long step_bytes,
                        int max_active, void* stream, c3pt_server** server);
 int c3pt_server_submit(c3pt_server* server, const c3pt_request* req, long long* id);
+int c3pt_server_set_step_work(c3pt_server* server, double max_work);
 int c3pt_server_step(c3pt_server* server, int* n_active, int* n_queued);
 int c3pt_server_poll(c3pt_server* server, long long id);
 int c3pt_server_result(c3pt_server* server, long long id, c3pt_result* res);

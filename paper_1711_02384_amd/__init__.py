@@ -52,7 +52,7 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
             "c3pt_batch_destroy", "c3pt_server_create", "c3pt_server_submit", "c3pt_server_step",
             "c3pt_server_poll", "c3pt_server_result", "c3pt_server_release", "c3pt_server_info",
             "c3pt_server_destroy", "c3pt_insertion_noalloc", "c3pt_noalloc_scratch_bytes",
-            "c3pt_debug_scale_allocations")
+            "c3pt_debug_scale_allocations", "c3pt_server_set_step_work")
 
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
 MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4, "fs16": 5, "fsbf16": 5, "batchfac": 6}
@@ -166,8 +166,10 @@ def _load():
     lib.c3pt_server_release.argtypes = [vp, ctypes.c_longlong]
     lib.c3pt_server_info.argtypes = [vp, ip, ip, ctypes.POINTER(ull)]
     lib.c3pt_server_destroy.argtypes = [vp]
+    lib.c3pt_server_set_step_work.argtypes = [vp, ctypes.c_double]
     for name in ("c3pt_server_create", "c3pt_server_submit", "c3pt_server_step", "c3pt_server_poll",
-                 "c3pt_server_result", "c3pt_server_release", "c3pt_server_info", "c3pt_server_destroy"):
+                 "c3pt_server_result", "c3pt_server_release", "c3pt_server_info", "c3pt_server_destroy",
+                 "c3pt_server_set_step_work"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -705,7 +707,7 @@ class Server:
     until the request is released; the object keeps references to them."""
 
     def __init__(self, proj: int = PROJ_NATIVE, arena_bytes: int = 1 << 30, step_bytes: int = 256 << 20,
-                 max_active: int = 8, stream=None):
+                 max_active: int = 8, stream=None, step_work: float = 0.0):
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
         self._handle = ctypes.c_void_p()
@@ -715,6 +717,8 @@ class Server:
         _check(lib.c3pt_server_create(int(proj), self.arena.data_ptr(), int(arena_bytes), int(step_bytes),
                                       int(max_active), ctypes.c_void_p(self.stream.cuda_stream),
                                       ctypes.byref(self._handle)))
+        if step_work:
+            _check(lib.c3pt_server_set_step_work(self._handle, float(step_work)))
 
     def submit(self, req: dict) -> int:
         """req: kind ("meson" | "nucleon"), L, T, r, t_src, t_f, eta [N,12,V3], G_t (dict/list of

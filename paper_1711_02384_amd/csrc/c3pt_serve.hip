@@ -157,6 +157,7 @@ struct c3pt_server {
     size_t arena_bytes = 0;
     Arena alloc;
     size_t step_bytes = 0, packet_cap = 0;
+    double step_work = 0;      // cap on a step's work (column blocks x sites); 0: none
     void* partial = nullptr;
     // step parameters: one device block, two pinned staging blocks
     size_t params_cap = 0;
@@ -181,6 +182,7 @@ constexpr int kMaxLaunches = 32;
 constexpr int kMaxStepJobs = 4096;
 constexpr size_t kMaxStepItems = (size_t)1 << 20;
 constexpr int kMaxStepTau = 1 << 16;
+constexpr int kServeMaxChunks = 16;   // factored: x3-plane chunks per request at most
 
 int spin_of(const Request& q) { return q.kind == C3PT_REQ_MESON ? 64 : 1024; }
 
@@ -197,25 +199,33 @@ size_t request_cap(const Request& q, size_t packet_cap) {
 }
 
 // Packets of a request, each within the packet cap (the caller checks that
-// one noise vector of one timeslice fits).
-void make_packets(Request& q, size_t packet_cap) {
+// one noise vector of one timeslice fits) and, when work_cap > 0, within
+// work_cap column blocks x sites where a packet of one noise vector (of one
+// timeslice) allows it.
+void make_packets(Request& q, size_t packet_cap, double work_cap) {
     const size_t cap = request_cap(q, packet_cap);
     const size_t per_cb = (size_t)q.n_chunks * q.n_mom * kBlockCols * sizeof(float2);
     const int n_tau = (int)q.taus.size();
     const int spec_kind = q.kind == C3PT_REQ_MESON ? 0 : 1;
     const int spec_cb = spec_kind == 1 ? 16 : 1;
-    const int nn_spec = std::max<int>(1, std::min<size_t>(q.n_noise, cap / (per_cb * spec_cb)));
+    auto by_work = [&](double per_unit) {
+        return work_cap > 0 ? std::max(1.0, std::floor(work_cap / per_unit)) : 1e9;
+    };
+    const int nn_spec = std::max<int>(
+        1, (int)std::min<double>({(double)q.n_noise, (double)(cap / (per_cb * spec_cb)), by_work((double)spec_cb * q.V3)}));
     for (int part = 0; part < q.n_parts; ++part)
         for (int n0 = 0; n0 < q.n_noise; n0 += nn_spec)
             q.todo.push_back(Packet{spec_kind, part, n0, std::min(nn_spec, q.n_noise - n0), 0, 0});
     const size_t per_tau = per_cb * q.n_noise * q.n_ops;
+    const double work_tau = (double)q.n_noise * q.n_ops * q.V3;
     for (int part = 0; part < q.n_parts; ++part) {
-        if (per_tau <= cap) {
-            const int nt = std::max<int>(1, std::min<size_t>(n_tau, cap / per_tau));
+        if (per_tau <= cap && by_work(work_tau) >= 1.0 && (work_cap <= 0 || work_tau <= work_cap)) {
+            const int nt = std::max<int>(1, (int)std::min<double>({(double)n_tau, (double)(cap / per_tau), by_work(work_tau)}));
             for (int t0 = 0; t0 < n_tau; t0 += nt)
                 q.todo.push_back(Packet{2, part, 0, q.n_noise, t0, std::min(nt, n_tau - t0)});
         } else {
-            const int nn = std::max<int>(1, cap / (per_cb * q.n_ops));
+            const int nn = std::max<int>(
+                1, (int)std::min<double>((double)(cap / (per_cb * q.n_ops)), by_work((double)q.n_ops * q.V3)));
             for (int t0 = 0; t0 < n_tau; ++t0)
                 for (int n0 = 0; n0 < q.n_noise; n0 += nn)
                     q.todo.push_back(Packet{2, part, n0, std::min(nn, q.n_noise - n0), t0, 1});
@@ -407,7 +417,7 @@ int admit(c3pt_server* sv) {
             sv->alloc.release(off, q->bytes);
             return api_fail(C3PT_EDEVICE, "uploading request parameters failed");
         }
-        make_packets(*q, sv->packet_cap);
+        make_packets(*q, sv->packet_cap, sv->step_work / 4);
         q->state = kActive;
         if (q != head) head->bypassed += 1;
         sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), q));
@@ -493,6 +503,7 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     };
     std::vector<Chosen> chosen;
     size_t used = 0, items = 0, tau_rows = 0;
+    double work = 0;
     std::vector<std::pair<double, Request*>> order;
     for (Request* q : sv->active) {
         if (q->todo.empty()) continue;
@@ -512,11 +523,14 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
             const size_t b = packet_partial(*q, p);
             const size_t it = b / ((size_t)q->n_mom * kBlockCols * sizeof(float2));
             const size_t tr = p.kind == 2 ? (size_t)p.nt : 0;
+            const double wk = packet_work(*q, p);
             if (!chosen.empty() && (used + b > sv->step_bytes || items + it > kMaxStepItems ||
-                                    tau_rows + tr > (size_t)kMaxStepTau || chosen.size() >= (size_t)kMaxStepJobs))
+                                    tau_rows + tr > (size_t)kMaxStepTau || chosen.size() >= (size_t)kMaxStepJobs ||
+                                    (sv->step_work > 0 && work + wk > sv->step_work)))
                 break;
             chosen.push_back({q, p, b});
             used += b;
+            work += wk;
             items += it;
             tau_rows += tr;
             q->todo.pop_front();
@@ -846,7 +860,10 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
             return reject("the momentum list does not factor (too many distinct k1 or (k1, k2))");
         // chunks of about 2048 or 4096 sites: the insertion's tuned variant (its
         // work dominates a request) sets them for every part of the request
-        q->chunk_sites = batch_fac_chunk_planes(q->L, api_variant(2, kModeBatchFacVariants, (q->n_mom + 7) / 8));
+        // and at most kServeMaxChunks chunks, so that large lattices keep their
+        // partial sums (and packets) small
+        q->chunk_sites = std::max(batch_fac_chunk_planes(q->L, api_variant(2, kModeBatchFacVariants, (q->n_mom + 7) / 8)),
+                                  (q->L[2] + kServeMaxChunks - 1) / kServeMaxChunks);
         q->n_chunks = (q->L[2] + q->chunk_sites - 1) / q->chunk_sites;
     } else {
         q->n_chunks = (q->V3 + kMaxSitesPerChunkF32 - 1) / kMaxSitesPerChunkF32;
@@ -880,13 +897,20 @@ int c3pt_server_submit(c3pt_server* sv, const c3pt_request* R, long long* id) {
     for (int i = 0; i < q->n_noise; ++i) w[i] = 1.0 / q->n_noise;
     if (sv->fac)
         for (int sg = 0; sg < 2; ++sg) memcpy(q->pinned + (q->o_plan[sg] - q->o_k), &plans[sg], sizeof(FactorPlan));
-    make_packets(*q, sv->packet_cap);
+    make_packets(*q, sv->packet_cap, 0);
     for (const Packet& pk : q->todo) q->work += packet_work(*q, pk);
     q->todo.clear();
     q->id = sv->next_id++;
     sv->all[q->id] = q;
     sv->queue.push_back(q);
     *id = q->id;
+    return api_ok();
+}
+
+int c3pt_server_set_step_work(c3pt_server* sv, double max_work) {
+    if (!sv) return api_fail(C3PT_EINVAL, "server is NULL");
+    if (!(max_work >= 0)) return api_fail(C3PT_EINVAL, "max_work must be >= 0");
+    sv->step_work = max_work;
     return api_ok();
 }
 

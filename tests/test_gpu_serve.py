@@ -134,6 +134,17 @@ def test_serve_mix_matches_oracle_and_alone(proj, name):
             for a, b in zip(got[key], want[key]):
                 assert torch.equal(a, b)
     sv2.close()
+    # and with a cap on each step's work (packets of a few column blocks)
+    sv3 = c3pt.Server(proj=proj, arena_bytes=64 << 20, step_bytes=4 << 20, max_active=8, step_work=3e4)
+    ids3 = [sv3.submit(q.request()) for q in reqs]
+    sv3.run_until_done(ids3)
+    torch.cuda.synchronize()
+    for i, want in zip(ids3, mix):
+        got = sv3.result(i)
+        for key in ("spec", "ins", "comb"):
+            for a, b in zip(got[key], want[key]):
+                assert torch.equal(a, b)
+    sv3.close()
 
 
 def _request_bytes(q, proj):
