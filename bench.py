@@ -123,25 +123,10 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
                      "fs_plans", "fs_scratch", "fs_spectator", "fs_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
-    # 32^3 step: local (484189 + 264384 KiB) and derivative (1940642 + 1114112 KiB) dispatches of one call
-    ("meson32", "fac", "fac_insertion", 5): ((484189 + 1940642) * 2048 + (264384 + 1114112) * 1024, "d9861a908adb74c3"),
-    # the same with the symmetrized derivative: + left-derivative dispatch (1169850 + 1057536 KiB)
-    ("meson32", "fac", "fac_insertion", 9): ((484190 + 1947661 + 1169850) * 2048
-                                             + (264384 + 1114112 + 1057536) * 1024, "d9861a908adb74c3"),
-    # with the two-derivative operators: local + five derivative-producer dispatches (1941550 + 1114112 KiB each)
-    ("meson32", "fac", "fac_insertion", 21): ((484218 + 5 * 1941550) * 2048 + (264384 + 5 * 1114112) * 1024,
-                                              "d9861a908adb74c3"),
-    # with the symmetrized two-derivative operators: 17 local-producer dispatches (484185 + 264384 KiB each)
-    # and 9 derivative-producer dispatches (1958778 + 1114112 KiB each) per call
-    ("meson32", "fac", "fac_insertion", 37): ((17 * 484185 + 9 * 1958778) * 2048 + (17 * 264384 + 9 * 1114112) * 1024,
-                                              "d9861a908adb74c3"),
-    # 48^3 step: one nucleon spectator dispatch (414814 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414814 * 2048 + 857088 * 1024, "d9861a908adb74c3"),
-    # 48^3 step, split-precision fused form: one local insertion dispatch (1555470 + 803520 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): (1555470 * 2048 + 803520 * 1024, "0b4eb1b293354a4e"),
-    # two-sink 32^3 x 96 step: local (3771200 + 4687200 KiB) and derivative (32728293 + 19622400 KiB)
-    ("twosink32", "fac", "fac_insertion", 5): ((3771200 + 32728293) * 2048 + (4687200 + 19622400) * 1024,
-                                               "d9861a908adb74c3"),
+    # 48^3 step, split-precision fused form: one local insertion dispatch (1555510 + 803520 KiB)
+    ("nucleon48", "fs16", "fs_insertion", 1): (1555510 * 2048 + 803520 * 1024, "3057e56867de2af4"),
+    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413222 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413222 * 2048 + 857088 * 1024, "3057e56867de2af4"),
 }
 
 

@@ -53,6 +53,7 @@ struct SmearArgs {
     int n_outer, n_inner;
     double norm;            // 1 / (1 + 6 kappa)
     double kappa_norm;      // kappa / (1 + 6 kappa)
+    int vb_per_item;        // 8-vector blocks one workgroup runs on its tile (set by launch_smear)
 };
 hipError_t launch_smear(bool f64, const SmearArgs& a, hipStream_t st);
 

@@ -45,39 +45,50 @@ __global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
 // Nucleon diquark -> split B blocks.  Block (a1', a1), plane p' = 48 c + 3 q + c'
 // with q = 4 a2' + a2:
 //   Q[q][c][c'] = sum eps_{abc} eps_{a'b'c'} G1[(a1',a)][(a1,a')] G2[(a2',b)][(a2,b')]
-// One thread per (block, q, site x1 of a padded row): consecutive lanes read
-// consecutive sites of each propagator plane and write the hi and lo words of
-// their site into the four-site groups.
+// A workgroup takes 256 consecutive sites of the padded rows and one block;
+// each thread reads its site's G1 entries of the block once and loops over
+// the 16 q, reading G2's (a2', a2) entries.  Items are (site tile, block),
+// block fastest, and consecutive items run on one XCD, so the 16 blocks of a
+// tile read G2 from that XCD's L2 and each propagator entry comes from HBM
+// once.  Lanes are consecutive sites: every read and every hi / lo word
+// written is coalesced.
 // ---------------------------------------------------------------------------
 template <typename T16>
 __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
     const int Lp = a.Lp;
-    const long long total = 256LL * a.rows * Lp;
     const int L1 = a.L[0];
     const unsigned V3 = (unsigned)(a.L[0] * a.L[1] * a.L[2]);
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (long long)gridDim.x * blockDim.x) {
-        const int x1 = (int)(idx % Lp);
-        long long rest = idx / Lp;
-        const int row = (int)(rest % a.rows);
-        rest /= a.rows;
-        const int q = (int)(rest % 16);
-        const int blk = (int)(rest / 16);
-        const int a1p = blk >> 2, a1 = blk & 3, a2p = q >> 2, a2 = q & 3;
-        const bool ok = x1 < L1;
-        const unsigned n = (unsigned)(min(x1, L1 - 1) + L1 * row);
-        C2<float> g1[3][3], g2[3][3];
+    const int nw = gridDim.x, w = blockIdx.x;
+    const int full = (nw / 8) * 8;
+    const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
+    const int blk = item % 16;
+    const long long sidx = (long long)(item / 16) * 256 + threadIdx.x;
+    if (sidx >= (long long)a.rows * Lp) return;
+    const int x1 = (int)(sidx % Lp);
+    const int row = (int)(sidx / Lp);
+    const int a1p = blk >> 2, a1 = blk & 3;
+    const bool ok = x1 < L1;
+    const unsigned n = (unsigned)(min(x1, L1 - 1) + L1 * row);
+    C2<float> g1[3][3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const float2 x = a.G1[(unsigned)((3 * a1p + u) * 12 + 3 * a1 + v) * V3 + n];
+            g1[u][v] = {x.x, x.y};
+        }
+    unsigned* out = (unsigned*)((FsGroup*)a.out + (size_t)blk * kFsPlanes * a.rows * (Lp / 4));
+    const size_t gw = (size_t)(x1 >> 2) * 8 + (x1 & 3);   // the site's hi word in its group; lo is 4 words on
+    for (int q = 0; q < 16; ++q) {
+        const int a2p = q >> 2, a2 = q & 3;
+        C2<float> g2[3][3];
 #pragma unroll
         for (int u = 0; u < 3; ++u)
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-                const float2 x = a.G1[(unsigned)((3 * a1p + u) * 12 + 3 * a1 + v) * V3 + n];
                 const float2 y = a.G2[(unsigned)((3 * a2p + u) * 12 + 3 * a2 + v) * V3 + n];
-                g1[u][v] = {x.x, x.y};
                 g2[u][v] = {y.x, y.y};
             }
-        unsigned* out = (unsigned*)((FsGroup*)a.out + (size_t)blk * kFsPlanes * a.rows * (Lp / 4));
-        const size_t gw = (size_t)(x1 >> 2) * 8 + (x1 & 3);   // the site's hi word in its group; lo is 4 words on
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
@@ -179,11 +190,13 @@ hipError_t launch_fs_split(bool bf16, const FsSplitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_fs_diquark(bool bf16, const FsDiquarkArgs& a, hipStream_t st) {
-    const long long total = 256LL * a.rows * a.Lp;
+    const long long tiles = ((long long)a.rows * a.Lp + 255) / 256;
+    if (tiles * 16 > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(tiles * 16));
     if (bf16)
-        hipLaunchKernelGGL(fs_diquark_kernel<__bf16>, dim3(grid_for(total)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(fs_diquark_kernel<__bf16>, grid, dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(fs_diquark_kernel<_Float16>, dim3(grid_for(total)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(fs_diquark_kernel<_Float16>, grid, dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -6,12 +6,14 @@
 // propagator slice (n_outer = 4 spins, n_inner = 12 columns) or noise and
 // solution vectors (n_outer = 4 N, n_inner = 1).
 //
-// A workgroup takes 64 consecutive sites and 8 vectors, one (site, vector)
-// per thread: the six links of each site go to LDS once and serve all 8;
-// lanes run over sites, so every field read (centre and the six neighbours)
-// is a coalesced row.  Work items
-// are dealt to the eight XCDs in contiguous ranges of sites, so that the
-// x2 / x3 neighbours a workgroup reads were mostly fetched into the same L2.
+// A workgroup takes 64 consecutive sites and a run of 8-vector blocks, one
+// (site, vector) per thread and block: the six links of each site go to LDS
+// once and serve every block of the run (the link bytes are read once per
+// run, not once per 8 vectors); lanes run over sites, so every field read
+// (centre and the six neighbours) is a coalesced row.  Work items are (site
+// tile, run) with the tile fastest, dealt to the eight XCDs in contiguous
+// ranges, so that the x2 / x3 neighbour rows a workgroup reads were mostly
+// fetched into the same L2 by the tiles just before it.
 #include "c3pt_device.h"
 #include "c3pt_analysis.h"
 
@@ -32,7 +34,7 @@ __global__ void __launch_bounds__(kSmThreads) smear_kernel(SmearArgs a) {
     const int nw = gridDim.x, w = blockIdx.x;
     const int full = (nw / 8) * 8;
     const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
-    const int tile = item % gx, vb = item / gx;
+    const int tile = item % gx, run = item / gx;
     const int s0 = tile * kSmSites;
     const C2<R>* U = (const C2<R>*)a.U;
     const unsigned V3 = (unsigned)a.V3;
@@ -81,8 +83,10 @@ __global__ void __launch_bounds__(kSmThreads) smear_kernel(SmearArgs a) {
     const C2<R>* in = (const C2<R>*)a.in;
     C2<R>* out = (C2<R>*)a.out;
     const int n_vec = a.n_outer * a.n_inner;
-    const int v = vb * kSmVecs + tid / kSmSites;
-    if (v < n_vec) {
+    const int vb0 = run * a.vb_per_item;
+    for (int vb = vb0; vb < vb0 + a.vb_per_item; ++vb) {
+        const int v = vb * kSmVecs + tid / kSmSites;
+        if (v >= n_vec) break;
         const int o = v / a.n_inner, in_i = v - o * a.n_inner;
         unsigned base[3];
 #pragma unroll
@@ -113,10 +117,15 @@ __global__ void __launch_bounds__(kSmThreads) smear_kernel(SmearArgs a) {
     }
 }
 
-hipError_t launch_smear(bool f64, const SmearArgs& a, hipStream_t st) {
-    const long long gx = (a.V3 + kSmSites - 1) / kSmSites;
-    const long long gy = (a.n_outer * (long long)a.n_inner + kSmVecs - 1) / kSmVecs;
-    const dim3 grid((unsigned)(gx * gy));
+hipError_t launch_smear(bool f64, const SmearArgs& a0, hipStream_t st) {
+    const long long gx = (a0.V3 + kSmSites - 1) / kSmSites;
+    const long long gy = (a0.n_outer * (long long)a0.n_inner + kSmVecs - 1) / kSmVecs;
+    // runs of vector blocks: about 2048 workgroups in all (at least one block each)
+    const long long runs = std::max<long long>(1, std::min<long long>(gy, (2048 + gx - 1) / gx));
+    SmearArgs a = a0;
+    a.vb_per_item = (int)((gy + runs - 1) / runs);
+    const long long n_runs = (gy + a.vb_per_item - 1) / a.vb_per_item;
+    const dim3 grid((unsigned)(gx * n_runs));
     if (f64)
         hipLaunchKernelGGL(smear_kernel<double>, grid, dim3(kSmThreads), 0, st, a);
     else
