@@ -100,3 +100,29 @@ def test_fused_is_deterministic_and_matches_fp32_factored():
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert rel_err(a.cpu().numpy(), f.cpu().numpy()) < TOL
+
+
+def test_fused_two_momentum_groups():
+    """A momentum list of more than 128 momenta (|k|^2 <= 10: 147) runs as two
+    groups, each with its own factor plan; every part against the oracle."""
+    import paper_1711_02384_amd as c3pt
+    L, T, taus, N, r = (12, 8, 6), 4, [0, 3], 2, (3, 1, 2)
+    k = c3pt.momentum_list(10)
+    assert len(k) > 128
+    w = Workload(L, T, N, cfg=71, taus=taus, links=True, reduced=True, second_prop=True)
+    geom = c3pt.Geom(L, T, r=r, proj=c3pt.PROJ_FACTORED_F16)
+    _say(f"fused f16 two groups: {len(k)} momenta")
+    S = c3pt.spectator_meson(_t(w.G1), _t(w.eta), k, geom).cpu().numpy()
+    SB = c3pt.spectator_baryon(_t(w.G1), _t(w.G1b), _t(w.eta), k, geom).cpu().numpy()
+    G = {t: _t(v) for t, v in w.G3.items()}
+    s = {t: _t(v) for t, v in w.s.items()}
+    U = {t: _t(v) for t, v in w.U.items()}
+    I5 = c3pt.insertion(G, s, taus, k, geom, U_t=U, n_ops=5).cpu().numpy()
+    torch.cuda.synchronize()
+    S_o = oracle.spectator_meson(w.G1, w.eta, L, k, r=r)
+    SB_o = oracle.spectator_baryon(w.G1, w.G1b, w.eta, L, k, r=r)
+    I_o = oracle.insertion(w.G3, w.s, taus, L, T, k, r=r, U_t=w.U, n_ops=5)
+    es, eb = rel_err(S, S_o), rel_err(SB, SB_o)
+    e5 = max(rel_err(I5[:, j, op], I_o[:, j, op]) for j in range(len(taus)) for op in range(5))
+    _say(f"fused f16 two groups: meson {es:.2e} nucleon {eb:.2e} insertion max {e5:.2e}")
+    assert es < TOL and eb < TOL and e5 < TOL
