@@ -98,16 +98,25 @@ __global__ void reset_kernel(int* counters, int n) {
 
 // ---------------------------------------------------------------------------
 // Combine: C[pair][tau][op][s][t] = sum_i w_i sum_c S_i(p')[s][c] I_i(q,tau)[op][t][c]
-// One workgroup per (pair, tau, op) x 64-row spectator block; 256 threads, each
-// a 4x4 block of the 64x64 output tile.  FP64 throughout.
+// One workgroup per (pair, tau, op) x 64-row spectator block: a 64 x 64
+// complex GEMM over K = (noise, colour).  The weighted spectator rows and the
+// insertion columns of four noise vectors at a time are staged in LDS; each
+// of the four waves owns a 32 x 32 quadrant as 2 x 2 tiles of the FP64 MFMA
+// 16x16x4, with the complex product as four real products
+// (re += ar br - ai bi, im += ar bi + ai br).  FP64 throughout.
 // ---------------------------------------------------------------------------
 constexpr int kCombNoiseChunk = 4;
+constexpr int kCombK = kCombNoiseChunk * 3;   // staged K entries (a multiple of the MFMA's 4)
 
 __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
-    __shared__ double2 sA[kCombNoiseChunk * 3][64];
-    __shared__ double2 sB[kCombNoiseChunk * 3][64];
+    using MF = Mfma<double>;
+    using acc_t = MF::acc_t;
+    __shared__ double2 sA[kCombK][64];
+    __shared__ double2 sB[kCombK][64];
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r0 = (wave >> 1) * 32, c0 = (wave & 1) * 32;   // the wave's quadrant
+    const int li = lane & 15, lk = lane >> 4;
     const int sb = blockIdx.y;
     size_t rest = blockIdx.x;
     const int o = (int)(rest % a.n_sel);
@@ -126,51 +135,68 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
     const size_t spin3 = (size_t)a.spin * 3;
     const int n_tau_in = a.n_tau_in > 0 ? a.n_tau_in : a.n_tau;
 
-    double2 acc[4][4];
+    acc_t cr[2][2], ci[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+        for (int tj = 0; tj < 2; ++tj) {
+            cr[ti][tj] = acc_t{0.0, 0.0, 0.0, 0.0};
+            ci[ti][tj] = acc_t{0.0, 0.0, 0.0, 0.0};
+        }
 
     for (int i0 = 0; i0 < a.n_noise; i0 += kCombNoiseChunk) {
-        const int nc = min(kCombNoiseChunk, a.n_noise - i0);
+        const int nk = min(kCombNoiseChunk, a.n_noise - i0) * 3;
         __syncthreads();
-        for (int e = tid; e < nc * 3 * 64; e += 256) {
+        // K entries past the last noise vector are zero
+        for (int e = tid; e < kCombK * 64; e += 256) {
             const int kk = e >> 6, x = e & 63;
-            const int i = i0 + kk / 3, c = kk % 3;
-            const double w = a.w[i];
-            const double2 sv = a.S[((size_t)i * a.n_p + p) * spin3 + (size_t)(sb * 64 + x) * 3 + c];
-            sA[kk][x] = make_double2(w * sv.x, w * sv.y);
-            sB[kk][x] = a.I[((((size_t)i * n_tau_in + a.tau0 + tau) * a.n_ops + op) * a.n_q + q) * kBlockCols +
-                            x * 3 + c];
+            double2 av = make_double2(0.0, 0.0), bv = make_double2(0.0, 0.0);
+            if (kk < nk) {
+                const int i = i0 + kk / 3, c = kk % 3;
+                const double w = a.w[i];
+                const double2 sv = a.S[((size_t)i * a.n_p + p) * spin3 + (size_t)(sb * 64 + x) * 3 + c];
+                av = make_double2(w * sv.x, w * sv.y);
+                bv = a.I[((((size_t)i * n_tau_in + a.tau0 + tau) * a.n_ops + op) * a.n_q + q) * kBlockCols + x * 3 + c];
+            }
+            sA[kk][x] = av;
+            sB[kk][x] = bv;
         }
         __syncthreads();
-        for (int kk = 0; kk < nc * 3; ++kk) {
-            double2 av[4], bv[4];
+        for (int k0 = 0; k0 < nk; k0 += 4) {
+            // A operand: row li of the tile, K entry k0 + lk; B: column li, K entry k0 + lk
+            double2 av[2], bv[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = sA[kk][ty + 16 * i];
+            for (int t = 0; t < 2; ++t) {
+                av[t] = sA[k0 + lk][r0 + 16 * t + li];
+                bv[t] = sB[k0 + lk][c0 + 16 * t + li];
+            }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = sB[kk][tx + 16 * j];
+            for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc[i][j].x = fma(av[i].x, bv[j].x, fma(-av[i].y, bv[j].y, acc[i][j].x));
-                    acc[i][j].y = fma(av[i].x, bv[j].y, fma(av[i].y, bv[j].x, acc[i][j].y));
+                for (int tj = 0; tj < 2; ++tj) {
+                    cr[ti][tj] = MF::mac(av[ti].x, bv[tj].x, cr[ti][tj]);
+                    cr[ti][tj] = MF::mac(-av[ti].y, bv[tj].y, cr[ti][tj]);
+                    ci[ti][tj] = MF::mac(av[ti].x, bv[tj].y, ci[ti][tj]);
+                    ci[ti][tj] = MF::mac(av[ti].y, bv[tj].x, ci[ti][tj]);
                 }
         }
     }
     // the output is written once and not read again by this step: streaming
-    // (non-temporal) stores keep it from displacing the inputs in the caches
+    // (non-temporal) stores keep it from displacing the inputs in the caches.
+    // FP64 accumulator layout: register j of lane l holds row 4 j + l / 16,
+    // column l % 16 of its tile.
     typedef double d2v __attribute__((ext_vector_type(2)));
     d2v* out = (d2v*)(a.out + ((((size_t)pr * a.n_tau + tau) * a.n_sel + o) * a.spin + (size_t)sb * 64) * 64);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const d2v v = {acc[i][j].x, acc[i][j].y};
-            __builtin_nontemporal_store(v, &out[(size_t)(ty + 16 * i) * 64 + tx + 16 * j]);
-        }
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int row = r0 + 16 * ti + 4 * j + lk, col = c0 + 16 * tj + li;
+                const d2v v = {cr[ti][tj][j], ci[ti][tj][j]};
+                __builtin_nontemporal_store(v, &out[(size_t)row * 64 + col]);
+            }
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
