@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--arena-gib", type=float, default=48.0, help="serve: output arena")
     ap.add_argument("--step-mib", type=float, default=1024.0, help="serve: partial-sum workspace per step")
     ap.add_argument("--max-active", type=int, default=32, help="serve: requests in flight")
+    ap.add_argument("--streams", type=int, default=1, choices=[1, 2],
+                    help="nucleon48: run the two isovector halves of the step on two streams")
     ap.add_argument("--step-work", type=float, default=0.0,
                     help="serve: cap on a step's work in column blocks x sites (0: none)")
     return ap.parse_args()
@@ -432,9 +434,11 @@ class Nucleon48(Meson32):
         self.baryon = True
         self.n2 = args.n2 if args.n2 is not None else 8
         self.analysis = args.analysis
+        self.streams = args.streams
         self.name = (f"nucleon 3pt, 48^3x64, t_f=14, tau=0..14, N=8, |k|^2<={self.n2}, spectators (u,u) and "
                      f"(u,d), isovector insertion (u and d), local"
-                     + (", proton channels (C gamma5, parity projectors, 16 Gamma_ins)" if self.analysis else ""))
+                     + (", proton channels (C gamma5, parity projectors, 16 Gamma_ins)" if self.analysis else "")
+                     + (", the two isovector halves on two streams" if self.streams == 2 else ""))
 
     def setup(self, c3pt, syn, dev, geom, k):
         import torch
@@ -454,6 +458,7 @@ class Nucleon48(Meson32):
         self.Cd = mk(len(self.pairs), n_tau, 1, 1024, 64)
         self.Cu = mk(len(self.pairs), n_tau, 1, 1024, 64)
         self.c3pt, self.geom, self.k = c3pt, geom, k
+        self.side = torch.cuda.Stream(device=dev) if self.streams == 2 else None   # default priority
         j0, j1 = self.taus.index(self.sample_taus[0]), self.taus.index(self.sample_taus[-1]) + 1
         self.sample_outputs = {"spectator_baryon": lambda: self.Suu[:self.sample_noise],
                                "insertion": lambda: self.Iu[:, j0:j1]}
@@ -466,15 +471,32 @@ class Nucleon48(Meson32):
                                                                 out=self.Suu))]
 
     def step(self):
+        """With --streams 2 the two isovector halves of the step run on two
+        streams: (u,u) spectator, d insertion and their combine on the current
+        stream, (u,d) spectator, u insertion and their combine on a second one
+        (default priority), joined at the end, so that the memory-bound passes
+        of one half (diquark, reduction, combine) run beside the
+        arithmetic-bound kernels of the other and the launch tails overlap.
+        Kernel durations then include that sharing."""
+        import torch
         c, g, k = self.c3pt, self.geom, self.k
         tf = self.t_f
+        main = torch.cuda.current_stream()
+        side = self.side if self.side is not None else main
+        fork = torch.cuda.Event()
+        fork.record(main)
+        side.wait_event(fork)
+        gs = c.Geom(g.L, g.T, r=g.r, proj=g.proj, stream=side.cuda_stream)
         # proton isovector: spectators (u,u) with the d insertion, (u,d) with the u insertion
         c.spectator_baryon(self.Gu[tf], self.Gu[tf], self.eta, k, g, out=self.Suu)
-        c.spectator_baryon(self.Gu[tf], self.Gd[tf], self.eta, k, g, out=self.Sud)
-        c.insertion(self.Gu, self.s, self.taus, k, g, out=self.Iu)
+        c.spectator_baryon(self.Gu[tf], self.Gd[tf], self.eta, k, gs, out=self.Sud)
         c.insertion(self.Gd, self.s, self.taus, k, g, out=self.Id)
+        c.insertion(self.Gu, self.s, self.taus, k, gs, out=self.Iu)
         c.combine(self.Suu, self.Id, pairs=self.pairs, out=self.Cd)
-        c.combine(self.Sud, self.Iu, pairs=self.pairs, out=self.Cu)
+        c.combine(self.Sud, self.Iu, pairs=self.pairs, out=self.Cu, stream=side.cuda_stream)
+        join = torch.cuda.Event()
+        join.record(side)
+        main.wait_event(join)
         if self.analysis:
             # proton channels of both currents: tr[P_pm G] for the 16 Gamma_ins
             self.ch_d = c.gamma_nucleon(self.Cd, c.PROTON_D)
