@@ -6,6 +6,12 @@
     counter per dispatch divided by the N MiB actually read (written) is the
     counter's scale factor on this GPU.
 
+``python -m paper_1711_02384_amd.pmc smear --kind prop|noise [--L 32] [--iters 50]``
+    The smearing kernel alone on a random 32^3 propagator slice (48 colour
+    vectors per site) or 50 random noise vectors (200 per site), ``iters``
+    launches timed with HIP events; prints microseconds per launch and the
+    algorithmic bytes (field read and written once, 216 B of links per site).
+
 ``python -m paper_1711_02384_amd.pmc summary DIR [--kernel SUBSTR] [--bytes B]``
     Summarise every ``*counter_collection.csv`` and ``*kernel_stats.csv`` under
     DIR (rocprofv3 output): per kernel, the mean of each counter per dispatch
@@ -33,6 +39,35 @@ def copy_main(mib: float, reps: int) -> None:
         dst.copy_(src)
     torch.cuda.synchronize()
     print(f"copied {n} bytes x {reps}", flush=True)
+
+
+def smear_main(kind: str, L: int, iters: int) -> None:
+    import torch
+    import paper_1711_02384_amd as c3pt
+    V3 = L ** 3
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    U = torch.randn((4, 3, 3, V3), dtype=torch.complex64, device=dev, generator=g)
+    geom = c3pt.Geom((L, L, L), 2 * L)
+    if kind == "prop":
+        f = torch.randn((12, 12, V3), dtype=torch.complex64, device=dev, generator=g)
+        run = lambda: c3pt.smear_propagator(f, U, geom, 0.25, iters, out=f)
+        alg = 144 * V3 * 8 * 2 + 216 * V3
+    else:
+        f = torch.randn((50, 12, V3), dtype=torch.complex64, device=dev, generator=g)
+        run = lambda: c3pt.smear_vectors(f, U, geom, 0.25, iters, out=f)
+        alg = 600 * V3 * 8 * 2 + 216 * V3
+    run()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    run()
+    b.record()
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / iters
+    print(f"smear {kind} {L}^3: {us:.1f} us per launch, algorithmic {alg / 1e6:.1f} MB, "
+          f"{alg / us / 1e3:.0f} GB/s", flush=True)
 
 
 def _rows(path):
@@ -77,6 +112,10 @@ def main(argv=None) -> None:
     c = sub.add_parser("copy")
     c.add_argument("--mib", type=float, default=1024.0)
     c.add_argument("--reps", type=int, default=5)
+    m = sub.add_parser("smear")
+    m.add_argument("--kind", choices=["prop", "noise"], default="prop")
+    m.add_argument("--L", type=int, default=32)
+    m.add_argument("--iters", type=int, default=50)
     s = sub.add_parser("summary")
     s.add_argument("dir")
     s.add_argument("--kernel", default=None)
@@ -84,6 +123,9 @@ def main(argv=None) -> None:
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         copy_main(a.mib, a.reps)
+        return
+    if a.cmd == "smear":
+        smear_main(a.kind, a.L, a.iters)
         return
     res = summary(a.dir, a.kernel)
     for name, d in sorted(res.items(), key=lambda kv: -kv[1].get("avg_ns", 0.0)):
