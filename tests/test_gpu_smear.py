@@ -2,8 +2,9 @@
 (pinned by the unit-link FFT multiplier, hermiticity, gauge covariance and a
 brute-force loop): propagator rows and noise vectors, complex128 (1e-12) and
 complex64 (1e-5), site counts that leave a ragged last tile, in-place calls
-with odd and even step counts, zero steps, kappa = 0, a 32^3 slice, and
-argument errors."""
+with odd and even step counts, zero steps, kappa = 0, a 32^3 slice, the
+shapes of the tiled complex64 kernel (ragged x2 tiles, one and two planes,
+long rows, several vector blocks), and argument errors."""
 import numpy as np
 import pytest
 
@@ -31,6 +32,14 @@ CASES = [
     ((7, 3, 2), "prop", 0, 0.1, 3, True, True),
     ((4, 4, 1), "vec", 1, 0.3, 2, False, False),
     ((32, 32, 32), "vec", 4, 0.25, 10, True, False),
+    # complex64 lattices of the tiled (x3-marching) kernel: tiles of several
+    # x1 rows with a ragged last one, one and two planes, long rows, more than
+    # one vector block, in-place
+    ((24, 12, 5), "prop", 0, 0.25, 3, True, False),
+    ((100, 3, 2), "vec", 2, 0.3, 2, True, False),
+    ((16, 9, 1), "vec", 3, 0.2, 3, True, True),
+    ((12, 40, 10), "prop", 0, 0.25, 2, True, False),
+    ((13, 7, 9), "vec", 5, 0.25, 4, True, False),
 ]
 
 
