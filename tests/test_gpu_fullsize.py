@@ -8,9 +8,11 @@ outputs (selected timeslices, noise vectors or momenta) one by one.
   and the combine on sampled pairs built from the oracle's own parts.
 * the same insertion with the symmetrized derivative (n_ops = 9), checked at
   the first and last timeslice;
-* 48^3 x 64 nucleon step with split-precision projection (BF16 and FP16 hi+lo):
-  the nucleon spectator for one noise vector and a momentum subset, and one
-  insertion timeslice.  Tolerance 1e-5 relative (Frobenius), the same as FP32.
+* 48^3 x 64 nucleon step with the fused split-precision projection (FP16 hi+lo,
+  the benchmark's form, and BF16), the dense split-precision projection and
+  the factored FP32 one: the nucleon spectator for one noise vector and a
+  momentum subset, and one insertion timeslice.  Tolerance 1e-5 relative
+  (the larger of Frobenius and max-element), the same as FP32.
 """
 import numpy as np
 import pytest
@@ -96,7 +98,8 @@ def test_meson32_symmetric_sampled():
             assert e < TOL32
 
 
-@pytest.mark.parametrize("proj,name", [(2, "bf16x2"), (1, "f16x2"), (3, "factored")])
+@pytest.mark.parametrize("proj,name", [(4, "fused f16 (the benchmark's form)"), (5, "fused bf16"), (2, "bf16x2"),
+                                       (1, "f16x2"), (3, "factored")])
 def test_nucleon48_split_sampled(proj, name):
     import paper_1711_02384_amd as c3pt
     L, T, N, t_f, cfg = (48, 48, 48), 64, 8, 14, 3
@@ -115,8 +118,17 @@ def test_nucleon48_split_sampled(proj, name):
     tau = 7
     G7 = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, tau))
     s7 = syn.round_to_c64(syn.solution_slice(L, N, cfg, tau))
-    I = c3pt.insertion({tau: _up(G7)}, {tau: _up(s7)}, [tau], k, geom).cpu().numpy()
+    Id = c3pt.insertion({tau: _up(G7)}, {tau: _up(s7)}, [tau], k, geom)
+    I = Id.cpu().numpy()
     I_o = oracle.insertion({tau: G7}, {tau: s7}, [tau], L, T, k)
     err = rel_err(I, I_o)
     _say(f"nucleon48 {name}: insertion tau={tau} rel err {err:.2e}")
     assert err < TOL32
+    if proj == 4:
+        # the full-size nucleon combine (1024 x 64 per pair) on these parts
+        pairs = [(0, 0), (30, 30), (0, 92), (122, 7)]
+        SBd = torch.from_numpy(SB).cuda()
+        C = c3pt.combine(SBd, Id, pairs=pairs).cpu().numpy()
+        e = rel_err(C, oracle.combine(SB, I, pairs=pairs))
+        _say(f"nucleon48 {name}: combine on {len(pairs)} pairs rel err {e:.2e}")
+        assert e < 1e-12
