@@ -126,9 +126,9 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
     # 48^3 step, split-precision fused form: one local insertion dispatch (1555510 + 803520 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): (1555510 * 2048 + 803520 * 1024, "3057e56867de2af4"),
+    ("nucleon48", "fs16", "fs_insertion", 1): (1555510 * 2048 + 803520 * 1024, "ae1117ea05b172de"),
     # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413222 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413222 * 2048 + 857088 * 1024, "3057e56867de2af4"),
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413222 * 2048 + 857088 * 1024, "ae1117ea05b172de"),
 }
 
 
@@ -147,17 +147,33 @@ def _function_text(src: str, name: str) -> str:
     raise KeyError(name)
 
 
-def sources_hash():
+def _code_only(src: str) -> str:
+    """C++ source without its comments and blank lines, each line stripped, so
+    that a change of comments alone leaves the hash of the kernels unchanged
+    (the sources hold no string literal with comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(ln.strip() for ln in src.splitlines() if ln.strip())
+
+
+def sources_hash(read=None):
+    """Hash of the code (comments excluded) of the factored and fused kernels
+    and of the host functions that plan and launch them; `read(name)` returns
+    the text of a file of csrc/ (default: the working tree)."""
     import hashlib
+    if read is None:
+        base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_02384_amd", "csrc")
+
+        def read(name):
+            with open(os.path.join(base, name)) as f:
+                return f.read()
     h = hashlib.sha256()
-    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1711_02384_amd", "csrc")
     for name in TRAFFIC_SOURCES:
-        with open(os.path.join(base, name), "rb") as f:
-            h.update(f.read())
-    with open(os.path.join(base, "c3pt_api.hip")) as f:
-        api = f.read()
+        h.update(_code_only(read(name)).encode())
+    api = read("c3pt_api.hip")
     for name in TRAFFIC_FUNCTIONS:
-        h.update(_function_text(api, name).encode())
+        h.update(_code_only(_function_text(api, name)).encode())
     return h.hexdigest()[:16]
 
 

@@ -389,10 +389,13 @@ int c3pt_profile_read(c3pt_kernel_stat* stats, int max, int reset);
  * work on one GPU.  c3pt_batch_create validates every job, builds the phase
  * tables and work queues and records the whole schedule into one HIP graph;
  * c3pt_batch_run replays it.  The projection work of all jobs of one kind is
- * executed by one persistent kernel whose workgroups take (job, column block,
- * site chunk) items from a queue, so lattices of different sizes share the
- * chip until the last item.  A job's sites are summed in FP32 chunks of at
- * most 2048 sites (fixed by its own extents) and the chunks in FP64 in a
+ * one launch over a list of (job, column block, site chunk) items (factored:
+ * one workgroup per item, handed out in order as CUs free up; dense: a
+ * persistent kernel whose workgroups take items from a queue), so lattices of
+ * different sizes share the chip until the last item.  A job's sites are
+ * summed in FP32 chunks (at most 2048 sites, or whole x3 planes of about 2048
+ * or 4096 sites for the factored kernels, fixed by its own extents and the
+ * tuned variant) and the chunks in FP64 in a
  * fixed order, so its output does not depend on the other jobs of the batch
  * or on the schedule: a job gives bit-identical results alone or in any mix
  * (with the same kernel variant).  Against the single calls, which split

@@ -57,7 +57,7 @@ EXPORTED = ("c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion", "
 KIND = {"spectator_meson": 0, "spectator_baryon": 1, "insertion": 2}
 MODE = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3, "fac": 4, "fs16": 5, "fsbf16": 5, "batchfac": 6}
 # "fac", "fs16" / "fsbf16", "batchfac": variant slots of the factored projection, the
-# split-precision fused projection and the persistent factored kernels (batches, serving)
+# split-precision fused projection and the factored kernels of batches and serving
 
 
 class C3ptError(RuntimeError):

@@ -275,9 +275,8 @@ int variant_count(int kind, int mode, int cls) {
     // workgroup; 3 = split in the kernel, one block per workgroup.  The
     // nucleon's diquark always has its pass.
     if (mode == kModeFsVariants) return 4;
-    // persistent factored (batches and serving): bit 0 chunk planes summed in
-    // registers, bit 1 32-site tiles where they apply, bit 2 chunks of about
-    // 4096 instead of 2048 sites
+    // factored kernels of batches and serving: bit 0 32-site tiles where they
+    // apply, bit 1 chunks of about 4096 instead of 2048 sites
     if (mode == kModeBatchFacVariants) return kBatchFacVariants;
     if (mode == kModeF64) return cls == 0 ? 1 : 0;
     return kVariantsPerClass[cls];

@@ -1,14 +1,16 @@
 // Batches: many spectator / insertion calls over uneven lattices, executed as
-// one HIP graph whose projection work runs in persistent kernels that take
-// (job, column block, chunk) items from a queue.  This is how the many source
-// positions of a measurement are handled on one GPU (the paper distributes
-// them over MPI ranks, Sec. 2.2-2.3): jobs of different lattice sizes share
-// the queue, so the chip stays loaded until the last item.
+// one HIP graph whose projection work runs over lists of (job, column block,
+// chunk) items: one workgroup per item for the factored kernels, persistent
+// workgroups taking items from a queue for the dense ones.  This is how the
+// many source positions of a measurement are handled on one GPU (the paper
+// distributes them over MPI ranks, Sec. 2.2-2.3): jobs of different lattice
+// sizes share a launch, so the chip stays loaded until the last item.
 //
 // Schedule (recorded once into a graph at creation):
 //   for each group of jobs whose partial sums fit the budget:
 //     reset the queue counters (a kernel, not a memset node)
-//     persistent projection kernel per producer kind present in the group
+//     one projection launch per producer kind present in the group (factored:
+//     and per tile length)
 //     batched FP64 reduction of the group's partial sums (source factors applied)
 //   combines of (spectator job, insertion job) pairs
 #include <string.h>
@@ -362,7 +364,8 @@ int c3pt_batch_create(const c3pt_job* jobs, int n_jobs, const c3pt_combine_job* 
             void* dev;
             if (int rc = dmalloc(b, &dev, items.size() * sizeof(int4))) return bail(rc);
             if (int rc = upload_sync(dev, items.data(), items.size() * sizeof(int4), st)) return bail(rc);
-            // persistent grid: as many workgroups as fit on the chip at once
+            // dense persistent grid: as many workgroups as fit on the chip at once
+            // (the factored launch takes one workgroup per item)
             const int variant = fac ? (t32 ? kBatchFacKT32 : 0) : api_variant(kind, mode, mt);
             hipError_t e = hipSuccess;
             int per_cu;

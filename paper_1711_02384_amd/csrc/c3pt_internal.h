@@ -127,7 +127,9 @@ struct BatchJob {
     double2* out;      // output in the layout of the single call
 };
 
-// A persistent projection launch over the items of several jobs of one kind.
+// A projection launch over the items of several jobs of one kind (factored:
+// one workgroup per item; dense: persistent workgroups taking items from the
+// queue whose head is `counter`).
 struct BatchGrid {
     const BatchJob* jobs;
     const int4* items;     // (job, column block, chunk, 0) in issue order
@@ -224,7 +226,7 @@ int batch_fac_insertion(int variant, int ops, const BatchGrid* bg, hipStream_t s
 // Factor plan of a momentum list for extents L and sign sigma (FP32 limits);
 // false if the list needs more distinct k1 / (k1, k2) than the kernel holds.
 bool api_factor_plan(const int L[3], int sigma, const int* k, int n_mom, FactorPlan* plan);
-// Persistent batch launch of one producer kind; with bg == nullptr only the
+// Dense persistent batch launch of one producer kind; with bg == nullptr only the
 // occupancy (workgroups per CU) of the variant is returned.
 int batch_meson(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);
 int batch_baryon(int mode, int mt, int variant, const BatchGrid* bg, int n_wg, hipStream_t st, hipError_t* err);

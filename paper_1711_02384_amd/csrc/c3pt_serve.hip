@@ -7,16 +7,19 @@
 // here many of them share one GPU.
 //
 //  * Admission by memory: each request's outputs (and its small parameter
-//    tables) are sub-allocated first-fit from an arena of caller-provided
-//    device memory; requests are admitted in arrival order while a slot
-//    (max_active) and arena space are free.
+//    tables, factor plans, dense phase tables) are sub-allocated first-fit
+//    from an arena of caller-provided device memory; requests are admitted
+//    while a slot (max_active) and arena space are free, the one with the
+//    least work first (with a bound on how often the first in line is passed).
 //  * Packets: an admitted request is cut into packets -- a block of noise
 //    vectors of a spectator, a block of timeslices (or of timeslices x noise
 //    vectors) of an insertion -- whose FP32 partial sums fit a fixed share of
 //    the step workspace.
-//  * Steps: every step takes packets round-robin from all active requests
-//    until the workspace is full, runs them through the persistent queue
-//    kernels (one launch per producer kind and momentum-tile class), reduces
+//  * Steps: every step takes packets from the active requests with the least
+//    remaining work first (one left out for four steps goes first), each as
+//    many as fit, until the workspace (or the
+//    step work cap) is full, runs them through one launch per producer kind
+//    (dense: and momentum-tile class; factored: and tile length), reduces
 //    the partial sums in FP64 into the requests' outputs, and enqueues the
 //    combines of every request whose last packet ran in the step, followed by
 //    an event that marks the request complete.  Requests arriving while

@@ -315,7 +315,8 @@ def test_gamma_and_smear_reject_bad_arguments():
 
 def test_bench_host_logic():
     """bench.py's host-side helpers: the traffic hash covers the factored
-    kernels' planning functions, the recorded traffic matches the sources, the
+    kernels' planning functions and ignores comments, the recorded traffic
+    matches the sources, the
     two-sink pair list has the 185 pairs of 93 momenta."""
     import sys
     sys.path.insert(0, ROOT)
@@ -330,6 +331,16 @@ def test_bench_host_logic():
         assert nbytes > 0 and len(hsh) == 16
         assert (bench.measured_traffic(*key) == nbytes) == (hsh == h)
     assert len(bench.pairs_diag_or_zero(93)) == 185
+    # comments do not enter the hash; code does
+    csrc = os.path.join(ROOT, "paper_1711_02384_amd", "csrc")
+
+    def read_edited(edit):
+        def read(name):
+            txt = open(os.path.join(csrc, name)).read()
+            return edit(txt) if name == "c3pt_fs.h" else txt
+        return read
+    assert bench.sources_hash(read_edited(lambda t: "// note\n/* block\n comment */\n" + t)) == h
+    assert bench.sources_hash(read_edited(lambda t: t + "\nstatic int c3pt_extra_;\n")) != h
     r = bench.roofline_entry("fac_insertion", 1.0e12, 50.0, "fac", traffic=None)
     assert r["bound"] == "alu" and abs(r["achieved"] - 20.0) < 1e-9 and abs(r["frac"] - 20.0 / 78.6) < 1e-4
 
