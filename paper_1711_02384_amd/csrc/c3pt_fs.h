@@ -290,8 +290,8 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         }
         fs_unroll<S::KU>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            const int e = tid + k * NT;
-            if (e >= S::NU) return;
+            // threads past the last entry repeat it (same load, same value stored)
+            const int e = min(tid + k * NT, S::NU - 1);
             const int bj = e / (12 * KT), rem = e % (12 * KT);
             const int A = rem / KT, xl = rem % KT;
             const int x1 = min(q.seg * KT + xl, L1 - 1);
@@ -367,8 +367,8 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         }
         fs_unroll<S::KU>([&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
-            const int e = tid + k * NT;
-            if (e >= S::NU) return;
+            // threads past the last entry repeat it (same load, same value stored)
+            const int e = min(tid + k * NT, S::NU - 1);
             const int bj = e / (12 * KT), rem = e % (12 * KT);
             const int A = rem / KT, xl = rem % KT;
             const int atk = A / 3;
@@ -408,8 +408,11 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     }
     if (n_tiles <= 0) return;   // uniform: no barrier follows
 
+    // pa: the tile computed, pb: the next (staged during it), pc: the one after
+    // (loaded during it); past the end pb and pc repeat the last tile
     TilePos pa = {0, 0, p0, 0};
     TilePos pb = n_tiles > 1 ? advance(pa) : pa;
+    TilePos pc = n_tiles > 2 ? advance(pb) : pb;
     load_tile(pa);
     __syncthreads();            // W1 and the plan are in LDS
     store_tile(pa, 0);
@@ -426,8 +429,8 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         // ---- stage 1: A = w1 u (split), B from LDS, three products ----
         // row (a, part) of the real form: part 0 takes (Re z, -Im z), part 1
         // (Im z, Re z) of z = w u; as linear maps of (u.x, u.y):
-        //   v0 = c0 u.x + c1 u.y,  v1 = c2 u.x + c3 u.y
-        float cf[S::HS][4][4];
+        //   v0 = c0 u.x + c1 u.y,  v1 = c1 u.x - c0 u.y
+        float cf[S::HS][4][2];
 #pragma unroll
         for (int h = 0; h < S::HS; ++h)
 #pragma unroll
@@ -435,50 +438,95 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
                 const C2<float> wv = W1[(seg * kFacMaxK1 + a_row) * S::W1S + 16 * h + 4 * g + j];
                 cf[h][j][0] = part ? wv.y : wv.x;
                 cf[h][j][1] = part ? wv.x : -wv.y;
-                cf[h][j][2] = part ? wv.x : -wv.y;
-                cf[h][j][3] = part ? -wv.y : -wv.x;
             }
+        // Steps st = (cs, h) in order, each nine MFMAs (three column tiles ct x
+        // three products).  The A operands of step st + 1 are formed (VALU)
+        // while the MFMAs of step st issue, and the B operands of each column
+        // tile are read from LDS one tile ahead.
+        auto form_a = [&](int st, vec_t& ahi, vec_t& alo) __attribute__((always_inline)) {
+            const int cs = st / S::HS, h = st % S::HS;
+            u32x4 ah, al;
 #pragma unroll
-        for (int cs = 0; cs < 3; ++cs) {
-#pragma unroll
-            for (int h = 0; h < S::HS; ++h) {
-                u32x4 ah, al;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const C2<float> uv = sm.U[par][cbj][3 * at + cs][16 * h + 4 * g + j];
-                    const f32x2 v = {cf[h][j][0] * uv.x + cf[h][j][1] * uv.y, cf[h][j][2] * uv.x + cf[h][j][3] * uv.y};
-                    unsigned hh, ll;
-                    fs_split2<T16>(v, hh, ll);
-                    ah[j] = hh;
-                    al[j] = ll;
-                }
-                const vec_t ahi = __builtin_bit_cast(vec_t, ah);
-                const vec_t alo = __builtin_bit_cast(vec_t, al);
-#pragma unroll
-                for (int ct = 0; ct < 3; ++ct) {
-                    const unsigned char* bp = sm.B[par] + (48 * cs + 16 * ct + cl) * S::PSTR + (4 * h + g) * 32;
-                    const vec_t bhi = *(const vec_t*)bp;
-                    const vec_t blo = *(const vec_t*)(bp + 16);
-                    acc[ct] = MF::mac(alo, bhi, acc[ct]);
-                    acc[ct] = MF::mac(ahi, blo, acc[ct]);
-                    acc[ct] = MF::mac(ahi, bhi, acc[ct]);
-                }
+            for (int j = 0; j < 4; ++j) {
+                const C2<float> uv = sm.U[par][cbj][3 * at + cs][16 * h + 4 * g + j];
+                const f32x2 v = {cf[h][j][0] * uv.x + cf[h][j][1] * uv.y, cf[h][j][1] * uv.x - cf[h][j][0] * uv.y};
+                unsigned hh, ll;
+                fs_split2<T16>(v, hh, ll);
+                ah[j] = hh;
+                al[j] = ll;
             }
+            ahi = __builtin_bit_cast(vec_t, ah);
+            alo = __builtin_bit_cast(vec_t, al);
+        };
+        auto read_b = [&](int sub, vec_t& bhi, vec_t& blo) __attribute__((always_inline)) {
+            const int st = sub / 3, ct = sub % 3;
+            const int cs = st / S::HS, h = st % S::HS;
+            const unsigned char* bp = sm.B[par] + (48 * cs + 16 * ct + cl) * S::PSTR + (4 * h + g) * 32;
+            bhi = *(const vec_t*)bp;
+            blo = *(const vec_t*)(bp + 16);
+        };
+        constexpr int NST = 3 * S::HS;
+        // The insertion on 32-site tiles has no registers to spare for the
+        // overlap: it forms and reads each step's operands in place and stages
+        // the next tiles after the MFMAs.
+        constexpr bool kPipe = !(KIND == 2 && KT == 32);
+        vec_t a_hi[2], a_lo[2], b_hi[2], b_lo[2];
+        if constexpr (kPipe) {
+            read_b(0, b_hi[0], b_lo[0]);
+            form_a(0, a_hi[0], a_lo[0]);
         }
+        fs_unroll<3 * NST>([&](auto subc) __attribute__((always_inline)) {
+            constexpr int sub = decltype(subc)::value;
+            constexpr int st = sub / 3, ct = sub % 3;
+            constexpr int ca = kPipe ? st & 1 : 0, cb2 = kPipe ? sub & 1 : 0;
+            if constexpr (!kPipe) {
+                if constexpr (ct == 0) form_a(st, a_hi[0], a_lo[0]);
+                read_b(sub, b_hi[0], b_lo[0]);
+            } else {
+                if constexpr (sub + 1 < 3 * NST) read_b(sub + 1, b_hi[cb2 ^ 1], b_lo[cb2 ^ 1]);
+                if constexpr (ct == 0 && st + 1 < NST) form_a(st + 1, a_hi[ca ^ 1], a_lo[ca ^ 1]);
+                if constexpr (ct == 0 && st + 1 == NST) {
+                    // the last step's MFMAs run beside the staging of the next
+                    // tile (into the other buffer, last read before the previous
+                    // barrier) and the loads of the one after; past the end both
+                    // repeat the last tile, which nothing reads again
+                    store_tile(pb, par ^ 1);
+                    load_tile(pc);
+                }
+            }
+            acc[ct] = MF::mac(a_lo[ca], b_hi[cb2], acc[ct]);
+            acc[ct] = MF::mac(a_hi[ca], b_lo[cb2], acc[ct]);
+            acc[ct] = MF::mac(a_hi[ca], b_hi[cb2], acc[ct]);
+            if constexpr (kPipe && ct == 2) {
+                // interleave the step's MFMAs with the next step's A formation,
+                // or with the staging after the last step
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, st);   // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, 4, st);   // four VALU
+                }
+            }
+        });
         if (row_end) {
             // ---- stage 2: over x2, in registers -------------------------
+            // coefficients of the lane's pairs, read together (the table is
+            // zero-padded by kFacMaxBPerA entries)
             const C2<float>* cf = sm.coef2[row & 1];
+            C2<float> cw[2][kFacMaxBPerA];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < kFacMaxBPerA; ++i) cw[h][i] = cf[bs[h] + i];
 #pragma unroll
             for (int i = 0; i < kFacMaxBPerA; ++i) {
                 if (i >= nbmax) break;   // uniform
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const C2<float> cw = cf[bs[h] + i];
 #pragma unroll
                     for (int ct = 0; ct < 3; ++ct) {
                         const C2<float> v =
                             h == 0 ? C2<float>{acc[ct][0], acc[ct][1]} : C2<float>{acc[ct][2], acc[ct][3]};
-                        r2[ct][h][i] = cfma(r2[ct][h][i], cw, v);
+                        r2[ct][h][i] = cfma(r2[ct][h][i], cw[h][i], v);
                     }
                 }
             }
@@ -518,18 +566,16 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
                 }
             }
         }
-        // ---- next tile into the other buffer, the one after into registers
-        if (T + 1 < n_tiles) {
+        if constexpr (!kPipe) {
             store_tile(pb, par ^ 1);
-            if (pb.seg == 0) fill_coef2(pb.row & 1, pb.x2);
-        }
-        if (T + 2 < n_tiles) {
-            const TilePos pc = advance(pb);
             load_tile(pc);
         }
+        // ---- the next tile's stage-2 coefficients (the other row parity)
+        if (T + 1 < n_tiles && pb.seg == 0) fill_coef2(pb.row & 1, pb.x2);
         __syncthreads();
         pa = pb;
-        if (T + 2 < n_tiles) pb = advance(pb);
+        pb = pc;
+        if (T + 3 < n_tiles) pc = advance(pc);
     }
 }
 
