@@ -272,9 +272,10 @@ int variant_count(int kind, int mode, int cls) {
     if (mode == kModeFacVariants) return 2;
     // fused: 0 = propagator tiles split in the kernel, two column blocks per workgroup;
     // 1 = slices split by a pass first, two blocks; 2 = split pass, one block per
-    // workgroup; 3 = split in the kernel, one block per workgroup.  The
+    // workgroup; 3 = split in the kernel, one block per workgroup; 4 = split in
+    // the kernel, three blocks per workgroup where it applies (else as 0).  The
     // nucleon's diquark always has its pass.
-    if (mode == kModeFsVariants) return 4;
+    if (mode == kModeFsVariants) return 5;
     // factored kernels of batches and serving: bit 0 32-site tiles where they
     // apply, bit 1 chunks of about 4096 instead of 2048 sites
     if (mode == kModeBatchFacVariants) return kBatchFacVariants;
@@ -367,7 +368,8 @@ int phase_table(const c3pt_geom* g, int sigma, int mode, int mtmax, const int* k
 // values, distinct (k1, k2) pairs grouped by k1, and each momentum's pair and
 // k3, all reduced mod L.  False when the group needs more k1 values or pairs
 // than the kernel holds; the group then runs on the dense kernel.
-bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGroup& mg, bool f64, FactorPlan* p) {
+bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGroup& mg, bool f64, FactorPlan* p,
+                       int max_per_slot = kFacMaxBPerA) {
     memset(p, 0, sizeof(*p));
     for (int j = 0; j < 3; ++j) p->L[j] = g->L[j];
     p->sigma = sigma;
@@ -391,12 +393,12 @@ bool build_factor_plan(const c3pt_geom* g, int sigma, const int* k, const MomGro
         jm[m] = jj;
         p->k3[m] = posmod(km[2], g->L[2]);
     }
-    // slots: a k1 with n pairs takes ceil(n / kFacMaxBPerA) slots of nearly equal size
+    // slots: a k1 with n pairs takes ceil(n / max_per_slot) slots of nearly equal size
     std::vector<int> first_slot(k1s.size()), parts(k1s.size());
     int n_slots = 0, nb = 0;
     for (size_t a = 0; a < k1s.size(); ++a) {
         const int n = (int)k2s[a].size();
-        parts[a] = (n + kFacMaxBPerA - 1) / kFacMaxBPerA;
+        parts[a] = (n + max_per_slot - 1) / max_per_slot;
         first_slot[a] = n_slots;
         n_slots += parts[a];
         nb += n;
@@ -650,14 +652,36 @@ bool is_fused(const c3pt_geom* g) {
     return g->proj == C3PT_PROJ_FACTORED_F16 || g->proj == C3PT_PROJ_FACTORED_BF16;
 }
 
-// Factor plans of every momentum group (FP32 limits); false if one does not factor.
-bool fs_plans(const c3pt_geom* g, int sigma, const int* k, int n_mom, std::vector<MomGroup>* groups,
-              std::vector<FactorPlan>* plans) {
-    *groups = momentum_groups(n_mom, false);
-    plans->resize(groups->size());
-    for (size_t i = 0; i < groups->size(); ++i)
-        if (!build_factor_plan(g, sigma, k, (*groups)[i], false, &(*plans)[i])) return false;
+// Factor plans of every momentum group (FP32 limits, at most max_per_slot
+// pairs per k1 slot); false if one does not factor.
+bool fs_plans(const c3pt_geom* g, int sigma, const int* k, const std::vector<MomGroup>& groups,
+              std::vector<FactorPlan>* plans, int max_per_slot) {
+    plans->resize(groups.size());
+    for (size_t i = 0; i < groups.size(); ++i)
+        if (!build_factor_plan(g, sigma, k, groups[i], false, &(*plans)[i], max_per_slot)) return false;
     return true;
+}
+
+// Fused launch shape of a call: the tuned variant of (producer kind, momentum
+// class) sets whether B is split by a pass and how many column blocks share a
+// workgroup (variant 4: three, for 16-site tiles of the spectators and the
+// local insertion when every momentum group factors with at most
+// kFsPairsCB3 pairs per k1 slot; otherwise two), then the factor plans.
+int fs_setup(const c3pt_geom* g, int sigma, const int* k, int n_mom, int vkind, bool derivative,
+             std::vector<MomGroup>* groups, std::vector<FactorPlan>* plans, bool* bsplit, int* cbw) {
+    *groups = momentum_groups(n_mom, false);
+    int v;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        v = g_variant[vkind][kModeFsVariants][mt_class(((*groups)[0].n + 7) / 8)];
+    }
+    *bsplit = vkind == 1 || v == 1 || v == 2;
+    *cbw = v == 4 ? 3 : (v >= 2 ? 1 : 2);
+    if (*cbw == 3 && (fs_kt(g->L) != 16 || derivative)) *cbw = 2;
+    if (*cbw == 3 && !fs_plans(g, sigma, k, *groups, plans, kFsPairsCB3)) *cbw = 2;
+    if (*cbw != 3 && !fs_plans(g, sigma, k, *groups, plans, kFacMaxBPerA))
+        return fail(C3PT_EUNSUPPORTED, "the momentum list does not factor (too many distinct k1 or (k1, k2))");
+    return C3PT_OK;
 }
 
 // Partial sums then split B blocks in this stream's scratch.
@@ -675,8 +699,9 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
                  const int* k, int n_mom, void* out) {
     std::vector<MomGroup> groups;
     std::vector<FactorPlan> plans;
-    if (!fs_plans(geom, -1, k, n_mom, &groups, &plans))
-        return fail(C3PT_EUNSUPPORTED, "the momentum list does not factor (too many distinct k1 or (k1, k2))");
+    bool bsplit;
+    int cbw;
+    if (int rc = fs_setup(geom, -1, k, n_mom, baryon ? 1 : 0, false, &groups, &plans, &bsplit, &cbw)) return rc;
     hipStream_t st = (hipStream_t)geom->stream;
     const bool bf16 = geom->proj == C3PT_PROJ_FACTORED_BF16;
     const int KT = fs_kt(geom->L), Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
@@ -684,13 +709,6 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
     const size_t bb = fs_block_bytes(geom->L);
     const int n_slots = baryon ? 16 : 1;
     const int ncb = N * n_slots;
-    int fs_variant;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        fs_variant = g_variant[baryon ? 1 : 0][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
-    }
-    const bool bsplit = baryon || fs_variant == 1 || fs_variant == 2;
-    const int cbw = fs_variant >= 2 ? 1 : 2;
     const int n_per_share = n_slots * ((N + cbw - 1) / cbw);
     int cp, nch;
     plan_planes(geom->L, n_per_share, &cp, &nch);
@@ -784,8 +802,9 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
                  int n_tau, const void* const* U_t, int n_ops, const int* k, int n_mom, void* out) {
     std::vector<MomGroup> groups;
     std::vector<FactorPlan> plans;
-    if (!fs_plans(geom, +1, k, n_mom, &groups, &plans))
-        return fail(C3PT_EUNSUPPORTED, "the momentum list does not factor (too many distinct k1 or (k1, k2))");
+    bool bsplit;
+    int cbw;
+    if (int rc = fs_setup(geom, +1, k, n_mom, 2, n_ops == 5, &groups, &plans, &bsplit, &cbw)) return rc;
     hipStream_t st = (hipStream_t)geom->stream;
     const bool bf16 = geom->proj == C3PT_PROJ_FACTORED_BF16;
     const int KT = fs_kt(geom->L), Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
@@ -794,13 +813,6 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
     const int kind = n_ops == 5 ? 2 : 1;
     const int n_slots = n_ops == 5 ? 9 : 1;
     const size_t bb = fs_block_bytes(geom->L);
-    int fs_variant;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        fs_variant = g_variant[2][kModeFsVariants][mt_class((groups[0].n + 7) / 8)];
-    }
-    const bool bsplit = fs_variant == 1 || fs_variant == 2;
-    const int cbw = fs_variant >= 2 ? 1 : 2;
     for (int j0 = 0; j0 < n_tau; j0 += kMaxTauPerLaunch) {
         const int nt = std::min(kMaxTauPerLaunch, n_tau - j0);
         FsArgs fa;

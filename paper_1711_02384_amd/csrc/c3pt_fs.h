@@ -397,14 +397,17 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     };
 
     f32x4 acc[3];
-    C2<float> r2[3][2][kFacMaxBPerA];
+    // pairs per k1 slot held in registers: fewer with three column blocks per
+    // workgroup (the host plans those launches with at most kFsPairsCB3)
+    constexpr int NBP = CB == 3 ? kFsPairsCB3 : kFacMaxBPerA;
+    C2<float> r2[3][2][NBP];
 #pragma unroll
     for (int ct = 0; ct < 3; ++ct) {
         acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int i = 0; i < kFacMaxBPerA; ++i) r2[ct][h][i] = C2<float>{0.f, 0.f};
+            for (int i = 0; i < NBP; ++i) r2[ct][h][i] = C2<float>{0.f, 0.f};
     }
     if (n_tiles <= 0) return;   // uniform: no barrier follows
 
@@ -512,13 +515,13 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
             // coefficients of the lane's pairs, read together (the table is
             // zero-padded by kFacMaxBPerA entries)
             const C2<float>* cf = sm.coef2[row & 1];
-            C2<float> cw[2][kFacMaxBPerA];
+            C2<float> cw[2][NBP];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int i = 0; i < kFacMaxBPerA; ++i) cw[h][i] = cf[bs[h] + i];
+                for (int i = 0; i < NBP; ++i) cw[h][i] = cf[bs[h] + i];
 #pragma unroll
-            for (int i = 0; i < kFacMaxBPerA; ++i) {
+            for (int i = 0; i < NBP; ++i) {
                 if (i >= nbmax) break;   // uniform
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -542,7 +545,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                        for (int i = 0; i < kFacMaxBPerA; ++i) {
+                        for (int i = 0; i < NBP; ++i) {
                             if (i < nb[h]) {
                                 const int b = bs[h] + i;
                                 for (int jm = sm.plan.mstart[b]; jm < sm.plan.mstart[b + 1]; ++jm) {

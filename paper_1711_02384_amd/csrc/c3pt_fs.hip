@@ -227,6 +227,24 @@ static hipError_t launch_fs_cb(int kind, bool bsplit, const ProjGrid& pg, const 
 
 template <typename T16, int KT>
 static hipError_t launch_fs_t(int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+    if (cb == 3) {
+        // three column blocks per workgroup: 16-site tiles, spectators and the
+        // local insertion only (the host plans no other)
+        if constexpr (KT == 16) {
+            const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(768);
+            const size_t dyn = fs_dyn_bytes(a.L);
+            if (kind == 0 && bsplit)
+                hipLaunchKernelGGL((fs_kernel<T16, 16, 0, true, 3>), grid, block, dyn, st, pg, a);
+            else if (kind == 0)
+                hipLaunchKernelGGL((fs_kernel<T16, 16, 0, false, 3>), grid, block, dyn, st, pg, a);
+            else if (kind == 1 && !bsplit)
+                hipLaunchKernelGGL((fs_kernel<T16, 16, 1, false, 3>), grid, block, dyn, st, pg, a);
+            else
+                return hipErrorInvalidValue;
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     return cb == 1 ? launch_fs_cb<T16, KT, 1>(kind, bsplit, pg, a, st) : launch_fs_cb<T16, KT, 2>(kind, bsplit, pg, a, st);
 }
 

@@ -6,6 +6,7 @@
 namespace c3pt {
 
 constexpr int kFsPlanes = 144;   // 3 summed colours x 48 B columns
+constexpr int kFsPairsCB3 = 5;   // (k1, k2) pairs per k1 slot with three column blocks per workgroup
 
 // Kernel arguments besides the grid.
 //   kind 0: spectator (u = g eta), 1: insertion, local operator only,

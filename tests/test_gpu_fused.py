@@ -50,11 +50,14 @@ def _set_fused_variant(c3pt, v):
             c3pt.set_variant(kind, c3pt.MODE["fs16"], cls, v)
 
 
-@pytest.mark.parametrize("prec,variant", [("f16", 0), ("f16", 1), ("f16", 2), ("f16", 3), ("bf16", 0), ("bf16", 3)])
+@pytest.mark.parametrize("prec,variant", [("f16", 0), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4), ("bf16", 0),
+                                          ("bf16", 3), ("bf16", 4)])
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_fused_parts(case, prec, variant):
     """variant 0 splits the propagator tiles in the kernel, 1 in a pass first, 2 with one
-    column block per workgroup, 3 in the kernel with one column block per workgroup."""
+    column block per workgroup, 3 in the kernel with one column block per workgroup, 4 in
+    the kernel with three column blocks per workgroup (16-site tiles; an odd noise count
+    leaves blocks of the last group empty; 32-site tiles and the derivative slots run as 0)."""
     import paper_1711_02384_amd as c3pt
     L, T, taus, N, n2, r = CASES[case]
     k = c3pt.momentum_list(n2)
