@@ -43,14 +43,20 @@ int ok() {
 // Per-(device, stream) scratch: device memory for split-site partial sums and
 // small parameter tables, plus a pinned staging buffer for host->device
 // parameter uploads guarded by an event.
+// Pinned staging slots for parameter uploads, used in turn: an upload waits
+// only for the copy made kUploadSlots uploads earlier from the same slot, so
+// the host stays ahead of the stream instead of waiting for the kernels queued
+// before the previous upload.
+constexpr int kUploadSlots = 8;
 struct Scratch {
     void* dev = nullptr;
     size_t dev_bytes = 0;
     void* aux = nullptr;       // second region: fields derived inside a call (stencil outputs)
     size_t aux_bytes = 0;
-    void* pinned = nullptr;
-    size_t pinned_bytes = 0;
-    hipEvent_t ev = nullptr;
+    void* pinned[kUploadSlots] = {};
+    size_t pinned_bytes[kUploadSlots] = {};
+    hipEvent_t ev[kUploadSlots] = {};
+    int next_slot = 0;
 };
 
 std::mutex g_mu;
@@ -114,35 +120,39 @@ int scratch_aux(hipStream_t st, size_t bytes, void** out) {
     return C3PT_OK;
 }
 
-// Copy `bytes` of host data into device scratch at byte offset `off` through the
-// pinned staging buffer; the event orders reuse of the staging buffer.
+// Copy `bytes` of host data into device scratch at byte offset `off` through
+// the next pinned staging slot; the slot's event orders its reuse.  The device
+// region is ordered by the stream (kernels of earlier calls that read it run
+// before the copy).
 int upload(hipStream_t st, void* dev_base, size_t off, const void* host, size_t bytes) {
     int dev;
     if (int rc = current_device(&dev)) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Scratch& s = g_scratch[{dev, st}];
-    if (!s.ev) {
-        if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess)
+    const int k = s.next_slot;
+    s.next_slot = (k + 1) % kUploadSlots;
+    if (!s.ev[k]) {
+        if (hipEventCreateWithFlags(&s.ev[k], hipEventDisableTiming) != hipSuccess)
             return fail(C3PT_EDEVICE, "event creation failed");
-    } else if (hipEventSynchronize(s.ev) != hipSuccess) {
+    } else if (hipEventSynchronize(s.ev[k]) != hipSuccess) {
         return fail(C3PT_EDEVICE, "event sync failed");
     }
-    if (s.pinned_bytes < bytes) {
-        if (s.pinned) hipHostFree(s.pinned);
-        s.pinned = nullptr;
-        s.pinned_bytes = 0;
+    if (s.pinned_bytes[k] < bytes) {
+        if (s.pinned[k]) hipHostFree(s.pinned[k]);
+        s.pinned[k] = nullptr;
+        s.pinned_bytes[k] = 0;
         size_t want = std::max(bytes, (size_t)65536);
-        if (hipHostMalloc(&s.pinned, want, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc(&s.pinned[k], want, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
-            s.pinned = nullptr;
+            s.pinned[k] = nullptr;
             return fail(C3PT_ENOMEM, "pinned staging allocation failed");
         }
-        s.pinned_bytes = want;
+        s.pinned_bytes[k] = want;
     }
-    memcpy(s.pinned, host, bytes);
-    if (hipMemcpyAsync((char*)dev_base + off, s.pinned, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    memcpy(s.pinned[k], host, bytes);
+    if (hipMemcpyAsync((char*)dev_base + off, s.pinned[k], bytes, hipMemcpyHostToDevice, st) != hipSuccess)
         return fail(C3PT_EDEVICE, "parameter upload failed");
-    if (hipEventRecord(s.ev, st) != hipSuccess) return fail(C3PT_EDEVICE, "event record failed");
+    if (hipEventRecord(s.ev[k], st) != hipSuccess) return fail(C3PT_EDEVICE, "event record failed");
     return C3PT_OK;
 }
 
@@ -1091,8 +1101,10 @@ int c3pt_release_scratch(void) {
         hipStreamSynchronize(kv.first.second);
         if (kv.second.dev) hipFree(kv.second.dev);
         if (kv.second.aux) hipFree(kv.second.aux);
-        if (kv.second.pinned) hipHostFree(kv.second.pinned);
-        if (kv.second.ev) hipEventDestroy(kv.second.ev);
+        for (int k = 0; k < kUploadSlots; ++k) {
+            if (kv.second.pinned[k]) hipHostFree(kv.second.pinned[k]);
+            if (kv.second.ev[k]) hipEventDestroy(kv.second.ev[k]);
+        }
     }
     g_scratch.clear();
     hipSetDevice(cur);

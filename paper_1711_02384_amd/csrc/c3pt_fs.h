@@ -267,7 +267,9 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     C2<float> sreg[S::KU][KIND == 2 ? 3 : 1];
     C2<float> lreg[S::KU][KIND == 2 ? 3 : 1];
     auto load_tile = [&](const TilePos& q) __attribute__((always_inline)) {
-        const size_t rowoff = (size_t)(q.x2 + L2 * q.x3) * (size_t)(fa.Lp / 4) + (size_t)q.seg * S::GB;
+        // split blocks are [row][plane][Lp / 4] groups: the tile's 144 plane
+        // segments lie within one row's span
+        const size_t rowoff = (size_t)(q.x2 + L2 * q.x3) * kFsPlanes * (size_t)(fa.Lp / 4) + (size_t)q.seg * S::GB;
         if constexpr (BSPLIT) {
             fs_unroll<S::KB>([&](auto kc) __attribute__((always_inline)) {
                 constexpr int k = decltype(kc)::value;
@@ -276,7 +278,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
                 const int e0 = tid + k * NT;
                 const int e = e0 < S::NB16 ? e0 : e0 - S::NB16;
                 const int p = e / (2 * S::GB), r = e % (2 * S::GB);
-                breg[k] = *(const u32x4*)(Bg + (((size_t)p * fa.rows) * (size_t)(fa.Lp / 4) + rowoff) * 32 + r * 16);
+                breg[k] = *(const u32x4*)(Bg + ((size_t)p * (size_t)(fa.Lp / 4) + rowoff) * 32 + r * 16);
             });
         } else {
             const unsigned rowL1 = (unsigned)(L1 * (q.x2 + L2 * q.x3));

@@ -10,8 +10,9 @@ namespace c3pt {
 // ---------------------------------------------------------------------------
 // Propagator slices -> split B blocks.  Plane p' = 48 c + X of block s holds
 // B[c][X] = G_s[(bt, c)][(b, c0)] with X = 12 bt + 3 b + c0 (times
-// g[bt] g[b] and conjugated for the meson spectator), rows of Lp sites
-// (zero beyond L1), four sites per group.  One thread per site.
+// g[bt] g[b] and conjugated for the meson spectator); a block is [row][plane]
+// segments of Lp sites (zero beyond L1), four sites per group, so the planes
+// of one row lie together.  One thread per (site, plane).
 // ---------------------------------------------------------------------------
 template <typename T16>
 __global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
@@ -23,10 +24,10 @@ __global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
          idx += (long long)gridDim.x * blockDim.x) {
         const int x1 = (int)(idx % Lp);
         long long rest = idx / Lp;
-        const int row = (int)(rest % a.rows);
-        rest /= a.rows;
         const int p = (int)(rest % kFsPlanes);
-        const int sl = (int)(rest / kFsPlanes);
+        rest /= kFsPlanes;
+        const int row = (int)(rest % a.rows);
+        const int sl = (int)(rest / a.rows);
         const int X = p % 48, cs = p / 48;
         const int bt = X / 12, rem = X % 12;
         const float2 v = a.G[sl][(unsigned)((3 * bt + cs) * 12 + rem) * V3 + (unsigned)(min(x1, L1 - 1) + L1 * row)];
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
         const float sy = a.conj_sign ? -sg : sg;
         unsigned hw, lw;
         fs_split2<T16>(x1 < L1 ? f32x2{sg * v.x, sy * v.y} : f32x2{0.f, 0.f}, hw, lw);
-        unsigned* dst = (unsigned*)a.out + (((size_t)sl * kFsPlanes + p) * a.rows + row) * (size_t)(Lp / 4) * 8 +
+        unsigned* dst = (unsigned*)a.out + (((size_t)sl * a.rows + row) * kFsPlanes + p) * (size_t)(Lp / 4) * 8 +
                         (size_t)(x1 >> 2) * 8 + (x1 & 3);
         dst[0] = hw;
         dst[4] = lw;
@@ -42,8 +43,8 @@ __global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Nucleon diquark -> split B blocks.  Block (a1', a1), plane p' = 48 c + 3 q + c'
-// with q = 4 a2' + a2:
+// Nucleon diquark -> split B blocks ([row][plane] segments, as above).  Block
+// (a1', a1), plane p' = 48 c + 3 q + c' with q = 4 a2' + a2:
 //   Q[q][c][c'] = sum eps_{abc} eps_{a'b'c'} G1[(a1',a)][(a1,a')] G2[(a2',b)][(a2,b')]
 // A workgroup takes 256 consecutive sites of the padded rows and one block;
 // each thread reads its site's G1 entries of the block once and loops over
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
                 t = cfma(t, g1[c2][d2], g2[c1][d1]);
                 unsigned hw, lw;
                 fs_split2<T16>(ok ? f32x2{t.x, t.y} : f32x2{0.f, 0.f}, hw, lw);
-                unsigned* dst = out + ((size_t)(48 * c + 3 * q + cp) * a.rows + row) * (size_t)(Lp / 4) * 8 + gw;
+                unsigned* dst = out + ((size_t)row * kFsPlanes + 48 * c + 3 * q + cp) * (size_t)(Lp / 4) * 8 + gw;
                 dst[0] = hw;
                 dst[4] = lw;
             }

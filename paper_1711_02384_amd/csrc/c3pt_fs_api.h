@@ -37,7 +37,7 @@ struct FsSplitArgs {
     int n_slices;
     int conj_sign;         // meson spectator: conj(G) g[a'] g[a]
     const float2* G[kMaxTauPerLaunch + 2];
-    void* out;             // [n_slices][144][rows][Lp/4] groups of four sites
+    void* out;             // [n_slices][rows][144][Lp/4] groups of four sites
 };
 
 // Nucleon diquark of (G1, G2) -> 16 split B blocks (fs_diquark_kernel).
@@ -46,7 +46,7 @@ struct FsDiquarkArgs {
     int Lp, rows;
     const float2* G1;
     const float2* G2;
-    void* out;             // [16][144][rows][Lp/4]
+    void* out;             // [16][rows][144][Lp/4]
 };
 
 // FP64 reduction of an insertion launch with the nine derivative slots.
