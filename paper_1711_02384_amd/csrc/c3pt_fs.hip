@@ -46,30 +46,37 @@ __global__ void __launch_bounds__(256) fs_split_kernel(FsSplitArgs a) {
 // Nucleon diquark -> split B blocks ([row][plane] segments, as above).  Block
 // (a1', a1), plane p' = 48 c + 3 q + c' with q = 4 a2' + a2:
 //   Q[q][c][c'] = sum eps_{abc} eps_{a'b'c'} G1[(a1',a)][(a1,a')] G2[(a2',b)][(a2,b')]
-// A workgroup takes 256 consecutive sites of the padded rows and one block;
+// A workgroup takes R = max(1, 256 / Lp) whole padded rows and one block;
 // each thread reads its site's G1 entries of the block once and loops over
-// the 16 q, reading G2's (a2', a2) entries.  Items are (site tile, block),
-// block fastest, and consecutive items run on one XCD, so the 16 blocks of a
-// tile read G2 from that XCD's L2 and each propagator entry comes from HBM
-// once.  Lanes are consecutive sites: every read and every hi / lo word
-// written is coalesced.
+// the 16 q, reading G2's (a2', a2) entries.  The nine planes of one q are
+// three runs of three consecutive planes, so per q and row the block holds
+// three contiguous runs of 3 Lp sites: the split words go through LDS (double
+// buffered, one barrier per q) and leave as 16-byte stores that fill whole
+// lines.  Items are (row tile, block), block fastest, and consecutive items
+// run on one XCD, so the 16 blocks of a tile read G2 from that XCD's L2 and
+// each propagator entry comes from HBM once.
 // ---------------------------------------------------------------------------
 template <typename T16>
 __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
     const int Lp = a.Lp;
     const int L1 = a.L[0];
     const unsigned V3 = (unsigned)(a.L[0] * a.L[1] * a.L[2]);
+    const int R = Lp <= 128 ? 256 / Lp : 1;
     const int nw = gridDim.x, w = blockIdx.x;
     const int full = (nw / 8) * 8;
     const int item = (w < full) ? (w % 8) * (nw / 8) + w / 8 : w;
     const int blk = item % 16;
-    const long long sidx = (long long)(item / 16) * 256 + threadIdx.x;
-    if (sidx >= (long long)a.rows * Lp) return;
-    const int x1 = (int)(sidx % Lp);
-    const int row = (int)(sidx / Lp);
+    const int row0 = (item / 16) * R;
+    const int nr = min(R, a.rows - row0);
+    const int tid = threadIdx.x;
+    const int rl = tid / Lp, x1 = tid % Lp;
+    const bool active = rl < nr;
+    const int row = row0 + min(rl, nr - 1);
     const int a1p = blk >> 2, a1 = blk & 3;
-    const bool ok = x1 < L1;
+    const bool ok = active && x1 < L1;
     const unsigned n = (unsigned)(min(x1, L1 - 1) + L1 * row);
+    // [buffer][R rows][9 planes][Lp / 4 groups][hi 4 | lo 4], R * Lp <= 256
+    __shared__ __attribute__((aligned(16))) unsigned stage[2][9 * 256 * 2];
     C2<float> g1[3][3];
 #pragma unroll
     for (int u = 0; u < 3; ++u)
@@ -78,9 +85,11 @@ __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
             const float2 x = a.G1[(unsigned)((3 * a1p + u) * 12 + 3 * a1 + v) * V3 + n];
             g1[u][v] = {x.x, x.y};
         }
-    unsigned* out = (unsigned*)((FsGroup*)a.out + (size_t)blk * kFsPlanes * a.rows * (Lp / 4));
-    const size_t gw = (size_t)(x1 >> 2) * 8 + (x1 & 3);   // the site's hi word in its group; lo is 4 words on
+    unsigned char* out = (unsigned char*)((FsGroup*)a.out + (size_t)blk * kFsPlanes * a.rows * (Lp / 4));
+    const int sw = (rl * 9) * (Lp / 4) * 8 + (x1 >> 2) * 8 + (x1 & 3);   // the site's hi word of plane 0
+    const int run_units = 3 * Lp / 2;                                      // 16-byte units of one run (3 planes)
     for (int q = 0; q < 16; ++q) {
+        unsigned* st = stage[q & 1];
         const int a2p = q >> 2, a2 = q & 3;
         C2<float> g2[3][3];
 #pragma unroll
@@ -102,10 +111,21 @@ __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
                 t = cfma(t, g1[c2][d2], g2[c1][d1]);
                 unsigned hw, lw;
                 fs_split2<T16>(ok ? f32x2{t.x, t.y} : f32x2{0.f, 0.f}, hw, lw);
-                unsigned* dst = out + ((size_t)row * kFsPlanes + 48 * c + 3 * q + cp) * (size_t)(Lp / 4) * 8 + gw;
-                dst[0] = hw;
-                dst[4] = lw;
+                if (active) {
+                    st[sw + (3 * c + cp) * (Lp / 4) * 8] = hw;
+                    st[sw + (3 * c + cp) * (Lp / 4) * 8 + 4] = lw;
+                }
             }
+        }
+        __syncthreads();
+        // runs (row, c): planes 48 c + 3 q .. + 2 of the row, contiguous in the block
+        for (int e = tid; e < nr * 3 * run_units; e += 256) {
+            const int r = e / (3 * run_units), rem = e % (3 * run_units);
+            const int c = rem / run_units, k = rem % run_units;
+            const uint4 v = *(const uint4*)(st + (r * 9 + 3 * c) * (Lp / 4) * 8 + 4 * k);
+            unsigned char* dst =
+                out + (((size_t)(row0 + r) * kFsPlanes + 48 * c + 3 * q) * (size_t)(Lp / 4)) * 32 + (size_t)k * 16;
+            *(uint4*)dst = v;
         }
     }
 }
@@ -191,7 +211,9 @@ hipError_t launch_fs_split(bool bf16, const FsSplitArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_fs_diquark(bool bf16, const FsDiquarkArgs& a, hipStream_t st) {
-    const long long tiles = ((long long)a.rows * a.Lp + 255) / 256;
+    const int R = a.Lp <= 128 ? 256 / a.Lp : 1;   // rows per workgroup (the kernel's rule)
+    if (a.Lp > 256 || a.Lp % 16 != 0) return hipErrorInvalidValue;
+    const long long tiles = ((long long)a.rows + R - 1) / R;
     if (tiles * 16 > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)(tiles * 16));
     if (bf16)
