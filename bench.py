@@ -125,10 +125,10 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
                      "fs_plans", "fs_scratch", "fs_spectator", "fs_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
-    # 48^3 step, split-precision fused form: one local insertion dispatch (1555510 + 803520 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): (1555510 * 2048 + 803520 * 1024, "ae1117ea05b172de"),
-    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413222 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413222 * 2048 + 857088 * 1024, "ae1117ea05b172de"),
+    # 48^3 step, split-precision fused form: one local insertion dispatch (1626158 + 803520 KiB)
+    ("nucleon48", "fs16", "fs_insertion", 1): (1626158 * 2048 + 803520 * 1024, "2c0ea9667a8dfdfc"),
+    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413669 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413669 * 2048 + 857088 * 1024, "2c0ea9667a8dfdfc"),
 }
 
 
