@@ -283,9 +283,10 @@ int variant_count(int kind, int mode, int cls) {
     // fused: 0 = propagator tiles split in the kernel, two column blocks per workgroup;
     // 1 = slices split by a pass first, two blocks; 2 = split pass, one block per
     // workgroup; 3 = split in the kernel, one block per workgroup; 4 = split in
-    // the kernel, three blocks per workgroup where it applies (else as 0).  The
-    // nucleon's diquark always has its pass.
-    if (mode == kModeFsVariants) return 5;
+    // the kernel, three blocks per workgroup where it applies (else as 0); 5 =
+    // as 0 with 48-site tiles where it applies (L1 = 48, no derivative slots;
+    // else as 0).  The nucleon's diquark always has its pass.
+    if (mode == kModeFsVariants) return 6;
     // factored kernels of batches and serving: bit 0 32-site tiles where they
     // apply, bit 1 chunks of about 4096 instead of 2048 sites
     if (mode == kModeBatchFacVariants) return kBatchFacVariants;
@@ -673,12 +674,14 @@ bool fs_plans(const c3pt_geom* g, int sigma, const int* k, const std::vector<Mom
 }
 
 // Fused launch shape of a call: the tuned variant of (producer kind, momentum
-// class) sets whether B is split by a pass and how many column blocks share a
+// class) sets whether B is split by a pass, how many column blocks share a
 // workgroup (variant 4: three, for 16-site tiles of the spectators and the
 // local insertion when every momentum group factors with at most
-// kFsPairsCB3 pairs per k1 slot; otherwise two), then the factor plans.
+// kFsPairsCB3 pairs per k1 slot; otherwise two) and the tile length
+// (variant 5: rows of 48 sites as one tile, for the spectators and the local
+// insertion when L1 = 48), then the factor plans.
 int fs_setup(const c3pt_geom* g, int sigma, const int* k, int n_mom, int vkind, bool derivative,
-             std::vector<MomGroup>* groups, std::vector<FactorPlan>* plans, bool* bsplit, int* cbw) {
+             std::vector<MomGroup>* groups, std::vector<FactorPlan>* plans, bool* bsplit, int* cbw, int* kt) {
     *groups = momentum_groups(n_mom, false);
     int v;
     {
@@ -686,7 +689,8 @@ int fs_setup(const c3pt_geom* g, int sigma, const int* k, int n_mom, int vkind, 
         v = g_variant[vkind][kModeFsVariants][mt_class(((*groups)[0].n + 7) / 8)];
     }
     *bsplit = vkind == 1 || v == 1 || v == 2;
-    *cbw = v == 4 ? 3 : (v >= 2 ? 1 : 2);
+    *cbw = v == 4 ? 3 : (v == 2 || v == 3 ? 1 : 2);
+    *kt = (v == 5 && !derivative && g->L[0] == 48 && (vkind == 1 || !*bsplit)) ? 48 : fs_kt(g->L);
     if (*cbw == 3 && (fs_kt(g->L) != 16 || derivative)) *cbw = 2;
     if (*cbw == 3 && !fs_plans(g, sigma, k, *groups, plans, kFsPairsCB3)) *cbw = 2;
     if (*cbw != 3 && !fs_plans(g, sigma, k, *groups, plans, kFacMaxBPerA))
@@ -711,10 +715,11 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
     std::vector<FactorPlan> plans;
     bool bsplit;
     int cbw;
-    if (int rc = fs_setup(geom, -1, k, n_mom, baryon ? 1 : 0, false, &groups, &plans, &bsplit, &cbw)) return rc;
+    int KT;
+    if (int rc = fs_setup(geom, -1, k, n_mom, baryon ? 1 : 0, false, &groups, &plans, &bsplit, &cbw, &KT)) return rc;
     hipStream_t st = (hipStream_t)geom->stream;
     const bool bf16 = geom->proj == C3PT_PROJ_FACTORED_BF16;
-    const int KT = fs_kt(geom->L), Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
+    const int Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
     const int V3 = geom->L[0] * rows;
     const size_t bb = fs_block_bytes(geom->L);
     const int n_slots = baryon ? 16 : 1;
@@ -814,10 +819,11 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
     std::vector<FactorPlan> plans;
     bool bsplit;
     int cbw;
-    if (int rc = fs_setup(geom, +1, k, n_mom, 2, n_ops == 5, &groups, &plans, &bsplit, &cbw)) return rc;
+    int KT;
+    if (int rc = fs_setup(geom, +1, k, n_mom, 2, n_ops == 5, &groups, &plans, &bsplit, &cbw, &KT)) return rc;
     hipStream_t st = (hipStream_t)geom->stream;
     const bool bf16 = geom->proj == C3PT_PROJ_FACTORED_BF16;
-    const int KT = fs_kt(geom->L), Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
+    const int Lp = fs_lp(geom->L), rows = geom->L[1] * geom->L[2];
     const int V3 = geom->L[0] * rows;
     const int T = geom->T;
     const int kind = n_ops == 5 ? 2 : 1;

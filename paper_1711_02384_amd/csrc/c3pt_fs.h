@@ -435,26 +435,32 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
         // row (a, part) of the real form: part 0 takes (Re z, -Im z), part 1
         // (Im z, Re z) of z = w u; as linear maps of (u.x, u.y):
         //   v0 = c0 u.x + c1 u.y,  v1 = c1 u.x - c0 u.y
-        float cf[S::HS][4][2];
-#pragma unroll
-        for (int h = 0; h < S::HS; ++h)
+        // (one 16-site half: with longer tiles each step reads its own, which
+        // keeps the registers of one half live instead of all)
+        auto make_cf = [&](int h, float (&c)[4][2]) __attribute__((always_inline)) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const C2<float> wv = W1[(seg * kFacMaxK1 + a_row) * S::W1S + 16 * h + 4 * g + j];
-                cf[h][j][0] = part ? wv.y : wv.x;
-                cf[h][j][1] = part ? wv.x : -wv.y;
+                c[j][0] = part ? wv.y : wv.x;
+                c[j][1] = part ? wv.x : -wv.y;
             }
+        };
+        float cf1[4][2];
+        if constexpr (S::HS == 1) make_cf(0, cf1);
         // Steps st = (cs, h) in order, each nine MFMAs (three column tiles ct x
         // three products).  The A operands of step st + 1 are formed (VALU)
         // while the MFMAs of step st issue, and the B operands of each column
         // tile are read from LDS one tile ahead.
         auto form_a = [&](int st, vec_t& ahi, vec_t& alo) __attribute__((always_inline)) {
             const int cs = st / S::HS, h = st % S::HS;
+            float cfs[4][2];
+            if constexpr (S::HS > 1) make_cf(h, cfs);
+            const float(&cf)[4][2] = S::HS == 1 ? cf1 : cfs;
             u32x4 ah, al;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const C2<float> uv = sm.U[par][cbj][3 * at + cs][16 * h + 4 * g + j];
-                const f32x2 v = {cf[h][j][0] * uv.x + cf[h][j][1] * uv.y, cf[h][j][1] * uv.x - cf[h][j][0] * uv.y};
+                const f32x2 v = {cf[j][0] * uv.x + cf[j][1] * uv.y, cf[j][1] * uv.x - cf[j][0] * uv.y};
                 unsigned hh, ll;
                 fs_split2<T16>(v, hh, ll);
                 ah[j] = hh;

@@ -232,7 +232,7 @@ hipError_t launch_fs_reduce(const FsReduceArgs& a, hipStream_t st) {
 template <typename T16, int KT, int CB>
 static hipError_t launch_fs_cb(int kind, bool bsplit, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
     const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(256 * CB);
-    const size_t dyn = fs_dyn_bytes(a.L);
+    const size_t dyn = fs_dyn_bytes(a.L, KT);
     if (kind == 0 && bsplit)
         hipLaunchKernelGGL((fs_kernel<T16, KT, 0, true, CB>), grid, block, dyn, st, pg, a);
     else if (kind == 0)
@@ -255,7 +255,7 @@ static hipError_t launch_fs_t(int kind, bool bsplit, int cb, const ProjGrid& pg,
         // local insertion only (the host plans no other)
         if constexpr (KT == 16) {
             const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(768);
-            const size_t dyn = fs_dyn_bytes(a.L);
+            const size_t dyn = fs_dyn_bytes(a.L, 16);
             if (kind == 0 && bsplit)
                 hipLaunchKernelGGL((fs_kernel<T16, 16, 0, true, 3>), grid, block, dyn, st, pg, a);
             else if (kind == 0)
@@ -271,8 +271,28 @@ static hipError_t launch_fs_t(int kind, bool bsplit, int cb, const ProjGrid& pg,
     return cb == 1 ? launch_fs_cb<T16, KT, 1>(kind, bsplit, pg, a, st) : launch_fs_cb<T16, KT, 2>(kind, bsplit, pg, a, st);
 }
 
+// 48-site tiles (rows of 48 sites as one tile, a third of the barriers), two
+// blocks per workgroup: the spectators and the local insertion
+template <typename T16>
+static hipError_t launch_fs48(int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a, hipStream_t st) {
+    if (cb != 2) return hipErrorInvalidValue;
+    const dim3 grid(pg.n_share * pg.n_per_share * pg.n_chunks), block(512);
+    const size_t dyn = fs_dyn_bytes(a.L, 48);
+    if (kind == 0 && bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, 48, 0, true, 2>), grid, block, dyn, st, pg, a);
+    else if (kind == 0)
+        hipLaunchKernelGGL((fs_kernel<T16, 48, 0, false, 2>), grid, block, dyn, st, pg, a);
+    else if (kind == 1 && !bsplit)
+        hipLaunchKernelGGL((fs_kernel<T16, 48, 1, false, 2>), grid, block, dyn, st, pg, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_fs(bool bf16, int KT, int kind, bool bsplit, int cb, const ProjGrid& pg, const FsArgs& a,
                      hipStream_t st) {
+    if (KT == 48) return bf16 ? launch_fs48<__bf16>(kind, bsplit, cb, pg, a, st)
+                              : launch_fs48<_Float16>(kind, bsplit, cb, pg, a, st);
     if (bf16)
         return KT == 32 ? launch_fs_t<__bf16, 32>(kind, bsplit, cb, pg, a, st)
                         : launch_fs_t<__bf16, 16>(kind, bsplit, cb, pg, a, st);

@@ -70,8 +70,7 @@ inline int fs_lp(const int L[3]) {
 inline size_t fs_block_bytes(const int L[3]) { return (size_t)kFsPlanes * L[1] * L[2] * fs_lp(L) * 8; }
 // Dynamic LDS of the fused kernel: the w1 table [nseg][kFacMaxK1][KT + 2] and
 // the three root tables (L1 + L2 + L3 entries), complex FP32.
-inline size_t fs_dyn_bytes(const int L[3]) {
-    const int kt = fs_kt(L);
+inline size_t fs_dyn_bytes(const int L[3], int kt) {
     const int nseg = (L[0] + kt - 1) / kt;
     return ((size_t)nseg * kFacMaxK1 * (kt + 2) + L[0] + L[1] + L[2]) * 8;
 }

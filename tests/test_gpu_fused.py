@@ -2,7 +2,8 @@
 _BF16: the colour contraction folded into the x1 stage of the factored
 projection on hi+lo 16-bit MFMA, FP32 accumulation) with the FP64 oracle.
 
-Cases: 32-site tiles (rows of 32, 64: one and two segments), 16-site tiles
+Cases: 32-site tiles (rows of 32, 64: one and two segments), rows of 48 (one
+48-site tile under variant 5), 16-site tiles
 (rows of 24 and 72: ragged last segment, five segments; rows of 6 shorter
 than a tile), an extent of 1 in x2 (the derivative's neighbours are the site
 itself), an odd noise count (the second block of the last pair is empty), a
@@ -41,6 +42,7 @@ CASES = [
     ((72, 3, 2), 4, [1], 1, 3, (0, 1, 1)),
     ((6, 1, 5), 4, [2], 2, 3, (2, 0, 4)),
     ((64, 2, 2), 4, [0, 3], 2, 8, (1, 1, 1)),
+    ((48, 3, 2), 4, [0, 3], 3, 8, (7, 2, 1)),
 ]
 
 
@@ -50,14 +52,15 @@ def _set_fused_variant(c3pt, v):
             c3pt.set_variant(kind, c3pt.MODE["fs16"], cls, v)
 
 
-@pytest.mark.parametrize("prec,variant", [("f16", 0), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4), ("bf16", 0),
-                                          ("bf16", 3), ("bf16", 4)])
+@pytest.mark.parametrize("prec,variant", [("f16", 0), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4), ("f16", 5),
+                                          ("bf16", 0), ("bf16", 3), ("bf16", 4), ("bf16", 5)])
 @pytest.mark.parametrize("case", range(len(CASES)))
 def test_fused_parts(case, prec, variant):
     """variant 0 splits the propagator tiles in the kernel, 1 in a pass first, 2 with one
     column block per workgroup, 3 in the kernel with one column block per workgroup, 4 in
     the kernel with three column blocks per workgroup (16-site tiles; an odd noise count
-    leaves blocks of the last group empty; 32-site tiles and the derivative slots run as 0)."""
+    leaves blocks of the last group empty; 32-site tiles and the derivative slots run as 0),
+    5 as 0 with 48-site tiles for the local insertion when L1 = 48 (elsewhere as 0)."""
     import paper_1711_02384_amd as c3pt
     L, T, taus, N, n2, r = CASES[case]
     k = c3pt.momentum_list(n2)
