@@ -25,28 +25,50 @@ __device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
 // Deterministic FP64 reduction of the split-site partial sums, times the
 // source factor of each momentum.
 // ---------------------------------------------------------------------------
-template <typename P2>
+// Each thread sums one output element over the chunks in a fixed order: eight
+// interleaved FP64 partial sums (chunk ch into sum ch % 8, so eight loads are
+// in flight), combined pairwise at the end.  Index arithmetic is 32-bit (the
+// launcher takes the 64-bit form when an index would not fit).
+template <typename P2, typename I>
 __global__ void __launch_bounds__(256) reduce_kernel(ReduceArgs a) {
-    const size_t total = (size_t)a.n_groups * a.n_mom_grp * a.group_cols;
+    const I total = (I)a.n_groups * (I)a.n_mom_grp * (I)a.group_cols;
     const int blocks_per_group = a.group_cols / kBlockCols;
     const P2* partial = (const P2*)a.partial;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(idx % a.group_cols);
-        const size_t rest = idx / a.group_cols;
-        const int m = (int)(rest % a.n_mom_grp);
-        const int g = (int)(rest / a.n_mom_grp);
+    const size_t cstride = (size_t)a.n_colblocks * a.n_mom_grp * kBlockCols;   // elements between chunks
+    for (I idx = (I)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (I)gridDim.x * blockDim.x) {
+        const int c = (int)(idx % (I)a.group_cols);
+        const I rest = idx / (I)a.group_cols;
+        const int m = (int)(rest % (I)a.n_mom_grp);
+        const int g = (int)(rest / (I)a.n_mom_grp);
         const int cb = g * blocks_per_group + c / kBlockCols;
         const int cc = c % kBlockCols;
-        double sx = 0.0, sy = 0.0;
-        for (int ch = 0; ch < a.n_chunks; ++ch) {
-            const P2 v = partial[(((size_t)ch * a.n_colblocks + cb) * a.n_mom_grp + m) * kBlockCols + cc];
-            sx += (double)v.x;
-            sy += (double)v.y;
+        const P2* p = partial + ((size_t)cb * a.n_mom_grp + m) * kBlockCols + cc;
+        double sx[8], sy[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sx[k] = sy[k] = 0.0;
+        int ch = 0;
+        for (; ch + 8 <= a.n_chunks; ch += 8) {
+            P2 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(ch + k) * cstride];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                sx[k] += (double)v[k].x;
+                sy[k] += (double)v[k].y;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if (ch + k < a.n_chunks) {
+                const P2 v = p[(size_t)(ch + k) * cstride];
+                sx[k] += (double)v.x;
+                sy[k] += (double)v.y;
+            }
+        const double tx = ((sx[0] + sx[1]) + (sx[2] + sx[3])) + ((sx[4] + sx[5]) + (sx[6] + sx[7]));
+        const double ty = ((sy[0] + sy[1]) + (sy[2] + sy[3])) + ((sy[4] + sy[5]) + (sy[6] + sy[7]));
         const double2 f = source_factor(a.ph.L, a.ph.r, a.ph.sigma, a.ph.k[0][m], a.ph.k[1][m], a.ph.k[2][m]);
         const size_t G = (size_t)(g / a.inner) * a.outer_stride + a.off + g % a.inner;
-        a.out[(G * a.n_mom_total + a.m_off + m) * (size_t)a.group_cols + c] = cmul_d(f, make_double2(sx, sy));
+        a.out[(G * a.n_mom_total + a.m_off + m) * (size_t)a.group_cols + c] = cmul_d(f, make_double2(tx, ty));
     }
 }
 
@@ -204,10 +226,15 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
     size_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
-    if (a.f64)
-        hipLaunchKernelGGL(reduce_kernel<double2>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    const bool small = total + (size_t)65536 * 256 < ((size_t)1 << 32);
+    if (a.f64 && small)
+        hipLaunchKernelGGL((reduce_kernel<double2, unsigned>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    else if (a.f64)
+        hipLaunchKernelGGL((reduce_kernel<double2, size_t>), dim3((unsigned)blocks), dim3(256), 0, st, a);
+    else if (small)
+        hipLaunchKernelGGL((reduce_kernel<float2, unsigned>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(reduce_kernel<float2>, dim3((unsigned)blocks), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((reduce_kernel<float2, size_t>), dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
