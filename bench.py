@@ -122,7 +122,7 @@ TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_de
 # host functions of c3pt_api.hip that plan and launch the factored and fused kernels
 TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table", "plan_planes", "plan_chunks",
                      "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion",
-                     "fs_plans", "fs_scratch", "fs_spectator", "fs_insertion"]
+                     "fs_plans", "fs_setup", "fs_scratch", "fs_spectator", "fs_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
     # 48^3 step, split-precision fused form: one local insertion dispatch (1626158 + 803520 KiB)
