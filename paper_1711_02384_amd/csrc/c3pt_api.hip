@@ -698,6 +698,32 @@ int fs_setup(const c3pt_geom* g, int sigma, const int* k, int n_mom, int vkind, 
     return C3PT_OK;
 }
 
+// The kernel launches of one fused projection: with three blocks per
+// workgroup and N not a multiple of three, the last N % 3 noise vectors run as
+// a two-block launch over the same work grid, so that no workgroup carries an
+// empty block; both write the call's partial sums (column blocks keep their
+// indexes).  pg.n_per_share is set per launch from n_slots.
+hipError_t fs_launch_noise_parts(bool bf16, int KT, int kind, bool bsplit, int cbw, int N, int n_slots,
+                                 ProjGrid pg, FsArgs fa, hipStream_t st) {
+    int base[2], cnt[2], cbs[2], nparts = 0;
+    if (cbw == 3 && N % 3 != 0) {
+        if (N >= 3) {
+            base[nparts] = 0, cnt[nparts] = N - N % 3, cbs[nparts++] = 3;
+        }
+        base[nparts] = N - N % 3, cnt[nparts] = N % 3, cbs[nparts++] = 2;
+    } else {
+        base[0] = 0, cnt[0] = N, cbs[0] = cbw, nparts = 1;
+    }
+    for (int i = 0; i < nparts; ++i) {
+        fa.i_base = base[i];
+        fa.N = cnt[i];
+        pg.n_per_share = n_slots * ((cnt[i] + cbs[i] - 1) / cbs[i]);
+        const hipError_t e = launch_fs(bf16, KT, kind, bsplit, cbs[i], pg, fa, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Partial sums then split B blocks in this stream's scratch.
 int fs_scratch(hipStream_t st, size_t part_bytes, size_t b_bytes, void** part, void** B) {
     const size_t off = (part_bytes + 255) & ~(size_t)255;
@@ -788,7 +814,10 @@ int fs_spectator(const c3pt_geom* geom, bool baryon, const void* G1, const void*
         fa.G[0][0] = G1;
         fa.u0[0] = eta;
         if (int rc = to_status(timed(baryon ? "fs_spectator_baryon" : "fs_spectator_meson", st,
-                                     [&] { return launch_fs(bf16, KT, 0, bsplit, cbw, pg, fa, st); }),
+                                     [&] {
+                                         return fs_launch_noise_parts(bf16, KT, 0, bsplit, cbw, N, n_slots, pg,
+                                                                      fa, st);
+                                     }),
                                "projection launch"))
             return rc;
         ReduceArgs ra;
@@ -919,7 +948,10 @@ int fs_insertion(const c3pt_geom* geom, const void* const* G_t, const void* cons
             pg.phase = tab;
             pg.partial = part;
             if (int rc = to_status(timed("fs_insertion", st,
-                                         [&] { return launch_fs(bf16, KT, kind, bsplit, cbw, pg, fa, st); }),
+                                         [&] {
+                                             return fs_launch_noise_parts(bf16, KT, kind, bsplit, cbw, N, n_slots,
+                                                                          pg, fa, st);
+                                         }),
                                    "projection launch"))
                 return rc;
             if (kind == 1) {

@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
     const int slot = within / ngroup;
     const int i0 = CB * (within % ngroup);
     const bool valid = i0 + cbj < N;   // an odd noise count leaves the second block of the last pair empty
-    const int cb = ((min(i0 + cbj, N - 1) * fa.n_share + share) * fa.n_slots + slot);
+    const int cb = (((fa.i_base + min(i0 + cbj, N - 1)) * fa.n_share + share) * fa.n_slots + slot);
     const int L1 = fa.L[0], L2 = fa.L[1], L3 = fa.L[2];
     const int V3 = L1 * L2 * L3;
     const float inv1 = 1.0f / (float)L1, inv2 = 1.0f / (float)L2, inv3 = 1.0f / (float)L3;
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
             const int bj = e / (12 * KT), rem = e % (12 * KT);
             const int A = rem / KT, xl = rem % KT;
             const int x1 = min(q.seg * KT + xl, L1 - 1);
-            const int noise = min(i0 + bj, N - 1);
+            const int noise = fa.i_base + min(i0 + bj, N - 1);
             const C2<float>* src = ubase + (size_t)noise * 12 * V3;
             const int n = x1 + L1 * (q.x2 + L2 * q.x3);
             if (KIND != 2 || slot == 0) {

@@ -16,7 +16,8 @@ constexpr int kFsPairsCB3 = 5;   // (k1, k2) pairs per k1 slot with three column
 struct FsArgs {
     int L[3];
     int Lp, rows;          // padded row length of a split B block (multiple of KT), L2 * L3
-    int N;                 // noise vectors
+    int N;                 // noise vectors of this launch: i_base .. i_base + N - 1 of the call
+    int i_base;
     int n_share, n_slots;  // shares (timeslices of the launch; 1 for spectators), slots per share
     int colmap;            // 0: column at*48 + X; 1: nucleon (X/3)*12 + at*3 + X%3
     const void* B;         // split B source: blocks b_stride bytes apart; spectators: block = slot,

@@ -8,7 +8,7 @@ Cases: 32-site tiles (rows of 32, 64: one and two segments), rows of 48 (one
 than a tile), an extent of 1 in x2 (the derivative's neighbours are the site
 itself), an odd noise count (the second block of the last pair is empty), a
 source off the origin, the |k|^2 <= 9 list (a k1 with seven k2 over two
-stage-1 slots), timeslices wrapping around T.  Every part: meson spectator,
+stage-1 slots; five noise vectors), timeslices wrapping around T.  Every part: meson spectator,
 nucleon spectator, insertion with the local operator alone and with the four
 D_nu (whose shifted parts are combined in the FP64 reduction).  Inputs are
 complex64; the oracle gets the same values in FP64.  Tolerance 1e-5 (rel_err:
@@ -38,11 +38,11 @@ CASES = [
     ((32, 4, 3), 6, [0, 2], 2, 3, (5, 1, 2)),
     ((24, 3, 2), 6, [1, 5], 3, 6, (0, 2, 1)),
     ((6, 5, 4), 6, [0, 3], 1, 3, (1, 0, 3)),
-    ((12, 8, 6), 4, [0, 3], 2, 9, (3, 1, 2)),
+    ((12, 8, 6), 4, [0, 3], 5, 9, (3, 1, 2)),
     ((72, 3, 2), 4, [1], 1, 3, (0, 1, 1)),
     ((6, 1, 5), 4, [2], 2, 3, (2, 0, 4)),
     ((64, 2, 2), 4, [0, 3], 2, 8, (1, 1, 1)),
-    ((48, 3, 2), 4, [0, 3], 3, 8, (7, 2, 1)),
+    ((48, 3, 2), 4, [0, 3], 4, 8, (7, 2, 1)),
 ]
 
 
@@ -58,8 +58,9 @@ def _set_fused_variant(c3pt, v):
 def test_fused_parts(case, prec, variant):
     """variant 0 splits the propagator tiles in the kernel, 1 in a pass first, 2 with one
     column block per workgroup, 3 in the kernel with one column block per workgroup, 4 in
-    the kernel with three column blocks per workgroup (16-site tiles; an odd noise count
-    leaves blocks of the last group empty; 32-site tiles and the derivative slots run as 0),
+    the kernel with three column blocks per workgroup (16-site tiles; N = 4 and 5 run the
+    last one or two noise vectors as a two-block launch, N = 1 and 2 as that launch
+    alone; 32-site tiles and the derivative slots run as 0),
     5 as 0 with 48-site tiles for the local insertion when L1 = 48 (elsewhere as 0)."""
     import paper_1711_02384_amd as c3pt
     L, T, taus, N, n2, r = CASES[case]
