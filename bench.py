@@ -124,11 +124,14 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
                      "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion",
                      "fs_plans", "fs_setup", "fs_scratch", "fs_spectator", "fs_insertion"]
 MEASURED_TRAFFIC = {
-    # workload, projection, timed kernel name, insertion operators -> (bytes per launch, source hash)
-    # 48^3 step, split-precision fused form: one local insertion dispatch (1626158 + 803520 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): (1626158 * 2048 + 803520 * 1024, "2c0ea9667a8dfdfc"),
-    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413669 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413669 * 2048 + 857088 * 1024, "2c0ea9667a8dfdfc"),
+    # workload, projection, timed kernel name, insertion operators -> (bytes per call, source hash)
+    # 48^3 step, split-precision fused form: one local insertion call, i.e. its
+    # three-block launch (1429337 + 602640 KiB) and the two-block launch of the
+    # last two noise vectors (1089842 + 200880 KiB)
+    ("nucleon48", "fs16", "fs_insertion", 1): ((1429337 + 1089842) * 2048 + (602640 + 200880) * 1024,
+                                               "d0bb46589d6938b7"),
+    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (414322 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414322 * 2048 + 857088 * 1024, "d0bb46589d6938b7"),
 }
 
 
@@ -214,14 +217,20 @@ PEAK_MFMA_F16 = 2500.0   # dense FP16 / BF16 MFMA, TFLOP/s
 
 
 def fused_mfma_flops(L, N, n_slots, n_share, n_groups=1, cb=2):
-    """MFMA flops the fused split-precision kernel issues in one launch: every
+    """MFMA flops the fused split-precision kernel issues in one call: every
     wave (four per column block, CB blocks per workgroup, ceil(N / CB)
-    workgroups per slot and share) runs, per tile of KT sites of one (x2, x3)
+    workgroups per slot and share; with CB = 3 the last N mod 3 blocks run two
+    to a workgroup) runs, per tile of KT sites of one (x2, x3)
     row, 3 summed colours x KT / 16 K steps x 3 column tiles x 3 products
     (lo.hi, hi.lo, hi.hi) of a 16x16x32 MFMA (16384 flops)."""
     kt = 32 if L[0] % 32 == 0 else 16
     tiles = L[1] * L[2] * ((L[0] + kt - 1) // kt)
-    waves = 4 * cb * ((N + cb - 1) // cb) * n_slots * n_share * n_groups
+    if cb == 3:
+        # full groups of three, then the last N mod 3 noise vectors as a two-block launch
+        blocks = 3 * (N // 3) + 2 * ((N % 3 + 1) // 2)
+    else:
+        blocks = cb * ((N + cb - 1) // cb)
+    waves = 4 * blocks * n_slots * n_share * n_groups
     return float(waves) * tiles * 27 * (kt // 16) * 16384
 
 
@@ -1324,8 +1333,9 @@ def main():
         kms = prof.get(kname, {}).get("avg_ms", float("nan"))
     roofline = roofline_entry(kname, flops, kms, proj, measured_traffic(args.workload, proj, kname, getattr(W, "n_ops", 1)))
     if roofline["traffic"] is not None:
-        roofline["traffic_note"] = ("HBM bytes per launch from rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1 "
-                                    "(copy-calibrated), measured on these kernel sources")
+        roofline["traffic_note"] = ("HBM bytes per call of the timed kernel (all its launches) from rocprofv3 "
+                                    "FETCH_SIZE x 2 + WRITE_SIZE x 1 (copy-calibrated), measured on these kernel "
+                                    "sources")
         roofline["hbm_frac"] = round(roofline["traffic"] / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     mf = getattr(W, "mfma_flops", lambda kn, pj: None)(kname, proj)
     if mf is not None:
