@@ -122,16 +122,17 @@ TRAFFIC_SOURCES = ["c3pt_fac.h", "c3pt_fac_prod.h", "c3pt_producers.h", "c3pt_de
 # host functions of c3pt_api.hip that plan and launch the factored and fused kernels
 TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table", "plan_planes", "plan_chunks",
                      "run_projection", "c3pt_spectator_meson", "c3pt_spectator_baryon", "c3pt_insertion",
-                     "fs_plans", "fs_setup", "fs_scratch", "fs_spectator", "fs_insertion"]
+                     "fs_plans", "fs_setup", "fs_launch_noise_parts", "fs_scratch", "fs_spectator",
+                     "fs_insertion"]
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per call, source hash)
     # 48^3 step, split-precision fused form: one local insertion call, i.e. its
-    # three-block launch (1429337 + 602640 KiB) and the two-block launch of the
-    # last two noise vectors (1089842 + 200880 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): ((1429337 + 1089842) * 2048 + (602640 + 200880) * 1024,
-                                               "d0bb46589d6938b7"),
-    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (414322 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414322 * 2048 + 857088 * 1024, "d0bb46589d6938b7"),
+    # three-block launch (1431329 + 602640 KiB) and the two-block launch of the
+    # last two noise vectors (1089896 + 200880 KiB)
+    ("nucleon48", "fs16", "fs_insertion", 1): ((1431329 + 1089896) * 2048 + (602640 + 200880) * 1024,
+                                               "4633be0e50241083"),
+    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413917 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413917 * 2048 + 857088 * 1024, "4633be0e50241083"),
 }
 
 

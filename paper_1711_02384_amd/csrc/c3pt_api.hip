@@ -702,7 +702,10 @@ int fs_setup(const c3pt_geom* g, int sigma, const int* k, int n_mom, int vkind, 
 // workgroup and N not a multiple of three, the last N % 3 noise vectors run as
 // a two-block launch over the same work grid, so that no workgroup carries an
 // empty block; both write the call's partial sums (column blocks keep their
-// indexes).  pg.n_per_share is set per launch from n_slots.
+// indexes).  The second launch reads the B blocks again (for the 48^3 local
+// insertion 1.9 GB of propagator slices) and is still faster: spectator 2.70
+// -> 2.54 ms, insertion 2.93 -> 2.79 ms against one launch with an empty
+// block in each last group.  pg.n_per_share is set per launch from n_slots.
 hipError_t fs_launch_noise_parts(bool bf16, int KT, int kind, bool bsplit, int cbw, int N, int n_slots,
                                  ProjGrid pg, FsArgs fa, hipStream_t st) {
     int base[2], cnt[2], cbs[2], nparts = 0;
