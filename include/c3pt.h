@@ -340,9 +340,14 @@ int c3pt_release_scratch(void);
  * runs two column blocks per workgroup, variant 1 splits the call's slices
  * once in a pass before it, variant 2 does that and runs one column block per
  * workgroup, variant 3 splits in the kernel with one column block per
- * workgroup.  The nucleon spectator
- * always forms its diquark in a pass (variants 0 and 1, and 2 and 3, are the
- * same for it).  Mode 6 selects
+ * workgroup, variant 4 splits in the kernel with three column blocks per
+ * workgroup (16-site tiles, spectators and the local insertion; factor plans
+ * with at most five (k1, k2) pairs per k1 slot; when N is not a multiple of
+ * three the last N % 3 noise vectors run as a second, two-block launch;
+ * elsewhere it runs as variant 0), variant 5 takes rows of 48 sites as one
+ * tile when L1 = 48 (spectators and the local insertion; elsewhere as 0).
+ * The nucleon spectator always forms its diquark in a pass (variants 0 and
+ * 1, and 2 and 3, are the same for it).  Mode 6 selects
  * the factored kernels of batches and of the server (read when a batch is
  * created and when the server plans a step), as two bits: 1 takes 32-site
  * tiles for jobs with L1 % 32 == 0 (meson spectator and local insertion; the
