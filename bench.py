@@ -85,8 +85,9 @@ def parse():
     ap.add_argument("--arena-gib", type=float, default=48.0, help="serve: output arena")
     ap.add_argument("--step-mib", type=float, default=1024.0, help="serve: partial-sum workspace per step")
     ap.add_argument("--max-active", type=int, default=32, help="serve: requests in flight")
-    ap.add_argument("--streams", type=int, default=1, choices=[1, 2],
-                    help="nucleon48: run the two isovector halves of the step on two streams")
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="nucleon48: run the two isovector halves of the step on two streams (default) "
+                         "or on one; kernel durations always come from one-stream profiled steps")
     ap.add_argument("--step-work", type=float, default=0.0,
                     help="serve: cap on a step's work in column blocks x sites (0: none)")
     return ap.parse_args()
@@ -462,6 +463,7 @@ class Nucleon48(Meson32):
         self.n2 = args.n2 if args.n2 is not None else 8
         self.analysis = args.analysis
         self.streams = args.streams
+        self.one_stream = False   # set while profiling: kernel durations without sharing
         self.name = (f"nucleon 3pt, 48^3x64, t_f=14, tau=0..14, N=8, |k|^2<={self.n2}, spectators (u,u) and "
                      f"(u,d), isovector insertion (u and d), local"
                      + (", proton channels (C gamma5, parity projectors, 16 Gamma_ins)" if self.analysis else "")
@@ -509,7 +511,7 @@ class Nucleon48(Meson32):
         c, g, k = self.c3pt, self.geom, self.k
         tf = self.t_f
         main = torch.cuda.current_stream()
-        side = self.side if self.side is not None else main
+        side = self.side if self.side is not None and not self.one_stream else main
         fork = torch.cuda.Event()
         fork.record(main)
         side.wait_event(fork)
@@ -1308,12 +1310,16 @@ def main():
     # launches one by one instead of the graph)
     prof_steps = max(1, min(args.steps, 3))
     log(f"[bench] profiling {prof_steps} steps")
+    if hasattr(W, "one_stream"):
+        W.one_stream = True    # per-kernel durations on one stream, without sharing
     c3pt.profile_read(reset=True)
     c3pt.profile_enable(True)
     for _ in range(prof_steps):
         W.step()
     torch.cuda.synchronize()
     c3pt.profile_enable(False)
+    if hasattr(W, "one_stream"):
+        W.one_stream = False
     prof = c3pt.profile_read(reset=True)
 
     if batched:
