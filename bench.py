@@ -516,11 +516,13 @@ class Nucleon48(Meson32):
         fork.record(main)
         side.wait_event(fork)
         gs = c.Geom(g.L, g.T, r=g.r, proj=g.proj, stream=side.cuda_stream)
-        # proton isovector: spectators (u,u) with the d insertion, (u,d) with the u insertion
+        # proton isovector: spectators (u,u) with the d insertion, (u,d) with the u
+        # insertion; the second stream starts with its insertion while the first
+        # forms its diquark, so that the memory-bound passes do not coincide
         c.spectator_baryon(self.Gu[tf], self.Gu[tf], self.eta, k, g, out=self.Suu)
-        c.spectator_baryon(self.Gu[tf], self.Gd[tf], self.eta, k, gs, out=self.Sud)
-        c.insertion(self.Gd, self.s, self.taus, k, g, out=self.Id)
         c.insertion(self.Gu, self.s, self.taus, k, gs, out=self.Iu)
+        c.insertion(self.Gd, self.s, self.taus, k, g, out=self.Id)
+        c.spectator_baryon(self.Gu[tf], self.Gd[tf], self.eta, k, gs, out=self.Sud)
         c.combine(self.Suu, self.Id, pairs=self.pairs, out=self.Cd)
         c.combine(self.Sud, self.Iu, pairs=self.pairs, out=self.Cu, stream=side.cuda_stream)
         join = torch.cuda.Event()
