@@ -1444,6 +1444,9 @@ def main():
         "kernels_ms": {kn: round(v["avg_ms"], 4) for kn, v in prof.items()},
         "kernels_ms_per_step": {kn: round(v["total_ms"] / prof_steps, 3) for kn, v in prof.items()},
         "kernel_launches": {kn: v["count"] for kn, v in prof.items()},
+        "kernels_note": ("per-call durations (HIP events on the launch stream) over "
+                         f"{prof_steps} separate profiled steps"
+                         + (" run on one stream" if hasattr(W, "one_stream") else "")),
         "roofline": roofline,
         "variants": {kn: c3pt.get_variant(c3pt.KIND[kn], mode, cls)
                      for kn in ("spectator_meson", "spectator_baryon", "insertion")},
