@@ -31,12 +31,15 @@
 // Each (nu, +-) is its own column block ("slot") of partial sums; the FP64
 // reduction applies the per-momentum factors and forms the difference.
 //
-// Workgroup: 4 CB waves = CB column blocks (CB = 2: two noise vectors of one
-// slot, sharing the B tile in LDS) x four A indices; a wave owns one A index
-// and all 48 B columns as three 16-column MFMA tiles.  With CB = 1 two
-// workgroups fit a CU and run their phases independently.  The tile loop is the factored
-// kernel's: tiles are KT sites of one x1 row, one workgroup barrier per tile,
-// B and u of the next tile staged while the current one is computed.
+// Workgroup: 4 CB waves = CB column blocks (noise vectors of one slot,
+// sharing the B tile in LDS; CB = 1, 2 or 3) x four A indices; a wave owns
+// one A index and all 48 B columns as three 16-column MFMA tiles.  Three
+// blocks give twelve waves (three per SIMD) and share the propagator tile's
+// split three ways.  The tile loop is the factored kernel's: tiles are KT
+// sites of one x1 row, one workgroup barrier per tile, B and u of the next
+// tile staged while the current one is computed; within a tile the A
+// operands of the next K step are formed while the MFMAs of the current one
+// issue.
 #pragma once
 
 #include "c3pt_device.h"
