@@ -133,3 +133,33 @@ def test_fused_two_momentum_groups():
     e5 = max(rel_err(I5[:, j, op], I_o[:, j, op]) for j in range(len(taus)) for op in range(5))
     _say(f"fused f16 two groups: meson {es:.2e} nucleon {eb:.2e} insertion max {e5:.2e}")
     assert es < TOL and eb < TOL and e5 < TOL
+
+
+def test_fused_three_blocks_remainder_of_one_and_two_groups():
+    """Variant 4 (three blocks per workgroup) with N = 7 (groups of three, then
+    one vector in a two-block launch with its second block empty) and a
+    147-momentum list (two momentum groups, each planned with at most five
+    pairs per k1 slot); every part against the oracle."""
+    import paper_1711_02384_amd as c3pt
+    L, T, taus, N, r = (12, 8, 6), 4, [1, 2], 7, (2, 3, 1)
+    k = c3pt.momentum_list(10)
+    w = Workload(L, T, N, cfg=72, taus=taus, links=True, reduced=True, second_prop=True)
+    geom = c3pt.Geom(L, T, r=r, proj=c3pt.PROJ_FACTORED_F16)
+    _say(f"fused f16 variant 4, N = {N}, {len(k)} momenta")
+    _set_fused_variant(c3pt, 4)
+    try:
+        S = c3pt.spectator_meson(_t(w.G1), _t(w.eta), k, geom).cpu().numpy()
+        SB = c3pt.spectator_baryon(_t(w.G1), _t(w.G1b), _t(w.eta), k, geom).cpu().numpy()
+        G = {t: _t(v) for t, v in w.G3.items()}
+        s = {t: _t(v) for t, v in w.s.items()}
+        I1 = c3pt.insertion(G, s, taus, k, geom, n_ops=1).cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        _set_fused_variant(c3pt, 0)
+    S_o = oracle.spectator_meson(w.G1, w.eta, L, k, r=r)
+    SB_o = oracle.spectator_baryon(w.G1, w.G1b, w.eta, L, k, r=r)
+    I_o = oracle.insertion(w.G3, w.s, taus, L, T, k, r=r, n_ops=1)
+    es, eb = rel_err(S, S_o), rel_err(SB, SB_o)
+    e1 = max(rel_err(I1[:, j, 0], I_o[:, j, 0]) for j in range(len(taus)))
+    _say(f"fused f16 variant 4, N = {N}: meson {es:.2e} nucleon {eb:.2e} insertion {e1:.2e}")
+    assert es < TOL and eb < TOL and e1 < TOL
