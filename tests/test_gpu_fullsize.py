@@ -13,6 +13,10 @@ outputs (selected timeslices, noise vectors or momenta) one by one.
   the factored FP32 one: the nucleon spectator for one noise vector and a
   momentum subset, and one insertion timeslice.  Tolerance 1e-5 relative
   (the larger of Frobenius and max-element), the same as FP32.
+* the 48^3 x 64 nucleon step in the exact launch configuration of the
+  benchmark (93 momenta, tuned fused variants with the two-block remainder
+  launch, 15 timeslices in one insertion call, 185 combine pairs), sampled
+  in both launches of each call.
 """
 import numpy as np
 import pytest
@@ -132,3 +136,59 @@ def test_nucleon48_split_sampled(proj, name):
         e = rel_err(C, oracle.combine(SB, I, pairs=pairs))
         _say(f"nucleon48 {name}: combine on {len(pairs)} pairs rel err {e:.2e}")
         assert e < 1e-12
+
+
+def test_nucleon48_benchmark_launches_sampled():
+    """The 48^3 x 64 nucleon step exactly as bench.py launches it: 93 momenta
+    (|k|^2 <= 8, one momentum group), N = 8, the fused FP16 projection with the
+    tuned variants (three column blocks per workgroup over noise vectors 0-5 and
+    a two-block launch over 6-7), the insertion over all 15 timeslices in one
+    call and the combine on the 185 (p' = q or p' = 0) pairs.  Sampled: the
+    (u,d) spectator for noise vectors 2 and 7 (one from each launch) at three
+    momenta, the insertion at tau = 0 and 14 for every noise vector and
+    momentum, and the combine of the GPU's parts on four pairs."""
+    import paper_1711_02384_amd as c3pt
+    c3pt.apply_tuning(c3pt.DEFAULT_TUNING)
+    L, T, N, t_f, cfg = (48, 48, 48), 64, 8, 14, 3
+    taus = list(range(15))
+    k = c3pt.momentum_list(8)
+    assert len(k) == 93
+    cls = c3pt.mt_class(len(k))
+    for kind in ("spectator_baryon", "insertion"):
+        assert c3pt.get_variant(c3pt.KIND[kind], c3pt.MODE["fs16"], cls) == 4, kind
+    geom = c3pt.Geom(L, T, proj=c3pt.PROJ_FACTORED_F16)
+    _say("nucleon48 benchmark launches: generating inputs")
+    Gu = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t_f))
+    Gd = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G1, t_f))
+    eta = syn.round_to_c64(syn.z2z2_noise(L, N, cfg, t_f))
+    SB = c3pt.spectator_baryon(_up(Gu), _up(Gd), _up(eta), k, geom)
+    # distinct slices at the checked timeslices and one other slice shared by
+    # the rest (a launch reading the wrong slice shows at tau = 0 or 14)
+    G = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in (0, 7, 14)}
+    s = {t: syn.round_to_c64(syn.solution_slice(L, N, cfg, t)) for t in (0, 7, 14)}
+    Gdev = {t: _up(a) for t, a in G.items()}
+    sdev = {t: _up(a) for t, a in s.items()}
+    Gt = {t: Gdev.get(t, Gdev[7]) for t in taus}
+    st = {t: sdev.get(t, sdev[7]) for t in taus}
+    Id = c3pt.insertion(Gt, st, taus, k, geom)
+    pairs = np.array([(p, p) for p in range(93)] + [(0, q) for q in range(1, 93)], dtype=np.int32)
+    C = c3pt.combine(SB, Id, pairs=pairs)
+    torch.cuda.synchronize()
+    sel_p = [0, 50, 93, 184]
+    C_sel = C[sel_p].cpu().numpy()
+    del C
+    S = SB.cpu().numpy()
+    I = Id.cpu().numpy()
+    sel_n, sel_m = [2, 7], [0, 46, 92]
+    want = oracle.spectator_baryon(Gu, Gd, eta[sel_n], L, k[sel_m])
+    err = rel_err(S[sel_n][:, sel_m], want)
+    _say(f"nucleon48 benchmark launches: spectator (noise 2 and 7, 3 momenta) rel err {err:.2e}")
+    assert err < TOL32
+    for tau in (0, 14):
+        I_o = oracle.insertion({tau: G[tau]}, {tau: s[tau]}, [tau], L, T, k)
+        err = rel_err(I[:, tau], I_o[:, 0])
+        _say(f"nucleon48 benchmark launches: insertion tau={tau} (8 noise vectors, 93 momenta) rel err {err:.2e}")
+        assert err < TOL32
+    e = rel_err(C_sel, oracle.combine(S, I, pairs=pairs[sel_p]))
+    _say(f"nucleon48 benchmark launches: combine on pairs {sel_p} rel err {e:.2e}")
+    assert e < 1e-12
