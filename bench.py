@@ -128,12 +128,12 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per call, source hash)
     # 48^3 step, split-precision fused form: one local insertion call, i.e. its
-    # three-block launch (1431329 + 602640 KiB) and the two-block launch of the
+    # three-block launch (1432296 + 602640 KiB) and the two-block launch of the
     # last two noise vectors (1089896 + 200880 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): ((1431329 + 1089896) * 2048 + (602640 + 200880) * 1024,
-                                               "4633be0e50241083"),
-    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413917 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413917 * 2048 + 857088 * 1024, "4633be0e50241083"),
+    ("nucleon48", "fs16", "fs_insertion", 1): ((1432296 + 1089896) * 2048 + (602640 + 200880) * 1024,
+                                               "287b4b579a2a535b"),
+    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413552 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413552 * 2048 + 857088 * 1024, "287b4b579a2a535b"),
 }
 
 

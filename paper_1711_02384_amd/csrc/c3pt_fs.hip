@@ -88,17 +88,23 @@ __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
     unsigned char* out = (unsigned char*)((FsGroup*)a.out + (size_t)blk * kFsPlanes * a.rows * (Lp / 4));
     const int sw = (rl * 9) * (Lp / 4) * 8 + (x1 >> 2) * 8 + (x1 & 3);   // the site's hi word of plane 0
     const int run_units = 3 * Lp / 2;                                      // 16-byte units of one run (3 planes)
-    for (int q = 0; q < 16; ++q) {
-        unsigned* st = stage[q & 1];
+    // G2 of the next q is loaded while the current one is formed and written
+    auto load_g2 = [&](int q, C2<float> (&g)[3][3]) __attribute__((always_inline)) {
         const int a2p = q >> 2, a2 = q & 3;
-        C2<float> g2[3][3];
 #pragma unroll
         for (int u = 0; u < 3; ++u)
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 const float2 y = a.G2[(unsigned)((3 * a2p + u) * 12 + 3 * a2 + v) * V3 + n];
-                g2[u][v] = {y.x, y.y};
+                g[u][v] = {y.x, y.y};
             }
+    };
+    C2<float> g2[3][3], g2n[3][3];
+    load_g2(0, g2);
+#pragma unroll 2
+    for (int q = 0; q < 16; ++q) {
+        unsigned* st = stage[q & 1];
+        if (q + 1 < 16) load_g2(q + 1, g2n);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
@@ -122,11 +128,16 @@ __global__ void __launch_bounds__(256) fs_diquark_kernel(FsDiquarkArgs a) {
         for (int e = tid; e < nr * 3 * run_units; e += 256) {
             const int r = e / (3 * run_units), rem = e % (3 * run_units);
             const int c = rem / run_units, k = rem % run_units;
-            const uint4 v = *(const uint4*)(st + (r * 9 + 3 * c) * (Lp / 4) * 8 + 4 * k);
+            const u32x4 v = *(const u32x4*)(st + (r * 9 + 3 * c) * (Lp / 4) * 8 + 4 * k);
             unsigned char* dst =
                 out + (((size_t)(row0 + r) * kFsPlanes + 48 * c + 3 * q) * (size_t)(Lp / 4)) * 32 + (size_t)k * 16;
-            *(uint4*)dst = v;
+            // streaming stores: 2 GB at 48^3, far more than the caches hold
+            __builtin_nontemporal_store(v, (u32x4*)dst);
         }
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) g2[u][v] = g2n[u][v];
     }
 }
 
