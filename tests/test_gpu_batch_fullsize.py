@@ -1,20 +1,26 @@
 """Parity of the batched form at full lattice sizes, in the launch
 configuration bench.py times for its batch workload: the workload class
-itself draws the inputs on the GPU (seeded) and records the persistent,
-graph-replayed batch with the factored projection and the default
-partial-sum budget; here with 6 sources instead of 64, so that every
-lattice size (24^3 x 48, 32^3 x 64, 48^3 x 96) and both kinds (meson,
-nucleon) are in the one launch.  The FP64 oracle recomputes sampled outputs
-from the same inputs, copied back to the host:
+itself draws the inputs on the GPU (seeded) and records the graph-replayed
+batch of all 64 sources (every lattice size 24^3 x 48, 32^3 x 64, 48^3 x 96,
+both kinds, meson and nucleon) with the factored projection and the default
+partial-sum budget.  The FP64 oracle recomputes sampled outputs from the
+same inputs, copied back to the host:
 
 * source 0 (24^3 meson): the spectator (all noise vectors and momenta), the
   insertion at its first and last timeslice, and the recorded combine on its
   185 (p', q) pairs at those timeslices;
 * source 5 (48^3 nucleon): the (u, d) spectator for one noise vector and five
   momenta, and the d-quark insertion at its first timeslice for two noise
-  vectors.
+  vectors;
+* source 62 (48^3 meson, among the last jobs of the batch): the spectator for
+  two noise vectors and every momentum, the insertion at its last timeslice
+  for two noise vectors;
+* source 63 (24^3 nucleon, the last job): the (u, u) spectator, the u
+  insertion at its last timeslice and the combine of the (u, d) spectator
+  with it on the 7 recorded pairs.
 
-Tolerance 1e-5 relative (Frobenius), the FP32 bar.
+Tolerance 1e-5 relative (the larger of Frobenius and max-element), the FP32
+bar.
 """
 import argparse
 
@@ -42,12 +48,12 @@ def _host(t):
 def batch():
     import bench
     import paper_1711_02384_amd as c3pt
-    args = argparse.Namespace(sources=6, partial_budget_gib=24.0, no_plain=True)
+    args = argparse.Namespace(sources=64, partial_budget_gib=24.0, no_plain=True)
     W = bench.Batch64(args)
     k = c3pt.momentum_list(W.n2)
     W.proj_flag = c3pt.PROJ_FACTORED
     geom = c3pt.Geom((1, 1, 1), 1, proj=c3pt.PROJ_FACTORED)
-    _say("batch full size: drawing inputs and recording 6 sources")
+    _say("batch full size: drawing inputs and recording 64 sources")
     W.setup(c3pt, syn, torch.device("cuda:0"), geom, k)
     _say(f"batch full size: {W.batch.info()}")
     W.step()
@@ -61,6 +67,10 @@ def batch():
 
 def _first_job(W, j):
     return sum(4 if s["nucleon"] else 2 for s in W.src[:j])
+
+
+def _first_combine(W, j):
+    return sum(2 if s["nucleon"] else 1 for s in W.src[:j])
 
 
 def test_batch_fullsize_meson_source(batch):
@@ -111,3 +121,60 @@ def test_batch_fullsize_nucleon_source(batch):
     err = rel_err(I[2:4, 0], I_o[:, 0])
     _say(f"batch nucleon 48^3: d insertion tau={tau} (noise 2, 3) rel err {err:.2e}")
     assert err < TOL
+
+
+def test_batch_fullsize_last_meson_source(batch):
+    W, k, _ = batch
+    assert len(W.src) == 64
+    s = W.src[62]
+    assert not s["nucleon"] and tuple(s["L"]) == (48, 48, 48)
+    L, T, r = s["L"], s["T"], s["r"]
+    j0 = _first_job(W, 62)
+    js, ji = W.jobs[j0], W.jobs[j0 + 1]
+    assert js["kind"] == "spectator_meson" and ji["kind"] == "insertion"
+    _say(f"batch meson 48^3 (source 62): r={r} taus={s['taus'][0]}..{s['taus'][-1]}")
+    sel = [0, 7]
+    S_o = oracle.spectator_meson(_host(js["G"]), _host(js["eta"])[sel], L, k, r=r)
+    S = W.batch.outputs[j0].cpu().numpy()
+    err = rel_err(S[sel], S_o)
+    _say(f"batch meson 48^3 (source 62): spectator (noise 0, 7) rel err {err:.2e}")
+    assert err < TOL
+    tl = len(s["taus"]) - 1
+    tau = s["taus"][tl]
+    I_o = oracle.insertion({tau: _host(ji["G_t"][tau])}, {tau: _host(ji["s_t"][tau])[6:8]}, [tau], L, T, k, r=r)
+    I = W.batch.outputs[j0 + 1].cpu().numpy()
+    err = rel_err(I[6:8, tl], I_o[:, 0])
+    _say(f"batch meson 48^3 (source 62): insertion tau={tau} (noise 6, 7) rel err {err:.2e}")
+    assert err < TOL
+
+
+def test_batch_fullsize_last_nucleon_source(batch):
+    W, k, _ = batch
+    s = W.src[63]
+    assert s["nucleon"] and tuple(s["L"]) == (24, 24, 24)
+    L, T, r = s["L"], s["T"], s["r"]
+    j0 = _first_job(W, 63)
+    assert j0 + 4 == len(W.jobs)
+    juu, jud, ju = W.jobs[j0], W.jobs[j0 + 1], W.jobs[j0 + 2]
+    assert juu["kind"] == jud["kind"] == "spectator_baryon" and ju["kind"] == "insertion"
+    _say(f"batch nucleon 24^3 (source 63): r={r} t_f={s['t_f']}")
+    Suu_o = oracle.spectator_baryon(_host(juu["G1"]), _host(juu["G2"]), _host(juu["eta"]), L, k, r=r)
+    err = rel_err(W.batch.outputs[j0].cpu().numpy(), Suu_o)
+    _say(f"batch nucleon 24^3 (source 63): (u,u) spectator rel err {err:.2e}")
+    assert err < TOL
+    tl = len(s["taus"]) - 1
+    tau = s["taus"][tl]
+    Iu_o = oracle.insertion({tau: _host(ju["G_t"][tau])}, {tau: _host(ju["s_t"][tau])}, [tau], L, T, k, r=r)
+    Iu = W.batch.outputs[j0 + 2].cpu().numpy()
+    err = rel_err(Iu[:, tl], Iu_o[:, 0])
+    _say(f"batch nucleon 24^3 (source 63): u insertion tau={tau} rel err {err:.2e}")
+    assert err < TOL
+    # the (u,d) spectator with the u insertion: the second combine of the source
+    c = _first_combine(W, 63) + 1
+    assert c + 1 == len(W.combs) and W.combs[c]["spec"] == j0 + 1 and W.combs[c]["ins"] == j0 + 2
+    Sud = W.batch.outputs[j0 + 1].cpu().numpy()
+    C = W.batch.combine_outputs[c].cpu().numpy()
+    C_o = oracle.combine(Sud, Iu[:, tl:tl + 1], pairs=W.combs[c]["pairs"])
+    err = rel_err(C[:, tl], C_o[:, 0])
+    _say(f"batch nucleon 24^3 (source 63): combine tau={tau} ({len(W.combs[c]['pairs'])} pairs) rel err {err:.2e}")
+    assert err < 1e-12
