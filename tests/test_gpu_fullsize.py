@@ -145,8 +145,10 @@ def test_nucleon48_benchmark_launches_sampled():
     a two-block launch over 6-7), the insertion over all 15 timeslices in one
     call and the combine on the 185 (p' = q or p' = 0) pairs.  Sampled: the
     (u,d) spectator for noise vectors 2 and 7 (one from each launch) at three
-    momenta, the insertion at tau = 0 and 14 for every noise vector and
-    momentum, and the combine of the GPU's parts on four pairs."""
+    momenta, the (u,u) spectator (one buffer for both propagators, as the step
+    passes it) for noise vector 6 at two momenta, the insertion at tau = 0 and
+    14 for every noise vector and momentum, and the combine of the GPU's parts
+    on four pairs."""
     import paper_1711_02384_amd as c3pt
     c3pt.apply_tuning(c3pt.DEFAULT_TUNING)
     L, T, N, t_f, cfg = (48, 48, 48), 64, 8, 14, 3
@@ -161,7 +163,10 @@ def test_nucleon48_benchmark_launches_sampled():
     Gu = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t_f))
     Gd = syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G1, t_f))
     eta = syn.round_to_c64(syn.z2z2_noise(L, N, cfg, t_f))
-    SB = c3pt.spectator_baryon(_up(Gu), _up(Gd), _up(eta), k, geom)
+    Gu_dev, eta_dev = _up(Gu), _up(eta)
+    SB = c3pt.spectator_baryon(Gu_dev, _up(Gd), eta_dev, k, geom)
+    # (u,u) as the step calls it: one buffer for both propagators
+    SBuu = c3pt.spectator_baryon(Gu_dev, Gu_dev, eta_dev, k, geom)
     # distinct slices at the checked timeslices and one other slice shared by
     # the rest (a launch reading the wrong slice shows at tau = 0 or 14)
     G = {t: syn.round_to_c64(syn.propagator_slice(L, cfg, syn.FIELD_G3, t)) for t in (0, 7, 14)}
@@ -183,6 +188,10 @@ def test_nucleon48_benchmark_launches_sampled():
     want = oracle.spectator_baryon(Gu, Gd, eta[sel_n], L, k[sel_m])
     err = rel_err(S[sel_n][:, sel_m], want)
     _say(f"nucleon48 benchmark launches: spectator (noise 2 and 7, 3 momenta) rel err {err:.2e}")
+    assert err < TOL32
+    want = oracle.spectator_baryon(Gu, Gu, eta[6:7], L, k[[0, 92]])
+    err = rel_err(SBuu[6:7, [0, 92]].cpu().numpy(), want)
+    _say(f"nucleon48 benchmark launches: (u,u) spectator (noise 6, 2 momenta) rel err {err:.2e}")
     assert err < TOL32
     for tau in (0, 14):
         I_o = oracle.insertion({tau: G[tau]}, {tau: s[tau]}, [tau], L, T, k)
