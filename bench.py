@@ -134,6 +134,10 @@ MEASURED_TRAFFIC = {
                                                "287b4b579a2a535b"),
     # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413552 + 857088 KiB)
     ("nucleon48", "fac", "fac_spectator_baryon", 1): (413552 * 2048 + 857088 * 1024, "287b4b579a2a535b"),
+    # 32^3 meson step, factored FP32: one insertion call with local + 4 D_nu, i.e.
+    # its local (484210 + 264310 KiB) and derivative (1794856 + 1114112 KiB) dispatches
+    ("meson32", "fac", "fac_insertion", 5): ((484210 + 1794856) * 2048 + (264310 + 1114112) * 1024,
+                                             "287b4b579a2a535b"),
 }
 
 
