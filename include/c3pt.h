@@ -528,12 +528,13 @@ int c3pt_batch_destroy(c3pt_batch* batch);
  *   cannot be built, or cannot fit even with nothing else active) leaves the
  *   queue as failed.
  * c3pt_server_set_step_work(server, max_work)   cap a step's work at max_work
- *   column blocks x sites (0, the default: no cap beyond the workspace).  A
- *   step ends where the next packet would pass the cap (it always takes one),
- *   and requests admitted afterwards are cut into packets of at most a
- *   quarter of it where one noise vector (of one timeslice) allows; shorter
- *   steps bound how long a newly admitted request waits for the steps in
- *   flight.  C3PT_EINVAL for a negative cap.
+ *   column blocks x sites (0, the default: no cap beyond the workspace).
+ *   While no request waits for admission, a step ends where the next packet
+ *   would pass the cap (it always takes one); with requests waiting, steps
+ *   fill the workspace.  Requests admitted after the call are cut into
+ *   packets of at most a quarter of the cap where one noise vector (of one
+ *   timeslice) allows.  Shorter steps bound how long a new arrival waits for
+ *   the steps in flight.  C3PT_EINVAL for a negative cap.
  * c3pt_server_poll(server, id)   1 when the request's results are complete on
  *   the device, 0 if not yet, or a negative status (a failed request: the
  *   status of its failure, with its message in c3pt_last_error).

@@ -17,8 +17,8 @@
 //    the step workspace.
 //  * Steps: every step takes packets from the active requests with the least
 //    remaining work first (one left out for four steps goes first), each as
-//    many as fit, until the workspace (or the
-//    step work cap) is full, runs them through one launch per producer kind
+//    many as fit, until the workspace (or, while no request waits for
+//    admission, the step work cap) is full, runs them through one launch per producer kind
 //    (dense: and momentum-tile class; factored: and tile length), reduces
 //    the partial sums in FP64 into the requests' outputs, and enqueues the
 //    combines of every request whose last packet ran in the step, followed by
@@ -507,6 +507,10 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
     std::vector<Chosen> chosen;
     size_t used = 0, items = 0, tau_rows = 0;
     double work = 0;
+    // The work cap holds while no request waits for admission: it bounds how
+    // long a new arrival waits for the steps in flight.  With requests
+    // waiting, steps fill the workspace (throughput first).
+    const bool capped = sv->step_work > 0 && sv->queue.empty();
     std::vector<std::pair<double, Request*>> order;
     for (Request* q : sv->active) {
         if (q->todo.empty()) continue;
@@ -529,7 +533,7 @@ int step(c3pt_server* sv, int* n_done_enqueued) {
             const double wk = packet_work(*q, p);
             if (!chosen.empty() && (used + b > sv->step_bytes || items + it > kMaxStepItems ||
                                     tau_rows + tr > (size_t)kMaxStepTau || chosen.size() >= (size_t)kMaxStepJobs ||
-                                    (sv->step_work > 0 && work + wk > sv->step_work)))
+                                    (capped && work + wk > sv->step_work)))
                 break;
             chosen.push_back({q, p, b});
             used += b;
