@@ -89,7 +89,8 @@ def parse():
                     help="nucleon48: run the two isovector halves of the step on two streams (default) "
                          "or on one; kernel durations always come from one-stream profiled steps")
     ap.add_argument("--step-work", type=float, default=0.0,
-                    help="serve: cap on a step's work in column blocks x sites (0: none)")
+                    help="serve: cap on a step's work in column blocks x sites while no request waits "
+                         "for admission (0: none)")
     return ap.parse_args()
 
 
