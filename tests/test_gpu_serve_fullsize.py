@@ -16,6 +16,8 @@ flight together:
 The FP64 oracle recomputes these from the inputs copied back to the host.
 Tolerance 1e-5 relative (Frobenius), the FP32 bar.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -61,7 +63,12 @@ def served():
     for i in ids:
         sv.release(i)
     sv.close()
-    del pool, reqs
+    # pytest still holds the yielded requests here: drop their tensors and the
+    # resident pool (about 120 GiB) so that later modules find the memory free
+    for q in reqs:
+        q.clear()
+    pool.__dict__.clear()
+    gc.collect()
     torch.cuda.empty_cache()
 
 
