@@ -129,18 +129,18 @@ TRAFFIC_FUNCTIONS = ["momentum_groups", "build_factor_plan", "factor_plan_table"
 MEASURED_TRAFFIC = {
     # workload, projection, timed kernel name, insertion operators -> (bytes per call, source hash)
     # 48^3 step, split-precision fused form: one local insertion call, i.e. its
-    # three-block launch (1445842 + 602640 KiB) and the two-block launch of the
-    # last two noise vectors (1089618 + 200880 KiB)
-    ("nucleon48", "fs16", "fs_insertion", 1): ((1445842 + 1089618) * 2048 + (602640 + 200880) * 1024,
-                                               "a24c8316465dd19a"),
-    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (414049 + 857088 KiB)
-    ("nucleon48", "fac", "fac_spectator_baryon", 1): (414049 * 2048 + 857088 * 1024, "a24c8316465dd19a"),
+    # three-block launch (1457191 + 602640 KiB) and the two-block launch of the
+    # last two noise vectors (1089615 + 200880 KiB)
+    ("nucleon48", "fs16", "fs_insertion", 1): ((1457191 + 1089615) * 2048 + (602640 + 200880) * 1024,
+                                               "44654bcb5941f5dc"),
+    # 48^3 step, factored FP32 form: one nucleon spectator dispatch (413926 + 857088 KiB)
+    ("nucleon48", "fac", "fac_spectator_baryon", 1): (413926 * 2048 + 857088 * 1024, "44654bcb5941f5dc"),
     # 32^3 meson step, factored FP32: one insertion call with local + 4 D_nu, i.e.
     # its local (484210 + 264310 KiB) and derivative (1794856 + 1114112 KiB)
     # dispatches; taken on sources 287b4b579a2a535b, whose factored kernels and
     # planning are those of this hash (only the fused kernel's tile loop differs)
     ("meson32", "fac", "fac_insertion", 5): ((484210 + 1794856) * 2048 + (264310 + 1114112) * 1024,
-                                             "a24c8316465dd19a"),
+                                             "44654bcb5941f5dc"),
 }
 
 

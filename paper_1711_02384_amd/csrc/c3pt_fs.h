@@ -519,11 +519,13 @@ __global__ void __launch_bounds__(256 * CB) fs_kernel(ProjGrid pg, FsArgs fa) {
             acc[ct] = MF::mac(a_hi[ca], b_hi[cb2], acc[ct]);
             if constexpr (kPipe && ct == 2) {
                 // interleave the step's MFMAs with the next step's A formation,
-                // or with the staging after the last step
+                // or with the staging after the last step (three VALU per MFMA:
+                // 13.60 -> 13.49 ms per 48^3 step against four; two or six
+                // were no better than four)
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, st);   // one MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x002, 4, st);   // four VALU
+                    __builtin_amdgcn_sched_group_barrier(0x002, 3, st);   // three VALU
                 }
             }
         });
