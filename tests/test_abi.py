@@ -388,3 +388,18 @@ def test_extent_checks_catch_an_under_sized_buffer():
                "partial sums", "noalloc")
     finally:
         c.lib.c3pt_debug_scale_allocations(1.0)
+
+
+def test_shipped_tuning_table_applies_every_entry():
+    """Every entry of the tuning table in the package names a variant the
+    library has for its (kind, mode, class), and applying the table selects
+    it (a typo would otherwise be skipped without a word)."""
+    import json
+
+    import paper_1711_02384_amd as c3pt
+    with open(c3pt.DEFAULT_TUNING) as f:
+        table = json.load(f)
+    entries = table["entries"]
+    assert c3pt.apply_tuning(table) == len(entries)
+    for e in entries:
+        assert c3pt.get_variant(e["kind"], e["mode"], e["mt_class"]) == e["variant"], e
